@@ -1,0 +1,290 @@
+"""Python face of the FP64 oracle (test infrastructure only).
+
+The oracle is a plain binary64 CPU implementation of the VOiLA planning hot
+path (``voila_oracle.c``).  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the product library
+never does.  Inputs are converted to binary64 here (binary32 inputs convert
+exactly), the C code does all of the arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_uint32, c_uint64, c_size_t
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+OR_OK, OR_ERR_ARG, OR_ERR_NUMERIC = 0, 1, 2
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class _CModel(ctypes.Structure):
+    _fields_ = [
+        ("d_s", c_int), ("n_actions", c_int), ("d_a", c_int), ("d_w", c_int),
+        ("d_o", c_int), ("d_wz", c_int), ("residual", c_int),
+        ("t_layers", c_int), ("t_dims", POINTER(c_int)), ("t_params", POINTER(c_double)),
+        ("z_layers", c_int), ("z_dims", POINTER(c_int)), ("z_params", POINTER(c_double)),
+        ("l_layers", c_int), ("l_dims", POINTER(c_int)), ("l_params", POINTER(c_double)),
+    ]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        dp, ip, i32p, u32p = POINTER(c_double), POINTER(c_int), POINTER(c_int32), POINTER(c_uint32)
+        mp = POINTER(_CModel)
+        L.or_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.or_uniform.argtypes = [c_uint32]
+        L.or_uniform.restype = c_double
+        L.or_normals.argtypes = [c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int, dp]
+        L.or_round_bf16.argtypes = [c_double]
+        L.or_round_bf16.restype = c_double
+        L.or_mlp.argtypes = [c_int, ip, dp, c_int, dp, dp, c_int]
+        L.or_plan.argtypes = [mp, c_int, dp, dp, c_int, c_int, i32p, dp, c_double, dp, c_int,
+                              dp, c_uint64, c_int, c_int, dp, dp]
+        L.or_rollouts.argtypes = [mp, c_int, dp, c_int, c_int, i32p, dp, c_double, dp, c_int,
+                                  c_uint64, c_int, c_int, c_int, i32p, i32p, dp]
+        L.or_weighted_mean.argtypes = [c_int, dp, dp]
+        L.or_weighted_mean.restype = c_double
+        L.or_normalize.argtypes = [c_int, dp, dp, c_double, dp, dp]
+        L.or_resample_bits.argtypes = [c_int]
+        L.or_resample.argtypes = [c_int, dp, c_uint32, i32p]
+        L.or_update.argtypes = [mp, c_int, dp, dp, c_int, dp, dp, c_double, dp, c_uint64, c_uint32,
+                                c_int, dp, dp, dp, dp, i32p, dp]
+        L.or_observe.argtypes = [mp, c_int, dp, i32p, dp, dp, c_uint64, c_int, dp]
+        L.or_transition.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, dp]
+        L.or_mlp_param_count.argtypes = [c_int, ip]
+        L.or_mlp_param_count.restype = c_size_t
+        _LIB = L
+    return _LIB
+
+
+# --------------------------------------------------------------------------- helpers
+def _d(a):
+    """Contiguous binary64 copy (exact for binary32 input) or None."""
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a, ctype=c_double):
+    return None if a is None else a.ctypes.data_as(POINTER(ctype))
+
+
+def _check(rc, what):
+    if rc != OR_OK:
+        raise OracleError(f"oracle {what} failed with code {rc}")
+
+
+def flatten_layers(layers):
+    """(dims int32 array, params float64 array) from [(W, b), ...]."""
+    dims = [int(layers[0][0].shape[1])] + [int(W.shape[0]) for W, _ in layers]
+    parts = []
+    for W, b in layers:
+        parts.append(np.asarray(W, np.float64).ravel())
+        parts.append(np.asarray(b, np.float64).ravel())
+    return np.array(dims, dtype=np.int32), np.ascontiguousarray(np.concatenate(parts))
+
+
+class _Bound:
+    """A C model struct together with the arrays it points into."""
+
+    def __init__(self, model):
+        self.keep = []
+        cm = _CModel()
+        cm.d_s, cm.n_actions, cm.d_a = model.d_s, model.n_actions, model.d_a
+        cm.d_w, cm.d_o, cm.d_wz = model.d_w, model.d_o, model.d_wz
+        cm.residual = 1 if model.residual else 0
+        for tag, layers in (("t", model.trans), ("z", model.obs), ("l", model.lik)):
+            if layers:
+                dims, params = flatten_layers(layers)
+                self.keep += [dims, params]
+                setattr(cm, f"{tag}_layers", len(layers))
+                setattr(cm, f"{tag}_dims", dims.ctypes.data_as(POINTER(c_int)))
+                setattr(cm, f"{tag}_params", params.ctypes.data_as(POINTER(c_double)))
+            else:
+                setattr(cm, f"{tag}_layers", 0)
+        self.c = cm
+
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def _cands(model, cands):
+    if model.n_actions > 0:
+        return np.ascontiguousarray(np.asarray(cands, np.int32)), None
+    return None, _d(cands)
+
+
+# --------------------------------------------------------------------------- RNG
+def philox(counter, key):
+    """Philox4x32-10 of one 4-word counter under a 2-word key -> 4 uint32."""
+    c = np.ascontiguousarray(np.asarray(counter, np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, np.uint32))
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c, c_uint32), _p(k, c_uint32), _p(out, c_uint32))
+    return out
+
+
+def uniform(x: int) -> float:
+    return lib().or_uniform(int(x))
+
+
+def normals(seed, c0, c1, c2, stream, d):
+    out = np.zeros(d, np.float64)
+    lib().or_normals(int(seed), int(c0), int(c1), int(c2), int(stream), int(d), _p(out))
+    return out
+
+
+def round_bf16(x):
+    x = np.asarray(x, np.float64)
+    f = np.vectorize(lambda v: lib().or_round_bf16(float(v)), otypes=[np.float64])
+    return f(x)
+
+
+# --------------------------------------------------------------------------- networks
+def mlp(layers, X, bf16=False):
+    """Rows of X through the network: ReLU hidden layers, linear output."""
+    dims, params = flatten_layers(layers)
+    X = _d(np.atleast_2d(X))
+    Y = np.zeros((X.shape[0], int(dims[-1])), np.float64)
+    _check(lib().or_mlp(len(layers), dims.ctypes.data_as(POINTER(c_int)), _p(params), X.shape[0],
+                        _p(X), _p(Y), int(bf16)), "mlp")
+    return Y
+
+
+def transition(model, S, actions, noise, bf16=False):
+    """s' = s + f_T([s, a, w]) for given rows (actions one per row)."""
+    S = _d(np.atleast_2d(S))
+    n = S.shape[0]
+    a_disc, a_cont = (np.ascontiguousarray(np.asarray(actions, np.int32).reshape(n)), None) \
+        if model.n_actions > 0 else (None, _d(np.asarray(actions).reshape(n, model.d_a)))
+    W = _d(np.asarray(noise).reshape(n, model.d_w))
+    out = np.zeros((n, model.d_s), np.float64)
+    b = _Bound(model)
+    _check(lib().or_transition(b.ref(), n, _p(S), _p(a_disc, c_int32), _p(a_cont), _p(W),
+                               int(bf16), _p(out)), "transition")
+    return out
+
+
+def observe(model, S, actions, noise=None, seed=0, bf16=False):
+    """o = f_Z([s', a, w_Z]) per row; noise given or drawn from stream 4."""
+    S = _d(np.atleast_2d(S))
+    n = S.shape[0]
+    a_disc, a_cont = (np.ascontiguousarray(np.asarray(actions, np.int32).reshape(n)), None) \
+        if model.n_actions > 0 else (None, _d(np.asarray(actions).reshape(n, model.d_a)))
+    W = None if noise is None else _d(np.asarray(noise).reshape(n, model.d_wz))
+    out = np.zeros((n, model.d_o), np.float64)
+    b = _Bound(model)
+    _check(lib().or_observe(b.ref(), n, _p(S), _p(a_disc, c_int32), _p(a_cont), _p(W), int(seed),
+                            int(bf16), _p(out)), "observe")
+    return out
+
+
+# --------------------------------------------------------------------------- plan
+def plan(model, states, cands, gamma, goal, belief_w=None, noise=None, seed=0, crn=False,
+         reward_at=0, bf16=False, return_G=False):
+    """Q[K] (and G[K, N]) of open-loop candidate sequences from a particle belief."""
+    S = _d(states)
+    N = S.shape[0]
+    cd, cc = _cands(model, cands)
+    K, H = int(np.asarray(cands).shape[0]), int(np.asarray(cands).shape[1])
+    Q = np.zeros(K, np.float64)
+    G = np.zeros((K, N), np.float64)
+    nz = None if noise is None else _d(noise)
+    if nz is not None:
+        assert nz.shape == (K, N, H, model.d_w), nz.shape
+    b = _Bound(model)
+    _check(lib().or_plan(b.ref(), N, _p(S), _p(_d(belief_w)), K, H, _p(cd, c_int32), _p(cc),
+                         float(gamma), _p(_d(goal)), int(reward_at), _p(nz), int(seed), int(crn),
+                         int(bf16), _p(Q), _p(G)), "plan")
+    return (Q, G) if return_G else Q
+
+
+def rollouts(model, states, cands, gamma, goal, pairs, seed=0, crn=False, reward_at=0, bf16=False):
+    """Returns G of selected rollouts [(k, i), ...] under counter-RNG noise."""
+    S = _d(states)
+    N = S.shape[0]
+    cd, cc = _cands(model, cands)
+    K, H = int(np.asarray(cands).shape[0]), int(np.asarray(cands).shape[1])
+    pairs = np.asarray(pairs, np.int32).reshape(-1, 2)
+    ks = np.ascontiguousarray(pairs[:, 0])
+    is_ = np.ascontiguousarray(pairs[:, 1])
+    out = np.zeros(len(pairs), np.float64)
+    b = _Bound(model)
+    _check(lib().or_rollouts(b.ref(), N, _p(S), K, H, _p(cd, c_int32), _p(cc), float(gamma),
+                             _p(_d(goal)), int(reward_at), int(seed), int(crn), int(bf16), len(pairs),
+                             _p(ks, c_int32), _p(is_, c_int32), _p(out)), "rollouts")
+    return out
+
+
+def weighted_mean(G, w=None):
+    G = _d(G)
+    return lib().or_weighted_mean(G.shape[0], _p(G), _p(_d(w)))
+
+
+# --------------------------------------------------------------------------- update
+def normalize(loglik, lam=1.0, prior_w=None):
+    """(w', [log evidence, ESS]) for weights proportional to prior * exp(l / lam)."""
+    ll = _d(loglik)
+    N = ll.shape[0]
+    w = np.zeros(N, np.float64)
+    st = np.zeros(2, np.float64)
+    _check(lib().or_normalize(N, _p(ll), _p(_d(prior_w)), float(lam), _p(w), _p(st)), "normalize")
+    return w, st
+
+
+def resample_bits(N: int) -> int:
+    return lib().or_resample_bits(int(N))
+
+
+def resample(w, U):
+    """Systematic resampling indices [N] int32 on quantised weights."""
+    w = _d(w)
+    N = w.shape[0]
+    idx = np.zeros(N, np.int32)
+    _check(lib().or_resample(N, _p(w), int(U) & 0xFFFFFFFF, _p(idx, c_int32)), "resample")
+    return idx
+
+
+def update(model, states, action, obs, lam=1.0, prior_w=None, noise=None, seed=0, U=0, bf16=False):
+    """SIR belief update.  Returns a dict with S_prop, loglik, w, stats, idx, S_new."""
+    S = _d(states)
+    N = S.shape[0]
+    if model.n_actions > 0:
+        a_disc, a_cont = int(action), None
+    else:
+        a_disc, a_cont = 0, _d(np.asarray(action).reshape(model.d_a))
+    o = _d(np.asarray(obs).reshape(model.d_o))
+    nz = None if noise is None else _d(np.asarray(noise).reshape(N, model.d_w))
+    out = dict(S_prop=np.zeros((N, model.d_s)), loglik=np.zeros(N), w=np.zeros(N),
+               stats=np.zeros(2), idx=np.zeros(N, np.int32), S_new=np.zeros((N, model.d_s)))
+    b = _Bound(model)
+    _check(lib().or_update(b.ref(), N, _p(S), _p(_d(prior_w)), a_disc, _p(a_cont), _p(o), float(lam),
+                           _p(nz), int(seed), int(U) & 0xFFFFFFFF, int(bf16), _p(out["S_prop"]),
+                           _p(out["loglik"]), _p(out["w"]), _p(out["stats"]),
+                           _p(out["idx"], c_int32), _p(out["S_new"])), "update")
+    return out
+
+
+def draw_observation(w, bf16=False):
+    """The observation of a workload: a true state drawn from the belief is moved
+    by the transition sampler with the executed action and observed through the
+    observation sampler, both with the workload's explicit noise."""
+    m = w.model
+    s_true = np.asarray(w.states[w.true_index], np.float64)[None, :]
+    a = np.asarray(w.update_action)
+    s_next = transition(m, s_true, a.reshape(1, -1) if m.n_actions == 0 else [int(a)],
+                        w.true_noise[None, :], bf16=bf16)
+    return observe(m, s_next, a.reshape(1, -1) if m.n_actions == 0 else [int(a)],
+                   noise=w.obs_noise[None, :], bf16=bf16)[0]

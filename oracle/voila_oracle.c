@@ -1,0 +1,543 @@
+/*
+ * voila_oracle.c -- plain FP64 CPU reference of the VOiLA planning hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg do.  It shares no header, helper, table or constant with
+ * the HIP implementation: every step below is written out from the paper
+ * (Hoerger et al., "VOiLA: Vectorized Online Planning with Learned Diffusion
+ * Models for POMDP Agents") and from the published definitions it relies on.
+ *
+ * What it computes (all arithmetic in IEEE binary64, sums in ascending index
+ * order, built with -ffp-contract=off so no fused multiply-adds appear):
+ *
+ *   mlp       Feed-forward generator / likelihood network: affine layers with
+ *             ReLU between them, linear output layer (Sec. 4.2, Eq. 2 and
+ *             Eq. 5 for the samplers, Sec. 4.2 "Likelihood Model" for l).
+ *   plan      Monte-Carlo estimate of the discounted return of open-loop
+ *             action sequences from a particle belief: the expected reward
+ *             R(b,a) is a Monte-Carlo average over belief particles (Sec. 2.1,
+ *             Sec. 2.2 below Eq. 1), forward simulation draws successor
+ *             states from the learned transition sampler s'=f_T(s,a,w_T),
+ *             w_T ~ N(0,I) (Eq. 2, Sec. 4.3), and the return is discounted
+ *             by gamma^t (Sec. 2.1, value definition).
+ *   update    Sequential-importance-resampling belief update (Sec. 3, last
+ *             paragraph): proposal particles from f_T, weights
+ *             exp(l(s',a,o)/lambda) from the likelihood network (Sec. 4.2,
+ *             "Likelihood Model", last paragraph), normalisation of the
+ *             weights (the proportionality in the belief operator tau of
+ *             Sec. 2.1), then resampling.
+ *   resample  Systematic resampling on weights quantised to integer
+ *             multiples of 2^-b of a particle (the paper leaves the scheme
+ *             open; this reading makes every prefix sum exact in binary64).
+ *   observe   Observation sampler z=f_Z(s',a,w_Z) (Eq. 5).
+ *   philox    Philox4x32-10 counter-based generator (Salmon, Moraes, Dror,
+ *             Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11),
+ *             Box-Muller transform for N(0,1) draws.
+ *
+ * Input vector convention: x = [s, a, w] where a discrete action is one-hot
+ * over the action set (0-based index) and a continuous action is used as
+ * given; the likelihood network takes [s', a, o]; the observation sampler
+ * takes [s', a, w_Z].  Layer parameters are packed per layer as W (rows =
+ * outputs, row-major, i.e. W[n*in + k]) followed by the bias b[n].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR_ARG 1
+#define OR_ERR_NUMERIC 2
+
+#define OR_MAX_WIDTH 4096
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (SC'11 paper: Philox-4x32 with R = 10 rounds).              */
+/* One round multiplies the even words by the two published multipliers,    */
+/* xors the high halves into the odd words together with the round key, and */
+/* permutes; the key is bumped by the two published Weyl constants between  */
+/* rounds.                                                                   */
+/* ------------------------------------------------------------------------- */
+static const uint32_t PHILOX_MUL0 = 0xD2511F53u;
+static const uint32_t PHILOX_MUL1 = 0xCD9E8D57u;
+static const uint32_t PHILOX_WEYL0 = 0x9E3779B9u;
+static const uint32_t PHILOX_WEYL1 = 0xBB67AE85u;
+
+void or_philox4x32_10(const uint32_t counter[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = counter[0], c1 = counter[1], c2 = counter[2], c3 = counter[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)PHILOX_MUL0 * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)PHILOX_MUL1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += PHILOX_WEYL0;
+        k1 += PHILOX_WEYL1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform on the open interval (0,1) from the top 23 bits of a word:
+ * u = (2*(x >> 9) + 1) * 2^-24.  The value has at most 24 significant bits,
+ * so it is exact in binary32 as well as binary64, and it is never 0 or 1. */
+double or_uniform(uint32_t x)
+{
+    return (2.0 * (double)(x >> 9) + 1.0) * 0x1p-24;
+}
+
+/* d standard normal draws for one counter triple (c0,c1,c2) of a stream.
+ * Block j of four draws uses counter (c0, c1, c2, (stream << 16) | j); its
+ * four words give two uniform pairs (u0,u1), (u2,u3), each turned into two
+ * normals by the Box-Muller transform:
+ *   z_a = sqrt(-2 ln u_a) cos(2 pi u_b),  z_b = sqrt(-2 ln u_a) sin(2 pi u_b). */
+void or_normals(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t stream,
+                int d, double* z)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    for (int block = 0; 4 * block < d; ++block) {
+        uint32_t ctr[4] = {c0, c1, c2, (stream << 16) | (uint32_t)block};
+        uint32_t w[4];
+        or_philox4x32_10(ctr, key, w);
+        double u0 = or_uniform(w[0]), u1 = or_uniform(w[1]);
+        double u2 = or_uniform(w[2]), u3 = or_uniform(w[3]);
+        double r0 = sqrt(-2.0 * log(u0));
+        double r1 = sqrt(-2.0 * log(u2));
+        double four[4] = {r0 * cos(two_pi * u1), r0 * sin(two_pi * u1),
+                          r1 * cos(two_pi * u3), r1 * sin(two_pi * u3)};
+        for (int j = 0; j < 4; ++j)
+            if (4 * block + j < d) z[4 * block + j] = four[j];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* bfloat16 emulation: round to 8 significant bits, ties to even.           */
+/* ------------------------------------------------------------------------- */
+double or_round_bf16(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    double m = frexp(x, &e);           /* x = m * 2^e, 0.5 <= |m| < 1 */
+    double scaled = ldexp(m, 8);       /* 128 <= |scaled| < 256       */
+    double r = nearbyint(scaled);      /* default mode: ties to even  */
+    return ldexp(r, e - 8);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Multilayer perceptron (Sec. 4.2; layer widths Sec. 5.2).                  */
+/* ------------------------------------------------------------------------- */
+static size_t mlp_param_count(int n_layers, const int* dims)
+{
+    size_t n = 0;
+    for (int l = 0; l < n_layers; ++l) n += (size_t)dims[l + 1] * dims[l] + dims[l + 1];
+    return n;
+}
+
+static int mlp_check(int n_layers, const int* dims)
+{
+    if (n_layers < 1) return OR_ERR_ARG;
+    for (int l = 0; l <= n_layers; ++l)
+        if (dims[l] < 1 || dims[l] > OR_MAX_WIDTH) return OR_ERR_ARG;
+    return OR_OK;
+}
+
+/* y = MLP(x).  Hidden layers: h = max(W h_prev + b, 0); output layer linear.
+ * With bf16 != 0 each weight and each layer input is first rounded to
+ * bfloat16 (biases, accumulation and outputs stay binary64). */
+static void mlp_forward(int n_layers, const int* dims, const double* params,
+                        const double* x, double* y, int bf16)
+{
+    double buf0[OR_MAX_WIDTH], buf1[OR_MAX_WIDTH];
+    double* in = buf0;
+    double* out = buf1;
+    for (int k = 0; k < dims[0]; ++k) in[k] = bf16 ? or_round_bf16(x[k]) : x[k];
+    const double* p = params;
+    for (int l = 0; l < n_layers; ++l) {
+        int n_in = dims[l], n_out = dims[l + 1];
+        const double* W = p;
+        const double* b = p + (size_t)n_out * n_in;
+        for (int n = 0; n < n_out; ++n) {
+            double acc = 0.0;
+            for (int k = 0; k < n_in; ++k) {
+                double wk = bf16 ? or_round_bf16(W[(size_t)n * n_in + k]) : W[(size_t)n * n_in + k];
+                acc += wk * in[k];
+            }
+            acc += b[n];
+            if (l < n_layers - 1) {
+                if (acc < 0.0) acc = 0.0;
+                if (bf16) acc = or_round_bf16(acc);
+            }
+            out[n] = acc;
+        }
+        p += (size_t)n_out * n_in + n_out;
+        double* t = in; in = out; out = t;
+    }
+    for (int n = 0; n < dims[n_layers]; ++n) y[n] = in[n];
+}
+
+int or_mlp(int n_layers, const int* dims, const double* params, int rows,
+           const double* X, double* Y, int bf16)
+{
+    if (mlp_check(n_layers, dims) != OR_OK || rows < 0) return OR_ERR_ARG;
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < rows; ++r)
+        mlp_forward(n_layers, dims, params, X + (size_t)r * dims[0], Y + (size_t)r * dims[n_layers], bf16);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Generator model: transition sampler f_T (Eq. 2, used with a residual     */
+/* state update s' = s + f_T(x), the increment form of Eq. 2), observation  */
+/* sampler f_Z (Eq. 5) and likelihood l (Sec. 4.2).                         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int d_s;        /* state dimension                                   */
+    int n_actions;  /* > 0: discrete action set fed one-hot; 0: continuous */
+    int d_a;        /* continuous action dimension (ignored if discrete)  */
+    int d_w;        /* transition-noise dimension                         */
+    int d_o;        /* observation dimension                              */
+    int d_wz;       /* observation-noise dimension                        */
+    int residual;   /* 1: s' = s + f_T(x); 0: s' = f_T(x)                 */
+    int t_layers; const int* t_dims; const double* t_params;
+    int z_layers; const int* z_dims; const double* z_params;
+    int l_layers; const int* l_dims; const double* l_params;
+} or_model;
+
+static int action_width(const or_model* m)
+{
+    return m->n_actions > 0 ? m->n_actions : m->d_a;
+}
+
+/* Writes the action part of an input vector. */
+static void put_action(const or_model* m, double* dst, int a_disc, const double* a_cont)
+{
+    if (m->n_actions > 0) {
+        for (int j = 0; j < m->n_actions; ++j) dst[j] = (j == a_disc) ? 1.0 : 0.0;
+    } else {
+        for (int j = 0; j < m->d_a; ++j) dst[j] = a_cont[j];
+    }
+}
+
+/* One transition draw s_next = s + f_T([s, a, w]) (or f_T(...) if not residual). */
+static void transition(const or_model* m, const double* s, int a_disc, const double* a_cont,
+                       const double* w, double* s_next, int bf16)
+{
+    double x[OR_MAX_WIDTH], d[OR_MAX_WIDTH];
+    int aw = action_width(m);
+    for (int j = 0; j < m->d_s; ++j) x[j] = s[j];
+    put_action(m, x + m->d_s, a_disc, a_cont);
+    for (int j = 0; j < m->d_w; ++j) x[m->d_s + aw + j] = w[j];
+    mlp_forward(m->t_layers, m->t_dims, m->t_params, x, d, bf16);
+    for (int j = 0; j < m->d_s; ++j) s_next[j] = m->residual ? s[j] + d[j] : d[j];
+}
+
+static int model_check(const or_model* m)
+{
+    if (m->d_s < 1 || m->d_w < 0 || m->n_actions < 0) return OR_ERR_ARG;
+    if (m->n_actions == 0 && m->d_a < 0) return OR_ERR_ARG;
+    if (mlp_check(m->t_layers, m->t_dims) != OR_OK) return OR_ERR_ARG;
+    if (m->t_dims[0] != m->d_s + action_width(m) + m->d_w) return OR_ERR_ARG;
+    if (m->t_dims[m->t_layers] != m->d_s) return OR_ERR_ARG;
+    return OR_OK;
+}
+
+/* Reward R(s) = -||s - g||^2 (action independent). */
+static double reward(int d_s, const double* s, const double* goal)
+{
+    double acc = 0.0;
+    for (int j = 0; j < d_s; ++j) {
+        double e = s[j] - goal[j];
+        acc += e * e;
+    }
+    return -acc;
+}
+
+/* Noise of the plan rollouts: stream 3, counter (particle, candidate or 0
+ * under common random numbers, step). */
+#define OR_STREAM_PLAN 3u
+#define OR_STREAM_OBS 4u
+#define OR_STREAM_UPDATE 5u
+
+/* Discounted return of rollout (k, i):
+ *   s_0 = S_i;  s_{t+1} = s_t + f_T([s_t, a_{k,t}, w_{k,i,t}]);
+ *   reward_at == 0: r_t = R(s_{t+1})   (reward on arrival, default)
+ *   reward_at == 1: r_t = R(s_t)       (reward of the state acted from)
+ *   G = sum_{t<H} gamma^t r_t. */
+static double rollout_return(const or_model* m, const double* S_i, int k, int i, int N, int H,
+                             const int32_t* cand_disc, const double* cand_cont,
+                             double gamma, const double* goal, int reward_at,
+                             const double* noise, uint64_t seed, int crn, int bf16)
+{
+    double s[OR_MAX_WIDTH], s_next[OR_MAX_WIDTH], w[OR_MAX_WIDTH];
+    for (int j = 0; j < m->d_s; ++j) s[j] = S_i[j];
+    double G = 0.0, disc = 1.0;
+    for (int t = 0; t < H; ++t) {
+        if (noise) {
+            const double* src = noise + (((size_t)k * N + i) * H + t) * m->d_w;
+            for (int j = 0; j < m->d_w; ++j) w[j] = src[j];
+        } else {
+            or_normals(seed, (uint32_t)i, crn ? 0u : (uint32_t)k, (uint32_t)t, OR_STREAM_PLAN, m->d_w, w);
+        }
+        int a_disc = cand_disc ? cand_disc[(size_t)k * H + t] : 0;
+        const double* a_cont = cand_cont ? cand_cont + ((size_t)k * H + t) * m->d_a : NULL;
+        transition(m, s, a_disc, a_cont, w, s_next, bf16);
+        double r = reward_at ? reward(m->d_s, s, goal) : reward(m->d_s, s_next, goal);
+        G += disc * r;
+        disc *= gamma;
+        for (int j = 0; j < m->d_s; ++j) s[j] = s_next[j];
+    }
+    return G;
+}
+
+/* Neumaier-compensated sum of a[i] * b[i] (b may be NULL: uniform 1/n). */
+static double weighted_sum(int n, const double* a, const double* b, size_t stride)
+{
+    double sum = 0.0, comp = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double term = a[(size_t)i * stride] * (b ? b[i] : 1.0 / (double)n);
+        double t = sum + term;
+        if (fabs(sum) >= fabs(term)) comp += (sum - t) + term;
+        else comp += (term - t) + sum;
+        sum = t;
+    }
+    return sum + comp;
+}
+
+int or_plan(const or_model* m, int N, const double* S, const double* belief_w,
+            int K, int H, const int32_t* cand_disc, const double* cand_cont,
+            double gamma, const double* goal, int reward_at,
+            const double* noise, uint64_t seed, int crn, int bf16,
+            double* Q, double* G)
+{
+    if (model_check(m) != OR_OK || N < 1 || K < 0 || H < 0) return OR_ERR_ARG;
+    if (m->n_actions > 0 ? !cand_disc : !cand_cont) return OR_ERR_ARG;
+    double* Gbuf = G ? G : (double*)malloc(sizeof(double) * (size_t)K * N + 1);
+    if (!Gbuf) return OR_ERR_ARG;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (long r = 0; r < (long)K * N; ++r) {
+        int k = (int)(r / N), i = (int)(r % N);
+        Gbuf[r] = rollout_return(m, S + (size_t)i * m->d_s, k, i, N, H, cand_disc, cand_cont,
+                                 gamma, goal, reward_at, noise, seed, crn, bf16);
+    }
+    for (int k = 0; k < K; ++k) Q[k] = weighted_sum(N, Gbuf + (size_t)k * N, belief_w, 1);
+    if (!G) free(Gbuf);
+    return OR_OK;
+}
+
+/* Returns of selected rollouts (k_list[p], i_list[p]) only -- used to check
+ * sampled outputs of full-size workloads. */
+int or_rollouts(const or_model* m, int N, const double* S, int K, int H,
+                const int32_t* cand_disc, const double* cand_cont,
+                double gamma, const double* goal, int reward_at,
+                uint64_t seed, int crn, int bf16,
+                int n_pairs, const int32_t* k_list, const int32_t* i_list, double* G_out)
+{
+    if (model_check(m) != OR_OK || N < 1 || K < 0 || H < 0 || n_pairs < 0) return OR_ERR_ARG;
+    for (int p = 0; p < n_pairs; ++p)
+        if (k_list[p] < 0 || k_list[p] >= K || i_list[p] < 0 || i_list[p] >= N) return OR_ERR_ARG;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int p = 0; p < n_pairs; ++p) {
+        int k = k_list[p], i = i_list[p];
+        G_out[p] = rollout_return(m, S + (size_t)i * m->d_s, k, i, N, H, cand_disc, cand_cont,
+                                  gamma, goal, reward_at, NULL, seed, crn, bf16);
+    }
+    return OR_OK;
+}
+
+/* Weighted sum of given returns: Q = sum_i w_i G_i (w NULL: 1/N). */
+double or_weighted_mean(int n, const double* G, const double* w)
+{
+    return weighted_sum(n, G, w, 1);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Belief update (Sec. 3; Sec. 4.2 likelihood model; Sec. 2.1 operator tau). */
+/* ------------------------------------------------------------------------- */
+
+/* Weight normalisation.  x_i = l_i / lambda (+ log w_i for a weighted prior),
+ * m = max x_i, e_i = exp(x_i - m), S = sum e_i, w'_i = e_i / S;
+ * stats[0] = log evidence = m + log S (- log N under a uniform prior),
+ * stats[1] = effective sample size 1 / sum w'_i^2. */
+int or_normalize(int N, const double* loglik, const double* prior_w, double lambda,
+                 double* w_out, double* stats)
+{
+    if (N < 1 || !(lambda > 0.0)) return OR_ERR_ARG;
+    double* x = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!x) return OR_ERR_ARG;
+    double mx = -INFINITY;
+    for (int i = 0; i < N; ++i) {
+        if (!isfinite(loglik[i])) { free(x); return OR_ERR_NUMERIC; }
+        x[i] = loglik[i] / lambda;
+        if (prior_w) x[i] += log(prior_w[i]);
+        if (x[i] > mx) mx = x[i];
+    }
+    if (!isfinite(mx)) { free(x); return OR_ERR_NUMERIC; }
+    double sum = 0.0, comp = 0.0;
+    for (int i = 0; i < N; ++i) {
+        x[i] = exp(x[i] - mx);
+        double t = sum + x[i];
+        if (fabs(sum) >= fabs(x[i])) comp += (sum - t) + x[i];
+        else comp += (x[i] - t) + sum;
+        sum = t;
+    }
+    double S = sum + comp;
+    double sq = 0.0;
+    for (int i = 0; i < N; ++i) {
+        w_out[i] = x[i] / S;
+        sq += w_out[i] * w_out[i];
+    }
+    if (stats) {
+        stats[0] = mx + log(S) - (prior_w ? 0.0 : log((double)N));
+        stats[1] = 1.0 / sq;
+    }
+    free(x);
+    return OR_OK;
+}
+
+/* Fraction bits of the quantised weights: b(N) = min(32, 52 - ceil(log2 N)),
+ * so every partial sum of the integers q_i stays below 2^53. */
+int or_resample_bits(int N)
+{
+    int c = 0;
+    while (((int64_t)1 << c) < (int64_t)N) ++c;
+    return 52 - c < 32 ? 52 - c : 32;
+}
+
+/* Systematic resampling on quantised weights.
+ *   q_i = rint(w_i * N * 2^b)       (one binary64 product, ties to even)
+ *   C_i = q_0 + ... + q_i           (integers below 2^53: exact)
+ *   u   = U >> (32 - b),  P_j = j * 2^b + u
+ *   idx_j = smallest i with C_i > P_j; if none, the last i with q_i > 0.
+ * This is systematic resampling with offset u / 2^b in [0,1) on the weights
+ * rounded to multiples of 2^-b particles. */
+int or_resample(int N, const double* w, uint32_t U, int32_t* idx)
+{
+    if (N < 1) return OR_ERR_ARG;
+    int b = or_resample_bits(N);
+    double scale = ldexp((double)N, b);
+    double* C = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!C) return OR_ERR_ARG;
+    double run = 0.0;
+    int last_positive = -1;
+    for (int i = 0; i < N; ++i) {
+        if (!(w[i] >= 0.0) || !isfinite(w[i])) { free(C); return OR_ERR_NUMERIC; }
+        double q = nearbyint(w[i] * scale);
+        if (q > 0.0) last_positive = i;
+        run += q;
+        C[i] = run;
+    }
+    if (last_positive < 0) { free(C); return OR_ERR_NUMERIC; }
+    double u = (double)(U >> (32 - b));
+    double step = ldexp(1.0, b);
+    int i = 0;
+    for (int j = 0; j < N; ++j) {
+        double P = (double)j * step + u;
+        while (i < N && !(C[i] > P)) ++i;
+        idx[j] = (i < N) ? i : last_positive;
+    }
+    free(C);
+    return OR_OK;
+}
+
+/* Full SIR update for one executed action a and received observation o.
+ *   s'_i = s_i + f_T([s_i, a, w_i])          w_i: given noise or stream 5,
+ *                                              counter (i, 0, 0)
+ *   l_i  = l([s'_i, a, o])
+ *   w'   = normalise(l / lambda, prior)
+ *   idx  = resample(w', U);  S_new_j = s'_{idx_j}
+ * Outputs may be NULL except S_new. */
+int or_update(const or_model* m, int N, const double* S, const double* prior_w,
+              int a_disc, const double* a_cont, const double* o, double lambda,
+              const double* noise, uint64_t seed, uint32_t U, int bf16,
+              double* S_prop, double* loglik, double* w_out, double* stats,
+              int32_t* idx, double* S_new)
+{
+    if (model_check(m) != OR_OK || N < 1) return OR_ERR_ARG;
+    if (mlp_check(m->l_layers, m->l_dims) != OR_OK) return OR_ERR_ARG;
+    if (m->l_dims[0] != m->d_s + action_width(m) + m->d_o || m->l_dims[m->l_layers] != 1) return OR_ERR_ARG;
+    if (m->n_actions > 0 ? (a_disc < 0 || a_disc >= m->n_actions) : !a_cont) return OR_ERR_ARG;
+    int d_s = m->d_s, aw = action_width(m);
+    double* sp = (double*)malloc(sizeof(double) * (size_t)N * d_s);
+    double* ll = (double*)malloc(sizeof(double) * (size_t)N);
+    double* wn = (double*)malloc(sizeof(double) * (size_t)N);
+    int32_t* ix = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+    if (!sp || !ll || !wn || !ix) { free(sp); free(ll); free(wn); free(ix); return OR_ERR_ARG; }
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i) {
+        double w[OR_MAX_WIDTH], x[OR_MAX_WIDTH], y[1];
+        if (noise) {
+            for (int j = 0; j < m->d_w; ++j) w[j] = noise[(size_t)i * m->d_w + j];
+        } else {
+            or_normals(seed, (uint32_t)i, 0u, 0u, OR_STREAM_UPDATE, m->d_w, w);
+        }
+        transition(m, S + (size_t)i * d_s, a_disc, a_cont, w, sp + (size_t)i * d_s, bf16);
+        for (int j = 0; j < d_s; ++j) x[j] = sp[(size_t)i * d_s + j];
+        put_action(m, x + d_s, a_disc, a_cont);
+        for (int j = 0; j < m->d_o; ++j) x[d_s + aw + j] = o[j];
+        mlp_forward(m->l_layers, m->l_dims, m->l_params, x, y, bf16);
+        ll[i] = y[0];
+    }
+    int rc = or_normalize(N, ll, prior_w, lambda, wn, stats);
+    if (rc == OR_OK) rc = or_resample(N, wn, U, ix);
+    if (rc == OR_OK) {
+        for (int j = 0; j < N; ++j)
+            for (int c = 0; c < d_s; ++c) S_new[(size_t)j * d_s + c] = sp[(size_t)ix[j] * d_s + c];
+        if (S_prop) memcpy(S_prop, sp, sizeof(double) * (size_t)N * d_s);
+        if (loglik) memcpy(loglik, ll, sizeof(double) * (size_t)N);
+        if (w_out) memcpy(w_out, wn, sizeof(double) * (size_t)N);
+        if (idx) memcpy(idx, ix, sizeof(int32_t) * (size_t)N);
+    }
+    free(sp); free(ll); free(wn); free(ix);
+    return rc;
+}
+
+/* Observation sampler (Eq. 5): o_r = f_Z([s'_r, a_r, w_Z,r]) for n rows;
+ * noise given or stream 4 with counter (row, 0, 0).  Actions: one per row. */
+int or_observe(const or_model* m, int n, const double* S, const int32_t* a_disc,
+               const double* a_cont, const double* noise, uint64_t seed, int bf16, double* O)
+{
+    if (n < 0 || mlp_check(m->z_layers, m->z_dims) != OR_OK) return OR_ERR_ARG;
+    int aw = action_width(m);
+    if (m->z_dims[0] != m->d_s + aw + m->d_wz || m->z_dims[m->z_layers] != m->d_o) return OR_ERR_ARG;
+    if (m->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < n; ++r) {
+        double x[OR_MAX_WIDTH], w[OR_MAX_WIDTH];
+        for (int j = 0; j < m->d_s; ++j) x[j] = S[(size_t)r * m->d_s + j];
+        put_action(m, x + m->d_s, a_disc ? a_disc[r] : 0, a_cont ? a_cont + (size_t)r * m->d_a : NULL);
+        if (noise) {
+            for (int j = 0; j < m->d_wz; ++j) w[j] = noise[(size_t)r * m->d_wz + j];
+        } else {
+            or_normals(seed, (uint32_t)r, 0u, 0u, OR_STREAM_OBS, m->d_wz, w);
+        }
+        for (int j = 0; j < m->d_wz; ++j) x[m->d_s + aw + j] = w[j];
+        mlp_forward(m->z_layers, m->z_dims, m->z_params, x, O + (size_t)r * m->d_o, bf16);
+    }
+    return OR_OK;
+}
+
+/* Transition draws for n given (state, action, noise) rows: s'_r. */
+int or_transition(const or_model* m, int n, const double* S, const int32_t* a_disc,
+                  const double* a_cont, const double* noise, int bf16, double* S_next)
+{
+    if (model_check(m) != OR_OK || n < 0) return OR_ERR_ARG;
+    if (m->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < n; ++r)
+        transition(m, S + (size_t)r * m->d_s, a_disc ? a_disc[r] : 0,
+                   a_cont ? a_cont + (size_t)r * m->d_a : NULL,
+                   noise + (size_t)r * m->d_w, S_next + (size_t)r * m->d_s, bf16);
+    return OR_OK;
+}
+
+size_t or_mlp_param_count(int n_layers, const int* dims)
+{
+    return mlp_param_count(n_layers, dims);
+}

@@ -1,0 +1,483 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+The paper prints no worked numeric example of its generators, weights or
+resampling, so every pin here is a closed form, an invariant, an independent
+library routine or an independent implementation:
+
+* Philox4x32-10 against rocRAND's engine run on the host;
+* networks against numpy matrix products, bfloat16 rounding against torch;
+* plan against the closed-form Gaussian propagation of a generator whose
+  ReLUs are all active (the network is then affine), and special cases
+  (H = 0, gamma = 0, constant state, common random numbers, the shift between
+  the two reward timings);
+* normalisation against scipy's logsumexp and exact special cases;
+* resampling against numpy's searchsorted, the copy-count bounds of
+  systematic resampling, exact unbiasedness over the offset, and a
+  count-based formulation;
+* the whole update against the exponential-tilting closed form of a
+  Gaussian proposal weighted by an affine log-likelihood.
+"""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+import scipy.special
+import torch
+
+import oracle
+import workloads
+from workloads import Model
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ----------------------------------------------------------------------------- RNG
+@pytest.fixture(scope="module")
+def rocrand_host():
+    if shutil.which("hipcc") is None:
+        pytest.skip("hipcc not available")
+    d = tempfile.mkdtemp()
+    exe = os.path.join(d, "rr")
+    subprocess.run(["hipcc", "-O1", "-x", "hip", "--offload-arch=gfx950", "-w",
+                    os.path.join(HERE, "rocrand_philox_host.cpp"), "-o", exe], check=True)
+    return exe
+
+
+@pytest.mark.parametrize("seed", [0x123456789ABCDEF, 1, 0xFFFFFFFFFFFFFFFF])
+def test_philox_matches_rocrand_engine(rocrand_host, seed):
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    # rocRAND's (subsequence, offset) move counter words 2-3 and 0-1; every word
+    # of the counter and of the key is exercised.
+    cases = [((0, 0), [0, 0, 0, 0]), ((0, 4), [1, 0, 0, 0]), ((1, 0), [0, 0, 1, 0]),
+             ((1 << 32, 0), [0, 0, 0, 1]), ((0, 4 << 32), [0, 1, 0, 0]),
+             ((0x00050003, 4 * 0x0000000700000009), [9, 7, 0x00050003, 0])]
+    for (sub, off), ctr in cases:
+        out = subprocess.run([rocrand_host, hex(seed), hex(sub), hex(off), "4"], check=True,
+                             capture_output=True, text=True).stdout.split()
+        ref = [int(x, 16) for x in out]
+        got = [int(x) for x in oracle.philox(ctr, key)]
+        assert got == ref, (hex(seed), ctr)
+
+
+def test_uniform_is_open_and_exact_in_binary32():
+    for x in [0, 1, 511, 512, 0x7FFFFFFF, 0xFFFFFFFF, 0x12345678]:
+        u = oracle.uniform(x)
+        assert 0.0 < u < 1.0
+        assert float(np.float32(u)) == u
+    assert oracle.uniform(0) == 2.0 ** -24
+    assert oracle.uniform(0xFFFFFFFF) == 1.0 - 2.0 ** -24
+
+
+def test_box_muller_moments():
+    z = np.concatenate([oracle.normals(77, i, 3, 5, 3, 16) for i in range(8000)])
+    n = z.size
+    assert abs(z.mean()) < 5 / np.sqrt(n)
+    assert abs(z.var() - 1.0) < 5 * np.sqrt(2.0 / n)
+    assert abs(scipy.stats.skew(z)) < 5 * np.sqrt(6.0 / n)
+    assert abs(scipy.stats.kurtosis(z)) < 5 * np.sqrt(24.0 / n)
+    # the two draws of a pair share the radius: z0^2 + z1^2 = -2 ln u0
+    w = oracle.philox([4, 0, 0, (3 << 16) | 0], [9, 0])
+    zz = oracle.normals(9, 4, 0, 0, 3, 4)
+    assert np.isclose(zz[0] ** 2 + zz[1] ** 2, -2 * np.log(oracle.uniform(w[0])), rtol=1e-13)
+    assert np.isclose(zz[2] ** 2 + zz[3] ** 2, -2 * np.log(oracle.uniform(w[2])), rtol=1e-13)
+
+
+def test_normals_are_prefix_consistent_and_counter_separated():
+    a = oracle.normals(5, 1, 2, 3, 3, 7)
+    b = oracle.normals(5, 1, 2, 3, 3, 16)
+    assert np.array_equal(a, b[:7])
+    assert not np.allclose(oracle.normals(5, 1, 2, 4, 3, 4), oracle.normals(5, 1, 2, 3, 3, 4))
+    assert not np.allclose(oracle.normals(5, 1, 2, 3, 4, 4), oracle.normals(5, 1, 2, 3, 3, 4))
+
+
+# ----------------------------------------------------------------------------- networks
+def _numpy_mlp(layers, X):
+    h = np.asarray(X, np.float64)
+    for j, (W, b) in enumerate(layers):
+        h = h @ np.asarray(W, np.float64).T + np.asarray(b, np.float64)
+        if j < len(layers) - 1:
+            h = np.maximum(h, 0.0)
+    return h
+
+
+@pytest.mark.parametrize("dims", [[1, 1], [3, 5, 2], [5, 4, 3, 1], [2, 5, 5, 5, 4], [13, 64, 64, 4]])
+def test_mlp_matches_numpy(dims):
+    rng = np.random.default_rng(sum(dims))
+    layers = workloads.random_mlp(rng, dims)
+    X = rng.standard_normal((37, dims[0]))
+    np.testing.assert_allclose(oracle.mlp(layers, X), _numpy_mlp(layers, X), rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.standard_normal(4000).astype(np.float32),
+                        np.float32([1.0, -1.0, 1.00390625, 1.01171875, 3.0e-30, 65504.0, 0.0])])
+    # exact ties in bfloat16: 1 + 2^-8 (-> 1), 1 + 3 * 2^-8 (-> 1 + 2^-6)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(oracle.round_bf16(x), ref)
+
+
+def test_mlp_bf16_mode_matches_numpy_with_rounded_operands():
+    rng = np.random.default_rng(4)
+    layers = workloads.random_mlp(rng, [6, 16, 16, 3])
+    X = rng.standard_normal((20, 6)).astype(np.float32)
+    rb = oracle.round_bf16
+    h = rb(X)
+    for j, (W, b) in enumerate(layers):
+        h = h @ rb(W).T + np.asarray(b, np.float64)
+        if j < len(layers) - 1:
+            h = rb(np.maximum(h, 0.0))
+    np.testing.assert_allclose(oracle.mlp(layers, X, bf16=True), h, rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------- affine generator
+def affine_model(rng, d_s=4, n_actions=5, d_a=0, d_w=4, d_o=2, width=32, in_scale=0.08,
+                 out_scale=0.05, bias=20.0, lik_scale=0.05):
+    """Networks whose hidden ReLUs stay active on the inputs used here (large
+    positive hidden biases, small first-layer weights), so that each network is
+    an affine map of its input.  The output bias is re-centred so that the
+    constant term of the affine map is small."""
+    aw = n_actions if n_actions > 0 else d_a
+
+    def net(d_in, d_out, first, last):
+        W1 = (rng.standard_normal((width, d_in)) * first).astype(np.float32)
+        b1 = np.full(width, bias, np.float32)
+        W2 = (rng.standard_normal((width, width)) * 0.02).astype(np.float32)
+        b2 = np.full(width, bias, np.float32)
+        W3 = (rng.standard_normal((d_out, width)) * last).astype(np.float32)
+        layers = [(W1, b1), (W2, b2), (W3, np.zeros(d_out, np.float32))]
+        _, c = composite(layers)
+        b3 = (-c + rng.standard_normal(d_out) * 0.1).astype(np.float32)
+        return [(W1, b1), (W2, b2), (W3, b3)]
+
+    m = Model(d_s=d_s, n_actions=n_actions, d_a=d_a, d_w=d_w, d_o=d_o, d_wz=d_o,
+              trans=net(d_s + aw + d_w, d_s, in_scale, out_scale),
+              obs=net(d_s + aw + d_o, d_o, in_scale, out_scale),
+              lik=net(d_s + aw + d_o, 1, in_scale, lik_scale))
+    return m
+
+
+def composite(layers):
+    """(A, c) with net(x) = A x + c when every ReLU is active."""
+    A = np.eye(layers[0][0].shape[1])
+    c = np.zeros(layers[0][0].shape[1])
+    for W, b in layers:
+        A = np.asarray(W, np.float64) @ A
+        c = np.asarray(W, np.float64) @ c + np.asarray(b, np.float64)
+    return A, c
+
+
+def split_transition(m):
+    A, c = composite(m.trans)
+    aw = m.action_width
+    As, Aa, Aw = A[:, :m.d_s], A[:, m.d_s:m.d_s + aw], A[:, m.d_s + aw:]
+    return np.eye(m.d_s) + As, Aa, Aw, c
+
+
+def test_affine_generator_one_step_is_affine():
+    rng = np.random.default_rng(10)
+    m = affine_model(rng)
+    F, B, C, c = split_transition(m)
+    S = rng.standard_normal((50, 4))
+    a = rng.integers(0, 5, 50)
+    w = rng.standard_normal((50, 4))
+    ref = S @ F.T + B[:, a].T + w @ C.T + c
+    np.testing.assert_allclose(oracle.transition(m, S, a, w), ref, rtol=1e-10, atol=1e-10)
+
+
+def closed_form_q(m, states, cands, gamma, goal):
+    """E[Q_k] under s_{t+1} = F s_t + B a_t + C w + c, w ~ N(0, I)."""
+    F, B, C, c = split_transition(m)
+    K, H = cands.shape[0], cands.shape[1]
+    out = np.zeros(K)
+    for k in range(K):
+        mu = np.asarray(states, np.float64).copy()      # [N, d_s], one mean per particle
+        Sig = np.zeros((m.d_s, m.d_s))
+        disc, acc = 1.0, np.zeros(mu.shape[0])
+        for t in range(H):
+            act = B[:, cands[k, t]] if m.n_actions > 0 else B @ cands[k, t]
+            mu = mu @ F.T + act + c
+            Sig = F @ Sig @ F.T + C @ C.T
+            acc += disc * -(((mu - goal) ** 2).sum(1) + np.trace(Sig))
+            disc *= gamma
+        out[k] = acc.mean()
+    return out
+
+
+@pytest.mark.parametrize("noise_source", ["philox", "explicit"])
+def test_plan_matches_gaussian_propagation(noise_source):
+    rng = np.random.default_rng(11)
+    m = affine_model(rng)
+    N, K, H = 3000, 4, 8
+    states = (rng.standard_normal((N, 4)) * 0.5).astype(np.float32)
+    cands = rng.integers(0, 5, (K, H)).astype(np.int32)
+    goal = np.array([1, 1, 0, 0], np.float32)
+    noise = None if noise_source == "philox" else rng.standard_normal((K, N, H, 4)).astype(np.float32)
+    Q, G = oracle.plan(m, states, cands, 0.9, goal, noise=noise, seed=1234, return_G=True)
+    ref = closed_form_q(m, states, cands, 0.9, goal)
+    sigma = G.std(axis=1) / np.sqrt(N)
+    assert np.all(np.abs(Q - ref) < 5 * sigma), (Q, ref, sigma)
+    # the MC error is small compared with the value itself
+    assert np.all(np.abs(Q - ref) < 0.05 * np.abs(ref))
+
+
+def test_plan_continuous_actions_gaussian_propagation():
+    rng = np.random.default_rng(12)
+    m = affine_model(rng, d_s=6, n_actions=0, d_a=3, d_w=6, d_o=3)
+    N, K, H = 3000, 3, 6
+    states = (rng.standard_normal((N, 6)) * 0.5).astype(np.float32)
+    cands = rng.uniform(-1, 1, (K, H, 3)).astype(np.float32)
+    goal = np.zeros(6, np.float32)
+    goal[:2] = 1
+    Q, G = oracle.plan(m, states, cands, 0.97, goal, seed=99, return_G=True)
+    ref = closed_form_q(m, states, cands, 0.97, goal)
+    assert np.all(np.abs(Q - ref) < 5 * G.std(axis=1) / np.sqrt(N))
+
+
+def test_plan_special_cases():
+    w = workloads.small(N=16, K=6, H=5)
+    m = w.model
+    # H = 0: nothing accumulates
+    Q0 = oracle.plan(m, w.states, w.cands[:, :0], w.gamma, w.goal, seed=1)
+    assert np.array_equal(Q0, np.zeros(6))
+    # gamma = 0: the first reward only, r_0 = R(s_1)
+    Qg, G = oracle.plan(m, w.states, w.cands, 0.0, w.goal, seed=1, return_G=True)
+    Q1 = oracle.plan(m, w.states, w.cands[:, :1], 0.7, w.goal, seed=1)
+    np.testing.assert_allclose(Qg, Q1, rtol=1e-15)
+    # constant state (zero output layer): Q = -mean ||s - g||^2 (1 - gamma^H) / (1 - gamma)
+    zero = Model(**{**m.__dict__, "trans": m.trans[:-1] + [(np.zeros_like(m.trans[-1][0]),
+                                                             np.zeros_like(m.trans[-1][1]))]})
+    Qz = oracle.plan(zero, w.states, w.cands, w.gamma, w.goal, seed=1)
+    d2 = ((w.states.astype(np.float64) - w.goal) ** 2).sum(1).mean()
+    np.testing.assert_allclose(Qz, -d2 * (1 - w.gamma ** 5) / (1 - w.gamma), rtol=1e-13)
+    # identical candidates under common random numbers give identical Q
+    same = np.repeat(w.cands[:1], 3, axis=0)
+    Qc = oracle.plan(m, w.states, same, w.gamma, w.goal, seed=5, crn=True)
+    assert Qc[0] == Qc[1] == Qc[2]
+    Qi = oracle.plan(m, w.states, same, w.gamma, w.goal, seed=5, crn=False)
+    assert Qi[0] != Qi[1]
+    # weighted belief: Q is the weighted mean of the per-particle returns
+    bw = np.random.default_rng(1).dirichlet(np.ones(16))
+    Qw, Gw = oracle.plan(m, w.states, w.cands, w.gamma, w.goal, belief_w=bw, seed=1, return_G=True)
+    np.testing.assert_allclose(Qw, Gw @ bw, rtol=1e-13)
+
+
+def test_reward_timing_shift_identity():
+    # reward of the acted-from state over H steps equals R(s_0) plus gamma times
+    # the arrival-reward return over the first H-1 steps (same noise).
+    w = workloads.small(N=20, K=5, H=6)
+    noise = workloads.explicit_plan_noise(w)
+    Qcur = oracle.plan(w.model, w.states, w.cands, w.gamma, w.goal, noise=noise, reward_at=1)
+    Qnext = oracle.plan(w.model, w.states, w.cands[:, :5], w.gamma, w.goal, noise=noise[:, :, :5], reward_at=0)
+    r0 = -((w.states.astype(np.float64) - w.goal) ** 2).sum(1).mean()
+    np.testing.assert_allclose(Qcur, r0 + w.gamma * Qnext, rtol=1e-12)
+
+
+def test_rollouts_subset_matches_full_plan():
+    w = workloads.small(N=12, K=7, H=4)
+    Q, G = oracle.plan(w.model, w.states, w.cands, w.gamma, w.goal, seed=w.plan_seed, return_G=True)
+    pairs = [(0, 0), (6, 11), (3, 5)]
+    g = oracle.rollouts(w.model, w.states, w.cands, w.gamma, w.goal, pairs, seed=w.plan_seed)
+    assert np.array_equal(g, np.array([G[k, i] for k, i in pairs]))
+
+
+# ----------------------------------------------------------------------------- normalisation
+def test_normalize_uniform_is_exact():
+    for N in [1, 3, 128, 4096, 5000]:
+        w, st = oracle.normalize(np.full(N, -3.25), lam=1.25)
+        assert np.all(w == 1.0 / N)
+        assert st[0] == pytest.approx(-3.25 / 1.25, abs=1e-15)
+        assert st[1] == pytest.approx(N, rel=1e-12)
+
+
+def test_normalize_against_logsumexp_and_invariances():
+    rng = np.random.default_rng(21)
+    ll = rng.standard_normal(1000) * 4
+    for lam in [1.0, 1.25]:
+        w, st = oracle.normalize(ll, lam=lam)
+        ref_logz = scipy.special.logsumexp(ll / lam) - np.log(1000)
+        assert st[0] == pytest.approx(ref_logz, rel=1e-13)
+        ref_w = scipy.special.softmax(ll / lam)
+        np.testing.assert_allclose(w, ref_w, rtol=1e-12)
+        assert abs(w.sum() - 1) <= 1001 * 2.0 ** -53
+        assert st[1] == pytest.approx(1.0 / (ref_w ** 2).sum(), rel=1e-12)
+        w2, st2 = oracle.normalize(ll + 37.5, lam=lam)
+        np.testing.assert_allclose(w2, w, rtol=1e-12)
+        assert st2[0] == pytest.approx(st[0] + 37.5 / lam, rel=1e-13)
+        w3, _ = oracle.normalize(ll / lam, lam=1.0)
+        np.testing.assert_allclose(w3, w, rtol=1e-12)
+    prior = rng.dirichlet(np.ones(1000))
+    w, st = oracle.normalize(ll, lam=1.0, prior_w=prior)
+    assert st[0] == pytest.approx(scipy.special.logsumexp(ll, b=prior), rel=1e-13)
+    np.testing.assert_allclose(w, scipy.special.softmax(ll + np.log(prior)), rtol=1e-12)
+
+
+def test_normalize_rejects_non_finite():
+    with pytest.raises(oracle.OracleError):
+        oracle.normalize(np.array([0.0, np.nan, 1.0]))
+    with pytest.raises(oracle.OracleError):
+        oracle.normalize(np.array([0.0, np.inf]))
+
+
+# ----------------------------------------------------------------------------- resampling
+def quantised_cumsum(w):
+    N = len(w)
+    b = oracle.resample_bits(N)
+    q = np.rint(np.asarray(w, np.float64) * (N * 2.0 ** b))
+    return np.cumsum(q), b
+
+
+def test_resample_bits():
+    assert oracle.resample_bits(1) == 32
+    assert oracle.resample_bits(8192) == 32
+    assert oracle.resample_bits(1 << 20) == 32
+    assert oracle.resample_bits((1 << 20) + 1) == 31
+    assert oracle.resample_bits(1 << 24) == 28
+
+
+def test_resample_uniform_is_identity_and_one_hot_is_constant():
+    for N in [1, 2, 5, 128, 4096, 8191]:
+        w = np.full(N, 1.0 / N)
+        for U in [0, 1, 0x80000000, 0xFFFFFFFF]:
+            assert np.array_equal(oracle.resample(w, U), np.arange(N))
+        oh = np.zeros(N)
+        oh[N // 3] = 1.0
+        assert np.all(oracle.resample(oh, 0x1234) == N // 3)
+
+
+@pytest.mark.parametrize("N", [3, 17, 128, 1000, 4096])
+def test_resample_matches_searchsorted_and_count_bounds(N):
+    rng = np.random.default_rng(N)
+    for trial in range(5):
+        w = rng.dirichlet(np.full(N, 0.3))
+        w[rng.integers(0, N, N // 4)] = 0.0
+        w /= w.sum()
+        U = int(rng.integers(0, 2**32))
+        idx = oracle.resample(w, U)
+        C, b = quantised_cumsum(w)
+        P = np.arange(N, dtype=np.float64) * 2.0 ** b + (U >> (32 - b))
+        ref = np.searchsorted(C, P, side="right")
+        last = np.nonzero(np.diff(np.concatenate([[0.0], C])) > 0)[0][-1]
+        ref = np.where(ref >= N, last, ref)
+        assert np.array_equal(idx, ref)
+        assert np.all(np.diff(idx) >= 0)
+        counts = np.bincount(idx, minlength=N)
+        assert counts.sum() == N
+        assert np.all(counts[w == 0] == 0)
+        top_edge = C[-1] != N * 2.0 ** b
+        inner = np.ones(N, bool)
+        if top_edge:
+            inner[last] = False
+        assert np.all(counts[inner] >= np.floor(N * w[inner] - 1e-9))
+        assert np.all(counts[inner] <= np.ceil(N * w[inner] + 1e-9))
+
+
+def test_resample_count_formulation():
+    # copies of particle i = ceil((C_i - u) / 2^b) - ceil((C_{i-1} - u) / 2^b)
+    rng = np.random.default_rng(5)
+    N = 300
+    w = rng.dirichlet(np.ones(N))
+    U = 0xDEADBEEF
+    C, b = quantised_cumsum(w)
+    u = U >> (32 - b)
+    Cm = np.concatenate([[0.0], C])
+    start = np.ceil((Cm - u) / 2.0 ** b).clip(0, N)
+    counts = np.diff(start).astype(int)
+    assert np.array_equal(np.bincount(oracle.resample(w, U), minlength=N), counts)
+
+
+def test_resample_is_exactly_unbiased_over_the_offset():
+    # averaging the copy count of particle i over every offset u in [0, 2^b)
+    # gives q_i / 2^b exactly; integrate the piecewise-constant count.
+    rng = np.random.default_rng(6)
+    N = 7
+    w = rng.dirichlet(np.ones(N))
+    C, b = quantised_cumsum(w)
+    q = np.diff(np.concatenate([[0.0], C]))
+    step = 2.0 ** b
+    # breakpoints of the count as a function of u: C_i mod 2^b
+    brk = np.unique(np.concatenate([[0.0, step], np.mod(C, step)]))
+    mean = np.zeros(N)
+    for lo, hi in zip(brk[:-1], brk[1:]):
+        if hi <= lo:
+            continue
+        U = int(lo) << (32 - b)
+        idx = oracle.resample(w, U)
+        mean += np.bincount(idx, minlength=N) * (hi - lo) / step
+    if C[-1] == N * step:
+        np.testing.assert_allclose(mean, q / step, rtol=0, atol=1e-9)
+
+
+def test_resample_rejects_zero_mass():
+    with pytest.raises(oracle.OracleError):
+        oracle.resample(np.zeros(5), 0)
+
+
+# ----------------------------------------------------------------------------- update
+def test_update_matches_exponential_tilting():
+    # all particles at one state: proposal s' ~ N(mu, C C^T); an affine
+    # likelihood l = c.s' + d tilts it to mean mu + C C^T c / lambda, and
+    # log E[exp(l / lambda)] = (c.mu + d) / lambda + c^T C C^T c / (2 lambda^2).
+    rng = np.random.default_rng(31)
+    m = affine_model(rng, width=32, in_scale=0.5, out_scale=1.0, lik_scale=0.5)
+    F, B, C, c = split_transition(m)
+    Al, cl = composite(m.lik)
+    N = 1 << 15
+    s0 = np.array([0.3, -0.2, 0.1, 0.5], np.float32)
+    states = np.repeat(s0[None, :], N, axis=0)
+    a = 2
+    o = np.array([0.25, -0.5], np.float32)
+    lam = 1.25
+    out = oracle.update(m, states, a, o, lam=lam, seed=77, U=0x9E3779B9)
+    mu = F @ s0 + B[:, a] + c
+    Sig = C @ C.T
+    grad = Al[0, :4]
+    dconst = Al[0, 4:4 + 5] @ np.eye(5)[a] + Al[0, 9:] @ o + cl[0]
+    tilted = mu + Sig @ grad / lam
+    wmean = out["w"] @ out["S_prop"]
+    sd = np.sqrt((out["w"][:, None] ** 2 * (out["S_prop"] - wmean) ** 2).sum(0))
+    assert np.all(np.abs(wmean - tilted) < 5 * sd + 1e-12), (wmean, tilted, sd)
+    assert np.linalg.norm(tilted - mu) > 10 * sd.max()  # the tilt is resolved
+    logz = (grad @ mu + dconst) / lam + grad @ Sig @ grad / (2 * lam ** 2)
+    ll = out["loglik"]
+    sd_logz = np.exp(ll / lam - (ll / lam).max()).std() / np.exp(ll / lam - (ll / lam).max()).mean() / np.sqrt(N)
+    assert abs(out["stats"][0] - logz) < 5 * sd_logz + 1e-12
+    # resampled particles are proposal particles, and their mean follows the weights
+    assert np.allclose(out["S_new"], out["S_prop"][out["idx"]])
+    assert np.all(np.abs(out["S_new"].mean(0) - wmean) < 5 * sd + 1e-3)
+
+
+def test_update_philox_noise_is_stream_5():
+    w = workloads.small(N=40)
+    o = oracle.draw_observation(w)
+    a = oracle.update(w.model, w.states, w.update_action, o, seed=w.update_seed, U=w.resample_u)
+    noise = np.stack([oracle.normals(w.update_seed, i, 0, 0, 5, w.model.d_w) for i in range(40)])
+    b = oracle.update(w.model, w.states, w.update_action, o, noise=noise, U=w.resample_u)
+    for key in ["S_prop", "loglik", "w", "stats", "idx", "S_new"]:
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_update_constant_likelihood_keeps_the_proposal_set():
+    w = workloads.small(N=64)
+    m = w.model
+    flat = Model(**{**m.__dict__, "lik": m.lik[:-1] + [(np.zeros_like(m.lik[-1][0]),
+                                                        np.full_like(m.lik[-1][1], 2.5))]})
+    out = oracle.update(flat, w.states, 2, np.zeros(2), seed=3, U=12345)
+    assert np.all(out["w"] == 1.0 / 64)
+    assert np.array_equal(out["idx"], np.arange(64))
+    assert np.array_equal(out["S_new"], out["S_prop"])
+    assert out["stats"][0] == pytest.approx(2.5)
+
+
+def test_observe_is_affine_for_the_affine_sampler():
+    rng = np.random.default_rng(41)
+    m = affine_model(rng)
+    A, c = composite(m.obs)
+    S = rng.standard_normal((30, 4))
+    a = rng.integers(0, 5, 30)
+    wz = rng.standard_normal((30, 2))
+    X = np.concatenate([S, np.eye(5)[a], wz], axis=1)
+    np.testing.assert_allclose(oracle.observe(m, S, a, noise=wz), X @ A.T + c, rtol=1e-10, atol=1e-10)
