@@ -1,0 +1,191 @@
+"""Throughput of the VOiLA planning hot path on one MI355X.
+
+One step = plan (every candidate sequence x every belief particle x the
+horizon, through the transition network) + one SIR belief update of the whole
+belief, on the "realistic" synthetic workload: state dim 16, continuous
+actions in [-1,1]^4, noise dim 16, observation dim 32, three hidden layers of
+width 256 in every network, N = 4096 particles, K = 1024 candidates, H = 20,
+gamma = 0.99, binary32 network arithmetic.  Inputs are resident on the GPU
+before timing starts.
+
+Prints one JSON line: `value` is rollout steps per second of the whole step
+(K * N * H / step time); the update's particles per second, the plan-only rate,
+the bfloat16 form of the same workload, the roofline of the rollout kernel
+and the FP64 oracle's rate on the host cores are reported beside it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "generator rollout steps/s + belief-update particles/s, BF16 vs FP32 at tol"
+PEAK_F32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def trans_flops_per_step(model):
+    """2 * MACs of one transition-network evaluation, one-hot inputs excluded."""
+    dims = [model.d_s + model.d_a + model.d_w] + [int(W.shape[0]) for W, _ in model.trans]
+    return 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+
+
+def cpu_baseline(w, n_cands):
+    """The FP64 oracle on a bounded sample: n_cands candidates x all particles x H,
+    plus one full belief update; rate in rollout steps per second."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    pairs = [(k, i) for k in range(n_cands) for i in range(w.N)]
+    t0 = time.perf_counter()
+    oracle.rollouts(w.model, w.states, w.cands, w.gamma, w.goal, pairs, seed=w.plan_seed)
+    t_plan = time.perf_counter() - t0
+    o = np.zeros(w.model.d_o)
+    t0 = time.perf_counter()
+    oracle.update(w.model, w.states, w.update_action, o, lam=w.lam, seed=w.update_seed, U=w.resample_u)
+    t_upd = time.perf_counter() - t0
+    steps = len(pairs) * w.H
+    return {"value": steps / t_plan, "unit": "rollout steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_cands} candidates x {w.N} particles x {w.H} steps ({steps} rollout steps) "
+                      f"in {t_plan:.2f} s; one {w.N}-particle update in {t_upd:.3f} s "
+                      f"({w.N / t_upd:.3g} particles/s)",
+            "update_particles_per_s": w.N / t_upd}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-cands", type=int, default=2, help="candidates in the oracle's timed sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2606_19729_amd as V
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    w = workloads.realistic()
+    N, K, H = w.N, w.K, w.H
+    print(f"[bench] workload realistic N={N} K={K} H={H}", file=sys.stderr, flush=True)
+    m = V.Model(w.model, compute="f32")
+    S = torch.as_tensor(w.states, device=dev)
+    C = torch.as_tensor(w.cands, device=dev)
+    q = torch.empty(K, dtype=torch.float32, device=dev)
+    ws_plan = m.plan_workspace(N, K, H)
+    ws_upd = m.update_workspace(N)
+    obs = np.zeros(w.model.d_o, np.float32)
+    upd_out = {"states": torch.empty((N, w.model.d_s), dtype=torch.float32, device=dev),
+               "idx": torch.empty(N, dtype=torch.int32, device=dev),
+               "w": torch.empty(N, dtype=torch.float64, device=dev),
+               "loglik": torch.empty(N, dtype=torch.float32, device=dev),
+               "prop": torch.empty((N, w.model.d_s), dtype=torch.float32, device=dev),
+               "stats": torch.empty(2, dtype=torch.float64, device=dev)}
+    # the observation of the step: the observation network applied to the
+    # proposal of the workload's true particle
+    V.update(m, S, w.update_action, obs, lam=w.lam, seed=w.update_seed, U=w.resample_u, out=upd_out,
+             workspace=ws_upd)
+    s_true = upd_out["prop"][w.true_index:w.true_index + 1].clone()
+    obs = V.observe(m, s_true, w.update_action, noise=torch.as_tensor(w.obs_noise[None], device=dev))
+    torch.cuda.synchronize()
+    obs = obs.cpu().numpy()[0]
+
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def step(seed, rec=None):
+        e0, e1, e2 = (ev(), ev(), ev()) if rec is not None else (None, None, None)
+        if e0: e0.record(stream)
+        V.plan(m, S, C, w.gamma, w.goal, seed=seed, q_out=q, workspace=ws_plan)
+        if e1: e1.record(stream)
+        V.update(m, S, w.update_action, obs, lam=w.lam, seed=seed + 1, U=w.resample_u, out=upd_out,
+                 workspace=ws_upd)
+        if e2: e2.record(stream)
+        if rec is not None:
+            rec.append((e0, e1, e2))
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(2000 + 2 * i, rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in rec]))
+    upd_ms = float(np.mean([b.elapsed_time(c) for _, b, c in rec]))
+    ms_per_step = wall * 1000.0 / args.steps
+    steps_per_step = K * N * H
+    flops = trans_flops_per_step(w.model) * steps_per_step
+    achieved = flops / (plan_ms / 1000.0) / 1e12
+    print(f"[bench] f32: {ms_per_step:.2f} ms/step, plan {plan_ms:.2f} ms, update {upd_ms:.3f} ms",
+          file=sys.stderr, flush=True)
+
+    result = {
+        "metric": METRIC,
+        "value": steps_per_step / (ms_per_step / 1000.0),
+        "unit": "rollout steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "realistic: d_s=16, continuous d_a=4, d_w=16, d_o=32, three hidden layers "
+                               "of 256 (ReLU) per network, N=4096, K=1024, H=20, gamma=0.99; plan + one "
+                               "belief update per step", "N": N, "K": K, "H": H},
+        "plan_steps_per_s": steps_per_step / (plan_ms / 1000.0),
+        "plan_ms": plan_ms,
+        "update_ms": upd_ms,
+        "update_particles_per_s": N / (upd_ms / 1000.0),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_F32_TFLOPS, "traffic": None,
+                     "kernel": "plan_kernel (f32, realistic)"},
+    }
+
+    if not args.no_bf16:
+        mb = V.Model(w.model, compute="bf16")
+        wsb = mb.plan_workspace(N, K, H)
+        qb = torch.empty(K, dtype=torch.float32, device=dev)
+        for i in range(args.warmup):
+            V.plan(mb, S, C, w.gamma, w.goal, seed=w.plan_seed, q_out=qb, workspace=wsb)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        for i in range(args.steps):
+            V.plan(mb, S, C, w.gamma, w.goal, seed=w.plan_seed, q_out=qb, workspace=wsb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1) / args.steps
+        # accuracy of the bf16 form against the binary32 form on the same noise
+        V.plan(m, S, C, w.gamma, w.goal, seed=w.plan_seed, q_out=q, workspace=ws_plan)
+        torch.cuda.synchronize()
+        qf, qbh = q.cpu().numpy().astype(np.float64), qb.cpu().numpy().astype(np.float64)
+        result["bf16"] = {"plan_steps_per_s": steps_per_step / (bms / 1000.0), "plan_ms": bms,
+                          "speedup_vs_f32_plan": plan_ms / bms,
+                          "max_rel_q_diff_vs_f32": float(np.max(np.abs(qbh - qf) / np.abs(qf))),
+                          "roofline_frac_bf16_peak": flops / (bms / 1000.0) / 1e12 / PEAK_BF16_TFLOPS}
+        print(f"[bench] bf16 plan {bms:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_cands)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

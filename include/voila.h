@@ -1,0 +1,223 @@
+/*
+ * voila.h -- C ABI of the VOiLA planning hot path on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the two data-parallel halves of online POMDP planning
+ * with learned generative models (Hoerger et al., "VOiLA: Vectorized Online
+ * Planning with Learned Diffusion Models for POMDP Agents"):
+ *
+ *   plan    Monte-Carlo returns of open-loop candidate action sequences from a
+ *           particle belief, simulated through the distilled transition sampler
+ *           s' = f_T(s, a, w_T), w_T ~ N(0, I) (Sec. 4.2, Eq. 2; Sec. 4.3), with
+ *           the expected reward R(b, a) estimated as an average over belief
+ *           particles (Sec. 2.1; Sec. 2.2 below Eq. 1) and discounted by gamma^t.
+ *   update  The SIR belief update of Sec. 3: proposal particles from f_T,
+ *           weights proportional to exp(l(s', a, o) / lambda) from the learned
+ *           likelihood (Sec. 4.2, "Likelihood Model"), normalised in binary64,
+ *           then systematic resampling.
+ *   observe The observation sampler z = f_Z(s', a, w_Z) (Sec. 4.2, Eq. 5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named d_* are DEVICE pointers (memory of the model's device);
+ *   pointers named h_* are HOST pointers.  The caller owns every buffer it
+ *   passes; the library owns only the model object it creates.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  Compute
+ *   entry points only enqueue work on it: they do not allocate and do not
+ *   synchronise, so results are ready when the stream's earlier work and the
+ *   enqueued kernels have finished.  Entry points marked [sync] synchronise.
+ * - Argument errors are reported synchronously, before anything is enqueued,
+ *   and leave all outputs untouched.  Numeric failures detected on the device
+ *   (a non-finite log-likelihood, all weights zero) are reported through the
+ *   optional device status word d_status (set to a nonzero VOILA_ERR_NUMERIC,
+ *   never cleared by the library) and leave the outputs of that call
+ *   undefined.
+ * - voila_last_error() returns a thread-local description of the last
+ *   argument error.
+ * - Networks are multilayer perceptrons: affine layers with ReLU between them
+ *   and a linear output layer; each layer is given as nn.Linear stores it,
+ *   W[out][in] row-major and b[out].  Input vectors are concatenated as
+ *   [s, a, w] for the samplers and [s', a, o] for the likelihood; a discrete
+ *   action enters as a one-hot vector over the action set (0-based index).
+ * - Counter-based noise: draws come from Philox4x32-10 (Salmon et al., SC'11)
+ *   keyed by the 64-bit seed (low word first).  Block j of four draws of
+ *   particle i uses the counter (i, c1, t, (stream << 16) | j): plan uses
+ *   stream 3 with c1 = candidate index (0 under common random numbers) and t =
+ *   step; observe uses stream 4 with (row, 0, 0); update uses stream 5 with
+ *   (i, 0, 0).  Each word x gives u = (2 * (x >> 9) + 1) * 2^-24, and the pairs
+ *   (u0, u1), (u2, u3) give draws 4j..4j+3 by Box-Muller:
+ *   sqrt(-2 ln u_a) * {cos, sin}(2 pi u_b).
+ */
+#ifndef VOILA_H
+#define VOILA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t voila_status_t;
+#define VOILA_OK 0
+#define VOILA_ERR_INVALID_ARG 1  /* bad pointer, size or value                     */
+#define VOILA_ERR_UNSUPPORTED 2  /* network shape or size with no compiled kernel  */
+#define VOILA_ERR_WORKSPACE 3    /* workspace missing or too small                 */
+#define VOILA_ERR_DEVICE 4       /* the HIP runtime reported an error              */
+#define VOILA_ERR_NUMERIC 5      /* non-finite likelihood or zero total weight     */
+
+#define VOILA_F32 0   /* binary32 network arithmetic (MFMA 32x32x2 f32)               */
+#define VOILA_BF16 1  /* bfloat16 operands, binary32 accumulation (MFMA 32x32x16 bf16) */
+
+typedef struct voila_model_s* voila_model_t;
+
+/* One network.  h_dims has n_layers + 1 entries (input width first); h_W[l]
+ * and h_b[l] are host arrays of dims[l+1] * dims[l] and dims[l+1] floats. */
+typedef struct {
+    int32_t n_layers;
+    const int32_t* h_dims;
+    const float* const* h_W;
+    const float* const* h_b;
+} voila_mlp_desc_t;
+
+/* The three networks and the spaces they act on.
+ *   trans: [d_s + a_width + d_w] -> ... -> d_s   (state increment, s' = s + f_T)
+ *   obs:   [d_s + a_width + d_wz] -> ... -> d_o  (may have n_layers == 0: absent)
+ *   lik:   [d_s + a_width + d_o] -> ... -> 1     (may have n_layers == 0: absent)
+ * a_width = n_actions for a discrete action set (n_actions > 0), else d_a. */
+typedef struct {
+    int32_t d_s, n_actions, d_a, d_w, d_o, d_wz;
+    voila_mlp_desc_t trans, obs, lik;
+    int32_t compute;  /* VOILA_F32 or VOILA_BF16 */
+} voila_model_desc_t;
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t voila_version(void);
+/* Static description of a status code. */
+const char* voila_status_string(voila_status_t status);
+/* Thread-local description of the last argument error ("" if none). */
+const char* voila_last_error(void);
+
+/* [sync] Packs the networks into the on-device layout of the compiled kernels
+ * (MFMA operand fragments; one-hot action columns folded into per-action
+ * first-layer biases; bfloat16 rounding to nearest even for VOILA_BF16) on
+ * device `device` and returns an owned handle.  Host arrays are only read
+ * during the call.  Fails with VOILA_ERR_UNSUPPORTED for shapes without a
+ * compiled kernel. */
+voila_status_t voila_model_create(const voila_model_desc_t* h_desc, int32_t device, voila_model_t* out);
+/* [sync] Frees a model (NULL is accepted). */
+voila_status_t voila_model_destroy(voila_model_t model);
+
+/* ---------------------------------------------------------------------------
+ * plan: Q_k = sum_i w_i G_ik,  G_ik = sum_{t<H} gamma^t r_t  (Sec. 2.1, 2.2, 4.3)
+ * For candidate k and particle i: s_0 = S_i, s_{t+1} = s_t + f_T([s_t, a_kt, w]),
+ * r_t = -||s_{t+1} - g||^2 (reward_at = 0, default) or -||s_t - g||^2
+ * (reward_at = 1).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double gamma;           /* discount, 0 <= gamma <= 1                        */
+    const float* h_goal;    /* host [d_s] goal g of the reward                  */
+    uint64_t seed;          /* Philox key of the rollout noise                  */
+    int32_t crn;            /* 1: common random numbers across candidates       */
+    int32_t reward_at;      /* 0: reward on arrival s_{t+1}; 1: on s_t          */
+    const float* d_noise;   /* device [K][N][H][d_w] explicit noise, or NULL    */
+} voila_plan_opts_t;
+
+/* Bytes of device workspace voila_plan needs for these sizes. */
+size_t voila_plan_workspace_size(voila_model_t model, int32_t N, int32_t K, int32_t H);
+
+/* d_states [N][d_s] float; d_belief_w [N] double normalised weights or NULL
+ * (uniform 1/N); d_cands int32 [K][H] action indices (discrete) or float
+ * [K][H][d_a] (continuous); d_q_out [K] float; d_returns_out [K][N] float or
+ * NULL.  1 <= N, 0 <= K, 0 <= H.  A discrete action index outside
+ * [0, n_actions) sets *d_status (if given) to VOILA_ERR_INVALID_ARG and is
+ * replaced by action 0 (no memory outside the model is read). */
+voila_status_t voila_plan(voila_model_t model, const float* d_states, const double* d_belief_w, int32_t N,
+                          const void* d_cands, int32_t K, int32_t H, const voila_plan_opts_t* h_opts,
+                          void* d_workspace, size_t workspace_bytes, float* d_q_out, float* d_returns_out,
+                          int32_t* d_status, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * update: b' = tau(b, a, o) by sequential importance resampling (Sec. 3)
+ *   s'_i = s_i + f_T([s_i, a, w_i])                 (proposal)
+ *   l_i  = l([s'_i, a, o])                          (learned log-likelihood)
+ *   x_i  = l_i / lambda (+ log w_i under a weighted prior)
+ *   w'_i = exp(x_i - max x) / sum_j exp(x_j - max x)     (binary64)
+ *   stats = {log evidence = max x + log sum exp(x - max x) (- log N if uniform),
+ *            effective sample size = 1 / sum w'_i^2}
+ *   systematic resampling of w' with offset U (see voila_resample);
+ *   S_new_j = s'_{idx_j}, uniform weights.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double lambda;          /* likelihood temperature, > 0                       */
+    uint64_t seed;          /* Philox key of the proposal noise                  */
+    uint32_t resample_u;    /* 32-bit offset word of systematic resampling       */
+    const float* d_noise;   /* device [N][d_w] explicit proposal noise, or NULL  */
+} voila_update_opts_t;
+
+/* Bytes of device workspace voila_update needs for N particles. */
+size_t voila_update_workspace_size(voila_model_t model, int32_t N);
+
+/* h_action: host pointer to one int32 action index (discrete) or d_a floats
+ * (continuous); h_obs: host [d_o] floats.  Outputs: d_states_out [N][d_s]
+ * float (required); optional d_idx_out [N] int32, d_w_out [N] double (weights
+ * before resampling), d_loglik_out [N] float, d_prop_out [N][d_s] float
+ * (proposal particles), d_stats_out [2] double, d_status (int32 status word).
+ * 1 <= N <= voila_update_max_particles(). */
+voila_status_t voila_update(voila_model_t model, const float* d_states, const double* d_prior_w, int32_t N,
+                            const void* h_action, const float* h_obs, const voila_update_opts_t* h_opts,
+                            void* d_workspace, size_t workspace_bytes, float* d_states_out, int32_t* d_idx_out,
+                            double* d_w_out, float* d_loglik_out, float* d_prop_out, double* d_stats_out,
+                            int32_t* d_status, void* stream);
+
+/* Largest N accepted by voila_update / voila_normalize / voila_resample. */
+int32_t voila_update_max_particles(void);
+
+/* ---------------------------------------------------------------------------
+ * Stages of update, exported on their own.
+ * ------------------------------------------------------------------------- */
+/* Weight normalisation of given log-likelihoods d_loglik [N] float:
+ * w'_i and stats exactly as in voila_update.  d_prior_w [N] double or NULL. */
+voila_status_t voila_normalize(const float* d_loglik, const double* d_prior_w, int32_t N, double lambda,
+                               double* d_w_out, double* d_stats_out, int32_t* d_status, void* stream);
+
+/* Fraction bits b(N) = min(32, 52 - ceil(log2 N)) of the quantised weights. */
+int32_t voila_resample_bits(int32_t N);
+
+/* Systematic resampling of normalised binary64 weights d_w [N]:
+ *   q_i = rint(w_i * N * 2^b)   (ties to even; exact integers)
+ *   C_i = q_0 + ... + q_i       (binary64, exact because C_i < 2^53)
+ *   u = U >> (32 - b), P_j = j * 2^b + u
+ *   idx_j = min{ i : C_i > P_j }, or the last i with q_i > 0 if none.
+ * Writes d_idx_out [N] int32; if d_src and d_dst are both non-NULL also
+ * gathers rows: d_dst[j][:] = d_src[idx_j][:] for rows of `row_floats`
+ * floats.  Negative, non-finite or all-zero weights set d_status. */
+voila_status_t voila_resample(const double* d_w, int32_t N, uint32_t U, int32_t* d_idx_out,
+                              const float* d_src, float* d_dst, int32_t row_floats, int32_t* d_status,
+                              void* stream);
+
+/* ---------------------------------------------------------------------------
+ * observe: o_r = f_Z([s'_r, a, w_Z,r]) (Sec. 4.2, Eq. 5) for n rows sharing
+ * one action; noise explicit (d_noise [n][d_wz]) or Philox stream 4 with
+ * counter (r, 0, 0) under `seed`.  d_states [n][d_s] float, d_obs_out
+ * [n][d_o] float; the workspace holds the first-layer bias with the action
+ * folded in.
+ * ------------------------------------------------------------------------- */
+size_t voila_observe_workspace_size(voila_model_t model);
+voila_status_t voila_observe(voila_model_t model, const float* d_states, int32_t n, const void* h_action,
+                             uint64_t seed, const float* d_noise, void* d_workspace, size_t workspace_bytes,
+                             float* d_obs_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Test hook: the counter-based draws the kernels consume.  Fills
+ * d_out [n][d] float with the normals of counters (c0_base + r, c1, c2) of
+ * `stream` for r < n, and d_words [n][4 * ceil(d/4)] uint32 (may be NULL) with
+ * the raw Philox words.
+ * ------------------------------------------------------------------------- */
+voila_status_t voila_philox_normals(uint64_t seed, uint32_t c0_base, uint32_t c1, uint32_t c2, uint32_t stream_id,
+                                    int32_t n, int32_t d, float* d_out, uint32_t* d_words, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOILA_H */

@@ -1,0 +1,348 @@
+"""Python binding of libvoila: the VOiLA planning hot path on MI355X (gfx950).
+
+Argument marshalling only.  Every step of plan / update / observe runs in the
+HIP kernels of ``libvoila.so`` (built by ``build.py``); torch provides device
+memory and the stream.  There is no CPU fallback: importing this package
+raises if the library has not been built, and every call raises
+``VoilaError`` when the library reports a failure.
+
+Functions mirror include/voila.h:
+
+* ``Model(desc, compute="f32"|"bf16", device=0)``  voila_model_create
+* ``plan(model, states, cands, gamma, goal, ...)`` -> Q [K] (and G [K, N])
+* ``update(model, states, action, obs, ...)``      -> dict of the new belief
+* ``normalize(loglik, lam, prior_w)``              -> (w, stats)
+* ``resample(w, U, src=None)``                     -> idx (and gathered rows)
+* ``observe(model, states, action, ...)``          -> o [n, d_o]
+* ``philox_normals(seed, c0, c1, c2, stream, n, d)`` -> (normals, words)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvoila.so")
+
+VOILA_OK = 0
+VOILA_ERR_INVALID_ARG = 1
+VOILA_ERR_UNSUPPORTED = 2
+VOILA_ERR_WORKSPACE = 3
+VOILA_ERR_DEVICE = 4
+VOILA_ERR_NUMERIC = 5
+VOILA_F32 = 0
+VOILA_BF16 = 1
+
+
+class VoilaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"voila status {status}: {msg}")
+        self.status = status
+
+
+class _Mlp(ctypes.Structure):
+    _fields_ = [("n_layers", c_int32), ("h_dims", POINTER(c_int32)),
+                ("h_W", POINTER(POINTER(c_float))), ("h_b", POINTER(POINTER(c_float)))]
+
+
+class _ModelDesc(ctypes.Structure):
+    _fields_ = [("d_s", c_int32), ("n_actions", c_int32), ("d_a", c_int32), ("d_w", c_int32),
+                ("d_o", c_int32), ("d_wz", c_int32), ("trans", _Mlp), ("obs", _Mlp), ("lik", _Mlp),
+                ("compute", c_int32)]
+
+
+class _PlanOpts(ctypes.Structure):
+    _fields_ = [("gamma", c_double), ("h_goal", POINTER(c_float)), ("seed", c_uint64), ("crn", c_int32),
+                ("reward_at", c_int32), ("d_noise", c_void_p)]
+
+
+class _UpdateOpts(ctypes.Structure):
+    _fields_ = [("lambda_", c_double), ("seed", c_uint64), ("resample_u", c_uint32), ("d_noise", c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2606_19729_amd/build.py "
+                          "(the HIP library is the only implementation; there is no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = c_void_p
+    L.voila_version.restype = c_int32
+    L.voila_status_string.argtypes = [c_int32]
+    L.voila_status_string.restype = ctypes.c_char_p
+    L.voila_last_error.restype = ctypes.c_char_p
+    L.voila_model_create.argtypes = [POINTER(_ModelDesc), c_int32, POINTER(vp)]
+    L.voila_model_create.restype = c_int32
+    L.voila_model_destroy.argtypes = [vp]
+    L.voila_model_destroy.restype = c_int32
+    L.voila_plan_workspace_size.argtypes = [vp, c_int32, c_int32, c_int32]
+    L.voila_plan_workspace_size.restype = c_size_t
+    L.voila_plan.argtypes = [vp, vp, vp, c_int32, vp, c_int32, c_int32, POINTER(_PlanOpts), vp, c_size_t,
+                             vp, vp, vp, vp]
+    L.voila_plan.restype = c_int32
+    L.voila_update_workspace_size.argtypes = [vp, c_int32]
+    L.voila_update_workspace_size.restype = c_size_t
+    L.voila_update.argtypes = [vp, vp, vp, c_int32, vp, POINTER(c_float), POINTER(_UpdateOpts), vp, c_size_t,
+                               vp, vp, vp, vp, vp, vp, vp, vp]
+    L.voila_update.restype = c_int32
+    L.voila_update_max_particles.restype = c_int32
+    L.voila_normalize.argtypes = [vp, vp, c_int32, c_double, vp, vp, vp, vp]
+    L.voila_normalize.restype = c_int32
+    L.voila_resample_bits.argtypes = [c_int32]
+    L.voila_resample_bits.restype = c_int32
+    L.voila_resample.argtypes = [vp, c_int32, c_uint32, vp, vp, vp, c_int32, vp, vp]
+    L.voila_resample.restype = c_int32
+    L.voila_observe_workspace_size.argtypes = [vp]
+    L.voila_observe_workspace_size.restype = c_size_t
+    L.voila_observe.argtypes = [vp, vp, c_int32, vp, c_uint64, vp, vp, c_size_t, vp, vp]
+    L.voila_observe.restype = c_int32
+    L.voila_philox_normals.argtypes = [c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int32, c_int32, vp,
+                                       vp, vp]
+    L.voila_philox_normals.restype = c_int32
+    return L
+
+
+lib = _load()
+
+# the exported C symbols (checked by the test-suite against include/voila.h)
+EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_model_create",
+            "voila_model_destroy", "voila_plan_workspace_size", "voila_plan", "voila_update_workspace_size",
+            "voila_update", "voila_update_max_particles", "voila_normalize", "voila_resample_bits",
+            "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_philox_normals"]
+
+
+def _check(st):
+    if st != VOILA_OK:
+        raise VoilaError(st, lib.voila_last_error().decode() or lib.voila_status_string(st).decode())
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise VoilaError(VOILA_ERR_INVALID_ARG, f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise VoilaError(VOILA_ERR_INVALID_ARG, f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise VoilaError(VOILA_ERR_INVALID_ARG, f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise VoilaError(VOILA_ERR_INVALID_ARG, f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def version() -> int:
+    return lib.voila_version()
+
+
+def resample_bits(N: int) -> int:
+    return lib.voila_resample_bits(int(N))
+
+
+def max_update_particles() -> int:
+    return lib.voila_update_max_particles()
+
+
+class Model:
+    """Packed device copy of the transition / observation / likelihood networks.
+
+    ``desc`` has attributes d_s, n_actions, d_a, d_w, d_o, d_wz and lists
+    ``trans``, ``obs``, ``lik`` of (W [out, in], b [out]) float32 arrays.
+    """
+
+    def __init__(self, desc, compute: str = "f32", device: int = 0):
+        import numpy as np
+        self.desc = desc
+        self.compute = compute
+        self.device = device
+        self.handle = c_void_p()
+        keep = []
+
+        def mlp(layers):
+            m = _Mlp()
+            if not layers:
+                m.n_layers = 0
+                return m
+            dims = [int(layers[0][0].shape[1])] + [int(W.shape[0]) for W, _ in layers]
+            dims_arr = (c_int32 * len(dims))(*dims)
+            Ws = [np.ascontiguousarray(np.asarray(W, np.float32)) for W, _ in layers]
+            bs = [np.ascontiguousarray(np.asarray(b, np.float32)) for _, b in layers]
+            W_arr = (POINTER(c_float) * len(Ws))(*[w.ctypes.data_as(POINTER(c_float)) for w in Ws])
+            b_arr = (POINTER(c_float) * len(bs))(*[b.ctypes.data_as(POINTER(c_float)) for b in bs])
+            keep.extend([dims_arr, Ws, bs, W_arr, b_arr])
+            m.n_layers = len(layers)
+            m.h_dims = dims_arr
+            m.h_W = W_arr
+            m.h_b = b_arr
+            return m
+
+        d = _ModelDesc()
+        d.d_s, d.n_actions, d.d_a = desc.d_s, desc.n_actions, desc.d_a
+        d.d_w, d.d_o, d.d_wz = desc.d_w, desc.d_o, desc.d_wz
+        d.trans, d.obs, d.lik = mlp(desc.trans), mlp(desc.obs), mlp(desc.lik)
+        d.compute = {"f32": VOILA_F32, "bf16": VOILA_BF16}[compute]
+        _check(lib.voila_model_create(ctypes.byref(d), int(device), ctypes.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            lib.voila_model_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_device(self):
+        return torch.device("cuda", self.device)
+
+    def plan_workspace(self, N, K, H):
+        n = lib.voila_plan_workspace_size(self.handle, int(N), int(K), int(H))
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.torch_device)
+
+    def update_workspace(self, N):
+        n = lib.voila_update_workspace_size(self.handle, int(N))
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.torch_device)
+
+    def observe_workspace(self):
+        n = lib.voila_observe_workspace_size(self.handle)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.torch_device)
+
+
+def plan(model: Model, states, cands, gamma, goal, belief_w=None, seed=0, crn=False, reward_at=0, noise=None,
+         return_G=False, q_out=None, G_out=None, workspace=None, status=None, stream=None):
+    """Q [K] float32 (and G [K, N]) of candidate action sequences."""
+    d = model.desc
+    N = int(states.shape[0])
+    _dev(states, torch.float32, (N, d.d_s), "states")
+    if d.n_actions > 0:
+        _dev(cands, torch.int32, None, "cands")
+        K, H = int(cands.shape[0]), int(cands.shape[1])
+    else:
+        _dev(cands, torch.float32, None, "cands")
+        K, H = int(cands.shape[0]), int(cands.shape[1])
+        if cands.dim() != 3 or cands.shape[2] != d.d_a:
+            raise VoilaError(VOILA_ERR_INVALID_ARG, "continuous cands must be [K, H, d_a]")
+    if belief_w is not None:
+        _dev(belief_w, torch.float64, (N,), "belief_w")
+    if noise is not None:
+        _dev(noise, torch.float32, (K, N, H, d.d_w), "noise")
+    goal_arr = (c_float * d.d_s)(*[float(x) for x in goal])
+    opts = _PlanOpts(float(gamma), goal_arr, int(seed) & (2**64 - 1), int(bool(crn)), int(reward_at),
+                     _ptr(noise))
+    q = q_out if q_out is not None else torch.empty(K, dtype=torch.float32, device=states.device)
+    G = None
+    if return_G:
+        G = G_out if G_out is not None else torch.empty((K, N), dtype=torch.float32, device=states.device)
+    ws = workspace if workspace is not None else model.plan_workspace(N, K, H)
+    _check(lib.voila_plan(model.handle, _ptr(states), _ptr(belief_w), N, _ptr(cands), K, H, ctypes.byref(opts),
+                          _ptr(ws), ws.numel(), _ptr(q), _ptr(G), _ptr(status), _stream(stream)))
+    return (q, G) if return_G else q
+
+
+def _action_arg(model, action):
+    d = model.desc
+    if d.n_actions > 0:
+        return (c_int32 * 1)(int(action))
+    vals = [float(x) for x in (action.tolist() if hasattr(action, "tolist") else action)]
+    if len(vals) != d.d_a:
+        raise VoilaError(VOILA_ERR_INVALID_ARG, f"continuous action must have {d.d_a} values")
+    return (c_float * d.d_a)(*vals)
+
+
+def update(model: Model, states, action, obs, lam=1.0, prior_w=None, seed=0, U=0, noise=None, want_idx=True,
+           want_w=True, want_loglik=True, want_prop=True, out=None, workspace=None, status=None, stream=None):
+    """SIR belief update; returns dict(states, idx, w, loglik, prop, stats)."""
+    d = model.desc
+    N = int(states.shape[0])
+    _dev(states, torch.float32, (N, d.d_s), "states")
+    if prior_w is not None:
+        _dev(prior_w, torch.float64, (N,), "prior_w")
+    if noise is not None:
+        _dev(noise, torch.float32, (N, d.d_w), "noise")
+    obs_vals = [float(x) for x in (obs.tolist() if hasattr(obs, "tolist") else obs)]
+    if len(obs_vals) != d.d_o:
+        raise VoilaError(VOILA_ERR_INVALID_ARG, f"observation must have {d.d_o} values")
+    obs_arr = (c_float * d.d_o)(*obs_vals)
+    dev = states.device
+    o = out if out is not None else {}
+    res = {
+        "states": o.get("states", torch.empty((N, d.d_s), dtype=torch.float32, device=dev)),
+        "idx": o.get("idx", torch.empty(N, dtype=torch.int32, device=dev)) if want_idx else None,
+        "w": o.get("w", torch.empty(N, dtype=torch.float64, device=dev)) if want_w else None,
+        "loglik": o.get("loglik", torch.empty(N, dtype=torch.float32, device=dev)) if want_loglik else None,
+        "prop": o.get("prop", torch.empty((N, d.d_s), dtype=torch.float32, device=dev)) if want_prop else None,
+        "stats": o.get("stats", torch.empty(2, dtype=torch.float64, device=dev)),
+    }
+    opts = _UpdateOpts(float(lam), int(seed) & (2**64 - 1), int(U) & 0xFFFFFFFF, _ptr(noise))
+    ws = workspace if workspace is not None else model.update_workspace(N)
+    _check(lib.voila_update(model.handle, _ptr(states), _ptr(prior_w), N, ctypes.cast(_action_arg(model, action),
+                            c_void_p), obs_arr, ctypes.byref(opts), _ptr(ws), ws.numel(), _ptr(res["states"]),
+                            _ptr(res["idx"]), _ptr(res["w"]), _ptr(res["loglik"]), _ptr(res["prop"]),
+                            _ptr(res["stats"]), _ptr(status), _stream(stream)))
+    return res
+
+
+def normalize(loglik, lam=1.0, prior_w=None, status=None, stream=None):
+    """(w [N] float64, stats [2] float64) of weights proportional to prior * exp(l / lam)."""
+    N = int(loglik.shape[0])
+    _dev(loglik, torch.float32, (N,), "loglik")
+    if prior_w is not None:
+        _dev(prior_w, torch.float64, (N,), "prior_w")
+    w = torch.empty(N, dtype=torch.float64, device=loglik.device)
+    st = torch.empty(2, dtype=torch.float64, device=loglik.device)
+    _check(lib.voila_normalize(_ptr(loglik), _ptr(prior_w), N, float(lam), _ptr(w), _ptr(st), _ptr(status),
+                               _stream(stream)))
+    return w, st
+
+
+def resample(w, U, src=None, status=None, stream=None):
+    """Systematic resampling indices [N] int32 (and src rows gathered by them)."""
+    N = int(w.shape[0])
+    _dev(w, torch.float64, (N,), "w")
+    idx = torch.empty(N, dtype=torch.int32, device=w.device)
+    dst = None
+    rf = 0
+    if src is not None:
+        _dev(src, torch.float32, None, "src")
+        if src.shape[0] != N:
+            raise VoilaError(VOILA_ERR_INVALID_ARG, "src must have N rows")
+        rf = int(src.numel() // N)
+        dst = torch.empty_like(src)
+    _check(lib.voila_resample(_ptr(w), N, int(U) & 0xFFFFFFFF, _ptr(idx), _ptr(src), _ptr(dst), rf, _ptr(status),
+                              _stream(stream)))
+    return (idx, dst) if src is not None else idx
+
+
+def observe(model: Model, states, action, seed=0, noise=None, workspace=None, out=None, stream=None):
+    """o [n, d_o] float32 from the observation network."""
+    d = model.desc
+    n = int(states.shape[0])
+    _dev(states, torch.float32, (n, d.d_s), "states")
+    if noise is not None:
+        _dev(noise, torch.float32, (n, d.d_wz), "noise")
+    o = out if out is not None else torch.empty((n, d.d_o), dtype=torch.float32, device=states.device)
+    ws = workspace if workspace is not None else model.observe_workspace()
+    _check(lib.voila_observe(model.handle, _ptr(states), n, ctypes.cast(_action_arg(model, action), c_void_p),
+                             int(seed) & (2**64 - 1), _ptr(noise), _ptr(ws), ws.numel(), _ptr(o), _stream(stream)))
+    return o
+
+
+def philox_normals(seed, c0, c1, c2, stream_id, n, d, device=0, stream=None):
+    """(normals [n, d] float32, words [n, 4 * ceil(d / 4)] int32 view of the uint32 words)."""
+    dev = torch.device("cuda", device)
+    out = torch.empty((n, d), dtype=torch.float32, device=dev)
+    words = torch.empty((n, 4 * ((d + 3) // 4)), dtype=torch.int32, device=dev)
+    _check(lib.voila_philox_normals(int(seed) & (2**64 - 1), int(c0), int(c1), int(c2), int(stream_id), int(n),
+                                    int(d), _ptr(out), _ptr(words), _stream(stream)))
+    return out, words

@@ -1,0 +1,715 @@
+// abi.hip -- the extern "C" entry points of include/voila.h: argument checks,
+// packing of the networks into MFMA fragment order, workspace carving and
+// kernel launches.  Nothing here computes a result on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/voila.h"
+#include "kernels.hpp"
+
+using namespace voila;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+voila_status_t fail(voila_status_t st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define VOILA_CHECK_HIP(expr)                                                            \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(VOILA_ERR_DEVICE, std::string(#expr) + ": " + \
+                                                                hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Round a binary32 value to bfloat16 (nearest, ties to even) and back.
+float bf16_round(float v) {
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return v;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+uint16_t bf16_bits(float v) {
+    float r = bf16_round(v);
+    uint32_t u;
+    std::memcpy(&u, &r, 4);
+    return (uint16_t)(u >> 16);
+}
+
+struct HostNet {
+    int n_layers = 0;
+    std::vector<int> dims;
+    std::vector<const float*> W, b;
+    bool present() const { return n_layers > 0; }
+    int width() const { return dims[1]; }
+    int out() const { return dims[n_layers]; }
+    float w(int l, int o, int c) const { return W[l][(size_t)o * dims[l] + c]; }
+};
+
+// Input column of first-layer slot si of lane group g (-1: padding).
+struct SlotMap {
+    int d_s, d_ain, d_w, col_a, col_w;
+    int operator()(int si, int g) const {
+        const int SS = state_slots(d_s), SA = action_slots(d_ain), SW = noise_slots(d_w);
+        if (si < SS) {
+            int f = 2 * si + g;
+            return f < d_s ? f : -1;
+        }
+        si -= SS;
+        if (si < SA) {
+            int f = 2 * si + g;
+            return f < d_ain ? col_a + f : -1;
+        }
+        si -= SA;
+        if (si < SW) {
+            int f = noise_feature(si, g);
+            return f < d_w ? col_w + f : -1;
+        }
+        return -1;
+    }
+};
+
+// Output feature held by row r of the output tile (feature 2 i + g sits at out_row(i, g)).
+int row_feature(int r) {
+    int i = (r / 8) * 4 + (r % 4), g = (r / 4) % 2;
+    return 2 * i + g;
+}
+
+// Packs one network into a blob: fragments of every layer in the order the
+// kernels consume them, then the biases.  b0_variants holds n_var rows of
+// `width` first-layer biases.
+std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, const SlotMap& map,
+                           const std::vector<float>& b0_variants, int n_var, NetBlob& nb) {
+    const int W = n.width(), HT = W / 32, NHID = n.n_layers - 1, KP = kper(dt);
+    const int esz = dt == DT_F32 ? 4 : 2;
+    const size_t fb = (size_t)64 * KP * esz;
+    const int IN_KS = in_slots_per_group / KP, HID_KS = 16 * HT / KP;
+    const size_t nf0 = (size_t)IN_KS * HT, nfh = (size_t)HID_KS * HT, nfo = HID_KS;
+    const size_t off_f0 = 0;
+    const size_t off_fh = off_f0 + nf0 * fb;
+    const size_t off_fo = off_fh + (size_t)(NHID - 1) * nfh * fb;
+    const size_t off_b0 = align_up(off_fo + nfo * fb, 16);
+    const size_t off_bh = align_up(off_b0 + (size_t)n_var * W * 4, 16);
+    const size_t off_bo = align_up(off_bh + (size_t)(NHID - 1) * W * 4, 16);
+    const size_t total = align_up(off_bo + 32 * 4, 16);
+    std::vector<char> blob(total, 0);
+    auto put = [&](size_t frag_off, size_t frag, int lane, int j, float v) {
+        size_t e = (frag * 64 + lane) * KP + j;
+        char* p = blob.data() + frag_off + e * esz;
+        if (dt == DT_F32) {
+            std::memcpy(p, &v, 4);
+        } else {
+            uint16_t h = bf16_bits(v);
+            std::memcpy(p, &h, 2);
+        }
+    };
+    auto hidden_in = [](int ri, int g) { return 32 * (ri / 16) + out_row(ri % 16, g); };
+    for (int c = 0; c < IN_KS; ++c)
+        for (int t = 0; t < HT; ++t)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < KP; ++j) {
+                    int col = map(c * KP + j, lane / 32);
+                    put(off_f0, (size_t)c * HT + t, lane, j, col >= 0 ? n.w(0, 32 * t + lane % 32, col) : 0.0f);
+                }
+    for (int l = 1; l <= NHID - 1; ++l)
+        for (int c = 0; c < HID_KS; ++c)
+            for (int t = 0; t < HT; ++t)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < KP; ++j)
+                        put(off_fh + (size_t)(l - 1) * nfh * fb, (size_t)c * HT + t, lane, j,
+                            n.w(l, 32 * t + lane % 32, hidden_in(c * KP + j, lane / 32)));
+    const int L = NHID;
+    for (int c = 0; c < HID_KS; ++c)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int j = 0; j < KP; ++j) {
+                int f = row_feature(lane % 32);
+                put(off_fo, c, lane, j, f < n.out() ? n.w(L, f, hidden_in(c * KP + j, lane / 32)) : 0.0f);
+            }
+    std::memcpy(blob.data() + off_b0, b0_variants.data(), (size_t)n_var * W * 4);
+    for (int l = 1; l <= NHID - 1; ++l) std::memcpy(blob.data() + off_bh + (size_t)(l - 1) * W * 4, n.b[l], (size_t)W * 4);
+    float bo[32];
+    for (int r = 0; r < 32; ++r) {
+        int f = row_feature(r);
+        bo[r] = f < n.out() ? n.b[L][f] : 0.0f;
+    }
+    std::memcpy(blob.data() + off_bo, bo, sizeof(bo));
+    nb.base = nullptr;
+    nb.bytes = (uint32_t)total;
+    nb.off_f0 = (uint32_t)off_f0;
+    nb.off_fh = (uint32_t)off_fh;
+    nb.off_fo = (uint32_t)off_fo;
+    nb.off_b0 = (uint32_t)off_b0;
+    nb.off_bh = (uint32_t)off_bh;
+    nb.off_bo = (uint32_t)off_bo;
+    nb.b0_stride = (uint32_t)W;
+    return blob;
+}
+
+// First-layer columns [c0, c0 + nf) of a network (rounded to bfloat16 for
+// bfloat16 models), row-major [width][nf], for folding fixed inputs into the bias.
+std::vector<float> fold_columns(const HostNet& n, int c0, int nf, int dt) {
+    const int W = n.width();
+    std::vector<float> out((size_t)W * nf);
+    for (int o = 0; o < W; ++o)
+        for (int c = 0; c < nf; ++c) {
+            float v = n.w(0, o, c0 + c);
+            out[(size_t)o * nf + c] = dt == DT_BF16 ? bf16_round(v) : v;
+        }
+    return out;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct voila_model_s {
+    int device = 0, shape = -1, dt = DT_F32, cus = 1;
+    int d_s = 0, n_actions = 0, d_a = 0, d_w = 0, d_o = 0, d_wz = 0, width = 0, n_hidden = 0;
+    bool has_obs = false, has_lik = false;
+    char* mem = nullptr;
+    NetBlob trans_plan{}, trans_upd{}, obs{}, lik{};
+    const float* fold_w_trans = nullptr;
+    const float* fold_b_trans = nullptr;
+    const float* fold_w_obs = nullptr;
+    const float* fold_b_obs = nullptr;
+    const float* fold_w_lik = nullptr;
+    const float* fold_b_lik = nullptr;
+    int nf_trans = 0, nf_obs = 0, nf_lik = 0;
+    int plan_bpc = 1, prop_bpc = 1, obs_bpc = 1;
+    int action_width() const { return n_actions > 0 ? n_actions : d_a; }
+};
+
+extern "C" {
+
+int32_t voila_version(void) { return 100; }
+
+const char* voila_status_string(voila_status_t s) {
+    switch (s) {
+        case VOILA_OK: return "ok";
+        case VOILA_ERR_INVALID_ARG: return "invalid argument";
+        case VOILA_ERR_UNSUPPORTED: return "unsupported shape or size";
+        case VOILA_ERR_WORKSPACE: return "workspace missing or too small";
+        case VOILA_ERR_DEVICE: return "HIP runtime error";
+        case VOILA_ERR_NUMERIC: return "non-finite likelihood or zero total weight";
+        default: return "unknown status";
+    }
+}
+
+const char* voila_last_error(void) { return g_last_error.c_str(); }
+
+static voila_status_t read_net(const voila_mlp_desc_t& d, HostNet& n, const char* name) {
+    n = HostNet();
+    if (d.n_layers == 0) return VOILA_OK;
+    if (d.n_layers < 2 || !d.h_dims || !d.h_W || !d.h_b)
+        return fail(VOILA_ERR_INVALID_ARG, std::string(name) + ": needs >= 2 layers and non-NULL arrays");
+    n.n_layers = d.n_layers;
+    for (int l = 0; l <= d.n_layers; ++l) {
+        if (d.h_dims[l] < 1) return fail(VOILA_ERR_INVALID_ARG, std::string(name) + ": non-positive width");
+        n.dims.push_back(d.h_dims[l]);
+    }
+    for (int l = 0; l < d.n_layers; ++l) {
+        if (!d.h_W[l] || !d.h_b[l]) return fail(VOILA_ERR_INVALID_ARG, std::string(name) + ": NULL layer array");
+        n.W.push_back(d.h_W[l]);
+        n.b.push_back(d.h_b[l]);
+    }
+    for (int l = 1; l < d.n_layers; ++l)
+        if (n.dims[l] != n.dims[1]) return fail(VOILA_ERR_UNSUPPORTED, std::string(name) + ": hidden widths differ");
+    return VOILA_OK;
+}
+
+voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device, voila_model_t* out) {
+    if (!desc || !out) return fail(VOILA_ERR_INVALID_ARG, "NULL descriptor or output handle");
+    *out = nullptr;
+    if (desc->compute != VOILA_F32 && desc->compute != VOILA_BF16)
+        return fail(VOILA_ERR_INVALID_ARG, "compute must be VOILA_F32 or VOILA_BF16");
+    HostNet T, Z, L;
+    voila_status_t st;
+    if ((st = read_net(desc->trans, T, "trans")) != VOILA_OK) return st;
+    if ((st = read_net(desc->obs, Z, "obs")) != VOILA_OK) return st;
+    if ((st = read_net(desc->lik, L, "lik")) != VOILA_OK) return st;
+    if (!T.present()) return fail(VOILA_ERR_INVALID_ARG, "the transition network is required");
+    const int aw = desc->n_actions > 0 ? desc->n_actions : desc->d_a;
+    if (desc->d_s < 1 || desc->n_actions < 0 || desc->d_a < 0 || desc->d_w < 0 || desc->d_o < 0 || desc->d_wz < 0)
+        return fail(VOILA_ERR_INVALID_ARG, "negative or zero dimension");
+    if (T.dims[0] != desc->d_s + aw + desc->d_w || T.out() != desc->d_s)
+        return fail(VOILA_ERR_INVALID_ARG, "trans dims must be [d_s + a_width + d_w, ..., d_s]");
+    if (Z.present() && (Z.dims[0] != desc->d_s + aw + desc->d_wz || Z.out() != desc->d_o))
+        return fail(VOILA_ERR_INVALID_ARG, "obs dims must be [d_s + a_width + d_wz, ..., d_o]");
+    if (L.present() && (L.dims[0] != desc->d_s + aw + desc->d_o || L.out() != 1))
+        return fail(VOILA_ERR_INVALID_ARG, "lik dims must be [d_s + a_width + d_o, ..., 1]");
+    int shape = -1;
+    for (int s = 0; s < kNumShapes; ++s) {
+        const ShapeInfo& si = shape_info(s);
+        bool ok = si.d_s == desc->d_s && si.n_actions == desc->n_actions &&
+                  (desc->n_actions > 0 || si.d_a == desc->d_a) && si.d_w == desc->d_w &&
+                  si.width == T.width() && si.n_hidden == T.n_layers - 1;
+        if (Z.present()) ok = ok && si.d_wz == desc->d_wz && si.d_o == desc->d_o && Z.width() == si.width &&
+                              Z.n_layers - 1 == si.n_hidden;
+        if (L.present()) ok = ok && si.d_o == desc->d_o && L.width() == si.width && L.n_layers - 1 == si.n_hidden;
+        if (ok) {
+            shape = s;
+            break;
+        }
+    }
+    if (shape < 0) return fail(VOILA_ERR_UNSUPPORTED, "no compiled kernel for this network shape");
+
+    int ndev = 0;
+    VOILA_CHECK_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(VOILA_ERR_INVALID_ARG, "device index out of range");
+    DeviceGuard guard(device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+
+    voila_model_s* m = new voila_model_s();
+    m->device = device;
+    m->shape = shape;
+    m->dt = desc->compute;
+    m->d_s = desc->d_s;
+    m->n_actions = desc->n_actions;
+    m->d_a = desc->n_actions > 0 ? 0 : desc->d_a;
+    m->d_w = desc->d_w;
+    m->d_o = desc->d_o;
+    m->d_wz = desc->d_wz;
+    m->width = T.width();
+    m->n_hidden = T.n_layers - 1;
+    m->has_obs = Z.present();
+    m->has_lik = L.present();
+    const int dt = m->dt, W = m->width;
+
+    // first-layer bias variants of the plan: one per discrete action (the
+    // one-hot column folded in), or the plain bias for continuous actions
+    std::vector<float> b0_plan;
+    int n_var = 1;
+    if (m->n_actions > 0) {
+        n_var = m->n_actions;
+        for (int a = 0; a < m->n_actions; ++a)
+            for (int o = 0; o < W; ++o) {
+                float wv = T.w(0, o, m->d_s + a);
+                b0_plan.push_back(T.b[0][o] + (dt == DT_BF16 ? bf16_round(wv) : wv));
+            }
+    } else {
+        b0_plan.assign(T.b[0], T.b[0] + W);
+    }
+    std::vector<float> b0_plain_T(T.b[0], T.b[0] + W);
+    SlotMap map_plan{m->d_s, m->d_a, m->d_w, m->d_s, m->d_s + aw};
+    SlotMap map_upd{m->d_s, 0, m->d_w, m->d_s, m->d_s + aw};
+    std::vector<std::vector<char>> blobs;
+    blobs.push_back(pack_net(T, dt, plan_in_slots(shape, dt), map_plan, b0_plan, n_var, m->trans_plan));
+    blobs.push_back(pack_net(T, dt, update_in_slots(shape, dt), map_upd, b0_plain_T, 1, m->trans_upd));
+    if (Z.present()) {
+        std::vector<float> b0(Z.b[0], Z.b[0] + W);
+        SlotMap mz{m->d_s, 0, m->d_wz, m->d_s, m->d_s + aw};
+        blobs.push_back(pack_net(Z, dt, obs_in_slots(shape, dt), mz, b0, 1, m->obs));
+    } else {
+        blobs.emplace_back();
+    }
+    if (L.present()) {
+        std::vector<float> b0(L.b[0], L.b[0] + W);
+        SlotMap ml{m->d_s, 0, 0, m->d_s, m->d_s};
+        blobs.push_back(pack_net(L, dt, lik_in_slots(shape, dt), ml, b0, 1, m->lik));
+    } else {
+        blobs.emplace_back();
+    }
+    std::vector<std::vector<float>> folds;
+    m->nf_trans = aw;
+    folds.push_back(fold_columns(T, m->d_s, aw, dt));
+    folds.push_back(b0_plain_T);
+    if (Z.present()) {
+        m->nf_obs = aw;
+        folds.push_back(fold_columns(Z, m->d_s, aw, dt));
+        folds.push_back(std::vector<float>(Z.b[0], Z.b[0] + W));
+    } else {
+        folds.emplace_back();
+        folds.emplace_back();
+    }
+    if (L.present()) {
+        m->nf_lik = aw + m->d_o;
+        folds.push_back(fold_columns(L, m->d_s, aw + m->d_o, dt));
+        folds.push_back(std::vector<float>(L.b[0], L.b[0] + W));
+    } else {
+        folds.emplace_back();
+        folds.emplace_back();
+    }
+    size_t total = 0;
+    std::vector<size_t> offs;
+    for (auto& b : blobs) {
+        offs.push_back(total);
+        total = align_up(total + b.size(), 256);
+    }
+    for (auto& f : folds) {
+        offs.push_back(total);
+        total = align_up(total + f.size() * 4, 256);
+    }
+    if (hipMalloc(&m->mem, total) != hipSuccess) {
+        delete m;
+        return fail(VOILA_ERR_DEVICE, "hipMalloc of the packed model failed");
+    }
+    std::vector<char> host(total, 0);
+    for (size_t i = 0; i < blobs.size(); ++i)
+        if (!blobs[i].empty()) std::memcpy(host.data() + offs[i], blobs[i].data(), blobs[i].size());
+    for (size_t i = 0; i < folds.size(); ++i)
+        if (!folds[i].empty()) std::memcpy(host.data() + offs[blobs.size() + i], folds[i].data(), folds[i].size() * 4);
+    if (hipMemcpy(m->mem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(m->mem);
+        delete m;
+        return fail(VOILA_ERR_DEVICE, "upload of the packed model failed");
+    }
+    m->trans_plan.base = m->mem + offs[0];
+    m->trans_upd.base = m->mem + offs[1];
+    m->obs.base = m->mem + offs[2];
+    m->lik.base = m->mem + offs[3];
+    m->fold_w_trans = reinterpret_cast<const float*>(m->mem + offs[4]);
+    m->fold_b_trans = reinterpret_cast<const float*>(m->mem + offs[5]);
+    m->fold_w_obs = reinterpret_cast<const float*>(m->mem + offs[6]);
+    m->fold_b_obs = reinterpret_cast<const float*>(m->mem + offs[7]);
+    m->fold_w_lik = reinterpret_cast<const float*>(m->mem + offs[8]);
+    m->fold_b_lik = reinterpret_cast<const float*>(m->mem + offs[9]);
+
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->cus = prop.multiProcessorCount;
+    m->plan_bpc = plan_blocks_per_cu(shape, dt);
+    m->prop_bpc = propose_blocks_per_cu(shape, dt);
+    m->obs_bpc = observe_blocks_per_cu(shape, dt);
+    *out = m;
+    return VOILA_OK;
+}
+
+voila_status_t voila_model_destroy(voila_model_t m) {
+    if (!m) return VOILA_OK;
+    {
+        DeviceGuard guard(m->device);
+        if (m->mem) (void)hipFree(m->mem);
+    }
+    delete m;
+    return VOILA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+static size_t plan_ws(int N, int K) {
+    const size_t n_tiles = ((size_t)N + 31) / 32;
+    return align_up((size_t)K * n_tiles * sizeof(float), 256);
+}
+
+size_t voila_plan_workspace_size(voila_model_t model, int32_t N, int32_t K, int32_t H) {
+    (void)model;
+    (void)H;
+    if (N < 1 || K < 0) return 0;
+    return plan_ws(N, K);
+}
+
+voila_status_t voila_plan(voila_model_t m, const float* d_states, const double* d_belief_w, int32_t N,
+                          const void* d_cands, int32_t K, int32_t H, const voila_plan_opts_t* o, void* ws,
+                          size_t ws_bytes, float* d_q_out, float* d_returns_out, int32_t* d_status, void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!o) return fail(VOILA_ERR_INVALID_ARG, "NULL options");
+    if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
+    if (K < 0 || H < 0) return fail(VOILA_ERR_INVALID_ARG, "K and H must be >= 0");
+    if ((long long)K * N > (1LL << 31) - 1 || (long long)K * H > (1LL << 31) - 1)
+        return fail(VOILA_ERR_UNSUPPORTED, "K * N and K * H must fit in 31 bits");
+    if (!(o->gamma >= 0.0 && o->gamma <= 1.0)) return fail(VOILA_ERR_INVALID_ARG, "gamma must lie in [0, 1]");
+    if (!o->h_goal) return fail(VOILA_ERR_INVALID_ARG, "NULL goal");
+    if (o->reward_at != 0 && o->reward_at != 1) return fail(VOILA_ERR_INVALID_ARG, "reward_at must be 0 or 1");
+    if (K == 0) return VOILA_OK;
+    if (!d_states || !d_q_out || (!d_cands && H > 0)) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    if (m->d_s > 32) return fail(VOILA_ERR_UNSUPPORTED, "d_s > 32");
+    if (!ws || ws_bytes < plan_ws(N, K)) return fail(VOILA_ERR_WORKSPACE, "plan workspace too small");
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    const int n_tiles = (N + 31) / 32;
+    PlanParams p{};
+    p.net = m->trans_plan;
+    p.states = d_states;
+    p.belief_w = d_belief_w;
+    p.cands = d_cands;
+    p.noise = o->d_noise;
+    p.returns = d_returns_out;
+    p.partials = reinterpret_cast<float*>(ws);
+    p.status = d_status;
+    p.N = N;
+    p.K = K;
+    p.H = H;
+    p.n_tiles = n_tiles;
+    p.gamma = o->gamma;
+    p.key0 = (uint32_t)(o->seed & 0xffffffffu);
+    p.key1 = (uint32_t)(o->seed >> 32);
+    p.crn = o->crn ? 1 : 0;
+    p.reward_at = o->reward_at;
+    for (int j = 0; j < 32; ++j) p.goal[j] = j < m->d_s ? o->h_goal[j] : 0.0f;
+    const long units = (long)K * n_tiles;
+    const long want = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+    const long cap = (long)m->cus * m->plan_bpc;
+    const int blocks = (int)(want < cap ? want : cap);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    VOILA_CHECK_HIP(launch_plan(m->shape, m->dt, p, blocks, s));
+    QReduceParams q{};
+    q.partials = p.partials;
+    q.q = d_q_out;
+    q.K = K;
+    q.n_tiles = n_tiles;
+    q.scale = d_belief_w ? 1.0f : (float)(1.0 / (double)N);
+    VOILA_CHECK_HIP(launch_q_reduce(q, s));
+    return VOILA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// update
+// ---------------------------------------------------------------------------
+int32_t voila_update_max_particles(void) { return kNormResMaxN; }
+
+int32_t voila_resample_bits(int32_t N) {
+    if (N < 1) return 0;
+    int c = 0;
+    while ((1LL << c) < (long long)N) ++c;
+    return 52 - c < 32 ? 52 - c : 32;
+}
+
+namespace {
+struct UpdateWs {
+    float* b0_trans;
+    float* b0_lik;
+    double* x;
+    float* prop;
+    size_t bytes;
+};
+UpdateWs carve_update(char* base, int width, int N, int d_s) {
+    UpdateWs w{};
+    size_t off = 0;
+    w.b0_trans = reinterpret_cast<float*>(base + off);
+    off = align_up(off + (size_t)width * 4, 256);
+    w.b0_lik = reinterpret_cast<float*>(base + off);
+    off = align_up(off + (size_t)width * 4, 256);
+    w.x = reinterpret_cast<double*>(base + off);
+    off = align_up(off + (size_t)N * 8, 256);
+    w.prop = reinterpret_cast<float*>(base + off);
+    off = align_up(off + (size_t)N * d_s * 4, 256);
+    w.bytes = off;
+    return w;
+}
+
+voila_status_t fold_vector(voila_model_t m, const void* h_action, const float* h_obs, bool with_obs, FoldParams& f) {
+    int nf = 0;
+    if (m->n_actions > 0) {
+        int a = *reinterpret_cast<const int32_t*>(h_action);
+        if (a < 0 || a >= m->n_actions) return fail(VOILA_ERR_INVALID_ARG, "action index out of range");
+        for (int j = 0; j < m->n_actions; ++j) f.v[nf++] = j == a ? 1.0f : 0.0f;
+    } else {
+        const float* a = reinterpret_cast<const float*>(h_action);
+        for (int j = 0; j < m->d_a; ++j) {
+            if (!std::isfinite(a[j])) return fail(VOILA_ERR_INVALID_ARG, "non-finite action");
+            f.v[nf++] = m->dt == DT_BF16 ? bf16_round(a[j]) : a[j];
+        }
+    }
+    if (with_obs)
+        for (int j = 0; j < m->d_o; ++j) {
+            if (!std::isfinite(h_obs[j])) return fail(VOILA_ERR_INVALID_ARG, "non-finite observation");
+            f.v[nf++] = m->dt == DT_BF16 ? bf16_round(h_obs[j]) : h_obs[j];
+        }
+    f.nf = nf;
+    f.width = m->width;
+    return VOILA_OK;
+}
+}  // namespace
+
+size_t voila_update_workspace_size(voila_model_t m, int32_t N) {
+    if (!m || N < 1) return 0;
+    return carve_update(nullptr, m->width, N, m->d_s).bytes;
+}
+
+voila_status_t voila_update(voila_model_t m, const float* d_states, const double* d_prior_w, int32_t N,
+                            const void* h_action, const float* h_obs, const voila_update_opts_t* o, void* ws,
+                            size_t ws_bytes, float* d_states_out, int32_t* d_idx_out, double* d_w_out,
+                            float* d_loglik_out, float* d_prop_out, double* d_stats_out, int32_t* d_status,
+                            void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model has no likelihood network");
+    if (!o || !h_action || !h_obs) return fail(VOILA_ERR_INVALID_ARG, "NULL options, action or observation");
+    if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
+    if (N > kNormResMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
+    if (!(o->lambda > 0.0) || !std::isfinite(o->lambda)) return fail(VOILA_ERR_INVALID_ARG, "lambda must be > 0");
+    if (!d_states || !d_states_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    UpdateWs w = carve_update(reinterpret_cast<char*>(ws), m->width, N, m->d_s);
+    if (!ws || ws_bytes < w.bytes) return fail(VOILA_ERR_WORKSPACE, "update workspace too small");
+    FoldParams ft{}, fl{};
+    voila_status_t st;
+    if ((st = fold_vector(m, h_action, h_obs, false, ft)) != VOILA_OK) return st;
+    if ((st = fold_vector(m, h_action, h_obs, true, fl)) != VOILA_OK) return st;
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ft.w = m->fold_w_trans;
+    ft.b = m->fold_b_trans;
+    ft.out = w.b0_trans;
+    fl.w = m->fold_w_lik;
+    fl.b = m->fold_b_lik;
+    fl.out = w.b0_lik;
+    VOILA_CHECK_HIP(launch_fold(ft, s));
+    VOILA_CHECK_HIP(launch_fold(fl, s));
+    ProposeParams p{};
+    p.trans = m->trans_upd;
+    p.lik = m->lik;
+    p.b0_trans = w.b0_trans;
+    p.b0_lik = w.b0_lik;
+    p.states = d_states;
+    p.prior_w = d_prior_w;
+    p.noise = o->d_noise;
+    p.prop = d_prop_out ? d_prop_out : w.prop;
+    p.loglik = d_loglik_out;
+    p.x = w.x;
+    p.status = d_status;
+    p.N = N;
+    p.lambda = o->lambda;
+    p.key0 = (uint32_t)(o->seed & 0xffffffffu);
+    p.key1 = (uint32_t)(o->seed >> 32);
+    const int n_tiles = (N + 31) / 32;
+    const int want = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int cap = m->cus * m->prop_bpc;
+    VOILA_CHECK_HIP(launch_propose(m->shape, m->dt, p, want < cap ? want : cap, s));
+    NormResParams r{};
+    r.x = w.x;
+    r.N = N;
+    r.bits = voila_resample_bits(N);
+    r.uniform_prior = d_prior_w ? 0 : 1;
+    r.do_resample = 1;
+    r.U = o->resample_u;
+    r.lambda = o->lambda;
+    r.w_out = d_w_out;
+    r.stats = d_stats_out;
+    r.idx_out = d_idx_out;
+    r.src = p.prop;
+    r.dst = d_states_out;
+    r.row_floats = m->d_s;
+    r.status = d_status;
+    VOILA_CHECK_HIP(launch_norm_res(r, s));
+    return VOILA_OK;
+}
+
+voila_status_t voila_normalize(const float* d_loglik, const double* d_prior_w, int32_t N, double lambda,
+                               double* d_w_out, double* d_stats_out, int32_t* d_status, void* stream) {
+    if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
+    if (N > kNormResMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(VOILA_ERR_INVALID_ARG, "lambda must be > 0");
+    if (!d_loglik || !d_w_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    NormResParams r{};
+    r.loglik = d_loglik;
+    r.prior_w = d_prior_w;
+    r.lambda = lambda;
+    r.N = N;
+    r.bits = voila_resample_bits(N);
+    r.uniform_prior = d_prior_w ? 0 : 1;
+    r.do_resample = 0;
+    r.w_out = d_w_out;
+    r.stats = d_stats_out;
+    r.status = d_status;
+    VOILA_CHECK_HIP(launch_norm_res(r, reinterpret_cast<hipStream_t>(stream)));
+    return VOILA_OK;
+}
+
+voila_status_t voila_resample(const double* d_w, int32_t N, uint32_t U, int32_t* d_idx_out, const float* d_src,
+                              float* d_dst, int32_t row_floats, int32_t* d_status, void* stream) {
+    if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
+    if (N > kNormResMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
+    if (!d_w || !d_idx_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    if ((d_src != nullptr) != (d_dst != nullptr)) return fail(VOILA_ERR_INVALID_ARG, "give both or neither of src and dst");
+    if (d_src && row_floats < 1) return fail(VOILA_ERR_INVALID_ARG, "row_floats must be >= 1");
+    NormResParams r{};
+    r.w_in = d_w;
+    r.N = N;
+    r.bits = voila_resample_bits(N);
+    r.do_resample = 1;
+    r.U = U;
+    r.idx_out = d_idx_out;
+    r.src = d_src;
+    r.dst = d_dst;
+    r.row_floats = row_floats;
+    r.status = d_status;
+    VOILA_CHECK_HIP(launch_norm_res(r, reinterpret_cast<hipStream_t>(stream)));
+    return VOILA_OK;
+}
+
+size_t voila_observe_workspace_size(voila_model_t m) {
+    if (!m) return 0;
+    return align_up((size_t)m->width * 4, 256);
+}
+
+voila_status_t voila_observe(voila_model_t m, const float* d_states, int32_t n, const void* h_action, uint64_t seed,
+                             const float* d_noise, void* ws, size_t ws_bytes, float* d_obs_out, void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!m->has_obs) return fail(VOILA_ERR_INVALID_ARG, "the model has no observation network");
+    if (n < 0) return fail(VOILA_ERR_INVALID_ARG, "n must be >= 0");
+    if (!h_action) return fail(VOILA_ERR_INVALID_ARG, "NULL action");
+    if (n == 0) return VOILA_OK;
+    if (!d_states || !d_obs_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    if (!ws || ws_bytes < voila_observe_workspace_size(m)) return fail(VOILA_ERR_WORKSPACE, "observe workspace too small");
+    FoldParams f{};
+    voila_status_t st;
+    if ((st = fold_vector(m, h_action, nullptr, false, f)) != VOILA_OK) return st;
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    f.w = m->fold_w_obs;
+    f.b = m->fold_b_obs;
+    f.out = reinterpret_cast<float*>(ws);
+    VOILA_CHECK_HIP(launch_fold(f, s));
+    ObserveParams p{};
+    p.obs = m->obs;
+    p.b0 = f.out;
+    p.states = d_states;
+    p.noise = d_noise;
+    p.out = d_obs_out;
+    p.n = n;
+    p.key0 = (uint32_t)(seed & 0xffffffffu);
+    p.key1 = (uint32_t)(seed >> 32);
+    const int n_tiles = (n + 31) / 32;
+    const int want = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int cap = m->cus * m->obs_bpc;
+    VOILA_CHECK_HIP(launch_observe(m->shape, m->dt, p, want < cap ? want : cap, s));
+    return VOILA_OK;
+}
+
+voila_status_t voila_philox_normals(uint64_t seed, uint32_t c0_base, uint32_t c1, uint32_t c2, uint32_t stream_id,
+                                    int32_t n, int32_t d, float* d_out, uint32_t* d_words, void* stream) {
+    if (n < 0 || d < 1) return fail(VOILA_ERR_INVALID_ARG, "n must be >= 0 and d >= 1");
+    if (stream_id > 0xffffu) return fail(VOILA_ERR_INVALID_ARG, "stream id must fit in 16 bits");
+    if (n > 0 && !d_out) return fail(VOILA_ERR_INVALID_ARG, "NULL output");
+    PhiloxParams p{};
+    p.out = d_out;
+    p.words = d_words;
+    p.n = n;
+    p.d = d;
+    p.key0 = (uint32_t)(seed & 0xffffffffu);
+    p.key1 = (uint32_t)(seed >> 32);
+    p.c0 = c0_base;
+    p.c1 = c1;
+    p.c2 = c2;
+    p.stream = stream_id;
+    VOILA_CHECK_HIP(launch_philox(p, reinterpret_cast<hipStream_t>(stream)));
+    return VOILA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+// device.hpp -- wave-level MLP engine on gfx950 matrix cores, counter-based
+// noise, and the register layouts shared by the kernels and the host packer.
+//
+// Register layout (one wave = 64 lanes, lane l, group g = l / 32, column
+// n = l % 32):
+//   * A 32x32 MFMA output tile D (v_mfma_f32_32x32x2_f32 and
+//     v_mfma_f32_32x32x16_bf16 share it) leaves D[row][n] in register i of
+//     lane (g, n) with row = out_row(i, g) = 8 (i / 4) + 4 g + i % 4.
+//   * The networks are evaluated transposed, h^T = W x^T: the 32 columns of
+//     a tile are 32 rollouts (particles), rows are features.  The B operand
+//     of the next layer needs, per lane, features of the lane's own column,
+//     which is exactly what the D layout holds -- so a layer's output feeds
+//     the next layer straight from registers.  k-step c of a hidden layer
+//     consumes "register index" ri = c * KPER + j (j < KPER; KPER = 1 for
+//     f32, 8 for bf16), i.e. tile ri / 16, register ri % 16, whose feature in
+//     group g is 32 (ri / 16) + out_row(ri % 16, g).  The host packs the
+//     weight fragments of every layer in that order, so the feature
+//     permutation costs nothing at run time.
+//   * The first layer's input is assembled per lane in "slots": group g
+//     holds state features f = 2 s + g, then continuous-action features
+//     2 s + g, then noise features 4 (s / 2) + 2 g + s % 2 (pair g of Philox
+//     block s / 2), then zero padding to a multiple of KPER.
+//   * The output layer has one 32-row tile; output feature f = 2 i + g sits in
+//     register i of group g (row out_row(i, g)), which makes the state update
+//     s += f_T(...) a register-to-register add.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace voila {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int DT_F32 = 0;
+constexpr int DT_BF16 = 1;
+
+__host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+__host__ __device__ constexpr int rup(int a, int b) { return cdiv(a, b) * b; }
+__host__ __device__ constexpr int out_row(int i, int g) { return (i >> 2) * 8 + g * 4 + (i & 3); }
+__host__ __device__ constexpr int kper(int dt) { return dt == DT_F32 ? 1 : 8; }
+
+// Slots of the first-layer input held by each lane group.
+__host__ __device__ constexpr int state_slots(int d_s) { return cdiv(d_s, 2); }
+__host__ __device__ constexpr int action_slots(int d_ain) { return cdiv(d_ain, 2); }
+__host__ __device__ constexpr int noise_slots(int d_w) { return 2 * cdiv(d_w, 4); }
+__host__ __device__ constexpr int in_slots(int dt, int d_s, int d_ain, int d_w) {
+    return rup(state_slots(d_s) + action_slots(d_ain) + noise_slots(d_w), kper(dt));
+}
+
+// Compile-time shape of one network as the engine runs it.
+template <int DT_, int WIDTH_, int NHID_, int IN_SLOTS_>
+struct Net {
+    static constexpr int DT = DT_;
+    static constexpr int WIDTH = WIDTH_;           // hidden width (multiple of 32)
+    static constexpr int HT = WIDTH / 32;          // hidden 32-row tiles
+    static constexpr int NHID = NHID_;             // hidden layers (>= 1)
+    static constexpr int KPER = kper(DT);          // k values per lane per MFMA
+    static constexpr int IN_SLOTS = IN_SLOTS_;     // first-layer slots per lane group
+    static constexpr int IN_KS = IN_SLOTS / KPER;  // first-layer k-steps
+    static constexpr int HID_KS = 16 * HT / KPER;  // k-steps of a layer fed by a hidden layer
+    static constexpr int FRAG_BYTES = 64 * KPER * (DT == DT_F32 ? 4 : 2);
+    static constexpr int NF0 = IN_KS * HT;         // first-layer fragments
+    static constexpr int NFH = HID_KS * HT;        // fragments per hidden->hidden layer
+    static constexpr int NFO = HID_KS;             // output-layer fragments
+    static_assert(WIDTH % 32 == 0 && NHID >= 1 && IN_SLOTS % KPER == 0, "bad net shape");
+};
+
+// Device view of one packed network (all pointers into global memory or LDS).
+struct NetPtrs {
+    const char* f0;     // first-layer fragments  [IN_KS][HT]
+    const char* fh;     // hidden fragments       [NHID-1][HID_KS][HT]
+    const char* fo;     // output fragments       [HID_KS]
+    const float* b0;    // first-layer bias       [WIDTH] (row order)
+    const float* bh;    // hidden biases          [NHID-1][WIDTH]
+    const float* bo;    // output bias            [32] (row order)
+};
+
+// Offsets of the parts of a packed network blob (bytes from the blob start).
+struct NetBlob {
+    const char* base;
+    uint32_t bytes;
+    uint32_t off_f0, off_fh, off_fo, off_b0, off_bh, off_bo;
+    uint32_t b0_stride;  // floats between first-layer bias variants (discrete actions)
+};
+
+__device__ inline NetPtrs net_ptrs(const char* base, const NetBlob& nb) {
+    NetPtrs p;
+    p.f0 = base + nb.off_f0;
+    p.fh = base + nb.off_fh;
+    p.fo = base + nb.off_fo;
+    p.b0 = reinterpret_cast<const float*>(base + nb.off_b0);
+    p.bh = reinterpret_cast<const float*>(base + nb.off_bh);
+    p.bo = reinterpret_cast<const float*>(base + nb.off_bo);
+    return p;
+}
+
+// ----------------------------------------------------------------------------
+// Matrix-core primitives.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ f32x16 mfma(float a, float b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int DT> struct Frag;
+template <> struct Frag<DT_F32> {
+    typedef float type;
+    __device__ static __forceinline__ float load(const char* p, int idx, int lane) {
+        return reinterpret_cast<const float*>(p)[idx * 64 + lane];
+    }
+};
+template <> struct Frag<DT_BF16> {
+    typedef bf16x8 type;
+    __device__ static __forceinline__ bf16x8 load(const char* p, int idx, int lane) {
+        return reinterpret_cast<const bf16x8*>(p)[idx * 64 + lane];
+    }
+};
+
+// acc[t][i] = bias[32 t + out_row(i, g)]
+template <int NT>
+__device__ __forceinline__ void init_bias(f32x16 (&acc)[NT], const float* bias, int g) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f32x4 v = *reinterpret_cast<const f32x4*>(bias + 32 * t + 8 * q + 4 * g);
+            acc[t][4 * q + 0] = v[0];
+            acc[t][4 * q + 1] = v[1];
+            acc[t][4 * q + 2] = v[2];
+            acc[t][4 * q + 3] = v[3];
+        }
+    }
+}
+
+// Hidden activations as the B operands of the next layer.
+template <int DT, int HT> struct Act;
+template <int HT> struct Act<DT_F32, HT> {
+    f32x16 v[HT];
+    __device__ __forceinline__ void set_relu(const f32x16 (&acc)[HT]) {
+#pragma unroll
+        for (int t = 0; t < HT; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[t][i] = fmaxf(acc[t][i], 0.0f);
+    }
+    __device__ __forceinline__ float b(int c) const { return v[c >> 4][c & 15]; }
+};
+template <int HT> struct Act<DT_BF16, HT> {
+    bf16x8 v[2 * HT];
+    __device__ __forceinline__ void set_relu(const f32x16 (&acc)[HT]) {
+#pragma unroll
+        for (int t = 0; t < HT; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[2 * t + (i >> 3)][i & 7] = (__bf16)fmaxf(acc[t][i], 0.0f);
+    }
+    __device__ __forceinline__ bf16x8 b(int c) const { return v[c]; }
+};
+
+// First-layer B operand from per-lane slot values.
+template <int DT, int S> struct Slots;
+template <int S> struct Slots<DT_F32, S> {
+    __device__ static __forceinline__ float b(const float (&s)[S], int c) { return s[c]; }
+};
+template <int S> struct Slots<DT_BF16, S> {
+    __device__ static __forceinline__ bf16x8 b(const float (&s)[S], int c) {
+        bf16x8 r;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = (__bf16)s[8 * c + j];
+        return r;
+    }
+};
+
+// A zero the compiler cannot see through.  Adding it to a fragment address
+// keeps the (loop-invariant) weight loads inside the layer and k-step window
+// that uses them instead of letting them be hoisted out of the rollout loop,
+// which would need one register per weight.
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+
+// One layer: acc[t] += W_frag(c, t) * B(c) over k-steps c, in windows of CH
+// k-steps per address barrier.
+template <int DT, int KS, int NT, int CH, class BOp>
+__device__ __forceinline__ void layer_mfma(f32x16 (&acc)[NT], const char* frags, BOp bop, int lane) {
+    typedef Frag<DT> F;
+#pragma unroll
+    for (int c0 = 0; c0 < KS; c0 += CH) {
+        const char* fp = frags + opaque_zero();
+#pragma unroll
+        for (int c = c0; c < (c0 + CH < KS ? c0 + CH : KS); ++c) {
+            auto b = bop(c);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = mfma(F::load(fp, c * NT + t, lane), b, acc[t]);
+        }
+    }
+}
+
+// Runs one network on the 32 columns of a wave.  `slots` is the first-layer
+// input of this lane, `b0` the first-layer bias (row order, possibly with an
+// action folded in).  Returns the output tile: feature 2 i + g in out[i].
+template <class N, int CH = 8>
+__device__ __forceinline__ f32x16 run_net(const NetPtrs& P, const float* b0, const float (&slots)[N::IN_SLOTS],
+                                          int lane, int g) {
+    f32x16 acc[N::HT];
+    Act<N::DT, N::HT> act;
+    init_bias<N::HT>(acc, b0 + opaque_zero(), g);
+    layer_mfma<N::DT, N::IN_KS, N::HT, CH>(
+        acc, P.f0, [&](int c) { return Slots<N::DT, N::IN_SLOTS>::b(slots, c); }, lane);
+    act.set_relu(acc);
+#pragma unroll
+    for (int l = 1; l < N::NHID; ++l) {
+        const char* fl = P.fh + (size_t)(l - 1) * N::NFH * N::FRAG_BYTES;
+        init_bias<N::HT>(acc, P.bh + (l - 1) * N::WIDTH + opaque_zero(), g);
+        layer_mfma<N::DT, N::HID_KS, N::HT, CH>(acc, fl, [&](int c) { return act.b(c); }, lane);
+        act.set_relu(acc);
+    }
+    f32x16 out[1];
+    init_bias<1>(out, P.bo + opaque_zero(), g);
+    layer_mfma<N::DT, N::HID_KS, 1, CH>(out, P.fo, [&](int c) { return act.b(c); }, lane);
+    return out[0];
+}
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller draws.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// u = (2 (x >> 9) + 1) 2^-24, exact in binary32, inside (0, 1).
+__device__ __forceinline__ float word_to_uniform(uint32_t x) {
+    return (float)((x >> 8) | 1u) * 0x1p-24f;
+}
+
+// Box-Muller pair from two words: (r cos 2 pi u_b, r sin 2 pi u_b), r = sqrt(-2 ln u_a).
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z_cos, float& z_sin) {
+    float ua = word_to_uniform(wa), ub = word_to_uniform(wb);
+    float r = sqrtf(-2.0f * logf(ua));
+    float s, c;
+    sincospif(2.0f * ub, &s, &c);
+    z_cos = r * c;
+    z_sin = r * s;
+}
+
+// The noise slots of lane group g: slot s holds feature 4 (s / 2) + 2 g + s % 2,
+// i.e. pair g of Philox block s / 2 of counter (c0, c1, c2, (stream << 16) | block).
+template <int NS>
+__device__ __forceinline__ void noise_slots_philox(float (&out)[NS], uint32_t key0, uint32_t key1, uint32_t c0,
+                                                   uint32_t c1, uint32_t c2, uint32_t stream, int g) {
+#pragma unroll
+    for (int blk = 0; blk < NS / 2; ++blk) {
+        uint4 w = philox4x32_10(make_uint4(c0, c1, c2, (stream << 16) | (uint32_t)blk), key0, key1);
+        uint32_t wa = g ? w.z : w.x;
+        uint32_t wb = g ? w.w : w.y;
+        box_muller(wa, wb, out[2 * blk], out[2 * blk + 1]);
+    }
+}
+
+// Noise feature held by slot s of group g.
+__host__ __device__ constexpr int noise_feature(int s, int g) { return 4 * (s / 2) + 2 * g + (s % 2); }
+
+// Wave-wide reductions across the 32 columns of one lane group (fixed order).
+__device__ __forceinline__ float sum32(float v) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+
+}  // namespace voila

@@ -1,0 +1,618 @@
+// kernels.hip -- HIP kernels of the plan / update / observe hot path (gfx950).
+//
+// plan_kernel     persistent rollout kernel: each wave owns a (candidate, 32-particle)
+//                 tile, keeps the 32 states in registers for the whole horizon and
+//                 runs every transition-network layer on the matrix cores
+//                 (transposed evaluation, see device.hpp), with the noise drawn in
+//                 registers from Philox.  Small networks are staged in LDS once per
+//                 block; wide ones stream their fragments from L2.
+// q_reduce_kernel fixed-order sum of the per-tile partial returns into Q.
+// fold_kernel     folds a fixed action (and observation) into a first-layer bias.
+// propose_kernel  update stage 1: proposal s' = s + f_T and likelihood l(s', a, o)
+//                 for 32 particles per wave; writes s', l and x = l / lambda.
+// norm_res_kernel update stage 2 in one workgroup (N <= 8192): binary64 max /
+//                 exp / sum normalisation with fixed-order reductions, exact
+//                 quantised prefix sum, systematic resampling by binary search,
+//                 and the gather of the resampled particles.
+#include "kernels.hpp"
+
+#include <math.h>
+
+namespace voila {
+
+namespace {
+
+const ShapeInfo kShapeInfo[kNumShapes] = {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh) {ds, na, da, dw, dox, dwz, w, nh},
+    VOILA_SHAPES(X)
+#undef X
+};
+
+__device__ __forceinline__ float reward_of(const float* st, const float* goal, int n_slots, int d_s, int g) {
+    float part = 0.0f;
+    for (int s = 0; s < n_slots; ++s) {
+        int f = 2 * s + g;
+        if (f < d_s) {
+            float e = st[s] - goal[f];
+            part += e * e;
+        }
+    }
+    return -(part + __shfl_xor(part, 32));
+}
+
+// Copies a packed network blob into LDS (bytes is a multiple of 16).
+__device__ __forceinline__ void stage_blob(char* dst, const char* src, uint32_t bytes) {
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    uint4* d = reinterpret_cast<uint4*>(dst);
+    for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
+}  // namespace
+
+const ShapeInfo& shape_info(int shape) { return kShapeInfo[shape]; }
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, bool WLDS>
+__global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
+    constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    if (WLDS) {
+        stage_blob(smem, p.net.base, p.net.bytes);
+        __syncthreads();
+    }
+    const char* base = WLDS ? (const char*)smem : p.net.base;
+    const NetPtrs P = net_ptrs(base, p.net);
+
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wpb = blockDim.x >> 6;
+    const long total_waves = (long)gridDim.x * wpb;
+    const long n_units = (long)p.K * p.n_tiles;
+
+    for (long u = (long)blockIdx.x * wpb + (threadIdx.x >> 6); u < n_units; u += total_waves) {
+        const int k = (int)(u / p.n_tiles), tile = (int)(u % p.n_tiles);
+        const int i = tile * 32 + col;
+        const bool valid = i < p.N;
+        float st[SS];
+#pragma unroll
+        for (int s = 0; s < SS; ++s) {
+            int f = 2 * s + g;
+            st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+        }
+        float G = 0.0f;
+        double disc = 1.0;
+        for (int t = 0; t < p.H; ++t) {
+            float slots[NT::IN_SLOTS];
+#pragma unroll
+            for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+            for (int s = 0; s < SS; ++s) slots[s] = st[s];
+            if (D_A > 0) {
+                const float* a = reinterpret_cast<const float*>(p.cands) + ((size_t)k * p.H + t) * D_A;
+#pragma unroll
+                for (int s = 0; s < SA; ++s) {
+                    int f = 2 * s + g;
+                    slots[SS + s] = f < D_A ? a[f] : 0.0f;
+                }
+            }
+            if (p.noise) {
+                const float* src = p.noise + (((size_t)k * p.N + (valid ? i : 0)) * p.H + t) * D_W;
+#pragma unroll
+                for (int s = 0; s < SW; ++s) {
+                    int f = noise_feature(s, g);
+                    slots[SS + SA + s] = f < D_W ? src[f] : 0.0f;
+                }
+            } else {
+                float nz[SW];
+                noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 3u, g);
+#pragma unroll
+                for (int s = 0; s < SW; ++s) slots[SS + SA + s] = nz[s];
+            }
+            const float* b0 = P.b0;
+            if (N_ACT > 0) {
+                int a = reinterpret_cast<const int32_t*>(p.cands)[(size_t)k * p.H + t];
+                if (a < 0 || a >= N_ACT) {
+                    if (p.status && lane == 0) p.status[0] = 1;
+                    a = 0;
+                }
+                b0 += (size_t)a * p.net.b0_stride;
+            }
+            float r_cur = 0.0f;
+            if (p.reward_at) r_cur = reward_of(st, p.goal, SS, D_S, g);
+            f32x16 out = run_net<NT>(P, b0, slots, lane, g);
+#pragma unroll
+            for (int s = 0; s < SS; ++s) st[s] += out[s];
+            float r = p.reward_at ? r_cur : reward_of(st, p.goal, SS, D_S, g);
+            G += (float)disc * r;
+            disc *= p.gamma;
+        }
+        if (p.returns && g == 0 && valid) p.returns[(size_t)k * p.N + i] = G;
+        float contrib = valid ? (p.belief_w ? (float)p.belief_w[i] * G : G) : 0.0f;
+        float tot = sum32(contrib);
+        if (lane == 0) p.partials[(size_t)k * p.n_tiles + tile] = tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void q_reduce_kernel(QReduceParams p) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (k >= p.K) return;
+    float s = 0.0f;
+    for (int j = lane; j < p.n_tiles; j += 64) s += p.partials[(size_t)k * p.n_tiles + j];
+    s += __shfl_xor(s, 32);
+    s = sum32(s);
+    if (lane == 0) p.q[k] = s * p.scale;
+}
+
+__global__ __launch_bounds__(256) void fold_kernel(FoldParams p) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= p.width) return;
+    float acc = p.b[r];
+    for (int c = 0; c < p.nf; ++c) acc += p.w[(size_t)r * p.nf + c] * p.v[c];
+    p.out[r] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// update stage 1: proposal and likelihood
+// ---------------------------------------------------------------------------
+template <int DT, int D_S, int D_W, int WIDTH, int NHID, bool WLDS>
+__global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
+    constexpr int SS = state_slots(D_S), SW = noise_slots(D_W);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_W)> NTT;
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, 0)> NTL;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    if (WLDS) {
+        stage_blob(smem, p.trans.base, p.trans.bytes);
+        stage_blob(smem + p.trans.bytes, p.lik.base, p.lik.bytes);
+        __syncthreads();
+    }
+    const NetPtrs PT = net_ptrs(WLDS ? (const char*)smem : p.trans.base, p.trans);
+    const NetPtrs PL = net_ptrs(WLDS ? (const char*)smem + p.trans.bytes : p.lik.base, p.lik);
+
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wpb = blockDim.x >> 6;
+    const int n_tiles = (p.N + 31) / 32;
+    for (int tile = blockIdx.x * wpb + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * wpb) {
+        const int i = tile * 32 + col;
+        const bool valid = i < p.N;
+        float slots[NTT::IN_SLOTS];
+#pragma unroll
+        for (int s = 0; s < NTT::IN_SLOTS; ++s) slots[s] = 0.0f;
+        float st[SS];
+#pragma unroll
+        for (int s = 0; s < SS; ++s) {
+            int f = 2 * s + g;
+            st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+            slots[s] = st[s];
+        }
+        if (p.noise) {
+#pragma unroll
+            for (int s = 0; s < SW; ++s) {
+                int f = noise_feature(s, g);
+                slots[SS + s] = (valid && f < D_W) ? p.noise[(size_t)i * D_W + f] : 0.0f;
+            }
+        } else {
+            float nz[SW];
+            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, 0u, 0u, 5u, g);
+#pragma unroll
+            for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
+        }
+        f32x16 d = run_net<NTT>(PT, p.b0_trans, slots, lane, g);
+        float ls[NTL::IN_SLOTS];
+#pragma unroll
+        for (int s = 0; s < NTL::IN_SLOTS; ++s) ls[s] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SS; ++s) {
+            int f = 2 * s + g;
+            st[s] += d[s];
+            ls[s] = st[s];
+            if (valid && f < D_S) p.prop[(size_t)i * D_S + f] = st[s];
+        }
+        f32x16 lo = run_net<NTL>(PL, p.b0_lik, ls, lane, g);
+        if (g == 0 && valid) {
+            float l = lo[0];
+            if (p.loglik) p.loglik[i] = l;
+            if (!isfinite(l) && p.status) p.status[0] = 5;
+            double x = (double)l / p.lambda;
+            if (p.prior_w) x += log(p.prior_w[i]);
+            p.x[i] = x;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// observe
+// ---------------------------------------------------------------------------
+template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID, bool WLDS>
+__global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
+    constexpr int SS = state_slots(D_S), SW = noise_slots(D_WZ);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ)> NTO;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    if (WLDS) {
+        stage_blob(smem, p.obs.base, p.obs.bytes);
+        __syncthreads();
+    }
+    const NetPtrs PO = net_ptrs(WLDS ? (const char*)smem : p.obs.base, p.obs);
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wpb = blockDim.x >> 6;
+    const int n_tiles = (p.n + 31) / 32;
+    for (int tile = blockIdx.x * wpb + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * wpb) {
+        const int r = tile * 32 + col;
+        const bool valid = r < p.n;
+        float slots[NTO::IN_SLOTS];
+#pragma unroll
+        for (int s = 0; s < NTO::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SS; ++s) {
+            int f = 2 * s + g;
+            slots[s] = (valid && f < D_S) ? p.states[(size_t)r * D_S + f] : 0.0f;
+        }
+        if (p.noise) {
+#pragma unroll
+            for (int s = 0; s < SW; ++s) {
+                int f = noise_feature(s, g);
+                slots[SS + s] = (valid && f < D_WZ) ? p.noise[(size_t)r * D_WZ + f] : 0.0f;
+            }
+        } else {
+            float nz[SW];
+            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)r, 0u, 0u, 4u, g);
+#pragma unroll
+            for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
+        }
+        f32x16 o = run_net<NTO>(PO, p.b0, slots, lane, g);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            int f = 2 * s + g;
+            if (valid && f < D_O) p.out[(size_t)r * D_O + f] = o[s];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// update stage 2: normalisation and systematic resampling in one workgroup
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNRWaves = kNormResThreads / 64;
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m));
+    return v;
+}
+
+// Block reductions in a fixed order: lanes (butterfly), then waves 0..15 in order.
+__device__ double block_sum_d(double v, double* red) {
+    v = wave_sum_d(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kNRWaves; ++w) s += red[w];
+    return s;
+}
+__device__ double block_max_d(double v, double* red) {
+    v = wave_max_d(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = -INFINITY;
+    for (int w = 0; w < kNRWaves; ++w) m = fmax(m, red[w]);
+    return m;
+}
+__device__ int block_max_i(int v, int* red) {
+    v = wave_max_i(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int m = -1;
+    for (int w = 0; w < kNRWaves; ++w) m = max(m, red[w]);
+    return m;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kNormResThreads) void norm_res_kernel(NormResParams p) {
+    __shared__ double buf[kNormResMaxN];
+    __shared__ double redd[kNRWaves];
+    __shared__ int redi[kNRWaves];
+    const int tid = threadIdx.x, N = p.N;
+
+    if (!p.w_in) {
+        int bad = 0;
+        double mx = -INFINITY;
+        for (int i = tid; i < N; i += kNormResThreads) {
+            double x;
+            if (p.x) {
+                x = p.x[i];
+            } else {
+                float l = p.loglik[i];
+                if (!isfinite(l)) bad = 1;
+                x = (double)l / p.lambda;
+                if (p.prior_w) x += log(p.prior_w[i]);
+            }
+            if (isnan(x) || x == INFINITY) bad = 1;
+            buf[i] = x;
+            mx = fmax(mx, x);
+        }
+        mx = block_max_d(mx, redd);
+        int anybad = block_max_i(bad, redi);
+        if (anybad || !isfinite(mx)) {
+            if (tid == 0 && p.status) p.status[0] = 5;
+            return;
+        }
+        double s = 0.0;
+        for (int i = tid; i < N; i += kNormResThreads) {
+            double e = exp(buf[i] - mx);
+            buf[i] = e;
+            s += e;
+        }
+        const double S = block_sum_d(s, redd);
+        double sq = 0.0;
+        for (int i = tid; i < N; i += kNormResThreads) {
+            double w = buf[i] / S;
+            buf[i] = w;
+            if (p.w_out) p.w_out[i] = w;
+            sq += w * w;
+        }
+        const double SQ = block_sum_d(sq, redd);
+        if (tid == 0 && p.stats) {
+            p.stats[0] = mx + log(S) - (p.uniform_prior ? log((double)N) : 0.0);
+            p.stats[1] = 1.0 / SQ;
+        }
+    } else {
+        int bad = 0;
+        for (int i = tid; i < N; i += kNormResThreads) {
+            double w = p.w_in[i];
+            if (!(w >= 0.0) || w == INFINITY) bad = 1;
+            buf[i] = w;
+        }
+        if (block_max_i(bad, redi)) {
+            if (tid == 0 && p.status) p.status[0] = 5;
+            return;
+        }
+    }
+    if (!p.do_resample) return;
+    __syncthreads();
+
+    // quantise: q_i = rint(w_i * N * 2^b), exact integers below 2^53
+    const double scale = ldexp((double)N, p.bits);
+    int last = -1;
+    for (int i = tid; i < N; i += kNormResThreads) {
+        double q = rint(buf[i] * scale);
+        buf[i] = q;
+        if (q > 0.0) last = i;
+    }
+    last = block_max_i(last, redi);
+    if (last < 0) {
+        if (tid == 0 && p.status) p.status[0] = 5;
+        return;
+    }
+    // inclusive prefix sum; every partial sum is an exact integer, so the
+    // blocked order gives the same bits as a sequential sum.
+    const int per = (N + kNormResThreads - 1) / kNormResThreads;
+    const int lo = tid * per, hi = min(N, lo + per);
+    double run = 0.0;
+    for (int i = lo; i < hi; ++i) {
+        run += buf[i];
+        buf[i] = run;
+    }
+    // exclusive scan of the thread totals (wave scan + wave totals)
+    double incl = run;
+    const int lane = tid & 63;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        double o = __shfl_up(incl, m);
+        if (lane >= m) incl += o;
+    }
+    __syncthreads();
+    if (lane == 63) redd[tid >> 6] = incl;
+    __syncthreads();
+    double off = incl - run;
+    for (int w = 0; w < (tid >> 6); ++w) off += redd[w];
+    for (int i = lo; i < hi; ++i) buf[i] += off;
+    __syncthreads();
+
+    // systematic positions P_j = j 2^b + u; idx_j = first i with C_i > P_j
+    const double step = ldexp(1.0, p.bits);
+    const double u = (double)(p.U >> (32 - p.bits));
+    for (int j = tid; j < N; j += kNormResThreads) {
+        const double P = (double)j * step + u;
+        int a = 0, b = N;
+        while (a < b) {
+            int mid = (a + b) >> 1;
+            if (buf[mid] > P) b = mid;
+            else a = mid + 1;
+        }
+        const int idx = a < N ? a : last;
+        if (p.idx_out) p.idx_out[j] = idx;
+        if (p.src && p.dst)
+            for (int c = 0; c < p.row_floats; ++c)
+                p.dst[(size_t)j * p.row_floats + c] = p.src[(size_t)idx * p.row_floats + c];
+    }
+}
+
+__global__ __launch_bounds__(256) void philox_kernel(PhiloxParams p) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= p.n) return;
+    const int nb = (p.d + 3) / 4;
+    for (int b = 0; b < nb; ++b) {
+        uint4 w = philox4x32_10(make_uint4(p.c0 + (uint32_t)r, p.c1, p.c2, (p.stream << 16) | (uint32_t)b), p.key0,
+                                p.key1);
+        if (p.words) {
+            uint32_t* o = p.words + ((size_t)r * nb + b) * 4;
+            o[0] = w.x; o[1] = w.y; o[2] = w.z; o[3] = w.w;
+        }
+        float z[4];
+        box_muller(w.x, w.y, z[0], z[1]);
+        box_muller(w.z, w.w, z[2], z[3]);
+        for (int j = 0; j < 4; ++j)
+            if (4 * b + j < p.d) p.out[(size_t)r * p.d + 4 * b + j] = z[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int W> constexpr bool lds_for_width() { return W <= 64; }
+
+}  // namespace
+
+bool weights_in_lds(int shape) { return kShapeInfo[shape].width <= 64; }
+
+#define VOILA_IN_SLOTS(fn, expr)                                                                   \
+    int fn(int shape, int dt) {                                                                     \
+        const ShapeInfo& s = kShapeInfo[shape];                                                     \
+        (void)s;                                                                                    \
+        return expr;                                                                                \
+    }
+VOILA_IN_SLOTS(plan_in_slots, in_slots(dt, s.d_s, s.n_actions > 0 ? 0 : s.d_a, s.d_w))
+VOILA_IN_SLOTS(update_in_slots, in_slots(dt, s.d_s, 0, s.d_w))
+VOILA_IN_SLOTS(obs_in_slots, in_slots(dt, s.d_s, 0, s.d_wz))
+VOILA_IN_SLOTS(lik_in_slots, in_slots(dt, s.d_s, 0, 0))
+#undef VOILA_IN_SLOTS
+
+#define PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) plan_kernel<DT, ds, na, da, dw, w, nh, lds_for_width<w>()>
+#define PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) propose_kernel<DT, ds, dw, w, nh, lds_for_width<w>()>
+#define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, lds_for_width<w>()>
+
+hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s) {
+    const size_t lds = weights_in_lds(shape) ? p.net.bytes : 0;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
+    case id * 2 + 0:                                                                                       \
+        hipLaunchKernelGGL((PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);  \
+        break;                                                                                             \
+    case id * 2 + 1:                                                                                       \
+        hipLaunchKernelGGL((PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p); \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s) {
+    const size_t lds = weights_in_lds(shape) ? (size_t)p.trans.bytes + p.lik.bytes : 0;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
+    case id * 2 + 0:                                                                                       \
+        hipLaunchKernelGGL((PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);  \
+        break;                                                                                             \
+    case id * 2 + 1:                                                                                       \
+        hipLaunchKernelGGL((PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p); \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s) {
+    const size_t lds = weights_in_lds(shape) ? p.obs.bytes : 0;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                             \
+    case id * 2 + 0:                                                                                      \
+        hipLaunchKernelGGL((OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);  \
+        break;                                                                                            \
+    case id * 2 + 1:                                                                                      \
+        hipLaunchKernelGGL((OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p); \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+namespace {
+template <class KernelT>
+int occupancy(KernelT k, size_t lds) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, lds) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+// LDS bytes assumed for occupancy: the blob sizes of the small shape are a few tens of KB.
+constexpr size_t kLdsGuess = 32 * 1024;
+}  // namespace
+
+int plan_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
+    case id * 2 + 0:                                                                                        \
+        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : 0); \
+    case id * 2 + 1:                                                                                        \
+        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : 0);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+int propose_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                   \
+    case id * 2 + 0:                                                                                            \
+        return occupancy(PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? 2 * kLdsGuess : 0); \
+    case id * 2 + 1:                                                                                            \
+        return occupancy(PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? 2 * kLdsGuess : 0);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+int observe_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
+    case id * 2 + 0:                                                                                       \
+        return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : 0); \
+    case id * 2 + 1:                                                                                       \
+        return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : 0);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+hipError_t launch_q_reduce(const QReduceParams& p, hipStream_t s) {
+    const int blocks = (p.K + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(q_reduce_kernel, blocks, 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const FoldParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(fold_kernel, (p.width + 255) / 256, 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_res(const NormResParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(norm_res_kernel, 1, kNormResThreads, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const PhiloxParams& p, hipStream_t s) {
+    if (p.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_kernel, (p.n + 255) / 256, 256, 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace voila

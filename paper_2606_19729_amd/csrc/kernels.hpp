@@ -1,0 +1,132 @@
+// kernels.hpp -- host-visible parameter blocks and launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace voila {
+
+// Network shapes with compiled kernels: X(id, d_s, n_actions, d_a, d_w, d_o, d_wz, width, n_hidden)
+// (n_actions > 0: discrete one-hot actions; d_a > 0: continuous actions).
+#define VOILA_SHAPES(X)                          \
+    X(0, 4, 5, 0, 4, 2, 2, 64, 2)     /* small */ \
+    X(1, 16, 0, 4, 16, 32, 32, 256, 3) /* realistic */
+
+constexpr int kNumShapes = 2;
+
+struct ShapeInfo {
+    int d_s, n_actions, d_a, d_w, d_o, d_wz, width, n_hidden;
+};
+const ShapeInfo& shape_info(int shape);
+
+// First-layer slots per lane group for each use of a network.
+int plan_in_slots(int shape, int dt);     // transition net in plan: state + continuous action + noise
+int update_in_slots(int shape, int dt);   // transition net in update: state + noise (action folded)
+int obs_in_slots(int shape, int dt);      // observation net: state + obs noise (action folded)
+int lik_in_slots(int shape, int dt);      // likelihood net: state (action, observation folded)
+
+struct PlanParams {
+    NetBlob net;
+    const float* states;     // [N][d_s]
+    const double* belief_w;  // [N] or NULL
+    const void* cands;       // int32 [K][H] or float [K][H][d_a]
+    const float* noise;      // [K][N][H][d_w] or NULL
+    float* returns;          // [K][N] or NULL
+    float* partials;         // [K][n_tiles]
+    int32_t* status;         // or NULL
+    int N, K, H, n_tiles;
+    double gamma;
+    uint32_t key0, key1;
+    int crn, reward_at;
+    float goal[32];
+};
+
+struct QReduceParams {
+    const float* partials;
+    float* q;
+    int K, n_tiles;
+    float scale;
+};
+
+struct FoldParams {
+    const float* w;   // [width][nf]
+    const float* b;   // [width]
+    float* out;       // [width]
+    int width, nf;
+    float v[96];
+};
+
+struct ProposeParams {
+    NetBlob trans, lik;
+    const float* b0_trans;   // folded first-layer bias of the transition net [width]
+    const float* b0_lik;     // folded first-layer bias of the likelihood net [width]
+    const float* states;     // [N][d_s]
+    const double* prior_w;   // [N] or NULL
+    const float* noise;      // [N][d_w] or NULL
+    float* prop;             // [N][d_s]
+    float* loglik;           // [N] or NULL
+    double* x;               // [N]  l / lambda (+ log prior)
+    int32_t* status;         // or NULL
+    int N;
+    double lambda;
+    uint32_t key0, key1;
+};
+
+struct ObserveParams {
+    NetBlob obs;
+    const float* b0;         // folded first-layer bias [width]
+    const float* states;     // [n][d_s]
+    const float* noise;      // [n][d_wz] or NULL
+    float* out;              // [n][d_o]
+    int n;
+    uint32_t key0, key1;
+};
+
+struct NormResParams {
+    const double* x;         // [N] precomputed l / lambda (+ log prior), or NULL
+    const float* loglik;     // [N] used when x is NULL and w_in is NULL
+    const double* prior_w;   // [N] or NULL (with loglik)
+    const double* w_in;      // [N] given normalised weights (resample only), or NULL
+    double lambda;
+    int N, bits, uniform_prior, do_resample;
+    uint32_t U;
+    double* w_out;           // [N] or NULL
+    double* stats;           // [2] or NULL
+    int32_t* idx_out;        // [N] or NULL
+    const float* src;        // gather source rows or NULL
+    float* dst;              // gather destination rows or NULL
+    int row_floats;
+    int32_t* status;         // or NULL
+};
+
+struct PhiloxParams {
+    float* out;
+    uint32_t* words;
+    int n, d;
+    uint32_t key0, key1, c0, c1, c2, stream;
+};
+
+constexpr int kNormResMaxN = 8192;
+constexpr int kNormResThreads = 1024;
+
+// Kernel launchers (return the launch status).
+hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s);
+hipError_t launch_q_reduce(const QReduceParams& p, hipStream_t s);
+hipError_t launch_fold(const FoldParams& p, hipStream_t s);
+hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
+hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);
+hipError_t launch_norm_res(const NormResParams& p, hipStream_t s);
+hipError_t launch_philox(const PhiloxParams& p, hipStream_t s);
+
+// Resident blocks per CU of the plan / propose / observe kernels.
+int plan_blocks_per_cu(int shape, int dt);
+int propose_blocks_per_cu(int shape, int dt);
+int observe_blocks_per_cu(int shape, int dt);
+// Whether a shape's kernels stage the packed network in LDS.
+bool weights_in_lds(int shape);
+
+constexpr int kWavesPerBlock = 4;
+
+}  // namespace voila
