@@ -175,54 +175,120 @@ template <int S> struct Slots<DT_BF16, S> {
 };
 
 // A zero the compiler cannot see through.  Adding it to a fragment address
-// keeps the (loop-invariant) weight loads inside the layer and k-step window
-// that uses them instead of letting them be hoisted out of the rollout loop,
-// which would need one register per weight.
+// keeps the (loop-invariant) weight loads inside the window of fragments that
+// uses them instead of letting them be hoisted out of the rollout loop, which
+// would need one register per weight.
 __device__ __forceinline__ int opaque_zero() {
     int z = 0;
     asm volatile("" : "+s"(z));
     return z;
 }
 
-// One layer: acc[t] += W_frag(c, t) * B(c) over k-steps c, in windows of CH
-// k-steps per address barrier.
-template <int DT, int KS, int NT, int CH, class BOp>
-__device__ __forceinline__ void layer_mfma(f32x16 (&acc)[NT], const char* frags, BOp bop, int lane) {
-    typedef Frag<DT> F;
-#pragma unroll
-    for (int c0 = 0; c0 < KS; c0 += CH) {
-        const char* fp = frags + opaque_zero();
-#pragma unroll
-        for (int c = c0; c < (c0 + CH < KS ? c0 + CH : KS); ++c) {
-            auto b = bop(c);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mfma(F::load(fp, c * NT + t, lane), b, acc[t]);
+// Fragment source reading a resident copy of the packed network (global
+// memory or LDS) directly; the address is refreshed every WIN fragments.
+template <int DT, int WIN>
+struct DirectSrc {
+    const char* base;
+    const char* cur;
+    __device__ __forceinline__ explicit DirectSrc(const char* b) : base(b), cur(b) {}
+    __device__ __forceinline__ typename Frag<DT>::type load(int f, int lane) {
+        if (f % WIN == 0) cur = base + opaque_zero();
+        return Frag<DT>::load(cur, f, lane);
+    }
+    __device__ __forceinline__ void finish() {}
+};
+
+// Fragment source streaming the packed network from global memory through two
+// LDS chunk buffers shared by the whole workgroup.  Every wave of the block
+// must walk the same fragment sequence (the rollout loop is block-uniform):
+// at the first fragment of chunk ch all waves wait for their part of the
+// chunk's direct-to-LDS loads, meet at a barrier (which also retires chunk
+// ch - 1 from the other buffer) and then start loading chunk ch + 1 into that
+// other buffer, so the next chunk streams in while this one is multiplied.
+template <class N, int CHB = 32768, int WIN = 4 * N::HT>
+struct StreamSrc {
+    static constexpr int FB = N::FRAG_BYTES;
+    static constexpr int FPC = CHB / FB;  // fragments per chunk
+    static constexpr int NFR = N::NF0 + (N::NHID - 1) * N::NFH + N::NFO;
+    static constexpr int NCH = cdiv(NFR, FPC);
+    static constexpr int TOTAL = NFR * FB;
+    static_assert(CHB % 4096 == 0 && CHB % FB == 0, "chunk must be whole DMA rounds and fragments");
+    static_assert(TOTAL % 1024 == 0, "the fragment stream must be whole 1 KB DMA rounds");
+    char* lds;          // 2 * CHB bytes of LDS
+    const char* src;    // packed fragment stream in global memory
+    int cur;            // buffer of the current chunk
+    const char* win;    // current chunk's buffer, refreshed every WIN fragments
+
+    __device__ __forceinline__ StreamSrc(char* l, const char* s) : lds(l), src(s), cur(1), win(l) {}
+
+    // Copies chunk ch into buffer b: each wave moves 1 KB per round (64 lanes x 16 B).
+    __device__ __forceinline__ void fetch(int ch, int b) const {
+        // wave-uniform chunk addresses (scalar base + per-lane 16 B offset)
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
+        const int lane = threadIdx.x & 63;
+        const int chunk_bytes = (ch + 1) * CHB <= TOTAL ? CHB : TOTAL - ch * CHB;
+        const char* base = src + opaque_zero() + (size_t)ch * CHB;
+        for (int off = wave * 1024; off < chunk_bytes; off += nw * 1024) {
+            __builtin_amdgcn_global_load_lds((const void*)(base + off + lane * 16),
+                                             (__attribute__((address_space(3))) void*)(lds + b * CHB + off), 16, 0,
+                                             0);
         }
     }
-}
+    __device__ __forceinline__ void start() { fetch(0, 0); }
+    __device__ __forceinline__ typename Frag<N::DT>::type load(int f, int lane) {
+        const int ch = f / FPC, within = f % FPC;
+        if (within == 0) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            cur ^= 1;
+            fetch(ch + 1 < NCH ? ch + 1 : 0, cur ^ 1);
+        }
+        if (within % WIN == 0) win = lds + cur * CHB + opaque_zero();
+        return Frag<N::DT>::load(win, within, lane);
+    }
+    __device__ __forceinline__ void finish() { __builtin_amdgcn_s_waitcnt(0); }
+};
+
+// Fragment index of (k-step c, tile t) in each layer of the packed stream.
+template <class N> struct FragIdx {
+    __device__ static constexpr int first(int c, int t) { return c * N::HT + t; }
+    __device__ static constexpr int hidden(int l, int c, int t) { return N::NF0 + (l - 1) * N::NFH + c * N::HT + t; }
+    __device__ static constexpr int out(int c) { return N::NF0 + (N::NHID - 1) * N::NFH + c; }
+};
 
 // Runs one network on the 32 columns of a wave.  `slots` is the first-layer
 // input of this lane, `b0` the first-layer bias (row order, possibly with an
 // action folded in).  Returns the output tile: feature 2 i + g in out[i].
-template <class N, int CH = 8>
-__device__ __forceinline__ f32x16 run_net(const NetPtrs& P, const float* b0, const float (&slots)[N::IN_SLOTS],
-                                          int lane, int g) {
+template <class N, class Src>
+__device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const float* b0,
+                                          const float (&slots)[N::IN_SLOTS], int lane, int g) {
+    typedef FragIdx<N> FI;
     f32x16 acc[N::HT];
     Act<N::DT, N::HT> act;
     init_bias<N::HT>(acc, b0 + opaque_zero(), g);
-    layer_mfma<N::DT, N::IN_KS, N::HT, CH>(
-        acc, P.f0, [&](int c) { return Slots<N::DT, N::IN_SLOTS>::b(slots, c); }, lane);
+#pragma unroll
+    for (int c = 0; c < N::IN_KS; ++c) {
+        auto b = Slots<N::DT, N::IN_SLOTS>::b(slots, c);
+#pragma unroll
+        for (int t = 0; t < N::HT; ++t) acc[t] = mfma(src.load(FI::first(c, t), lane), b, acc[t]);
+    }
     act.set_relu(acc);
 #pragma unroll
     for (int l = 1; l < N::NHID; ++l) {
-        const char* fl = P.fh + (size_t)(l - 1) * N::NFH * N::FRAG_BYTES;
         init_bias<N::HT>(acc, P.bh + (l - 1) * N::WIDTH + opaque_zero(), g);
-        layer_mfma<N::DT, N::HID_KS, N::HT, CH>(acc, fl, [&](int c) { return act.b(c); }, lane);
+#pragma unroll
+        for (int c = 0; c < N::HID_KS; ++c) {
+            auto b = act.b(c);
+#pragma unroll
+            for (int t = 0; t < N::HT; ++t) acc[t] = mfma(src.load(FI::hidden(l, c, t), lane), b, acc[t]);
+        }
         act.set_relu(acc);
     }
     f32x16 out[1];
     init_bias<1>(out, P.bo + opaque_zero(), g);
-    layer_mfma<N::DT, N::HID_KS, 1, CH>(out, P.fo, [&](int c) { return act.b(c); }, lane);
+#pragma unroll
+    for (int c = 0; c < N::HID_KS; ++c) out[0] = mfma(src.load(FI::out(c), lane), act.b(c), out[0]);
     return out[0];
 }
 

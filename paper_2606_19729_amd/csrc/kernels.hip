@@ -54,84 +54,104 @@ const ShapeInfo& shape_info(int shape) { return kShapeInfo[shape]; }
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
-template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, bool WLDS>
+// How a kernel reads the weight fragments of a network.
+constexpr int kDirect = 0;    // straight from global memory (L2)
+constexpr int kResident = 1;  // whole network staged in LDS once per block
+constexpr int kStream = 2;    // streamed through double-buffered LDS chunks
+
+template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
     constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    if (WLDS) {
+    if (MODE == kResident) {
         stage_blob(smem, p.net.base, p.net.bytes);
         __syncthreads();
     }
-    const char* base = WLDS ? (const char*)smem : p.net.base;
-    const NetPtrs P = net_ptrs(base, p.net);
+    const NetPtrs P = net_ptrs(MODE == kResident ? (const char*)smem : p.net.base, p.net);
 
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
-    const int wpb = blockDim.x >> 6;
-    const long total_waves = (long)gridDim.x * wpb;
+    const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6;
     const long n_units = (long)p.K * p.n_tiles;
 
-    for (long u = (long)blockIdx.x * wpb + (threadIdx.x >> 6); u < n_units; u += total_waves) {
-        const int k = (int)(u / p.n_tiles), tile = (int)(u % p.n_tiles);
-        const int i = tile * 32 + col;
-        const bool valid = i < p.N;
-        float st[SS];
+    auto body = [&](auto& src) {
+        // block-uniform loop: every wave of a block walks the same sequence of
+        // (unit, step) iterations, idle waves on a masked dummy unit
+        for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
+            const long u = ub * wpb + wave;
+            const bool unit_ok = u < n_units;
+            const int k = unit_ok ? (int)(u / p.n_tiles) : 0;
+            const int tile = unit_ok ? (int)(u % p.n_tiles) : 0;
+            const int i = tile * 32 + col;
+            const bool valid = unit_ok && i < p.N;
+            float st[SS];
 #pragma unroll
-        for (int s = 0; s < SS; ++s) {
-            int f = 2 * s + g;
-            st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+            for (int s = 0; s < SS; ++s) {
+                int f = 2 * s + g;
+                st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+            }
+            float G = 0.0f;
+            double disc = 1.0;
+            for (int t = 0; t < p.H; ++t) {
+                float slots[NT::IN_SLOTS];
+#pragma unroll
+                for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+                for (int s = 0; s < SS; ++s) slots[s] = st[s];
+                if (D_A > 0) {
+                    const float* a = reinterpret_cast<const float*>(p.cands) + ((size_t)k * p.H + t) * D_A;
+#pragma unroll
+                    for (int s = 0; s < SA; ++s) {
+                        int f = 2 * s + g;
+                        slots[SS + s] = f < D_A ? a[f] : 0.0f;
+                    }
+                }
+                if (p.noise) {
+                    const float* nsrc = p.noise + (((size_t)k * p.N + (valid ? i : 0)) * p.H + t) * D_W;
+#pragma unroll
+                    for (int s = 0; s < SW; ++s) {
+                        int f = noise_feature(s, g);
+                        slots[SS + SA + s] = f < D_W ? nsrc[f] : 0.0f;
+                    }
+                } else {
+                    float nz[SW];
+                    noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t,
+                                           3u, g);
+#pragma unroll
+                    for (int s = 0; s < SW; ++s) slots[SS + SA + s] = nz[s];
+                }
+                const float* b0 = P.b0;
+                if (N_ACT > 0) {
+                    int a = reinterpret_cast<const int32_t*>(p.cands)[(size_t)k * p.H + t];
+                    if (a < 0 || a >= N_ACT) {
+                        if (p.status && lane == 0 && unit_ok) p.status[0] = 1;
+                        a = 0;
+                    }
+                    b0 += (size_t)a * p.net.b0_stride;
+                }
+                float r_cur = 0.0f;
+                if (p.reward_at) r_cur = reward_of(st, p.goal, SS, D_S, g);
+                f32x16 out = run_net<NT>(src, P, b0, slots, lane, g);
+#pragma unroll
+                for (int s = 0; s < SS; ++s) st[s] += out[s];
+                float r = p.reward_at ? r_cur : reward_of(st, p.goal, SS, D_S, g);
+                G += (float)disc * r;
+                disc *= p.gamma;
+            }
+            if (p.returns && g == 0 && valid) p.returns[(size_t)k * p.N + i] = G;
+            float contrib = valid ? (p.belief_w ? (float)p.belief_w[i] * G : G) : 0.0f;
+            float tot = sum32(contrib);
+            if (lane == 0 && unit_ok) p.partials[(size_t)k * p.n_tiles + tile] = tot;
         }
-        float G = 0.0f;
-        double disc = 1.0;
-        for (int t = 0; t < p.H; ++t) {
-            float slots[NT::IN_SLOTS];
-#pragma unroll
-            for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
-#pragma unroll
-            for (int s = 0; s < SS; ++s) slots[s] = st[s];
-            if (D_A > 0) {
-                const float* a = reinterpret_cast<const float*>(p.cands) + ((size_t)k * p.H + t) * D_A;
-#pragma unroll
-                for (int s = 0; s < SA; ++s) {
-                    int f = 2 * s + g;
-                    slots[SS + s] = f < D_A ? a[f] : 0.0f;
-                }
-            }
-            if (p.noise) {
-                const float* src = p.noise + (((size_t)k * p.N + (valid ? i : 0)) * p.H + t) * D_W;
-#pragma unroll
-                for (int s = 0; s < SW; ++s) {
-                    int f = noise_feature(s, g);
-                    slots[SS + SA + s] = f < D_W ? src[f] : 0.0f;
-                }
-            } else {
-                float nz[SW];
-                noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 3u, g);
-#pragma unroll
-                for (int s = 0; s < SW; ++s) slots[SS + SA + s] = nz[s];
-            }
-            const float* b0 = P.b0;
-            if (N_ACT > 0) {
-                int a = reinterpret_cast<const int32_t*>(p.cands)[(size_t)k * p.H + t];
-                if (a < 0 || a >= N_ACT) {
-                    if (p.status && lane == 0) p.status[0] = 1;
-                    a = 0;
-                }
-                b0 += (size_t)a * p.net.b0_stride;
-            }
-            float r_cur = 0.0f;
-            if (p.reward_at) r_cur = reward_of(st, p.goal, SS, D_S, g);
-            f32x16 out = run_net<NT>(P, b0, slots, lane, g);
-#pragma unroll
-            for (int s = 0; s < SS; ++s) st[s] += out[s];
-            float r = p.reward_at ? r_cur : reward_of(st, p.goal, SS, D_S, g);
-            G += (float)disc * r;
-            disc *= p.gamma;
-        }
-        if (p.returns && g == 0 && valid) p.returns[(size_t)k * p.N + i] = G;
-        float contrib = valid ? (p.belief_w ? (float)p.belief_w[i] * G : G) : 0.0f;
-        float tot = sum32(contrib);
-        if (lane == 0) p.partials[(size_t)k * p.n_tiles + tile] = tot;
+    };
+    if constexpr (MODE == kStream) {
+        StreamSrc<NT> src(smem, P.f0);
+        src.start();
+        body(src);
+        src.finish();
+    } else {
+        DirectSrc<DT, 8 * NT::HT> src(P.f0);
+        body(src);
     }
 }
 
@@ -157,8 +177,9 @@ __global__ __launch_bounds__(256) void fold_kernel(FoldParams p) {
 // ---------------------------------------------------------------------------
 // update stage 1: proposal and likelihood
 // ---------------------------------------------------------------------------
-template <int DT, int D_S, int D_W, int WIDTH, int NHID, bool WLDS>
+template <int DT, int D_S, int D_W, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
+    constexpr bool WLDS = MODE == kResident;
     constexpr int SS = state_slots(D_S), SW = noise_slots(D_W);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_W)> NTT;
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, 0)> NTL;
@@ -199,7 +220,8 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
 #pragma unroll
             for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
         }
-        f32x16 d = run_net<NTT>(PT, p.b0_trans, slots, lane, g);
+        DirectSrc<DT, 4 * NTT::HT> srct(PT.f0);
+        f32x16 d = run_net<NTT>(srct, PT, p.b0_trans, slots, lane, g);
         float ls[NTL::IN_SLOTS];
 #pragma unroll
         for (int s = 0; s < NTL::IN_SLOTS; ++s) ls[s] = 0.0f;
@@ -210,7 +232,8 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
             ls[s] = st[s];
             if (valid && f < D_S) p.prop[(size_t)i * D_S + f] = st[s];
         }
-        f32x16 lo = run_net<NTL>(PL, p.b0_lik, ls, lane, g);
+        DirectSrc<DT, 4 * NTL::HT> srcl(PL.f0);
+        f32x16 lo = run_net<NTL>(srcl, PL, p.b0_lik, ls, lane, g);
         if (g == 0 && valid) {
             float l = lo[0];
             if (p.loglik) p.loglik[i] = l;
@@ -225,8 +248,9 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
 // ---------------------------------------------------------------------------
 // observe
 // ---------------------------------------------------------------------------
-template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID, bool WLDS>
+template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
+    constexpr bool WLDS = MODE == kResident;
     constexpr int SS = state_slots(D_S), SW = noise_slots(D_WZ);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ)> NTO;
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -261,7 +285,8 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
 #pragma unroll
             for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
         }
-        f32x16 o = run_net<NTO>(PO, p.b0, slots, lane, g);
+        DirectSrc<DT, 4 * NTO::HT> srco(PO.f0);
+        f32x16 o = run_net<NTO>(srco, PO, p.b0, slots, lane, g);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             int f = 2 * s + g;
@@ -469,6 +494,10 @@ __global__ __launch_bounds__(256) void philox_kernel(PhiloxParams p) {
 namespace {
 
 template <int W> constexpr bool lds_for_width() { return W <= 64; }
+// weight access of the rollout kernel and of the single-pass kernels
+template <int W> constexpr int plan_mode() { return W <= 64 ? kResident : kStream; }
+template <int W> constexpr int pass_mode() { return W <= 64 ? kResident : kDirect; }
+constexpr size_t kStreamLds = 2 * 32768;
 
 }  // namespace
 
@@ -486,12 +515,12 @@ VOILA_IN_SLOTS(obs_in_slots, in_slots(dt, s.d_s, 0, s.d_wz))
 VOILA_IN_SLOTS(lik_in_slots, in_slots(dt, s.d_s, 0, 0))
 #undef VOILA_IN_SLOTS
 
-#define PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) plan_kernel<DT, ds, na, da, dw, w, nh, lds_for_width<w>()>
-#define PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) propose_kernel<DT, ds, dw, w, nh, lds_for_width<w>()>
-#define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, lds_for_width<w>()>
+#define PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) plan_kernel<DT, ds, na, da, dw, w, nh, plan_mode<w>()>
+#define PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) propose_kernel<DT, ds, dw, w, nh, pass_mode<w>()>
+#define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, pass_mode<w>()>
 
 hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s) {
-    const size_t lds = weights_in_lds(shape) ? p.net.bytes : 0;
+    const size_t lds = weights_in_lds(shape) ? p.net.bytes : kStreamLds;
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
     case id * 2 + 0:                                                                                       \
@@ -559,9 +588,9 @@ int plan_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
     case id * 2 + 0:                                                                                        \
-        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : 0); \
+        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kStreamLds); \
     case id * 2 + 1:                                                                                        \
-        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : 0);
+        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kStreamLds);
         VOILA_SHAPES(X)
 #undef X
     }
