@@ -28,6 +28,22 @@ METRIC = "generator rollout steps/s + belief-update particles/s, BF16 vs FP32 at
 PEAK_F32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 
+# HBM bytes per launch of the f32 rollout kernel from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes (scaled by the counters' reading of a copy kernel of known
+# size, see profiles/plan_kernel_f32_realistic.md), valid only for the kernel
+# sources they were taken on.
+MEASURED_TRAFFIC = {"sources_sha256_16": "dd1985543c094317", "bytes": (8293 + 1024) * 1024}
+
+
+def kernel_sources_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_19729_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def trans_flops_per_step(model):
     """2 * MACs of one transition-network evaluation, one-hot inputs excluded."""
@@ -61,9 +77,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-cands", type=int, default=2, help="candidates in the oracle's timed sample")
+    ap.add_argument("--cpu-cands", type=int, default=12, help="candidates in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build",
@@ -153,8 +171,12 @@ def main():
         "update_ms": upd_ms,
         "update_particles_per_s": N / (upd_ms / 1000.0),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_F32_TFLOPS, "traffic": None,
-                     "kernel": "plan_kernel (f32, realistic)"},
+                     "frac": achieved / PEAK_F32_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC["bytes"]
+                     if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"] else None,
+                     "kernel": "plan_kernel (f32, realistic)",
+                     "flop_per_rollout_step": trans_flops_per_step(w.model),
+                     "rollout_steps_per_launch": steps_per_step},
     }
 
     if not args.no_bf16:
@@ -180,6 +202,14 @@ def main():
                           "max_rel_q_diff_vs_f32": float(np.max(np.abs(qbh - qf) / np.abs(qf))),
                           "roofline_frac_bf16_peak": flops / (bms / 1000.0) / 1e12 / PEAK_BF16_TFLOPS}
         print(f"[bench] bf16 plan {bms:.2f} ms", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        x = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        result["calibration"] = {"kernel": "elementwise mul (torch)", "read_bytes": x.numel() * 4,
+                                 "write_bytes": y.numel() * 4}
 
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
