@@ -208,6 +208,71 @@ voila_status_t voila_observe(voila_model_t model, const float* d_states, int32_t
                              float* d_obs_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batches: many independent planning instances (uneven N, K, H; one network
+ * each, all of one shape and precision) in one persistent launch, each
+ * followed by its own belief update (the per-action-node grouping of
+ * simulations of Sec. 4.3 is the paper's analogue).  A batch is built once
+ * ([sync]: it uploads the instance tables and cost-sorted work lists and
+ * allocates its own device workspace), then run on a stream, or captured
+ * once into a hipGraph and replayed.  Per-run inputs -- executed actions,
+ * observations and resampling offsets -- are read from device arrays at run
+ * time, so a captured graph replays with whatever those arrays hold.
+ * Only network shapes whose kernels stage the whole network in LDS (hidden
+ * width <= 64) can be batched; N <= voila_update_max_particles() when the
+ * update is used.
+ * ------------------------------------------------------------------------- */
+typedef struct voila_batch_s* voila_batch_t;
+
+typedef struct {
+    voila_model_t model;       /* this instance's networks                        */
+    const float* d_states;     /* [N][d_s] belief particles                        */
+    const double* d_belief_w;  /* [N] normalised weights or NULL (uniform)         */
+    int32_t N;
+    const void* d_cands;       /* int32 [K][H] or float [K][H][d_a]                */
+    int32_t K, H;
+    double gamma;
+    const float* h_goal;       /* host [d_s], read during voila_batch_create       */
+    uint64_t seed;             /* Philox key of this instance's rollout noise      */
+    int32_t crn, reward_at;
+    float* d_q_out;            /* [K]                                              */
+    float* d_returns_out;      /* [K][N] or NULL                                   */
+    /* belief update of this instance (VOILA_BATCH_UPDATE) */
+    double lambda;
+    uint64_t update_seed;      /* Philox key of the proposal noise                 */
+    float* d_states_out;       /* [N][d_s] (required for the update)               */
+    int32_t* d_idx_out;        /* [N] or NULL                                      */
+    double* d_w_out;           /* [N] or NULL                                      */
+    double* d_stats_out;       /* [2] or NULL                                      */
+} voila_batch_item_t;
+
+/* Schedule of the persistent batch kernels (autotuned by the Python layer). */
+typedef struct {
+    int32_t waves_per_block;   /* 1..8 waves of 64 lanes per workgroup (default 4)             */
+    int32_t blocks_per_cu;     /* resident workgroups per CU; 0 = as many as fit (default)     */
+    int32_t dynamic;           /* 1 = atomic queue over cost-sorted items (default), 0 = static */
+} voila_batch_tuning_t;
+
+#define VOILA_BATCH_PLAN 1
+#define VOILA_BATCH_UPDATE 2
+
+/* [sync] h_tuning may be NULL (defaults). */
+voila_status_t voila_batch_create(const voila_batch_item_t* h_items, int32_t n_items,
+                                  const voila_batch_tuning_t* h_tuning, voila_batch_t* out);
+/* [sync] Frees the batch, its workspace and its graph (NULL accepted). */
+voila_status_t voila_batch_destroy(voila_batch_t batch);
+/* Enqueues plan and/or update (what = VOILA_BATCH_PLAN | VOILA_BATCH_UPDATE) of
+ * every instance.  For the update: d_actions int32 [n] or float [n][d_a],
+ * d_obs float [n][d_o], d_resample_u uint32 [n] (instance order). */
+voila_status_t voila_batch_run(voila_batch_t batch, int32_t what, const void* d_actions, const float* d_obs,
+                               const uint32_t* d_resample_u, int32_t* d_status, void* stream);
+/* [sync] Captures voila_batch_run with these arguments into a hipGraph owned
+ * by the batch (replacing a previous one). */
+voila_status_t voila_batch_capture(voila_batch_t batch, int32_t what, const void* d_actions, const float* d_obs,
+                                   const uint32_t* d_resample_u, int32_t* d_status);
+/* Launches the captured graph on `stream`. */
+voila_status_t voila_batch_replay(voila_batch_t batch, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Test hook: the counter-based draws the kernels consume.  Fills
  * d_out [n][d] float with the normals of counters (c0_base + r, c1, c2) of
  * `stream` for r < n, and d_words [n][4 * ceil(d/4)] uint32 (may be NULL) with

@@ -63,6 +63,23 @@ class _UpdateOpts(ctypes.Structure):
     _fields_ = [("lambda_", c_double), ("seed", c_uint64), ("resample_u", c_uint32), ("d_noise", c_void_p)]
 
 
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("model", c_void_p), ("d_states", c_void_p), ("d_belief_w", c_void_p), ("N", c_int32),
+                ("d_cands", c_void_p), ("K", c_int32), ("H", c_int32), ("gamma", c_double),
+                ("h_goal", POINTER(c_float)), ("seed", c_uint64), ("crn", c_int32), ("reward_at", c_int32),
+                ("d_q_out", c_void_p), ("d_returns_out", c_void_p), ("lambda_", c_double),
+                ("update_seed", c_uint64), ("d_states_out", c_void_p), ("d_idx_out", c_void_p),
+                ("d_w_out", c_void_p), ("d_stats_out", c_void_p)]
+
+
+class _BatchTuning(ctypes.Structure):
+    _fields_ = [("waves_per_block", c_int32), ("blocks_per_cu", c_int32), ("dynamic", c_int32)]
+
+
+VOILA_BATCH_PLAN = 1
+VOILA_BATCH_UPDATE = 2
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2606_19729_amd/build.py "
@@ -101,6 +118,16 @@ def _load():
     L.voila_philox_normals.argtypes = [c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int32, c_int32, vp,
                                        vp, vp]
     L.voila_philox_normals.restype = c_int32
+    L.voila_batch_create.argtypes = [POINTER(_BatchItem), c_int32, POINTER(_BatchTuning), POINTER(vp)]
+    L.voila_batch_create.restype = c_int32
+    L.voila_batch_destroy.argtypes = [vp]
+    L.voila_batch_destroy.restype = c_int32
+    L.voila_batch_run.argtypes = [vp, c_int32, vp, vp, vp, vp, vp]
+    L.voila_batch_run.restype = c_int32
+    L.voila_batch_capture.argtypes = [vp, c_int32, vp, vp, vp, vp]
+    L.voila_batch_capture.restype = c_int32
+    L.voila_batch_replay.argtypes = [vp, vp]
+    L.voila_batch_replay.restype = c_int32
     return L
 
 
@@ -110,7 +137,9 @@ lib = _load()
 EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_model_create",
             "voila_model_destroy", "voila_plan_workspace_size", "voila_plan", "voila_update_workspace_size",
             "voila_update", "voila_update_max_particles", "voila_normalize", "voila_resample_bits",
-            "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_philox_normals"]
+            "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_philox_normals",
+            "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
+            "voila_batch_replay"]
 
 
 def _check(st):
@@ -346,3 +375,87 @@ def philox_normals(seed, c0, c1, c2, stream_id, n, d, device=0, stream=None):
     _check(lib.voila_philox_normals(int(seed) & (2**64 - 1), int(c0), int(c1), int(c2), int(stream_id), int(n),
                                     int(d), _ptr(out), _ptr(words), _stream(stream)))
     return out, words
+
+
+class Batch:
+    """Many planning instances (+ their belief updates) in one persistent launch.
+
+    ``instances`` is a list of dicts with keys: model (Model), states [N, d_s],
+    cands, gamma, goal, seed, and optionally belief_w, crn, reward_at,
+    want_returns, and for the update: lam, update_seed.  Output tensors are
+    allocated here and exposed as ``q[j]``, ``returns[j]``, ``new_states[j]``,
+    ``idx[j]``, ``w[j]``, ``stats[j]``.
+    """
+
+    def __init__(self, instances, with_update=True, waves_per_block=4, blocks_per_cu=0, dynamic=True):
+        self.n = len(instances)
+        self.keep = []
+        items = (_BatchItem * self.n)()
+        self.q, self.returns, self.new_states, self.idx, self.w, self.stats = [], [], [], [], [], []
+        self.models = [inst["model"] for inst in instances]
+        for j, inst in enumerate(instances):
+            m = inst["model"]
+            d = m.desc
+            S = inst["states"]
+            N = int(S.shape[0])
+            _dev(S, torch.float32, (N, d.d_s), f"instances[{j}].states")
+            C = inst["cands"]
+            _dev(C, torch.int32 if d.n_actions > 0 else torch.float32, None, f"instances[{j}].cands")
+            K, H = int(C.shape[0]), int(C.shape[1])
+            bw = inst.get("belief_w")
+            if bw is not None:
+                _dev(bw, torch.float64, (N,), f"instances[{j}].belief_w")
+            dev = S.device
+            q = torch.empty(K, dtype=torch.float32, device=dev)
+            G = torch.empty((K, N), dtype=torch.float32, device=dev) if inst.get("want_returns") else None
+            goal = (c_float * d.d_s)(*[float(x) for x in inst["goal"]])
+            self.keep += [S, C, bw, goal]
+            it = items[j]
+            it.model, it.d_states, it.d_belief_w, it.N = m.handle, _ptr(S), _ptr(bw), N
+            it.d_cands, it.K, it.H = _ptr(C), K, H
+            it.gamma, it.h_goal, it.seed = float(inst["gamma"]), goal, int(inst.get("seed", 0)) & (2**64 - 1)
+            it.crn, it.reward_at = int(bool(inst.get("crn", False))), int(inst.get("reward_at", 0))
+            it.d_q_out, it.d_returns_out = _ptr(q), _ptr(G)
+            self.q.append(q)
+            self.returns.append(G)
+            if with_update:
+                ns = torch.empty((N, d.d_s), dtype=torch.float32, device=dev)
+                ix = torch.empty(N, dtype=torch.int32, device=dev)
+                ww = torch.empty(N, dtype=torch.float64, device=dev)
+                st = torch.empty(2, dtype=torch.float64, device=dev)
+                it.lambda_ = float(inst.get("lam", 1.0))
+                it.update_seed = int(inst.get("update_seed", 0)) & (2**64 - 1)
+                it.d_states_out, it.d_idx_out, it.d_w_out, it.d_stats_out = _ptr(ns), _ptr(ix), _ptr(ww), _ptr(st)
+                self.new_states.append(ns)
+                self.idx.append(ix)
+                self.w.append(ww)
+                self.stats.append(st)
+        tun = _BatchTuning(int(waves_per_block), int(blocks_per_cu), int(bool(dynamic)))
+        self.handle = c_void_p()
+        _check(lib.voila_batch_create(items, self.n, ctypes.byref(tun), ctypes.byref(self.handle)))
+        self.items = items
+
+    def run(self, what=VOILA_BATCH_PLAN | VOILA_BATCH_UPDATE, actions=None, obs=None, resample_u=None, status=None,
+            stream=None):
+        _check(lib.voila_batch_run(self.handle, int(what), _ptr(actions), _ptr(obs), _ptr(resample_u), _ptr(status),
+                                   _stream(stream)))
+
+    def capture(self, what=VOILA_BATCH_PLAN | VOILA_BATCH_UPDATE, actions=None, obs=None, resample_u=None,
+                status=None):
+        self._graph_args = (actions, obs, resample_u, status)
+        _check(lib.voila_batch_capture(self.handle, int(what), _ptr(actions), _ptr(obs), _ptr(resample_u),
+                                       _ptr(status)))
+
+    def replay(self, stream=None):
+        _check(lib.voila_batch_replay(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib.voila_batch_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

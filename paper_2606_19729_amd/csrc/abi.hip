@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -709,6 +710,335 @@ voila_status_t voila_philox_normals(uint64_t seed, uint32_t c0_base, uint32_t c1
     p.c2 = c2;
     p.stream = stream_id;
     VOILA_CHECK_HIP(launch_philox(p, reinterpret_cast<hipStream_t>(stream)));
+    return VOILA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+struct voila_batch_s {
+    int device = 0, shape = 0, dt = 0, n = 0, cus = 1, wpb = 4, dynamic = 1;
+    bool has_update = false;
+    char* mem = nullptr;
+    PlanParams* d_plan = nullptr;
+    QReduceParams* d_qr = nullptr;
+    ProposeParams* d_prop = nullptr;
+    FoldBatchItem* d_fold = nullptr;
+    NormResParams* d_nr = nullptr;
+    int4* d_plan_items = nullptr;
+    int4* d_prop_items = nullptr;
+    int* d_counters = nullptr;
+    int n_plan_items = 0, n_prop_items = 0, max_k = 0, width = 0;
+    size_t plan_lds = 0, prop_lds = 0;
+    int plan_blocks = 1, prop_blocks = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Work items of `count` units split into pieces of at most `wpb`: (instance, first, units, cost).
+void add_items(std::vector<int4>& out, int inst, long units, int wpb, int cost_per_unit) {
+    for (long u0 = 0; u0 < units; u0 += wpb) {
+        int c = (int)std::min<long>(wpb, units - u0);
+        out.push_back(make_int4(inst, (int)u0, c, cost_per_unit * c));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+voila_status_t voila_batch_create(const voila_batch_item_t* items, int32_t n, const voila_batch_tuning_t* tuning,
+                                  voila_batch_t* out) {
+    if (!items || !out || n < 1) return fail(VOILA_ERR_INVALID_ARG, "NULL items / output or n < 1");
+    *out = nullptr;
+    voila_batch_tuning_t tu{4, 0, 1};
+    if (tuning) tu = *tuning;
+    if (tu.waves_per_block < 1 || tu.waves_per_block > 8 || tu.blocks_per_cu < 0)
+        return fail(VOILA_ERR_INVALID_ARG, "waves_per_block must be 1..8 and blocks_per_cu >= 0");
+    const voila_model_s* m0 = items[0].model;
+    if (!m0) return fail(VOILA_ERR_INVALID_ARG, "NULL model in item 0");
+    const bool upd = items[0].d_states_out != nullptr;
+    for (int j = 0; j < n; ++j) {
+        const voila_batch_item_t& it = items[j];
+        const std::string tag = "item " + std::to_string(j) + ": ";
+        if (!it.model) return fail(VOILA_ERR_INVALID_ARG, tag + "NULL model");
+        if (it.model->shape != m0->shape || it.model->dt != m0->dt || it.model->device != m0->device)
+            return fail(VOILA_ERR_INVALID_ARG, tag + "models must share shape, precision and device");
+        if (it.N < 1 || it.K < 0 || it.H < 0) return fail(VOILA_ERR_INVALID_ARG, tag + "N >= 1, K >= 0, H >= 0");
+        if ((long long)it.K * it.N > (1LL << 31) - 1) return fail(VOILA_ERR_UNSUPPORTED, tag + "K * N too large");
+        if (!(it.gamma >= 0.0 && it.gamma <= 1.0)) return fail(VOILA_ERR_INVALID_ARG, tag + "gamma outside [0, 1]");
+        if (!it.h_goal || !it.d_states) return fail(VOILA_ERR_INVALID_ARG, tag + "NULL goal or states");
+        if (it.K > 0 && (!it.d_q_out || (it.H > 0 && !it.d_cands)))
+            return fail(VOILA_ERR_INVALID_ARG, tag + "NULL q_out or candidates");
+        if (it.reward_at != 0 && it.reward_at != 1) return fail(VOILA_ERR_INVALID_ARG, tag + "reward_at must be 0 or 1");
+        if ((it.d_states_out != nullptr) != upd)
+            return fail(VOILA_ERR_INVALID_ARG, tag + "either every item or no item has update outputs");
+        if (upd) {
+            if (!it.model->has_lik) return fail(VOILA_ERR_INVALID_ARG, tag + "model has no likelihood network");
+            if (!(it.lambda > 0.0) || !std::isfinite(it.lambda)) return fail(VOILA_ERR_INVALID_ARG, tag + "lambda must be > 0");
+            if (it.N > kNormResMaxN) return fail(VOILA_ERR_UNSUPPORTED, tag + "N above voila_update_max_particles()");
+        }
+    }
+    if (!weights_in_lds(m0->shape))
+        return fail(VOILA_ERR_UNSUPPORTED, "batches need networks that fit in LDS (hidden width <= 64)");
+    DeviceGuard guard(m0->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+
+    voila_batch_s* b = new voila_batch_s();
+    b->device = m0->device;
+    b->shape = m0->shape;
+    b->dt = m0->dt;
+    b->n = n;
+    b->cus = m0->cus;
+    b->wpb = tu.waves_per_block;
+    b->dynamic = tu.dynamic ? 1 : 0;
+    b->has_update = upd;
+    b->width = m0->width;
+    const int d_s = m0->d_s, W = m0->width;
+
+    // device memory plan: tables, work lists, partial sums, update workspace, counters
+    std::vector<PlanParams> hp(n);
+    std::vector<QReduceParams> hq(n);
+    std::vector<ProposeParams> hpr(upd ? n : 0);
+    std::vector<FoldBatchItem> hf(upd ? 2 * n : 0);
+    std::vector<NormResParams> hn(upd ? n : 0);
+    std::vector<int4> plan_items, prop_items;
+    std::vector<size_t> part_off(n), ws_off(n);
+    size_t part_bytes = 0, ws_bytes = 0;
+    for (int j = 0; j < n; ++j) {
+        const voila_batch_item_t& it = items[j];
+        const int n_tiles = (it.N + 31) / 32;
+        part_off[j] = part_bytes;
+        part_bytes = align_up(part_bytes + (size_t)it.K * n_tiles * 4, 256);
+        if (upd) {
+            ws_off[j] = ws_bytes;
+            ws_bytes += carve_update(nullptr, W, it.N, d_s).bytes;
+        }
+        add_items(plan_items, j, (long)it.K * n_tiles, b->wpb, it.H);
+        if (upd) add_items(prop_items, j, n_tiles, b->wpb, 1);
+        b->max_k = std::max(b->max_k, it.K);
+    }
+    if (b->dynamic) {
+        // longest first; items of one instance stay contiguous (equal cost per unit)
+        std::stable_sort(plan_items.begin(), plan_items.end(), [&](const int4& a, const int4& c) {
+            int ha = items[a.x].H, hc = items[c.x].H;
+            return ha != hc ? ha > hc : a.x < c.x;
+        });
+    }
+    b->n_plan_items = (int)plan_items.size();
+    b->n_prop_items = (int)prop_items.size();
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_plan = take(sizeof(PlanParams) * n), o_qr = take(sizeof(QReduceParams) * n);
+    const size_t o_prop = take(sizeof(ProposeParams) * hpr.size()), o_fold = take(sizeof(FoldBatchItem) * hf.size());
+    const size_t o_nr = take(sizeof(NormResParams) * hn.size());
+    const size_t o_pi = take(sizeof(int4) * plan_items.size()), o_ri = take(sizeof(int4) * prop_items.size());
+    const size_t o_cnt = take(2 * sizeof(int));
+    const size_t o_part = take(part_bytes), o_ws = take(ws_bytes);
+    if (hipMalloc(&b->mem, off) != hipSuccess) {
+        delete b;
+        return fail(VOILA_ERR_DEVICE, "hipMalloc of the batch workspace failed");
+    }
+    char* base = b->mem;
+    for (int j = 0; j < n; ++j) {
+        const voila_batch_item_t& it = items[j];
+        const voila_model_s* m = it.model;
+        const int n_tiles = (it.N + 31) / 32;
+        PlanParams& p = hp[j];
+        p = PlanParams{};
+        p.net = m->trans_plan;
+        p.states = it.d_states;
+        p.belief_w = it.d_belief_w;
+        p.cands = it.d_cands;
+        p.returns = it.d_returns_out;
+        p.partials = reinterpret_cast<float*>(base + o_part + part_off[j]);
+        p.N = it.N;
+        p.K = it.K;
+        p.H = it.H;
+        p.n_tiles = n_tiles;
+        p.gamma = it.gamma;
+        p.key0 = (uint32_t)(it.seed & 0xffffffffu);
+        p.key1 = (uint32_t)(it.seed >> 32);
+        p.crn = it.crn ? 1 : 0;
+        p.reward_at = it.reward_at;
+        for (int c = 0; c < 32; ++c) p.goal[c] = c < d_s ? it.h_goal[c] : 0.0f;
+        hq[j] = QReduceParams{p.partials, it.d_q_out, it.K, n_tiles,
+                              it.d_belief_w ? 1.0f : (float)(1.0 / (double)it.N)};
+        b->plan_lds = std::max<size_t>(b->plan_lds, m->trans_plan.bytes);
+        if (upd) {
+            UpdateWs w = carve_update(base + o_ws + ws_off[j], W, it.N, d_s);
+            const int aw = m->action_width();
+            hf[2 * j] = FoldBatchItem{m->fold_w_trans, m->fold_b_trans, w.b0_trans, W, m->nf_trans, m->n_actions,
+                                      m->d_a, m->d_o, m->dt == DT_BF16, 0, j};
+            hf[2 * j + 1] = FoldBatchItem{m->fold_w_lik, m->fold_b_lik, w.b0_lik, W, m->nf_lik, m->n_actions,
+                                          m->d_a, m->d_o, m->dt == DT_BF16, 1, j};
+            (void)aw;
+            ProposeParams& q = hpr[j];
+            q = ProposeParams{};
+            q.trans = m->trans_upd;
+            q.lik = m->lik;
+            q.b0_trans = w.b0_trans;
+            q.b0_lik = w.b0_lik;
+            q.states = it.d_states;
+            q.prior_w = it.d_belief_w;
+            q.prop = w.prop;
+            q.x = w.x;
+            q.N = it.N;
+            q.lambda = it.lambda;
+            q.key0 = (uint32_t)(it.update_seed & 0xffffffffu);
+            q.key1 = (uint32_t)(it.update_seed >> 32);
+            NormResParams& r = hn[j];
+            r = NormResParams{};
+            r.x = w.x;
+            r.N = it.N;
+            r.bits = voila_resample_bits(it.N);
+            r.uniform_prior = it.d_belief_w ? 0 : 1;
+            r.do_resample = 1;
+            r.lambda = it.lambda;
+            r.w_out = it.d_w_out;
+            r.stats = it.d_stats_out;
+            r.idx_out = it.d_idx_out;
+            r.src = w.prop;
+            r.dst = it.d_states_out;
+            r.row_floats = d_s;
+            b->prop_lds = std::max<size_t>(b->prop_lds, (size_t)m->trans_upd.bytes + m->lik.bytes);
+        }
+    }
+    b->d_plan = reinterpret_cast<PlanParams*>(base + o_plan);
+    b->d_qr = reinterpret_cast<QReduceParams*>(base + o_qr);
+    b->d_prop = reinterpret_cast<ProposeParams*>(base + o_prop);
+    b->d_fold = reinterpret_cast<FoldBatchItem*>(base + o_fold);
+    b->d_nr = reinterpret_cast<NormResParams*>(base + o_nr);
+    b->d_plan_items = reinterpret_cast<int4*>(base + o_pi);
+    b->d_prop_items = reinterpret_cast<int4*>(base + o_ri);
+    b->d_counters = reinterpret_cast<int*>(base + o_cnt);
+    std::vector<char> host(o_part, 0);
+    auto put = [&](size_t o, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(host.data() + o, src, bytes);
+    };
+    put(o_plan, hp.data(), sizeof(PlanParams) * n);
+    put(o_qr, hq.data(), sizeof(QReduceParams) * n);
+    put(o_prop, hpr.data(), sizeof(ProposeParams) * hpr.size());
+    put(o_fold, hf.data(), sizeof(FoldBatchItem) * hf.size());
+    put(o_nr, hn.data(), sizeof(NormResParams) * hn.size());
+    put(o_pi, plan_items.data(), sizeof(int4) * plan_items.size());
+    put(o_ri, prop_items.data(), sizeof(int4) * prop_items.size());
+    if (hipMemcpy(b->mem, host.data(), o_part, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(b->mem);
+        delete b;
+        return fail(VOILA_ERR_DEVICE, "upload of the batch tables failed");
+    }
+    const int bpc_plan = tu.blocks_per_cu ? tu.blocks_per_cu
+                                          : plan_batch_blocks_per_cu(b->shape, b->dt, b->wpb, b->plan_lds);
+    b->plan_blocks = std::max(1, std::min(b->n_plan_items, b->cus * bpc_plan));
+    if (upd) {
+        const int bpc_prop = tu.blocks_per_cu ? tu.blocks_per_cu
+                                              : propose_batch_blocks_per_cu(b->shape, b->dt, b->wpb, b->prop_lds);
+        b->prop_blocks = std::max(1, std::min(b->n_prop_items, b->cus * bpc_prop));
+    }
+    *out = b;
+    return VOILA_OK;
+}
+
+voila_status_t voila_batch_destroy(voila_batch_t b) {
+    if (!b) return VOILA_OK;
+    {
+        DeviceGuard guard(b->device);
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        if (b->mem) (void)hipFree(b->mem);
+    }
+    delete b;
+    return VOILA_OK;
+}
+
+static voila_status_t batch_enqueue(voila_batch_t b, int32_t what, const void* d_actions, const float* d_obs,
+                                    const uint32_t* d_u, int32_t* d_status, hipStream_t s) {
+    if (what & VOILA_BATCH_PLAN) {
+        if (b->dynamic) VOILA_CHECK_HIP(launch_reset_counter(b->d_counters, s));
+        BatchPlanParams p{b->d_plan, b->d_plan_items, b->n_plan_items, b->dynamic, b->d_counters, d_status};
+        VOILA_CHECK_HIP(launch_plan_batch(b->shape, b->dt, p, b->plan_blocks, b->wpb, b->plan_lds, s));
+        VOILA_CHECK_HIP(launch_q_reduce_batch(b->d_qr, b->n, b->max_k, s));
+    }
+    if (what & VOILA_BATCH_UPDATE) {
+        VOILA_CHECK_HIP(launch_fold_batch(b->d_fold, 2 * b->n, b->width, d_actions, d_obs, d_status, s));
+        if (b->dynamic) VOILA_CHECK_HIP(launch_reset_counter(b->d_counters + 1, s));
+        BatchProposeParams p{b->d_prop, b->d_prop_items, b->n_prop_items, b->dynamic, b->d_counters + 1, d_status};
+        VOILA_CHECK_HIP(launch_propose_batch(b->shape, b->dt, p, b->prop_blocks, b->wpb, b->prop_lds, s));
+        VOILA_CHECK_HIP(launch_norm_res_batch(b->d_nr, b->n, d_u, d_status, s));
+    }
+    return VOILA_OK;
+}
+
+static voila_status_t batch_check(voila_batch_t b, int32_t what, const void* d_actions, const float* d_obs,
+                                  const uint32_t* d_u) {
+    if (!b) return fail(VOILA_ERR_INVALID_ARG, "NULL batch");
+    if (what < 1 || what > 3) return fail(VOILA_ERR_INVALID_ARG, "what must combine VOILA_BATCH_PLAN / _UPDATE");
+    if (what & VOILA_BATCH_UPDATE) {
+        if (!b->has_update) return fail(VOILA_ERR_INVALID_ARG, "the batch was created without update outputs");
+        if (!d_actions || !d_obs || !d_u) return fail(VOILA_ERR_INVALID_ARG, "NULL actions, observations or offsets");
+    }
+    return VOILA_OK;
+}
+
+voila_status_t voila_batch_run(voila_batch_t b, int32_t what, const void* d_actions, const float* d_obs,
+                               const uint32_t* d_u, int32_t* d_status, void* stream) {
+    voila_status_t st = batch_check(b, what, d_actions, d_obs, d_u);
+    if (st != VOILA_OK) return st;
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    return batch_enqueue(b, what, d_actions, d_obs, d_u, d_status, reinterpret_cast<hipStream_t>(stream));
+}
+
+voila_status_t voila_batch_capture(voila_batch_t b, int32_t what, const void* d_actions, const float* d_obs,
+                                   const uint32_t* d_u, int32_t* d_status) {
+    voila_status_t st = batch_check(b, what, d_actions, d_obs, d_u);
+    if (st != VOILA_OK) return st;
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = nullptr;
+    VOILA_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = batch_enqueue(b, what, d_actions, d_obs, d_u, d_status, s);
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (st == VOILA_OK && e2 != hipSuccess) st = fail(VOILA_ERR_DEVICE, "hipStreamEndCapture failed");
+    } else {
+        st = fail(VOILA_ERR_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(s);
+    if (st != VOILA_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(VOILA_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph = g;
+    b->exec = ex;
+    return VOILA_OK;
+}
+
+voila_status_t voila_batch_replay(voila_batch_t b, void* stream) {
+    if (!b) return fail(VOILA_ERR_INVALID_ARG, "NULL batch");
+    if (!b->exec) return fail(VOILA_ERR_INVALID_ARG, "no captured graph: call voila_batch_capture first");
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    VOILA_CHECK_HIP(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
     return VOILA_OK;
 }
 

@@ -59,9 +59,80 @@ constexpr int kDirect = 0;    // straight from global memory (L2)
 constexpr int kResident = 1;  // whole network staged in LDS once per block
 constexpr int kStream = 2;    // streamed through double-buffered LDS chunks
 
+// One (candidate, 32-particle) tile of one planning instance: H steps of the
+// transition network with the states in registers, then the tile's returns
+// and their (weighted) sum.  `unit_ok` false runs a masked dummy tile (the
+// caller's loop is block-uniform) that writes nothing.
+template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, class Src>
+__device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const PlanParams& p, long u, bool unit_ok,
+                                          int lane, int g, int col) {
+    constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
+    const int k = unit_ok ? (int)(u / p.n_tiles) : 0;
+    const int tile = unit_ok ? (int)(u % p.n_tiles) : 0;
+    const int i = tile * 32 + col;
+    const bool valid = unit_ok && i < p.N;
+    float st[SS];
+#pragma unroll
+    for (int s = 0; s < SS; ++s) {
+        int f = 2 * s + g;
+        st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+    }
+    float G = 0.0f;
+    double disc = 1.0;
+    for (int t = 0; t < p.H; ++t) {
+        float slots[NT::IN_SLOTS];
+#pragma unroll
+        for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SS; ++s) slots[s] = st[s];
+        if (D_A > 0) {
+            const float* a = reinterpret_cast<const float*>(p.cands) + ((size_t)k * p.H + t) * D_A;
+#pragma unroll
+            for (int s = 0; s < SA; ++s) {
+                int f = 2 * s + g;
+                slots[SS + s] = f < D_A ? a[f] : 0.0f;
+            }
+        }
+        if (p.noise) {
+            const float* nsrc = p.noise + (((size_t)k * p.N + (valid ? i : 0)) * p.H + t) * D_W;
+#pragma unroll
+            for (int s = 0; s < SW; ++s) {
+                int f = noise_feature(s, g);
+                slots[SS + SA + s] = f < D_W ? nsrc[f] : 0.0f;
+            }
+        } else {
+            float nz[SW];
+            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 3u, g);
+#pragma unroll
+            for (int s = 0; s < SW; ++s) slots[SS + SA + s] = nz[s];
+        }
+        const float* b0 = P.b0;
+        if (N_ACT > 0) {
+            int a = reinterpret_cast<const int32_t*>(p.cands)[(size_t)k * p.H + t];
+            if (a < 0 || a >= N_ACT) {
+                if (p.status && lane == 0 && unit_ok) p.status[0] = 1;
+                a = 0;
+            }
+            b0 += (size_t)a * p.net.b0_stride;
+        }
+        float r_cur = 0.0f;
+        if (p.reward_at) r_cur = reward_of(st, p.goal, SS, D_S, g);
+        f32x16 out = run_net<NT>(src, P, b0, slots, lane, g);
+#pragma unroll
+        for (int s = 0; s < SS; ++s) st[s] += out[s];
+        float r = p.reward_at ? r_cur : reward_of(st, p.goal, SS, D_S, g);
+        G += (float)disc * r;
+        disc *= p.gamma;
+    }
+    if (p.returns && g == 0 && valid) p.returns[(size_t)k * p.N + i] = G;
+    float contrib = valid ? (p.belief_w ? (float)p.belief_w[i] * G : G) : 0.0f;
+    float tot = sum32(contrib);
+    if (lane == 0 && unit_ok) p.partials[(size_t)k * p.n_tiles + tile] = tot;
+}
+
 template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
-    constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     if (MODE == kResident) {
@@ -69,79 +140,15 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
         __syncthreads();
     }
     const NetPtrs P = net_ptrs(MODE == kResident ? (const char*)smem : p.net.base, p.net);
-
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6;
     const long n_units = (long)p.K * p.n_tiles;
-
     auto body = [&](auto& src) {
         // block-uniform loop: every wave of a block walks the same sequence of
         // (unit, step) iterations, idle waves on a masked dummy unit
         for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
             const long u = ub * wpb + wave;
-            const bool unit_ok = u < n_units;
-            const int k = unit_ok ? (int)(u / p.n_tiles) : 0;
-            const int tile = unit_ok ? (int)(u % p.n_tiles) : 0;
-            const int i = tile * 32 + col;
-            const bool valid = unit_ok && i < p.N;
-            float st[SS];
-#pragma unroll
-            for (int s = 0; s < SS; ++s) {
-                int f = 2 * s + g;
-                st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
-            }
-            float G = 0.0f;
-            double disc = 1.0;
-            for (int t = 0; t < p.H; ++t) {
-                float slots[NT::IN_SLOTS];
-#pragma unroll
-                for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
-#pragma unroll
-                for (int s = 0; s < SS; ++s) slots[s] = st[s];
-                if (D_A > 0) {
-                    const float* a = reinterpret_cast<const float*>(p.cands) + ((size_t)k * p.H + t) * D_A;
-#pragma unroll
-                    for (int s = 0; s < SA; ++s) {
-                        int f = 2 * s + g;
-                        slots[SS + s] = f < D_A ? a[f] : 0.0f;
-                    }
-                }
-                if (p.noise) {
-                    const float* nsrc = p.noise + (((size_t)k * p.N + (valid ? i : 0)) * p.H + t) * D_W;
-#pragma unroll
-                    for (int s = 0; s < SW; ++s) {
-                        int f = noise_feature(s, g);
-                        slots[SS + SA + s] = f < D_W ? nsrc[f] : 0.0f;
-                    }
-                } else {
-                    float nz[SW];
-                    noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t,
-                                           3u, g);
-#pragma unroll
-                    for (int s = 0; s < SW; ++s) slots[SS + SA + s] = nz[s];
-                }
-                const float* b0 = P.b0;
-                if (N_ACT > 0) {
-                    int a = reinterpret_cast<const int32_t*>(p.cands)[(size_t)k * p.H + t];
-                    if (a < 0 || a >= N_ACT) {
-                        if (p.status && lane == 0 && unit_ok) p.status[0] = 1;
-                        a = 0;
-                    }
-                    b0 += (size_t)a * p.net.b0_stride;
-                }
-                float r_cur = 0.0f;
-                if (p.reward_at) r_cur = reward_of(st, p.goal, SS, D_S, g);
-                f32x16 out = run_net<NT>(src, P, b0, slots, lane, g);
-#pragma unroll
-                for (int s = 0; s < SS; ++s) st[s] += out[s];
-                float r = p.reward_at ? r_cur : reward_of(st, p.goal, SS, D_S, g);
-                G += (float)disc * r;
-                disc *= p.gamma;
-            }
-            if (p.returns && g == 0 && valid) p.returns[(size_t)k * p.N + i] = G;
-            float contrib = valid ? (p.belief_w ? (float)p.belief_w[i] * G : G) : 0.0f;
-            float tot = sum32(contrib);
-            if (lane == 0 && unit_ok) p.partials[(size_t)k * p.n_tiles + tile] = tot;
+            plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, u, u < n_units, lane, g, col);
         }
     };
     if constexpr (MODE == kStream) {
@@ -154,6 +161,52 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
         body(src);
     }
 }
+
+// Many planning instances of one network shape in one persistent launch.
+// The work list holds block items (instance, first tile unit, number of
+// units): a block takes items from a queue (atomic counter, list sorted by
+// decreasing cost) or in a static stride, restages the instance's network in
+// LDS when the instance changes, and runs one unit per wave.
+template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID>
+__global__ __launch_bounds__(512) void plan_batch_kernel(BatchPlanParams bp) {
+    if constexpr (WIDTH > 64) {
+        return;  // batches need networks that fit in LDS (the launcher refuses wider ones)
+    } else {
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __shared__ int s_item;
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wave = threadIdx.x >> 6;
+    int loaded = -1;
+    int item = blockIdx.x;
+    for (int iter = 0;; ++iter) {
+        if (bp.dynamic) {
+            if (threadIdx.x == 0) s_item = atomicAdd(bp.counter, 1);
+            __syncthreads();
+            item = s_item;
+            __syncthreads();
+        } else if (iter > 0) {
+            item += gridDim.x;
+        }
+        if (item >= bp.n_items) break;
+        const int4 it = bp.items[item];  // (instance, first unit, units, cost)
+        PlanParams p = bp.insts[it.x];
+        p.status = bp.status;
+        if (it.x != loaded) {
+            __syncthreads();
+            stage_blob(smem, p.net.base, p.net.bytes);
+            __syncthreads();
+            loaded = it.x;
+        }
+        const NetPtrs P = net_ptrs(smem, p.net);
+        DirectSrc<DT, 8 * NT::HT> src(P.f0);
+        const long u = (long)it.y + wave;
+        plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, u, wave < it.z, lane, g, col);
+    }
+    }
+}
+
+__global__ __launch_bounds__(64) void reset_counter_kernel(int* counter) { if (threadIdx.x == 0) *counter = 0; }
 
 __global__ __launch_bounds__(256) void q_reduce_kernel(QReduceParams p) {
     const int lane = threadIdx.x & 63;
@@ -174,15 +227,117 @@ __global__ __launch_bounds__(256) void fold_kernel(FoldParams p) {
     p.out[r] = acc;
 }
 
+__global__ __launch_bounds__(256) void q_reduce_batch_kernel(const QReduceParams* qs) {
+    const QReduceParams p = qs[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (k >= p.K) return;
+    float s = 0.0f;
+    for (int j = lane; j < p.n_tiles; j += 64) s += p.partials[(size_t)k * p.n_tiles + j];
+    s += __shfl_xor(s, 32);
+    s = sum32(s);
+    if (lane == 0) p.q[k] = s * p.scale;
+}
+
+// Per-instance first-layer bias with the instance's action (and observation)
+// folded in; the fold inputs are read from device memory so the launch can be
+// replayed from a graph with new actions / observations.
+__global__ __launch_bounds__(256) void fold_batch_kernel(const FoldBatchItem* items, const void* actions,
+                                                         const float* obs, int32_t* status) {
+    const FoldBatchItem p = items[blockIdx.y];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= p.width) return;
+    float acc = p.b[r];
+    int c = 0;
+    if (p.n_actions > 0) {
+        int a = reinterpret_cast<const int32_t*>(actions)[p.inst];
+        if (a < 0 || a >= p.n_actions) {
+            if (status && r == 0) status[0] = 1;
+            a = 0;
+        }
+        acc += p.w[(size_t)r * p.nf + a];
+        c = p.n_actions;
+    } else {
+        const float* ac = reinterpret_cast<const float*>(actions) + (size_t)p.inst * p.d_a;
+        for (int j = 0; j < p.d_a; ++j, ++c) {
+            float v = ac[j];
+            if (p.bf16) v = (float)(__bf16)v;
+            acc += p.w[(size_t)r * p.nf + c] * v;
+        }
+    }
+    if (p.with_obs) {
+        const float* ob = obs + (size_t)p.inst * p.d_o;
+        for (int j = 0; j < p.d_o; ++j, ++c) {
+            float v = ob[j];
+            if (p.bf16) v = (float)(__bf16)v;
+            acc += p.w[(size_t)r * p.nf + c] * v;
+        }
+    }
+    p.out[r] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // update stage 1: proposal and likelihood
 // ---------------------------------------------------------------------------
-template <int DT, int D_S, int D_W, int WIDTH, int NHID, int MODE>
-__global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
-    constexpr bool WLDS = MODE == kResident;
+// One 32-particle tile of the update's first stage: proposal through the
+// transition network, likelihood of the proposal, x = l / lambda (+ log prior).
+template <int DT, int D_S, int D_W, int WIDTH, int NHID>
+__device__ __forceinline__ void propose_tile(const NetPtrs& PT, const NetPtrs& PL, const ProposeParams& p, int tile,
+                                             bool tile_ok, int lane, int g, int col) {
     constexpr int SS = state_slots(D_S), SW = noise_slots(D_W);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_W)> NTT;
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, 0)> NTL;
+    const int i = tile * 32 + col;
+    const bool valid = tile_ok && i < p.N;
+    float slots[NTT::IN_SLOTS];
+#pragma unroll
+    for (int s = 0; s < NTT::IN_SLOTS; ++s) slots[s] = 0.0f;
+    float st[SS];
+#pragma unroll
+    for (int s = 0; s < SS; ++s) {
+        int f = 2 * s + g;
+        st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+        slots[s] = st[s];
+    }
+    if (p.noise) {
+#pragma unroll
+        for (int s = 0; s < SW; ++s) {
+            int f = noise_feature(s, g);
+            slots[SS + s] = (valid && f < D_W) ? p.noise[(size_t)i * D_W + f] : 0.0f;
+        }
+    } else {
+        float nz[SW];
+        noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, 0u, 0u, 5u, g);
+#pragma unroll
+        for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
+    }
+    DirectSrc<DT, 4 * NTT::HT> srct(PT.f0);
+    f32x16 d = run_net<NTT>(srct, PT, p.b0_trans, slots, lane, g);
+    float ls[NTL::IN_SLOTS];
+#pragma unroll
+    for (int s = 0; s < NTL::IN_SLOTS; ++s) ls[s] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < SS; ++s) {
+        int f = 2 * s + g;
+        st[s] += d[s];
+        ls[s] = st[s];
+        if (valid && f < D_S) p.prop[(size_t)i * D_S + f] = st[s];
+    }
+    DirectSrc<DT, 4 * NTL::HT> srcl(PL.f0);
+    f32x16 lo = run_net<NTL>(srcl, PL, p.b0_lik, ls, lane, g);
+    if (g == 0 && valid) {
+        float l = lo[0];
+        if (p.loglik) p.loglik[i] = l;
+        if (!isfinite(l) && p.status) p.status[0] = 5;
+        double x = (double)l / p.lambda;
+        if (p.prior_w) x += log(p.prior_w[i]);
+        p.x[i] = x;
+    }
+}
+
+template <int DT, int D_S, int D_W, int WIDTH, int NHID, int MODE>
+__global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
+    constexpr bool WLDS = MODE == kResident;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     if (WLDS) {
         stage_blob(smem, p.trans.base, p.trans.bytes);
@@ -191,57 +346,50 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
     }
     const NetPtrs PT = net_ptrs(WLDS ? (const char*)smem : p.trans.base, p.trans);
     const NetPtrs PL = net_ptrs(WLDS ? (const char*)smem + p.trans.bytes : p.lik.base, p.lik);
-
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wpb = blockDim.x >> 6;
     const int n_tiles = (p.N + 31) / 32;
-    for (int tile = blockIdx.x * wpb + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * wpb) {
-        const int i = tile * 32 + col;
-        const bool valid = i < p.N;
-        float slots[NTT::IN_SLOTS];
-#pragma unroll
-        for (int s = 0; s < NTT::IN_SLOTS; ++s) slots[s] = 0.0f;
-        float st[SS];
-#pragma unroll
-        for (int s = 0; s < SS; ++s) {
-            int f = 2 * s + g;
-            st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
-            slots[s] = st[s];
+    for (int tile = blockIdx.x * wpb + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * wpb)
+        propose_tile<DT, D_S, D_W, WIDTH, NHID>(PT, PL, p, tile, true, lane, g, col);
+}
+
+// Update stage 1 of many instances: block items (instance, first tile, tiles),
+// networks restaged in LDS on an instance change.
+template <int DT, int D_S, int D_W, int WIDTH, int NHID>
+__global__ __launch_bounds__(512) void propose_batch_kernel(BatchProposeParams bp) {
+    if constexpr (WIDTH > 64) {
+        return;  // batches need networks that fit in LDS (the launcher refuses wider ones)
+    } else {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __shared__ int s_item;
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wave = threadIdx.x >> 6;
+    int loaded = -1;
+    int item = blockIdx.x;
+    for (int iter = 0;; ++iter) {
+        if (bp.dynamic) {
+            if (threadIdx.x == 0) s_item = atomicAdd(bp.counter, 1);
+            __syncthreads();
+            item = s_item;
+            __syncthreads();
+        } else if (iter > 0) {
+            item += gridDim.x;
         }
-        if (p.noise) {
-#pragma unroll
-            for (int s = 0; s < SW; ++s) {
-                int f = noise_feature(s, g);
-                slots[SS + s] = (valid && f < D_W) ? p.noise[(size_t)i * D_W + f] : 0.0f;
-            }
-        } else {
-            float nz[SW];
-            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, 0u, 0u, 5u, g);
-#pragma unroll
-            for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
+        if (item >= bp.n_items) break;
+        const int4 it = bp.items[item];
+        ProposeParams p = bp.insts[it.x];
+        p.status = bp.status;
+        if (it.x != loaded) {
+            __syncthreads();
+            stage_blob(smem, p.trans.base, p.trans.bytes);
+            stage_blob(smem + p.trans.bytes, p.lik.base, p.lik.bytes);
+            __syncthreads();
+            loaded = it.x;
         }
-        DirectSrc<DT, 4 * NTT::HT> srct(PT.f0);
-        f32x16 d = run_net<NTT>(srct, PT, p.b0_trans, slots, lane, g);
-        float ls[NTL::IN_SLOTS];
-#pragma unroll
-        for (int s = 0; s < NTL::IN_SLOTS; ++s) ls[s] = 0.0f;
-#pragma unroll
-        for (int s = 0; s < SS; ++s) {
-            int f = 2 * s + g;
-            st[s] += d[s];
-            ls[s] = st[s];
-            if (valid && f < D_S) p.prop[(size_t)i * D_S + f] = st[s];
-        }
-        DirectSrc<DT, 4 * NTL::HT> srcl(PL.f0);
-        f32x16 lo = run_net<NTL>(srcl, PL, p.b0_lik, ls, lane, g);
-        if (g == 0 && valid) {
-            float l = lo[0];
-            if (p.loglik) p.loglik[i] = l;
-            if (!isfinite(l) && p.status) p.status[0] = 5;
-            double x = (double)l / p.lambda;
-            if (p.prior_w) x += log(p.prior_w[i]);
-            p.x[i] = x;
-        }
+        const NetPtrs PT = net_ptrs(smem, p.trans);
+        const NetPtrs PL = net_ptrs(smem + p.trans.bytes, p.lik);
+        propose_tile<DT, D_S, D_W, WIDTH, NHID>(PT, PL, p, it.y + wave, wave < it.z, lane, g, col);
+    }
     }
 }
 
@@ -349,10 +497,7 @@ __device__ int block_max_i(int v, int* red) {
 
 }  // namespace
 
-__global__ __launch_bounds__(kNormResThreads) void norm_res_kernel(NormResParams p) {
-    __shared__ double buf[kNormResMaxN];
-    __shared__ double redd[kNRWaves];
-    __shared__ int redi[kNRWaves];
+__device__ void norm_res_body(const NormResParams& p, double* buf, double* redd, int* redi) {
     const int tid = threadIdx.x, N = p.N;
 
     if (!p.w_in) {
@@ -467,6 +612,25 @@ __global__ __launch_bounds__(kNormResThreads) void norm_res_kernel(NormResParams
             for (int c = 0; c < p.row_floats; ++c)
                 p.dst[(size_t)j * p.row_floats + c] = p.src[(size_t)idx * p.row_floats + c];
     }
+}
+
+__global__ __launch_bounds__(kNormResThreads) void norm_res_kernel(NormResParams p) {
+    __shared__ double buf[kNormResMaxN];
+    __shared__ double redd[kNRWaves];
+    __shared__ int redi[kNRWaves];
+    norm_res_body(p, buf, redd, redi);
+}
+
+// One workgroup per instance.
+__global__ __launch_bounds__(kNormResThreads) void norm_res_batch_kernel(const NormResParams* ps, const uint32_t* us,
+                                                                          int32_t* status) {
+    __shared__ double buf[kNormResMaxN];
+    __shared__ double redd[kNRWaves];
+    __shared__ int redi[kNRWaves];
+    NormResParams p = ps[blockIdx.x];
+    if (us) p.U = us[blockIdx.x];
+    p.status = status;
+    norm_res_body(p, buf, redd, redi);
 }
 
 __global__ __launch_bounds__(256) void philox_kernel(PhiloxParams p) {
@@ -619,6 +783,108 @@ int observe_blocks_per_cu(int shape, int dt) {
 #undef X
     }
     return 1;
+}
+
+#define PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) plan_batch_kernel<DT, ds, na, da, dw, w, nh>
+#define PROPB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) propose_batch_kernel<DT, ds, dw, w, nh>
+
+hipError_t launch_plan_batch(int shape, int dt, const BatchPlanParams& p, int blocks, int wpb, size_t lds,
+                             hipStream_t s) {
+    if (!weights_in_lds(shape)) return hipErrorInvalidValue;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                     \
+    case id * 2 + 0:                                                                                              \
+        hipLaunchKernelGGL((PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 64 * wpb, lds, s, p);   \
+        break;                                                                                                    \
+    case id * 2 + 1:                                                                                              \
+        hipLaunchKernelGGL((PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 64 * wpb, lds, s, p);  \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_propose_batch(int shape, int dt, const BatchProposeParams& p, int blocks, int wpb, size_t lds,
+                                hipStream_t s) {
+    if (!weights_in_lds(shape)) return hipErrorInvalidValue;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                     \
+    case id * 2 + 0:                                                                                              \
+        hipLaunchKernelGGL((PROPB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 64 * wpb, lds, s, p);   \
+        break;                                                                                                    \
+    case id * 2 + 1:                                                                                              \
+        hipLaunchKernelGGL((PROPB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 64 * wpb, lds, s, p);  \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+namespace {
+template <class KernelT>
+int occupancy_t(KernelT k, int threads, size_t lds) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+}  // namespace
+
+int plan_batch_blocks_per_cu(int shape, int dt, int wpb, size_t lds) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                        \
+    case id * 2 + 0:                                                                                 \
+        return occupancy_t(PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), 64 * wpb, lds);      \
+    case id * 2 + 1:                                                                                 \
+        return occupancy_t(PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), 64 * wpb, lds);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+int propose_batch_blocks_per_cu(int shape, int dt, int wpb, size_t lds) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                        \
+    case id * 2 + 0:                                                                                 \
+        return occupancy_t(PROPB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), 64 * wpb, lds);      \
+    case id * 2 + 1:                                                                                 \
+        return occupancy_t(PROPB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), 64 * wpb, lds);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+hipError_t launch_q_reduce_batch(const QReduceParams* d_qs, int n_inst, int max_k, hipStream_t s) {
+    if (n_inst == 0 || max_k == 0) return hipSuccess;
+    hipLaunchKernelGGL(q_reduce_batch_kernel, dim3((max_k + 3) / 4, n_inst), 256, 0, s, d_qs);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_batch(const FoldBatchItem* d_items, int n_items, int max_width, const void* d_actions,
+                             const float* d_obs, int32_t* d_status, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(fold_batch_kernel, dim3((max_width + 255) / 256, n_items), 256, 0, s, d_items, d_actions, d_obs,
+                       d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_res_batch(const NormResParams* d_ps, int n_inst, const uint32_t* d_u, int32_t* d_status,
+                                 hipStream_t s) {
+    if (n_inst == 0) return hipSuccess;
+    hipLaunchKernelGGL(norm_res_batch_kernel, n_inst, kNormResThreads, 0, s, d_ps, d_u, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(int* d_counter, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, 1, 64, 0, s, d_counter);
+    return hipGetLastError();
 }
 
 hipError_t launch_q_reduce(const QReduceParams& p, hipStream_t s) {

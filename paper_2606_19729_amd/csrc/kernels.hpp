@@ -101,6 +101,35 @@ struct NormResParams {
     int32_t* status;         // or NULL
 };
 
+// Many instances in one launch.  items[j] = (instance, first unit, units in
+// this item (<= waves per block), cost used for ordering).
+struct BatchPlanParams {
+    const PlanParams* insts;
+    const int4* items;
+    int n_items;
+    int dynamic;   // 1: items taken from the atomic counter in list order
+    int* counter;
+    int32_t* status;
+};
+
+struct BatchProposeParams {
+    const ProposeParams* insts;
+    const int4* items;
+    int n_items;
+    int dynamic;
+    int* counter;
+    int32_t* status;
+};
+
+// Fold of instance `inst`'s action (and observation) into a first-layer bias;
+// actions and observations are read at run time from arrays indexed by inst.
+struct FoldBatchItem {
+    const float* w;   // [width][nf]
+    const float* b;   // [width]
+    float* out;       // [width]
+    int width, nf, n_actions, d_a, d_o, bf16, with_obs, inst;
+};
+
 struct PhiloxParams {
     float* out;
     uint32_t* words;
@@ -119,6 +148,18 @@ hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks,
 hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);
 hipError_t launch_norm_res(const NormResParams& p, hipStream_t s);
 hipError_t launch_philox(const PhiloxParams& p, hipStream_t s);
+hipError_t launch_plan_batch(int shape, int dt, const BatchPlanParams& p, int blocks, int waves_per_block,
+                             size_t lds, hipStream_t s);
+hipError_t launch_q_reduce_batch(const QReduceParams* d_qs, int n_inst, int max_k, hipStream_t s);
+hipError_t launch_fold_batch(const FoldBatchItem* d_items, int n_items, int max_width, const void* d_actions,
+                             const float* d_obs, int32_t* d_status, hipStream_t s);
+hipError_t launch_propose_batch(int shape, int dt, const BatchProposeParams& p, int blocks, int waves_per_block,
+                                size_t lds, hipStream_t s);
+hipError_t launch_norm_res_batch(const NormResParams* d_ps, int n_inst, const uint32_t* d_u, int32_t* d_status,
+                                 hipStream_t s);
+hipError_t launch_reset_counter(int* d_counter, hipStream_t s);
+int plan_batch_blocks_per_cu(int shape, int dt, int waves_per_block, size_t lds);
+int propose_batch_blocks_per_cu(int shape, int dt, int waves_per_block, size_t lds);
 
 // Resident blocks per CU of the plan / propose / observe kernels.
 int plan_blocks_per_cu(int shape, int dt);

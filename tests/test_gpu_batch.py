@@ -1,0 +1,192 @@
+"""Batched persistent launches (many uneven instances + their updates), graph
+capture and replay, and the schedule autotuner.
+
+A batch runs exactly the per-tile arithmetic of the single-instance kernels,
+so its Q, returns, weights, indices and new beliefs must equal the
+single-instance calls bit for bit (and those are checked against the oracle in
+test_gpu_parity.py); a few instances are also compared with the oracle here.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_19729_amd as lib
+    return lib
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+SIZES = [(40, 3, 5), (256, 7, 0), (300, 5, 12), (1000, 2, 9), (33, 11, 1), (129, 4, 30), (5, 1, 3), (700, 6, 7)]
+
+
+def make_instances(V, compute, sizes=SIZES, seed0=500):
+    insts, works = [], []
+    for j, (N, K, H) in enumerate(sizes):
+        w = workloads.small(seed=seed0 + j, N=N, K=K, H=H, compute=compute)
+        m = V.Model(w.model, compute=compute)
+        insts.append(dict(model=m, states=dev(w.states), cands=dev(w.cands, torch.int32), gamma=w.gamma,
+                          goal=w.goal, seed=w.plan_seed, want_returns=True, lam=w.lam, update_seed=w.update_seed))
+        works.append(w)
+    return insts, works
+
+
+def update_inputs(works):
+    obs = np.stack([oracle.draw_observation(w).astype(np.float32) for w in works])
+    acts = np.array([w.update_action for w in works], np.int32)
+    us = np.array([w.resample_u for w in works], np.uint32)
+    return dev(acts, torch.int32), dev(obs), dev(us.view(np.int32), torch.int32), obs
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+@pytest.mark.parametrize("dynamic", [True, False])
+def test_batch_equals_single_instance_calls(V, compute, dynamic):
+    insts, works = make_instances(V, compute)
+    acts, obs, us, obs_h = update_inputs(works)
+    b = V.Batch(insts, with_update=True, waves_per_block=4, dynamic=dynamic)
+    b.run(actions=acts, obs=obs, resample_u=us)
+    torch.cuda.synchronize()
+    for j, (inst, w) in enumerate(zip(insts, works)):
+        print(f"batch instance {j} N={w.N} K={w.K} H={w.H} {compute} dynamic={dynamic}", flush=True)
+        q, G = V.plan(inst["model"], inst["states"], inst["cands"], w.gamma, w.goal, seed=w.plan_seed,
+                      return_G=True)
+        out = V.update(inst["model"], inst["states"], w.update_action, obs_h[j], lam=w.lam, seed=w.update_seed,
+                       U=w.resample_u)
+        torch.cuda.synchronize()
+        assert torch.equal(b.q[j], q)
+        assert torch.equal(b.returns[j], G)
+        assert torch.equal(b.new_states[j], out["states"])
+        assert torch.equal(b.idx[j], out["idx"])
+        assert torch.equal(b.w[j], out["w"])
+        assert torch.equal(b.stats[j], out["stats"])
+    b.close()
+
+
+def test_batch_matches_oracle_f32(V):
+    insts, works = make_instances(V, "f32", sizes=SIZES[:4])
+    acts, obs, us, obs_h = update_inputs(works)
+    b = V.Batch(insts, with_update=True)
+    b.run(actions=acts, obs=obs, resample_u=us)
+    torch.cuda.synchronize()
+    for j, w in enumerate(works):
+        if w.K == 0:
+            continue
+        Qr = oracle.plan(w.model, w.states, w.cands, w.gamma, w.goal, seed=w.plan_seed)
+        q = b.q[j].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(q - Qr) / np.abs(Qr)) <= 1e-5 if w.H > 0 else np.all(q == 0)
+        ref = oracle.update(w.model, w.states, w.update_action, obs_h[j], lam=w.lam, seed=w.update_seed,
+                            U=w.resample_u)
+        wd = b.w[j].cpu().numpy()
+        assert np.max(np.abs(wd - ref["w"])) <= 1e-5 * np.max(ref["w"]) + 1e-12
+        assert np.array_equal(b.idx[j].cpu().numpy(), oracle.resample(wd, w.resample_u))
+    b.close()
+
+
+def test_graph_replay_matches_eager_and_follows_new_inputs(V):
+    insts, works = make_instances(V, "bf16", sizes=SIZES[:5], seed0=700)
+    acts, obs, us, obs_h = update_inputs(works)
+    b = V.Batch(insts, with_update=True)
+    b.run(actions=acts, obs=obs, resample_u=us)
+    torch.cuda.synchronize()
+    ref = [(q.clone(), s.clone(), i.clone()) for q, s, i in zip(b.q, b.new_states, b.idx)]
+    b.capture(actions=acts, obs=obs, resample_u=us)
+    for rep in range(3):
+        for t in b.q + b.new_states:
+            t.fill_(float("nan"))
+        for t in b.idx:
+            t.fill_(-1)
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        _ = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
+        for j, (q, s, i) in enumerate(ref):
+            assert torch.equal(b.q[j], q), (rep, j)
+            assert torch.equal(b.new_states[j], s), (rep, j)
+            assert torch.equal(b.idx[j], i), (rep, j)
+    # new observations in the same device array: the replay follows them
+    obs2 = obs_h + np.float32(0.25)
+    obs.copy_(dev(obs2))
+    b.replay()
+    torch.cuda.synchronize()
+    for j, (inst, w) in enumerate(zip(insts, works)):
+        out = V.update(inst["model"], inst["states"], w.update_action, obs2[j], lam=w.lam, seed=w.update_seed,
+                       U=w.resample_u)
+        torch.cuda.synchronize()
+        assert torch.equal(b.new_states[j], out["states"])
+        assert torch.equal(b.w[j], out["w"])
+    b.close()
+
+
+def test_batch_rejects_bad_input(V):
+    insts, works = make_instances(V, "f32", sizes=SIZES[:2])
+    wide = workloads.realistic(N=64, K=2, H=2)
+    mw = V.Model(wide.model)
+    bad = dict(model=mw, states=dev(wide.states), cands=dev(wide.cands), gamma=0.9, goal=wide.goal)
+    with pytest.raises(V.VoilaError):
+        V.Batch([insts[0], bad])
+    b = V.Batch(insts, with_update=False)
+    with pytest.raises(V.VoilaError):
+        b.run(what=V.VOILA_BATCH_UPDATE)
+    acts, obs, us, _ = update_inputs(works)
+    acts.fill_(9)
+    b2 = V.Batch(insts, with_update=True)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b2.run(actions=acts, obs=obs, resample_u=us, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == V.VOILA_ERR_INVALID_ARG
+
+
+def test_autotuner_picks_a_measured_schedule(V, tmp_path, monkeypatch):
+    from paper_2606_19729_amd import autotune
+    monkeypatch.setenv("VOILA_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    insts, works = make_instances(V, "bf16", sizes=SIZES[:4], seed0=900)
+    acts, obs, us, _ = update_inputs(works)
+    cands = autotune.CANDIDATES[:3]
+    r = autotune.tune(insts, run_args=dict(actions=acts, obs=obs, resample_u=us), candidates=cands, reps=2)
+    assert not r["cached"] and r["schedule"] in cands
+    assert r["ms"] == min(t["ms"] for t in r["timings"])
+    r2 = autotune.tune(insts, run_args=dict(actions=acts, obs=obs, resample_u=us), candidates=cands)
+    assert r2["cached"] and r2["schedule"] == r["schedule"]
+
+
+def test_batched_workload_full_size_sampled(V):
+    # 64 instances, N in [256, 8192], H in [5, 30], K in [64, 1024], bf16
+    works = workloads.batched()
+    insts = []
+    for w in works:
+        m = V.Model(w.model, compute="bf16")
+        insts.append(dict(model=m, states=dev(w.states), cands=dev(w.cands, torch.int32), gamma=w.gamma,
+                          goal=w.goal, seed=w.plan_seed, lam=w.lam, update_seed=w.update_seed,
+                          want_returns=(w is works[0] or w is works[-1])))
+    acts, obs, us, obs_h = update_inputs(works)
+    b = V.Batch(insts, with_update=True)
+    b.run(actions=acts, obs=obs, resample_u=us)
+    torch.cuda.synchronize()
+    for j in [0, len(works) - 1]:
+        w = works[j]
+        G = b.returns[j].cpu().numpy().astype(np.float64)
+        rng = np.random.default_rng(j)
+        pairs = [(int(rng.integers(0, w.K)), int(rng.integers(0, w.N))) for _ in range(16)]
+        g_em = oracle.rollouts(w.model, w.states, w.cands, w.gamma, w.goal, pairs, seed=w.plan_seed, bf16=True)
+        e = np.median(np.abs(np.array([G[k, i] for k, i in pairs]) - g_em) / np.abs(g_em))
+        print(f"  instance {j}: N={w.N} K={w.K} H={w.H} median rollout err vs bf16 emulation {e:.2e}", flush=True)
+        assert e <= 2.0 ** -10
+        assert torch.allclose(b.q[j], b.returns[j].mean(dim=1), rtol=1e-5)
+        ref = oracle.update(w.model, w.states, w.update_action, obs_h[j], lam=w.lam, seed=w.update_seed,
+                            U=w.resample_u, bf16=True)
+        mean_d = b.w[j].cpu().numpy() @ ref["S_prop"]
+        mean_r = ref["w"] @ ref["S_prop"]
+        sd = np.sqrt(ref["w"] @ (ref["S_prop"] - mean_r) ** 2)
+        assert np.all(np.abs(mean_d - mean_r) <= 2.0 ** -8 * sd)
+    b.close()
