@@ -273,6 +273,50 @@ voila_status_t voila_batch_capture(voila_batch_t batch, int32_t what, const void
 voila_status_t voila_batch_replay(voila_batch_t batch, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Gradients through rollouts (adjoint with step checkpointing).  Rollout b:
+ * s_0 = S0_b, s_{t+1} = s_t + f_T([s_t, a_{b,t}, w_{b,t}]).  Objectives:
+ *   VOILA_OBJ_DISTILL  L = 1/(B H) sum_b sum_{t=1..H} ||s_{b,t} - T_{b,t}||^2:
+ *                      the distillation loss of Eq. 3 applied along
+ *                      free-running rollouts against teacher states T;
+ *   VOILA_OBJ_RETURN   J = 1/B sum_b sum_{t<H} gamma^t (-||s_{b,t+1} - g||^2):
+ *                      the mean discounted return of Sec. 2.1.
+ * Outputs: the objective, its gradient with respect to the transition
+ * network's parameters (W1, b1, W2, b2, W3, b3 concatenated, each as
+ * nn.Linear stores it) and, for continuous actions, with respect to the
+ * action sequences.  The forward pass stores a checkpoint every `checkpoint`
+ * steps; the reverse sweep recomputes each segment from its checkpoint.
+ * Binary32 models of networks with two hidden layers of width 64 only
+ * (otherwise VOILA_ERR_UNSUPPORTED).  Results are deterministic (fixed-order
+ * reductions).
+ * ------------------------------------------------------------------------- */
+#define VOILA_OBJ_DISTILL 0
+#define VOILA_OBJ_RETURN 1
+
+typedef struct {
+    int32_t B, H;               /* rollouts (>= 1), horizon (0..64)                            */
+    int32_t checkpoint;         /* checkpoint interval in steps (>= 1)                          */
+    const float* d_s0;          /* [B][d_s]                                                     */
+    const void* d_actions;      /* discrete: int32 [B][H]; continuous: float [B/particles][H][d_a] */
+    int32_t particles;          /* rollouts per continuous sequence (multiple of 32 when the
+                                   action gradient is requested); ignored for discrete actions  */
+    const float* d_noise;       /* [B][H][d_w] or NULL: Philox stream 3, counter (b, 0, t)       */
+    uint64_t seed;
+    int32_t objective;          /* VOILA_OBJ_DISTILL or VOILA_OBJ_RETURN                         */
+    const float* d_targets;     /* [B][H][d_s] teacher states s_1..s_H (distillation)           */
+    double gamma;               /* return objective                                             */
+    const float* h_goal;        /* host [d_s] (return objective)                                */
+    float* d_loss_out;          /* [1] or NULL                                                  */
+    float* d_grad_params;       /* [voila_grad_param_count(model)] or NULL                      */
+    float* d_grad_actions;      /* same layout as d_actions (continuous) or NULL                */
+} voila_grad_opts_t;
+
+/* Number of parameters of the transition network (length of d_grad_params). */
+int32_t voila_grad_param_count(voila_model_t model);
+size_t voila_rollout_grad_workspace_size(voila_model_t model, const voila_grad_opts_t* h_opts);
+voila_status_t voila_rollout_grad(voila_model_t model, const voila_grad_opts_t* h_opts, void* d_workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Test hook: the counter-based draws the kernels consume.  Fills
  * d_out [n][d] float with the normals of counters (c0_base + r, c1, c2) of
  * `stream` for r < n, and d_words [n][4 * ceil(d/4)] uint32 (may be NULL) with

@@ -146,6 +146,17 @@ def normals(seed, c0, c1, c2, stream, d):
     return out
 
 
+def normals_rows(seed, n, c1, c2, stream, d):
+    """Normals of counters (r, c1, c2) for r = 0..n-1 as an [n, d] array."""
+    L = lib()
+    if not hasattr(L, "_rows_ready"):
+        L.or_normals_rows.argtypes = [c_uint64, c_int, c_uint32, c_uint32, c_uint32, c_int, POINTER(c_double)]
+        L._rows_ready = True
+    out = np.zeros((n, d), np.float64)
+    L.or_normals_rows(int(seed), int(n), int(c1), int(c2), int(stream), int(d), _p(out))
+    return out
+
+
 def round_bf16(x):
     x = np.asarray(x, np.float64)
     f = np.vectorize(lambda v: lib().or_round_bf16(float(v)), otypes=[np.float64])
@@ -288,3 +299,95 @@ def draw_observation(w, bf16=False):
                         w.true_noise[None, :], bf16=bf16)
     return observe(m, s_next, a.reshape(1, -1) if m.n_actions == 0 else [int(a)],
                    noise=w.obs_noise[None, :], bf16=bf16)[0]
+
+
+# --------------------------------------------------------------------------- gradients
+DISTILL, RETURN = 0, 1
+
+
+def _grad_args(model, S0, actions, H, particles, noise, targets, goal):
+    S0 = _d(S0)
+    B = S0.shape[0]
+    if model.n_actions > 0:
+        ad = np.ascontiguousarray(np.asarray(actions, np.int32).reshape(B, H))
+        ac = None
+    else:
+        ad = None
+        ac = _d(np.asarray(actions).reshape(-1, H, model.d_a))
+    nz = None if noise is None else _d(np.asarray(noise).reshape(B, H, model.d_w))
+    tg = None if targets is None else _d(np.asarray(targets).reshape(B, H, model.d_s))
+    g = _d(goal) if goal is not None else np.zeros(model.d_s)
+    return S0, B, ad, ac, nz, tg, g
+
+
+def _lib_grad():
+    L = lib()
+    if not hasattr(L, "_grad_ready"):
+        dp, i32p, mp = POINTER(c_double), POINTER(c_int32), POINTER(_CModel)
+        L.or_rollout_objective.argtypes = [mp, c_int, c_int, c_int, dp, i32p, dp, dp, c_uint64, c_int, dp,
+                                           c_double, dp, POINTER(c_uint64)]
+        L.or_rollout_objective.restype = c_double
+        L.or_rollout_grad.argtypes = [mp, c_int, c_int, c_int, dp, i32p, dp, dp, c_uint64, c_int, dp, c_double,
+                                      dp, dp, dp, dp]
+        L._grad_ready = True
+    return L
+
+
+def rollout_objective(model, S0, actions, H, objective, targets=None, gamma=1.0, goal=None, particles=1,
+                      noise=None, seed=0, patterns=False):
+    """Distillation loss (objective 0) or mean discounted return (objective 1)
+    of free-running rollouts; with patterns=True also each rollout's ReLU
+    sign-pattern hash (to detect finite differences that straddle a kink)."""
+    S0, B, ad, ac, nz, tg, g = _grad_args(model, S0, actions, H, particles, noise, targets, goal)
+    pat = np.zeros(B, np.uint64) if patterns else None
+    b = _Bound(model)
+    v = _lib_grad().or_rollout_objective(b.ref(), B, H, particles, _p(S0), _p(ad, c_int32), _p(ac), _p(nz),
+                                         int(seed), int(objective), _p(tg), float(gamma), _p(g),
+                                         None if pat is None else pat.ctypes.data_as(POINTER(c_uint64)))
+    return (v, pat) if patterns else v
+
+
+def rollout_grad(model, S0, actions, H, objective, targets=None, gamma=1.0, goal=None, particles=1, noise=None,
+                 seed=0, want_params=True, want_actions=False):
+    """(objective value, d/dparams as [(dW, db), ...] or None, d/dA or None)."""
+    S0, B, ad, ac, nz, tg, g = _grad_args(model, S0, actions, H, particles, noise, targets, goal)
+    dims, params = flatten_layers(model.trans)
+    gp = np.zeros_like(params) if want_params else None
+    ga = np.zeros_like(ac) if (want_actions and ac is not None) else None
+    loss = np.zeros(1)
+    b = _Bound(model)
+    _check(_lib_grad().or_rollout_grad(b.ref(), B, H, particles, _p(S0), _p(ad, c_int32), _p(ac), _p(nz), int(seed),
+                                       int(objective), _p(tg), float(gamma), _p(g), _p(loss), _p(gp), _p(ga)),
+           "rollout_grad")
+    layers = None
+    if gp is not None:
+        layers, off = [], 0
+        for n_in, n_out in zip(dims[:-1], dims[1:]):
+            W = gp[off:off + n_out * n_in].reshape(n_out, n_in)
+            off += n_out * n_in
+            bb = gp[off:off + n_out]
+            off += n_out
+            layers.append((W, bb))
+    return float(loss[0]), layers, ga
+
+
+def teacher_targets(teacher_model, S0, actions, H, particles=1, noise=None, seed=0):
+    """States s_1..s_H [B, H, d_s] of the teacher network's rollouts from the
+    same initial states, actions and noise (the distillation targets)."""
+    S0 = _d(S0)
+    B, d_s = S0.shape
+    out = np.zeros((B, H, d_s))
+    s = S0.copy()
+    for t in range(H):
+        if teacher_model.n_actions > 0:
+            a = np.asarray(actions, np.int32).reshape(B, H)[:, t]
+        else:
+            A = np.asarray(actions, np.float64).reshape(-1, H, teacher_model.d_a)
+            a = A[np.arange(B) // particles, t]
+        if noise is not None:
+            w = np.asarray(noise, np.float64).reshape(B, H, teacher_model.d_w)[:, t]
+        else:
+            w = normals_rows(seed, B, 0, t, 3, teacher_model.d_w)
+        s = transition(teacher_model, s, a, w)
+        out[:, t] = s
+    return out

@@ -541,3 +541,274 @@ size_t or_mlp_param_count(int n_layers, const int* dims)
 {
     return mlp_param_count(n_layers, dims);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Gradients through rollouts of the transition sampler (reverse mode).      */
+/*                                                                           */
+/* Rollout b: s_0 = S0_b; for t < H: s_{t+1} = s_t + f_T([s_t, a_{b,t}, w_{b,t}]). */
+/* Objectives:                                                               */
+/*   distill (objective 0): L = 1/(B H) sum_b sum_{t=1..H} ||s_{b,t} - T_{b,t}||^2 */
+/*            with teacher states T (the distillation loss of Eq. 3 applied  */
+/*            along free-running rollouts);                                  */
+/*   return  (objective 1): J = 1/B sum_b sum_{t<H} gamma^t (-||s_{b,t+1} - g||^2). */
+/* Actions: discrete a_{b,t} = actions[b*H + t] (one-hot), or continuous     */
+/* sequences A[k][t][:] shared by `particles` consecutive rollouts           */
+/* (rollout b uses k = b / particles).  Noise: given [B][H][d_w] or Philox   */
+/* stream 3 with counter (b, 0, t).  The reverse sweep stores the whole     */
+/* trajectory (no checkpointing) and uses ReLU'(0) = 0.                      */
+/* ------------------------------------------------------------------------- */
+#define OR_GRAD_CHUNK 64
+
+static void grad_action(const or_model* m, int H, int particles, const int32_t* a_disc, const double* a_cont,
+                        int b, int t, int* ad, const double** ac)
+{
+    *ad = 0;
+    *ac = NULL;
+    if (m->n_actions > 0) *ad = a_disc[(size_t)b * H + t];
+    else *ac = a_cont + ((size_t)(b / particles) * H + t) * m->d_a;
+}
+
+static void grad_noise(const or_model* m, int H, const double* noise, uint64_t seed, int b, int t, double* w)
+{
+    if (noise) {
+        for (int j = 0; j < m->d_w; ++j) w[j] = noise[((size_t)b * H + t) * m->d_w + j];
+    } else {
+        or_normals(seed, (uint32_t)b, 0u, (uint32_t)t, OR_STREAM_PLAN, m->d_w, w);
+    }
+}
+
+/* Objective of one rollout and the hash of its ReLU sign pattern. */
+static double rollout_objective(const or_model* m, int B, int H, int particles, const double* S0,
+                                const int32_t* a_disc, const double* a_cont, const double* noise, uint64_t seed,
+                                int objective, const double* targets, double gamma, const double* goal, int b,
+                                uint64_t* pattern)
+{
+    double s[OR_MAX_WIDTH], x[OR_MAX_WIDTH], h[2][OR_MAX_WIDTH], w[OR_MAX_WIDTH];
+    int d_s = m->d_s, aw = action_width(m);
+    for (int j = 0; j < d_s; ++j) s[j] = S0[(size_t)b * d_s + j];
+    double acc = 0.0, disc = 1.0;
+    uint64_t hsh = 1469598103934665603ull;
+    for (int t = 0; t < H; ++t) {
+        int ad;
+        const double* ac;
+        grad_action(m, H, particles, a_disc, a_cont, b, t, &ad, &ac);
+        grad_noise(m, H, noise, seed, b, t, w);
+        for (int j = 0; j < d_s; ++j) x[j] = s[j];
+        put_action(m, x + d_s, ad, ac);
+        for (int j = 0; j < m->d_w; ++j) x[d_s + aw + j] = w[j];
+        /* forward through the layers, recording the ReLU signs */
+        const double* p = m->t_params;
+        const double* in = x;
+        int cur = 0;
+        for (int l = 0; l < m->t_layers; ++l) {
+            int n_in = m->t_dims[l], n_out = m->t_dims[l + 1];
+            const double* W = p;
+            const double* bb = p + (size_t)n_out * n_in;
+            double* out = h[cur];
+            for (int n = 0; n < n_out; ++n) {
+                double z = 0.0;
+                for (int k = 0; k < n_in; ++k) z += W[(size_t)n * n_in + k] * in[k];
+                z += bb[n];
+                if (l < m->t_layers - 1) {
+                    int on = z > 0.0;
+                    hsh = (hsh ^ (uint64_t)on) * 1099511628211ull;
+                    z = on ? z : 0.0;
+                }
+                out[n] = z;
+            }
+            p += (size_t)n_out * n_in + n_out;
+            in = out;
+            cur ^= 1;
+        }
+        for (int j = 0; j < d_s; ++j) s[j] += in[j];
+        if (objective == 0) {
+            const double* T = targets + ((size_t)b * H + t) * d_s;
+            for (int j = 0; j < d_s; ++j) acc += (s[j] - T[j]) * (s[j] - T[j]);
+        } else {
+            acc += disc * reward(d_s, s, goal);
+            disc *= gamma;
+        }
+    }
+    if (pattern) *pattern = hsh;
+    return acc;
+}
+
+/* Objective value over all rollouts (Neumaier over b) and, if `patterns` is
+ * non-NULL, each rollout's ReLU sign-pattern hash. */
+double or_rollout_objective(const or_model* m, int B, int H, int particles, const double* S0,
+                            const int32_t* a_disc, const double* a_cont, const double* noise, uint64_t seed,
+                            int objective, const double* targets, double gamma, const double* goal,
+                            uint64_t* patterns)
+{
+    double* per = (double*)malloc(sizeof(double) * (size_t)(B > 0 ? B : 1));
+    #pragma omp parallel for schedule(static)
+    for (int b = 0; b < B; ++b)
+        per[b] = rollout_objective(m, B, H, particles, S0, a_disc, a_cont, noise, seed, objective, targets, gamma,
+                                   goal, b, patterns ? patterns + b : NULL);
+    double total = weighted_sum(B, per, NULL, 1) * (double)B;  /* plain sum in order */
+    free(per);
+    double scale = objective == 0 ? 1.0 / ((double)B * H) : 1.0 / (double)B;
+    return total * scale;
+}
+
+/* Reverse-mode gradient.  grad_params (may be NULL) receives d/d(parameters)
+ * in the packed per-layer order (W then b); grad_actions (may be NULL,
+ * continuous actions only) receives d/dA in the layout of a_cont. */
+int or_rollout_grad(const or_model* m, int B, int H, int particles, const double* S0, const int32_t* a_disc,
+                    const double* a_cont, const double* noise, uint64_t seed, int objective, const double* targets,
+                    double gamma, const double* goal, double* loss, double* grad_params, double* grad_actions)
+{
+    if (model_check(m) != OR_OK || B < 1 || H < 0 || particles < 1) return OR_ERR_ARG;
+    if (objective != 0 && objective != 1) return OR_ERR_ARG;
+    if (objective == 0 && !targets) return OR_ERR_ARG;
+    if (m->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    if (grad_actions && m->n_actions > 0) return OR_ERR_ARG;
+    const int L = m->t_layers, d_s = m->d_s, aw = action_width(m);
+    const size_t P = mlp_param_count(L, m->t_dims);
+    int maxw = 0;
+    for (int l = 0; l <= L; ++l) if (m->t_dims[l] > maxw) maxw = m->t_dims[l];
+    const double scale = objective == 0 ? 1.0 / ((double)B * H) : 1.0 / (double)B;
+    const int n_seq = m->n_actions > 0 ? 0 : (B + particles - 1) / particles;
+    /* parameter gradients accumulate per chunk of OR_GRAD_CHUNK consecutive
+     * rollouts (sequentially inside a chunk); chunks are summed in order
+     * afterwards, so the result does not depend on the thread count */
+    const int n_chunks = (B + OR_GRAD_CHUNK - 1) / OR_GRAD_CHUNK;
+    double* gp = grad_params ? (double*)calloc((size_t)n_chunks * P, sizeof(double)) : NULL;
+    double* ga = grad_actions ? (double*)calloc((size_t)B * H * (aw > 0 ? aw : 1), sizeof(double)) : NULL;
+    double* lo = (double*)malloc(sizeof(double) * (size_t)B);
+    int rc = OR_OK;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int chunk = 0; chunk < n_chunks; ++chunk)
+    for (int b = chunk * OR_GRAD_CHUNK; b < B && b < (chunk + 1) * OR_GRAD_CHUNK; ++b) {
+        /* forward: store the layer inputs and pre-activations of every step */
+        double* acts = (double*)malloc(sizeof(double) * (size_t)(H > 0 ? H : 1) * (L + 1) * maxw);
+        double* pre = (double*)malloc(sizeof(double) * (size_t)(H > 0 ? H : 1) * L * maxw);
+        double* st = (double*)malloc(sizeof(double) * (size_t)(H + 1) * d_s);
+        double* dsc = (double*)malloc(sizeof(double) * (size_t)(H > 0 ? H : 1));
+        double w[OR_MAX_WIDTH];
+        for (int j = 0; j < d_s; ++j) st[j] = S0[(size_t)b * d_s + j];
+        double acc = 0.0, disc = 1.0;
+        for (int t = 0; t < H; ++t) {
+            int ad;
+            const double* ac;
+            grad_action(m, H, particles, a_disc, a_cont, b, t, &ad, &ac);
+            grad_noise(m, H, noise, seed, b, t, w);
+            double* x = acts + ((size_t)t * (L + 1)) * maxw;
+            for (int j = 0; j < d_s; ++j) x[j] = st[(size_t)t * d_s + j];
+            put_action(m, x + d_s, ad, ac);
+            for (int j = 0; j < m->d_w; ++j) x[d_s + aw + j] = w[j];
+            const double* p = m->t_params;
+            for (int l = 0; l < L; ++l) {
+                int n_in = m->t_dims[l], n_out = m->t_dims[l + 1];
+                const double* Wl = p;
+                const double* bl = p + (size_t)n_out * n_in;
+                const double* in = acts + ((size_t)t * (L + 1) + l) * maxw;
+                double* zz = pre + ((size_t)t * L + l) * maxw;
+                double* out = acts + ((size_t)t * (L + 1) + l + 1) * maxw;
+                for (int n = 0; n < n_out; ++n) {
+                    double z = 0.0;
+                    for (int k = 0; k < n_in; ++k) z += Wl[(size_t)n * n_in + k] * in[k];
+                    z += bl[n];
+                    zz[n] = z;
+                    out[n] = (l < L - 1) ? (z > 0.0 ? z : 0.0) : z;
+                }
+                p += (size_t)n_out * n_in + n_out;
+            }
+            const double* d = acts + ((size_t)t * (L + 1) + L) * maxw;
+            for (int j = 0; j < d_s; ++j) st[(size_t)(t + 1) * d_s + j] = st[(size_t)t * d_s + j] + d[j];
+            const double* s1 = st + (size_t)(t + 1) * d_s;
+            if (objective == 0) {
+                const double* T = targets + ((size_t)b * H + t) * d_s;
+                for (int j = 0; j < d_s; ++j) acc += (s1[j] - T[j]) * (s1[j] - T[j]);
+            } else {
+                dsc[t] = disc;
+                acc += disc * reward(d_s, s1, goal);
+                disc *= gamma;
+            }
+        }
+        lo[b] = acc;
+        /* reverse sweep: lam = dObjective/ds_{t+1} */
+        double lam[OR_MAX_WIDTH], g_out[OR_MAX_WIDTH], g_in[OR_MAX_WIDTH];
+        for (int j = 0; j < d_s; ++j) lam[j] = 0.0;
+        for (int t = H - 1; t >= 0; --t) {
+            const double* s1 = st + (size_t)(t + 1) * d_s;
+            if (objective == 0) {
+                const double* T = targets + ((size_t)b * H + t) * d_s;
+                for (int j = 0; j < d_s; ++j) lam[j] += 2.0 * (s1[j] - T[j]) * scale;
+            } else {
+                for (int j = 0; j < d_s; ++j) lam[j] += dsc[t] * (-2.0 * (s1[j] - goal[j])) * scale;
+            }
+            /* back through the layers of step t; d(out of last layer) = lam */
+            for (int j = 0; j < d_s; ++j) g_out[j] = lam[j];
+            size_t off_end = P;
+            for (int l = L - 1; l >= 0; --l) {
+                int n_in = m->t_dims[l], n_out = m->t_dims[l + 1];
+                size_t off = off_end - ((size_t)n_out * n_in + n_out);
+                const double* Wl = m->t_params + off;
+                const double* in = acts + ((size_t)t * (L + 1) + l) * maxw;
+                const double* zz = pre + ((size_t)t * L + l) * maxw;
+                if (l < L - 1)
+                    for (int n = 0; n < n_out; ++n) if (!(zz[n] > 0.0)) g_out[n] = 0.0;
+                if (gp) {
+                    double* G = gp + (size_t)chunk * P + off;
+                    for (int n = 0; n < n_out; ++n) {
+                        for (int k = 0; k < n_in; ++k) G[(size_t)n * n_in + k] += g_out[n] * in[k];
+                        G[(size_t)n_out * n_in + n] += g_out[n];
+                    }
+                }
+                for (int k = 0; k < n_in; ++k) {
+                    double a = 0.0;
+                    for (int n = 0; n < n_out; ++n) a += Wl[(size_t)n * n_in + k] * g_out[n];
+                    g_in[k] = a;
+                }
+                for (int k = 0; k < n_in; ++k) g_out[k] = g_in[k];
+                off_end = off;
+            }
+            /* g_out now holds d/dx_t: state part adds to lam, action part to dA */
+            if (ga)
+                for (int j = 0; j < aw; ++j) ga[((size_t)b * H + t) * aw + j] = g_out[d_s + j];
+            for (int j = 0; j < d_s; ++j) lam[j] += g_out[j];
+        }
+        free(acts);
+        free(pre);
+        free(st);
+        free(dsc);
+    }
+    if (loss) {
+        double tot = weighted_sum(B, lo, NULL, 1) * (double)B;
+        *loss = tot * scale;
+    }
+    if (gp) {
+        for (size_t q = 0; q < P; ++q) {
+            double sum = 0.0, comp = 0.0;
+            for (int c = 0; c < n_chunks; ++c) {
+                double term = gp[(size_t)c * P + q];
+                double tt = sum + term;
+                if (fabs(sum) >= fabs(term)) comp += (sum - tt) + term; else comp += (term - tt) + sum;
+                sum = tt;
+            }
+            grad_params[q] = sum + comp;
+        }
+    }
+    if (ga) {
+        for (int k = 0; k < n_seq; ++k)
+            for (int t = 0; t < H; ++t)
+                for (int j = 0; j < aw; ++j) {
+                    double sum = 0.0;
+                    for (int b = k * particles; b < (k + 1) * particles && b < B; ++b)
+                        sum += ga[((size_t)b * H + t) * aw + j];
+                    grad_actions[((size_t)k * H + t) * aw + j] = sum;
+                }
+    }
+    free(gp);
+    free(ga);
+    free(lo);
+    return rc;
+}
+
+/* Normals of n consecutive first counter words c0 = 0..n-1 (rows of out[n][d]). */
+void or_normals_rows(uint64_t seed, int n, uint32_t c1, uint32_t c2, uint32_t stream, int d, double* out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < n; ++r) or_normals(seed, (uint32_t)r, c1, c2, stream, d, out + (size_t)r * d);
+}

@@ -72,6 +72,17 @@ class _BatchItem(ctypes.Structure):
                 ("d_w_out", c_void_p), ("d_stats_out", c_void_p)]
 
 
+class _GradOpts(ctypes.Structure):
+    _fields_ = [("B", c_int32), ("H", c_int32), ("checkpoint", c_int32), ("d_s0", c_void_p),
+                ("d_actions", c_void_p), ("particles", c_int32), ("d_noise", c_void_p), ("seed", c_uint64),
+                ("objective", c_int32), ("d_targets", c_void_p), ("gamma", c_double), ("h_goal", POINTER(c_float)),
+                ("d_loss_out", c_void_p), ("d_grad_params", c_void_p), ("d_grad_actions", c_void_p)]
+
+
+VOILA_OBJ_DISTILL = 0
+VOILA_OBJ_RETURN = 1
+
+
 class _BatchTuning(ctypes.Structure):
     _fields_ = [("waves_per_block", c_int32), ("blocks_per_cu", c_int32), ("dynamic", c_int32)]
 
@@ -128,6 +139,12 @@ def _load():
     L.voila_batch_capture.restype = c_int32
     L.voila_batch_replay.argtypes = [vp, vp]
     L.voila_batch_replay.restype = c_int32
+    L.voila_grad_param_count.argtypes = [vp]
+    L.voila_grad_param_count.restype = c_int32
+    L.voila_rollout_grad_workspace_size.argtypes = [vp, POINTER(_GradOpts)]
+    L.voila_rollout_grad_workspace_size.restype = c_size_t
+    L.voila_rollout_grad.argtypes = [vp, POINTER(_GradOpts), vp, c_size_t, vp]
+    L.voila_rollout_grad.restype = c_int32
     return L
 
 
@@ -139,7 +156,8 @@ EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_m
             "voila_update", "voila_update_max_particles", "voila_normalize", "voila_resample_bits",
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
-            "voila_batch_replay"]
+            "voila_batch_replay", "voila_grad_param_count", "voila_rollout_grad_workspace_size",
+            "voila_rollout_grad"]
 
 
 def _check(st):
@@ -459,3 +477,50 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def grad_param_count(model: Model) -> int:
+    return lib.voila_grad_param_count(model.handle)
+
+
+def unflatten_params(model: Model, flat):
+    """[(dW [out, in], db [out]), ...] views of a flat parameter vector."""
+    dims = [int(model.desc.trans[0][0].shape[1])] + [int(W.shape[0]) for W, _ in model.desc.trans]
+    out, off = [], 0
+    for n_in, n_out in zip(dims[:-1], dims[1:]):
+        W = flat[off:off + n_out * n_in].reshape(n_out, n_in)
+        off += n_out * n_in
+        out.append((W, flat[off:off + n_out]))
+        off += n_out
+    return out
+
+
+def rollout_grad(model: Model, s0, actions, H, objective, targets=None, gamma=1.0, goal=None, particles=1,
+                 noise=None, seed=0, checkpoint=5, want_params=True, want_actions=False, workspace=None,
+                 stream=None):
+    """(objective [1], d/dparams [P] or None, d/dA (like actions) or None) through H-step rollouts."""
+    d = model.desc
+    B = int(s0.shape[0])
+    _dev(s0, torch.float32, (B, d.d_s), "s0")
+    if d.n_actions > 0:
+        _dev(actions, torch.int32, (B, H), "actions")
+    else:
+        _dev(actions, torch.float32, (B // max(particles, 1), H, d.d_a), "actions")
+    if targets is not None:
+        _dev(targets, torch.float32, (B, H, d.d_s), "targets")
+    if noise is not None:
+        _dev(noise, torch.float32, (B, H, d.d_w), "noise")
+    dev = s0.device
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    gp = torch.empty(grad_param_count(model), dtype=torch.float32, device=dev) if want_params else None
+    ga = torch.empty_like(actions) if want_actions else None
+    goal_arr = (c_float * d.d_s)(*[float(x) for x in (goal if goal is not None else [0.0] * d.d_s)])
+    o = _GradOpts(B, int(H), int(checkpoint), _ptr(s0), _ptr(actions), int(particles), _ptr(noise),
+                  int(seed) & (2**64 - 1), int(objective), _ptr(targets), float(gamma), goal_arr, _ptr(loss),
+                  _ptr(gp), _ptr(ga))
+    n = lib.voila_rollout_grad_workspace_size(model.handle, ctypes.byref(o))
+    if n == 0:
+        _check(lib.voila_rollout_grad(model.handle, ctypes.byref(o), None, 0, _stream(stream)))
+    ws = workspace if workspace is not None else torch.empty(n, dtype=torch.uint8, device=dev)
+    _check(lib.voila_rollout_grad(model.handle, ctypes.byref(o), _ptr(ws), ws.numel(), _stream(stream)))
+    return loss, gp, ga

@@ -173,6 +173,40 @@ std::vector<float> fold_columns(const HostNet& n, int c0, int nf, int dt) {
     return out;
 }
 
+// Transposed weights of a two-hidden-layer network for the adjoint kernel, as
+// f32 MFMA fragments [T3: ceil(d_out/2) x HT][T2: 16 HT x HT][T1: 16 HT]:
+// T3 maps the output-layer adjoint (output feature 2 c + g in k-step c) to
+// the second hidden layer, T2 the second hidden layer to the first (k-step c
+// = feature 32 (c / 16) + out_row(c % 16, g)), T1 the first hidden layer to
+// the input (row r of the tile = input feature row_feature(r)).
+std::vector<char> pack_bwd(const HostNet& n, NetBlob& nb) {
+    const int W = n.width(), HT = W / 32, d_out = n.out(), d_in = n.dims[0];
+    const int KS3 = (d_out + 1) / 2;
+    const size_t nfr = (size_t)KS3 * HT + (size_t)16 * HT * HT + 16 * HT;
+    std::vector<char> blob(align_up(nfr * 256, 1024), 0);
+    float* f = reinterpret_cast<float*>(blob.data());
+    auto hidden_in = [](int ri, int g) { return 32 * (ri / 16) + out_row(ri % 16, g); };
+    size_t fr = 0;
+    for (int c = 0; c < KS3; ++c)
+        for (int mt = 0; mt < HT; ++mt, ++fr)
+            for (int lane = 0; lane < 64; ++lane) {
+                int o = 2 * c + lane / 32;
+                f[fr * 64 + lane] = o < d_out ? n.w(2, o, 32 * mt + lane % 32) : 0.0f;
+            }
+    for (int c = 0; c < 16 * HT; ++c)
+        for (int mt = 0; mt < HT; ++mt, ++fr)
+            for (int lane = 0; lane < 64; ++lane)
+                f[fr * 64 + lane] = n.w(1, hidden_in(c, lane / 32), 32 * mt + lane % 32);
+    for (int c = 0; c < 16 * HT; ++c, ++fr)
+        for (int lane = 0; lane < 64; ++lane) {
+            int fin = row_feature(lane % 32);
+            f[fr * 64 + lane] = fin < d_in ? n.w(0, hidden_in(c, lane / 32), fin) : 0.0f;
+        }
+    nb = NetBlob{};
+    nb.bytes = (uint32_t)blob.size();
+    return blob;
+}
+
 struct DeviceGuard {
     int prev = -1;
     bool ok = true;
@@ -202,8 +236,18 @@ struct voila_model_s {
     const float* fold_b_lik = nullptr;
     int nf_trans = 0, nf_obs = 0, nf_lik = 0;
     int plan_bpc = 1, prop_bpc = 1, obs_bpc = 1;
+    bool has_grad = false;
+    NetBlob grad_fwd{}, grad_bwd{};
+    int grad_bpc = 1, n_params = 0;
     int action_width() const { return n_actions > 0 ? n_actions : d_a; }
 };
+
+namespace {
+constexpr int kGradWaves = 4;
+size_t grad_lds_bytes(const voila_model_s* m) {
+    return (size_t)m->grad_fwd.bytes + m->grad_bwd.bytes + (size_t)kGradWaves * 32 * 129 * sizeof(float);
+}
+}  // namespace
 
 extern "C" {
 
@@ -335,6 +379,17 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     } else {
         blobs.emplace_back();
     }
+    // adjoint packs (binary32 models of the shapes the adjoint kernel supports)
+    m->has_grad = grad_supported(shape) && dt == DT_F32;
+    if (m->has_grad) {
+        SlotMap mg{m->d_s, aw, m->d_w, m->d_s, m->d_s + aw};
+        blobs.push_back(pack_net(T, dt, in_slots(DT_F32, m->d_s, aw, m->d_w), mg, b0_plain_T, 1, m->grad_fwd));
+        blobs.push_back(pack_bwd(T, m->grad_bwd));
+        for (int l = 0; l < T.n_layers; ++l) m->n_params += T.dims[l + 1] * T.dims[l] + T.dims[l + 1];
+    } else {
+        blobs.emplace_back();
+        blobs.emplace_back();
+    }
     std::vector<std::vector<float>> folds;
     m->nf_trans = aw;
     folds.push_back(fold_columns(T, m->d_s, aw, dt));
@@ -383,18 +438,21 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->trans_upd.base = m->mem + offs[1];
     m->obs.base = m->mem + offs[2];
     m->lik.base = m->mem + offs[3];
-    m->fold_w_trans = reinterpret_cast<const float*>(m->mem + offs[4]);
-    m->fold_b_trans = reinterpret_cast<const float*>(m->mem + offs[5]);
-    m->fold_w_obs = reinterpret_cast<const float*>(m->mem + offs[6]);
-    m->fold_b_obs = reinterpret_cast<const float*>(m->mem + offs[7]);
-    m->fold_w_lik = reinterpret_cast<const float*>(m->mem + offs[8]);
-    m->fold_b_lik = reinterpret_cast<const float*>(m->mem + offs[9]);
+    m->grad_fwd.base = m->mem + offs[4];
+    m->grad_bwd.base = m->mem + offs[5];
+    m->fold_w_trans = reinterpret_cast<const float*>(m->mem + offs[6]);
+    m->fold_b_trans = reinterpret_cast<const float*>(m->mem + offs[7]);
+    m->fold_w_obs = reinterpret_cast<const float*>(m->mem + offs[8]);
+    m->fold_b_obs = reinterpret_cast<const float*>(m->mem + offs[9]);
+    m->fold_w_lik = reinterpret_cast<const float*>(m->mem + offs[10]);
+    m->fold_b_lik = reinterpret_cast<const float*>(m->mem + offs[11]);
 
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->cus = prop.multiProcessorCount;
     m->plan_bpc = plan_blocks_per_cu(shape, dt);
     m->prop_bpc = propose_blocks_per_cu(shape, dt);
     m->obs_bpc = observe_blocks_per_cu(shape, dt);
+    if (m->has_grad) m->grad_bpc = grad_blocks_per_cu(shape, grad_lds_bytes(m));
     *out = m;
     return VOILA_OK;
 }
@@ -1039,6 +1097,130 @@ voila_status_t voila_batch_replay(voila_batch_t b, void* stream) {
     DeviceGuard guard(b->device);
     if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
     VOILA_CHECK_HIP(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+    return VOILA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// gradients through rollouts
+// ---------------------------------------------------------------------------
+namespace {
+struct GradWs {
+    float* ckpt;
+    float* segst;
+    float* wpart;
+    float* lpart;
+    float* apart;
+    size_t bytes;
+    int blocks;
+};
+GradWs carve_grad(const voila_model_s* m, const voila_grad_opts_t* o, char* base) {
+    GradWs w{};
+    const int n_tiles = (o->B + 31) / 32;
+    const int C = o->checkpoint, NC = (o->H + C - 1) / C;
+    const int want = (n_tiles + kGradWaves - 1) / kGradWaves;
+    const int cap = m->cus * m->grad_bpc;
+    w.blocks = std::max(1, std::min(want, cap));
+    const int n_waves = w.blocks * kGradWaves;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off = align_up(off + bytes, 256);
+        return reinterpret_cast<float*>(p);
+    };
+    w.ckpt = take((size_t)o->B * std::max(NC, 1) * m->d_s * 4);
+    w.segst = take((size_t)o->B * (C + 1) * m->d_s * 4);
+    w.wpart = take((size_t)n_waves * m->n_params * 4);
+    w.lpart = take((size_t)n_waves * 4);
+    w.apart = take((size_t)n_tiles * std::max(o->H, 1) * std::max(m->d_a, 1) * 4);
+    w.bytes = off;
+    return w;
+}
+voila_status_t grad_check(const voila_model_s* m, const voila_grad_opts_t* o) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!o) return fail(VOILA_ERR_INVALID_ARG, "NULL options");
+    if (!m->has_grad) return fail(VOILA_ERR_UNSUPPORTED, "gradients need a binary32 model with two hidden layers of 64");
+    if (o->B < 1 || o->H < 0 || o->H > 64 || o->checkpoint < 1)
+        return fail(VOILA_ERR_INVALID_ARG, "B >= 1, 0 <= H <= 64, checkpoint >= 1");
+    if (o->objective != VOILA_OBJ_DISTILL && o->objective != VOILA_OBJ_RETURN)
+        return fail(VOILA_ERR_INVALID_ARG, "unknown objective");
+    if (!o->d_s0 || (o->H > 0 && !o->d_actions)) return fail(VOILA_ERR_INVALID_ARG, "NULL states or actions");
+    if (o->objective == VOILA_OBJ_DISTILL && o->H > 0 && !o->d_targets)
+        return fail(VOILA_ERR_INVALID_ARG, "the distillation objective needs teacher states");
+    if (o->objective == VOILA_OBJ_RETURN && (!o->h_goal || !(o->gamma >= 0.0 && o->gamma <= 1.0)))
+        return fail(VOILA_ERR_INVALID_ARG, "the return objective needs a goal and gamma in [0, 1]");
+    if (m->n_actions == 0 && (o->particles < 1 || o->B % o->particles != 0))
+        return fail(VOILA_ERR_INVALID_ARG, "particles must divide B");
+    if (o->d_grad_actions && (m->n_actions > 0 || o->particles % 32 != 0))
+        return fail(VOILA_ERR_INVALID_ARG, "action gradients need continuous actions and particles % 32 == 0");
+    return VOILA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int32_t voila_grad_param_count(voila_model_t m) { return m && m->has_grad ? m->n_params : 0; }
+
+size_t voila_rollout_grad_workspace_size(voila_model_t m, const voila_grad_opts_t* o) {
+    if (grad_check(m, o) != VOILA_OK) return 0;
+    return carve_grad(m, o, nullptr).bytes;
+}
+
+voila_status_t voila_rollout_grad(voila_model_t m, const voila_grad_opts_t* o, void* ws, size_t ws_bytes,
+                                  void* stream) {
+    voila_status_t st = grad_check(m, o);
+    if (st != VOILA_OK) return st;
+    GradWs w = carve_grad(m, o, reinterpret_cast<char*>(ws));
+    if (!ws || ws_bytes < w.bytes) return fail(VOILA_ERR_WORKSPACE, "gradient workspace too small");
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    GradParams p{};
+    p.fwd = m->grad_fwd;
+    p.bwd = m->grad_bwd;
+    p.s0 = o->d_s0;
+    p.actions = o->d_actions;
+    p.noise = o->d_noise;
+    p.targets = o->d_targets;
+    p.ckpt = w.ckpt;
+    p.segst = w.segst;
+    p.wpart = w.wpart;
+    p.lpart = w.lpart;
+    p.apart = o->d_grad_actions ? w.apart : nullptr;
+    p.B = o->B;
+    p.H = o->H;
+    p.C = o->checkpoint;
+    p.NC = (o->H + o->checkpoint - 1) / o->checkpoint;
+    p.particles = m->n_actions > 0 ? 1 : o->particles;
+    p.objective = o->objective;
+    p.want_params = o->d_grad_params ? 1 : 0;
+    p.n_params = m->n_params;
+    p.scale = o->objective == VOILA_OBJ_DISTILL ? 1.0 / ((double)o->B * std::max(o->H, 1)) : 1.0 / (double)o->B;
+    p.key0 = (uint32_t)(o->seed & 0xffffffffu);
+    p.key1 = (uint32_t)(o->seed >> 32);
+    for (int j = 0; j < 32; ++j) p.goal[j] = (o->h_goal && j < m->d_s) ? o->h_goal[j] : 0.0f;
+    double d = 1.0;
+    for (int t = 0; t < 64; ++t) {
+        p.disc[t] = (float)d;
+        d *= o->gamma;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    VOILA_CHECK_HIP(launch_grad(m->shape, p, w.blocks, grad_lds_bytes(m), s));
+    GradReduceParams r{};
+    r.wpart = w.wpart;
+    r.lpart = w.lpart;
+    r.apart = p.apart;
+    r.grad_params = o->d_grad_params;
+    r.grad_actions = o->d_grad_actions;
+    r.loss = o->d_loss_out;
+    r.n_params = o->d_grad_params ? m->n_params : 0;
+    r.n_waves = w.blocks * kGradWaves;
+    r.H = o->H;
+    r.d_a = m->d_a;
+    r.tiles_per_seq = m->n_actions > 0 ? 1 : o->particles / 32;
+    r.n_action_values = o->d_grad_actions ? (o->B / o->particles) * o->H * m->d_a : 0;
+    r.scale = p.scale;
+    VOILA_CHECK_HIP(launch_grad_reduce(r, s));
     return VOILA_OK;
 }
 

@@ -339,6 +339,13 @@ __device__ __forceinline__ void noise_slots_philox(float (&out)[NS], uint32_t ke
 // Noise feature held by slot s of group g.
 __host__ __device__ constexpr int noise_feature(int s, int g) { return 4 * (s / 2) + 2 * g + (s % 2); }
 
+// Copies a packed network blob into LDS (bytes is a multiple of 16).
+__device__ __forceinline__ void stage_blob(char* dst, const char* src, uint32_t bytes) {
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    uint4* d = reinterpret_cast<uint4*>(dst);
+    for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
 // Wave-wide reductions across the 32 columns of one lane group (fixed order).
 __device__ __forceinline__ float sum32(float v) {
     v += __shfl_xor(v, 16);

@@ -40,12 +40,6 @@ __device__ __forceinline__ float reward_of(const float* st, const float* goal, i
     return -(part + __shfl_xor(part, 32));
 }
 
-// Copies a packed network blob into LDS (bytes is a multiple of 16).
-__device__ __forceinline__ void stage_blob(char* dst, const char* src, uint32_t bytes) {
-    const uint4* s = reinterpret_cast<const uint4*>(src);
-    uint4* d = reinterpret_cast<uint4*>(dst);
-    for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
-}
 
 }  // namespace
 

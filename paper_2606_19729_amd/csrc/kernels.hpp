@@ -10,11 +10,12 @@ namespace voila {
 
 // Network shapes with compiled kernels: X(id, d_s, n_actions, d_a, d_w, d_o, d_wz, width, n_hidden)
 // (n_actions > 0: discrete one-hot actions; d_a > 0: continuous actions).
-#define VOILA_SHAPES(X)                          \
-    X(0, 4, 5, 0, 4, 2, 2, 64, 2)     /* small */ \
-    X(1, 16, 0, 4, 16, 32, 32, 256, 3) /* realistic */
+#define VOILA_SHAPES(X)                                 \
+    X(0, 4, 5, 0, 4, 2, 2, 64, 2)     /* small */        \
+    X(1, 16, 0, 4, 16, 32, 32, 256, 3) /* realistic */    \
+    X(2, 4, 0, 4, 4, 2, 2, 64, 2)      /* small, continuous actions */
 
-constexpr int kNumShapes = 2;
+constexpr int kNumShapes = 3;
 
 struct ShapeInfo {
     int d_s, n_actions, d_a, d_w, d_o, d_wz, width, n_hidden;
@@ -130,6 +131,36 @@ struct FoldBatchItem {
     int width, nf, n_actions, d_a, d_o, bf16, with_obs, inst;
 };
 
+// Adjoint rollouts (two hidden layers of width 64, binary32).
+struct GradParams {
+    NetBlob fwd, bwd;          // forward pack (actions as inputs) and transposed pack
+    const float* s0;           // [B][d_s]
+    const void* actions;       // int32 [B][H] or float [B / particles][H][d_a]
+    const float* noise;        // [B][H][d_w] or NULL
+    const float* targets;      // [B][H][d_s] (distillation)
+    float* ckpt;               // [B][NC][d_s] checkpoints
+    float* segst;              // [B][C + 1][d_s] states of the segment being reversed
+    float* wpart;              // [waves][n_params] parameter-gradient partials
+    float* lpart;              // [waves] objective partials
+    float* apart;              // [tiles][H][d_a] action-gradient partials or NULL
+    int B, H, C, NC, particles, objective, want_params, n_params;
+    double scale;
+    uint32_t key0, key1;
+    float goal[32];
+    float disc[64];            // gamma^t
+};
+
+struct GradReduceParams {
+    const float* wpart;
+    const float* lpart;
+    const float* apart;
+    float* grad_params;
+    float* grad_actions;
+    float* loss;
+    int n_params, n_waves, n_action_values, H, d_a, tiles_per_seq;
+    double scale;
+};
+
 struct PhiloxParams {
     float* out;
     uint32_t* words;
@@ -159,6 +190,10 @@ hipError_t launch_norm_res_batch(const NormResParams* d_ps, int n_inst, const ui
                                  hipStream_t s);
 hipError_t launch_reset_counter(int* d_counter, hipStream_t s);
 int plan_batch_blocks_per_cu(int shape, int dt, int waves_per_block, size_t lds);
+bool grad_supported(int shape);
+hipError_t launch_grad(int shape, const GradParams& p, int blocks, size_t lds, hipStream_t s);
+hipError_t launch_grad_reduce(const GradReduceParams& p, hipStream_t s);
+int grad_blocks_per_cu(int shape, size_t lds);
 int propose_batch_blocks_per_cu(int shape, int dt, int waves_per_block, size_t lds);
 
 // Resident blocks per CU of the plan / propose / observe kernels.

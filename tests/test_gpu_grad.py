@@ -1,0 +1,217 @@
+"""Adjoint rollout kernel (checkpointed reverse sweep) against the FP64 oracle.
+
+* 64-rollout subsets: the device gradient against binary64 central finite
+  differences of the oracle's objective (h = 1e-6, coordinates straddling a
+  ReLU kink excluded) and against the oracle's reverse-mode gradient.
+* Full size (65,536 rollouts x 20 steps, checkpoint every 5): distillation
+  gradient w.r.t. the 5,316 parameters against the oracle's adjoint, and the
+  return gradient w.r.t. [1024, 20, 4] action sequences on sampled sequences
+  (each sequence's gradient depends only on its own 64 particles).
+* The checkpoint interval does not change the result (recomputed states are
+  bit-identical), and repeated runs are bit-identical.
+
+Tolerance: binary32 device arithmetic against binary64; a gradient entry is
+a sum over rollouts and steps, so errors are bounded relative to the largest
+gradient entry: max |g_dev - g_ref| <= 1e-4 * max |g_ref|.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_19729_amd as lib
+    return lib
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def flat_layers(layers):
+    return np.concatenate([np.concatenate([np.asarray(W, np.float64).ravel(), np.asarray(b, np.float64)])
+                           for W, b in layers])
+
+
+def distill_inputs(B, H, seed=5, noise_seed=77):
+    """Student network, initial states, random discrete actions and the states
+    of a teacher network (another seed) driven by the same initial states,
+    actions and noise (Philox key noise_seed)."""
+    w = workloads.small(seed=seed)
+    rng = np.random.default_rng(seed)
+    S0 = rng.standard_normal((B, 4)).astype(np.float32)
+    A = rng.integers(0, 5, (B, H)).astype(np.int32)
+    teacher = workloads.small(seed=seed + 1).model
+    T = oracle.teacher_targets(teacher, S0, A, H, seed=noise_seed).astype(np.float32)
+    return w.model, S0, A, T
+
+
+def cont_model(seed=7):
+    rng = np.random.default_rng(seed)
+    return workloads.make_model(rng, d_s=4, n_actions=0, d_a=4, d_w=4, d_o=2, d_wz=2, width=64, n_hidden=2)
+
+
+def rel(got, ref):
+    return float(np.max(np.abs(np.asarray(got, np.float64) - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+
+def _with_params(model, flat):
+    layers, off = [], 0
+    for W, b in model.trans:
+        n = W.size
+        layers.append((flat[off:off + n].reshape(W.shape), flat[off + n:off + n + b.size]))
+        off += n + b.size
+    return workloads.Model(**{**model.__dict__, "trans": layers})
+
+
+def test_distillation_gradient_subset_vs_fd_and_oracle(V):
+    m, S0, A, T = distill_inputs(64, 20)
+    vm = V.Model(m)
+    print("grad case: distillation, B=64, H=20", flush=True)
+    loss, gp, _ = V.rollout_grad(vm, dev(S0), dev(A, torch.int32), 20, V.VOILA_OBJ_DISTILL, targets=dev(T), seed=77)
+    torch.cuda.synchronize()
+    gp = gp.cpu().numpy().astype(np.float64)
+    l_ref, g_ref, _ = oracle.rollout_grad(m, S0, A, 20, oracle.DISTILL, targets=T, seed=77)
+    g_ref = flat_layers(g_ref)
+    e_adj = rel(gp, g_ref)
+    assert abs(loss.item() - l_ref) <= 1e-5 * abs(l_ref)
+    # finite differences on a sample of coordinates
+    flat0 = flat_layers(m.trans)
+    worst, n = 0.0, 0
+    for q in np.random.default_rng(1).choice(flat0.size, 60, replace=False):
+        vals, pats = [], []
+        for sgn in (+1, -1):
+            f = flat0.copy()
+            f[q] += sgn * 1e-6
+            v, pat = oracle.rollout_objective(_with_params(m, f), S0, A, 20, oracle.DISTILL, targets=T, seed=77,
+                                              patterns=True)
+            vals.append(v)
+            pats.append(pat)
+        if np.array_equal(pats[0], pats[1]):
+            worst = max(worst, abs((vals[0] - vals[1]) / 2e-6 - gp[q]))
+            n += 1
+    e_fd = worst / np.max(np.abs(g_ref))
+    print(f"  vs oracle adjoint {e_adj:.2e}; vs FD ({n} coords) {e_fd:.2e}", flush=True)
+    assert e_adj <= TOL and e_fd <= TOL and n >= 50
+
+
+def test_return_action_gradient_subset_vs_fd(V):
+    m = cont_model()
+    rng = np.random.default_rng(1)
+    P, H = 64, 20
+    S0 = rng.standard_normal((P, 4)).astype(np.float32)
+    A = rng.uniform(-1, 1, (1, H, 4)).astype(np.float32)
+    goal = np.array([1.0, 1.0, 0.0, 0.0], np.float32)
+    vm = V.Model(m)
+    print("grad case: return, 1 sequence x 64 particles, H=20", flush=True)
+    J, gp, gA = V.rollout_grad(vm, dev(S0), dev(A), H, V.VOILA_OBJ_RETURN, gamma=0.95, goal=goal, particles=P,
+                               seed=9, want_actions=True)
+    torch.cuda.synchronize()
+    gA = gA.cpu().numpy().astype(np.float64)
+    J_ref, gp_ref, gA_ref = oracle.rollout_grad(m, S0, A, H, oracle.RETURN, gamma=0.95, goal=goal, particles=P,
+                                                seed=9, want_actions=True)
+    assert abs(J.item() - J_ref) <= 1e-5 * abs(J_ref)
+    fd = np.zeros_like(gA_ref)
+    mask = np.ones(A.shape, bool)
+    for idx in np.ndindex(A.shape):
+        vals, pats = [], []
+        for sgn in (+1, -1):
+            Ap = A.astype(np.float64)
+            Ap[idx] += sgn * 1e-6
+            v, pat = oracle.rollout_objective(m, S0, Ap, H, oracle.RETURN, gamma=0.95, goal=goal, particles=P,
+                                              seed=9, patterns=True)
+            vals.append(v)
+            pats.append(pat)
+        fd[idx] = (vals[0] - vals[1]) / 2e-6
+        mask[idx] = np.array_equal(pats[0], pats[1])
+    e_fd = float(np.max(np.abs(gA - fd)[mask]) / np.max(np.abs(fd)))
+    e_adj = rel(gA, gA_ref)
+    e_p = rel(gp.cpu().numpy(), flat_layers(gp_ref))
+    print(f"  dA vs FD {e_fd:.2e} ({(~mask).sum()} kinks), vs oracle {e_adj:.2e}; dparams vs oracle {e_p:.2e}",
+          flush=True)
+    assert e_fd <= TOL and e_adj <= TOL and e_p <= TOL
+
+
+def test_checkpoint_interval_and_repeat_do_not_change_results(V):
+    m, S0, A, T = distill_inputs(200, 13, seed=8, noise_seed=3)
+    vm = V.Model(m)
+    outs = []
+    for ck in [1, 5, 7, 13, 20]:
+        loss, gp, _ = V.rollout_grad(vm, dev(S0), dev(A, torch.int32), 13, V.VOILA_OBJ_DISTILL, targets=dev(T),
+                                     seed=3, checkpoint=ck)
+        outs.append((loss.clone(), gp.clone()))
+    loss, gp, _ = V.rollout_grad(vm, dev(S0), dev(A, torch.int32), 13, V.VOILA_OBJ_DISTILL, targets=dev(T),
+                                 seed=3, checkpoint=5)
+    torch.cuda.synchronize()
+    for lo, g in outs:
+        assert torch.equal(lo, outs[0][0]) and torch.equal(g, outs[0][1])
+    assert torch.equal(gp, outs[0][1])
+
+
+def test_full_size_distillation_and_return_gradients(V):
+    # distillation: 65,536 rollouts x 20 steps, checkpoint every 5
+    B, H = 65536, 20
+    m, S0, A, T = distill_inputs(B, H, seed=11, noise_seed=5)
+    vm = V.Model(m)
+    print("grad case: full-size distillation B=65536 H=20", flush=True)
+    loss, gp, _ = V.rollout_grad(vm, dev(S0), dev(A, torch.int32), H, V.VOILA_OBJ_DISTILL, targets=dev(T), seed=5)
+    torch.cuda.synchronize()
+    l_ref, g_ref, _ = oracle.rollout_grad(m, S0, A, H, oracle.DISTILL, targets=T, seed=5)
+    e = rel(gp.cpu().numpy(), flat_layers(g_ref))
+    print(f"  loss {loss.item():.6e} vs {l_ref:.6e}; gradient rel err {e:.2e}", flush=True)
+    assert abs(loss.item() - l_ref) <= 1e-5 * abs(l_ref) and e <= TOL
+    # return gradient w.r.t. [1024, 20, 4] actions, 64 particles per sequence
+    mc = cont_model(seed=12)
+    rng = np.random.default_rng(12)
+    K, P = 1024, 64
+    S0c = rng.standard_normal((K * P, 4)).astype(np.float32)
+    Ac = rng.uniform(-1, 1, (K, H, 4)).astype(np.float32)
+    goal = np.array([1.0, 1.0, 0.0, 0.0], np.float32)
+    vmc = V.Model(mc)
+    print("grad case: full-size return gradient [1024, 20, 4]", flush=True)
+    J, _, gA = V.rollout_grad(vmc, dev(S0c), dev(Ac), H, V.VOILA_OBJ_RETURN, gamma=0.99, goal=goal, particles=P,
+                              seed=13, want_params=False, want_actions=True)
+    torch.cuda.synchronize()
+    gA = gA.cpu().numpy().astype(np.float64)
+    for k in [0, 517, K - 1]:
+        sl = slice(k * P, (k + 1) * P)
+        # the sequence's own rollouts use Philox counters b = k*P + i: pass them as explicit noise
+        noise = np.stack([oracle.normals_rows(13, K * P, 0, t, 3, 4)[sl] for t in range(H)], axis=1)
+        _, _, ga_ref = oracle.rollout_grad(mc, S0c[sl], Ac[k:k + 1], H, oracle.RETURN, gamma=0.99, goal=goal,
+                                           particles=P, noise=noise, want_params=False, want_actions=True)
+        # the full objective is a mean over K*P rollouts: scale the subset's mean over P
+        ek = rel(gA[k], ga_ref[0] / K)
+        print(f"  sequence {k}: dA rel err {ek:.2e}", flush=True)
+        assert ek <= TOL
+
+
+def test_autograd_functions(V):
+    from paper_2606_19729_amd.autograd import DistillLoss, MeanReturn
+    mc = cont_model(seed=14)
+    rng = np.random.default_rng(14)
+    P, H = 64, 10
+    S0 = dev(rng.standard_normal((2 * P, 4)))
+    A = dev(rng.uniform(-1, 1, (2, H, 4))).requires_grad_(True)
+    vm = V.Model(mc)
+    J = MeanReturn.apply(A, vm, S0, H, 0.95, [1.0, 1.0, 0.0, 0.0], P, 21)
+    J.backward()
+    _, _, gA = V.rollout_grad(vm, S0, A.detach(), H, V.VOILA_OBJ_RETURN, gamma=0.95, goal=[1.0, 1.0, 0.0, 0.0],
+                              particles=P, seed=21, want_params=False, want_actions=True)
+    torch.cuda.synchronize()
+    assert torch.equal(A.grad, gA)
+    m, S0n, An, T = distill_inputs(64, 6, seed=15, noise_seed=31)
+    params = [torch.tensor(x, requires_grad=True) for W, b in m.trans for x in (W, b)]
+    L = DistillLoss.apply(*params, m, dev(S0n), dev(An, torch.int32), dev(T), 6, 31)
+    L.backward()
+    _, g_ref, _ = oracle.rollout_grad(m, S0n, An, 6, oracle.DISTILL, targets=T, seed=31)
+    got = np.concatenate([p.grad.numpy().ravel() for p in params])
+    assert rel(got, flat_layers(g_ref)) <= TOL
