@@ -51,6 +51,154 @@ def trans_flops_per_step(model):
     return 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
 
 
+def small_flops_per_step():
+    """2 * MACs of the small transition network, one-hot inputs excluded: (4 + 4) x 64 + 64 x 64 + 64 x 4."""
+    return 2 * ((4 + 4) * 64 + 64 * 64 + 64 * 4)
+
+
+def bench_batched(V, torch, reps):
+    """64 uneven small-network instances + their updates: bf16 persistent batch replayed
+    from a hipGraph vs the plain f32 form (one voila_plan / voila_update call each)."""
+    import workloads
+    works = workloads.batched()
+    dev = torch.device("cuda", 0)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    steps = sum(w.N * w.K * w.H for w in works)
+    parts = sum(w.N for w in works)
+    out = {"instances": len(works), "rollout_steps": steps, "particles": parts}
+    obs = torch.zeros((len(works), 2), dtype=torch.float32, device=dev)
+    acts = torch.tensor([w.update_action for w in works], dtype=torch.int32, device=dev)
+    us = torch.as_tensor(np.array([w.resample_u for w in works], np.uint32).view(np.int32), device=dev)
+    S = [torch.as_tensor(w.states, device=dev) for w in works]
+    C = [torch.as_tensor(w.cands, device=dev) for w in works]
+    for form in ["bf16", "f32"]:
+        models = [V.Model(w.model, compute=form) for w in works]
+        insts = [dict(model=m, states=s, cands=c, gamma=w.gamma, goal=w.goal, seed=w.plan_seed, lam=w.lam,
+                      update_seed=w.update_seed) for m, s, c, w in zip(models, S, C, works)]
+        if form == "bf16":
+            from paper_2606_19729_amd import autotune
+            tuned = autotune.tune(insts, run_args=dict(actions=acts, obs=obs, resample_u=us), reps=2)
+            b = V.Batch(insts, with_update=True, **tuned["schedule"])
+            b.capture(actions=acts, obs=obs, resample_u=us)
+            for what, key in [(V.VOILA_BATCH_PLAN | V.VOILA_BATCH_UPDATE, "plan+update")]:
+                b.replay()
+                torch.cuda.synchronize()
+                e0, e1 = ev(), ev()
+                e0.record()
+                for _ in range(reps):
+                    b.replay()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+            e0, e1 = ev(), ev()
+            b2 = V.Batch(insts, with_update=False, **tuned["schedule"])
+            b2.run(V.VOILA_BATCH_PLAN)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                b2.run(V.VOILA_BATCH_PLAN)
+            e1.record()
+            torch.cuda.synchronize()
+            plan_ms = e0.elapsed_time(e1) / reps
+            out["bf16_persistent_graph"] = {"ms": ms, "plan_ms": plan_ms, "rollout_steps_per_s": steps / (plan_ms / 1e3),
+                                            "step_rate_incl_updates": steps / (ms / 1e3),
+                                            "schedule": tuned["schedule"],
+                                            "mfma_frac_bf16_peak": small_flops_per_step() * steps / (plan_ms / 1e3) / 1e12
+                                            / PEAK_BF16_TFLOPS}
+            b.close()
+            b2.close()
+        else:
+            ws = [m.plan_workspace(w.N, w.K, w.H) for m, w in zip(models, works)]
+            q = [torch.empty(w.K, dtype=torch.float32, device=dev) for w in works]
+
+            def plain():
+                for m, s, c, w, wsp, qq in zip(models, S, C, works, ws, q):
+                    V.plan(m, s, c, w.gamma, w.goal, seed=w.plan_seed, q_out=qq, workspace=wsp)
+            plain()
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record()
+            for _ in range(reps):
+                plain()
+            e1.record()
+            torch.cuda.synchronize()
+            plan_ms = e0.elapsed_time(e1) / reps
+            out["f32_plain"] = {"plan_ms": plan_ms, "rollout_steps_per_s": steps / (plan_ms / 1e3),
+                                "mfma_frac_f32_peak": small_flops_per_step() * steps / (plan_ms / 1e3) / 1e12
+                                / PEAK_F32_TFLOPS}
+        for m in models:
+            m.close()
+    out["bf16_over_f32_rollout_rate"] = (out["bf16_persistent_graph"]["rollout_steps_per_s"]
+                                         / out["f32_plain"]["rollout_steps_per_s"])
+    return out
+
+
+def bench_grad(V, torch, reps):
+    """Adjoint through 65,536 rollouts x 20 steps (checkpoint every 5): distillation
+    gradient w.r.t. the 5,316 parameters; return gradient w.r.t. [1024, 20, 4] actions."""
+    import workloads
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(5)
+    B, H = 65536, 20
+    out = {"rollouts": B, "H": H, "checkpoint": 5}
+    w = workloads.small(seed=11)
+    m = V.Model(w.model)
+    S0 = torch.as_tensor(rng.standard_normal((B, 4)).astype(np.float32), device=dev)
+    A = torch.as_tensor(rng.integers(0, 5, (B, H)).astype(np.int32), device=dev)
+    T = torch.as_tensor(rng.standard_normal((B, H, 4)).astype(np.float32), device=dev)
+    mc = V.Model(workloads.make_model(rng, d_s=4, n_actions=0, d_a=4, d_w=4, d_o=2, d_wz=2, width=64, n_hidden=2))
+    Ac = torch.as_tensor(rng.uniform(-1, 1, (1024, H, 4)).astype(np.float32), device=dev)
+    for key, fn in [("distill_params", lambda: V.rollout_grad(m, S0, A, H, V.VOILA_OBJ_DISTILL, targets=T, seed=3)),
+                    ("return_actions", lambda: V.rollout_grad(mc, S0, Ac, H, V.VOILA_OBJ_RETURN, gamma=0.99,
+                                                              goal=[1, 1, 0, 0], particles=64, seed=3,
+                                                              want_params=False, want_actions=True))]:
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[key] = {"ms": ms, "rollout_steps_per_s": B * H / (ms / 1e3)}
+    return out
+
+
+def bench_update_sweep(V, torch, reps):
+    """Belief-update HBM sweep: normalise given binary32 log-likelihoods, resample and
+    gather 16-float particles; 136 algorithmic bytes per particle (4 B likelihood + 64 B
+    particle read + 64 B particle written + 4 B index)."""
+    dev = torch.device("cuda", 0)
+    out = []
+    for lg in (16, 20, 24):
+        N = 1 << lg
+        rng = np.random.default_rng(lg)
+        ll = torch.as_tensor(rng.standard_normal(N).astype(np.float32), device=dev)
+        src = torch.as_tensor(rng.standard_normal((N, 16)).astype(np.float32), device=dev)
+        ws = V.weights_workspace(N, dev)
+        w = torch.empty(N, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        idx = torch.empty(N, dtype=torch.int32, device=dev)
+
+        def once():
+            wv, _ = V.normalize(ll, 1.0, workspace=ws)
+            V.resample(wv, 12345, src=src, workspace=ws, dst=dst, idx=idx)
+        once()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            once()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = 136.0 * N / (ms / 1e3) / 1e9
+        out.append({"N": N, "ms": ms, "particles_per_s": N / (ms / 1e3), "algorithmic_GB_per_s": gbs,
+                    "hbm_frac": gbs / 8000.0})
+    return out
+
+
 def cpu_baseline(w, n_cands):
     """The FP64 oracle on a bounded sample: n_cands candidates x all particles x H,
     plus one full belief update; rate in rollout steps per second."""
@@ -80,6 +228,8 @@ def main():
     ap.add_argument("--cpu-cands", type=int, default=12, help="candidates in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, gradient and update-sweep measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -202,6 +352,14 @@ def main():
                           "max_rel_q_diff_vs_f32": float(np.max(np.abs(qbh - qf) / np.abs(qf))),
                           "roofline_frac_bf16_peak": flops / (bms / 1000.0) / 1e12 / PEAK_BF16_TFLOPS}
         print(f"[bench] bf16 plan {bms:.2f} ms", file=sys.stderr, flush=True)
+
+    if not args.no_extras:
+        print("[bench] batched instances (bf16 persistent graph vs f32 plain)", file=sys.stderr, flush=True)
+        result["batched"] = bench_batched(V, torch, max(2, args.steps // 2))
+        print("[bench] adjoint rollouts", file=sys.stderr, flush=True)
+        result["gradients"] = bench_grad(V, torch, max(2, args.steps))
+        print("[bench] belief-update sweep", file=sys.stderr, flush=True)
+        result["update_sweep"] = bench_update_sweep(V, torch, max(3, args.steps))
 
     if args.calibrate_copy:
         x = torch.ones(64 << 20, dtype=torch.float32, device=dev)

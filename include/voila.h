@@ -169,8 +169,13 @@ voila_status_t voila_update(voila_model_t model, const float* d_states, const do
                             double* d_w_out, float* d_loglik_out, float* d_prop_out, double* d_stats_out,
                             int32_t* d_status, void* stream);
 
-/* Largest N accepted by voila_update / voila_normalize / voila_resample. */
+/* Largest N accepted by voila_update / voila_normalize / voila_resample
+ * (beliefs above 8192 particles take a multi-workgroup path through HBM). */
 int32_t voila_update_max_particles(void);
+
+/* Bytes of device workspace voila_normalize / voila_resample need for N
+ * particles (0 up to 8192 particles, where one workgroup holds the belief). */
+size_t voila_weights_workspace_size(int32_t N);
 
 /* ---------------------------------------------------------------------------
  * Stages of update, exported on their own.
@@ -178,7 +183,8 @@ int32_t voila_update_max_particles(void);
 /* Weight normalisation of given log-likelihoods d_loglik [N] float:
  * w'_i and stats exactly as in voila_update.  d_prior_w [N] double or NULL. */
 voila_status_t voila_normalize(const float* d_loglik, const double* d_prior_w, int32_t N, double lambda,
-                               double* d_w_out, double* d_stats_out, int32_t* d_status, void* stream);
+                               double* d_w_out, double* d_stats_out, int32_t* d_status, void* d_workspace,
+                               size_t workspace_bytes, void* stream);
 
 /* Fraction bits b(N) = min(32, 52 - ceil(log2 N)) of the quantised weights. */
 int32_t voila_resample_bits(int32_t N);
@@ -193,7 +199,7 @@ int32_t voila_resample_bits(int32_t N);
  * floats.  Negative, non-finite or all-zero weights set d_status. */
 voila_status_t voila_resample(const double* d_w, int32_t N, uint32_t U, int32_t* d_idx_out,
                               const float* d_src, float* d_dst, int32_t row_floats, int32_t* d_status,
-                              void* stream);
+                              void* d_workspace, size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * observe: o_r = f_Z([s'_r, a, w_Z,r]) (Sec. 4.2, Eq. 5) for n rows sharing

@@ -116,11 +116,13 @@ def _load():
                                vp, vp, vp, vp, vp, vp, vp, vp]
     L.voila_update.restype = c_int32
     L.voila_update_max_particles.restype = c_int32
-    L.voila_normalize.argtypes = [vp, vp, c_int32, c_double, vp, vp, vp, vp]
+    L.voila_normalize.argtypes = [vp, vp, c_int32, c_double, vp, vp, vp, vp, c_size_t, vp]
     L.voila_normalize.restype = c_int32
     L.voila_resample_bits.argtypes = [c_int32]
     L.voila_resample_bits.restype = c_int32
-    L.voila_resample.argtypes = [vp, c_int32, c_uint32, vp, vp, vp, c_int32, vp, vp]
+    L.voila_resample.argtypes = [vp, c_int32, c_uint32, vp, vp, vp, c_int32, vp, vp, c_size_t, vp]
+    L.voila_weights_workspace_size.argtypes = [c_int32]
+    L.voila_weights_workspace_size.restype = c_size_t
     L.voila_resample.restype = c_int32
     L.voila_observe_workspace_size.argtypes = [vp]
     L.voila_observe_workspace_size.restype = c_size_t
@@ -153,7 +155,8 @@ lib = _load()
 # the exported C symbols (checked by the test-suite against include/voila.h)
 EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_model_create",
             "voila_model_destroy", "voila_plan_workspace_size", "voila_plan", "voila_update_workspace_size",
-            "voila_update", "voila_update_max_particles", "voila_normalize", "voila_resample_bits",
+            "voila_update", "voila_update_max_particles", "voila_weights_workspace_size", "voila_normalize",
+            "voila_resample_bits",
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
             "voila_batch_replay", "voila_grad_param_count", "voila_rollout_grad_workspace_size",
@@ -340,7 +343,12 @@ def update(model: Model, states, action, obs, lam=1.0, prior_w=None, seed=0, U=0
     return res
 
 
-def normalize(loglik, lam=1.0, prior_w=None, status=None, stream=None):
+def weights_workspace(N, device):
+    n = lib.voila_weights_workspace_size(int(N))
+    return None if n == 0 else torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def normalize(loglik, lam=1.0, prior_w=None, status=None, workspace=None, stream=None):
     """(w [N] float64, stats [2] float64) of weights proportional to prior * exp(l / lam)."""
     N = int(loglik.shape[0])
     _dev(loglik, torch.float32, (N,), "loglik")
@@ -348,26 +356,27 @@ def normalize(loglik, lam=1.0, prior_w=None, status=None, stream=None):
         _dev(prior_w, torch.float64, (N,), "prior_w")
     w = torch.empty(N, dtype=torch.float64, device=loglik.device)
     st = torch.empty(2, dtype=torch.float64, device=loglik.device)
-    _check(lib.voila_normalize(_ptr(loglik), _ptr(prior_w), N, float(lam), _ptr(w), _ptr(st), _ptr(status),
-                               _stream(stream)))
+    ws = workspace if workspace is not None else weights_workspace(N, loglik.device)
+    _check(lib.voila_normalize(_ptr(loglik), _ptr(prior_w), N, float(lam), _ptr(w), _ptr(st), _ptr(status), _ptr(ws),
+                               0 if ws is None else ws.numel(), _stream(stream)))
     return w, st
 
 
-def resample(w, U, src=None, status=None, stream=None):
+def resample(w, U, src=None, status=None, workspace=None, dst=None, idx=None, stream=None):
     """Systematic resampling indices [N] int32 (and src rows gathered by them)."""
     N = int(w.shape[0])
     _dev(w, torch.float64, (N,), "w")
-    idx = torch.empty(N, dtype=torch.int32, device=w.device)
-    dst = None
+    idx = idx if idx is not None else torch.empty(N, dtype=torch.int32, device=w.device)
     rf = 0
     if src is not None:
         _dev(src, torch.float32, None, "src")
         if src.shape[0] != N:
             raise VoilaError(VOILA_ERR_INVALID_ARG, "src must have N rows")
         rf = int(src.numel() // N)
-        dst = torch.empty_like(src)
+        dst = dst if dst is not None else torch.empty_like(src)
+    ws = workspace if workspace is not None else weights_workspace(N, w.device)
     _check(lib.voila_resample(_ptr(w), N, int(U) & 0xFFFFFFFF, _ptr(idx), _ptr(src), _ptr(dst), rf, _ptr(status),
-                              _stream(stream)))
+                              _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream)))
     return (idx, dst) if src is not None else idx
 
 

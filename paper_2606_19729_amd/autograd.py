@@ -49,4 +49,4 @@ class DistillLoss(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_out):
-        return tuple(grad_out * g for g in ctx.grads) + (None,) * 6
+        return tuple(grad_out.to(g.device) * g for g in ctx.grads) + (None,) * 6

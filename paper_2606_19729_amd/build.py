@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvoila.so")
-SOURCES = ["kernels.hip", "grad.hip", "abi.hip"]
+SOURCES = ["kernels.hip", "grad.hip", "resample_large.hip", "abi.hip"]
 ARCH = os.environ.get("VOILA_OFFLOAD_ARCH", "gfx950")
 
 

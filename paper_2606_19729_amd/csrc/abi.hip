@@ -539,7 +539,13 @@ voila_status_t voila_plan(voila_model_t m, const float* d_states, const double* 
 // ---------------------------------------------------------------------------
 // update
 // ---------------------------------------------------------------------------
-int32_t voila_update_max_particles(void) { return kNormResMaxN; }
+int32_t voila_update_max_particles(void) { return kLargeMaxN; }
+
+size_t voila_weights_workspace_size(int32_t N) {
+    if (N <= kNormResMaxN) return 0;
+    if (N > kLargeMaxN) return 0;
+    return large_res_workspace_bytes(N);
+}
 
 int32_t voila_resample_bits(int32_t N) {
     if (N < 1) return 0;
@@ -554,6 +560,7 @@ struct UpdateWs {
     float* b0_lik;
     double* x;
     float* prop;
+    char* large;   // multi-workgroup resampling workspace (N > 8192)
     size_t bytes;
 };
 UpdateWs carve_update(char* base, int width, int N, int d_s) {
@@ -567,6 +574,8 @@ UpdateWs carve_update(char* base, int width, int N, int d_s) {
     off = align_up(off + (size_t)N * 8, 256);
     w.prop = reinterpret_cast<float*>(base + off);
     off = align_up(off + (size_t)N * d_s * 4, 256);
+    w.large = base + off;
+    if (N > kNormResMaxN) off = align_up(off + large_res_workspace_bytes(N), 256);
     w.bytes = off;
     return w;
 }
@@ -609,7 +618,7 @@ voila_status_t voila_update(voila_model_t m, const float* d_states, const double
     if (!m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model has no likelihood network");
     if (!o || !h_action || !h_obs) return fail(VOILA_ERR_INVALID_ARG, "NULL options, action or observation");
     if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
-    if (N > kNormResMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
+    if (N > kLargeMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
     if (!(o->lambda > 0.0) || !std::isfinite(o->lambda)) return fail(VOILA_ERR_INVALID_ARG, "lambda must be > 0");
     if (!d_states || !d_states_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
     UpdateWs w = carve_update(reinterpret_cast<char*>(ws), m->width, N, m->d_s);
@@ -649,6 +658,26 @@ voila_status_t voila_update(voila_model_t m, const float* d_states, const double
     const int want = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int cap = m->cus * m->prop_bpc;
     VOILA_CHECK_HIP(launch_propose(m->shape, m->dt, p, want < cap ? want : cap, s));
+    if (N > kNormResMaxN) {
+        LargeResParams r{};
+        r.x = w.x;
+        r.lambda = o->lambda;
+        r.N = N;
+        r.bits = voila_resample_bits(N);
+        r.uniform_prior = d_prior_w ? 0 : 1;
+        r.do_resample = 1;
+        r.U = o->resample_u;
+        r.w_out = d_w_out;
+        r.stats = d_stats_out;
+        r.idx_out = d_idx_out;
+        r.src = p.prop;
+        r.dst = d_states_out;
+        r.row_floats = m->d_s;
+        r.status = d_status;
+        r.ws = carve_large_res(w.large, N);
+        VOILA_CHECK_HIP(launch_large_res(r, s));
+        return VOILA_OK;
+    }
     NormResParams r{};
     r.x = w.x;
     r.N = N;
@@ -669,11 +698,28 @@ voila_status_t voila_update(voila_model_t m, const float* d_states, const double
 }
 
 voila_status_t voila_normalize(const float* d_loglik, const double* d_prior_w, int32_t N, double lambda,
-                               double* d_w_out, double* d_stats_out, int32_t* d_status, void* stream) {
+                               double* d_w_out, double* d_stats_out, int32_t* d_status, void* ws, size_t ws_bytes,
+                               void* stream) {
     if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
-    if (N > kNormResMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
+    if (N > kLargeMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(VOILA_ERR_INVALID_ARG, "lambda must be > 0");
     if (!d_loglik || !d_w_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    if (N > kNormResMaxN) {
+        if (!ws || ws_bytes < voila_weights_workspace_size(N)) return fail(VOILA_ERR_WORKSPACE, "workspace too small");
+        LargeResParams r{};
+        r.loglik = d_loglik;
+        r.prior_w = d_prior_w;
+        r.lambda = lambda;
+        r.N = N;
+        r.bits = voila_resample_bits(N);
+        r.uniform_prior = d_prior_w ? 0 : 1;
+        r.w_out = d_w_out;
+        r.stats = d_stats_out;
+        r.status = d_status;
+        r.ws = carve_large_res(ws, N);
+        VOILA_CHECK_HIP(launch_large_res(r, reinterpret_cast<hipStream_t>(stream)));
+        return VOILA_OK;
+    }
     NormResParams r{};
     r.loglik = d_loglik;
     r.prior_w = d_prior_w;
@@ -690,12 +736,30 @@ voila_status_t voila_normalize(const float* d_loglik, const double* d_prior_w, i
 }
 
 voila_status_t voila_resample(const double* d_w, int32_t N, uint32_t U, int32_t* d_idx_out, const float* d_src,
-                              float* d_dst, int32_t row_floats, int32_t* d_status, void* stream) {
+                              float* d_dst, int32_t row_floats, int32_t* d_status, void* ws, size_t ws_bytes,
+                              void* stream) {
     if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
-    if (N > kNormResMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
+    if (N > kLargeMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
     if (!d_w || !d_idx_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
     if ((d_src != nullptr) != (d_dst != nullptr)) return fail(VOILA_ERR_INVALID_ARG, "give both or neither of src and dst");
     if (d_src && row_floats < 1) return fail(VOILA_ERR_INVALID_ARG, "row_floats must be >= 1");
+    if (N > kNormResMaxN) {
+        if (!ws || ws_bytes < voila_weights_workspace_size(N)) return fail(VOILA_ERR_WORKSPACE, "workspace too small");
+        LargeResParams r{};
+        r.w_in = d_w;
+        r.N = N;
+        r.bits = voila_resample_bits(N);
+        r.do_resample = 1;
+        r.U = U;
+        r.idx_out = d_idx_out;
+        r.src = d_src;
+        r.dst = d_dst;
+        r.row_floats = row_floats;
+        r.status = d_status;
+        r.ws = carve_large_res(ws, N);
+        VOILA_CHECK_HIP(launch_large_res(r, reinterpret_cast<hipStream_t>(stream)));
+        return VOILA_OK;
+    }
     NormResParams r{};
     r.w_in = d_w;
     r.N = N;

@@ -161,6 +161,43 @@ struct GradReduceParams {
     double scale;
 };
 
+// Multi-workgroup normalisation / resampling for large beliefs.
+struct LargeResWs {
+    double* bmax;    // per-chunk max
+    double* bsum;    // per-chunk sum of exp
+    double* btot;    // per-chunk total of quantised weights
+    double* bsq;     // per-chunk sum of squared weights
+    double* boff;    // exclusive prefix of chunk totals
+    double* bincl;   // inclusive prefix of chunk totals
+    int* blast;      // per-chunk last positive-mass particle
+    double* cloc;    // [N] chunk-relative inclusive prefix of quantised weights
+    double* scal;    // [0] max, [1] sum
+    int* last;       // last positive-mass particle overall
+};
+
+struct LargeResParams {
+    const double* x;        // [N] l / lambda (+ log prior), or NULL
+    const float* loglik;    // [N] used when x and w_in are NULL
+    const double* prior_w;  // with loglik, or NULL
+    const double* w_in;     // given normalised weights (resample only), or NULL
+    double lambda;
+    int N, bits, uniform_prior, do_resample, n_chunks;
+    uint32_t U;
+    double* w_out;
+    double* stats;
+    int32_t* idx_out;
+    const float* src;
+    float* dst;
+    int row_floats;
+    int32_t* status;
+    LargeResWs ws;
+};
+
+size_t large_res_workspace_bytes(int N);
+LargeResWs carve_large_res(void* base, int N);
+hipError_t launch_large_res(LargeResParams p, hipStream_t s);
+constexpr int kLargeMaxN = 1 << 26;
+
 struct PhiloxParams {
     float* out;
     uint32_t* words;

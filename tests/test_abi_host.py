@@ -67,12 +67,18 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     L = V.lib
     assert L.voila_plan(None, None, None, 1, None, 1, 1, None, None, 0, None, None, None, None) == \
         V.VOILA_ERR_INVALID_ARG
-    assert L.voila_normalize(None, None, 0, 1.0, None, None, None, None) == V.VOILA_ERR_INVALID_ARG
-    assert L.voila_normalize(None, None, 10, 0.0, None, None, None, None) == V.VOILA_ERR_INVALID_ARG
-    assert L.voila_normalize(None, None, 9000, 1.0, None, None, None, None) == V.VOILA_ERR_UNSUPPORTED
-    assert L.voila_resample(None, 0, 0, None, None, None, 0, None, None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_normalize(None, None, 0, 1.0, None, None, None, None, 0, None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_normalize(None, None, 10, 0.0, None, None, None, None, 0, None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_normalize(None, None, (1 << 26) + 1, 1.0, None, None, None, None, 0, None) == \
+        V.VOILA_ERR_UNSUPPORTED
     fake = ctypes.c_void_p(16)
-    assert L.voila_resample(fake, 4, 0, fake, fake, None, 1, None, None) == V.VOILA_ERR_INVALID_ARG
+    # beliefs above one workgroup need the caller's workspace
+    assert L.voila_normalize(fake, None, 9000, 1.0, fake, None, None, None, 0, None) == V.VOILA_ERR_WORKSPACE
+    assert L.voila_weights_workspace_size(8192) == 0
+    assert L.voila_weights_workspace_size(9000) > 9000 * 8
+    assert L.voila_resample(None, 0, 0, None, None, None, 0, None, None, 0, None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_resample(fake, 4, 0, fake, fake, None, 1, None, None, 0, None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_resample(fake, 9000, 0, fake, None, None, 0, None, None, 0, None) == V.VOILA_ERR_WORKSPACE
     assert L.voila_philox_normals(1, 0, 0, 0, 1 << 16, 1, 4, fake, None, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_philox_normals(1, 0, 0, 0, 3, 1, 0, fake, None, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_model_create(None, 0, None) == V.VOILA_ERR_INVALID_ARG

@@ -1,0 +1,92 @@
+"""Beliefs above one workgroup (N > 8192): the multi-workgroup normalisation,
+exact blocked prefix sum and two-level binary-search resampler against the
+oracle -- indices bit-exact given the oracle's weights, weights within 1e-13
+given the same log-likelihoods."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_19729_amd as lib
+    return lib
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("N", [8193, 50000, 1 << 20])
+def test_large_resample_bit_exact(V, N):
+    rng = np.random.default_rng(N)
+    cases = [np.full(N, 1.0 / N), rng.dirichlet(np.full(N, 0.2))]
+    oh = np.zeros(N)
+    oh[N // 3] = 1.0
+    cases.append(oh)
+    z = rng.dirichlet(np.ones(N))
+    z[rng.integers(0, N, N // 3)] = 0.0
+    cases.append(z / z.sum())
+    for ci, wv in enumerate(cases):
+        for U in [0, 0xFFFFFFFF, int(rng.integers(0, 2**32))]:
+            print(f"large resample N={N} case {ci} U={U}", flush=True)
+            idx = V.resample(dev(wv, torch.float64), U)
+            torch.cuda.synchronize()
+            assert np.array_equal(idx.cpu().numpy(), oracle.resample(wv, U)), (N, ci, U)
+
+
+def test_large_resample_gathers_rows(V):
+    rng = np.random.default_rng(3)
+    N = 30000
+    wv = rng.dirichlet(np.ones(N))
+    src = rng.standard_normal((N, 16)).astype(np.float32)
+    idx, dst = V.resample(dev(wv, torch.float64), 99, src=dev(src))
+    torch.cuda.synchronize()
+    ref = oracle.resample(wv, 99)
+    assert np.array_equal(idx.cpu().numpy(), ref)
+    assert np.array_equal(dst.cpu().numpy(), src[ref])
+
+
+@pytest.mark.parametrize("N", [8193, 100000])
+def test_large_normalize(V, N):
+    rng = np.random.default_rng(N)
+    ll = (rng.standard_normal(N) * 4).astype(np.float32)
+    for lam, prior in [(1.0, None), (1.25, rng.dirichlet(np.ones(N)))]:
+        w, st = V.normalize(dev(ll), lam, None if prior is None else dev(prior, torch.float64))
+        torch.cuda.synchronize()
+        wr, sr = oracle.normalize(ll.astype(np.float64), lam, prior)
+        assert np.max(np.abs(w.cpu().numpy() - wr) / wr) < 1e-13
+        assert np.max(np.abs(st.cpu().numpy() - sr) / np.abs(sr)) < 1e-12
+    w, st = V.normalize(dev(np.full(N, 0.5, np.float32)), 1.0)
+    torch.cuda.synchronize()
+    assert np.all(w.cpu().numpy() == 1.0 / N)
+
+
+def test_large_update_matches_oracle(V):
+    w = workloads.small(seed=41, N=20000)
+    m = V.Model(w.model)
+    o = oracle.draw_observation(w).astype(np.float32)
+    out = V.update(m, dev(w.states), w.update_action, o, lam=w.lam, seed=w.update_seed, U=w.resample_u)
+    torch.cuda.synchronize()
+    ref = oracle.update(w.model, w.states, w.update_action, o, lam=w.lam, seed=w.update_seed, U=w.resample_u)
+    prop = out["prop"].cpu().numpy()
+    assert np.max(np.abs(prop - ref["S_prop"])) <= 1e-5 * np.max(np.abs(ref["S_prop"]))
+    wd, st = oracle.normalize(out["loglik"].cpu().numpy().astype(np.float64), w.lam)
+    assert np.max(np.abs(out["w"].cpu().numpy() - wd) / wd) < 1e-12
+    idx = out["idx"].cpu().numpy()
+    assert np.array_equal(idx, oracle.resample(out["w"].cpu().numpy(), w.resample_u))
+    assert np.array_equal(out["states"].cpu().numpy(), prop[idx])
+
+
+def test_large_zero_mass_sets_status(V):
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    V.resample(dev(np.zeros(20000), torch.float64), 5, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == V.VOILA_ERR_NUMERIC
