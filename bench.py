@@ -133,6 +133,71 @@ def bench_batched(V, torch, reps):
     return out
 
 
+def bench_wide(V, torch, reps):
+    """Hidden width 1024 in bfloat16: throughput at 1024 candidates x 4096
+    particles x 20 steps, and plan + update latency at the small counts."""
+    import workloads
+    dev = torch.device("cuda", 0)
+    out = {}
+    w = workloads.wide(seed=3, N=4096, K=1024, H=20)
+    mb = V.Model(w.model, compute="bf16")
+    S = torch.as_tensor(w.states, device=dev)
+    C = torch.as_tensor(w.cands, device=dev)
+    q = torch.empty(w.K, dtype=torch.float32, device=dev)
+    ws = mb.plan_workspace(w.N, w.K, w.H)
+    V.plan(mb, S, C, w.gamma, w.goal, seed=w.plan_seed, q_out=q, workspace=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for r in range(reps):
+        V.plan(mb, S, C, w.gamma, w.goal, seed=w.plan_seed + r, q_out=q, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    steps = w.K * w.N * w.H
+    tflops = trans_flops_per_step(w.model) * steps / (ms / 1e3) / 1e12
+    out["large_counts"] = {"K": w.K, "N": w.N, "H": w.H, "plan_ms": ms, "rollout_steps_per_s": steps / (ms / 1e3),
+                           "achieved_tflops": tflops, "mfma_frac_bf16_peak": tflops / PEAK_BF16_TFLOPS,
+                           "flop_per_rollout_step": trans_flops_per_step(w.model)}
+    w = workloads.wide(seed=3)
+    mb = V.Model(w.model, compute="bf16")
+    S = torch.as_tensor(w.states, device=dev)
+    C = torch.as_tensor(w.cands, device=dev)
+    q = torch.empty(w.K, dtype=torch.float32, device=dev)
+    ws = mb.plan_workspace(w.N, w.K, w.H)
+    wsu = mb.update_workspace(w.N)
+    obs = np.zeros(w.model.d_o, np.float32)
+    upd_out = {"states": torch.empty((w.N, 4), dtype=torch.float32, device=dev),
+               "idx": torch.empty(w.N, dtype=torch.int32, device=dev),
+               "w": torch.empty(w.N, dtype=torch.float64, device=dev),
+               "loglik": torch.empty(w.N, dtype=torch.float32, device=dev),
+               "prop": torch.empty((w.N, 4), dtype=torch.float32, device=dev),
+               "stats": torch.empty(2, dtype=torch.float64, device=dev)}
+
+    def once(r):
+        V.plan(mb, S, C, w.gamma, w.goal, seed=r, q_out=q, workspace=ws)
+        e_mid.record(stream)
+        V.update(mb, S, w.update_action, obs, lam=w.lam, seed=r + 1, U=w.resample_u, out=upd_out, workspace=wsu)
+
+    e_mid = torch.cuda.Event(enable_timing=True)
+    once(0)
+    torch.cuda.synchronize()
+    pm, um = [], []
+    for r in range(max(3, reps)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e_mid = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        once(10 + r)
+        b.record(stream)
+        torch.cuda.synchronize()
+        pm.append(a.elapsed_time(e_mid))
+        um.append(e_mid.elapsed_time(b))
+    out["small_counts"] = {"K": w.K, "N": w.N, "H": w.H, "plan_ms": float(np.median(pm)),
+                           "update_ms": float(np.median(um))}
+    return out
+
+
 def bench_grad(V, torch, reps):
     """Adjoint through 65,536 rollouts x 20 steps (checkpoint every 5): distillation
     gradient w.r.t. the 5,316 parameters; return gradient w.r.t. [1024, 20, 4] actions."""
@@ -177,13 +242,13 @@ def bench_update_sweep(V, torch, reps):
         ll = torch.as_tensor(rng.standard_normal(N).astype(np.float32), device=dev)
         src = torch.as_tensor(rng.standard_normal((N, 16)).astype(np.float32), device=dev)
         ws = V.weights_workspace(N, dev)
-        w = torch.empty(N, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         idx = torch.empty(N, dtype=torch.int32, device=dev)
 
+        stats = torch.empty(2, dtype=torch.float64, device=dev)
+
         def once():
-            wv, _ = V.normalize(ll, 1.0, workspace=ws)
-            V.resample(wv, 12345, src=src, workspace=ws, dst=dst, idx=idx)
+            V.reweight_resample(ll, 12345, src=src, workspace=ws, idx=idx, dst=dst, stats=stats)
         once()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -358,6 +423,8 @@ def main():
         result["batched"] = bench_batched(V, torch, max(2, args.steps // 2))
         print("[bench] adjoint rollouts", file=sys.stderr, flush=True)
         result["gradients"] = bench_grad(V, torch, max(2, args.steps))
+        print("[bench] hidden width 1024 (bf16)", file=sys.stderr, flush=True)
+        result["wide_bf16"] = bench_wide(V, torch, max(2, args.steps // 2))
         print("[bench] belief-update sweep", file=sys.stderr, flush=True)
         result["update_sweep"] = bench_update_sweep(V, torch, max(3, args.steps))
 

@@ -186,6 +186,16 @@ voila_status_t voila_normalize(const float* d_loglik, const double* d_prior_w, i
                                double* d_w_out, double* d_stats_out, int32_t* d_status, void* d_workspace,
                                size_t workspace_bytes, void* stream);
 
+/* The update's second stage on its own, in one call: weights of given
+ * log-likelihoods d_loglik [N] (as voila_normalize) followed by systematic
+ * resampling and the optional row gather (as voila_resample), without a
+ * round trip of the weights through memory unless d_w_out is given.
+ * Workspace as voila_weights_workspace_size(N). */
+voila_status_t voila_reweight_resample(const float* d_loglik, const double* d_prior_w, int32_t N, double lambda,
+                                       uint32_t U, int32_t* d_idx_out, double* d_w_out, double* d_stats_out,
+                                       const float* d_src, float* d_dst, int32_t row_floats, int32_t* d_status,
+                                       void* d_workspace, size_t workspace_bytes, void* stream);
+
 /* Fraction bits b(N) = min(32, 52 - ceil(log2 N)) of the quantised weights. */
 int32_t voila_resample_bits(int32_t N);
 

@@ -149,8 +149,9 @@ static int mlp_check(int n_layers, const int* dims)
 }
 
 /* y = MLP(x).  Hidden layers: h = max(W h_prev + b, 0); output layer linear.
- * With bf16 != 0 each weight and each layer input is first rounded to
- * bfloat16 (biases, accumulation and outputs stay binary64). */
+ * With bf16 != 0 each layer input is first rounded to bfloat16, and the
+ * weights must already be bfloat16 values (round_weights; biases,
+ * accumulation and outputs stay binary64). */
 static void mlp_forward(int n_layers, const int* dims, const double* params,
                         const double* x, double* y, int bf16)
 {
@@ -166,8 +167,7 @@ static void mlp_forward(int n_layers, const int* dims, const double* params,
         for (int n = 0; n < n_out; ++n) {
             double acc = 0.0;
             for (int k = 0; k < n_in; ++k) {
-                double wk = bf16 ? or_round_bf16(W[(size_t)n * n_in + k]) : W[(size_t)n * n_in + k];
-                acc += wk * in[k];
+                acc += W[(size_t)n * n_in + k] * in[k];
             }
             acc += b[n];
             if (l < n_layers - 1) {
@@ -182,13 +182,35 @@ static void mlp_forward(int n_layers, const int* dims, const double* params,
     for (int n = 0; n < dims[n_layers]; ++n) y[n] = in[n];
 }
 
+/* Copy of a parameter vector with every weight rounded to bfloat16 and the
+ * biases unchanged (the bfloat16 emulation rounds each weight once). */
+static double* round_weights(int n_layers, const int* dims, const double* params)
+{
+    double* out = (double*)malloc(sizeof(double) * (mlp_param_count(n_layers, dims) + 1));
+    if (!out) return NULL;
+    const double* p = params;
+    double* q = out;
+    for (int l = 0; l < n_layers; ++l) {
+        size_t nw = (size_t)dims[l + 1] * dims[l];
+        for (size_t j = 0; j < nw; ++j) q[j] = or_round_bf16(p[j]);
+        for (int j = 0; j < dims[l + 1]; ++j) q[nw + j] = p[nw + j];
+        p += nw + dims[l + 1];
+        q += nw + dims[l + 1];
+    }
+    return out;
+}
+
 int or_mlp(int n_layers, const int* dims, const double* params, int rows,
            const double* X, double* Y, int bf16)
 {
     if (mlp_check(n_layers, dims) != OR_OK || rows < 0) return OR_ERR_ARG;
+    double* rw = bf16 ? round_weights(n_layers, dims, params) : NULL;
+    if (bf16 && !rw) return OR_ERR_ARG;
+    const double* P = bf16 ? rw : params;
     #pragma omp parallel for schedule(static)
     for (int r = 0; r < rows; ++r)
-        mlp_forward(n_layers, dims, params, X + (size_t)r * dims[0], Y + (size_t)r * dims[n_layers], bf16);
+        mlp_forward(n_layers, dims, P, X + (size_t)r * dims[0], Y + (size_t)r * dims[n_layers], bf16);
+    free(rw);
     return OR_OK;
 }
 
@@ -209,6 +231,32 @@ typedef struct {
     int z_layers; const int* z_dims; const double* z_params;
     int l_layers; const int* l_dims; const double* l_params;
 } or_model;
+
+/* The model with bfloat16-rounded weights for the bfloat16 emulation
+ * (m itself when bf16 == 0).  release_rounded frees the copies. */
+typedef struct {
+    or_model m;
+    double* buf[3];
+} rounded_model;
+
+static const or_model* rounded(const or_model* m, int bf16, rounded_model* r)
+{
+    r->buf[0] = r->buf[1] = r->buf[2] = NULL;
+    if (!bf16) return m;
+    r->m = *m;
+    if (m->t_params && m->t_layers > 0 && mlp_check(m->t_layers, m->t_dims) == OR_OK)
+        r->m.t_params = r->buf[0] = round_weights(m->t_layers, m->t_dims, m->t_params);
+    if (m->z_params && m->z_layers > 0 && mlp_check(m->z_layers, m->z_dims) == OR_OK)
+        r->m.z_params = r->buf[1] = round_weights(m->z_layers, m->z_dims, m->z_params);
+    if (m->l_params && m->l_layers > 0 && mlp_check(m->l_layers, m->l_dims) == OR_OK)
+        r->m.l_params = r->buf[2] = round_weights(m->l_layers, m->l_dims, m->l_params);
+    return &r->m;
+}
+
+static void release_rounded(rounded_model* r)
+{
+    for (int j = 0; j < 3; ++j) free(r->buf[j]);
+}
 
 static int action_width(const or_model* m)
 {
@@ -310,16 +358,18 @@ static double weighted_sum(int n, const double* a, const double* b, size_t strid
     return sum + comp;
 }
 
-int or_plan(const or_model* m, int N, const double* S, const double* belief_w,
+int or_plan(const or_model* m0, int N, const double* S, const double* belief_w,
             int K, int H, const int32_t* cand_disc, const double* cand_cont,
             double gamma, const double* goal, int reward_at,
             const double* noise, uint64_t seed, int crn, int bf16,
             double* Q, double* G)
 {
-    if (model_check(m) != OR_OK || N < 1 || K < 0 || H < 0) return OR_ERR_ARG;
-    if (m->n_actions > 0 ? !cand_disc : !cand_cont) return OR_ERR_ARG;
+    if (model_check(m0) != OR_OK || N < 1 || K < 0 || H < 0) return OR_ERR_ARG;
+    if (m0->n_actions > 0 ? !cand_disc : !cand_cont) return OR_ERR_ARG;
     double* Gbuf = G ? G : (double*)malloc(sizeof(double) * (size_t)K * N + 1);
     if (!Gbuf) return OR_ERR_ARG;
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
     #pragma omp parallel for schedule(dynamic, 16)
     for (long r = 0; r < (long)K * N; ++r) {
         int k = (int)(r / N), i = (int)(r % N);
@@ -328,26 +378,30 @@ int or_plan(const or_model* m, int N, const double* S, const double* belief_w,
     }
     for (int k = 0; k < K; ++k) Q[k] = weighted_sum(N, Gbuf + (size_t)k * N, belief_w, 1);
     if (!G) free(Gbuf);
+    release_rounded(&rm);
     return OR_OK;
 }
 
 /* Returns of selected rollouts (k_list[p], i_list[p]) only -- used to check
  * sampled outputs of full-size workloads. */
-int or_rollouts(const or_model* m, int N, const double* S, int K, int H,
+int or_rollouts(const or_model* m0, int N, const double* S, int K, int H,
                 const int32_t* cand_disc, const double* cand_cont,
                 double gamma, const double* goal, int reward_at,
                 uint64_t seed, int crn, int bf16,
                 int n_pairs, const int32_t* k_list, const int32_t* i_list, double* G_out)
 {
-    if (model_check(m) != OR_OK || N < 1 || K < 0 || H < 0 || n_pairs < 0) return OR_ERR_ARG;
+    if (model_check(m0) != OR_OK || N < 1 || K < 0 || H < 0 || n_pairs < 0) return OR_ERR_ARG;
     for (int p = 0; p < n_pairs; ++p)
         if (k_list[p] < 0 || k_list[p] >= K || i_list[p] < 0 || i_list[p] >= N) return OR_ERR_ARG;
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
     #pragma omp parallel for schedule(dynamic, 1)
     for (int p = 0; p < n_pairs; ++p) {
         int k = k_list[p], i = i_list[p];
         G_out[p] = rollout_return(m, S + (size_t)i * m->d_s, k, i, N, H, cand_disc, cand_cont,
                                   gamma, goal, reward_at, NULL, seed, crn, bf16);
     }
+    release_rounded(&rm);
     return OR_OK;
 }
 
@@ -453,22 +507,24 @@ int or_resample(int N, const double* w, uint32_t U, int32_t* idx)
  *   w'   = normalise(l / lambda, prior)
  *   idx  = resample(w', U);  S_new_j = s'_{idx_j}
  * Outputs may be NULL except S_new. */
-int or_update(const or_model* m, int N, const double* S, const double* prior_w,
+int or_update(const or_model* m0, int N, const double* S, const double* prior_w,
               int a_disc, const double* a_cont, const double* o, double lambda,
               const double* noise, uint64_t seed, uint32_t U, int bf16,
               double* S_prop, double* loglik, double* w_out, double* stats,
               int32_t* idx, double* S_new)
 {
-    if (model_check(m) != OR_OK || N < 1) return OR_ERR_ARG;
-    if (mlp_check(m->l_layers, m->l_dims) != OR_OK) return OR_ERR_ARG;
-    if (m->l_dims[0] != m->d_s + action_width(m) + m->d_o || m->l_dims[m->l_layers] != 1) return OR_ERR_ARG;
-    if (m->n_actions > 0 ? (a_disc < 0 || a_disc >= m->n_actions) : !a_cont) return OR_ERR_ARG;
-    int d_s = m->d_s, aw = action_width(m);
+    if (model_check(m0) != OR_OK || N < 1) return OR_ERR_ARG;
+    if (mlp_check(m0->l_layers, m0->l_dims) != OR_OK) return OR_ERR_ARG;
+    if (m0->l_dims[0] != m0->d_s + action_width(m0) + m0->d_o || m0->l_dims[m0->l_layers] != 1) return OR_ERR_ARG;
+    if (m0->n_actions > 0 ? (a_disc < 0 || a_disc >= m0->n_actions) : !a_cont) return OR_ERR_ARG;
+    int d_s = m0->d_s, aw = action_width(m0);
     double* sp = (double*)malloc(sizeof(double) * (size_t)N * d_s);
     double* ll = (double*)malloc(sizeof(double) * (size_t)N);
     double* wn = (double*)malloc(sizeof(double) * (size_t)N);
     int32_t* ix = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
     if (!sp || !ll || !wn || !ix) { free(sp); free(ll); free(wn); free(ix); return OR_ERR_ARG; }
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
     #pragma omp parallel for schedule(static)
     for (int i = 0; i < N; ++i) {
         double w[OR_MAX_WIDTH], x[OR_MAX_WIDTH], y[1];
@@ -495,18 +551,21 @@ int or_update(const or_model* m, int N, const double* S, const double* prior_w,
         if (idx) memcpy(idx, ix, sizeof(int32_t) * (size_t)N);
     }
     free(sp); free(ll); free(wn); free(ix);
+    release_rounded(&rm);
     return rc;
 }
 
 /* Observation sampler (Eq. 5): o_r = f_Z([s'_r, a_r, w_Z,r]) for n rows;
  * noise given or stream 4 with counter (row, 0, 0).  Actions: one per row. */
-int or_observe(const or_model* m, int n, const double* S, const int32_t* a_disc,
+int or_observe(const or_model* m0, int n, const double* S, const int32_t* a_disc,
                const double* a_cont, const double* noise, uint64_t seed, int bf16, double* O)
 {
-    if (n < 0 || mlp_check(m->z_layers, m->z_dims) != OR_OK) return OR_ERR_ARG;
-    int aw = action_width(m);
-    if (m->z_dims[0] != m->d_s + aw + m->d_wz || m->z_dims[m->z_layers] != m->d_o) return OR_ERR_ARG;
-    if (m->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    if (n < 0 || mlp_check(m0->z_layers, m0->z_dims) != OR_OK) return OR_ERR_ARG;
+    int aw = action_width(m0);
+    if (m0->z_dims[0] != m0->d_s + aw + m0->d_wz || m0->z_dims[m0->z_layers] != m0->d_o) return OR_ERR_ARG;
+    if (m0->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
     #pragma omp parallel for schedule(static)
     for (int r = 0; r < n; ++r) {
         double x[OR_MAX_WIDTH], w[OR_MAX_WIDTH];
@@ -520,20 +579,24 @@ int or_observe(const or_model* m, int n, const double* S, const int32_t* a_disc,
         for (int j = 0; j < m->d_wz; ++j) x[m->d_s + aw + j] = w[j];
         mlp_forward(m->z_layers, m->z_dims, m->z_params, x, O + (size_t)r * m->d_o, bf16);
     }
+    release_rounded(&rm);
     return OR_OK;
 }
 
 /* Transition draws for n given (state, action, noise) rows: s'_r. */
-int or_transition(const or_model* m, int n, const double* S, const int32_t* a_disc,
+int or_transition(const or_model* m0, int n, const double* S, const int32_t* a_disc,
                   const double* a_cont, const double* noise, int bf16, double* S_next)
 {
-    if (model_check(m) != OR_OK || n < 0) return OR_ERR_ARG;
-    if (m->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    if (model_check(m0) != OR_OK || n < 0) return OR_ERR_ARG;
+    if (m0->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
     #pragma omp parallel for schedule(static)
     for (int r = 0; r < n; ++r)
         transition(m, S + (size_t)r * m->d_s, a_disc ? a_disc[r] : 0,
                    a_cont ? a_cont + (size_t)r * m->d_a : NULL,
                    noise + (size_t)r * m->d_w, S_next + (size_t)r * m->d_s, bf16);
+    release_rounded(&rm);
     return OR_OK;
 }
 

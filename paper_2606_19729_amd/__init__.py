@@ -121,6 +121,9 @@ def _load():
     L.voila_resample_bits.argtypes = [c_int32]
     L.voila_resample_bits.restype = c_int32
     L.voila_resample.argtypes = [vp, c_int32, c_uint32, vp, vp, vp, c_int32, vp, vp, c_size_t, vp]
+    L.voila_reweight_resample.argtypes = [vp, vp, c_int32, c_double, c_uint32, vp, vp, vp, vp, vp, c_int32, vp,
+                                          vp, c_size_t, vp]
+    L.voila_reweight_resample.restype = c_int32
     L.voila_weights_workspace_size.argtypes = [c_int32]
     L.voila_weights_workspace_size.restype = c_size_t
     L.voila_resample.restype = c_int32
@@ -156,6 +159,7 @@ lib = _load()
 EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_model_create",
             "voila_model_destroy", "voila_plan_workspace_size", "voila_plan", "voila_update_workspace_size",
             "voila_update", "voila_update_max_particles", "voila_weights_workspace_size", "voila_normalize",
+            "voila_reweight_resample",
             "voila_resample_bits",
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
@@ -378,6 +382,32 @@ def resample(w, U, src=None, status=None, workspace=None, dst=None, idx=None, st
     _check(lib.voila_resample(_ptr(w), N, int(U) & 0xFFFFFFFF, _ptr(idx), _ptr(src), _ptr(dst), rf, _ptr(status),
                               _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream)))
     return (idx, dst) if src is not None else idx
+
+
+def reweight_resample(loglik, U, lam=1.0, prior_w=None, src=None, want_w=False, status=None, workspace=None,
+                      idx=None, dst=None, stats=None, stream=None):
+    """Weights exp(l / lam) (x prior) normalised in binary64, then systematic
+    resampling (and the gathered rows of src): dict(idx, w, stats, dst)."""
+    N = int(loglik.shape[0])
+    _dev(loglik, torch.float32, (N,), "loglik")
+    if prior_w is not None:
+        _dev(prior_w, torch.float64, (N,), "prior_w")
+    d = loglik.device
+    idx = idx if idx is not None else torch.empty(N, dtype=torch.int32, device=d)
+    w = torch.empty(N, dtype=torch.float64, device=d) if want_w else None
+    stats = stats if stats is not None else torch.empty(2, dtype=torch.float64, device=d)
+    rf = 0
+    if src is not None:
+        _dev(src, torch.float32, None, "src")
+        if src.shape[0] != N:
+            raise VoilaError(VOILA_ERR_INVALID_ARG, "src must have N rows")
+        rf = int(src.numel() // N)
+        dst = dst if dst is not None else torch.empty_like(src)
+    ws = workspace if workspace is not None else weights_workspace(N, d)
+    _check(lib.voila_reweight_resample(_ptr(loglik), _ptr(prior_w), N, float(lam), int(U) & 0xFFFFFFFF, _ptr(idx),
+                                       _ptr(w), _ptr(stats), _ptr(src), _ptr(dst), rf, _ptr(status), _ptr(ws),
+                                       0 if ws is None else ws.numel(), _stream(stream)))
+    return {"idx": idx, "w": w, "stats": stats, "dst": dst}
 
 
 def observe(model: Model, states, action, seed=0, noise=None, workspace=None, out=None, stream=None):

@@ -119,26 +119,28 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
         }
     };
     auto hidden_in = [](int ri, int g) { return 32 * (ri / 16) + out_row(ri % 16, g); };
+    // every fragment goes to its position in the consumption order (FragLayout)
+    const FragLayout lay{HT, IN_KS, HID_KS, chunk_tiles(W), NHID};
     for (int c = 0; c < IN_KS; ++c)
         for (int t = 0; t < HT; ++t)
             for (int lane = 0; lane < 64; ++lane)
                 for (int j = 0; j < KP; ++j) {
                     int col = map(c * KP + j, lane / 32);
-                    put(off_f0, (size_t)c * HT + t, lane, j, col >= 0 ? n.w(0, 32 * t + lane % 32, col) : 0.0f);
+                    put(off_f0, lay.first(c, t), lane, j, col >= 0 ? n.w(0, 32 * t + lane % 32, col) : 0.0f);
                 }
     for (int l = 1; l <= NHID - 1; ++l)
         for (int c = 0; c < HID_KS; ++c)
             for (int t = 0; t < HT; ++t)
                 for (int lane = 0; lane < 64; ++lane)
                     for (int j = 0; j < KP; ++j)
-                        put(off_fh + (size_t)(l - 1) * nfh * fb, (size_t)c * HT + t, lane, j,
+                        put(off_f0, lay.hidden(l, c, t), lane, j,
                             n.w(l, 32 * t + lane % 32, hidden_in(c * KP + j, lane / 32)));
     const int L = NHID;
     for (int c = 0; c < HID_KS; ++c)
         for (int lane = 0; lane < 64; ++lane)
             for (int j = 0; j < KP; ++j) {
                 int f = row_feature(lane % 32);
-                put(off_fo, c, lane, j, f < n.out() ? n.w(L, f, hidden_in(c * KP + j, lane / 32)) : 0.0f);
+                put(off_f0, lay.out(c), lane, j, f < n.out() ? n.w(L, f, hidden_in(c * KP + j, lane / 32)) : 0.0f);
             }
     std::memcpy(blob.data() + off_b0, b0_variants.data(), (size_t)n_var * W * 4);
     for (int l = 1; l <= NHID - 1; ++l) std::memcpy(blob.data() + off_bh + (size_t)(l - 1) * W * 4, n.b[l], (size_t)W * 4);
@@ -322,6 +324,8 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
         }
     }
     if (shape < 0) return fail(VOILA_ERR_UNSUPPORTED, "no compiled kernel for this network shape");
+    if (T.width() > 256 && desc->compute != VOILA_BF16)
+        return fail(VOILA_ERR_UNSUPPORTED, "hidden widths above 256 run in bfloat16 only");
 
     int ndev = 0;
     VOILA_CHECK_HIP(hipGetDeviceCount(&ndev));
@@ -766,6 +770,58 @@ voila_status_t voila_resample(const double* d_w, int32_t N, uint32_t U, int32_t*
     r.bits = voila_resample_bits(N);
     r.do_resample = 1;
     r.U = U;
+    r.idx_out = d_idx_out;
+    r.src = d_src;
+    r.dst = d_dst;
+    r.row_floats = row_floats;
+    r.status = d_status;
+    VOILA_CHECK_HIP(launch_norm_res(r, reinterpret_cast<hipStream_t>(stream)));
+    return VOILA_OK;
+}
+
+voila_status_t voila_reweight_resample(const float* d_loglik, const double* d_prior_w, int32_t N, double lambda,
+                                       uint32_t U, int32_t* d_idx_out, double* d_w_out, double* d_stats_out,
+                                       const float* d_src, float* d_dst, int32_t row_floats, int32_t* d_status,
+                                       void* ws, size_t ws_bytes, void* stream) {
+    if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
+    if (N > kLargeMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(VOILA_ERR_INVALID_ARG, "lambda must be > 0");
+    if (!d_loglik || !d_idx_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    if ((d_src != nullptr) != (d_dst != nullptr)) return fail(VOILA_ERR_INVALID_ARG, "give both or neither of src and dst");
+    if (d_src && row_floats < 1) return fail(VOILA_ERR_INVALID_ARG, "row_floats must be >= 1");
+    if (N > kNormResMaxN) {
+        if (!ws || ws_bytes < voila_weights_workspace_size(N)) return fail(VOILA_ERR_WORKSPACE, "workspace too small");
+        LargeResParams r{};
+        r.loglik = d_loglik;
+        r.prior_w = d_prior_w;
+        r.lambda = lambda;
+        r.N = N;
+        r.bits = voila_resample_bits(N);
+        r.uniform_prior = d_prior_w ? 0 : 1;
+        r.do_resample = 1;
+        r.U = U;
+        r.w_out = d_w_out;
+        r.stats = d_stats_out;
+        r.idx_out = d_idx_out;
+        r.src = d_src;
+        r.dst = d_dst;
+        r.row_floats = row_floats;
+        r.status = d_status;
+        r.ws = carve_large_res(ws, N);
+        VOILA_CHECK_HIP(launch_large_res(r, reinterpret_cast<hipStream_t>(stream)));
+        return VOILA_OK;
+    }
+    NormResParams r{};
+    r.loglik = d_loglik;
+    r.prior_w = d_prior_w;
+    r.lambda = lambda;
+    r.N = N;
+    r.bits = voila_resample_bits(N);
+    r.uniform_prior = d_prior_w ? 0 : 1;
+    r.do_resample = 1;
+    r.U = U;
+    r.w_out = d_w_out;
+    r.stats = d_stats_out;
     r.idx_out = d_idx_out;
     r.src = d_src;
     r.dst = d_dst;

@@ -26,6 +26,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
 #include <stdint.h>
 
 namespace voila {
@@ -39,6 +42,16 @@ constexpr int DT_BF16 = 1;
 
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int rup(int a, int b) { return cdiv(a, b) * b; }
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1 (compile-time indices).
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 __host__ __device__ constexpr int out_row(int i, int g) { return (i >> 2) * 8 + g * 4 + (i & 3); }
 __host__ __device__ constexpr int kper(int dt) { return dt == DT_F32 ? 1 : 8; }
 
@@ -49,6 +62,27 @@ __host__ __device__ constexpr int noise_slots(int d_w) { return 2 * cdiv(d_w, 4)
 __host__ __device__ constexpr int in_slots(int dt, int d_s, int d_ain, int d_w) {
     return rup(state_slots(d_s) + action_slots(d_ain) + noise_slots(d_w), kper(dt));
 }
+
+// Position of every weight fragment in the packed stream of a network
+// (fragment (k-step c, 32-row tile t)), in the order the kernels consume them:
+// first layer [c][t], each hidden->hidden layer [c][t], output layer [c].
+// Wider networks (two hidden layers) hold only the first hidden layer's
+// activations in registers and produce the second in groups of `ct` tiles, so
+// their hidden->hidden fragments are stored group by group: [t / ct][c][t % ct].
+struct FragLayout {
+    int ht, in_ks, hid_ks, ct, nhid;
+    __host__ __device__ constexpr bool grouped() const { return ct < ht; }
+    __host__ __device__ constexpr int nf0() const { return in_ks * ht; }
+    __host__ __device__ constexpr int first(int c, int t) const { return c * ht + t; }
+    __host__ __device__ constexpr int hidden(int l, int c, int t) const {
+        return grouped() ? nf0() + (t / ct) * hid_ks * ct + c * ct + t % ct
+                         : nf0() + (l - 1) * hid_ks * ht + c * ht + t;
+    }
+    __host__ __device__ constexpr int out(int c) const { return nf0() + (nhid - 1) * hid_ks * ht + c; }
+};
+
+// Output tiles produced per group by the grouped evaluation of wide networks.
+__host__ __device__ constexpr int chunk_tiles(int width) { return width > 256 ? 4 : width / 32; }
 
 // Compile-time shape of one network as the engine runs it.
 template <int DT_, int WIDTH_, int NHID_, int IN_SLOTS_>
@@ -65,7 +99,11 @@ struct Net {
     static constexpr int NF0 = IN_KS * HT;         // first-layer fragments
     static constexpr int NFH = HID_KS * HT;        // fragments per hidden->hidden layer
     static constexpr int NFO = HID_KS;             // output-layer fragments
+    static constexpr int CT = chunk_tiles(WIDTH);  // tiles per group of the grouped evaluation
+    static constexpr int OKS = HID_KS / HT;        // output k-steps per hidden tile
+    static constexpr FragLayout LAYOUT{HT, IN_KS, HID_KS, CT, NHID};
     static_assert(WIDTH % 32 == 0 && NHID >= 1 && IN_SLOTS % KPER == 0, "bad net shape");
+    static_assert(CT == HT || (NHID == 2 && HT % CT == 0), "grouped evaluation needs two hidden layers");
 };
 
 // Device view of one packed network (all pointers into global memory or LDS).
@@ -147,6 +185,13 @@ template <int HT> struct Act<DT_F32, HT> {
 #pragma unroll
             for (int i = 0; i < 16; ++i) v[t][i] = fmaxf(acc[t][i], 0.0f);
     }
+    template <int CT>
+    __device__ __forceinline__ void set_relu_at(const f32x16 (&acc)[CT], int t0) {
+#pragma unroll
+        for (int t = 0; t < CT; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[t0 + t][i] = fmaxf(acc[t][i], 0.0f);
+    }
     __device__ __forceinline__ float b(int c) const { return v[c >> 4][c & 15]; }
 };
 template <int HT> struct Act<DT_BF16, HT> {
@@ -156,6 +201,13 @@ template <int HT> struct Act<DT_BF16, HT> {
         for (int t = 0; t < HT; ++t)
 #pragma unroll
             for (int i = 0; i < 16; ++i) v[2 * t + (i >> 3)][i & 7] = (__bf16)fmaxf(acc[t][i], 0.0f);
+    }
+    template <int CT>
+    __device__ __forceinline__ void set_relu_at(const f32x16 (&acc)[CT], int t0) {
+#pragma unroll
+        for (int t = 0; t < CT; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[2 * (t0 + t) + (i >> 3)][i & 7] = (__bf16)fmaxf(acc[t][i], 0.0f);
     }
     __device__ __forceinline__ bf16x8 b(int c) const { return v[c]; }
 };
@@ -252,10 +304,14 @@ struct StreamSrc {
 
 // Fragment index of (k-step c, tile t) in each layer of the packed stream.
 template <class N> struct FragIdx {
-    __device__ static constexpr int first(int c, int t) { return c * N::HT + t; }
-    __device__ static constexpr int hidden(int l, int c, int t) { return N::NF0 + (l - 1) * N::NFH + c * N::HT + t; }
-    __device__ static constexpr int out(int c) { return N::NF0 + (N::NHID - 1) * N::NFH + c; }
+    __device__ static constexpr int first(int c, int t) { return N::LAYOUT.first(c, t); }
+    __device__ static constexpr int hidden(int l, int c, int t) { return N::LAYOUT.hidden(l, c, t); }
+    __device__ static constexpr int out(int c) { return N::LAYOUT.out(c); }
 };
+
+template <class N, class Src>
+__device__ __forceinline__ f32x16 run_net_grouped(Src& src, const NetPtrs& P, const float* b0,
+                                                  const float (&slots)[N::IN_SLOTS], int lane, int g);
 
 // Runs one network on the 32 columns of a wave.  `slots` is the first-layer
 // input of this lane, `b0` the first-layer bias (row order, possibly with an
@@ -263,6 +319,9 @@ template <class N> struct FragIdx {
 template <class N, class Src>
 __device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const float* b0,
                                           const float (&slots)[N::IN_SLOTS], int lane, int g) {
+    if constexpr (N::CT < N::HT) {
+        return run_net_grouped<N>(src, P, b0, slots, lane, g);
+    } else {
     typedef FragIdx<N> FI;
     f32x16 acc[N::HT];
     Act<N::DT, N::HT> act;
@@ -290,7 +349,143 @@ __device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const floa
 #pragma unroll
     for (int c = 0; c < N::HID_KS; ++c) out[0] = mfma(src.load(FI::out(c), lane), act.b(c), out[0]);
     return out[0];
+    }
 }
+
+// Wide two-hidden-layer networks.  The first hidden layer's activations (the
+// B operands of the second layer) stay in registers; the second hidden layer
+// is produced CT tiles at a time, and each finished group is multiplied into
+// the output layer at once, so only CT accumulator tiles of it are live.
+//
+// Fragment sources of the grouped evaluation: `first` reads the first layer,
+// `hid` the hidden->hidden fragments of one group at compile-time positions
+// after begin_group(gi), `out` points at the output-layer fragments.
+// A window of WINF fragments shares one opaque base address, which bounds how
+// many weight loads the compiler can issue ahead (and keeps them in the loop).
+template <class N, int WINF = 8>
+struct GroupDirect {  // hidden fragments straight from global memory (L2)
+    static constexpr int GF = N::HID_KS * N::CT;  // fragments per group
+    const char* base;
+    const char* grp;
+    const char* win;
+    __device__ __forceinline__ explicit GroupDirect(const char* b) : base(b), grp(b), win(b) {}
+    __device__ __forceinline__ void begin_group(int gi) { grp = base + (size_t)gi * GF * N::FRAG_BYTES; }
+    template <int POS>
+    __device__ __forceinline__ typename Frag<N::DT>::type load(int lane) {
+        if constexpr (POS % WINF == 0) win = grp + POS * N::FRAG_BYTES + opaque_zero();
+        return Frag<N::DT>::load(win, POS % WINF, lane);
+    }
+    __device__ __forceinline__ void start() {}
+    __device__ __forceinline__ void finish() {}
+};
+
+// Hidden fragments streamed through two LDS chunk buffers shared by the
+// workgroup (same protocol as StreamSrc); a group is a whole number of chunks,
+// so every chunk boundary sits at a compile-time position of the group.
+template <class N, int CHB = 32768, int WINF = 8>
+struct GroupStream {
+    static constexpr int FB = N::FRAG_BYTES;
+    static constexpr int FPC = CHB / FB;
+    static constexpr int GF = N::HID_KS * N::CT;
+    static constexpr int CPG = GF / FPC;                // chunks per group
+    static constexpr int NCH = (N::HT / N::CT) * CPG;   // chunks per network evaluation
+    static_assert(GF % FPC == 0 && CHB % 4096 == 0, "a group must be whole chunks of whole DMA rounds");
+    char* lds;
+    const char* src;
+    int cur, gch;
+    const char* win;
+    __device__ __forceinline__ GroupStream(char* l, const char* s) : lds(l), src(s), cur(1), gch(0), win(l) {}
+    __device__ __forceinline__ void fetch(int ch, int b) const {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
+        const int lane = threadIdx.x & 63;
+        const char* base = src + opaque_zero() + (size_t)ch * CHB;
+        for (int off = wave * 1024; off < CHB; off += nw * 1024)
+            __builtin_amdgcn_global_load_lds((const void*)(base + off + lane * 16),
+                                             (__attribute__((address_space(3))) void*)(lds + b * CHB + off), 16, 0,
+                                             0);
+    }
+    __device__ __forceinline__ void start() { fetch(0, 0); }
+    __device__ __forceinline__ void begin_group(int gi) { gch = gi * CPG; }
+    template <int POS>
+    __device__ __forceinline__ typename Frag<N::DT>::type load(int lane) {
+        constexpr int within = POS % FPC;
+        if constexpr (within == 0) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            cur ^= 1;
+            const int nxt = gch + POS / FPC + 1;
+            fetch(nxt < NCH ? nxt : 0, cur ^ 1);
+        }
+        if constexpr (within % WINF == 0) win = lds + cur * CHB + within * FB + opaque_zero();
+        return Frag<N::DT>::load(win, within % WINF, lane);
+    }
+    __device__ __forceinline__ void finish() { __builtin_amdgcn_s_waitcnt(0); }
+};
+
+template <class N, class HS>
+struct WideSrc {
+    DirectSrc<N::DT, 8> first;
+    HS hid;
+    const char* out;
+    __device__ __forceinline__ WideSrc(const char* f0, HS h, const char* fo) : first(f0), hid(h), out(fo) {}
+};
+
+template <class N, class Src>
+__device__ __forceinline__ f32x16 run_net_grouped(Src& src, const NetPtrs& P, const float* b0,
+                                                  const float (&slots)[N::IN_SLOTS], int lane, int g) {
+    typedef FragIdx<N> FI;
+    constexpr int CT = N::CT, OKS = N::OKS;
+    Act<N::DT, N::HT> act;
+    static_for<N::HT / CT>([&](auto gi) {
+        constexpr int tc = decltype(gi)::value * CT;
+        f32x16 acc[CT];
+        init_bias<CT>(acc, b0 + 32 * tc + opaque_zero(), g);
+        static_for<N::IN_KS>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            auto b = Slots<N::DT, N::IN_SLOTS>::b(slots, c);
+#pragma unroll
+            for (int t = 0; t < CT; ++t) acc[t] = mfma(src.first.load(FI::first(c, tc + t), lane), b, acc[t]);
+        });
+        act.template set_relu_at<CT>(acc, tc);
+    });
+    f32x16 out[1];
+    init_bias<1>(out, P.bo + opaque_zero(), g);
+#pragma unroll 1
+    for (int gi = 0; gi < N::HT / CT; ++gi) {
+        src.hid.begin_group(gi);
+        f32x16 acc[CT];
+        init_bias<CT>(acc, P.bh + 32 * CT * gi + opaque_zero(), g);
+        static_for<N::HID_KS>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            auto b = act.b(c);
+            static_for<CT>([&](auto ti) {
+                constexpr int t = decltype(ti)::value;
+                acc[t] = mfma(src.hid.template load<c * CT + t>(lane), b, acc[t]);
+            });
+        });
+        Act<N::DT, CT> a2;
+        a2.set_relu(acc);
+        const char* ob = src.out + (size_t)gi * OKS * CT * N::FRAG_BYTES + opaque_zero();
+#pragma unroll
+        for (int c = 0; c < OKS * CT; ++c) out[0] = mfma(Frag<N::DT>::load(ob, c, lane), a2.b(c), out[0]);
+    }
+    return out[0];
+}
+
+// Fragment source of a network read straight from global memory: the plain
+// source for networks evaluated layer by layer, the grouped bundle otherwise.
+template <class N, bool GROUPED = (N::CT < N::HT)> struct DirectFor;
+template <class N> struct DirectFor<N, false> {
+    typedef DirectSrc<N::DT, 4 * N::HT> type;
+    __device__ static __forceinline__ type make(const NetPtrs& P) { return type(P.f0); }
+};
+template <class N> struct DirectFor<N, true> {
+    typedef WideSrc<N, GroupDirect<N>> type;
+    __device__ static __forceinline__ type make(const NetPtrs& P) {
+        return type(P.f0, GroupDirect<N>(P.fh), P.fo);
+    }
+};
 
 // ----------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller draws.

@@ -48,6 +48,10 @@ const ShapeInfo& shape_info(int shape) { return kShapeInfo[shape]; }
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
+// Binary32 activations of a network wider than 256 do not fit in registers:
+// such networks run in bfloat16 only.
+constexpr bool net_compiled(int dt, int width) { return dt == DT_BF16 || width <= 256; }
+
 // How a kernel reads the weight fragments of a network.
 constexpr int kDirect = 0;    // straight from global memory (L2)
 constexpr int kResident = 1;  // whole network staged in LDS once per block
@@ -127,6 +131,9 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
 
 template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
+    if constexpr (!net_compiled(DT, WIDTH)) {
+        return;  // binary32 networks wider than 256 are refused at model creation
+    } else {
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     if (MODE == kResident) {
@@ -145,7 +152,18 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
             plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, u, u < n_units, lane, g, col);
         }
     };
-    if constexpr (MODE == kStream) {
+    if constexpr (MODE == kStream && NT::CT < NT::HT) {
+        // grouped wide network: hidden fragments stream through two 32 KB LDS
+        // buffers, the output layer is staged after them once per block, the
+        // first layer is read from L2
+        char* out_lds = smem + 2 * 32768;
+        stage_blob(out_lds, P.fo, (uint32_t)(p.net.off_b0 - p.net.off_fo));
+        __syncthreads();
+        WideSrc<NT, GroupStream<NT>> src(P.f0, GroupStream<NT>(smem, P.fh), out_lds);
+        src.hid.start();
+        body(src);
+        src.hid.finish();
+    } else if constexpr (MODE == kStream) {
         StreamSrc<NT> src(smem, P.f0);
         src.start();
         body(src);
@@ -153,6 +171,7 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
     } else {
         DirectSrc<DT, 8 * NT::HT> src(P.f0);
         body(src);
+    }
     }
 }
 
@@ -305,7 +324,7 @@ __device__ __forceinline__ void propose_tile(const NetPtrs& PT, const NetPtrs& P
 #pragma unroll
         for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
     }
-    DirectSrc<DT, 4 * NTT::HT> srct(PT.f0);
+    auto srct = DirectFor<NTT>::make(PT);
     f32x16 d = run_net<NTT>(srct, PT, p.b0_trans, slots, lane, g);
     float ls[NTL::IN_SLOTS];
 #pragma unroll
@@ -317,7 +336,7 @@ __device__ __forceinline__ void propose_tile(const NetPtrs& PT, const NetPtrs& P
         ls[s] = st[s];
         if (valid && f < D_S) p.prop[(size_t)i * D_S + f] = st[s];
     }
-    DirectSrc<DT, 4 * NTL::HT> srcl(PL.f0);
+    auto srcl = DirectFor<NTL>::make(PL);
     f32x16 lo = run_net<NTL>(srcl, PL, p.b0_lik, ls, lane, g);
     if (g == 0 && valid) {
         float l = lo[0];
@@ -331,6 +350,9 @@ __device__ __forceinline__ void propose_tile(const NetPtrs& PT, const NetPtrs& P
 
 template <int DT, int D_S, int D_W, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
+    if constexpr (!net_compiled(DT, WIDTH)) {
+        return;  // binary32 networks wider than 256 are refused at model creation
+    } else {
     constexpr bool WLDS = MODE == kResident;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     if (WLDS) {
@@ -345,6 +367,7 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
     const int n_tiles = (p.N + 31) / 32;
     for (int tile = blockIdx.x * wpb + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * wpb)
         propose_tile<DT, D_S, D_W, WIDTH, NHID>(PT, PL, p, tile, true, lane, g, col);
+    }
 }
 
 // Update stage 1 of many instances: block items (instance, first tile, tiles),
@@ -392,6 +415,9 @@ __global__ __launch_bounds__(512) void propose_batch_kernel(BatchProposeParams b
 // ---------------------------------------------------------------------------
 template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
+    if constexpr (!net_compiled(DT, WIDTH)) {
+        return;  // binary32 networks wider than 256 are refused at model creation
+    } else {
     constexpr bool WLDS = MODE == kResident;
     constexpr int SS = state_slots(D_S), SW = noise_slots(D_WZ);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ)> NTO;
@@ -427,13 +453,14 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
 #pragma unroll
             for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
         }
-        DirectSrc<DT, 4 * NTO::HT> srco(PO.f0);
+        auto srco = DirectFor<NTO>::make(PO);
         f32x16 o = run_net<NTO>(srco, PO, p.b0, slots, lane, g);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             int f = 2 * s + g;
             if (valid && f < D_O) p.out[(size_t)r * D_O + f] = o[s];
         }
+    }
     }
 }
 
@@ -678,13 +705,17 @@ VOILA_IN_SLOTS(lik_in_slots, in_slots(dt, s.d_s, 0, 0))
 #define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, pass_mode<w>()>
 
 hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s) {
-    const size_t lds = weights_in_lds(shape) ? p.net.bytes : kStreamLds;
+    size_t lds = weights_in_lds(shape) ? p.net.bytes : kStreamLds;
+    if (kShapeInfo[shape].width > 256) lds += p.net.off_b0 - p.net.off_fo;  // staged output layer
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
     case id * 2 + 0:                                                                                       \
         hipLaunchKernelGGL((PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);  \
         break;                                                                                             \
     case id * 2 + 1:                                                                                       \
+        if (lds > 65536)                                                                                   \
+            (void)hipFuncSetAttribute((const void*)PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),    \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
         hipLaunchKernelGGL((PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p); \
         break;
         VOILA_SHAPES(X)

@@ -13,9 +13,10 @@ namespace voila {
 #define VOILA_SHAPES(X)                                 \
     X(0, 4, 5, 0, 4, 2, 2, 64, 2)     /* small */        \
     X(1, 16, 0, 4, 16, 32, 32, 256, 3) /* realistic */    \
-    X(2, 4, 0, 4, 4, 2, 2, 64, 2)      /* small, continuous actions */
+    X(2, 4, 0, 4, 4, 2, 2, 64, 2)      /* small, continuous actions */ \
+    X(3, 4, 5, 0, 4, 2, 2, 1024, 2)    /* small, hidden width 1024 */
 
-constexpr int kNumShapes = 3;
+constexpr int kNumShapes = 4;
 
 struct ShapeInfo {
     int d_s, n_actions, d_a, d_w, d_o, d_wz, width, n_hidden;
@@ -173,6 +174,7 @@ struct LargeResWs {
     double* cloc;    // [N] chunk-relative inclusive prefix of quantised weights
     double* scal;    // [0] max, [1] sum
     int* last;       // last positive-mass particle overall
+    int* starts;     // [chunks + 1] particle of the first output of each output block
 };
 
 struct LargeResParams {

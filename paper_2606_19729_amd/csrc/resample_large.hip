@@ -1,22 +1,26 @@
 // resample_large.hip -- weight normalisation and systematic resampling for
 // beliefs larger than one workgroup can hold (N > 8192), streamed through HBM.
 //
-// Chunks of 4096 particles (256 threads x 16 consecutive particles):
-//   pass 1  per-chunk max of x_i = l_i / lambda (+ log w_i)            -> bmax
-//   red 1   m = max over chunks (one workgroup, fixed order)
-//   pass 2  per-chunk sum of exp(x_i - m) (thread order, then tree)     -> bsum
-//   red 2   S = sum over chunks in chunk order
-//   pass 3  w_i = exp(x_i - m) / S (or given weights), q_i = rint(w_i N 2^b),
-//           chunk-relative inclusive prefix C_i (exact integers), chunk
-//           total, sum of w_i^2, last positive-mass particle
-//   red 3   exclusive scan of the chunk totals (exact), statistics
-//   pass 4  per output j: P_j = j 2^b + u, first chunk whose inclusive
-//           prefix exceeds P_j (binary search over chunks), then first
-//           particle of that chunk with C_i > P_j - offset (binary search),
-//           gather of the particle's row.
-// Every prefix is an integer below 2^53, so the blocked scan gives the same
-// bits as a sequential one and the indices equal those of the one-workgroup
-// kernel and of the definition.
+// Chunks of 4096 particles, 256 threads; thread t touches particles
+// chunk_base + 256 k + t (k < 16), so every global access is coalesced.
+//   pass 1  per-chunk (max, sum exp(x - max)) of x_i = l_i / lambda (+ log w_i),
+//           accumulated online (the running sum is rescaled when the running
+//           max grows), in a fixed order                        -> bmax, bsum
+//   red 1   m = max over chunks, S = sum_c bsum_c exp(bmax_c - m) in chunk order
+//   pass 2  w_i = exp(x_i - m) / S (or given weights), q_i = rint(w_i N 2^b);
+//           the chunk-relative inclusive prefix C_i is formed in LDS (each
+//           thread scans 16 consecutive entries, then the thread totals are
+//           scanned); chunk total, sum of w_i^2, last positive particle
+//   red 2   exclusive scan of the chunk totals, statistics
+//   starts  per block of 4096 outputs, the particle of its first output
+//           (global two-level search, one thread per block)
+//   pass 3  one workgroup per 4096 consecutive outputs j: the particle range
+//           [start of this block, start of the next] bounds its indices; when
+//           it fits in LDS its global prefixes are staged there and every
+//           output searches LDS (otherwise it searches global memory), then
+//           the workgroup gathers the selected rows with coalesced accesses.
+// Every prefix is an integer below 2^53, so the blocked sums give the same
+// bits as a sequential sum and the indices equal those of the definition.
 #include "kernels.hpp"
 
 #include <math.h>
@@ -28,6 +32,7 @@ namespace {
 constexpr int kLgThreads = 256;
 constexpr int kLgItems = 16;
 constexpr int kLgChunk = kLgThreads * kLgItems;
+constexpr int kStageMax = 6144;  // particles of a search range staged in LDS
 
 __device__ __forceinline__ double lg_x(const LargeResParams& p, int i, int& bad) {
     if (p.x) {
@@ -42,21 +47,34 @@ __device__ __forceinline__ double lg_x(const LargeResParams& p, int i, int& bad)
     return x;
 }
 
-__device__ double blk_reduce(double v, double* red, bool is_max) {
-    for (int m = 32; m >= 1; m >>= 1) {
-        double o = __shfl_xor(v, m);
-        v = is_max ? fmax(v, o) : v + o;
+// (m, s) <- (m, s) combined with (m2, s2), where s = sum exp(x - m).
+__device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
+    if (m2 == -INFINITY) return;
+    if (m == -INFINITY) {
+        m = m2;
+        s = s2;
+        return;
     }
+    if (m2 > m) {
+        s = s * exp(m - m2) + s2;
+        m = m2;
+    } else {
+        s += s2 * exp(m2 - m);
+    }
+}
+
+__device__ double blk_sum(double v, double* red) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    double r = is_max ? -INFINITY : 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = is_max ? fmax(r, red[w]) : r + red[w];
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[w];
     return r;
 }
 
 __device__ int blk_max_i(int v, int* red) {
-    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m));
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d));
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -65,66 +83,96 @@ __device__ int blk_max_i(int v, int* red) {
     return r;
 }
 
+// Global prefix of particle i (exact integer).
+__device__ __forceinline__ double gprefix(const LargeResParams& p, int i) {
+    return p.ws.boff[i / kLgChunk] + p.ws.cloc[i];
+}
+
+// First particle with prefix > P (global memory), or `last` if none.
+__device__ int global_search(const LargeResParams& p, double P, int last) {
+    int a = 0, b = p.n_chunks;
+    while (a < b) {
+        int mid = (a + b) >> 1;
+        if (p.ws.bincl[mid] > P) b = mid;
+        else a = mid + 1;
+    }
+    if (a >= p.n_chunks) return last;
+    const double rel = P - p.ws.boff[a];
+    int lo = a * kLgChunk, hi = min(p.N, lo + kLgChunk);
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (p.ws.cloc[mid] > rel) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
 }  // namespace
 
-__global__ __launch_bounds__(kLgThreads) void lg_max_kernel(LargeResParams p) {
-    __shared__ double red[kLgThreads / 64];
+__global__ __launch_bounds__(kLgThreads) void lg_lse_kernel(LargeResParams p) {
+    __shared__ double rm[kLgThreads], rs[kLgThreads];
     __shared__ int redi[kLgThreads / 64];
-    const int base = blockIdx.x * kLgChunk + threadIdx.x * kLgItems;
-    double mx = -INFINITY;
+    const int base = blockIdx.x * kLgChunk + threadIdx.x;
+    double m = -INFINITY, s = 0.0;
     int bad = 0;
-    for (int k = 0; k < kLgItems; ++k)
-        if (base + k < p.N) mx = fmax(mx, lg_x(p, base + k, bad));
-    mx = blk_reduce(mx, red, true);
+    for (int k = 0; k < kLgItems; ++k) {
+        const int i = base + k * kLgThreads;
+        if (i < p.N) lse_merge(m, s, lg_x(p, i, bad), 1.0);
+    }
+    rm[threadIdx.x] = m;
+    rs[threadIdx.x] = s;
     bad = blk_max_i(bad, redi);
+    // fixed-shape tree: thread t merges t + h into t for h = 128, 64, ..., 1
+    for (int h = kLgThreads / 2; h >= 1; h >>= 1) {
+        __syncthreads();
+        if (threadIdx.x < h) {
+            double mm = rm[threadIdx.x], ss = rs[threadIdx.x];
+            lse_merge(mm, ss, rm[threadIdx.x + h], rs[threadIdx.x + h]);
+            rm[threadIdx.x] = mm;
+            rs[threadIdx.x] = ss;
+        }
+    }
     if (threadIdx.x == 0) {
-        p.ws.bmax[blockIdx.x] = mx;
+        p.ws.bmax[blockIdx.x] = rm[0];
+        p.ws.bsum[blockIdx.x] = rs[0];
         if (bad && p.status) p.status[0] = 5;
     }
 }
 
-__global__ __launch_bounds__(kLgThreads) void lg_reduce_max_kernel(LargeResParams p) {
-    __shared__ double red[kLgThreads / 64];
-    double mx = -INFINITY;
-    for (int c = threadIdx.x; c < p.n_chunks; c += blockDim.x) mx = fmax(mx, p.ws.bmax[c]);
-    mx = blk_reduce(mx, red, true);
+__global__ __launch_bounds__(kLgThreads) void lg_lse_reduce_kernel(LargeResParams p) {
+    __shared__ double rm[kLgThreads], rs[kLgThreads];
+    double m = -INFINITY, s = 0.0;
+    for (int c = threadIdx.x; c < p.n_chunks; c += kLgThreads) lse_merge(m, s, p.ws.bmax[c], p.ws.bsum[c]);
+    rm[threadIdx.x] = m;
+    rs[threadIdx.x] = s;
+    for (int h = kLgThreads / 2; h >= 1; h >>= 1) {
+        __syncthreads();
+        if (threadIdx.x < h) {
+            double mm = rm[threadIdx.x], ss = rs[threadIdx.x];
+            lse_merge(mm, ss, rm[threadIdx.x + h], rs[threadIdx.x + h]);
+            rm[threadIdx.x] = mm;
+            rs[threadIdx.x] = ss;
+        }
+    }
     if (threadIdx.x == 0) {
-        p.ws.scal[0] = mx;
-        if (!isfinite(mx) && p.status) p.status[0] = 5;
+        p.ws.scal[0] = rm[0];
+        p.ws.scal[1] = rs[0];
+        if (!isfinite(rm[0]) && p.status) p.status[0] = 5;
     }
 }
 
-__global__ __launch_bounds__(kLgThreads) void lg_sum_kernel(LargeResParams p) {
-    __shared__ double red[kLgThreads / 64];
-    const double m = p.ws.scal[0];
-    const int base = blockIdx.x * kLgChunk + threadIdx.x * kLgItems;
-    double s = 0.0;
-    int bad = 0;
-    for (int k = 0; k < kLgItems; ++k)
-        if (base + k < p.N) s += exp(lg_x(p, base + k, bad) - m);
-    s = blk_reduce(s, red, false);
-    if (threadIdx.x == 0) p.ws.bsum[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(64) void lg_reduce_sum_kernel(LargeResParams p) {
-    if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int c = 0; c < p.n_chunks; ++c) s += p.ws.bsum[c];
-    p.ws.scal[1] = s;
-}
-
 __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) {
+    __shared__ double q[kLgChunk];
     __shared__ double red[kLgThreads / 64];
     __shared__ int redi[kLgThreads / 64];
     __shared__ double tot[kLgThreads / 64];
-    const int base = blockIdx.x * kLgChunk + threadIdx.x * kLgItems;
+    const int cbase = blockIdx.x * kLgChunk;
     const double m = p.ws.scal[0], S = p.ws.scal[1];
     const double scale = ldexp((double)p.N, p.bits);
-    double q[kLgItems];
-    double sq = 0.0, run = 0.0;
+    double sq = 0.0;
     int last = -1, bad = 0;
     for (int k = 0; k < kLgItems; ++k) {
-        const int i = base + k;
+        const int r = k * kLgThreads + threadIdx.x, i = cbase + r;
         double w = 0.0;
         if (i < p.N) {
             if (p.w_in) {
@@ -136,12 +184,17 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
             }
         }
         sq += w * w;
-        q[k] = rint(w * scale);
-        if (q[k] > 0.0) last = i;
-        run += q[k];
-        q[k] = run;
+        const double qi = rint(w * scale);
+        if (qi > 0.0) last = i;
+        q[r] = qi;
     }
-    // chunk-level exclusive scan of the thread totals (exact integers)
+    __syncthreads();
+    // chunk-relative inclusive prefix: 16 consecutive entries per thread, then the thread totals
+    double run = 0.0;
+    for (int k = 0; k < kLgItems; ++k) {
+        run += q[threadIdx.x * kLgItems + k];
+        q[threadIdx.x * kLgItems + k] = run;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double incl = run;
     for (int d = 1; d < 64; d <<= 1) {
@@ -152,12 +205,16 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
     __syncthreads();
     double off = incl - run;
     for (int w2 = 0; w2 < wave; ++w2) off += tot[w2];
-    if (p.do_resample)
-        for (int k = 0; k < kLgItems; ++k)
-            if (base + k < p.N) p.ws.cloc[base + k] = q[k] + off;
+    for (int k = 0; k < kLgItems; ++k) q[threadIdx.x * kLgItems + k] += off;
     double total = 0.0;
-    for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) total += tot[w2];
-    sq = blk_reduce(sq, red, false);
+    for (int w2 = 0; w2 < kLgThreads / 64; ++w2) total += tot[w2];
+    __syncthreads();
+    if (p.do_resample)
+        for (int k = 0; k < kLgItems; ++k) {
+            const int r = k * kLgThreads + threadIdx.x;
+            if (cbase + r < p.N) p.ws.cloc[cbase + r] = q[r];
+        }
+    sq = blk_sum(sq, red);
     last = blk_max_i(last, redi);
     bad = blk_max_i(bad, redi);
     if (threadIdx.x == 0) {
@@ -198,7 +255,7 @@ __global__ __launch_bounds__(1024) void lg_scan_kernel(LargeResParams p) {
         off += p.ws.btot[c];
         p.ws.bincl[c] = off;
     }
-    sq = blk_reduce(sq, red, false);
+    sq = blk_sum(sq, red);
     last = blk_max_i(last, redi);
     if (threadIdx.x == 0) {
         p.ws.last[0] = last;
@@ -211,38 +268,68 @@ __global__ __launch_bounds__(1024) void lg_scan_kernel(LargeResParams p) {
     }
 }
 
-__global__ __launch_bounds__(256) void lg_search_kernel(LargeResParams p) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= p.N) return;
+// Particle index of the first output of every block of 4096 outputs (and
+// `last` after the final block): the search range of each output block.
+__global__ __launch_bounds__(256) void lg_starts_kernel(LargeResParams p) {
+    const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blk > p.n_chunks) return;
+    const int last = p.ws.last[0];
+    if (last < 0) return;
+    if (blk == p.n_chunks) {
+        p.ws.starts[blk] = last;
+        return;
+    }
+    const double step = ldexp(1.0, p.bits), u = (double)(p.U >> (32 - p.bits));
+    p.ws.starts[blk] = global_search(p, (double)blk * kLgChunk * step + u, last);
+}
+
+__global__ __launch_bounds__(kLgThreads) void lg_search_kernel(LargeResParams p) {
+    __shared__ double cs[kStageMax];
+    __shared__ int ids[kLgChunk];
     const int last = p.ws.last[0];
     if (last < 0) return;  // no particle has mass: outputs left untouched, status set
-    const double P = (double)j * ldexp(1.0, p.bits) + (double)(p.U >> (32 - p.bits));
-    int a = 0, b = p.n_chunks;
-    while (a < b) {
-        int mid = (a + b) >> 1;
-        if (p.ws.bincl[mid] > P) b = mid;
-        else a = mid + 1;
-    }
-    int idx = last;
-    if (a < p.n_chunks) {
-        const double rel = P - p.ws.boff[a];
-        int lo = a * kLgChunk, hi = min(p.N, lo + kLgChunk);
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (p.ws.cloc[mid] > rel) hi = mid;
-            else lo = mid + 1;
+    const int j0 = blockIdx.x * kLgChunk;
+    const int n_out = min(kLgChunk, p.N - j0);
+    const double step = ldexp(1.0, p.bits), u = (double)(p.U >> (32 - p.bits));
+    // outputs of this block select particles in [starts[blk], starts[blk + 1]] (indices are monotone)
+    const int a = p.ws.starts[blockIdx.x], b = max(a, p.ws.starts[blockIdx.x + 1]);
+    const bool staged = b - a + 1 <= kStageMax;
+    if (staged)
+        for (int i = a + threadIdx.x; i <= b; i += kLgThreads) cs[i - a] = gprefix(p, i);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n_out; r += kLgThreads) {
+        const double P = (double)(j0 + r) * step + u;
+        int idx;
+        if (staged) {
+            // first i in [a, b] with prefix > P; outputs of this block all land in [a, b]
+            int lo = a, hi = b;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (cs[mid - a] > P) hi = mid;
+                else lo = mid + 1;
+            }
+            idx = (cs[lo - a] > P) ? lo : last;
+        } else {
+            idx = global_search(p, P, last);
         }
-        idx = lo;
+        ids[r] = idx;
+        if (p.idx_out) p.idx_out[j0 + r] = idx;
     }
-    if (p.idx_out) p.idx_out[j] = idx;
-    if (p.src && p.dst)
-        for (int c = 0; c < p.row_floats; ++c) p.dst[(size_t)j * p.row_floats + c] = p.src[(size_t)idx * p.row_floats + c];
+    __syncthreads();
+    if (p.src && p.dst) {
+        const int rf = p.row_floats;
+        const long total = (long)n_out * rf;
+        for (long e = threadIdx.x; e < total; e += kLgThreads) {
+            const int r = (int)(e / rf), c = (int)(e % rf);
+            p.dst[(size_t)(j0 + r) * rf + c] = p.src[(size_t)ids[r] * rf + c];
+        }
+    }
 }
 
 size_t large_res_workspace_bytes(int N) {
     const size_t nc = ((size_t)N + kLgChunk - 1) / kLgChunk;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-    return al(nc * 8) * 6 + al(nc * 4) + al((size_t)N * 8) + al(64);
+    return al(nc * 8) * 6 + al(nc * 4) + al((size_t)N * 8) + al(64) + al((nc + 1) * 4);
 }
 
 LargeResWs carve_large_res(void* base, int N) {
@@ -260,6 +347,8 @@ LargeResWs carve_large_res(void* base, int N) {
     w.cloc = reinterpret_cast<double*>(b); b += al((size_t)N * 8);
     w.scal = reinterpret_cast<double*>(b);
     w.last = reinterpret_cast<int*>(b + 32);
+    b += al(64);
+    w.starts = reinterpret_cast<int*>(b);
     return w;
 }
 
@@ -267,14 +356,15 @@ hipError_t launch_large_res(LargeResParams p, hipStream_t s) {
     p.n_chunks = (p.N + kLgChunk - 1) / kLgChunk;
     const int nc = p.n_chunks;
     if (!p.w_in) {
-        hipLaunchKernelGGL(lg_max_kernel, nc, kLgThreads, 0, s, p);
-        hipLaunchKernelGGL(lg_reduce_max_kernel, 1, kLgThreads, 0, s, p);
-        hipLaunchKernelGGL(lg_sum_kernel, nc, kLgThreads, 0, s, p);
-        hipLaunchKernelGGL(lg_reduce_sum_kernel, 1, 64, 0, s, p);
+        hipLaunchKernelGGL(lg_lse_kernel, nc, kLgThreads, 0, s, p);
+        hipLaunchKernelGGL(lg_lse_reduce_kernel, 1, kLgThreads, 0, s, p);
     }
     hipLaunchKernelGGL(lg_quant_kernel, nc, kLgThreads, 0, s, p);
     hipLaunchKernelGGL(lg_scan_kernel, 1, 1024, 0, s, p);
-    if (p.do_resample) hipLaunchKernelGGL(lg_search_kernel, (p.N + 255) / 256, 256, 0, s, p);
+    if (p.do_resample) {
+        hipLaunchKernelGGL(lg_starts_kernel, (nc + 1 + 255) / 256, 256, 0, s, p);
+        hipLaunchKernelGGL(lg_search_kernel, nc, kLgThreads, 0, s, p);
+    }
     return hipGetLastError();
 }
 

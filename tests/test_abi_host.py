@@ -79,6 +79,14 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert L.voila_resample(None, 0, 0, None, None, None, 0, None, None, 0, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_resample(fake, 4, 0, fake, fake, None, 1, None, None, 0, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_resample(fake, 9000, 0, fake, None, None, 0, None, None, 0, None) == V.VOILA_ERR_WORKSPACE
+    assert L.voila_reweight_resample(None, None, 10, 1.0, 0, None, None, None, None, None, 0, None, None, 0,
+                                     None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_reweight_resample(fake, None, 10, -1.0, 0, fake, None, None, None, None, 0, None, None, 0,
+                                     None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_reweight_resample(fake, None, 10, 1.0, 0, fake, None, None, fake, None, 4, None, None, 0,
+                                     None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_reweight_resample(fake, None, 9000, 1.0, 0, fake, None, None, None, None, 0, None, None, 0,
+                                     None) == V.VOILA_ERR_WORKSPACE
     assert L.voila_philox_normals(1, 0, 0, 0, 1 << 16, 1, 4, fake, None, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_philox_normals(1, 0, 0, 0, 3, 1, 0, fake, None, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_model_create(None, 0, None) == V.VOILA_ERR_INVALID_ARG

@@ -90,3 +90,29 @@ def test_large_zero_mass_sets_status(V):
     V.resample(dev(np.zeros(20000), torch.float64), 5, status=st)
     torch.cuda.synchronize()
     assert int(st.item()) == V.VOILA_ERR_NUMERIC
+
+
+@pytest.mark.parametrize("N", [1000, 8192, 8193, 300000])
+def test_reweight_resample_fused(V, N):
+    """The one-call weights + resampling path: weights within 1e-13 of the
+    oracle's, indices bit-exact with the oracle's resampler on those weights,
+    and identical to the two-call normalise-then-resample path."""
+    rng = np.random.default_rng(N + 7)
+    ll = (rng.standard_normal(N) * 3).astype(np.float32)
+    src = rng.standard_normal((N, 8)).astype(np.float32)
+    U = int(rng.integers(0, 2**32))
+    for lam, prior in [(1.0, None), (0.7, rng.dirichlet(np.ones(N)))]:
+        pw = None if prior is None else dev(prior, torch.float64)
+        print(f"reweight_resample N={N} lam={lam}", flush=True)
+        out = V.reweight_resample(dev(ll), U, lam, prior_w=pw, src=dev(src), want_w=True)
+        w2, st2 = V.normalize(dev(ll), lam, pw)
+        idx2 = V.resample(w2, U)
+        torch.cuda.synchronize()
+        w = out["w"].cpu().numpy()
+        wr, sr = oracle.normalize(ll.astype(np.float64), lam, prior)
+        assert np.max(np.abs(w - wr) / wr) < 1e-13
+        assert np.max(np.abs(out["stats"].cpu().numpy() - sr) / np.abs(sr)) < 1e-12
+        idx = out["idx"].cpu().numpy()
+        assert np.array_equal(idx, oracle.resample(w, U))
+        assert np.array_equal(out["dst"].cpu().numpy(), src[idx])
+        assert np.array_equal(w, w2.cpu().numpy()) and np.array_equal(idx, idx2.cpu().numpy())
