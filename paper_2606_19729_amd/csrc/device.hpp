@@ -67,18 +67,25 @@ __host__ __device__ constexpr int in_slots(int dt, int d_s, int d_ain, int d_w) 
 // (fragment (k-step c, 32-row tile t)), in the order the kernels consume them:
 // first layer [c][t], each hidden->hidden layer [c][t], output layer [c].
 // Wider networks (two hidden layers) hold only the first hidden layer's
-// activations in registers and produce the second in groups of `ct` tiles, so
-// their hidden->hidden fragments are stored group by group: [t / ct][c][t % ct].
+// activations in registers and produce the second in groups of `ct` tiles:
+// their hidden->hidden and output fragments are stored group by group, each
+// group holding its hidden fragments [c][t % ct] followed by the output-layer
+// k-steps that consume the group's tiles.
 struct FragLayout {
     int ht, in_ks, hid_ks, ct, nhid;
     __host__ __device__ constexpr bool grouped() const { return ct < ht; }
     __host__ __device__ constexpr int nf0() const { return in_ks * ht; }
+    __host__ __device__ constexpr int oks() const { return hid_ks / ht; }  // output k-steps per hidden tile
+    __host__ __device__ constexpr int group() const { return hid_ks * ct + oks() * ct; }
     __host__ __device__ constexpr int first(int c, int t) const { return c * ht + t; }
     __host__ __device__ constexpr int hidden(int l, int c, int t) const {
-        return grouped() ? nf0() + (t / ct) * hid_ks * ct + c * ct + t % ct
+        return grouped() ? nf0() + (t / ct) * group() + c * ct + t % ct
                          : nf0() + (l - 1) * hid_ks * ht + c * ht + t;
     }
-    __host__ __device__ constexpr int out(int c) const { return nf0() + (nhid - 1) * hid_ks * ht + c; }
+    __host__ __device__ constexpr int out(int c) const {
+        return grouped() ? nf0() + (c / (oks() * ct)) * group() + hid_ks * ct + c % (oks() * ct)
+                         : nf0() + (nhid - 1) * hid_ks * ht + c;
+    }
 };
 
 // Output tiles produced per group by the grouped evaluation of wide networks.
@@ -101,7 +108,6 @@ struct Net {
     static constexpr int NFO = HID_KS;             // output-layer fragments
     static constexpr int CT = chunk_tiles(WIDTH);  // tiles per group of the grouped evaluation
     static constexpr int OKS = HID_KS / HT;        // output k-steps per hidden tile
-    static constexpr FragLayout LAYOUT{HT, IN_KS, HID_KS, CT, NHID};
     static_assert(WIDTH % 32 == 0 && NHID >= 1 && IN_SLOTS % KPER == 0, "bad net shape");
     static_assert(CT == HT || (NHID == 2 && HT % CT == 0), "grouped evaluation needs two hidden layers");
 };
@@ -302,11 +308,52 @@ struct StreamSrc {
     __device__ __forceinline__ void finish() { __builtin_amdgcn_s_waitcnt(0); }
 };
 
+// Instruction classes of the scheduling-group barriers: LDS or vector-memory
+// reads, matrix-core instructions.
+constexpr int kSchedReads = 0x100 | 0x020;
+constexpr int kSchedMfma = 0x008;
+
+// acc[t] += A(c, t) B(c) over k-steps c < KS and tiles t < NT, with the A
+// fragments of the next D - 1 k-steps already loading while k-step c is
+// multiplied (register ring indexed at compile time).  `ld(c, t)` issues the
+// load of fragment (c, t) (in increasing c, so a streaming source meets its
+// chunk boundaries in order); `bop(c)` gives the B operand of k-step c.
+template <int KS, int NT, int D, class FT, class LD, class BOP>
+__device__ __forceinline__ void mfma_layer(f32x16 (&acc)[NT], LD&& ld, BOP&& bop) {
+    constexpr int DD = D < KS ? D : KS;
+    FT ring[DD][NT];
+    static_for<DD - 1>([&](auto pi) {
+        constexpr int c = decltype(pi)::value;
+        static_for<NT>([&](auto ti) { ring[c][decltype(ti)::value] = ld(c, decltype(ti)::value); });
+    });
+    static_for<KS>([&](auto ci) {
+        constexpr int c = decltype(ci)::value;
+        if constexpr (c + DD - 1 < KS) {
+            static_for<NT>([&](auto ti) {
+                ring[(c + DD - 1) % DD][decltype(ti)::value] = ld(c + DD - 1, decltype(ti)::value);
+            });
+        }
+        auto b = bop(c);
+        static_for<NT>([&](auto ti) {
+            constexpr int t = decltype(ti)::value;
+            acc[t] = mfma(ring[c % DD][t], b, acc[t]);
+        });
+        // issue this k-step's prefetch loads before its products, and keep the
+        // scheduler from hoisting later loads (one register set per k-step)
+        if constexpr (c + DD - 1 < KS) __builtin_amdgcn_sched_group_barrier(kSchedReads, NT, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedMfma, NT, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
 // Fragment index of (k-step c, tile t) in each layer of the packed stream.
+// (The layout is rebuilt from the shape constants in each call: a static
+// constexpr layout object would be read from memory at run time.)
 template <class N> struct FragIdx {
-    __device__ static constexpr int first(int c, int t) { return N::LAYOUT.first(c, t); }
-    __device__ static constexpr int hidden(int l, int c, int t) { return N::LAYOUT.hidden(l, c, t); }
-    __device__ static constexpr int out(int c) { return N::LAYOUT.out(c); }
+    __device__ static constexpr FragLayout lay() { return FragLayout{N::HT, N::IN_KS, N::HID_KS, N::CT, N::NHID}; }
+    __device__ static constexpr int first(int c, int t) { return lay().first(c, t); }
+    __device__ static constexpr int hidden(int l, int c, int t) { return lay().hidden(l, c, t); }
+    __device__ static constexpr int out(int c) { return lay().out(c); }
 };
 
 template <class N, class Src>
@@ -321,6 +368,32 @@ __device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const floa
                                           const float (&slots)[N::IN_SLOTS], int lane, int g) {
     if constexpr (N::CT < N::HT) {
         return run_net_grouped<N>(src, P, b0, slots, lane, g);
+    } else if constexpr (N::DT == DT_BF16) {
+        // bfloat16: every loop unrolled at compile time (fragment positions,
+        // and a streaming source's chunk boundaries, are constants) and the
+        // weight fragments of the next k-step load while this one multiplies
+        typedef FragIdx<N> FI;
+        typedef typename Frag<N::DT>::type FT;
+        f32x16 acc[N::HT];
+        Act<N::DT, N::HT> act;
+        init_bias<N::HT>(acc, b0 + opaque_zero(), g);
+        mfma_layer<N::IN_KS, N::HT, 2, FT>(
+            acc, [&](int c, int t) { return src.load(FI::first(c, t), lane); },
+            [&](int c) { return Slots<N::DT, N::IN_SLOTS>::b(slots, c); });
+        act.set_relu(acc);
+        static_for<N::NHID - 1>([&](auto li) {
+            constexpr int l = decltype(li)::value + 1;
+            init_bias<N::HT>(acc, P.bh + (l - 1) * N::WIDTH + opaque_zero(), g);
+            mfma_layer<N::HID_KS, N::HT, 2, FT>(
+                acc, [&](int c, int t) { return src.load(FI::hidden(l, c, t), lane); },
+                [&](int c) { return act.b(c); });
+            act.set_relu(acc);
+        });
+        f32x16 out[1];
+        init_bias<1>(out, P.bo + opaque_zero(), g);
+        mfma_layer<N::HID_KS, 1, 4, FT>(
+            out, [&](int c, int) { return src.load(FI::out(c), lane); }, [&](int c) { return act.b(c); });
+        return out[0];
     } else {
     typedef FragIdx<N> FI;
     f32x16 acc[N::HT];
@@ -363,8 +436,8 @@ __device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const floa
 // A window of WINF fragments shares one opaque base address, which bounds how
 // many weight loads the compiler can issue ahead (and keeps them in the loop).
 template <class N, int WINF = 8>
-struct GroupDirect {  // hidden fragments straight from global memory (L2)
-    static constexpr int GF = N::HID_KS * N::CT;  // fragments per group
+struct GroupDirect {  // group fragments straight from global memory (L2)
+    static constexpr int GF = N::HID_KS * N::CT + N::OKS * N::CT;  // fragments per group
     const char* base;
     const char* grp;
     const char* win;
@@ -379,17 +452,17 @@ struct GroupDirect {  // hidden fragments straight from global memory (L2)
     __device__ __forceinline__ void finish() {}
 };
 
-// Hidden fragments streamed through two LDS chunk buffers shared by the
-// workgroup (same protocol as StreamSrc); a group is a whole number of chunks,
-// so every chunk boundary sits at a compile-time position of the group.
-template <class N, int CHB = 32768, int WINF = 8>
+// Group fragments streamed through two LDS chunk buffers shared by the
+// workgroup (same protocol as StreamSrc); a group is CPG whole chunks, so
+// every chunk boundary sits at a compile-time position of the group.
+template <class N, int CPG = 8, int WINF = 8>
 struct GroupStream {
     static constexpr int FB = N::FRAG_BYTES;
-    static constexpr int FPC = CHB / FB;
-    static constexpr int GF = N::HID_KS * N::CT;
-    static constexpr int CPG = GF / FPC;                // chunks per group
+    static constexpr int GF = N::HID_KS * N::CT + N::OKS * N::CT;
+    static constexpr int FPC = GF / CPG;                // fragments per chunk
+    static constexpr int CHB = FPC * FB;                // chunk bytes
     static constexpr int NCH = (N::HT / N::CT) * CPG;   // chunks per network evaluation
-    static_assert(GF % FPC == 0 && CHB % 4096 == 0, "a group must be whole chunks of whole DMA rounds");
+    static_assert(GF % CPG == 0 && CHB % 1024 == 0, "a group must be whole chunks of whole 1 KB DMA rounds");
     char* lds;
     const char* src;
     int cur, gch;
@@ -423,30 +496,35 @@ struct GroupStream {
     __device__ __forceinline__ void finish() { __builtin_amdgcn_s_waitcnt(0); }
 };
 
+// Bytes of one LDS chunk buffer of a streaming network source.
+template <class N, bool G = (N::CT < N::HT)> struct StreamChunk {
+    static constexpr int CHB = 32768;
+};
+template <class N> struct StreamChunk<N, true> {
+    static constexpr int CHB = GroupStream<N>::CHB;
+};
+
 template <class N, class HS>
 struct WideSrc {
     DirectSrc<N::DT, 8> first;
     HS hid;
-    const char* out;
-    __device__ __forceinline__ WideSrc(const char* f0, HS h, const char* fo) : first(f0), hid(h), out(fo) {}
+    __device__ __forceinline__ WideSrc(const char* f0, HS h) : first(f0), hid(h) {}
 };
 
 template <class N, class Src>
 __device__ __forceinline__ f32x16 run_net_grouped(Src& src, const NetPtrs& P, const float* b0,
                                                   const float (&slots)[N::IN_SLOTS], int lane, int g) {
     typedef FragIdx<N> FI;
+    typedef typename Frag<N::DT>::type FT;
     constexpr int CT = N::CT, OKS = N::OKS;
     Act<N::DT, N::HT> act;
     static_for<N::HT / CT>([&](auto gi) {
         constexpr int tc = decltype(gi)::value * CT;
         f32x16 acc[CT];
         init_bias<CT>(acc, b0 + 32 * tc + opaque_zero(), g);
-        static_for<N::IN_KS>([&](auto ci) {
-            constexpr int c = decltype(ci)::value;
-            auto b = Slots<N::DT, N::IN_SLOTS>::b(slots, c);
-#pragma unroll
-            for (int t = 0; t < CT; ++t) acc[t] = mfma(src.first.load(FI::first(c, tc + t), lane), b, acc[t]);
-        });
+        mfma_layer<N::IN_KS, CT, 2, FT>(
+            acc, [&](int c, int t) { return src.first.load(FI::first(c, tc + t), lane); },
+            [&](int c) { return Slots<N::DT, N::IN_SLOTS>::b(slots, c); });
         act.template set_relu_at<CT>(acc, tc);
     });
     f32x16 out[1];
@@ -456,19 +534,45 @@ __device__ __forceinline__ f32x16 run_net_grouped(Src& src, const NetPtrs& P, co
         src.hid.begin_group(gi);
         f32x16 acc[CT];
         init_bias<CT>(acc, P.bh + 32 * CT * gi + opaque_zero(), g);
+        // hidden fragments: ring of two k-steps, positions known at compile time
+        FT ring[2][CT];
+        static_for<CT>([&](auto ti) {
+            constexpr int t = decltype(ti)::value;
+            ring[0][t] = src.hid.template load<t>(lane);
+        });
+        // the group's output-layer k-steps follow its hidden fragments; they
+        // load during the last hidden k-step
+        constexpr int OB = N::HID_KS * CT;
+        FT of[OKS * CT];
         static_for<N::HID_KS>([&](auto ci) {
             constexpr int c = decltype(ci)::value;
+            if constexpr (c + 1 < N::HID_KS) {
+                static_for<CT>([&](auto ti) {
+                    constexpr int t = decltype(ti)::value;
+                    ring[(c + 1) % 2][t] = src.hid.template load<(c + 1) * CT + t>(lane);
+                });
+            } else {
+                static_for<OKS * CT>([&](auto oi) {
+                    constexpr int o = decltype(oi)::value;
+                    of[o] = src.hid.template load<OB + o>(lane);
+                });
+            }
             auto b = act.b(c);
             static_for<CT>([&](auto ti) {
                 constexpr int t = decltype(ti)::value;
-                acc[t] = mfma(src.hid.template load<c * CT + t>(lane), b, acc[t]);
+                acc[t] = mfma(ring[c % 2][t], b, acc[t]);
             });
+            __builtin_amdgcn_sched_group_barrier(kSchedReads, c + 1 < N::HID_KS ? CT : OKS * CT, 0);
+            __builtin_amdgcn_sched_group_barrier(kSchedMfma, CT, 0);
+            __builtin_amdgcn_sched_barrier(0);
         });
         Act<N::DT, CT> a2;
         a2.set_relu(acc);
-        const char* ob = src.out + (size_t)gi * OKS * CT * N::FRAG_BYTES + opaque_zero();
-#pragma unroll
-        for (int c = 0; c < OKS * CT; ++c) out[0] = mfma(Frag<N::DT>::load(ob, c, lane), a2.b(c), out[0]);
+        static_for<OKS * CT>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            out[0] = mfma(of[c], a2.b(c), out[0]);
+        });
+        __builtin_amdgcn_sched_barrier(0);
     }
     return out[0];
 }
@@ -482,9 +586,7 @@ template <class N> struct DirectFor<N, false> {
 };
 template <class N> struct DirectFor<N, true> {
     typedef WideSrc<N, GroupDirect<N>> type;
-    __device__ static __forceinline__ type make(const NetPtrs& P) {
-        return type(P.f0, GroupDirect<N>(P.fh), P.fo);
-    }
+    __device__ static __forceinline__ type make(const NetPtrs& P) { return type(P.f0, GroupDirect<N>(P.fh)); }
 };
 
 // ----------------------------------------------------------------------------

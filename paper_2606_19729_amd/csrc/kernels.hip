@@ -140,7 +140,21 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
         stage_blob(smem, p.net.base, p.net.bytes);
         __syncthreads();
     }
-    const NetPtrs P = net_ptrs(MODE == kResident ? (const char*)smem : p.net.base, p.net);
+    NetPtrs P = net_ptrs(MODE == kResident ? (const char*)smem : p.net.base, p.net);
+    // streamed networks: the biases (and, for grouped wide networks, the first
+    // layer) are staged in LDS after the two chunk buffers
+    constexpr int CHB = StreamChunk<NT>::CHB;
+    char* const extra = smem + 2 * CHB;
+    if constexpr (MODE == kStream) {
+        const uint32_t f0_bytes = NT::CT < NT::HT ? (uint32_t)(NT::NF0 * NT::FRAG_BYTES) : 0u;
+        if (f0_bytes) stage_blob(extra, P.f0, f0_bytes);
+        char* bias = extra + f0_bytes;
+        stage_blob(bias, p.net.base + p.net.off_b0, p.net.bytes - p.net.off_b0);
+        __syncthreads();
+        P.b0 = reinterpret_cast<const float*>(bias);
+        P.bh = reinterpret_cast<const float*>(bias + (p.net.off_bh - p.net.off_b0));
+        P.bo = reinterpret_cast<const float*>(bias + (p.net.off_bo - p.net.off_b0));
+    }
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6;
     const long n_units = (long)p.K * p.n_tiles;
@@ -153,13 +167,9 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
         }
     };
     if constexpr (MODE == kStream && NT::CT < NT::HT) {
-        // grouped wide network: hidden fragments stream through two 32 KB LDS
-        // buffers, the output layer is staged after them once per block, the
-        // first layer is read from L2
-        char* out_lds = smem + 2 * 32768;
-        stage_blob(out_lds, P.fo, (uint32_t)(p.net.off_b0 - p.net.off_fo));
-        __syncthreads();
-        WideSrc<NT, GroupStream<NT>> src(P.f0, GroupStream<NT>(smem, P.fh), out_lds);
+        // grouped wide network: the groups' fragments stream through the two
+        // LDS chunk buffers, the first layer is read from its LDS copy
+        WideSrc<NT, GroupStream<NT>> src(extra, GroupStream<NT>(smem, P.fh));
         src.hid.start();
         body(src);
         src.hid.finish();
@@ -701,15 +711,41 @@ VOILA_IN_SLOTS(lik_in_slots, in_slots(dt, s.d_s, 0, 0))
 #undef VOILA_IN_SLOTS
 
 #define PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) plan_kernel<DT, ds, na, da, dw, w, nh, plan_mode<w>()>
+
+// LDS of a streaming rollout kernel before its staged biases: the two chunk
+// buffers (and the first layer of a grouped wide network).
+template <int DT, int D_S, int D_AIN, int D_W, int WIDTH, int NHID>
+constexpr size_t stream_lds_of() {
+    if constexpr (DT == DT_BF16 && WIDTH > 256) {
+        typedef Net<DT_BF16, WIDTH, NHID, in_slots(DT_BF16, D_S, D_AIN, D_W)> NT;
+        return 2 * (size_t)GroupStream<NT>::CHB + (size_t)NT::NF0 * NT::FRAG_BYTES;
+    } else {
+        return kStreamLds;
+    }
+}
+size_t plan_stream_lds(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                      \
+    case id * 2 + 0:                                                               \
+        return stream_lds_of<DT_F32, ds, (na > 0 ? 0 : da), dw, w, nh>();            \
+    case id * 2 + 1:                                                               \
+        return stream_lds_of<DT_BF16, ds, (na > 0 ? 0 : da), dw, w, nh>();
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return kStreamLds;
+}
 #define PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) propose_kernel<DT, ds, dw, w, nh, pass_mode<w>()>
 #define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, pass_mode<w>()>
 
 hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s) {
-    size_t lds = weights_in_lds(shape) ? p.net.bytes : kStreamLds;
-    if (kShapeInfo[shape].width > 256) lds += p.net.off_b0 - p.net.off_fo;  // staged output layer
+    size_t lds = weights_in_lds(shape) ? p.net.bytes : plan_stream_lds(shape, dt) + (p.net.bytes - p.net.off_b0);
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
     case id * 2 + 0:                                                                                       \
+        if (lds > 65536)                                                                                   \
+            (void)hipFuncSetAttribute((const void*)PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),     \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
         hipLaunchKernelGGL((PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);  \
         break;                                                                                             \
     case id * 2 + 1:                                                                                       \
