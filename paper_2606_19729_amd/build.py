@@ -2,7 +2,9 @@
 
 One hipcc invocation compiles the kernels and the ABI into a shared library
 next to this file.  Packed FP32 instructions are disabled for the device code
-(-packed-fp32-ops is turned off), the library is built at -O3 without fast-math.
+(-packed-fp32-ops is turned off), the library is built at -O3 without fast-math
+and without implicit contraction of multiply-adds (kernels that share device
+functions then round identically; fused operations are written explicitly).
 """
 import os
 import subprocess
@@ -17,7 +19,7 @@ ARCH = os.environ.get("VOILA_OFFLOAD_ARCH", "gfx950")
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
            "-I", os.path.join(ROOT, "include")]

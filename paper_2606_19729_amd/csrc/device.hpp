@@ -40,6 +40,24 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int DT_F32 = 0;
 constexpr int DT_BF16 = 1;
 
+// Pipeline depth (k-steps of weight fragments in registers, including the
+// one being multiplied) of the bfloat16 evaluation, chunks per group of the
+// grouped wide networks' stream, and the chunk bytes of other streamed
+// networks.
+#ifndef VOILA_PF_DEPTH
+#define VOILA_PF_DEPTH 3
+#endif
+#ifndef VOILA_WIDE_CPG
+#define VOILA_WIDE_CPG 11
+#endif
+#ifndef VOILA_WIDE_NBUF
+#define VOILA_WIDE_NBUF 3
+#endif
+#ifndef VOILA_STREAM_CHB
+#define VOILA_STREAM_CHB 32768
+#endif
+constexpr int kPfDepth = VOILA_PF_DEPTH;
+
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int rup(int a, int b) { return cdiv(a, b) * b; }
 // Calls f(std::integral_constant<int, i>) for i = 0 .. N-1 (compile-time indices).
@@ -263,7 +281,7 @@ struct DirectSrc {
 // chunk's direct-to-LDS loads, meet at a barrier (which also retires chunk
 // ch - 1 from the other buffer) and then start loading chunk ch + 1 into that
 // other buffer, so the next chunk streams in while this one is multiplied.
-template <class N, int CHB = 32768, int WIN = 4 * N::HT>
+template <class N, int CHB = VOILA_STREAM_CHB, int WIN = 4 * N::HT>
 struct StreamSrc {
     static constexpr int FB = N::FRAG_BYTES;
     static constexpr int FPC = CHB / FB;  // fragments per chunk
@@ -384,7 +402,7 @@ __device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const floa
         static_for<N::NHID - 1>([&](auto li) {
             constexpr int l = decltype(li)::value + 1;
             init_bias<N::HT>(acc, P.bh + (l - 1) * N::WIDTH + opaque_zero(), g);
-            mfma_layer<N::HID_KS, N::HT, 2, FT>(
+            mfma_layer<N::HID_KS, N::HT, kPfDepth, FT>(
                 acc, [&](int c, int t) { return src.load(FI::hidden(l, c, t), lane); },
                 [&](int c) { return act.b(c); });
             act.set_relu(acc);
@@ -452,43 +470,65 @@ struct GroupDirect {  // group fragments straight from global memory (L2)
     __device__ __forceinline__ void finish() {}
 };
 
-// Group fragments streamed through two LDS chunk buffers shared by the
-// workgroup (same protocol as StreamSrc); a group is CPG whole chunks, so
-// every chunk boundary sits at a compile-time position of the group.
-template <class N, int CPG = 8, int WINF = 8>
+// s_waitcnt immediate: wait until at most `vm` vector-memory operations of
+// this wave are outstanding and all of its LDS operations are done.
+__host__ __device__ constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4); }
+
+// Group fragments streamed through NBUF LDS chunk buffers shared by the
+// workgroup of four waves; a group is CPG whole chunks, so every chunk
+// boundary sits at a compile-time position of the group.  Each wave moves a
+// quarter of every chunk with direct-to-LDS loads, issued NBUF - 1 chunks
+// ahead.  At the first fragment of a chunk a wave waits until only its loads
+// of the NBUF - 2 newer chunks are outstanding (vector-memory loads complete
+// in order) and its LDS reads are done, then the workgroup meets at a
+// barrier, after which the chunk is complete and the buffer read before it
+// is free: the loads of the chunk NBUF - 1 ahead go there.
+template <class N, int CPG = VOILA_WIDE_CPG, int NBUF = VOILA_WIDE_NBUF, int WINF = 8>
 struct GroupStream {
     static constexpr int FB = N::FRAG_BYTES;
     static constexpr int GF = N::HID_KS * N::CT + N::OKS * N::CT;
     static constexpr int FPC = GF / CPG;                // fragments per chunk
     static constexpr int CHB = FPC * FB;                // chunk bytes
     static constexpr int NCH = (N::HT / N::CT) * CPG;   // chunks per network evaluation
-    static_assert(GF % CPG == 0 && CHB % 1024 == 0, "a group must be whole chunks of whole 1 KB DMA rounds");
+    static constexpr int kWaves = 4;                    // waves of the workgroup
+    static constexpr int ROUNDS = CHB / 1024 / kWaves;  // 1 KB loads per wave per chunk
+    static constexpr int LDS_BYTES = NBUF * CHB;
+    static_assert(GF % CPG == 0 && CHB % (1024 * kWaves) == 0, "a chunk must be whole 1 KB rounds of every wave");
+    static_assert(NBUF >= 2 && (NBUF - 2) * ROUNDS <= 63 && NCH >= NBUF, "bad chunk pipeline");
     char* lds;
     const char* src;
-    int cur, gch;
+    int cur, nxt_buf, gch;
     const char* win;
-    __device__ __forceinline__ GroupStream(char* l, const char* s) : lds(l), src(s), cur(1), gch(0), win(l) {}
+    __device__ __forceinline__ GroupStream(char* l, const char* s)
+        : lds(l), src(s), cur(NBUF - 1), nxt_buf(NBUF - 1), gch(0), win(l) {}
     __device__ __forceinline__ void fetch(int ch, int b) const {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
         const int lane = threadIdx.x & 63;
         const char* base = src + opaque_zero() + (size_t)ch * CHB;
-        for (int off = wave * 1024; off < CHB; off += nw * 1024)
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const int off = (r * kWaves + wave) * 1024;
             __builtin_amdgcn_global_load_lds((const void*)(base + off + lane * 16),
                                              (__attribute__((address_space(3))) void*)(lds + b * CHB + off), 16, 0,
                                              0);
+        }
     }
-    __device__ __forceinline__ void start() { fetch(0, 0); }
+    __device__ __forceinline__ void start() {
+#pragma unroll
+        for (int j = 0; j < NBUF - 1; ++j) fetch(j, j);
+    }
     __device__ __forceinline__ void begin_group(int gi) { gch = gi * CPG; }
     template <int POS>
     __device__ __forceinline__ typename Frag<N::DT>::type load(int lane) {
         constexpr int within = POS % FPC;
         if constexpr (within == 0) {
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            cur ^= 1;
-            const int nxt = gch + POS / FPC + 1;
-            fetch(nxt < NCH ? nxt : 0, cur ^ 1);
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NBUF - 2) * ROUNDS));
+            __builtin_amdgcn_s_barrier();
+            cur = cur + 1 == NBUF ? 0 : cur + 1;
+            int nxt = gch + POS / FPC + NBUF - 1;
+            nxt = nxt < NCH ? nxt : nxt - NCH;
+            fetch(nxt, nxt_buf);
+            nxt_buf = nxt_buf + 1 == NBUF ? 0 : nxt_buf + 1;
         }
         if constexpr (within % WINF == 0) win = lds + cur * CHB + within * FB + opaque_zero();
         return Frag<N::DT>::load(win, within % WINF, lane);
@@ -498,11 +538,20 @@ struct GroupStream {
 
 // Bytes of one LDS chunk buffer of a streaming network source.
 template <class N, bool G = (N::CT < N::HT)> struct StreamChunk {
-    static constexpr int CHB = 32768;
+    static constexpr int BYTES = 2 * VOILA_STREAM_CHB;  // LDS of the chunk buffers
 };
 template <class N> struct StreamChunk<N, true> {
-    static constexpr int CHB = GroupStream<N>::CHB;
+    static constexpr int BYTES = GroupStream<N>::LDS_BYTES;
 };
+
+// LDS per workgroup, and whether a grouped wide network's first layer is
+// staged in LDS beside its chunk buffers and staged biases (n_var first-layer
+// bias variants), or read from L2.
+constexpr int kLdsMax = 160 * 1024;
+template <class N>
+__host__ __device__ constexpr bool first_layer_in_lds(int n_var) {
+    return StreamChunk<N>::BYTES + N::NF0 * N::FRAG_BYTES + (n_var + N::NHID - 1) * N::WIDTH * 4 + 1024 <= kLdsMax;
+}
 
 template <class N, class HS>
 struct WideSrc {
@@ -535,10 +584,14 @@ __device__ __forceinline__ f32x16 run_net_grouped(Src& src, const NetPtrs& P, co
         f32x16 acc[CT];
         init_bias<CT>(acc, P.bh + 32 * CT * gi + opaque_zero(), g);
         // hidden fragments: ring of two k-steps, positions known at compile time
-        FT ring[2][CT];
-        static_for<CT>([&](auto ti) {
-            constexpr int t = decltype(ti)::value;
-            ring[0][t] = src.hid.template load<t>(lane);
+        constexpr int D = kPfDepth;
+        FT ring[D][CT];
+        static_for<D - 1>([&](auto pi) {
+            constexpr int c = decltype(pi)::value;
+            static_for<CT>([&](auto ti) {
+                constexpr int t = decltype(ti)::value;
+                ring[c][t] = src.hid.template load<c * CT + t>(lane);
+            });
         });
         // the group's output-layer k-steps follow its hidden fragments; they
         // load during the last hidden k-step
@@ -546,12 +599,12 @@ __device__ __forceinline__ f32x16 run_net_grouped(Src& src, const NetPtrs& P, co
         FT of[OKS * CT];
         static_for<N::HID_KS>([&](auto ci) {
             constexpr int c = decltype(ci)::value;
-            if constexpr (c + 1 < N::HID_KS) {
+            if constexpr (c + D - 1 < N::HID_KS) {
                 static_for<CT>([&](auto ti) {
                     constexpr int t = decltype(ti)::value;
-                    ring[(c + 1) % 2][t] = src.hid.template load<(c + 1) * CT + t>(lane);
+                    ring[(c + D - 1) % D][t] = src.hid.template load<(c + D - 1) * CT + t>(lane);
                 });
-            } else {
+            } else if constexpr (c + 1 == N::HID_KS) {
                 static_for<OKS * CT>([&](auto oi) {
                     constexpr int o = decltype(oi)::value;
                     of[o] = src.hid.template load<OB + o>(lane);
@@ -560,9 +613,10 @@ __device__ __forceinline__ f32x16 run_net_grouped(Src& src, const NetPtrs& P, co
             auto b = act.b(c);
             static_for<CT>([&](auto ti) {
                 constexpr int t = decltype(ti)::value;
-                acc[t] = mfma(ring[c % 2][t], b, acc[t]);
+                acc[t] = mfma(ring[c % D][t], b, acc[t]);
             });
-            __builtin_amdgcn_sched_group_barrier(kSchedReads, c + 1 < N::HID_KS ? CT : OKS * CT, 0);
+            constexpr int NR = c + D - 1 < N::HID_KS ? CT : (c + 1 == N::HID_KS ? OKS * CT : 0);
+            if constexpr (NR > 0) __builtin_amdgcn_sched_group_barrier(kSchedReads, NR, 0);
             __builtin_amdgcn_sched_group_barrier(kSchedMfma, CT, 0);
             __builtin_amdgcn_sched_barrier(0);
         });

@@ -28,17 +28,22 @@ const ShapeInfo kShapeInfo[kNumShapes] = {
 #undef X
 };
 
-__device__ __forceinline__ float reward_of(const float* st, const float* goal, int n_slots, int d_s, int g) {
+// Global memory that no kernel of the launch writes, read through the
+// constant address space so wave-uniform reads become scalar loads.
+#define kconst __attribute__((address_space(4)))
+
+// r = -||s - g||^2 with the goal already in this lane's slot order.
+__device__ __forceinline__ float reward_to(const float* st, const float* goal_slots, int n_slots, int d_s, int g) {
     float part = 0.0f;
     for (int s = 0; s < n_slots; ++s) {
-        int f = 2 * s + g;
-        if (f < d_s) {
-            float e = st[s] - goal[f];
-            part += e * e;
+        if (2 * s + g < d_s) {
+            float e = st[s] - goal_slots[s];
+            part = __builtin_fmaf(e, e, part);
         }
     }
     return -(part + __shfl_xor(part, 32));
 }
+
 
 
 }  // namespace
@@ -66,16 +71,24 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
                                           int lane, int g, int col) {
     constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
-    const int k = unit_ok ? (int)(u / p.n_tiles) : 0;
-    const int tile = unit_ok ? (int)(u % p.n_tiles) : 0;
+    // the unit (candidate, tile) is uniform over the wave: its candidate's
+    // actions are read with scalar loads, which leaves the vector-memory
+    // counter to the weight stream
+    const int uw = __builtin_amdgcn_readfirstlane(unit_ok ? (int)u : 0);
+    const int k = uw / p.n_tiles;
+    const int tile = uw - k * p.n_tiles;
     const int i = tile * 32 + col;
     const bool valid = unit_ok && i < p.N;
-    float st[SS];
+    float st[SS], goal[SS];
 #pragma unroll
     for (int s = 0; s < SS; ++s) {
         int f = 2 * s + g;
         st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+        goal[s] = f < D_S ? p.goal[f] : 0.0f;
     }
+    // complete these loads here, once per unit, so that no wait for them (and
+    // with them for the weight stream's loads in flight) lands in the step loop
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
     float G = 0.0f;
     double disc = 1.0;
     for (int t = 0; t < p.H; ++t) {
@@ -85,11 +98,12 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
 #pragma unroll
         for (int s = 0; s < SS; ++s) slots[s] = st[s];
         if (D_A > 0) {
-            const float* a = reinterpret_cast<const float*>(p.cands) + ((size_t)k * p.H + t) * D_A;
+            const kconst float* a = (const kconst float*)p.cands + ((size_t)k * p.H + t) * D_A;
 #pragma unroll
             for (int s = 0; s < SA; ++s) {
-                int f = 2 * s + g;
-                slots[SS + s] = f < D_A ? a[f] : 0.0f;
+                const float a0 = 2 * s < D_A ? a[2 * s] : 0.0f;
+                const float a1 = 2 * s + 1 < D_A ? a[2 * s + 1] : 0.0f;
+                slots[SS + s] = g ? a1 : a0;
             }
         }
         if (p.noise) {
@@ -99,6 +113,8 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
                 int f = noise_feature(s, g);
                 slots[SS + SA + s] = f < D_W ? nsrc[f] : 0.0f;
             }
+            // wait on this path only (the merged path would wait on every step)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
         } else {
             float nz[SW];
             noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 3u, g);
@@ -107,7 +123,7 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
         }
         const float* b0 = P.b0;
         if (N_ACT > 0) {
-            int a = reinterpret_cast<const int32_t*>(p.cands)[(size_t)k * p.H + t];
+            int a = ((const kconst int32_t*)p.cands)[(size_t)k * p.H + t];
             if (a < 0 || a >= N_ACT) {
                 if (p.status && lane == 0 && unit_ok) p.status[0] = 1;
                 a = 0;
@@ -115,12 +131,12 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
             b0 += (size_t)a * p.net.b0_stride;
         }
         float r_cur = 0.0f;
-        if (p.reward_at) r_cur = reward_of(st, p.goal, SS, D_S, g);
+        if (p.reward_at) r_cur = reward_to(st, goal, SS, D_S, g);
         f32x16 out = run_net<NT>(src, P, b0, slots, lane, g);
 #pragma unroll
         for (int s = 0; s < SS; ++s) st[s] += out[s];
-        float r = p.reward_at ? r_cur : reward_of(st, p.goal, SS, D_S, g);
-        G += (float)disc * r;
+        float r = p.reward_at ? r_cur : reward_to(st, goal, SS, D_S, g);
+        G = __builtin_fmaf((float)disc, r, G);
         disc *= p.gamma;
     }
     if (p.returns && g == 0 && valid) p.returns[(size_t)k * p.N + i] = G;
@@ -143,10 +159,10 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
     NetPtrs P = net_ptrs(MODE == kResident ? (const char*)smem : p.net.base, p.net);
     // streamed networks: the biases (and, for grouped wide networks, the first
     // layer) are staged in LDS after the two chunk buffers
-    constexpr int CHB = StreamChunk<NT>::CHB;
-    char* const extra = smem + 2 * CHB;
+    constexpr bool F0_LDS = NT::CT < NT::HT && first_layer_in_lds<NT>(N_ACT > 0 ? N_ACT : 1);
+    char* const extra = smem + StreamChunk<NT>::BYTES;
     if constexpr (MODE == kStream) {
-        const uint32_t f0_bytes = NT::CT < NT::HT ? (uint32_t)(NT::NF0 * NT::FRAG_BYTES) : 0u;
+        const uint32_t f0_bytes = F0_LDS ? (uint32_t)(NT::NF0 * NT::FRAG_BYTES) : 0u;
         if (f0_bytes) stage_blob(extra, P.f0, f0_bytes);
         char* bias = extra + f0_bytes;
         stage_blob(bias, p.net.base + p.net.off_b0, p.net.bytes - p.net.off_b0);
@@ -169,7 +185,7 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
     if constexpr (MODE == kStream && NT::CT < NT::HT) {
         // grouped wide network: the groups' fragments stream through the two
         // LDS chunk buffers, the first layer is read from its LDS copy
-        WideSrc<NT, GroupStream<NT>> src(extra, GroupStream<NT>(smem, P.fh));
+        WideSrc<NT, GroupStream<NT>> src(F0_LDS ? (const char*)extra : P.f0, GroupStream<NT>(smem, P.fh));
         src.hid.start();
         body(src);
         src.hid.finish();
@@ -692,7 +708,7 @@ template <int W> constexpr bool lds_for_width() { return W <= 64; }
 // weight access of the rollout kernel and of the single-pass kernels
 template <int W> constexpr int plan_mode() { return W <= 64 ? kResident : kStream; }
 template <int W> constexpr int pass_mode() { return W <= 64 ? kResident : kDirect; }
-constexpr size_t kStreamLds = 2 * 32768;
+constexpr size_t kStreamLds = 2 * (size_t)VOILA_STREAM_CHB;
 
 }  // namespace
 
@@ -714,11 +730,12 @@ VOILA_IN_SLOTS(lik_in_slots, in_slots(dt, s.d_s, 0, 0))
 
 // LDS of a streaming rollout kernel before its staged biases: the two chunk
 // buffers (and the first layer of a grouped wide network).
-template <int DT, int D_S, int D_AIN, int D_W, int WIDTH, int NHID>
+template <int DT, int D_S, int N_ACT, int D_AIN, int D_W, int WIDTH, int NHID>
 constexpr size_t stream_lds_of() {
     if constexpr (DT == DT_BF16 && WIDTH > 256) {
         typedef Net<DT_BF16, WIDTH, NHID, in_slots(DT_BF16, D_S, D_AIN, D_W)> NT;
-        return 2 * (size_t)GroupStream<NT>::CHB + (size_t)NT::NF0 * NT::FRAG_BYTES;
+        return (size_t)StreamChunk<NT>::BYTES +
+               (first_layer_in_lds<NT>(N_ACT > 0 ? N_ACT : 1) ? (size_t)NT::NF0 * NT::FRAG_BYTES : 0);
     } else {
         return kStreamLds;
     }
@@ -727,9 +744,9 @@ size_t plan_stream_lds(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                      \
     case id * 2 + 0:                                                               \
-        return stream_lds_of<DT_F32, ds, (na > 0 ? 0 : da), dw, w, nh>();            \
+        return stream_lds_of<DT_F32, ds, na, (na > 0 ? 0 : da), dw, w, nh>();            \
     case id * 2 + 1:                                                               \
-        return stream_lds_of<DT_BF16, ds, (na > 0 ? 0 : da), dw, w, nh>();
+        return stream_lds_of<DT_BF16, ds, na, (na > 0 ? 0 : da), dw, w, nh>();
         VOILA_SHAPES(X)
 #undef X
     }
