@@ -175,6 +175,7 @@ struct LargeResWs {
     double* scal;    // [0] max, [1] sum
     int* last;       // last positive-mass particle overall
     int* starts;     // [chunks + 1] particle of the first output of each output block
+    int* idx;        // [N] indices when the caller keeps none
 };
 
 struct LargeResParams {

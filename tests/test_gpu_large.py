@@ -116,3 +116,16 @@ def test_reweight_resample_fused(V, N):
         assert np.array_equal(idx, oracle.resample(w, U))
         assert np.array_equal(out["dst"].cpu().numpy(), src[idx])
         assert np.array_equal(w, w2.cpu().numpy()) and np.array_equal(idx, idx2.cpu().numpy())
+
+
+def test_large_update_without_index_output(V):
+    # the gather reads the indices back from the workspace when the caller keeps none
+    w = workloads.small(seed=43, N=30000)
+    m = V.Model(w.model)
+    o = oracle.draw_observation(w).astype(np.float32)
+    a = V.update(m, dev(w.states), w.update_action, o, lam=w.lam, seed=w.update_seed, U=w.resample_u)
+    b = V.update(m, dev(w.states), w.update_action, o, lam=w.lam, seed=w.update_seed, U=w.resample_u,
+                 want_idx=False)
+    torch.cuda.synchronize()
+    assert b["idx"] is None
+    assert torch.equal(a["states"], b["states"])
