@@ -56,6 +56,9 @@ constexpr int DT_BF16 = 1;
 #ifndef VOILA_STREAM_CHB
 #define VOILA_STREAM_CHB 32768
 #endif
+#ifndef VOILA_STREAM_NBUF
+#define VOILA_STREAM_NBUF 2
+#endif
 constexpr int kPfDepth = VOILA_PF_DEPTH;
 
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -281,25 +284,32 @@ struct DirectSrc {
 // chunk's direct-to-LDS loads, meet at a barrier (which also retires chunk
 // ch - 1 from the other buffer) and then start loading chunk ch + 1 into that
 // other buffer, so the next chunk streams in while this one is multiplied.
+// s_waitcnt immediate: wait until at most `vm` vector-memory operations of
+// this wave are outstanding and all of its LDS operations are done.
+__host__ __device__ constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4); }
+
+// Streaming source of binary32 networks (their evaluation reaches the loads
+// from run-time fragment positions): two chunk buffers, a full wait and a
+// workgroup barrier at every chunk boundary, the next chunk's direct-to-LDS
+// loads issued right after it.
 template <class N, int CHB = VOILA_STREAM_CHB, int WIN = 4 * N::HT>
-struct StreamSrc {
+struct StreamSrc32 {
     static constexpr int FB = N::FRAG_BYTES;
     static constexpr int FPC = CHB / FB;  // fragments per chunk
     static constexpr int NFR = N::NF0 + (N::NHID - 1) * N::NFH + N::NFO;
     static constexpr int NCH = cdiv(NFR, FPC);
     static constexpr int TOTAL = NFR * FB;
+    static constexpr int LDS_BYTES = 2 * CHB;
     static_assert(CHB % 4096 == 0 && CHB % FB == 0, "chunk must be whole DMA rounds and fragments");
     static_assert(TOTAL % 1024 == 0, "the fragment stream must be whole 1 KB DMA rounds");
-    char* lds;          // 2 * CHB bytes of LDS
-    const char* src;    // packed fragment stream in global memory
-    int cur;            // buffer of the current chunk
-    const char* win;    // current chunk's buffer, refreshed every WIN fragments
+    char* lds;
+    const char* src;
+    int cur;
+    const char* win;
 
-    __device__ __forceinline__ StreamSrc(char* l, const char* s) : lds(l), src(s), cur(1), win(l) {}
+    __device__ __forceinline__ StreamSrc32(char* l, const char* s) : lds(l), src(s), cur(1), win(l) {}
 
-    // Copies chunk ch into buffer b: each wave moves 1 KB per round (64 lanes x 16 B).
     __device__ __forceinline__ void fetch(int ch, int b) const {
-        // wave-uniform chunk addresses (scalar base + per-lane 16 B offset)
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
         const int lane = threadIdx.x & 63;
@@ -319,6 +329,67 @@ struct StreamSrc {
             __syncthreads();
             cur ^= 1;
             fetch(ch + 1 < NCH ? ch + 1 : 0, cur ^ 1);
+        }
+        if (within % WIN == 0) win = lds + cur * CHB + opaque_zero();
+        return Frag<N::DT>::load(win, within, lane);
+    }
+    __device__ __forceinline__ void finish() { __builtin_amdgcn_s_waitcnt(0); }
+};
+
+// Streaming source of bfloat16 networks, whose evaluation is unrolled at
+// compile time: NBUF chunk buffers, the packed stream padded to whole chunks.
+template <class N, int CHB = VOILA_STREAM_CHB, int NBUF = VOILA_STREAM_NBUF, int WIN = 4 * N::HT>
+struct StreamSrc {
+    static constexpr int FB = N::FRAG_BYTES;
+    static constexpr int FPC = CHB / FB;  // fragments per chunk
+    static constexpr int NFR = N::NF0 + (N::NHID - 1) * N::NFH + N::NFO;
+    static constexpr int NCH = cdiv(NFR, FPC);  // the packed stream is padded to whole chunks
+    static constexpr int kWaves = 4;            // waves of the workgroup
+    static constexpr int ROUNDS = CHB / 1024 / kWaves;
+    static constexpr int LDS_BYTES = NBUF * CHB;
+    static_assert(CHB % (1024 * kWaves) == 0 && CHB % FB == 0, "chunk must be whole DMA rounds and fragments");
+    static_assert(NBUF >= 2 && (NBUF - 2) * ROUNDS <= 63 && NCH >= NBUF, "bad chunk pipeline");
+    char* lds;          // NBUF * CHB bytes of LDS
+    const char* src;    // packed fragment stream in global memory
+    int cur, nxt_buf;   // buffer of the current chunk, buffer of the next load
+    const char* win;    // current chunk's buffer, refreshed every WIN fragments
+
+    __device__ __forceinline__ StreamSrc(char* l, const char* s)
+        : lds(l), src(s), cur(NBUF - 1), nxt_buf(NBUF - 1), win(l) {}
+
+    // Copies chunk ch into buffer b: each wave moves a quarter, 1 KB per
+    // round (64 lanes x 16 B), with direct-to-LDS loads.
+    __device__ __forceinline__ void fetch(int ch, int b) const {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        const char* base = src + opaque_zero() + (size_t)ch * CHB;
+        auto round = [&](int r) {
+            const int off = (r * kWaves + wave) * 1024;
+            __builtin_amdgcn_global_load_lds((const void*)(base + off + lane * 16),
+                                             (__attribute__((address_space(3))) void*)(lds + b * CHB + off), 16, 0,
+                                             0);
+        };
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) round(r);
+    }
+    __device__ __forceinline__ void start() {
+#pragma unroll
+        for (int j = 0; j < NBUF - 1; ++j) fetch(j, j);
+    }
+    // At the first fragment of a chunk: wait until only this wave's loads of
+    // the NBUF - 2 newer chunks are outstanding and its LDS reads are done,
+    // meet the workgroup (the chunk is then complete and the buffer read
+    // before it free), and start loading the chunk NBUF - 1 ahead there.
+    __device__ __forceinline__ typename Frag<N::DT>::type load(int f, int lane) {
+        const int ch = f / FPC, within = f % FPC;
+        if (within == 0) {
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NBUF - 2) * ROUNDS));
+            __builtin_amdgcn_s_barrier();
+            cur = cur + 1 == NBUF ? 0 : cur + 1;
+            int nxt = ch + NBUF - 1;
+            nxt = nxt < NCH ? nxt : nxt - NCH;
+            fetch(nxt, nxt_buf);
+            nxt_buf = nxt_buf + 1 == NBUF ? 0 : nxt_buf + 1;
         }
         if (within % WIN == 0) win = lds + cur * CHB + opaque_zero();
         return Frag<N::DT>::load(win, within, lane);
@@ -470,10 +541,6 @@ struct GroupDirect {  // group fragments straight from global memory (L2)
     __device__ __forceinline__ void finish() {}
 };
 
-// s_waitcnt immediate: wait until at most `vm` vector-memory operations of
-// this wave are outstanding and all of its LDS operations are done.
-__host__ __device__ constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4); }
-
 // Group fragments streamed through NBUF LDS chunk buffers shared by the
 // workgroup of four waves; a group is CPG whole chunks, so every chunk
 // boundary sits at a compile-time position of the group.  Each wave moves a
@@ -537,8 +604,12 @@ struct GroupStream {
 };
 
 // Bytes of one LDS chunk buffer of a streaming network source.
+// The streaming source of a network evaluated layer by layer.
+template <class N>
+using StreamFor = typename std::conditional<N::DT == DT_F32, StreamSrc32<N>, StreamSrc<N>>::type;
+
 template <class N, bool G = (N::CT < N::HT)> struct StreamChunk {
-    static constexpr int BYTES = 2 * VOILA_STREAM_CHB;  // LDS of the chunk buffers
+    static constexpr int BYTES = StreamFor<N>::LDS_BYTES;  // LDS of the chunk buffers
 };
 template <class N> struct StreamChunk<N, true> {
     static constexpr int BYTES = GroupStream<N>::LDS_BYTES;
@@ -550,7 +621,10 @@ template <class N> struct StreamChunk<N, true> {
 constexpr int kLdsMax = 160 * 1024;
 template <class N>
 __host__ __device__ constexpr bool first_layer_in_lds(int n_var) {
-    return StreamChunk<N>::BYTES + N::NF0 * N::FRAG_BYTES + (n_var + N::NHID - 1) * N::WIDTH * 4 + 1024 <= kLdsMax;
+    if constexpr (N::CT < N::HT)
+        return StreamChunk<N>::BYTES + N::NF0 * N::FRAG_BYTES + (n_var + N::NHID - 1) * N::WIDTH * 4 + 1024 <= kLdsMax;
+    else
+        return false;
 }
 
 template <class N, class HS>

@@ -160,8 +160,9 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
     // streamed networks: the biases (and, for grouped wide networks, the first
     // layer) are staged in LDS after the two chunk buffers
     constexpr bool F0_LDS = NT::CT < NT::HT && first_layer_in_lds<NT>(N_ACT > 0 ? N_ACT : 1);
-    char* const extra = smem + StreamChunk<NT>::BYTES;
+    char* extra = smem;
     if constexpr (MODE == kStream) {
+        extra = smem + StreamChunk<NT>::BYTES;
         const uint32_t f0_bytes = F0_LDS ? (uint32_t)(NT::NF0 * NT::FRAG_BYTES) : 0u;
         if (f0_bytes) stage_blob(extra, P.f0, f0_bytes);
         char* bias = extra + f0_bytes;
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
         body(src);
         src.hid.finish();
     } else if constexpr (MODE == kStream) {
-        StreamSrc<NT> src(smem, P.f0);
+        StreamFor<NT> src(smem, P.f0);
         src.start();
         body(src);
         src.finish();
@@ -708,7 +709,7 @@ template <int W> constexpr bool lds_for_width() { return W <= 64; }
 // weight access of the rollout kernel and of the single-pass kernels
 template <int W> constexpr int plan_mode() { return W <= 64 ? kResident : kStream; }
 template <int W> constexpr int pass_mode() { return W <= 64 ? kResident : kDirect; }
-constexpr size_t kStreamLds = 2 * (size_t)VOILA_STREAM_CHB;
+constexpr size_t kStreamLds = (size_t)VOILA_STREAM_NBUF * VOILA_STREAM_CHB;
 
 }  // namespace
 
@@ -732,12 +733,13 @@ VOILA_IN_SLOTS(lik_in_slots, in_slots(dt, s.d_s, 0, 0))
 // buffers (and the first layer of a grouped wide network).
 template <int DT, int D_S, int N_ACT, int D_AIN, int D_W, int WIDTH, int NHID>
 constexpr size_t stream_lds_of() {
-    if constexpr (DT == DT_BF16 && WIDTH > 256) {
-        typedef Net<DT_BF16, WIDTH, NHID, in_slots(DT_BF16, D_S, D_AIN, D_W)> NT;
-        return (size_t)StreamChunk<NT>::BYTES +
-               (first_layer_in_lds<NT>(N_ACT > 0 ? N_ACT : 1) ? (size_t)NT::NF0 * NT::FRAG_BYTES : 0);
-    } else {
+    if constexpr (!net_compiled(DT, WIDTH) || WIDTH <= 64) {
         return kStreamLds;
+    } else {
+        typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_AIN, D_W)> NT;
+        return (size_t)StreamChunk<NT>::BYTES +
+               (NT::CT < NT::HT && first_layer_in_lds<NT>(N_ACT > 0 ? N_ACT : 1) ? (size_t)NT::NF0 * NT::FRAG_BYTES
+                                                                                : 0);
     }
 }
 size_t plan_stream_lds(int shape, int dt) {
