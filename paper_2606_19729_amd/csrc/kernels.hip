@@ -67,8 +67,8 @@ constexpr int kStream = 2;    // streamed through double-buffered LDS chunks
 // and their (weighted) sum.  `unit_ok` false runs a masked dummy tile (the
 // caller's loop is block-uniform) that writes nothing.
 template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, class Src>
-__device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const PlanParams& p, long u, bool unit_ok,
-                                          int lane, int g, int col) {
+__device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const PlanParams& p, const float* goal_src,
+                                          long u, bool unit_ok, int lane, int g, int col) {
     constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
     // the unit (candidate, tile) is uniform over the wave: its candidate's
@@ -84,7 +84,7 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
     for (int s = 0; s < SS; ++s) {
         int f = 2 * s + g;
         st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
-        goal[s] = f < D_S ? p.goal[f] : 0.0f;
+        goal[s] = f < D_S ? goal_src[f] : 0.0f;
     }
     // complete these loads here, once per unit, so that no wait for them (and
     // with them for the weight stream's loads in flight) lands in the step loop
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
         // (unit, step) iterations, idle waves on a masked dummy unit
         for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
             const long u = ub * wpb + wave;
-            plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, u, u < n_units, lane, g, col);
+            plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, p.goal, u, u < n_units, lane, g, col);
         }
     };
     if constexpr (MODE == kStream && NT::CT < NT::HT) {
@@ -241,7 +241,10 @@ __global__ __launch_bounds__(512) void plan_batch_kernel(BatchPlanParams bp) {
         const NetPtrs P = net_ptrs(smem, p.net);
         DirectSrc<DT, 8 * NT::HT> src(P.f0);
         const long u = (long)it.y + wave;
-        plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, u, wave < it.z, lane, g, col);
+        // the goal is read from the instance table (a lane-indexed read of the
+        // copy above would place the whole copy in scratch memory)
+        plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, bp.insts[it.x].goal, u, wave < it.z, lane, g,
+                                                         col);
     }
     }
 }

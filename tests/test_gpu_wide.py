@@ -20,11 +20,15 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-# Bounds for width 1024 (calibrated like the width-64/256 ones: twice the
-# largest error over seeds, rounded up to a power of two).
+# Bounds for width 1024, calibrated like the width-64/256 ones: twice the
+# largest error seen over 13 seeds (3..14 and 31) at these counts, rounded up
+# to a power of two.  Largest seen: Q vs binary64 9.9e-3, Q vs bfloat16
+# emulation 2.9e-4, observations vs emulation 7.5e-4 (of their scale),
+# posterior mean 1.7e-3 posterior standard deviations.
 BOUND_Q_FP64 = 2.0 ** -5
-BOUND_Q_EMUL = 2.0 ** -9
-BOUND_POST = 2.0 ** -6
+BOUND_Q_EMUL = 2.0 ** -10
+BOUND_OBS = 2.0 ** -9
+BOUND_POST = 2.0 ** -8
 
 
 @pytest.fixture(scope="module")
@@ -135,7 +139,7 @@ def test_wide_plan_update_observe_within_bounds(V, seed):
     print(f"  Q err vs fp64 {e64:.2e} vs bf16-emulation {eem:.2e}; obs vs emulation {e_obs:.2e}; "
           f"posterior mean {post:.2e} sd", flush=True)
     assert e64 <= BOUND_Q_FP64 and eem <= BOUND_Q_EMUL
-    assert e_obs <= BOUND_Q_EMUL
+    assert e_obs <= BOUND_OBS
     assert post <= BOUND_POST
     assert np.array_equal(out["idx"].cpu().numpy(), oracle.resample(wd, w.resample_u))
 
