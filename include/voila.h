@@ -102,7 +102,11 @@ const char* voila_last_error(void);
  * first-layer biases; bfloat16 rounding to nearest even for VOILA_BF16) on
  * device `device` and returns an owned handle.  Host arrays are only read
  * during the call.  Fails with VOILA_ERR_UNSUPPORTED for shapes without a
- * compiled kernel. */
+ * compiled kernel.  Compiled shapes (d_s, actions, d_w, d_o, d_wz, hidden
+ * layers x width): (4, 5 discrete, 4, 2, 2, 2 x 64); (4, d_a = 4, 4, 2, 2,
+ * 2 x 64); (16, d_a = 4, 16, 32, 32, 3 x 256); (4, 5 discrete, 4, 2, 2,
+ * 2 x 1024, VOILA_BF16 only: binary32 activations of that width do not fit
+ * in registers). */
 voila_status_t voila_model_create(const voila_model_desc_t* h_desc, int32_t device, voila_model_t* out);
 /* [sync] Frees a model (NULL is accepted). */
 voila_status_t voila_model_destroy(voila_model_t model);
