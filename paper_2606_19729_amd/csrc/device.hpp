@@ -380,6 +380,12 @@ struct StreamSrc {
     // the NBUF - 2 newer chunks are outstanding and its LDS reads are done,
     // meet the workgroup (the chunk is then complete and the buffer read
     // before it free), and start loading the chunk NBUF - 1 ahead there.
+    // The loads of the chunk NBUF - 1 ahead are spread over the fragments the
+    // current chunk actually serves (the last chunk is padding past its end):
+    // round r is issued at fragment floor(r * V / ROUNDS) of a chunk of V
+    // served fragments (positions are compile-time constants).
+    static constexpr int LASTF = NFR - (NCH - 1) * FPC;
+    int nxt_ch = 0;
     __device__ __forceinline__ typename Frag<N::DT>::type load(int f, int lane) {
         const int ch = f / FPC, within = f % FPC;
         if (within == 0) {
@@ -387,9 +393,18 @@ struct StreamSrc {
             __builtin_amdgcn_s_barrier();
             cur = cur + 1 == NBUF ? 0 : cur + 1;
             int nxt = ch + NBUF - 1;
-            nxt = nxt < NCH ? nxt : nxt - NCH;
-            fetch(nxt, nxt_buf);
-            nxt_buf = nxt_buf + 1 == NBUF ? 0 : nxt_buf + 1;
+            nxt_ch = nxt < NCH ? nxt : nxt - NCH;
+        }
+        const int served = ch == NCH - 1 ? LASTF : FPC;
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            if ((r * served) / ROUNDS != within) continue;
+            const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            const int off = (r * kWaves + wave) * 1024;
+            __builtin_amdgcn_global_load_lds(
+                (const void*)(src + opaque_zero() + (size_t)nxt_ch * CHB + off + (threadIdx.x & 63) * 16),
+                (__attribute__((address_space(3))) void*)(lds + nxt_buf * CHB + off), 16, 0, 0);
+            if (r == ROUNDS - 1) nxt_buf = nxt_buf + 1 == NBUF ? 0 : nxt_buf + 1;
         }
         if (within % WIN == 0) win = lds + cur * CHB + opaque_zero();
         return Frag<N::DT>::load(win, within, lane);
@@ -567,7 +582,7 @@ struct GroupStream {
     int cur, nxt_buf, gch;
     const char* win;
     __device__ __forceinline__ GroupStream(char* l, const char* s)
-        : lds(l), src(s), cur(NBUF - 1), nxt_buf(NBUF - 1), gch(0), win(l) {}
+        : lds(l), src(s), cur(NBUF - 1), nxt_buf(NBUF - 1), gch(0), win(l), nxt_ch(0) {}
     __device__ __forceinline__ void fetch(int ch, int b) const {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
@@ -585,6 +600,20 @@ struct GroupStream {
         for (int j = 0; j < NBUF - 1; ++j) fetch(j, j);
     }
     __device__ __forceinline__ void begin_group(int gi) { gch = gi * CPG; }
+    // One 1 KB load of chunk ch into buffer b (round r of this wave).
+    __device__ __forceinline__ void fetch_round(int ch, int b, int r) const {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        const int off = (r * kWaves + wave) * 1024;
+        __builtin_amdgcn_global_load_lds((const void*)(src + opaque_zero() + (size_t)ch * CHB + off + lane * 16),
+                                         (__attribute__((address_space(3))) void*)(lds + b * CHB + off), 16, 0, 0);
+    }
+    // The loads of the chunk NBUF - 1 ahead are spread over the current chunk
+    // (one round every SPREAD fragments) rather than issued in a burst at its
+    // boundary, where four waves queueing behind the address unit would stall.
+    static constexpr int SPREAD = FPC / ROUNDS;
+    static_assert(FPC % ROUNDS == 0, "every fragment of a group is served: rounds must divide a chunk");
+    int nxt_ch;
     template <int POS>
     __device__ __forceinline__ typename Frag<N::DT>::type load(int lane) {
         constexpr int within = POS % FPC;
@@ -593,9 +622,11 @@ struct GroupStream {
             __builtin_amdgcn_s_barrier();
             cur = cur + 1 == NBUF ? 0 : cur + 1;
             int nxt = gch + POS / FPC + NBUF - 1;
-            nxt = nxt < NCH ? nxt : nxt - NCH;
-            fetch(nxt, nxt_buf);
-            nxt_buf = nxt_buf + 1 == NBUF ? 0 : nxt_buf + 1;
+            nxt_ch = nxt < NCH ? nxt : nxt - NCH;
+        }
+        if constexpr (within % SPREAD == 0 && within / SPREAD < ROUNDS) {
+            fetch_round(nxt_ch, nxt_buf, within / SPREAD);
+            if constexpr (within / SPREAD == ROUNDS - 1) nxt_buf = nxt_buf + 1 == NBUF ? 0 : nxt_buf + 1;
         }
         if constexpr (within % WINF == 0) win = lds + cur * CHB + within * FB + opaque_zero();
         return Frag<N::DT>::load(win, within % WINF, lane);
