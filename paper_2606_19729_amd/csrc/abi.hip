@@ -663,7 +663,8 @@ voila_status_t voila_update(voila_model_t m, const float* d_states, const double
     p.key0 = (uint32_t)(o->seed & 0xffffffffu);
     p.key1 = (uint32_t)(o->seed >> 32);
     const int n_tiles = (N + 31) / 32;
-    const int want = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int tpb = pass_tiles_per_block(m->shape);
+    const int want = (n_tiles + tpb - 1) / tpb;
     const int cap = m->cus * m->prop_bpc;
     VOILA_CHECK_HIP(launch_propose(m->shape, m->dt, p, want < cap ? want : cap, s));
     if (N > kNormResMaxN) {
@@ -869,7 +870,8 @@ voila_status_t voila_observe(voila_model_t m, const float* d_states, int32_t n, 
     p.key0 = (uint32_t)(seed & 0xffffffffu);
     p.key1 = (uint32_t)(seed >> 32);
     const int n_tiles = (n + 31) / 32;
-    const int want = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int tpb = pass_tiles_per_block(m->shape);
+    const int want = (n_tiles + tpb - 1) / tpb;
     const int cap = m->cus * m->obs_bpc;
     VOILA_CHECK_HIP(launch_observe(m->shape, m->dt, p, want < cap ? want : cap, s));
     return VOILA_OK;

@@ -736,6 +736,103 @@ __device__ __forceinline__ f32x16 run_net_grouped(Src& src, const NetPtrs& P, co
     return out[0];
 }
 
+// Layered networks evaluated by the four waves of a workgroup together, on
+// the same 32 rollouts (a pass over few particles then keeps four SIMDs busy
+// per tile instead of one): wave w produces the 32-row tiles
+// [w HT/4, (w + 1) HT/4) of every hidden layer, the activations pass through
+// LDS with each tile's registers stored as they are (so k-step c of the next
+// layer reads its B operand at [c][lane]), the output layer's k-steps are
+// split over the waves and the four partial tiles are added in wave order.
+// Weights are read from global memory at per-wave offsets, D - 1 k-steps
+// ahead.
+template <class N> struct SplitLds {
+    static constexpr int ACT = N::DT == DT_F32 ? N::HT * 16 * 64 * 4 : 2 * N::HT * 64 * 16;
+    static constexpr int PART = 4 * 16 * 64 * 4;
+    static constexpr int BYTES = ACT + PART;
+};
+
+template <class N>
+__device__ __forceinline__ typename Frag<N::DT>::type split_act(const char* lds, int c, int lane) {
+    return reinterpret_cast<const typename Frag<N::DT>::type*>(lds)[c * 64 + lane];
+}
+
+template <class N, int TPW>
+__device__ __forceinline__ void split_store(char* lds, const f32x16 (&acc)[TPW], int t0, int lane) {
+    if constexpr (N::DT == DT_F32) {
+        float* a = reinterpret_cast<float*>(lds);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) a[((t0 + t) * 16 + i) * 64 + lane] = fmaxf(acc[t][i], 0.0f);
+    } else {
+        bf16x8* a = reinterpret_cast<bf16x8*>(lds);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                bf16x8 v;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = (__bf16)fmaxf(acc[t][8 * h + j], 0.0f);
+                a[(2 * (t0 + t) + h) * 64 + lane] = v;
+            }
+    }
+}
+
+template <class N>
+__device__ __forceinline__ f32x16 run_net_split(const NetPtrs& P, const float* b0, const float (&slots)[N::IN_SLOTS],
+                                                int lane, int g, int wave, char* lds) {
+    static_assert(N::HT % 4 == 0 && N::CT == N::HT, "split evaluation needs a layered network of 4k tiles");
+    constexpr int TPW = N::HT / 4, KQ = N::HID_KS / 4;
+    constexpr int D = N::DT == DT_F32 ? 16 : 8;
+    typedef typename Frag<N::DT>::type FT;
+    typedef FragIdx<N> FI;
+    const int t0 = wave * TPW;
+    // the fragments of k-step c start HT fragments after those of k-step c - 1;
+    // a fresh scalar base per k-step keeps every load's offset small
+    auto kstep = [&](const char* base, int c) { return base + (size_t)c * N::HT * N::FRAG_BYTES + opaque_zero(); };
+    f32x16 acc[TPW];
+    init_bias<TPW>(acc, b0 + 32 * t0 + opaque_zero(), g);
+    {
+        const char* base = P.f0 + (size_t)FI::first(0, t0) * N::FRAG_BYTES + opaque_zero();
+        mfma_layer<N::IN_KS, TPW, D, FT>(
+            acc, [&](int c, int t) { return Frag<N::DT>::load(kstep(base, c), t, lane); },
+            [&](int c) { return Slots<N::DT, N::IN_SLOTS>::b(slots, c); });
+    }
+    split_store<N, TPW>(lds, acc, t0, lane);
+    __syncthreads();
+    static_for<N::NHID - 1>([&](auto li) {
+        constexpr int l = decltype(li)::value + 1;
+        init_bias<TPW>(acc, P.bh + (l - 1) * N::WIDTH + 32 * t0 + opaque_zero(), g);
+        const char* base = P.f0 + (size_t)FI::hidden(l, 0, t0) * N::FRAG_BYTES + opaque_zero();
+        mfma_layer<N::HID_KS, TPW, D, FT>(
+            acc, [&](int c, int t) { return Frag<N::DT>::load(kstep(base, c), t, lane); },
+            [&](int c) { return split_act<N>(lds, c, lane); });
+        __syncthreads();
+        split_store<N, TPW>(lds, acc, t0, lane);
+        __syncthreads();
+    });
+    f32x16 part[1];
+    init_bias<1>(part, P.bo + opaque_zero(), g);
+    if (wave != 0) part[0] = f32x16{};
+    {
+        const int k0 = wave * KQ;
+        const char* base = P.f0 + (size_t)(FI::out(0) + k0) * N::FRAG_BYTES + opaque_zero();
+        mfma_layer<KQ, 1, D, FT>(
+            part, [&](int c, int) { return Frag<N::DT>::load(base + (size_t)c * N::FRAG_BYTES + opaque_zero(), 0, lane); },
+            [&](int c) { return split_act<N>(lds, k0 + c, lane); });
+    }
+    float* pl = reinterpret_cast<float*>(lds + SplitLds<N>::ACT);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) pl[(wave * 16 + i) * 64 + lane] = part[0][i];
+    __syncthreads();
+    f32x16 out;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        out[i] = ((pl[i * 64 + lane] + pl[(16 + i) * 64 + lane]) + pl[(32 + i) * 64 + lane]) + pl[(48 + i) * 64 + lane];
+    __syncthreads();
+    return out;
+}
+
 // Fragment source of a network read straight from global memory: the plain
 // source for networks evaluated layer by layer, the grouped bundle otherwise.
 template <class N, bool GROUPED = (N::CT < N::HT)> struct DirectFor;

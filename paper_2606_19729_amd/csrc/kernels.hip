@@ -61,6 +61,7 @@ constexpr bool net_compiled(int dt, int width) { return dt == DT_BF16 || width <
 constexpr int kDirect = 0;    // straight from global memory (L2)
 constexpr int kResident = 1;  // whole network staged in LDS once per block
 constexpr int kStream = 2;    // streamed through double-buffered LDS chunks
+constexpr int kSplit = 3;     // the four waves of a block split each layer of one tile (global memory)
 
 // One (candidate, 32-particle) tile of one planning instance: H steps of the
 // transition network with the states in registers, then the tile's returns
@@ -324,9 +325,10 @@ __global__ __launch_bounds__(256) void fold_batch_kernel(const FoldBatchItem* it
 // ---------------------------------------------------------------------------
 // One 32-particle tile of the update's first stage: proposal through the
 // transition network, likelihood of the proposal, x = l / lambda (+ log prior).
-template <int DT, int D_S, int D_W, int WIDTH, int NHID>
+template <int DT, int D_S, int D_W, int WIDTH, int NHID, bool SPLIT = false>
 __device__ __forceinline__ void propose_tile(const NetPtrs& PT, const NetPtrs& PL, const ProposeParams& p, int tile,
-                                             bool tile_ok, int lane, int g, int col) {
+                                             bool tile_ok, int lane, int g, int col, int wave = 0,
+                                             char* lds = nullptr) {
     constexpr int SS = state_slots(D_S), SW = noise_slots(D_W);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_W)> NTT;
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, 0)> NTL;
@@ -354,8 +356,14 @@ __device__ __forceinline__ void propose_tile(const NetPtrs& PT, const NetPtrs& P
 #pragma unroll
         for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
     }
-    auto srct = DirectFor<NTT>::make(PT);
-    f32x16 d = run_net<NTT>(srct, PT, p.b0_trans, slots, lane, g);
+    f32x16 d;
+    if constexpr (SPLIT) {
+        d = run_net_split<NTT>(PT, p.b0_trans, slots, lane, g, wave, lds);
+    } else {
+        auto srct = DirectFor<NTT>::make(PT);
+        d = run_net<NTT>(srct, PT, p.b0_trans, slots, lane, g);
+    }
+    const bool writer = !SPLIT || wave == 0;  // a split tile is written by its first wave
     float ls[NTL::IN_SLOTS];
 #pragma unroll
     for (int s = 0; s < NTL::IN_SLOTS; ++s) ls[s] = 0.0f;
@@ -364,11 +372,16 @@ __device__ __forceinline__ void propose_tile(const NetPtrs& PT, const NetPtrs& P
         int f = 2 * s + g;
         st[s] += d[s];
         ls[s] = st[s];
-        if (valid && f < D_S) p.prop[(size_t)i * D_S + f] = st[s];
+        if (writer && valid && f < D_S) p.prop[(size_t)i * D_S + f] = st[s];
     }
-    auto srcl = DirectFor<NTL>::make(PL);
-    f32x16 lo = run_net<NTL>(srcl, PL, p.b0_lik, ls, lane, g);
-    if (g == 0 && valid) {
+    f32x16 lo;
+    if constexpr (SPLIT) {
+        lo = run_net_split<NTL>(PL, p.b0_lik, ls, lane, g, wave, lds);
+    } else {
+        auto srcl = DirectFor<NTL>::make(PL);
+        lo = run_net<NTL>(srcl, PL, p.b0_lik, ls, lane, g);
+    }
+    if (writer && g == 0 && valid) {
         float l = lo[0];
         if (p.loglik) p.loglik[i] = l;
         if (!isfinite(l) && p.status) p.status[0] = 5;
@@ -395,8 +408,14 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wpb = blockDim.x >> 6;
     const int n_tiles = (p.N + 31) / 32;
-    for (int tile = blockIdx.x * wpb + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * wpb)
-        propose_tile<DT, D_S, D_W, WIDTH, NHID>(PT, PL, p, tile, true, lane, g, col);
+    if constexpr (MODE == kSplit) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+            propose_tile<DT, D_S, D_W, WIDTH, NHID, true>(PT, PL, p, tile, true, lane, g, col, wave, smem);
+    } else {
+        for (int tile = blockIdx.x * wpb + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * wpb)
+            propose_tile<DT, D_S, D_W, WIDTH, NHID>(PT, PL, p, tile, true, lane, g, col);
+    }
     }
 }
 
@@ -458,9 +477,12 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
     }
     const NetPtrs PO = net_ptrs(WLDS ? (const char*)smem : p.obs.base, p.obs);
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
-    const int wpb = blockDim.x >> 6;
     const int n_tiles = (p.n + 31) / 32;
-    for (int tile = blockIdx.x * wpb + (threadIdx.x >> 6); tile < n_tiles; tile += gridDim.x * wpb) {
+    // split mode: the block's four waves evaluate one tile together
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tpb = MODE == kSplit ? 1 : (int)(blockDim.x >> 6);
+    const int first = MODE == kSplit ? (int)blockIdx.x : (int)blockIdx.x * tpb + wave;
+    for (int tile = first; tile < n_tiles; tile += gridDim.x * tpb) {
         const int r = tile * 32 + col;
         const bool valid = r < p.n;
         float slots[NTO::IN_SLOTS];
@@ -483,12 +505,18 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
 #pragma unroll
             for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
         }
-        auto srco = DirectFor<NTO>::make(PO);
-        f32x16 o = run_net<NTO>(srco, PO, p.b0, slots, lane, g);
+        f32x16 o;
+        if constexpr (MODE == kSplit) {
+            o = run_net_split<NTO>(PO, p.b0, slots, lane, g, wave, smem);
+        } else {
+            auto srco = DirectFor<NTO>::make(PO);
+            o = run_net<NTO>(srco, PO, p.b0, slots, lane, g);
+        }
+        const bool writer = MODE != kSplit || wave == 0;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             int f = 2 * s + g;
-            if (valid && f < D_O) p.out[(size_t)r * D_O + f] = o[s];
+            if (writer && valid && f < D_O) p.out[(size_t)r * D_O + f] = o[s];
         }
     }
     }
@@ -548,7 +576,23 @@ __device__ int block_max_i(int v, int* red) {
 
 }  // namespace
 
-__device__ void norm_res_body(const NormResParams& p, double* buf, double* redd, int* redi) {
+// dst row r = src row ids[r] for r < n (rows of w elements) by the whole
+// workgroup: each thread keeps one column and walks rows, so consecutive
+// threads move consecutive elements.
+template <class T>
+__device__ __forceinline__ void block_gather(T* dst, const T* src, const int* ids, int n, int w) {
+    const int nt = blockDim.x;
+    if (w <= nt) {
+        const int rpp = nt / w, r0 = threadIdx.x / w, c = threadIdx.x - r0 * w;
+        if (r0 < rpp)
+            for (int r = r0; r < n; r += rpp) dst[(size_t)r * w + c] = src[(size_t)ids[r] * w + c];
+    } else {
+        for (int r = 0; r < n; ++r)
+            for (int c = threadIdx.x; c < w; c += nt) dst[(size_t)r * w + c] = src[(size_t)ids[r] * w + c];
+    }
+}
+
+__device__ void norm_res_body(const NormResParams& p, double* buf, double* redd, int* redi, int* ids) {
     const int tid = threadIdx.x, N = p.N;
 
     if (!p.w_in) {
@@ -659,29 +703,37 @@ __device__ void norm_res_body(const NormResParams& p, double* buf, double* redd,
         }
         const int idx = a < N ? a : last;
         if (p.idx_out) p.idx_out[j] = idx;
-        if (p.src && p.dst)
-            for (int c = 0; c < p.row_floats; ++c)
-                p.dst[(size_t)j * p.row_floats + c] = p.src[(size_t)idx * p.row_floats + c];
+        ids[j] = idx;
+    }
+    if (p.src && p.dst) {
+        __syncthreads();
+        const int rf = p.row_floats;
+        if (rf % 4 == 0 && ((reinterpret_cast<uintptr_t>(p.src) | reinterpret_cast<uintptr_t>(p.dst)) & 15) == 0)
+            block_gather(reinterpret_cast<float4*>(p.dst), reinterpret_cast<const float4*>(p.src), ids, N, rf / 4);
+        else
+            block_gather(p.dst, p.src, ids, N, rf);
     }
 }
 
 __global__ __launch_bounds__(kNormResThreads) void norm_res_kernel(NormResParams p) {
     __shared__ double buf[kNormResMaxN];
+    __shared__ int ids[kNormResMaxN];
     __shared__ double redd[kNRWaves];
     __shared__ int redi[kNRWaves];
-    norm_res_body(p, buf, redd, redi);
+    norm_res_body(p, buf, redd, redi, ids);
 }
 
 // One workgroup per instance.
 __global__ __launch_bounds__(kNormResThreads) void norm_res_batch_kernel(const NormResParams* ps, const uint32_t* us,
                                                                           int32_t* status) {
     __shared__ double buf[kNormResMaxN];
+    __shared__ int ids[kNormResMaxN];
     __shared__ double redd[kNRWaves];
     __shared__ int redi[kNRWaves];
     NormResParams p = ps[blockIdx.x];
     if (us) p.U = us[blockIdx.x];
     p.status = status;
-    norm_res_body(p, buf, redd, redi);
+    norm_res_body(p, buf, redd, redi, ids);
 }
 
 __global__ __launch_bounds__(256) void philox_kernel(PhiloxParams p) {
@@ -711,7 +763,7 @@ namespace {
 template <int W> constexpr bool lds_for_width() { return W <= 64; }
 // weight access of the rollout kernel and of the single-pass kernels
 template <int W> constexpr int plan_mode() { return W <= 64 ? kResident : kStream; }
-template <int W> constexpr int pass_mode() { return W <= 64 ? kResident : kDirect; }
+template <int W> constexpr int pass_mode() { return W <= 64 ? kResident : W <= 256 ? kSplit : kDirect; }
 constexpr size_t kStreamLds = (size_t)VOILA_STREAM_NBUF * VOILA_STREAM_CHB;
 
 }  // namespace
@@ -784,8 +836,13 @@ hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipSt
     return hipGetLastError();
 }
 
+// Split-mode passes (one tile per block, LDS for activations and partials).
+bool pass_split(int shape) { return kShapeInfo[shape].width > 64 && kShapeInfo[shape].width <= 256; }
+int pass_tiles_per_block(int shape) { return pass_split(shape) ? 1 : 4; }
+constexpr size_t kSplitLds = 48 * 1024;  // binary32 width 256: 32 KB activations + 16 KB partials
+
 hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s) {
-    const size_t lds = weights_in_lds(shape) ? (size_t)p.trans.bytes + p.lik.bytes : 0;
+    const size_t lds = weights_in_lds(shape) ? (size_t)p.trans.bytes + p.lik.bytes : pass_split(shape) ? kSplitLds : 0;
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
     case id * 2 + 0:                                                                                       \
@@ -803,7 +860,7 @@ hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks,
 }
 
 hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s) {
-    const size_t lds = weights_in_lds(shape) ? p.obs.bytes : 0;
+    const size_t lds = weights_in_lds(shape) ? p.obs.bytes : pass_split(shape) ? kSplitLds : 0;
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                             \
     case id * 2 + 0:                                                                                      \
@@ -847,9 +904,9 @@ int propose_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                   \
     case id * 2 + 0:                                                                                            \
-        return occupancy(PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? 2 * kLdsGuess : 0); \
+        return occupancy(PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? 2 * kLdsGuess : kSplitLds); \
     case id * 2 + 1:                                                                                            \
-        return occupancy(PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? 2 * kLdsGuess : 0);
+        return occupancy(PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? 2 * kLdsGuess : kSplitLds);
         VOILA_SHAPES(X)
 #undef X
     }
@@ -859,9 +916,9 @@ int observe_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
     case id * 2 + 0:                                                                                       \
-        return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : 0); \
+        return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kSplitLds); \
     case id * 2 + 1:                                                                                       \
-        return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : 0);
+        return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kSplitLds);
         VOILA_SHAPES(X)
 #undef X
     }

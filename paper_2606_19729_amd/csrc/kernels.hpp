@@ -239,6 +239,7 @@ int propose_batch_blocks_per_cu(int shape, int dt, int waves_per_block, size_t l
 // Resident blocks per CU of the plan / propose / observe kernels.
 int plan_blocks_per_cu(int shape, int dt);
 int propose_blocks_per_cu(int shape, int dt);
+int pass_tiles_per_block(int shape);  // 32-particle tiles one propose / observe block covers
 int observe_blocks_per_cu(int shape, int dt);
 // Whether a shape's kernels stage the packed network in LDS.
 bool weights_in_lds(int shape);
