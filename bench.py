@@ -259,8 +259,17 @@ def bench_update_sweep(V, torch, reps):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         gbs = 136.0 * N / (ms / 1e3) / 1e9
+        # a plain device copy of the particle rows, for the achievable bandwidth
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * src.numel() * 4 / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
         out.append({"N": N, "ms": ms, "particles_per_s": N / (ms / 1e3), "algorithmic_GB_per_s": gbs,
-                    "hbm_frac": gbs / 8000.0})
+                    "hbm_frac": gbs / 8000.0, "copy_GB_per_s": copy_gbs, "frac_of_copy": gbs / copy_gbs})
     return out
 
 
@@ -278,11 +287,20 @@ def cpu_baseline(w, n_cands):
     oracle.update(w.model, w.states, w.update_action, o, lam=w.lam, seed=w.update_seed, U=w.resample_u)
     t_upd = time.perf_counter() - t0
     steps = len(pairs) * w.H
+    # the same computation on one thread, on a smaller sample (rates scale linearly)
+    prev = oracle.set_threads(1)
+    pairs1 = [(0, i) for i in range(min(w.N, 256))]
+    t0 = time.perf_counter()
+    oracle.rollouts(w.model, w.states, w.cands, w.gamma, w.goal, pairs1, seed=w.plan_seed)
+    t_plan1 = time.perf_counter() - t0
+    oracle.set_threads(prev)
     return {"value": steps / t_plan, "unit": "rollout steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_cands} candidates x {w.N} particles x {w.H} steps ({steps} rollout steps) "
                       f"in {t_plan:.2f} s; one {w.N}-particle update in {t_upd:.3f} s "
-                      f"({w.N / t_upd:.3g} particles/s)",
-            "update_particles_per_s": w.N / t_upd}
+                      f"({w.N / t_upd:.3g} particles/s); one thread: 1 candidate x {len(pairs1)} particles "
+                      f"x {w.H} steps in {t_plan1:.2f} s",
+            "update_particles_per_s": w.N / t_upd,
+            "value_1thread": len(pairs1) * w.H / t_plan1}
 
 
 def main():

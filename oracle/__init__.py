@@ -65,6 +65,8 @@ def lib():
         L.or_transition.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, dp]
         L.or_mlp_param_count.argtypes = [c_int, ip]
         L.or_mlp_param_count.restype = c_size_t
+        L.or_set_threads.argtypes = [c_int]
+        L.or_set_threads.restype = c_int
         _LIB = L
     return _LIB
 
@@ -391,3 +393,8 @@ def teacher_targets(teacher_model, S0, actions, H, particles=1, noise=None, seed
         s = transition(teacher_model, s, a, w)
         out[:, t] = s
     return out
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (results do not depend on it); returns the previous count."""
+    return int(lib().or_set_threads(int(n)))

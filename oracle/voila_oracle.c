@@ -45,6 +45,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_ERR_ARG 1
@@ -874,4 +877,18 @@ void or_normals_rows(uint64_t seed, int n, uint32_t c1, uint32_t c2, uint32_t st
 {
     #pragma omp parallel for schedule(static)
     for (int r = 0; r < n; ++r) or_normals(seed, (uint32_t)r, c1, c2, stream, d, out + (size_t)r * d);
+}
+
+/* Threads of the OpenMP loops (the results do not depend on it); returns
+ * the previous setting.  Used to time the oracle on one core. */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    int prev = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return prev;
+#else
+    (void)n;
+    return 1;
+#endif
 }
