@@ -60,6 +60,10 @@ constexpr int DT_BF16 = 1;
 #define VOILA_STREAM_NBUF 2
 #endif
 constexpr int kPfDepth = VOILA_PF_DEPTH;
+#ifndef VOILA_PF_DEPTH_F32
+#define VOILA_PF_DEPTH_F32 6
+#endif
+constexpr int kPfDepthF32 = VOILA_PF_DEPTH_F32;  // binary32 fragments are one register each
 
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int rup(int a, int b) { return cdiv(a, b) * b; }
@@ -277,67 +281,15 @@ struct DirectSrc {
     __device__ __forceinline__ void finish() {}
 };
 
-// Fragment source streaming the packed network from global memory through two
-// LDS chunk buffers shared by the whole workgroup.  Every wave of the block
-// must walk the same fragment sequence (the rollout loop is block-uniform):
-// at the first fragment of chunk ch all waves wait for their part of the
-// chunk's direct-to-LDS loads, meet at a barrier (which also retires chunk
-// ch - 1 from the other buffer) and then start loading chunk ch + 1 into that
-// other buffer, so the next chunk streams in while this one is multiplied.
 // s_waitcnt immediate: wait until at most `vm` vector-memory operations of
 // this wave are outstanding and all of its LDS operations are done.
 __host__ __device__ constexpr int waitcnt_vm_lgkm0(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4); }
 
-// Streaming source of binary32 networks (their evaluation reaches the loads
-// from run-time fragment positions): two chunk buffers, a full wait and a
-// workgroup barrier at every chunk boundary, the next chunk's direct-to-LDS
-// loads issued right after it.
-template <class N, int CHB = VOILA_STREAM_CHB, int WIN = 4 * N::HT>
-struct StreamSrc32 {
-    static constexpr int FB = N::FRAG_BYTES;
-    static constexpr int FPC = CHB / FB;  // fragments per chunk
-    static constexpr int NFR = N::NF0 + (N::NHID - 1) * N::NFH + N::NFO;
-    static constexpr int NCH = cdiv(NFR, FPC);
-    static constexpr int TOTAL = NFR * FB;
-    static constexpr int LDS_BYTES = 2 * CHB;
-    static_assert(CHB % 4096 == 0 && CHB % FB == 0, "chunk must be whole DMA rounds and fragments");
-    static_assert(TOTAL % 1024 == 0, "the fragment stream must be whole 1 KB DMA rounds");
-    char* lds;
-    const char* src;
-    int cur;
-    const char* win;
-
-    __device__ __forceinline__ StreamSrc32(char* l, const char* s) : lds(l), src(s), cur(1), win(l) {}
-
-    __device__ __forceinline__ void fetch(int ch, int b) const {
-        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
-        const int lane = threadIdx.x & 63;
-        const int chunk_bytes = (ch + 1) * CHB <= TOTAL ? CHB : TOTAL - ch * CHB;
-        const char* base = src + opaque_zero() + (size_t)ch * CHB;
-        for (int off = wave * 1024; off < chunk_bytes; off += nw * 1024) {
-            __builtin_amdgcn_global_load_lds((const void*)(base + off + lane * 16),
-                                             (__attribute__((address_space(3))) void*)(lds + b * CHB + off), 16, 0,
-                                             0);
-        }
-    }
-    __device__ __forceinline__ void start() { fetch(0, 0); }
-    __device__ __forceinline__ typename Frag<N::DT>::type load(int f, int lane) {
-        const int ch = f / FPC, within = f % FPC;
-        if (within == 0) {
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            cur ^= 1;
-            fetch(ch + 1 < NCH ? ch + 1 : 0, cur ^ 1);
-        }
-        if (within % WIN == 0) win = lds + cur * CHB + opaque_zero();
-        return Frag<N::DT>::load(win, within, lane);
-    }
-    __device__ __forceinline__ void finish() { __builtin_amdgcn_s_waitcnt(0); }
-};
-
-// Streaming source of bfloat16 networks, whose evaluation is unrolled at
-// compile time: NBUF chunk buffers, the packed stream padded to whole chunks.
+// Fragment source streaming the packed network from global memory through
+// NBUF LDS chunk buffers shared by the workgroup's four waves; the network's
+// evaluation is unrolled at compile time and the packed stream is padded to
+// whole chunks.  Every wave walks the same fragment sequence (the rollout
+// loop is block-uniform).
 template <class N, int CHB = VOILA_STREAM_CHB, int NBUF = VOILA_STREAM_NBUF, int WIN = 4 * N::HT>
 struct StreamSrc {
     static constexpr int FB = N::FRAG_BYTES;
@@ -472,10 +424,11 @@ __device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const floa
                                           const float (&slots)[N::IN_SLOTS], int lane, int g) {
     if constexpr (N::CT < N::HT) {
         return run_net_grouped<N>(src, P, b0, slots, lane, g);
-    } else if constexpr (N::DT == DT_BF16) {
-        // bfloat16: every loop unrolled at compile time (fragment positions,
-        // and a streaming source's chunk boundaries, are constants) and the
-        // weight fragments of the next k-step load while this one multiplies
+    } else if constexpr (N::DT == DT_BF16 || N::WIDTH > 64) {
+        // bfloat16 and streamed binary32 networks: every loop unrolled at
+        // compile time (fragment positions, and a streaming source's chunk
+        // boundaries, are constants) and the weight fragments of the next
+        // k-steps load while this one multiplies
         typedef FragIdx<N> FI;
         typedef typename Frag<N::DT>::type FT;
         f32x16 acc[N::HT];
@@ -488,7 +441,7 @@ __device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const floa
         static_for<N::NHID - 1>([&](auto li) {
             constexpr int l = decltype(li)::value + 1;
             init_bias<N::HT>(acc, P.bh + (l - 1) * N::WIDTH + opaque_zero(), g);
-            mfma_layer<N::HID_KS, N::HT, kPfDepth, FT>(
+            mfma_layer<N::HID_KS, N::HT, (N::DT == DT_F32 ? kPfDepthF32 : kPfDepth), FT>(
                 acc, [&](int c, int t) { return src.load(FI::hidden(l, c, t), lane); },
                 [&](int c) { return act.b(c); });
             act.set_relu(acc);
@@ -637,7 +590,7 @@ struct GroupStream {
 // Bytes of one LDS chunk buffer of a streaming network source.
 // The streaming source of a network evaluated layer by layer.
 template <class N>
-using StreamFor = typename std::conditional<N::DT == DT_F32, StreamSrc32<N>, StreamSrc<N>>::type;
+using StreamFor = StreamSrc<N>;
 
 template <class N, bool G = (N::CT < N::HT)> struct StreamChunk {
     static constexpr int BYTES = StreamFor<N>::LDS_BYTES;  // LDS of the chunk buffers
