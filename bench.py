@@ -198,6 +198,43 @@ def bench_wide(V, torch, reps):
     return out
 
 
+def bench_small(V, torch, reps):
+    """The small workload (32 candidates x 128 particles x 10 steps, one
+    128-particle update), binary32: latency of plan and update."""
+    import workloads
+    dev = torch.device("cuda", 0)
+    w = workloads.small()
+    m = V.Model(w.model, compute="f32")
+    S = torch.as_tensor(w.states, device=dev)
+    C = torch.as_tensor(w.cands, device=dev)
+    q = torch.empty(w.K, dtype=torch.float32, device=dev)
+    ws = m.plan_workspace(w.N, w.K, w.H)
+    wsu = m.update_workspace(w.N)
+    obs = np.zeros(w.model.d_o, np.float32)
+    upd_out = {"states": torch.empty((w.N, w.model.d_s), dtype=torch.float32, device=dev),
+               "idx": torch.empty(w.N, dtype=torch.int32, device=dev),
+               "w": torch.empty(w.N, dtype=torch.float64, device=dev),
+               "loglik": torch.empty(w.N, dtype=torch.float32, device=dev),
+               "prop": torch.empty((w.N, w.model.d_s), dtype=torch.float32, device=dev),
+               "stats": torch.empty(2, dtype=torch.float64, device=dev)}
+    stream = torch.cuda.current_stream()
+    pm, um = [], []
+    for r in range(max(5, reps) + 1):
+        a, mid, b = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record(stream)
+        V.plan(m, S, C, w.gamma, w.goal, seed=r, q_out=q, workspace=ws)
+        mid.record(stream)
+        V.update(m, S, w.update_action, obs, lam=w.lam, seed=r + 1, U=w.resample_u, out=upd_out, workspace=wsu)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if r > 0:
+            pm.append(a.elapsed_time(mid))
+            um.append(mid.elapsed_time(b))
+    return {"K": w.K, "N": w.N, "H": w.H, "plan_ms": float(np.median(pm)), "update_ms": float(np.median(um)),
+            "rollout_steps_per_s": w.K * w.N * w.H / (float(np.median(pm)) / 1e3),
+            "update_particles_per_s": w.N / (float(np.median(um)) / 1e3)}
+
+
 def bench_grad(V, torch, reps):
     """Adjoint through 65,536 rollouts x 20 steps (checkpoint every 5): distillation
     gradient w.r.t. the 5,316 parameters; return gradient w.r.t. [1024, 20, 4] actions."""
@@ -441,6 +478,8 @@ def main():
         result["batched"] = bench_batched(V, torch, max(2, args.steps // 2))
         print("[bench] adjoint rollouts", file=sys.stderr, flush=True)
         result["gradients"] = bench_grad(V, torch, max(2, args.steps))
+        print("[bench] small workload latency", file=sys.stderr, flush=True)
+        result["small_f32"] = bench_small(V, torch, args.steps)
         print("[bench] hidden width 1024 (bf16)", file=sys.stderr, flush=True)
         result["wide_bf16"] = bench_wide(V, torch, max(2, args.steps // 2))
         print("[bench] belief-update sweep", file=sys.stderr, flush=True)
