@@ -63,6 +63,8 @@ def lib():
                                 c_int, dp, dp, dp, dp, i32p, dp]
         L.or_observe.argtypes = [mp, c_int, dp, i32p, dp, dp, c_uint64, c_int, dp]
         L.or_transition.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, dp]
+        L.or_plan_steps.argtypes = [mp, c_int, dp, c_int, c_int, i32p, dp, dp, dp, c_uint64, c_int, c_int,
+                                    dp, dp]
         L.or_mlp_param_count.argtypes = [c_int, ip]
         L.or_mlp_param_count.restype = c_size_t
         L.or_set_threads.argtypes = [c_int]
@@ -239,6 +241,27 @@ def rollouts(model, states, cands, gamma, goal, pairs, seed=0, crn=False, reward
                              _p(_d(goal)), int(reward_at), int(seed), int(crn), int(bf16), len(pairs),
                              _p(ks, c_int32), _p(is_, c_int32), _p(out)), "rollouts")
     return out
+
+
+def plan_steps(model, states, cands, noise=None, obs_noise=None, seed=0, crn=False, bf16=False, want_obs=True):
+    """(traj [K, N, H, d_s], obs [K, N, H, d_o] or None): the rollout states
+    s_1..s_H of plan and an observation f_Z([s_{t+1}, a_t, w_Z]) per step."""
+    S = _d(states)
+    N = S.shape[0]
+    cd, cc = _cands(model, cands)
+    K, H = int(np.asarray(cands).shape[0]), int(np.asarray(cands).shape[1])
+    nz = None if noise is None else _d(noise)
+    if nz is not None:
+        assert nz.shape == (K, N, H, model.d_w), nz.shape
+    oz = None if obs_noise is None else _d(obs_noise)
+    if oz is not None:
+        assert oz.shape == (K, N, H, model.d_wz), oz.shape
+    traj = np.zeros((K, N, H, model.d_s), np.float64)
+    obs = np.zeros((K, N, H, model.d_o), np.float64) if want_obs else None
+    b = _Bound(model)
+    _check(lib().or_plan_steps(b.ref(), N, _p(S), K, H, _p(cd, c_int32), _p(cc), _p(nz), _p(oz), int(seed),
+                               int(crn), int(bf16), _p(traj), _p(obs)), "plan_steps")
+    return traj, obs
 
 
 def weighted_mean(G, w=None):

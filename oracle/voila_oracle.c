@@ -31,6 +31,9 @@
  *             multiples of 2^-b of a particle (the paper leaves the scheme
  *             open; this reading makes every prefix sum exact in binary64).
  *   observe   Observation sampler z=f_Z(s',a,w_Z) (Eq. 5).
+ *   plan_steps  The states of the plan rollouts and an observation drawn
+ *             from f_Z at every step (Sec. 4.3 forward-simulates with both
+ *             learned samplers).
  *   philox    Philox4x32-10 counter-based generator (Salmon, Moraes, Dror,
  *             Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11),
  *             Box-Muller transform for N(0,1) draws.
@@ -320,11 +323,12 @@ static double reward(int d_s, const double* s, const double* goal)
  *   s_0 = S_i;  s_{t+1} = s_t + f_T([s_t, a_{k,t}, w_{k,i,t}]);
  *   reward_at == 0: r_t = R(s_{t+1})   (reward on arrival, default)
  *   reward_at == 1: r_t = R(s_t)       (reward of the state acted from)
- *   G = sum_{t<H} gamma^t r_t. */
+ *   G = sum_{t<H} gamma^t r_t.
+ * traj (NULL or [H][d_s]) receives s_1 .. s_H. */
 static double rollout_return(const or_model* m, const double* S_i, int k, int i, int N, int H,
                              const int32_t* cand_disc, const double* cand_cont,
                              double gamma, const double* goal, int reward_at,
-                             const double* noise, uint64_t seed, int crn, int bf16)
+                             const double* noise, uint64_t seed, int crn, int bf16, double* traj)
 {
     double s[OR_MAX_WIDTH], s_next[OR_MAX_WIDTH], w[OR_MAX_WIDTH];
     for (int j = 0; j < m->d_s; ++j) s[j] = S_i[j];
@@ -343,6 +347,8 @@ static double rollout_return(const or_model* m, const double* S_i, int k, int i,
         G += disc * r;
         disc *= gamma;
         for (int j = 0; j < m->d_s; ++j) s[j] = s_next[j];
+        if (traj)
+            for (int j = 0; j < m->d_s; ++j) traj[(size_t)t * m->d_s + j] = s_next[j];
     }
     return G;
 }
@@ -377,7 +383,7 @@ int or_plan(const or_model* m0, int N, const double* S, const double* belief_w,
     for (long r = 0; r < (long)K * N; ++r) {
         int k = (int)(r / N), i = (int)(r % N);
         Gbuf[r] = rollout_return(m, S + (size_t)i * m->d_s, k, i, N, H, cand_disc, cand_cont,
-                                 gamma, goal, reward_at, noise, seed, crn, bf16);
+                                 gamma, goal, reward_at, noise, seed, crn, bf16, NULL);
     }
     for (int k = 0; k < K; ++k) Q[k] = weighted_sum(N, Gbuf + (size_t)k * N, belief_w, 1);
     if (!G) free(Gbuf);
@@ -402,7 +408,7 @@ int or_rollouts(const or_model* m0, int N, const double* S, int K, int H,
     for (int p = 0; p < n_pairs; ++p) {
         int k = k_list[p], i = i_list[p];
         G_out[p] = rollout_return(m, S + (size_t)i * m->d_s, k, i, N, H, cand_disc, cand_cont,
-                                  gamma, goal, reward_at, NULL, seed, crn, bf16);
+                                  gamma, goal, reward_at, NULL, seed, crn, bf16, NULL);
     }
     release_rounded(&rm);
     return OR_OK;
@@ -558,32 +564,98 @@ int or_update(const or_model* m0, int N, const double* S, const double* prior_w,
     return rc;
 }
 
+/* One observation draw o = f_Z([s', a, w_Z]) (Eq. 5). */
+static void observation(const or_model* m, const double* s_next, int a_disc, const double* a_cont,
+                        const double* wz, double* o, int bf16)
+{
+    double x[OR_MAX_WIDTH];
+    int aw = action_width(m);
+    for (int j = 0; j < m->d_s; ++j) x[j] = s_next[j];
+    put_action(m, x + m->d_s, a_disc, a_cont);
+    for (int j = 0; j < m->d_wz; ++j) x[m->d_s + aw + j] = wz[j];
+    mlp_forward(m->z_layers, m->z_dims, m->z_params, x, o, bf16);
+}
+
+static int obs_net_check(const or_model* m)
+{
+    if (mlp_check(m->z_layers, m->z_dims) != OR_OK) return OR_ERR_ARG;
+    if (m->z_dims[0] != m->d_s + action_width(m) + m->d_wz || m->z_dims[m->z_layers] != m->d_o) return OR_ERR_ARG;
+    return OR_OK;
+}
+
 /* Observation sampler (Eq. 5): o_r = f_Z([s'_r, a_r, w_Z,r]) for n rows;
  * noise given or stream 4 with counter (row, 0, 0).  Actions: one per row. */
 int or_observe(const or_model* m0, int n, const double* S, const int32_t* a_disc,
                const double* a_cont, const double* noise, uint64_t seed, int bf16, double* O)
 {
-    if (n < 0 || mlp_check(m0->z_layers, m0->z_dims) != OR_OK) return OR_ERR_ARG;
-    int aw = action_width(m0);
-    if (m0->z_dims[0] != m0->d_s + aw + m0->d_wz || m0->z_dims[m0->z_layers] != m0->d_o) return OR_ERR_ARG;
+    if (n < 0 || obs_net_check(m0) != OR_OK) return OR_ERR_ARG;
     if (m0->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
     rounded_model rm;
     const or_model* m = rounded(m0, bf16, &rm);
     #pragma omp parallel for schedule(static)
     for (int r = 0; r < n; ++r) {
-        double x[OR_MAX_WIDTH], w[OR_MAX_WIDTH];
-        for (int j = 0; j < m->d_s; ++j) x[j] = S[(size_t)r * m->d_s + j];
-        put_action(m, x + m->d_s, a_disc ? a_disc[r] : 0, a_cont ? a_cont + (size_t)r * m->d_a : NULL);
+        double w[OR_MAX_WIDTH];
         if (noise) {
             for (int j = 0; j < m->d_wz; ++j) w[j] = noise[(size_t)r * m->d_wz + j];
         } else {
             or_normals(seed, (uint32_t)r, 0u, 0u, OR_STREAM_OBS, m->d_wz, w);
         }
-        for (int j = 0; j < m->d_wz; ++j) x[m->d_s + aw + j] = w[j];
-        mlp_forward(m->z_layers, m->z_dims, m->z_params, x, O + (size_t)r * m->d_o, bf16);
+        observation(m, S + (size_t)r * m->d_s, a_disc ? a_disc[r] : 0,
+                    a_cont ? a_cont + (size_t)r * m->d_a : NULL, w, O + (size_t)r * m->d_o, bf16);
     }
     release_rounded(&rm);
     return OR_OK;
+}
+
+/* States and observations along the plan rollouts (Sec. 4.3 simulates with
+ * both samplers; Eq. 2 and Eq. 5).  For candidate k, particle i and step
+ * t < H: s_{t+1} is the rollout state of rollout_return (same transition
+ * noise: given [K][N][H][d_w] or stream 3), written to traj[k][i][t] ([K][N]
+ * [H][d_s], may be NULL); o_{k,i,t} = f_Z([s_{t+1}, a_{k,t}, w_Z]) with w_Z
+ * given (obs_noise [K][N][H][d_wz]) or drawn from stream 4 at counter
+ * (i, k or 0 under common random numbers, t), written to obs[k][i][t]
+ * ([K][N][H][d_o], may be NULL). */
+int or_plan_steps(const or_model* m0, int N, const double* S, int K, int H,
+                  const int32_t* cand_disc, const double* cand_cont, const double* noise,
+                  const double* obs_noise, uint64_t seed, int crn, int bf16, double* traj, double* obs)
+{
+    if (model_check(m0) != OR_OK || N < 1 || K < 0 || H < 0) return OR_ERR_ARG;
+    if (m0->n_actions > 0 ? !cand_disc : !cand_cont) return OR_ERR_ARG;
+    if (obs && obs_net_check(m0) != OR_OK) return OR_ERR_ARG;
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
+    int rc = OR_OK;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (long r = 0; r < (long)K * N; ++r) {
+        int k = (int)(r / N), i = (int)(r % N);
+        double* tr = (double*)malloc(sizeof(double) * ((size_t)H * m->d_s + 1));
+        if (!tr) {
+            #pragma omp atomic write
+            rc = OR_ERR_ARG;
+            continue;
+        }
+        double goal0[OR_MAX_WIDTH] = {0};
+        rollout_return(m, S + (size_t)i * m->d_s, k, i, N, H, cand_disc, cand_cont, 1.0, goal0, 0,
+                       noise, seed, crn, bf16, tr);
+        for (int t = 0; t < H; ++t) {
+            size_t row = (size_t)r * H + t;
+            if (traj)
+                for (int j = 0; j < m->d_s; ++j) traj[row * m->d_s + j] = tr[(size_t)t * m->d_s + j];
+            if (!obs) continue;
+            double wz[OR_MAX_WIDTH];
+            if (obs_noise) {
+                for (int j = 0; j < m->d_wz; ++j) wz[j] = obs_noise[row * m->d_wz + j];
+            } else {
+                or_normals(seed, (uint32_t)i, crn ? 0u : (uint32_t)k, (uint32_t)t, OR_STREAM_OBS, m->d_wz, wz);
+            }
+            observation(m, tr + (size_t)t * m->d_s, cand_disc ? cand_disc[(size_t)k * H + t] : 0,
+                        cand_cont ? cand_cont + ((size_t)k * H + t) * m->d_a : NULL, wz,
+                        obs + row * m->d_o, bf16);
+        }
+        free(tr);
+    }
+    release_rounded(&rm);
+    return rc;
 }
 
 /* Transition draws for n given (state, action, noise) rows: s'_r. */

@@ -481,3 +481,87 @@ def test_observe_is_affine_for_the_affine_sampler():
     wz = rng.standard_normal((30, 2))
     X = np.concatenate([S, np.eye(5)[a], wz], axis=1)
     np.testing.assert_allclose(oracle.observe(m, S, a, noise=wz), X @ A.T + c, rtol=1e-10, atol=1e-10)
+
+
+# ----------------------------------------------------------------------------- per-step observations
+def affine_steps(m, states, cands, noise, obs_noise):
+    """States and observations of every rollout step, written out with the
+    affine maps of the two samplers (every ReLU active)."""
+    F, B, C, c = split_transition(m)
+    Az, cz = composite(m.obs)
+    K, N, H = noise.shape[0], states.shape[0], noise.shape[2]
+    aw = m.action_width
+    traj = np.zeros((K, N, H, m.d_s))
+    obs = np.zeros((K, N, H, m.d_o))
+    for k in range(K):
+        s = np.asarray(states, np.float64).copy()
+        for t in range(H):
+            a = np.eye(aw)[cands[k, t]] if m.n_actions > 0 else np.asarray(cands[k, t], np.float64)
+            s = s @ F.T + a @ B.T + noise[k, :, t] @ C.T + c
+            traj[k, :, t] = s
+            x = np.concatenate([s, np.broadcast_to(a, (N, aw)), obs_noise[k, :, t]], axis=1)
+            obs[k, :, t] = x @ Az.T + cz
+    return traj, obs
+
+
+@pytest.mark.parametrize("discrete", [True, False])
+def test_plan_steps_follow_the_affine_samplers(discrete):
+    rng = np.random.default_rng(43)
+    m = affine_model(rng) if discrete else affine_model(rng, d_s=6, n_actions=0, d_a=3, d_w=6, d_o=3)
+    N, K, H = 7, 3, 5
+    states = (rng.standard_normal((N, m.d_s)) * 0.5).astype(np.float32)
+    cands = rng.integers(0, 5, (K, H)).astype(np.int32) if discrete else \
+        rng.uniform(-1, 1, (K, H, 3)).astype(np.float32)
+    noise = rng.standard_normal((K, N, H, m.d_w)).astype(np.float32)
+    obs_noise = rng.standard_normal((K, N, H, m.d_wz)).astype(np.float32)
+    traj, obs = oracle.plan_steps(m, states, cands, noise=noise, obs_noise=obs_noise)
+    rt, ro = affine_steps(m, states, cands, noise, obs_noise)
+    np.testing.assert_allclose(traj, rt, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(obs, ro, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("crn", [False, True])
+def test_plan_steps_counter_noise(crn):
+    """Observation noise is stream 4 at counter (particle, candidate or 0 under
+    common random numbers, step); the transition noise is the plan's."""
+    rng = np.random.default_rng(44)
+    m = affine_model(rng)
+    N, K, H, seed = 5, 3, 4, 0xABCDEF012345
+    states = (rng.standard_normal((N, 4)) * 0.5).astype(np.float32)
+    cands = rng.integers(0, 5, (K, H)).astype(np.int32)
+    noise = np.zeros((K, N, H, m.d_w))
+    obs_noise = np.zeros((K, N, H, m.d_wz))
+    for k in range(K):
+        for i in range(N):
+            for t in range(H):
+                kk = 0 if crn else k
+                noise[k, i, t] = oracle.normals(seed, i, kk, t, 3, m.d_w)
+                obs_noise[k, i, t] = oracle.normals(seed, i, kk, t, 4, m.d_wz)
+    traj, obs = oracle.plan_steps(m, states, cands, seed=seed, crn=crn)
+    rt, ro = affine_steps(m, states, cands, noise, obs_noise)
+    np.testing.assert_allclose(traj, rt, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(obs, ro, rtol=1e-9, atol=1e-9)
+
+
+def test_plan_steps_are_the_states_the_returns_are_taken_on():
+    """The returns of plan are the discounted rewards of the written states."""
+    w = workloads.small(N=16, K=4, H=6)
+    goal = np.asarray(w.goal, np.float64)
+    traj, obs = oracle.plan_steps(w.model, w.states, w.cands, seed=w.plan_seed)
+    _, G = oracle.plan(w.model, w.states, w.cands, w.gamma, w.goal, seed=w.plan_seed, return_G=True)
+    r = -((traj - goal) ** 2).sum(-1)                       # [K, N, H]
+    G_ref = (r * w.gamma ** np.arange(w.H)).sum(-1)
+    np.testing.assert_allclose(G, G_ref, rtol=1e-12, atol=1e-12)
+    # each observation equals the observation sampler applied to its row
+    acts = np.repeat(w.cands[:, None, :], w.N, axis=1)      # [K, N, H]
+    nz = np.zeros((w.K, w.N, w.H, w.model.d_wz))
+    for k in range(w.K):
+        for i in range(w.N):
+            for t in range(w.H):
+                nz[k, i, t] = oracle.normals(w.plan_seed, i, k, t, 4, w.model.d_wz)
+    o_ref = oracle.observe(w.model, traj.reshape(-1, w.model.d_s), acts.reshape(-1),
+                           noise=nz.reshape(-1, w.model.d_wz))
+    np.testing.assert_allclose(obs.reshape(-1, w.model.d_o), o_ref, rtol=0, atol=0)
+    # H = 0 and K = 0 write nothing
+    t0, o0 = oracle.plan_steps(w.model, w.states, w.cands[:, :0], seed=1)
+    assert t0.shape == (w.K, w.N, 0, w.model.d_s) and o0.shape == (w.K, w.N, 0, w.model.d_o)
