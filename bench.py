@@ -235,6 +235,54 @@ def bench_small(V, torch, reps):
             "update_particles_per_s": w.N / (float(np.median(um)) / 1e3)}
 
 
+def obs_flops_per_row(model):
+    """2 * MACs of one observation-network evaluation at its full input width."""
+    dims = [model.d_s + model.d_a + model.d_wz] + [int(W.shape[0]) for W, _ in model.obs]
+    return 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+
+
+def bench_plan_observe(V, torch, reps, w, S, C):
+    """The realistic plan with its rollout states written out (K x N x H x d_s
+    floats) and an observation drawn at every rollout step (K x N x H x d_o):
+    binary32 and bfloat16."""
+    dev = S.device
+    out = {}
+    traj = torch.empty((w.K, w.N, w.H, w.model.d_s), dtype=torch.float32, device=dev)
+    obs = torch.empty((w.K, w.N, w.H, w.model.d_o), dtype=torch.float32, device=dev)
+    rows = w.K * w.N * w.H
+    stream = torch.cuda.current_stream()
+    for compute in ["f32", "bf16"]:
+        m = V.Model(w.model, compute=compute)
+        ws = m.plan_workspace(w.N, w.K, w.H)
+        q = torch.empty(w.K, dtype=torch.float32, device=dev)
+        n_ws = V.lib.voila_plan_observe_workspace_size(m.handle, w.K, w.H)
+        wso = torch.empty(int(n_ws), dtype=torch.uint8, device=dev)
+        pm, om = [], []
+        for r in range(reps + 1):
+            a, mid, b = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            a.record(stream)
+            V.plan(m, S, C, w.gamma, w.goal, seed=w.plan_seed + r, q_out=q, workspace=ws, return_traj=True,
+                   traj_out=traj)
+            mid.record(stream)
+            V.plan_observe(m, traj, C, seed=w.plan_seed + r, out=obs, workspace=wso)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                pm.append(a.elapsed_time(mid))
+                om.append(mid.elapsed_time(b))
+        p_ms, o_ms = float(np.median(pm)), float(np.median(om))
+        peak = PEAK_F32_TFLOPS if compute == "f32" else PEAK_BF16_TFLOPS
+        out[compute] = {"plan_with_states_ms": p_ms, "observe_ms": o_ms,
+                        "observations_per_s": rows / (o_ms / 1e3),
+                        "observe_mfma_frac": obs_flops_per_row(w.model) * rows / (o_ms / 1e3) / 1e12 / peak,
+                        "states_GB_per_s": rows * w.model.d_s * 4 / (p_ms / 1e3) / 1e9}
+        print(f"[bench]   {compute}: plan + states {p_ms:.2f} ms, observations {o_ms:.2f} ms",
+              file=sys.stderr, flush=True)
+    out["rows"] = rows
+    out["flop_per_observation"] = obs_flops_per_row(w.model)
+    return out
+
+
 def bench_grad(V, torch, reps):
     """Adjoint through 65,536 rollouts x 20 steps (checkpoint every 5): distillation
     gradient w.r.t. the 5,316 parameters; return gradient w.r.t. [1024, 20, 4] actions."""
@@ -482,6 +530,8 @@ def main():
         result["small_f32"] = bench_small(V, torch, args.steps)
         print("[bench] hidden width 1024 (bf16)", file=sys.stderr, flush=True)
         result["wide_bf16"] = bench_wide(V, torch, max(2, args.steps // 2))
+        print("[bench] rollout states and per-step observations", file=sys.stderr, flush=True)
+        result["plan_observe"] = bench_plan_observe(V, torch, max(2, args.steps // 2), w, S, C)
         print("[bench] belief-update sweep", file=sys.stderr, flush=True)
         result["update_sweep"] = bench_update_sweep(V, torch, max(3, args.steps))
 

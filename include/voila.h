@@ -124,6 +124,8 @@ typedef struct {
     int32_t crn;            /* 1: common random numbers across candidates       */
     int32_t reward_at;      /* 0: reward on arrival s_{t+1}; 1: on s_t          */
     const float* d_noise;   /* device [K][N][H][d_w] explicit noise, or NULL    */
+    float* d_traj_out;      /* device [K][N][H][d_s] rollout states s_1..s_H    */
+                            /* (caller-owned, written in full), or NULL         */
 } voila_plan_opts_t;
 
 /* Bytes of device workspace voila_plan needs for these sizes. */
@@ -226,6 +228,27 @@ size_t voila_observe_workspace_size(voila_model_t model);
 voila_status_t voila_observe(voila_model_t model, const float* d_states, int32_t n, const void* h_action,
                              uint64_t seed, const float* d_noise, void* d_workspace, size_t workspace_bytes,
                              float* d_obs_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Per-step observations of the plan rollouts: the forward simulation of
+ * Sec. 4.3 runs both learned samplers, drawing an observation (Eq. 5) at
+ * every simulated step.  It does not enter Q.
+ *   o_{k,i,t} = f_Z([s_{k,i,t+1}, a_{k,t}, w_Z]),  k < K, i < N, t < H,
+ * with s_{k,i,t+1} the rollout states voila_plan writes to opts.d_traj_out
+ * (same N, K, H, candidates, seed and crn).  w_Z is given (d_noise, device
+ * [K][N][H][d_wz]) or drawn from Philox stream 4 at counter (i, k, or 0 when
+ * crn != 0, t) under key `seed`.
+ * d_traj [K][N][H][d_s] float; d_cands as in voila_plan; d_obs_out
+ * [K][N][H][d_o] float (caller-owned).  The workspace holds one folded
+ * first-layer bias per (candidate, step).  A discrete action outside
+ * [0, n_actions) sets *d_status (if given) to VOILA_ERR_INVALID_ARG and is
+ * replaced by action 0.  K = 0 or H = 0 writes nothing.
+ * ------------------------------------------------------------------------- */
+size_t voila_plan_observe_workspace_size(voila_model_t model, int32_t K, int32_t H);
+voila_status_t voila_plan_observe(voila_model_t model, const float* d_traj, int32_t N, const void* d_cands,
+                                  int32_t K, int32_t H, uint64_t seed, int32_t crn, const float* d_noise,
+                                  void* d_workspace, size_t workspace_bytes, float* d_obs_out, int32_t* d_status,
+                                  void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent planning instances (uneven N, K, H; one network

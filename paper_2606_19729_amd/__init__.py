@@ -56,7 +56,7 @@ class _ModelDesc(ctypes.Structure):
 
 class _PlanOpts(ctypes.Structure):
     _fields_ = [("gamma", c_double), ("h_goal", POINTER(c_float)), ("seed", c_uint64), ("crn", c_int32),
-                ("reward_at", c_int32), ("d_noise", c_void_p)]
+                ("reward_at", c_int32), ("d_noise", c_void_p), ("d_traj_out", c_void_p)]
 
 
 class _UpdateOpts(ctypes.Structure):
@@ -131,6 +131,11 @@ def _load():
     L.voila_observe_workspace_size.restype = c_size_t
     L.voila_observe.argtypes = [vp, vp, c_int32, vp, c_uint64, vp, vp, c_size_t, vp, vp]
     L.voila_observe.restype = c_int32
+    L.voila_plan_observe_workspace_size.argtypes = [vp, c_int32, c_int32]
+    L.voila_plan_observe_workspace_size.restype = c_size_t
+    L.voila_plan_observe.argtypes = [vp, vp, c_int32, vp, c_int32, c_int32, c_uint64, c_int32, vp, vp, c_size_t, vp,
+                                     vp, vp]
+    L.voila_plan_observe.restype = c_int32
     L.voila_philox_normals.argtypes = [c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int32, c_int32, vp,
                                        vp, vp]
     L.voila_philox_normals.restype = c_int32
@@ -161,7 +166,8 @@ EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_m
             "voila_update", "voila_update_max_particles", "voila_weights_workspace_size", "voila_normalize",
             "voila_reweight_resample",
             "voila_resample_bits",
-            "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_philox_normals",
+            "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_plan_observe_workspace_size",
+            "voila_plan_observe", "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
             "voila_batch_replay", "voila_grad_param_count", "voila_rollout_grad_workspace_size",
             "voila_rollout_grad"]
@@ -274,8 +280,10 @@ class Model:
 
 
 def plan(model: Model, states, cands, gamma, goal, belief_w=None, seed=0, crn=False, reward_at=0, noise=None,
-         return_G=False, q_out=None, G_out=None, workspace=None, status=None, stream=None):
-    """Q [K] float32 (and G [K, N]) of candidate action sequences."""
+         return_G=False, q_out=None, G_out=None, workspace=None, status=None, stream=None, return_traj=False,
+         traj_out=None):
+    """Q [K] float32 (then G [K, N] if return_G, then the rollout states
+    [K, N, H, d_s] if return_traj) of candidate action sequences."""
     d = model.desc
     N = int(states.shape[0])
     _dev(states, torch.float32, (N, d.d_s), "states")
@@ -292,8 +300,13 @@ def plan(model: Model, states, cands, gamma, goal, belief_w=None, seed=0, crn=Fa
     if noise is not None:
         _dev(noise, torch.float32, (K, N, H, d.d_w), "noise")
     goal_arr = (c_float * d.d_s)(*[float(x) for x in goal])
+    traj = None
+    if return_traj:
+        traj = traj_out if traj_out is not None else \
+            torch.empty((K, N, H, d.d_s), dtype=torch.float32, device=states.device)
+        _dev(traj, torch.float32, (K, N, H, d.d_s), "traj_out")
     opts = _PlanOpts(float(gamma), goal_arr, int(seed) & (2**64 - 1), int(bool(crn)), int(reward_at),
-                     _ptr(noise))
+                     _ptr(noise), _ptr(traj))
     q = q_out if q_out is not None else torch.empty(K, dtype=torch.float32, device=states.device)
     G = None
     if return_G:
@@ -301,7 +314,34 @@ def plan(model: Model, states, cands, gamma, goal, belief_w=None, seed=0, crn=Fa
     ws = workspace if workspace is not None else model.plan_workspace(N, K, H)
     _check(lib.voila_plan(model.handle, _ptr(states), _ptr(belief_w), N, _ptr(cands), K, H, ctypes.byref(opts),
                           _ptr(ws), ws.numel(), _ptr(q), _ptr(G), _ptr(status), _stream(stream)))
-    return (q, G) if return_G else q
+    out = (q,) + ((G,) if return_G else ()) + ((traj,) if return_traj else ())
+    return out if len(out) > 1 else q
+
+
+def plan_observe(model: Model, traj, cands, seed=0, crn=False, noise=None, out=None, workspace=None, status=None,
+                 stream=None):
+    """Observations [K, N, H, d_o] drawn at every step of the rollouts whose
+    states `traj` [K, N, H, d_s] plan returned (same candidates, seed, crn)."""
+    d = model.desc
+    if traj.dim() != 4:
+        raise VoilaError(VOILA_ERR_INVALID_ARG, "traj must be [K, N, H, d_s]")
+    K, N, H = int(traj.shape[0]), int(traj.shape[1]), int(traj.shape[2])
+    _dev(traj, torch.float32, (K, N, H, d.d_s), "traj")
+    if d.n_actions > 0:
+        _dev(cands, torch.int32, (K, H), "cands")
+    else:
+        _dev(cands, torch.float32, (K, H, d.d_a), "cands")
+    if noise is not None:
+        _dev(noise, torch.float32, (K, N, H, d.d_wz), "noise")
+    o = out if out is not None else torch.empty((K, N, H, d.d_o), dtype=torch.float32, device=traj.device)
+    _dev(o, torch.float32, (K, N, H, d.d_o), "out")
+    if workspace is None:
+        n = lib.voila_plan_observe_workspace_size(model.handle, K, H)
+        workspace = torch.empty(max(int(n), 1), dtype=torch.uint8, device=traj.device)
+    _check(lib.voila_plan_observe(model.handle, _ptr(traj), N, _ptr(cands), K, H, int(seed) & (2**64 - 1),
+                                  int(bool(crn)), _ptr(noise), _ptr(workspace), workspace.numel(), _ptr(o),
+                                  _ptr(status), _stream(stream)))
+    return o
 
 
 def _action_arg(model, action):

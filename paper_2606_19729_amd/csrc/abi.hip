@@ -516,6 +516,7 @@ voila_status_t voila_plan(voila_model_t m, const float* d_states, const double* 
     p.cands = d_cands;
     p.noise = o->d_noise;
     p.returns = d_returns_out;
+    p.traj = o->d_traj_out;
     p.partials = reinterpret_cast<float*>(ws);
     p.status = d_status;
     p.N = N;
@@ -836,6 +837,17 @@ voila_status_t voila_reweight_resample(const float* d_loglik, const double* d_pr
     return VOILA_OK;
 }
 
+namespace {
+// Blocks of an observe launch over `tiles` 32-row tiles: enough to cover
+// them, at most the resident blocks of the whole chip.
+int observe_blocks(voila_model_t m, long tiles) {
+    const long tpb = pass_tiles_per_block(m->shape);
+    const long want = (tiles + tpb - 1) / tpb;
+    const long cap = (long)m->cus * m->obs_bpc;
+    return (int)(want < cap ? want : cap);
+}
+}  // namespace
+
 size_t voila_observe_workspace_size(voila_model_t m) {
     if (!m) return 0;
     return align_up((size_t)m->width * 4, 256);
@@ -863,17 +875,69 @@ voila_status_t voila_observe(voila_model_t m, const float* d_states, int32_t n, 
     ObserveParams p{};
     p.obs = m->obs;
     p.b0 = f.out;
+    p.b0_stride = 0;
     p.states = d_states;
     p.noise = d_noise;
     p.out = d_obs_out;
-    p.n = n;
+    p.N = n;
+    p.K = 1;
+    p.H = 1;
     p.key0 = (uint32_t)(seed & 0xffffffffu);
     p.key1 = (uint32_t)(seed >> 32);
-    const int n_tiles = (n + 31) / 32;
-    const int tpb = pass_tiles_per_block(m->shape);
-    const int want = (n_tiles + tpb - 1) / tpb;
-    const int cap = m->cus * m->obs_bpc;
-    VOILA_CHECK_HIP(launch_observe(m->shape, m->dt, p, want < cap ? want : cap, s));
+    VOILA_CHECK_HIP(launch_observe(m->shape, m->dt, p, observe_blocks(m, (n + 31) / 32), s));
+    return VOILA_OK;
+}
+
+size_t voila_plan_observe_workspace_size(voila_model_t m, int32_t K, int32_t H) {
+    if (!m || K < 0 || H < 0) return 0;
+    return align_up((size_t)K * H * m->width * 4, 256);
+}
+
+voila_status_t voila_plan_observe(voila_model_t m, const float* d_traj, int32_t N, const void* d_cands, int32_t K,
+                                  int32_t H, uint64_t seed, int32_t crn, const float* d_noise, void* ws,
+                                  size_t ws_bytes, float* d_obs_out, int32_t* d_status, void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!m->has_obs) return fail(VOILA_ERR_INVALID_ARG, "the model has no observation network");
+    if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
+    if (K < 0 || H < 0) return fail(VOILA_ERR_INVALID_ARG, "K and H must be >= 0");
+    if ((long long)K * N > (1LL << 31) - 1 || (long long)K * H > (1LL << 31) - 1)
+        return fail(VOILA_ERR_UNSUPPORTED, "K * N and K * H must fit in 31 bits");
+    if ((long long)K * H * ((N + 31) / 32) > (1LL << 31) - 1)
+        return fail(VOILA_ERR_UNSUPPORTED, "K * H * ceil(N / 32) must fit in 31 bits");
+    if (K == 0 || H == 0) return VOILA_OK;
+    if (!d_traj || !d_cands || !d_obs_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    if (!ws || ws_bytes < voila_plan_observe_workspace_size(m, K, H))
+        return fail(VOILA_ERR_WORKSPACE, "plan-observe workspace too small");
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    FoldStepsParams f{};
+    f.w = m->fold_w_obs;
+    f.b = m->fold_b_obs;
+    f.out = reinterpret_cast<float*>(ws);
+    f.cands = d_cands;
+    f.width = m->width;
+    f.nf = m->nf_obs;
+    f.rows = K * H;
+    f.n_actions = m->n_actions;
+    f.d_a = m->d_a;
+    f.bf16 = m->dt == DT_BF16 ? 1 : 0;
+    f.status = d_status;
+    VOILA_CHECK_HIP(launch_fold_steps(f, s));
+    ObserveParams p{};
+    p.obs = m->obs;
+    p.b0 = f.out;
+    p.b0_stride = m->width;
+    p.states = d_traj;
+    p.noise = d_noise;
+    p.out = d_obs_out;
+    p.N = N;
+    p.K = K;
+    p.H = H;
+    p.crn = crn ? 1 : 0;
+    p.key0 = (uint32_t)(seed & 0xffffffffu);
+    p.key1 = (uint32_t)(seed >> 32);
+    VOILA_CHECK_HIP(launch_observe(m->shape, m->dt, p, observe_blocks(m, (long)K * H * ((N + 31) / 32)), s));
     return VOILA_OK;
 }
 

@@ -136,6 +136,12 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
         f32x16 out = run_net<NT>(src, P, b0, slots, lane, g);
 #pragma unroll
         for (int s = 0; s < SS; ++s) st[s] += out[s];
+        if (p.traj && valid) {
+            float* dst = p.traj + (((size_t)k * p.N + i) * p.H + t) * D_S;
+#pragma unroll
+            for (int s = 0; s < SS; ++s)
+                if (2 * s + g < D_S) dst[2 * s + g] = st[s];
+        }
         float r = p.reward_at ? r_cur : reward_to(st, goal, SS, D_S, g);
         G = __builtin_fmaf((float)disc, r, G);
         disc *= p.gamma;
@@ -269,6 +275,32 @@ __global__ __launch_bounds__(256) void fold_kernel(FoldParams p) {
     float acc = p.b[r];
     for (int c = 0; c < p.nf; ++c) acc += p.w[(size_t)r * p.nf + c] * p.v[c];
     p.out[r] = acc;
+}
+
+// First-layer biases with the action of every (candidate, step) group folded
+// in, in the column order of fold_kernel.
+__global__ __launch_bounds__(256) void fold_steps_kernel(FoldStepsParams p) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= p.width) return;
+    for (int j = blockIdx.y; j < p.rows; j += gridDim.y) {
+        float acc = p.b[r];
+        if (p.n_actions > 0) {
+            int a = reinterpret_cast<const int32_t*>(p.cands)[j];
+            if (a < 0 || a >= p.n_actions) {
+                if (p.status && r == 0) p.status[0] = 1;
+                a = 0;
+            }
+            for (int c = 0; c < p.n_actions; ++c) acc += p.w[(size_t)r * p.nf + c] * (c == a ? 1.0f : 0.0f);
+        } else {
+            const float* ac = reinterpret_cast<const float*>(p.cands) + (size_t)j * p.d_a;
+            for (int c = 0; c < p.d_a; ++c) {
+                float v = ac[c];
+                if (p.bf16) v = (float)(__bf16)v;
+                acc += p.w[(size_t)r * p.nf + c] * v;
+            }
+        }
+        p.out[(size_t)j * p.width + r] = acc;
+    }
 }
 
 __global__ __launch_bounds__(256) void q_reduce_batch_kernel(const QReduceParams* qs) {
@@ -462,6 +494,11 @@ __global__ __launch_bounds__(512) void propose_batch_kernel(BatchProposeParams b
 // ---------------------------------------------------------------------------
 // observe
 // ---------------------------------------------------------------------------
+// Rows are (group, particle) pairs: group j = k * H + t has its own folded
+// first-layer bias (its action) and 32-particle tiles; row (k, i, t) reads
+// state row (k * N + i) * H + t, draws its noise at counter (i, k or 0 under
+// common random numbers, t) and writes the same output row.  A plain
+// observation of n states is the case K = H = 1.
 template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
     if constexpr (!net_compiled(DT, WIDTH)) {
@@ -477,46 +514,52 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
     }
     const NetPtrs PO = net_ptrs(WLDS ? (const char*)smem : p.obs.base, p.obs);
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
-    const int n_tiles = (p.n + 31) / 32;
+    const int n_tiles = (p.N + 31) / 32;
+    const long n_units = (long)p.K * p.H * n_tiles;
     // split mode: the block's four waves evaluate one tile together
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tpb = MODE == kSplit ? 1 : (int)(blockDim.x >> 6);
-    const int first = MODE == kSplit ? (int)blockIdx.x : (int)blockIdx.x * tpb + wave;
-    for (int tile = first; tile < n_tiles; tile += gridDim.x * tpb) {
-        const int r = tile * 32 + col;
-        const bool valid = r < p.n;
+    const long first = MODE == kSplit ? (long)blockIdx.x : (long)blockIdx.x * tpb + wave;
+    for (long u = first; u < n_units; u += (long)gridDim.x * tpb) {
+        const int grp = (int)(u / n_tiles);
+        const int tile = (int)(u - (long)grp * n_tiles);
+        const int k = grp / p.H, t = grp - k * p.H;
+        const int i = tile * 32 + col;
+        const bool valid = i < p.N;
+        const size_t r = ((size_t)k * p.N + (valid ? i : 0)) * p.H + t;
         float slots[NTO::IN_SLOTS];
 #pragma unroll
         for (int s = 0; s < NTO::IN_SLOTS; ++s) slots[s] = 0.0f;
 #pragma unroll
         for (int s = 0; s < SS; ++s) {
             int f = 2 * s + g;
-            slots[s] = (valid && f < D_S) ? p.states[(size_t)r * D_S + f] : 0.0f;
+            slots[s] = (valid && f < D_S) ? p.states[r * D_S + f] : 0.0f;
         }
         if (p.noise) {
 #pragma unroll
             for (int s = 0; s < SW; ++s) {
                 int f = noise_feature(s, g);
-                slots[SS + s] = (valid && f < D_WZ) ? p.noise[(size_t)r * D_WZ + f] : 0.0f;
+                slots[SS + s] = (valid && f < D_WZ) ? p.noise[r * D_WZ + f] : 0.0f;
             }
         } else {
             float nz[SW];
-            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)r, 0u, 0u, 4u, g);
+            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 4u, g);
 #pragma unroll
             for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
         }
+        const float* b0 = p.b0 + (size_t)grp * p.b0_stride;
         f32x16 o;
         if constexpr (MODE == kSplit) {
-            o = run_net_split<NTO>(PO, p.b0, slots, lane, g, wave, smem);
+            o = run_net_split<NTO>(PO, b0, slots, lane, g, wave, smem);
         } else {
             auto srco = DirectFor<NTO>::make(PO);
-            o = run_net<NTO>(srco, PO, p.b0, slots, lane, g);
+            o = run_net<NTO>(srco, PO, b0, slots, lane, g);
         }
         const bool writer = MODE != kSplit || wave == 0;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             int f = 2 * s + g;
-            if (writer && valid && f < D_O) p.out[(size_t)r * D_O + f] = o[s];
+            if (writer && valid && f < D_O) p.out[r * D_O + f] = o[s];
         }
     }
     }
@@ -1036,6 +1079,12 @@ hipError_t launch_q_reduce(const QReduceParams& p, hipStream_t s) {
 
 hipError_t launch_fold(const FoldParams& p, hipStream_t s) {
     hipLaunchKernelGGL(fold_kernel, (p.width + 255) / 256, 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_steps(const FoldStepsParams& p, hipStream_t s) {
+    if (p.rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(fold_steps_kernel, dim3((p.width + 255) / 256, p.rows < 65535 ? p.rows : 65535), 256, 0, s, p);
     return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ struct PlanParams {
     const void* cands;       // int32 [K][H] or float [K][H][d_a]
     const float* noise;      // [K][N][H][d_w] or NULL
     float* returns;          // [K][N] or NULL
+    float* traj;             // [K][N][H][d_s] rollout states s_1..s_H, or NULL
     float* partials;         // [K][n_tiles]
     int32_t* status;         // or NULL
     int N, K, H, n_tiles;
@@ -76,14 +77,26 @@ struct ProposeParams {
     uint32_t key0, key1;
 };
 
+// Observations of rows (k, i, t), k < K, i < N, t < H (K = H = 1: n plain rows).
 struct ObserveParams {
     NetBlob obs;
-    const float* b0;         // folded first-layer bias [width]
-    const float* states;     // [n][d_s]
-    const float* noise;      // [n][d_wz] or NULL
-    float* out;              // [n][d_o]
-    int n;
+    const float* b0;         // folded first-layer biases, row k * H + t at b0 + (k * H + t) * b0_stride
+    int b0_stride;           // 0: one bias for every row
+    const float* states;     // [K][N][H][d_s]
+    const float* noise;      // [K][N][H][d_wz] or NULL
+    float* out;              // [K][N][H][d_o]
+    int N, K, H, crn;
     uint32_t key0, key1;
+};
+
+// First-layer biases with the action of each (candidate, step) folded in.
+struct FoldStepsParams {
+    const float* w;      // [width][nf] action columns of the first layer
+    const float* b;      // [width]
+    float* out;          // [rows][width]
+    const void* cands;   // int32 [rows] action indices or float [rows][d_a]
+    int width, nf, rows, n_actions, d_a, bf16;
+    int32_t* status;     // or NULL
 };
 
 struct NormResParams {
@@ -215,6 +228,7 @@ constexpr int kNormResThreads = 1024;
 hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s);
 hipError_t launch_q_reduce(const QReduceParams& p, hipStream_t s);
 hipError_t launch_fold(const FoldParams& p, hipStream_t s);
+hipError_t launch_fold_steps(const FoldStepsParams& p, hipStream_t s);
 hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
 hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);
 hipError_t launch_norm_res(const NormResParams& p, hipStream_t s);

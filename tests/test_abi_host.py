@@ -94,3 +94,6 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert L.voila_plan_workspace_size(None, 0, 1, 1) == 0
     assert L.voila_update_workspace_size(None, 10) == 0
     assert L.voila_last_error()
+    assert L.voila_plan_observe(None, None, 1, None, 1, 1, 0, 0, None, None, 0, None, None, None) == \
+        V.VOILA_ERR_INVALID_ARG
+    assert L.voila_plan_observe_workspace_size(None, 4, 4) == 0

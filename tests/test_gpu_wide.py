@@ -4,8 +4,9 @@ hidden layer) and an integer-exact pin of every packed network shape.
 * Integer-exact networks: small-integer weights, biases, states, actions and
   explicit noise, with discount 1/2 and N = 64, so every binary32 and
   bfloat16 operation on the device and every binary64 operation in the oracle
-  is exact: Q must equal the oracle's bit for bit, for every compiled shape
-  and both precisions.  Any misplaced weight fragment changes the result.
+  is exact: Q, the returns, the rollout states and the per-step observations
+  must equal the oracle's bit for bit, for every compiled shape and both
+  precisions.  Any misplaced weight fragment changes the result.
 * Width 1024 in bfloat16 at the small workload's counts (K = 32, N = 128,
   H = 10): Q, observations and the update against the oracle in binary64 and
   in bfloat16 emulation, within the stated bounds; at the large counts
@@ -77,7 +78,8 @@ def integer_workload(shape, seed):
         C = rng.integers(-1, 2, (K, H, d_a)).astype(np.float32)
     noise = rng.integers(-2, 3, (K, N, H, d_w)).astype(np.float32)
     goal = rng.integers(-2, 3, d_s).astype(np.float32)
-    return model, S, C, noise, goal
+    obs_noise = rng.integers(-2, 3, (K, N, H, d_wz)).astype(np.float32)
+    return model, S, C, noise, goal, obs_noise
 
 
 SHAPES = {
@@ -92,16 +94,22 @@ SHAPES = {
                                           ("realistic", "bf16"), ("continuous", "f32"),
                                           ("continuous", "bf16"), ("wide", "bf16")])
 def test_integer_exact_networks_match_bitwise(V, name, compute):
-    model, S, C, noise, goal = integer_workload(SHAPES[name], seed=len(name) * 7 + len(compute))
+    model, S, C, noise, goal, obs_noise = integer_workload(SHAPES[name], seed=len(name) * 7 + len(compute))
     print(f"integer-exact plan: {name} {compute}", flush=True)
     vm = V.Model(model, compute=compute)
-    q, G = V.plan(vm, dev(S), dev(C, torch.int32 if model.n_actions > 0 else torch.float32), 0.5, goal,
-                  noise=dev(noise), return_G=True)
+    Cd = dev(C, torch.int32 if model.n_actions > 0 else torch.float32)
+    q, G, traj = V.plan(vm, dev(S), Cd, 0.5, goal, noise=dev(noise), return_G=True, return_traj=True)
+    obs = V.plan_observe(vm, traj, Cd, noise=dev(obs_noise))
     torch.cuda.synchronize()
     q_ref, G_ref = oracle.plan(model, S, C, 0.5, goal, noise=noise, return_G=True)
     assert np.max(np.abs(G_ref)) > 1.0  # the pin is not vacuous
     assert np.array_equal(G.cpu().numpy().astype(np.float64), G_ref)
     assert np.array_equal(q.cpu().numpy().astype(np.float64), q_ref)
+    # the rollout states and the per-step observations, bit for bit
+    t_ref, o_ref = oracle.plan_steps(model, S, C, noise=noise, obs_noise=obs_noise)
+    assert np.max(np.abs(o_ref)) >= 1.0
+    assert np.array_equal(traj.cpu().numpy().astype(np.float64), t_ref)
+    assert np.array_equal(obs.cpu().numpy().astype(np.float64), o_ref)
 
 
 def test_binary32_wide_model_is_refused(V):

@@ -187,6 +187,22 @@ def explicit_plan_noise(w: Workload, seed: int = 11) -> np.ndarray:
     return rng.standard_normal((w.K, w.N, w.H, w.model.d_w)).astype(np.float32)
 
 
+def explicit_obs_noise(w: Workload, seed: int = 13) -> np.ndarray:
+    """Explicit per-step observation noise of the rollouts [K, N, H, d_wz] float32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((w.K, w.N, w.H, w.model.d_wz)).astype(np.float32)
+
+
+def continuous(seed: int = 5, N: int = 128, K: int = 32, H: int = 10) -> Workload:
+    """The small workload with continuous actions in [-1, 1]^4 instead of 5 one-hot actions."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    model = make_model(rng, d_s=4, n_actions=0, d_a=4, d_w=4, d_o=2, d_wz=2, width=64, n_hidden=2)
+    states = rng.standard_normal((N, 4)).astype(np.float32)
+    cands = rng.uniform(-1.0, 1.0, size=(K, H, 4)).astype(np.float32)
+    goal = np.array([1, 1, 0, 0], np.float32)
+    return _finish("continuous", rng, model, states, cands, 0.95, goal, cands[0, 0].copy(), 1.0)
+
+
 def explicit_update_noise(w: Workload, seed: int = 12) -> np.ndarray:
     """Explicit proposal noise [N, d_w] float32."""
     rng = np.random.Generator(np.random.PCG64(seed))
