@@ -241,7 +241,7 @@ struct voila_model_s {
     const float* fold_w_lik = nullptr;
     const float* fold_b_lik = nullptr;
     int nf_trans = 0, nf_obs = 0, nf_lik = 0;
-    int plan_bpc = 1, prop_bpc = 1, obs_bpc = 1;
+    int plan_bpc = 1, prop_bpc = 1, obs_bpc = 1, obs_roll_bpc = 1;
     bool has_grad = false;
     NetBlob grad_fwd{}, grad_bwd{};
     int grad_bpc = 1, n_params = 0;
@@ -460,6 +460,7 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->plan_bpc = plan_blocks_per_cu(shape, dt);
     m->prop_bpc = propose_blocks_per_cu(shape, dt);
     m->obs_bpc = observe_blocks_per_cu(shape, dt);
+    m->obs_roll_bpc = observe_rollout_blocks_per_cu(shape, dt);
     if (m->has_grad) m->grad_bpc = grad_blocks_per_cu(shape, grad_lds_bytes(m));
     *out = m;
     return VOILA_OK;
@@ -937,7 +938,10 @@ voila_status_t voila_plan_observe(voila_model_t m, const float* d_traj, int32_t 
     p.crn = crn ? 1 : 0;
     p.key0 = (uint32_t)(seed & 0xffffffffu);
     p.key1 = (uint32_t)(seed >> 32);
-    VOILA_CHECK_HIP(launch_observe(m->shape, m->dt, p, observe_blocks(m, (long)K * H * ((N + 31) / 32)), s));
+    const long units = (long)K * H * ((N + 31) / 32);
+    const long want = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+    const long cap = (long)m->cus * m->obs_roll_bpc;
+    VOILA_CHECK_HIP(launch_observe_rollouts(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));
     return VOILA_OK;
 }
 

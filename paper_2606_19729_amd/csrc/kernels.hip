@@ -152,6 +152,50 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
     if (lane == 0 && unit_ok) p.partials[(size_t)k * p.n_tiles + tile] = tot;
 }
 
+// The weight source of a rollout-sized launch of network NT, handed to
+// body(src, P) with the network's pointers: the whole network staged in LDS
+// once per block (kResident), streamed through the LDS chunk buffers with the
+// biases -- and for a grouped wide network the first layer -- staged after
+// them (kStream), or read from L2 (kDirect).  B0_ROWS is the number of
+// first-layer bias rows the blob carries (one per discrete action).
+template <class NT, int MODE, int B0_ROWS, class Body>
+__device__ __forceinline__ void with_weights(char* smem, const NetBlob& net, Body&& body) {
+    if (MODE == kResident) {
+        stage_blob(smem, net.base, net.bytes);
+        __syncthreads();
+    }
+    NetPtrs P = net_ptrs(MODE == kResident ? (const char*)smem : net.base, net);
+    constexpr bool F0_LDS = NT::CT < NT::HT && first_layer_in_lds<NT>(B0_ROWS);
+    char* extra = smem;
+    if constexpr (MODE == kStream) {
+        extra = smem + StreamChunk<NT>::BYTES;
+        const uint32_t f0_bytes = F0_LDS ? (uint32_t)(NT::NF0 * NT::FRAG_BYTES) : 0u;
+        if (f0_bytes) stage_blob(extra, P.f0, f0_bytes);
+        char* bias = extra + f0_bytes;
+        stage_blob(bias, net.base + net.off_b0, net.bytes - net.off_b0);
+        __syncthreads();
+        P.b0 = reinterpret_cast<const float*>(bias);
+        P.bh = reinterpret_cast<const float*>(bias + (net.off_bh - net.off_b0));
+        P.bo = reinterpret_cast<const float*>(bias + (net.off_bo - net.off_b0));
+    }
+    if constexpr (MODE == kStream && NT::CT < NT::HT) {
+        // grouped wide network: the groups' fragments stream through the LDS
+        // chunk buffers, the first layer is read from its LDS copy
+        WideSrc<NT, GroupStream<NT>> src(F0_LDS ? (const char*)extra : P.f0, GroupStream<NT>(smem, P.fh));
+        src.hid.start();
+        body(src, P);
+        src.hid.finish();
+    } else if constexpr (MODE == kStream) {
+        StreamFor<NT> src(smem, P.f0);
+        src.start();
+        body(src, P);
+        src.finish();
+    } else {
+        DirectSrc<NT::DT, 8 * NT::HT> src(P.f0);
+        body(src, P);
+    }
+}
+
 template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
     if constexpr (!net_compiled(DT, WIDTH)) {
@@ -159,53 +203,17 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
     } else {
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    if (MODE == kResident) {
-        stage_blob(smem, p.net.base, p.net.bytes);
-        __syncthreads();
-    }
-    NetPtrs P = net_ptrs(MODE == kResident ? (const char*)smem : p.net.base, p.net);
-    // streamed networks: the biases (and, for grouped wide networks, the first
-    // layer) are staged in LDS after the two chunk buffers
-    constexpr bool F0_LDS = NT::CT < NT::HT && first_layer_in_lds<NT>(N_ACT > 0 ? N_ACT : 1);
-    char* extra = smem;
-    if constexpr (MODE == kStream) {
-        extra = smem + StreamChunk<NT>::BYTES;
-        const uint32_t f0_bytes = F0_LDS ? (uint32_t)(NT::NF0 * NT::FRAG_BYTES) : 0u;
-        if (f0_bytes) stage_blob(extra, P.f0, f0_bytes);
-        char* bias = extra + f0_bytes;
-        stage_blob(bias, p.net.base + p.net.off_b0, p.net.bytes - p.net.off_b0);
-        __syncthreads();
-        P.b0 = reinterpret_cast<const float*>(bias);
-        P.bh = reinterpret_cast<const float*>(bias + (p.net.off_bh - p.net.off_b0));
-        P.bo = reinterpret_cast<const float*>(bias + (p.net.off_bo - p.net.off_b0));
-    }
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6;
     const long n_units = (long)p.K * p.n_tiles;
-    auto body = [&](auto& src) {
+    with_weights<NT, MODE, (N_ACT > 0 ? N_ACT : 1)>(smem, p.net, [&](auto& src, const NetPtrs& P) {
         // block-uniform loop: every wave of a block walks the same sequence of
         // (unit, step) iterations, idle waves on a masked dummy unit
         for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
             const long u = ub * wpb + wave;
             plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, p.goal, u, u < n_units, lane, g, col);
         }
-    };
-    if constexpr (MODE == kStream && NT::CT < NT::HT) {
-        // grouped wide network: the groups' fragments stream through the two
-        // LDS chunk buffers, the first layer is read from its LDS copy
-        WideSrc<NT, GroupStream<NT>> src(F0_LDS ? (const char*)extra : P.f0, GroupStream<NT>(smem, P.fh));
-        src.hid.start();
-        body(src);
-        src.hid.finish();
-    } else if constexpr (MODE == kStream) {
-        StreamFor<NT> src(smem, P.f0);
-        src.start();
-        body(src);
-        src.finish();
-    } else {
-        DirectSrc<DT, 8 * NT::HT> src(P.f0);
-        body(src);
-    }
+    });
     }
 }
 
@@ -499,67 +507,107 @@ __global__ __launch_bounds__(512) void propose_batch_kernel(BatchProposeParams b
 // state row (k * N + i) * H + t, draws its noise at counter (i, k or 0 under
 // common random numbers, t) and writes the same output row.  A plain
 // observation of n states is the case K = H = 1.
+struct ObsRow {
+    size_t r;     // state / noise / output row
+    int grp;      // bias row
+    bool valid;   // this lane's particle exists
+};
+
+// Inputs [s', w_Z] of this lane's row of tile unit u in first-layer slot order.
+template <int D_S, int D_WZ, int IN_SLOTS>
+__device__ __forceinline__ ObsRow observe_inputs(const ObserveParams& p, long u, int n_tiles, int g, int col,
+                                                 float (&slots)[IN_SLOTS]) {
+    constexpr int SS = state_slots(D_S), SW = noise_slots(D_WZ);
+    ObsRow w;
+    w.grp = (int)(u / n_tiles);
+    const int tile = (int)(u - (long)w.grp * n_tiles);
+    const int k = w.grp / p.H, t = w.grp - k * p.H;
+    const int i = tile * 32 + col;
+    w.valid = i < p.N;
+    w.r = ((size_t)k * p.N + (w.valid ? i : 0)) * p.H + t;
+#pragma unroll
+    for (int s = 0; s < IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < SS; ++s) {
+        int f = 2 * s + g;
+        slots[s] = (w.valid && f < D_S) ? p.states[w.r * D_S + f] : 0.0f;
+    }
+    if (p.noise) {
+#pragma unroll
+        for (int s = 0; s < SW; ++s) {
+            int f = noise_feature(s, g);
+            slots[SS + s] = (w.valid && f < D_WZ) ? p.noise[w.r * D_WZ + f] : 0.0f;
+        }
+    } else {
+        float nz[SW];
+        noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 4u, g);
+#pragma unroll
+        for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
+    }
+    return w;
+}
+
+template <int D_O>
+__device__ __forceinline__ void observe_store(const ObserveParams& p, const ObsRow& w, const f32x16& o, bool writer,
+                                              int g) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        int f = 2 * s + g;
+        if (writer && w.valid && f < D_O) p.out[w.r * D_O + f] = o[s];
+    }
+}
+
+// MODE kResident / kSplit / kDirect: sized for one belief (n rows); kStream:
+// sized for the rows of whole rollouts, one tile per wave with the weights
+// streamed through LDS like the rollout kernel's.
 template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
     if constexpr (!net_compiled(DT, WIDTH)) {
         return;  // binary32 networks wider than 256 are refused at model creation
     } else {
-    constexpr bool WLDS = MODE == kResident;
-    constexpr int SS = state_slots(D_S), SW = noise_slots(D_WZ);
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ)> NTO;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    if (WLDS) {
-        stage_blob(smem, p.obs.base, p.obs.bytes);
-        __syncthreads();
-    }
-    const NetPtrs PO = net_ptrs(WLDS ? (const char*)smem : p.obs.base, p.obs);
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int n_tiles = (p.N + 31) / 32;
     const long n_units = (long)p.K * p.H * n_tiles;
-    // split mode: the block's four waves evaluate one tile together
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tpb = MODE == kSplit ? 1 : (int)(blockDim.x >> 6);
-    const long first = MODE == kSplit ? (long)blockIdx.x : (long)blockIdx.x * tpb + wave;
-    for (long u = first; u < n_units; u += (long)gridDim.x * tpb) {
-        const int grp = (int)(u / n_tiles);
-        const int tile = (int)(u - (long)grp * n_tiles);
-        const int k = grp / p.H, t = grp - k * p.H;
-        const int i = tile * 32 + col;
-        const bool valid = i < p.N;
-        const size_t r = ((size_t)k * p.N + (valid ? i : 0)) * p.H + t;
-        float slots[NTO::IN_SLOTS];
-#pragma unroll
-        for (int s = 0; s < NTO::IN_SLOTS; ++s) slots[s] = 0.0f;
-#pragma unroll
-        for (int s = 0; s < SS; ++s) {
-            int f = 2 * s + g;
-            slots[s] = (valid && f < D_S) ? p.states[r * D_S + f] : 0.0f;
-        }
-        if (p.noise) {
-#pragma unroll
-            for (int s = 0; s < SW; ++s) {
-                int f = noise_feature(s, g);
-                slots[SS + s] = (valid && f < D_WZ) ? p.noise[r * D_WZ + f] : 0.0f;
+    if constexpr (MODE == kStream) {
+        const int wpb = blockDim.x >> 6;
+        with_weights<NTO, MODE, 1>(smem, p.obs, [&](auto& src, const NetPtrs& P) {
+            // block-uniform loop (the stream's chunk barriers need every wave)
+            for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
+                const long u = ub * wpb + wave;
+                const bool ok = u < n_units;
+                float slots[NTO::IN_SLOTS];
+                const ObsRow w = observe_inputs<D_S, D_WZ>(p, ok ? u : 0, n_tiles, g, col, slots);
+                // complete the row loads here so that the compiler's wait for
+                // them does not also drain the weight stream inside the layers
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+                const f32x16 o = run_net<NTO>(src, P, p.b0 + (size_t)w.grp * p.b0_stride, slots, lane, g);
+                observe_store<D_O>(p, w, o, ok, g);
             }
-        } else {
-            float nz[SW];
-            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 4u, g);
-#pragma unroll
-            for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
+        });
+    } else {
+        if (MODE == kResident) {
+            stage_blob(smem, p.obs.base, p.obs.bytes);
+            __syncthreads();
         }
-        const float* b0 = p.b0 + (size_t)grp * p.b0_stride;
-        f32x16 o;
-        if constexpr (MODE == kSplit) {
-            o = run_net_split<NTO>(PO, b0, slots, lane, g, wave, smem);
-        } else {
-            auto srco = DirectFor<NTO>::make(PO);
-            o = run_net<NTO>(srco, PO, b0, slots, lane, g);
-        }
-        const bool writer = MODE != kSplit || wave == 0;
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            int f = 2 * s + g;
-            if (writer && valid && f < D_O) p.out[r * D_O + f] = o[s];
+        const NetPtrs PO = net_ptrs(MODE == kResident ? (const char*)smem : p.obs.base, p.obs);
+        // split mode: the block's four waves evaluate one tile together
+        const int tpb = MODE == kSplit ? 1 : (int)(blockDim.x >> 6);
+        const long first = MODE == kSplit ? (long)blockIdx.x : (long)blockIdx.x * tpb + wave;
+        for (long u = first; u < n_units; u += (long)gridDim.x * tpb) {
+            float slots[NTO::IN_SLOTS];
+            const ObsRow w = observe_inputs<D_S, D_WZ>(p, u, n_tiles, g, col, slots);
+            const float* b0 = p.b0 + (size_t)w.grp * p.b0_stride;
+            f32x16 o;
+            if constexpr (MODE == kSplit) {
+                o = run_net_split<NTO>(PO, b0, slots, lane, g, wave, smem);
+            } else {
+                auto srco = DirectFor<NTO>::make(PO);
+                o = run_net<NTO>(srco, PO, b0, slots, lane, g);
+            }
+            observe_store<D_O>(p, w, o, MODE != kSplit || wave == 0, g);
         }
     }
     }
@@ -920,6 +968,49 @@ hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks,
     return hipGetLastError();
 }
 
+#define OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, plan_mode<w>()>
+
+size_t observe_rollout_lds(int shape, int dt, const NetBlob& obs) {
+    if (weights_in_lds(shape)) return obs.bytes;
+    size_t chunks = kStreamLds;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                       \
+    case id * 2 + 0:                                                \
+        chunks = stream_lds_of<DT_F32, ds, 0, 0, dwz, w, nh>();     \
+        break;                                                      \
+    case id * 2 + 1:                                                \
+        chunks = stream_lds_of<DT_BF16, ds, 0, 0, dwz, w, nh>();    \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return chunks + (obs.bytes - obs.off_b0);
+}
+
+hipError_t launch_observe_rollouts(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s) {
+    const size_t lds = observe_rollout_lds(shape, dt, p.obs);
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                \
+    case id * 2 + 0:                                                                                         \
+        if (lds > 65536)                                                                                     \
+            (void)hipFuncSetAttribute((const void*)OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),       \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                 \
+        hipLaunchKernelGGL((OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);    \
+        break;                                                                                               \
+    case id * 2 + 1:                                                                                         \
+        if (lds > 65536)                                                                                     \
+            (void)hipFuncSetAttribute((const void*)OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),      \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                 \
+        hipLaunchKernelGGL((OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p);   \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 namespace {
 template <class KernelT>
 int occupancy(KernelT k, size_t lds) {
@@ -962,6 +1053,19 @@ int observe_blocks_per_cu(int shape, int dt) {
         return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kSplitLds); \
     case id * 2 + 1:                                                                                       \
         return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kSplitLds);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+int observe_rollout_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
+    case id * 2 + 0:                                                                                        \
+        return occupancy(OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kStreamLds); \
+    case id * 2 + 1:                                                                                        \
+        return occupancy(OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kStreamLds);
         VOILA_SHAPES(X)
 #undef X
     }

@@ -231,6 +231,9 @@ hipError_t launch_fold(const FoldParams& p, hipStream_t s);
 hipError_t launch_fold_steps(const FoldStepsParams& p, hipStream_t s);
 hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
 hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);
+// The observe kernel sized for the rows of whole rollouts (weights streamed like the rollout kernel's).
+hipError_t launch_observe_rollouts(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);
+int observe_rollout_blocks_per_cu(int shape, int dt);
 hipError_t launch_norm_res(const NormResParams& p, hipStream_t s);
 hipError_t launch_philox(const PhiloxParams& p, hipStream_t s);
 hipError_t launch_plan_batch(int shape, int dt, const BatchPlanParams& p, int blocks, int waves_per_block,
