@@ -63,6 +63,9 @@ def lib():
                                 c_int, dp, dp, dp, dp, i32p, dp]
         L.or_observe.argtypes = [mp, c_int, dp, i32p, dp, dp, c_uint64, c_int, dp]
         L.or_transition.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, dp]
+        L.or_pw_widen.argtypes = [c_int, c_int, c_double, c_double, c_int]
+        L.or_pw_step.argtypes = [mp, c_int, dp, c_int, i32p, i32p, dp, i32p, i32p, c_int, dp, c_double, c_double,
+                                 c_double, c_uint64, u32p, c_int, i32p, i32p, dp, dp, dp, i32p, dp]
         L.or_plan_steps.argtypes = [mp, c_int, dp, c_int, c_int, i32p, dp, dp, dp, c_uint64, c_int, c_int,
                                     dp, dp]
         L.or_mlp_param_count.argtypes = [c_int, ip]
@@ -262,6 +265,40 @@ def plan_steps(model, states, cands, noise=None, obs_noise=None, seed=0, crn=Fal
     _check(lib().or_plan_steps(b.ref(), N, _p(S), K, H, _p(cd, c_int32), _p(cc), _p(nz), _p(oz), int(seed),
                                int(crn), int(bf16), _p(traj), _p(obs)), "plan_steps")
     return traj, obs
+
+
+def pw_widen(visits, children, k_o, alpha_o, capacity):
+    """Progressive-widening test of one action node (1: add a branch)."""
+    return lib().or_pw_widen(int(visits), int(children), float(k_o), float(alpha_o), int(capacity))
+
+
+def pw_step(model, succ, seg, actions, visits, children, obs_table, k_o, alpha_o, lam, seed, U, bf16=False):
+    """Grouped progressive-widening step over M action nodes.  Returns a dict
+    (widen, branch, loglik, w, stats, idx, S_out, children, obs_table); the
+    last two are updated copies of the inputs."""
+    S = _d(succ)
+    T = S.shape[0]
+    seg = np.ascontiguousarray(np.asarray(seg, np.int32))
+    M = seg.shape[0] - 1
+    a_disc, a_cont = (np.ascontiguousarray(np.asarray(actions, np.int32).reshape(M)), None) \
+        if model.n_actions > 0 else (None, _d(np.asarray(actions).reshape(M, model.d_a)))
+    vis = np.ascontiguousarray(np.asarray(visits, np.int32))
+    ch = np.array(children, np.int32)
+    tab = np.array(obs_table, np.float64)
+    B = tab.shape[1]
+    assert tab.shape == (M, B, model.d_o)
+    Uv = np.ascontiguousarray(np.asarray(U, np.uint32))
+    out = dict(widen=np.zeros(M, np.int32), branch=np.zeros(M, np.int32), loglik=np.zeros(T), w=np.zeros(T),
+               stats=np.zeros((M, 2)), idx=np.zeros(T, np.int32), S_out=np.zeros((T, model.d_s)))
+    b = _Bound(model)
+    _check(lib().or_pw_step(b.ref(), T, _p(S), M, _p(seg, c_int32), _p(a_disc, c_int32), _p(a_cont),
+                            _p(vis, c_int32), _p(ch, c_int32), B, _p(tab), float(k_o), float(alpha_o), float(lam),
+                            int(seed), _p(Uv, c_uint32), int(bf16), _p(out["widen"], c_int32),
+                            _p(out["branch"], c_int32), _p(out["loglik"]), _p(out["w"]), _p(out["stats"]),
+                            _p(out["idx"], c_int32), _p(out["S_out"])), "pw_step")
+    out["children"] = ch
+    out["obs_table"] = tab
+    return out
 
 
 def weighted_mean(G, w=None):

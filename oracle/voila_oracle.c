@@ -31,6 +31,9 @@
  *             multiples of 2^-b of a particle (the paper leaves the scheme
  *             open; this reading makes every prefix sum exact in binary64).
  *   observe   Observation sampler z=f_Z(s',a,w_Z) (Eq. 5).
+ *   pw_step   Progressive widening of many action nodes at once (Sec. 4.3):
+ *             the widening test, a new or reused observation branch per node,
+ *             and each node's successors weighted and resampled as a group.
  *   plan_steps  The states of the plan rollouts and an observation drawn
  *             from f_Z at every step (Sec. 4.3 forward-simulates with both
  *             learned samplers).
@@ -963,4 +966,99 @@ int or_set_threads(int n)
     (void)n;
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Grouped progressive-widening step (Sec. 4.3): simulations are grouped by  */
+/* their parent action node and every group is handled at once.             */
+/* ------------------------------------------------------------------------- */
+#define OR_STREAM_BRANCH 6u
+
+/* Widening test of one action node with n_visits visits and n_children
+ * observation branches: widen when |C(a)| < k_o N(a)^alpha_o (binary64), or
+ * when the node has no branch yet; never beyond `capacity` branches. */
+int or_pw_widen(int n_visits, int n_children, double k_o, double alpha_o, int capacity)
+{
+    if (n_children >= capacity) return 0;
+    if (n_children == 0) return 1;
+    return (double)n_children < k_o * pow((double)n_visits, alpha_o);
+}
+
+/* For M action nodes whose successor states S[seg[m] .. seg[m+1]) (rows of
+ * d_s) were simulated under the node's action:
+ *   1. widen_m = or_pw_widen(visits[m], children[m], k_o, alpha_o, B).
+ *   2. widening: a new observation o = f_Z([S[seg[m]], a_m, w_Z]) (Eq. 5),
+ *      w_Z drawn from stream 4 at counter (0, m, 0), is stored as branch
+ *      children[m] of the node's table obs_table[m][B][d_o] and children[m]
+ *      grows by one; otherwise an existing branch is taken uniformly:
+ *      floor(u * children[m]) with u the uniform of word 0 of Philox at
+ *      counter (m, 1, 0, stream 6 << 16).
+ *   3. every successor of the node is weighted against the chosen branch's
+ *      observation, l_j = l([s'_j, a_m, o_branch]) (Sec. 4.2), and the group is
+ *      normalised (or_normalize, uniform prior) and resampled (or_resample
+ *      with the node's offset U[m]); idx holds indices within the group and
+ *      S_out[j] = S[seg[m] + idx_j].
+ * Empty groups are skipped (branch -1, nothing written).  Outputs: widen [M],
+ * branch [M], loglik [T], w [T], stats [M][2], idx [T], S_out [T][d_s];
+ * children and obs_table are updated in place. */
+int or_pw_step(const or_model* m0, int T, const double* S, int M, const int32_t* seg,
+               const int32_t* a_disc, const double* a_cont, const int32_t* visits, int32_t* children,
+               int B, double* obs_table, double k_o, double alpha_o, double lambda, uint64_t seed,
+               const uint32_t* U, int bf16, int32_t* widen, int32_t* branch, double* loglik, double* w,
+               double* stats, int32_t* idx, double* S_out)
+{
+    if (M < 0 || T < 0 || B < 1 || !(lambda > 0.0) || obs_net_check(m0) != OR_OK) return OR_ERR_ARG;
+    if (mlp_check(m0->l_layers, m0->l_dims) != OR_OK) return OR_ERR_ARG;
+    if (m0->l_dims[0] != m0->d_s + action_width(m0) + m0->d_o || m0->l_dims[m0->l_layers] != 1) return OR_ERR_ARG;
+    if (m0->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    if (seg[0] != 0 || seg[M] != T) return OR_ERR_ARG;
+    for (int g = 0; g < M; ++g)
+        if (seg[g + 1] < seg[g] || children[g] < 0 || children[g] > B) return OR_ERR_ARG;
+    const int d_s = m0->d_s, d_o = m0->d_o, aw = action_width(m0);
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
+    int rc = OR_OK;
+    for (int g = 0; g < M && rc == OR_OK; ++g) {
+        const int lo = seg[g], n = seg[g + 1] - lo;
+        const int ad = a_disc ? a_disc[g] : 0;
+        const double* ac = a_cont ? a_cont + (size_t)g * m->d_a : NULL;
+        if (n == 0) {
+            widen[g] = 0;
+            branch[g] = -1;
+            continue;
+        }
+        double* row = obs_table + (size_t)g * B * d_o;
+        widen[g] = or_pw_widen(visits[g], children[g], k_o, alpha_o, B);
+        if (widen[g]) {
+            double wz[OR_MAX_WIDTH];
+            or_normals(seed, 0u, (uint32_t)g, 0u, OR_STREAM_OBS, m->d_wz, wz);
+            observation(m, S + (size_t)lo * d_s, ad, ac, wz, row + (size_t)children[g] * d_o, bf16);
+            branch[g] = children[g];
+            children[g] += 1;
+        } else {
+            uint32_t ctr[4] = {(uint32_t)g, 1u, 0u, OR_STREAM_BRANCH << 16};
+            uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+            uint32_t word[4];
+            or_philox4x32_10(ctr, key, word);
+            branch[g] = (int32_t)floor(or_uniform(word[0]) * (double)children[g]);
+        }
+        const double* o = row + (size_t)branch[g] * d_o;
+        #pragma omp parallel for schedule(static)
+        for (int j = 0; j < n; ++j) {
+            double x[OR_MAX_WIDTH], y[1];
+            for (int c = 0; c < d_s; ++c) x[c] = S[(size_t)(lo + j) * d_s + c];
+            put_action(m, x + d_s, ad, ac);
+            for (int c = 0; c < d_o; ++c) x[d_s + aw + c] = o[c];
+            mlp_forward(m->l_layers, m->l_dims, m->l_params, x, y, bf16);
+            loglik[lo + j] = y[0];
+        }
+        rc = or_normalize(n, loglik + lo, NULL, lambda, w + lo, stats + 2 * (size_t)g);
+        if (rc == OR_OK) rc = or_resample(n, w + lo, U[g], idx + lo);
+        if (rc == OR_OK)
+            for (int j = 0; j < n; ++j)
+                for (int c = 0; c < d_s; ++c)
+                    S_out[(size_t)(lo + j) * d_s + c] = S[(size_t)(lo + idx[lo + j]) * d_s + c];
+    }
+    release_rounded(&rm);
+    return rc;
 }

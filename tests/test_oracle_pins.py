@@ -565,3 +565,109 @@ def test_plan_steps_are_the_states_the_returns_are_taken_on():
     # H = 0 and K = 0 write nothing
     t0, o0 = oracle.plan_steps(w.model, w.states, w.cands[:, :0], seed=1)
     assert t0.shape == (w.K, w.N, 0, w.model.d_s) and o0.shape == (w.K, w.N, 0, w.model.d_o)
+
+
+# ----------------------------------------------------------------------------- progressive widening
+def test_pw_widen_matches_integer_forms():
+    """|C| < k N^alpha in integer form where the threshold is exact:
+    k = 1, alpha = 1/2 -> C^2 < N; k = 1/2, alpha = 1 -> 2C < N; plus the
+    no-branch and capacity rules."""
+    B = 16
+    for N in range(0, 300):
+        for C in range(0, B + 2):
+            got1 = oracle.pw_widen(N, C, 1.0, 0.5, B)
+            got2 = oracle.pw_widen(N, C, 0.5, 1.0, B)
+            if C >= B:
+                assert got1 == 0 and got2 == 0
+            elif C == 0:
+                assert got1 == 1 and got2 == 1
+            else:
+                assert got1 == int(C * C < N), (N, C)
+                assert got2 == int(2 * C < N), (N, C)
+
+
+def pw_case(seed, M=40, B=6, d_max=60, model=None):
+    rng = np.random.default_rng(seed)
+    w = workloads.small(seed=seed, N=8, K=1, H=1) if model is None else None
+    m = model or w.model
+    sizes = rng.integers(0, d_max, M)
+    sizes[:3] = [0, 1, d_max]
+    seg = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    T = int(seg[-1])
+    succ = rng.standard_normal((T, m.d_s)).astype(np.float32)
+    actions = rng.integers(0, m.n_actions, M).astype(np.int32) if m.n_actions > 0 else \
+        rng.uniform(-1, 1, (M, m.d_a)).astype(np.float32)
+    children = rng.integers(0, B + 1, M).astype(np.int32)
+    visits = (children.astype(np.int64) ** 2 + rng.integers(-2, 3, M)).clip(0).astype(np.int32)
+    table = rng.standard_normal((M, B, m.d_o)).astype(np.float32)
+    U = rng.integers(0, 2**32, M, dtype=np.uint64).astype(np.uint32)
+    return m, succ, seg, actions, visits, children, table, U
+
+
+def test_pw_step_branch_choice_and_new_observations():
+    m, succ, seg, actions, visits, children, table, U = pw_case(51)
+    seed = 0x5EED
+    out = oracle.pw_step(m, succ, seg, actions, visits, children, table, 1.0, 0.5, 1.0, seed, U)
+    M, B = len(visits), table.shape[1]
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    n_new = n_reuse = 0
+    for g in range(M):
+        if seg[g + 1] == seg[g]:
+            assert out["branch"][g] == -1 and out["widen"][g] == 0
+            assert out["children"][g] == children[g]
+            continue
+        wid = oracle.pw_widen(visits[g], children[g], 1.0, 0.5, B)
+        assert out["widen"][g] == wid
+        if wid:
+            n_new += 1
+            assert out["branch"][g] == children[g] and out["children"][g] == children[g] + 1
+            nz = oracle.normals(seed, 0, g, 0, 4, m.d_wz)
+            o_ref = oracle.observe(m, succ[seg[g]][None, :], [int(actions[g])], noise=nz[None, :])[0]
+            np.testing.assert_array_equal(out["obs_table"][g, children[g]], o_ref)
+        else:
+            n_reuse += 1
+            word = oracle.philox([g, 1, 0, 6 << 16], key)[0]
+            assert out["branch"][g] == int(np.floor(oracle.uniform(word) * children[g]))
+            assert 0 <= out["branch"][g] < children[g]
+            assert out["children"][g] == children[g]
+        untouched = [b for b in range(B) if not (wid and b == children[g])]
+        np.testing.assert_array_equal(out["obs_table"][g, untouched], np.asarray(table[g, untouched], np.float64))
+    assert n_new > 5 and n_reuse > 5
+
+
+def test_pw_step_groups_are_independent_updates():
+    """Each group: l from the likelihood network against the chosen branch's
+    observation, weights and resampling of the single-belief definitions."""
+    m, succ, seg, actions, visits, children, table, U = pw_case(52)
+    out = oracle.pw_step(m, succ, seg, actions, visits, children, table, 1.0, 0.5, 0.7, 99, U)
+    aw = m.n_actions
+    for g in range(len(visits)):
+        lo, hi = seg[g], seg[g + 1]
+        if hi == lo:
+            continue
+        o = out["obs_table"][g, out["branch"][g]]
+        X = np.concatenate([succ[lo:hi].astype(np.float64), np.tile(np.eye(aw)[actions[g]], (hi - lo, 1)),
+                            np.tile(o, (hi - lo, 1))], axis=1)
+        ll = oracle.mlp(m.lik, X)[:, 0]
+        np.testing.assert_array_equal(out["loglik"][lo:hi], ll)
+        w, st = oracle.normalize(ll, 0.7)
+        np.testing.assert_array_equal(out["w"][lo:hi], w)
+        np.testing.assert_array_equal(out["stats"][g], st)
+        idx = oracle.resample(w, U[g])
+        np.testing.assert_array_equal(out["idx"][lo:hi], idx)
+        np.testing.assert_array_equal(out["S_out"][lo:hi], succ[lo:hi][idx])
+
+
+def test_pw_reused_branches_are_uniform():
+    M, C = 5000, 5
+    rng = np.random.default_rng(53)
+    w = workloads.small(seed=53, N=8, K=1, H=1)
+    m = w.model
+    seg = np.arange(M + 1, dtype=np.int32)
+    succ = rng.standard_normal((M, 4)).astype(np.float32)
+    out = oracle.pw_step(m, succ, seg, np.zeros(M, np.int32), np.full(M, 4, np.int32), np.full(M, C, np.int32),
+                         np.zeros((M, C, 2)), 1.0, 0.5, 1.0, 7, np.zeros(M, np.uint32))
+    assert not out["widen"].any()
+    counts = np.bincount(out["branch"], minlength=C)
+    chi2 = ((counts - M / C) ** 2 / (M / C)).sum()
+    assert chi2 < 20.5   # 4 degrees of freedom, p ~ 4e-4
