@@ -283,6 +283,50 @@ def bench_plan_observe(V, torch, reps, w, S, C):
     return out
 
 
+def bench_pw(V, torch, reps):
+    """Grouped progressive widening with the realistic networks: 4,096 action
+    nodes with U{1..1024} successors each (about 2.1 M successors), binary32
+    and bfloat16."""
+    import workloads
+    dev = torch.device("cuda", 0)
+    w = workloads.realistic(seed=7, N=8, K=1, H=1)
+    rng = np.random.default_rng(7)
+    M, B = 4096, 8
+    sizes = rng.integers(1, 1025, M)
+    seg = torch.as_tensor(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32), device=dev)
+    T = int(sizes.sum())
+    succ = torch.as_tensor(rng.standard_normal((T, w.model.d_s)).astype(np.float32), device=dev)
+    actions = torch.as_tensor(rng.uniform(-1, 1, (M, w.model.d_a)).astype(np.float32), device=dev)
+    children0 = rng.integers(0, B + 1, M).astype(np.int32)
+    visits = torch.as_tensor((children0.astype(np.int64) ** 2 + rng.integers(-2, 3, M)).clip(0).astype(np.int32),
+                             device=dev)
+    table0 = torch.as_tensor(rng.standard_normal((M, B, w.model.d_o)).astype(np.float32), device=dev)
+    U = torch.as_tensor(rng.integers(0, 2**31, M).astype(np.int32), device=dev)
+    out = {"groups": M, "successors": T}
+    stream = torch.cuda.current_stream()
+    for compute in ["f32", "bf16"]:
+        m = V.Model(w.model, compute=compute)
+        ws = torch.empty(int(V.lib.voila_pw_step_workspace_size(m.handle, T, M)), dtype=torch.uint8, device=dev)
+        res = None
+        ms = []
+        for r in range(reps + 1):
+            ch = torch.as_tensor(children0, device=dev)
+            tab = table0.clone()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            res = V.pw_step(m, succ, seg, actions, visits, ch, tab, U, 1.0, 0.5, lam=1.0, seed=r, out=res,
+                            workspace=ws)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                ms.append(a.elapsed_time(b))
+        t = float(np.median(ms))
+        out[compute] = {"ms": t, "successors_per_s": T / (t / 1e3),
+                        "widened": int(res["widen"].sum().item())}
+        print(f"[bench]   {compute}: {t:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_grad(V, torch, reps):
     """Adjoint through 65,536 rollouts x 20 steps (checkpoint every 5): distillation
     gradient w.r.t. the 5,316 parameters; return gradient w.r.t. [1024, 20, 4] actions."""
@@ -532,6 +576,8 @@ def main():
         result["wide_bf16"] = bench_wide(V, torch, max(2, args.steps // 2))
         print("[bench] rollout states and per-step observations", file=sys.stderr, flush=True)
         result["plan_observe"] = bench_plan_observe(V, torch, max(2, args.steps // 2), w, S, C)
+        print("[bench] grouped progressive widening", file=sys.stderr, flush=True)
+        result["pw_step"] = bench_pw(V, torch, max(3, args.steps))
         print("[bench] belief-update sweep", file=sys.stderr, flush=True)
         result["update_sweep"] = bench_update_sweep(V, torch, max(3, args.steps))
 

@@ -251,6 +251,50 @@ voila_status_t voila_plan_observe(voila_model_t model, const float* d_traj, int3
                                   void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Grouped progressive widening (Sec. 4.3): the simulations of a planning
+ * pass are grouped by their parent action node and all groups are handled at
+ * once.  For each of the M nodes, with successor states d_succ[seg[m] ..
+ * seg[m+1]) simulated under the node's action a_m:
+ *   1. widen_m = |C(a)| < k_o N(a)^alpha_o in binary64 (N(a) = d_visits[m],
+ *      |C(a)| = d_children[m]); a node without branches always widens, a
+ *      node with `capacity` branches never does.
+ *   2. widening: o = f_Z([s'_first, a_m, w_Z]) (Eq. 5) at the group's first
+ *      successor, w_Z from Philox stream 4 at counter (0, m, 0), becomes
+ *      branch |C(a)| of the node (d_obs_table[m][branch]) and d_children[m]
+ *      grows by one; otherwise an existing branch is taken uniformly:
+ *      floor(u |C(a)|), u the uniform of word 0 of Philox at counter
+ *      (m, 1, 0, 6 << 16).  Both draws use key `seed`.
+ *   3. l_j = l([s'_j, a_m, o_branch]) for the group's successors, weights
+ *      w_j = exp(l_j / lambda) / sum over the group (binary64), stats
+ *      {log evidence - log n_m, ESS}, systematic resampling of the group
+ *      with offset d_U[m] (as voila_resample), d_succ_out rows gathered.
+ * d_succ [T][d_s] float; d_seg [M + 1] int32 (seg[0] = 0, non-decreasing,
+ * seg[M] = T, every group at most 8192 successors: a group that breaks this
+ * sets *d_status to VOILA_ERR_INVALID_ARG and is skipped); d_actions int32
+ * [M] or float [M][d_a]; d_visits [M] int32; d_children [M] int32 in
+ * [0, capacity] (updated); d_obs_table [M][capacity][d_o] float (updated:
+ * the new branch's row); d_U [M] uint32.  Outputs (NULL to skip, except as
+ * noted): d_widen_out [M] int32 flags, d_branch_out [M] int32 (-1 for an
+ * empty group), d_loglik_out [T] float, d_w_out [T] double, d_stats_out
+ * [M][2] double, d_idx_out [T] int32 indices within each group,
+ * d_succ_out [T][d_s] float.  Non-finite likelihoods set VOILA_ERR_NUMERIC.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double k_o, alpha_o;    /* widening constants, > 0                          */
+    double lambda;          /* likelihood temperature, > 0                      */
+    uint64_t seed;          /* Philox key of new-branch noise and branch draws  */
+    int32_t capacity;       /* branches per node in d_obs_table, >= 1          */
+} voila_pw_opts_t;
+
+size_t voila_pw_step_workspace_size(voila_model_t model, int32_t T, int32_t M);
+voila_status_t voila_pw_step(voila_model_t model, const float* d_succ, int32_t T, const int32_t* d_seg, int32_t M,
+                             const void* d_actions, const int32_t* d_visits, int32_t* d_children,
+                             float* d_obs_table, const uint32_t* d_U, const voila_pw_opts_t* h_opts,
+                             void* d_workspace, size_t workspace_bytes, int32_t* d_widen_out,
+                             int32_t* d_branch_out, float* d_loglik_out, double* d_w_out, double* d_stats_out,
+                             int32_t* d_idx_out, float* d_succ_out, int32_t* d_status, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batches: many independent planning instances (uneven N, K, H; one network
  * each, all of one shape and precision) in one persistent launch, each
  * followed by its own belief update (the per-action-node grouping of

@@ -72,6 +72,11 @@ class _BatchItem(ctypes.Structure):
                 ("d_w_out", c_void_p), ("d_stats_out", c_void_p)]
 
 
+class _PwOpts(ctypes.Structure):
+    _fields_ = [("k_o", c_double), ("alpha_o", c_double), ("lambda_", c_double), ("seed", c_uint64),
+                ("capacity", c_int32)]
+
+
 class _GradOpts(ctypes.Structure):
     _fields_ = [("B", c_int32), ("H", c_int32), ("checkpoint", c_int32), ("d_s0", c_void_p),
                 ("d_actions", c_void_p), ("particles", c_int32), ("d_noise", c_void_p), ("seed", c_uint64),
@@ -136,6 +141,11 @@ def _load():
     L.voila_plan_observe.argtypes = [vp, vp, c_int32, vp, c_int32, c_int32, c_uint64, c_int32, vp, vp, c_size_t, vp,
                                      vp, vp]
     L.voila_plan_observe.restype = c_int32
+    L.voila_pw_step_workspace_size.argtypes = [vp, c_int32, c_int32]
+    L.voila_pw_step_workspace_size.restype = c_size_t
+    L.voila_pw_step.argtypes = [vp, vp, c_int32, vp, c_int32, vp, vp, vp, vp, vp, POINTER(_PwOpts), vp, c_size_t,
+                                vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.voila_pw_step.restype = c_int32
     L.voila_philox_normals.argtypes = [c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int32, c_int32, vp,
                                        vp, vp]
     L.voila_philox_normals.restype = c_int32
@@ -167,7 +177,7 @@ EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_m
             "voila_reweight_resample",
             "voila_resample_bits",
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_plan_observe_workspace_size",
-            "voila_plan_observe", "voila_philox_normals",
+            "voila_plan_observe", "voila_pw_step_workspace_size", "voila_pw_step", "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
             "voila_batch_replay", "voila_grad_param_count", "voila_rollout_grad_workspace_size",
             "voila_rollout_grad"]
@@ -342,6 +352,49 @@ def plan_observe(model: Model, traj, cands, seed=0, crn=False, noise=None, out=N
                                   int(bool(crn)), _ptr(noise), _ptr(workspace), workspace.numel(), _ptr(o),
                                   _ptr(status), _stream(stream)))
     return o
+
+
+def pw_step(model: Model, succ, seg, actions, visits, children, obs_table, U, k_o, alpha_o, lam=1.0, seed=0,
+            out=None, workspace=None, status=None, stream=None):
+    """Grouped progressive widening over M action nodes (successors
+    succ[seg[m]:seg[m+1]]).  `children` [M] int32 and `obs_table`
+    [M, capacity, d_o] float32 are updated in place.  Returns dict(widen,
+    branch, loglik, w, stats, idx, succ)."""
+    d = model.desc
+    T = int(succ.shape[0])
+    M = int(seg.shape[0]) - 1
+    _dev(succ, torch.float32, (T, d.d_s), "succ")
+    _dev(seg, torch.int32, (M + 1,), "seg")
+    if d.n_actions > 0:
+        _dev(actions, torch.int32, (M,), "actions")
+    else:
+        _dev(actions, torch.float32, (M, d.d_a), "actions")
+    _dev(visits, torch.int32, (M,), "visits")
+    _dev(children, torch.int32, (M,), "children")
+    if obs_table.dim() != 3:
+        raise VoilaError(VOILA_ERR_INVALID_ARG, "obs_table must be [M, capacity, d_o]")
+    B = int(obs_table.shape[1])
+    _dev(obs_table, torch.float32, (M, B, d.d_o), "obs_table")
+    _dev(U, torch.int32, (M,), "U")
+    dev = succ.device
+    o = out if out is not None else {}
+    res = {"widen": o.get("widen", torch.empty(M, dtype=torch.int32, device=dev)),
+           "branch": o.get("branch", torch.empty(M, dtype=torch.int32, device=dev)),
+           "loglik": o.get("loglik", torch.empty(T, dtype=torch.float32, device=dev)),
+           "w": o.get("w", torch.empty(T, dtype=torch.float64, device=dev)),
+           "stats": o.get("stats", torch.empty((M, 2), dtype=torch.float64, device=dev)),
+           "idx": o.get("idx", torch.empty(T, dtype=torch.int32, device=dev)),
+           "succ": o.get("succ", torch.empty((T, d.d_s), dtype=torch.float32, device=dev))}
+    opts = _PwOpts(float(k_o), float(alpha_o), float(lam), int(seed) & (2**64 - 1), B)
+    if workspace is None:
+        n = lib.voila_pw_step_workspace_size(model.handle, T, M)
+        workspace = torch.empty(max(int(n), 1), dtype=torch.uint8, device=dev)
+    _check(lib.voila_pw_step(model.handle, _ptr(succ), T, _ptr(seg), M, _ptr(actions), _ptr(visits), _ptr(children),
+                             _ptr(obs_table), _ptr(U), ctypes.byref(opts), _ptr(workspace), workspace.numel(),
+                             _ptr(res["widen"]), _ptr(res["branch"]), _ptr(res["loglik"]), _ptr(res["w"]),
+                             _ptr(res["stats"]), _ptr(res["idx"]), _ptr(res["succ"]), _ptr(status),
+                             _stream(stream)))
+    return res
 
 
 def _action_arg(model, action):

@@ -241,7 +241,7 @@ struct voila_model_s {
     const float* fold_w_lik = nullptr;
     const float* fold_b_lik = nullptr;
     int nf_trans = 0, nf_obs = 0, nf_lik = 0;
-    int plan_bpc = 1, prop_bpc = 1, obs_bpc = 1, obs_roll_bpc = 1;
+    int plan_bpc = 1, prop_bpc = 1, obs_bpc = 1, obs_roll_bpc = 1, pw_bpc = 1;
     bool has_grad = false;
     NetBlob grad_fwd{}, grad_bwd{};
     int grad_bpc = 1, n_params = 0;
@@ -461,6 +461,7 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->prop_bpc = propose_blocks_per_cu(shape, dt);
     m->obs_bpc = observe_blocks_per_cu(shape, dt);
     m->obs_roll_bpc = observe_rollout_blocks_per_cu(shape, dt);
+    m->pw_bpc = pw_lik_blocks_per_cu(shape, dt);
     if (m->has_grad) m->grad_bpc = grad_blocks_per_cu(shape, grad_lds_bytes(m));
     *out = m;
     return VOILA_OK;
@@ -886,6 +887,147 @@ voila_status_t voila_observe(voila_model_t m, const float* d_states, int32_t n, 
     p.key0 = (uint32_t)(seed & 0xffffffffu);
     p.key1 = (uint32_t)(seed >> 32);
     VOILA_CHECK_HIP(launch_observe(m->shape, m->dt, p, observe_blocks(m, (n + 31) / 32), s));
+    return VOILA_OK;
+}
+
+namespace {
+struct PwWs {
+    float* first;
+    float* b0_obs;
+    float* o_new;
+    float* o_sel;
+    float* b0_lik;
+    int32_t* tiles;
+    double* x;
+    size_t bytes;
+};
+PwWs carve_pw(char* base, voila_model_t m, int T, int M) {
+    PwWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + off;
+        off = align_up(off + bytes, 256);
+        return p;
+    };
+    w.first = reinterpret_cast<float*>(take((size_t)M * m->d_s * 4));
+    w.b0_obs = reinterpret_cast<float*>(take((size_t)M * m->width * 4));
+    w.o_new = reinterpret_cast<float*>(take((size_t)M * m->d_o * 4));
+    w.o_sel = reinterpret_cast<float*>(take((size_t)M * m->d_o * 4));
+    w.b0_lik = reinterpret_cast<float*>(take((size_t)M * m->width * 4));
+    w.tiles = reinterpret_cast<int32_t*>(take(((size_t)M + 1) * 4));
+    w.x = reinterpret_cast<double*>(take((size_t)T * 8));
+    w.bytes = off;
+    return w;
+}
+}  // namespace
+
+size_t voila_pw_step_workspace_size(voila_model_t m, int32_t T, int32_t M) {
+    if (!m || T < 0 || M < 0) return 0;
+    return carve_pw(nullptr, m, T, M).bytes;
+}
+
+voila_status_t voila_pw_step(voila_model_t m, const float* d_succ, int32_t T, const int32_t* d_seg, int32_t M,
+                             const void* d_actions, const int32_t* d_visits, int32_t* d_children,
+                             float* d_obs_table, const uint32_t* d_U, const voila_pw_opts_t* o, void* ws,
+                             size_t ws_bytes, int32_t* d_widen_out, int32_t* d_branch_out, float* d_loglik_out,
+                             double* d_w_out, double* d_stats_out, int32_t* d_idx_out, float* d_succ_out,
+                             int32_t* d_status, void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!m->has_obs || !m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model needs observation and likelihood networks");
+    if (!o) return fail(VOILA_ERR_INVALID_ARG, "NULL options");
+    if (T < 0 || M < 0) return fail(VOILA_ERR_INVALID_ARG, "T and M must be >= 0");
+    if (o->capacity < 1) return fail(VOILA_ERR_INVALID_ARG, "capacity must be >= 1");
+    if (!(o->k_o > 0.0) || !(o->alpha_o > 0.0) || !std::isfinite(o->k_o) || !std::isfinite(o->alpha_o))
+        return fail(VOILA_ERR_INVALID_ARG, "k_o and alpha_o must be finite and > 0");
+    if (!(o->lambda > 0.0) || !std::isfinite(o->lambda)) return fail(VOILA_ERR_INVALID_ARG, "lambda must be > 0");
+    if ((long long)M * o->capacity * m->d_o > (1LL << 31) - 1)
+        return fail(VOILA_ERR_UNSUPPORTED, "M * capacity * d_o must fit in 31 bits");
+    if (M == 0) return VOILA_OK;
+    if (!d_seg || !d_actions || !d_visits || !d_children || !d_obs_table || !d_U || (T > 0 && !d_succ))
+        return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    PwWs w = carve_pw(reinterpret_cast<char*>(ws), m, T, M);
+    if (!ws || ws_bytes < w.bytes) return fail(VOILA_ERR_WORKSPACE, "progressive-widening workspace too small");
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    PwParams p{};
+    p.lik = m->lik;
+    p.succ = d_succ;
+    p.seg = d_seg;
+    p.actions = d_actions;
+    p.visits = d_visits;
+    p.children = d_children;
+    p.table = d_obs_table;
+    p.U = d_U;
+    p.first = w.first;
+    p.o_new = w.o_new;
+    p.o_sel = w.o_sel;
+    p.b0_lik = w.b0_lik;
+    p.tiles = w.tiles;
+    p.x = w.x;
+    p.widen = d_widen_out;
+    p.branch = d_branch_out;
+    p.loglik = d_loglik_out;
+    p.w = d_w_out;
+    p.stats = d_stats_out;
+    p.idx = d_idx_out;
+    p.succ_out = d_succ_out;
+    p.status = d_status;
+    p.T = T;
+    p.M = M;
+    p.B = o->capacity;
+    p.d_s = m->d_s;
+    p.d_o = m->d_o;
+    p.k_o = o->k_o;
+    p.alpha_o = o->alpha_o;
+    p.lambda = o->lambda;
+    p.key0 = (uint32_t)(o->seed & 0xffffffffu);
+    p.key1 = (uint32_t)(o->seed >> 32);
+    // 1. an observation drawn at each group's first successor (used by the groups that widen)
+    VOILA_CHECK_HIP(launch_pw_first(p, s));
+    FoldStepsParams fo{};
+    fo.w = m->fold_w_obs;
+    fo.b = m->fold_b_obs;
+    fo.out = w.b0_obs;
+    fo.cands = d_actions;
+    fo.width = m->width;
+    fo.nf = m->nf_obs;
+    fo.rows = M;
+    fo.n_actions = m->n_actions;
+    fo.d_a = m->d_a;
+    fo.bf16 = m->dt == DT_BF16 ? 1 : 0;
+    fo.status = d_status;
+    VOILA_CHECK_HIP(launch_fold_steps(fo, s));
+    ObserveParams op{};
+    op.obs = m->obs;
+    op.b0 = w.b0_obs;
+    op.b0_stride = m->width;
+    op.states = w.first;
+    op.out = w.o_new;
+    op.N = 1;
+    op.K = M;
+    op.H = 1;
+    op.key0 = p.key0;
+    op.key1 = p.key1;
+    VOILA_CHECK_HIP(launch_observe(m->shape, m->dt, op, observe_blocks(m, M), s));
+    // 2. widening test, branch choice, table update
+    VOILA_CHECK_HIP(launch_pw_branch(p, s));
+    // 3. likelihood of every successor against its group's branch observation
+    FoldStepsParams fl = fo;
+    fl.w = m->fold_w_lik;
+    fl.b = m->fold_b_lik;
+    fl.out = w.b0_lik;
+    fl.nf = m->nf_lik;
+    fl.obs = w.o_sel;
+    fl.d_o = m->d_o;
+    VOILA_CHECK_HIP(launch_fold_steps(fl, s));
+    VOILA_CHECK_HIP(launch_pw_tiles(p, s));
+    const long units = (long)T / 32 + M;
+    const long want = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+    const long cap = (long)m->cus * m->pw_bpc;
+    VOILA_CHECK_HIP(launch_pw_lik(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));
+    // 4. per-group weights and systematic resampling
+    VOILA_CHECK_HIP(launch_pw_norm_res(p, M < m->cus ? M : m->cus, s));
     return VOILA_OK;
 }
 

@@ -307,6 +307,15 @@ __global__ __launch_bounds__(256) void fold_steps_kernel(FoldStepsParams p) {
                 acc += p.w[(size_t)r * p.nf + c] * v;
             }
         }
+        if (p.obs) {
+            const int c0 = p.n_actions > 0 ? p.n_actions : p.d_a;
+            const float* ob = p.obs + (size_t)j * p.d_o;
+            for (int c = 0; c < p.d_o; ++c) {
+                float v = ob[c];
+                if (p.bf16) v = (float)(__bf16)v;
+                acc += p.w[(size_t)r * p.nf + c0 + c] * v;
+            }
+        }
         p.out[(size_t)j * p.width + r] = acc;
     }
 }
@@ -827,6 +836,183 @@ __global__ __launch_bounds__(kNormResThreads) void norm_res_batch_kernel(const N
     norm_res_body(p, buf, redd, redi, ids);
 }
 
+// ---------------------------------------------------------------------------
+// grouped progressive widening (simulations grouped by parent action node)
+// ---------------------------------------------------------------------------
+namespace {
+// Group m's successors [lo, lo + n) if the offsets are consistent and the
+// group fits one workgroup; otherwise the group is skipped and *status set.
+__device__ __forceinline__ bool pw_group(const PwParams& p, int m, int& lo, int& n) {
+    lo = p.seg[m];
+    const int hi = p.seg[m + 1];
+    n = hi - lo;
+    if (lo < 0 || hi < lo || hi > p.T || n > kPwMaxGroup) {
+        if (p.status) p.status[0] = 1;
+        n = 0;
+        return false;
+    }
+    return true;
+}
+}  // namespace
+
+// First successor of each group (the state a new branch's observation is drawn at).
+__global__ __launch_bounds__(256) void pw_first_kernel(PwParams p) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= p.M * p.d_s) return;
+    const int m = e / p.d_s, c = e - m * p.d_s;
+    int lo, n;
+    pw_group(p, m, lo, n);
+    p.first[e] = n > 0 ? p.succ[(size_t)lo * p.d_s + c] : 0.0f;
+}
+
+// Widening test, branch choice and table update, one thread per action node.
+__global__ __launch_bounds__(256) void pw_branch_kernel(PwParams p) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= p.M) return;
+    int lo, n;
+    pw_group(p, m, lo, n);
+    int wid = 0, br = -1;
+    const int C = p.children[m];
+    if (C < 0 || C > p.B) {
+        if (p.status) p.status[0] = 1;
+        n = 0;
+    }
+    if (n > 0) {
+        wid = C < p.B && (C == 0 || (double)C < p.k_o * pow((double)p.visits[m], p.alpha_o));
+        float* row = p.table + (size_t)m * p.B * p.d_o;
+        if (wid) {
+            br = C;
+            for (int c = 0; c < p.d_o; ++c) row[(size_t)br * p.d_o + c] = p.o_new[(size_t)m * p.d_o + c];
+            p.children[m] = C + 1;
+        } else {
+            const uint4 w = philox4x32_10(make_uint4((uint32_t)m, 1u, 0u, 6u << 16), p.key0, p.key1);
+            br = (int)floor((double)word_to_uniform(w.x) * (double)C);
+        }
+        for (int c = 0; c < p.d_o; ++c) p.o_sel[(size_t)m * p.d_o + c] = row[(size_t)br * p.d_o + c];
+    } else {
+        for (int c = 0; c < p.d_o; ++c) p.o_sel[(size_t)m * p.d_o + c] = 0.0f;
+    }
+    if (p.widen) p.widen[m] = wid;
+    if (p.branch) p.branch[m] = br;
+}
+
+// Exclusive prefix of the groups' 32-row tile counts (one workgroup).
+__global__ __launch_bounds__(1024) void pw_tiles_kernel(PwParams p) {
+    __shared__ int wtot[16];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int per = (p.M + 1023) / 1024;
+    const int a = tid * per, b = min(p.M, a + per);
+    int run = 0;
+    for (int m = a; m < b; ++m) {
+        int lo, n;
+        pw_group(p, m, lo, n);
+        run += (n + 31) / 32;
+    }
+    int incl = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int o = __shfl_up(incl, d);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wtot[tid >> 6] = incl;
+    __syncthreads();
+    int off = incl - run;
+    for (int w = 0; w < (tid >> 6); ++w) off += wtot[w];
+    for (int m = a; m < b; ++m) {
+        int lo, n;
+        pw_group(p, m, lo, n);
+        p.tiles[m] = off;
+        off += (n + 31) / 32;
+    }
+    if (tid == 1023) p.tiles[p.M] = off;
+}
+
+// Likelihood of every successor against its group's chosen observation:
+// x_j = l([s'_j, a_m, o_m]) / lambda, one 32-row tile of one group per wave.
+template <int DT, int D_S, int WIDTH, int NHID, int MODE>
+__global__ __launch_bounds__(256) void pw_lik_kernel(PwParams p) {
+    if constexpr (!net_compiled(DT, WIDTH)) {
+        return;  // binary32 networks wider than 256 are refused at model creation
+    } else {
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, 0)> NTL;
+    constexpr int SS = state_slots(D_S);
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wpb = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const kconst int32_t* tiles = (const kconst int32_t*)p.tiles;
+    const kconst int32_t* seg = (const kconst int32_t*)p.seg;
+    const long n_units = tiles[p.M];
+    with_weights<NTL, MODE, 1>(smem, p.lik, [&](auto& src, const NetPtrs& P) {
+        // block-uniform loop (a streamed network's chunk barriers need every wave)
+        for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
+            const int u = (int)(ub * wpb + wave);
+            const bool ok = u < n_units;
+            // the group of this tile: the last m with tiles[m] <= u
+            int a = 0, b = p.M;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (tiles[mid] <= u) a = mid;
+                else b = mid - 1;
+            }
+            const int m = ok ? a : 0;
+            const int lo = seg[m], hi = seg[m + 1];
+            const int j = ok ? lo + (u - tiles[m]) * 32 + col : 0;
+            const bool valid = ok && j < hi;
+            float slots[NTL::IN_SLOTS];
+#pragma unroll
+            for (int s = 0; s < NTL::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+            for (int s = 0; s < SS; ++s) {
+                const int f = 2 * s + g;
+                slots[s] = (valid && f < D_S) ? p.succ[(size_t)j * D_S + f] : 0.0f;
+            }
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+            const f32x16 o = run_net<NTL>(src, P, p.b0_lik + (size_t)m * NTL::WIDTH, slots, lane, g);
+            if (g == 0 && valid) {
+                const float l = o[0];
+                if (p.loglik) p.loglik[j] = l;
+                if (!isfinite(l) && p.status) p.status[0] = 5;
+                p.x[j] = (double)l / p.lambda;
+            }
+        }
+    });
+    }
+}
+
+// Weights, statistics and systematic resampling of every group, one
+// workgroup per group (the single-belief procedure on the group's rows).
+__global__ __launch_bounds__(kNormResThreads) void pw_norm_res_kernel(PwParams pw) {
+    __shared__ double buf[kNormResMaxN];
+    __shared__ int ids[kNormResMaxN];
+    __shared__ double redd[kNRWaves];
+    __shared__ int redi[kNRWaves];
+    for (int m = blockIdx.x; m < pw.M; m += gridDim.x) {
+        int lo, n;
+        pw_group(pw, m, lo, n);
+        if (n == 0) continue;
+        int c = 0;
+        while ((1 << c) < n) ++c;
+        NormResParams p{};
+        p.x = pw.x + lo;
+        p.lambda = pw.lambda;
+        p.N = n;
+        p.bits = 52 - c < 32 ? 52 - c : 32;
+        p.uniform_prior = 1;
+        p.do_resample = 1;
+        p.U = pw.U[m];
+        p.w_out = pw.w ? pw.w + lo : nullptr;
+        p.stats = pw.stats ? pw.stats + 2 * (size_t)m : nullptr;
+        p.idx_out = pw.idx ? pw.idx + lo : nullptr;
+        p.src = pw.succ_out ? pw.succ + (size_t)lo * pw.d_s : nullptr;
+        p.dst = pw.succ_out ? pw.succ_out + (size_t)lo * pw.d_s : nullptr;
+        p.row_floats = pw.d_s;
+        p.status = pw.status;
+        norm_res_body(p, buf, redd, redi, ids);
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(256) void philox_kernel(PhiloxParams p) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= p.n) return;
@@ -1059,6 +1245,59 @@ int observe_blocks_per_cu(int shape, int dt) {
     return 1;
 }
 
+#define PWL_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) pw_lik_kernel<DT, ds, w, nh, plan_mode<w>()>
+
+hipError_t launch_pw_lik(int shape, int dt, const PwParams& p, int blocks, hipStream_t s) {
+    size_t lds = p.lik.bytes;
+    if (!weights_in_lds(shape)) {
+        switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                           \
+    case id * 2 + 0:                                                    \
+        lds = stream_lds_of<DT_F32, ds, 0, 0, 0, w, nh>();              \
+        break;                                                          \
+    case id * 2 + 1:                                                    \
+        lds = stream_lds_of<DT_BF16, ds, 0, 0, 0, w, nh>();             \
+        break;
+            VOILA_SHAPES(X)
+#undef X
+        }
+        lds += p.lik.bytes - p.lik.off_b0;
+    }
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                \
+    case id * 2 + 0:                                                                                         \
+        if (lds > 65536)                                                                                     \
+            (void)hipFuncSetAttribute((const void*)PWL_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),        \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                 \
+        hipLaunchKernelGGL((PWL_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);     \
+        break;                                                                                               \
+    case id * 2 + 1:                                                                                         \
+        if (lds > 65536)                                                                                     \
+            (void)hipFuncSetAttribute((const void*)PWL_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),       \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                 \
+        hipLaunchKernelGGL((PWL_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p);    \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int pw_lik_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
+    case id * 2 + 0:                                                                                        \
+        return occupancy(PWL_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kStreamLds); \
+    case id * 2 + 1:                                                                                        \
+        return occupancy(PWL_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kStreamLds);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
 int observe_rollout_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
@@ -1189,6 +1428,30 @@ hipError_t launch_fold(const FoldParams& p, hipStream_t s) {
 hipError_t launch_fold_steps(const FoldStepsParams& p, hipStream_t s) {
     if (p.rows == 0) return hipSuccess;
     hipLaunchKernelGGL(fold_steps_kernel, dim3((p.width + 255) / 256, p.rows < 65535 ? p.rows : 65535), 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pw_first(const PwParams& p, hipStream_t s) {
+    const int n = p.M * p.d_s;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(pw_first_kernel, (n + 255) / 256, 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pw_branch(const PwParams& p, hipStream_t s) {
+    if (p.M == 0) return hipSuccess;
+    hipLaunchKernelGGL(pw_branch_kernel, (p.M + 255) / 256, 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pw_tiles(const PwParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(pw_tiles_kernel, 1, 1024, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pw_norm_res(const PwParams& p, int blocks, hipStream_t s) {
+    if (p.M == 0 || blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(pw_norm_res_kernel, blocks, kNormResThreads, 0, s, p);
     return hipGetLastError();
 }
 

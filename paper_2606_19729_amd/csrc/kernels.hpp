@@ -89,14 +89,45 @@ struct ObserveParams {
     uint32_t key0, key1;
 };
 
-// First-layer biases with the action of each (candidate, step) folded in.
+// First-layer biases with the action (and observation) of each row folded in.
 struct FoldStepsParams {
-    const float* w;      // [width][nf] action columns of the first layer
+    const float* w;      // [width][nf] action (then observation) columns of the first layer
     const float* b;      // [width]
     float* out;          // [rows][width]
     const void* cands;   // int32 [rows] action indices or float [rows][d_a]
-    int width, nf, rows, n_actions, d_a, bf16;
+    const float* obs;    // [rows][d_o] observations to fold, or NULL
+    int width, nf, rows, n_actions, d_a, d_o, bf16;
     int32_t* status;     // or NULL
+};
+
+// Grouped progressive-widening step over M action nodes (groups of successors
+// seg[m] .. seg[m+1]).
+struct PwParams {
+    NetBlob lik;
+    const float* succ;        // [T][d_s]
+    const int32_t* seg;       // [M + 1]
+    const void* actions;      // int32 [M] or float [M][d_a]
+    const int32_t* visits;    // [M]
+    int32_t* children;        // [M], updated
+    float* table;             // [M][B][d_o], updated
+    const uint32_t* U;        // [M] resampling offsets
+    float* first;             // [M][d_s] first successor of each group (workspace)
+    const float* o_new;       // [M][d_o] observation drawn at the first successor
+    float* o_sel;             // [M][d_o] observation of the chosen branch (workspace)
+    const float* b0_lik;      // [M][width] folded likelihood biases
+    int32_t* tiles;           // [M + 1] exclusive prefix of the groups' 32-row tile counts
+    double* x;                // [T] l / lambda
+    int32_t* widen;           // [M] or NULL
+    int32_t* branch;          // [M] or NULL
+    float* loglik;            // [T] or NULL
+    double* w;                // [T] or NULL
+    double* stats;            // [M][2] or NULL
+    int32_t* idx;             // [T] indices within the group, or NULL
+    float* succ_out;          // [T][d_s] or NULL
+    int32_t* status;          // or NULL
+    int T, M, B, d_s, d_o;
+    double k_o, alpha_o, lambda;
+    uint32_t key0, key1;
 };
 
 struct NormResParams {
@@ -229,6 +260,14 @@ hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipSt
 hipError_t launch_q_reduce(const QReduceParams& p, hipStream_t s);
 hipError_t launch_fold(const FoldParams& p, hipStream_t s);
 hipError_t launch_fold_steps(const FoldStepsParams& p, hipStream_t s);
+// Grouped progressive-widening stages.
+hipError_t launch_pw_first(const PwParams& p, hipStream_t s);
+hipError_t launch_pw_branch(const PwParams& p, hipStream_t s);
+hipError_t launch_pw_tiles(const PwParams& p, hipStream_t s);
+hipError_t launch_pw_lik(int shape, int dt, const PwParams& p, int blocks, hipStream_t s);
+int pw_lik_blocks_per_cu(int shape, int dt);
+hipError_t launch_pw_norm_res(const PwParams& p, int blocks, hipStream_t s);
+constexpr int kPwMaxGroup = 8192;  // successors per group (one workgroup normalises and resamples a group)
 hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
 hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);
 // The observe kernel sized for the rows of whole rollouts (weights streamed like the rollout kernel's).
