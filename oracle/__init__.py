@@ -66,6 +66,7 @@ def lib():
         L.or_pw_widen.argtypes = [c_int, c_int, c_double, c_double, c_int]
         L.or_pw_step.argtypes = [mp, c_int, dp, c_int, i32p, i32p, dp, i32p, i32p, c_int, dp, c_double, c_double,
                                  c_double, c_uint64, u32p, c_int, i32p, i32p, dp, dp, dp, i32p, dp]
+        L.or_soft_value.argtypes = [c_int, c_int, dp, dp, c_double, dp, dp, i32p]
         L.or_plan_steps.argtypes = [mp, c_int, dp, c_int, c_int, i32p, dp, dp, dp, c_uint64, c_int, c_int,
                                     dp, dp]
         L.or_mlp_param_count.argtypes = [c_int, ip]
@@ -299,6 +300,20 @@ def pw_step(model, succ, seg, actions, visits, children, obs_table, k_o, alpha_o
     out["children"] = ch
     out["obs_table"] = tab
     return out
+
+
+def soft_value(Q, eta, log_pi0=None):
+    """(V [M], pi [M, K], best [M]) of preferences Q [M, K] (1-D: one node)
+    with reference-policy log-probabilities log_pi0 (None: uniform)."""
+    Qa = np.atleast_2d(_d(Q))
+    M, K = Qa.shape
+    lp = None if log_pi0 is None else np.ascontiguousarray(np.atleast_2d(_d(log_pi0)))
+    V = np.zeros(M)
+    pi = np.zeros((M, K))
+    best = np.zeros(M, np.int32)
+    _check(lib().or_soft_value(M, K, _p(np.ascontiguousarray(Qa)), _p(lp), float(eta), _p(V), _p(pi),
+                               _p(best, c_int32)), "soft_value")
+    return V, pi, best
 
 
 def weighted_mean(G, w=None):

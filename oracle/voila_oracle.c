@@ -34,6 +34,9 @@
  *   pw_step   Progressive widening of many action nodes at once (Sec. 4.3):
  *             the widening test, a new or reused observation branch per node,
  *             and each node's successors weighted and resampled as a group.
+ *   soft_value  The log-sum-exp operator of the preference formulation
+ *             (Sec. 2.2): soft value, soft policy and greedy action of the
+ *             candidates' preferences, with a reference-policy prior.
  *   plan_steps  The states of the plan rollouts and an observation drawn
  *             from f_Z at every step (Sec. 4.3 forward-simulates with both
  *             learned samplers).
@@ -1060,5 +1063,50 @@ int or_pw_step(const or_model* m0, int T, const double* S, int M, const int32_t*
                     S_out[(size_t)(lo + j) * d_s + c] = S[(size_t)(lo + idx[lo + j]) * d_s + c];
     }
     release_rounded(&rm);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Soft value and action selection (Sec. 2.2): the log-sum-exp operator      */
+/* L_eta over the preferences of M nodes with K candidates each.             */
+/* ------------------------------------------------------------------------- */
+/* x_k = eta Q_k + log pi0_k (pi0 given as log-probabilities, NULL: uniform
+ * 1/K), i.e. eta times the preference Q_k + (1/eta) log pi0_k;
+ *   V = (1/eta) log sum_k exp(x_k)      (max-shifted, compensated sum)
+ *   pi_k = exp(x_k - eta V)             (the soft policy)
+ *   best = argmax_k x_k                 (lowest k on ties). */
+int or_soft_value(int M, int K, const double* Q, const double* log_pi0, double eta,
+                  double* V, double* pi, int32_t* best)
+{
+    if (M < 0 || K < 1 || !(eta > 0.0) || !isfinite(eta)) return OR_ERR_ARG;
+    double* x = (double*)malloc(sizeof(double) * (size_t)K);
+    if (!x) return OR_ERR_ARG;
+    int rc = OR_OK;
+    for (int m = 0; m < M && rc == OR_OK; ++m) {
+        double mx = -INFINITY;
+        int arg = 0;
+        for (int k = 0; k < K; ++k) {
+            size_t e = (size_t)m * K + k;
+            x[k] = eta * Q[e] + (log_pi0 ? log_pi0[e] : -log((double)K));
+            if (isnan(x[k]) || x[k] == INFINITY) { rc = OR_ERR_NUMERIC; break; }
+            if (x[k] > mx) { mx = x[k]; arg = k; }
+        }
+        if (rc != OR_OK) break;
+        if (!isfinite(mx)) { rc = OR_ERR_NUMERIC; break; }
+        double sum = 0.0, comp = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double v = exp(x[k] - mx);
+            double t = sum + v;
+            if (fabs(sum) >= fabs(v)) comp += (sum - t) + v;
+            else comp += (v - t) + sum;
+            sum = t;
+        }
+        double S = sum + comp;
+        V[m] = (mx + log(S)) / eta;
+        if (pi)
+            for (int k = 0; k < K; ++k) pi[(size_t)m * K + k] = exp(x[k] - mx) / S;
+        if (best) best[m] = arg;
+    }
+    free(x);
     return rc;
 }

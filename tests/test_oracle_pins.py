@@ -671,3 +671,33 @@ def test_pw_reused_branches_are_uniform():
     counts = np.bincount(out["branch"], minlength=C)
     chi2 = ((counts - M / C) ** 2 / (M / C)).sum()
     assert chi2 < 20.5   # 4 degrees of freedom, p ~ 4e-4
+
+
+# ----------------------------------------------------------------------------- soft value
+def test_soft_value_against_scipy_and_limits():
+    rng = np.random.default_rng(71)
+    Q = rng.standard_normal((6, 50)) * 3
+    lp = np.log(rng.dirichlet(np.ones(50), size=6))
+    for eta in [0.1, 1.0, 7.0]:
+        V, pi, best = oracle.soft_value(Q, eta, lp)
+        x = eta * Q + lp
+        np.testing.assert_allclose(V, scipy.special.logsumexp(x, axis=1) / eta, rtol=1e-14, atol=1e-14)
+        np.testing.assert_allclose(pi, scipy.special.softmax(x, axis=1), rtol=1e-12, atol=1e-15)
+        assert np.array_equal(best, np.argmax(x, axis=1))
+    # uniform prior: V = (1/eta) log mean exp(eta Q); constant Q gives V = Q exactly
+    V, pi, _ = oracle.soft_value(np.full((1, 8), 2.5), 0.5)
+    assert V[0] == 2.5 and np.all(pi == 0.125)
+    # a single candidate: V = Q + log pi0 / eta
+    V, _, _ = oracle.soft_value(np.array([[1.25]]), 2.0, np.array([[np.log(0.5)]]))
+    assert V[0] == pytest.approx(1.25 + np.log(0.5) / 2.0, abs=1e-15)
+    # eta -> infinity: the maximum; eta -> 0 under the uniform prior: the mean
+    V, _, _ = oracle.soft_value(Q, 1e6)
+    np.testing.assert_allclose(V, Q.max(axis=1), atol=1e-5)
+    V, _, _ = oracle.soft_value(Q, 1e-7)
+    np.testing.assert_allclose(V, Q.mean(axis=1), rtol=1e-5)
+    # shift invariance and ties to the lowest index
+    V2, _, _ = oracle.soft_value(Q + 10.0, 1.0, lp)
+    V1, _, _ = oracle.soft_value(Q, 1.0, lp)
+    np.testing.assert_allclose(V2, V1 + 10.0, rtol=1e-14)
+    _, _, b = oracle.soft_value(np.array([[1.0, 3.0, 3.0, 2.0]]), 1.0)
+    assert b[0] == 1
