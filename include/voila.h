@@ -251,6 +251,22 @@ voila_status_t voila_plan_observe(voila_model_t model, const float* d_traj, int3
                                   void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Soft value and action selection (the log-sum-exp operator L_eta of the
+ * preference formulation the planner builds on, Sec. 2.2): for M nodes with
+ * K candidate preferences each (d_Q [M][K] float, e.g. voila_plan's Q) and a
+ * reference policy (d_log_pi0 [M][K] double log-probabilities, or NULL for
+ * the uniform 1/K), with x_k = eta Q_k + log pi0_k in binary64:
+ *   V_m = (1/eta) log sum_k exp(x_k)       (max-shifted; d_V_out [M] double)
+ *   pi_mk = exp(x_k - eta V_m)             (soft policy; d_pi_out [M][K] or NULL)
+ *   best_m = argmax_k x_k, lowest k on ties (d_best_out [M] int32 or NULL).
+ * eta > 0.  A NaN or +inf preference sets *d_status to VOILA_ERR_NUMERIC and
+ * leaves the node's outputs unwritten.
+ * ------------------------------------------------------------------------- */
+voila_status_t voila_soft_value(const float* d_Q, const double* d_log_pi0, int32_t M, int32_t K, double eta,
+                                double* d_V_out, double* d_pi_out, int32_t* d_best_out, int32_t* d_status,
+                                void* stream);
+
+/* ---------------------------------------------------------------------------
  * Grouped progressive widening (Sec. 4.3): the simulations of a planning
  * pass are grouped by their parent action node and all groups are handled at
  * once.  For each of the M nodes, with successor states d_succ[seg[m] ..

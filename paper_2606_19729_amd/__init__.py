@@ -141,6 +141,8 @@ def _load():
     L.voila_plan_observe.argtypes = [vp, vp, c_int32, vp, c_int32, c_int32, c_uint64, c_int32, vp, vp, c_size_t, vp,
                                      vp, vp]
     L.voila_plan_observe.restype = c_int32
+    L.voila_soft_value.argtypes = [vp, vp, c_int32, c_int32, c_double, vp, vp, vp, vp, vp]
+    L.voila_soft_value.restype = c_int32
     L.voila_pw_step_workspace_size.argtypes = [vp, c_int32, c_int32]
     L.voila_pw_step_workspace_size.restype = c_size_t
     L.voila_pw_step.argtypes = [vp, vp, c_int32, vp, c_int32, vp, vp, vp, vp, vp, POINTER(_PwOpts), vp, c_size_t,
@@ -177,7 +179,8 @@ EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_m
             "voila_reweight_resample",
             "voila_resample_bits",
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_plan_observe_workspace_size",
-            "voila_plan_observe", "voila_pw_step_workspace_size", "voila_pw_step", "voila_philox_normals",
+            "voila_plan_observe", "voila_pw_step_workspace_size", "voila_pw_step", "voila_soft_value",
+            "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
             "voila_batch_replay", "voila_grad_param_count", "voila_rollout_grad_workspace_size",
             "voila_rollout_grad"]
@@ -352,6 +355,24 @@ def plan_observe(model: Model, traj, cands, seed=0, crn=False, noise=None, out=N
                                   int(bool(crn)), _ptr(noise), _ptr(workspace), workspace.numel(), _ptr(o),
                                   _ptr(status), _stream(stream)))
     return o
+
+
+def soft_value(Q, eta, log_pi0=None, want_pi=True, status=None, stream=None):
+    """(V [M] float64, pi [M, K] float64 or None, best [M] int32) of
+    preferences Q [M, K] float32 under a reference policy (log-probabilities
+    [M, K] float64, None: uniform)."""
+    if Q.dim() != 2:
+        raise VoilaError(VOILA_ERR_INVALID_ARG, "Q must be [M, K]")
+    M, K = int(Q.shape[0]), int(Q.shape[1])
+    _dev(Q, torch.float32, (M, K), "Q")
+    if log_pi0 is not None:
+        _dev(log_pi0, torch.float64, (M, K), "log_pi0")
+    V = torch.empty(M, dtype=torch.float64, device=Q.device)
+    pi = torch.empty((M, K), dtype=torch.float64, device=Q.device) if want_pi else None
+    best = torch.empty(M, dtype=torch.int32, device=Q.device)
+    _check(lib.voila_soft_value(_ptr(Q), _ptr(log_pi0), M, K, float(eta), _ptr(V), _ptr(pi), _ptr(best),
+                                _ptr(status), _stream(stream)))
+    return V, pi, best
 
 
 def pw_step(model: Model, succ, seg, actions, visits, children, obs_table, U, k_o, alpha_o, lam=1.0, seed=0,

@@ -1031,6 +1031,28 @@ voila_status_t voila_pw_step(voila_model_t m, const float* d_succ, int32_t T, co
     return VOILA_OK;
 }
 
+voila_status_t voila_soft_value(const float* d_Q, const double* d_log_pi0, int32_t M, int32_t K, double eta,
+                                double* d_V_out, double* d_pi_out, int32_t* d_best_out, int32_t* d_status,
+                                void* stream) {
+    if (M < 0 || K < 1) return fail(VOILA_ERR_INVALID_ARG, "M must be >= 0 and K >= 1");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(VOILA_ERR_INVALID_ARG, "eta must be finite and > 0");
+    if ((long long)M * K > (1LL << 31) - 1) return fail(VOILA_ERR_UNSUPPORTED, "M * K must fit in 31 bits");
+    if (M == 0) return VOILA_OK;
+    if (!d_Q || !d_V_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    SoftValueParams p{};
+    p.Q = d_Q;
+    p.log_pi0 = d_log_pi0;
+    p.V = d_V_out;
+    p.pi = d_pi_out;
+    p.best = d_best_out;
+    p.status = d_status;
+    p.M = M;
+    p.K = K;
+    p.eta = eta;
+    VOILA_CHECK_HIP(launch_soft_value(p, M < 4096 ? M : 4096, reinterpret_cast<hipStream_t>(stream)));
+    return VOILA_OK;
+}
+
 size_t voila_plan_observe_workspace_size(voila_model_t m, int32_t K, int32_t H) {
     if (!m || K < 0 || H < 0) return 0;
     return align_up((size_t)K * H * m->width * 4, 256);

@@ -837,6 +837,84 @@ __global__ __launch_bounds__(kNormResThreads) void norm_res_batch_kernel(const N
 }
 
 // ---------------------------------------------------------------------------
+// soft value: V = (1/eta) log sum_k exp(eta Q_k + log pi0_k), per node
+// ---------------------------------------------------------------------------
+constexpr int kSoftThreads = 256;
+
+__global__ __launch_bounds__(kSoftThreads) void soft_value_kernel(SoftValueParams p) {
+    __shared__ double redd[kSoftThreads / 64];
+    __shared__ int redi[kSoftThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double lp_uniform = -log((double)p.K);
+    for (int m = blockIdx.x; m < p.M; m += gridDim.x) {
+        const float* q = p.Q + (size_t)m * p.K;
+        const double* lp = p.log_pi0 ? p.log_pi0 + (size_t)m * p.K : nullptr;
+        // x_k = eta Q_k + log pi0_k; maximum and its first index
+        double mx = -INFINITY;
+        int arg = p.K;
+        int bad = 0;
+        for (int k = tid; k < p.K; k += kSoftThreads) {
+            const double x = p.eta * (double)q[k] + (lp ? lp[k] : lp_uniform);
+            if (isnan(x) || x == INFINITY) bad = 1;
+            if (x > mx) {
+                mx = x;
+                arg = k;
+            }
+        }
+        // (max, lowest index) over the block, in a fixed order
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const double om = __shfl_xor(mx, d);
+            const int oa = __shfl_xor(arg, d);
+            if (om > mx || (om == mx && oa < arg)) {
+                mx = om;
+                arg = oa;
+            }
+            bad |= __shfl_xor(bad, d);
+        }
+        __syncthreads();
+        if (lane == 0) {
+            redd[wave] = mx;
+            redi[wave] = bad ? -1 : arg;
+        }
+        __syncthreads();
+        mx = redd[0];
+        arg = redi[0];
+        bad = redi[0] < 0;
+        for (int w = 1; w < kSoftThreads / 64; ++w) {
+            bad |= redi[w] < 0;
+            if (redd[w] > mx || (redd[w] == mx && redi[w] < arg)) {
+                mx = redd[w];
+                arg = redi[w];
+            }
+        }
+        if (bad || !isfinite(mx)) {
+            if (tid == 0 && p.status) p.status[0] = 5;
+            __syncthreads();
+            continue;
+        }
+        double s = 0.0;
+        for (int k = tid; k < p.K; k += kSoftThreads)
+            s += exp(p.eta * (double)q[k] + (lp ? lp[k] : lp_uniform) - mx);
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+        __syncthreads();
+        if (lane == 0) redd[wave] = s;
+        __syncthreads();
+        double S = 0.0;
+        for (int w = 0; w < kSoftThreads / 64; ++w) S += redd[w];
+        if (tid == 0) {
+            p.V[m] = (mx + log(S)) / p.eta;
+            if (p.best) p.best[m] = arg;
+        }
+        if (p.pi)
+            for (int k = tid; k < p.K; k += kSoftThreads)
+                p.pi[(size_t)m * p.K + k] = exp(p.eta * (double)q[k] + (lp ? lp[k] : lp_uniform) - mx) / S;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // grouped progressive widening (simulations grouped by parent action node)
 // ---------------------------------------------------------------------------
 namespace {
@@ -1428,6 +1506,12 @@ hipError_t launch_fold(const FoldParams& p, hipStream_t s) {
 hipError_t launch_fold_steps(const FoldStepsParams& p, hipStream_t s) {
     if (p.rows == 0) return hipSuccess;
     hipLaunchKernelGGL(fold_steps_kernel, dim3((p.width + 255) / 256, p.rows < 65535 ? p.rows : 65535), 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_soft_value(const SoftValueParams& p, int blocks, hipStream_t s) {
+    if (p.M == 0 || blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(soft_value_kernel, blocks, kSoftThreads, 0, s, p);
     return hipGetLastError();
 }
 

@@ -100,6 +100,19 @@ struct FoldStepsParams {
     int32_t* status;     // or NULL
 };
 
+// Soft value of M nodes' candidate preferences (one workgroup per node).
+struct SoftValueParams {
+    const float* Q;          // [M][K] preferences (plan's Q)
+    const double* log_pi0;   // [M][K] reference-policy log-probabilities, or NULL (uniform)
+    double* V;               // [M]
+    double* pi;              // [M][K] or NULL
+    int32_t* best;           // [M] or NULL
+    int32_t* status;         // or NULL
+    int M, K;
+    double eta;
+};
+hipError_t launch_soft_value(const SoftValueParams& p, int blocks, hipStream_t s);
+
 // Grouped progressive-widening step over M action nodes (groups of successors
 // seg[m] .. seg[m+1]).
 struct PwParams {
