@@ -316,6 +316,47 @@ def soft_value(Q, eta, log_pi0=None):
     return V, pi, best
 
 
+def plan_closed_loop(model, states, first, n_obs, cont, gamma, eta, lam, goal, seed, U, log_pi0=None, bf16=False):
+    """One-level closed-loop tree of the preference backup (Eq. 1), built
+    from the functions above:
+      1. every particle is moved one step under each first action a (plan of
+         horizon 1, key `seed`): successors s'_{a,i} and R(b, a) = mean_i R(s'_{a,i});
+      2. n_obs observation branches per first action: branch j of action a is
+         the successor set of a starting at successor j, widened once by the
+         grouped progressive-widening step (key `seed`, offsets U[a n_obs + j]),
+         which draws its observation at that successor and resamples the set
+         against it -- the child belief tau(b, a, o_j);
+      3. every child belief is valued by the continuation candidates (plan of
+         their horizon, key seed + 1): Q_child[k] = mean over the child's
+         particles of the returns, V_child = L_eta Q_child (uniform prior);
+      4. Psi(b, a) = (1/eta) log pi0(a) + R(b, a) + gamma mean_j V_child(a, j),
+         V(b) = L_eta Psi, with the soft policy and the greedy first action.
+    Returns a dict (psi, V, pi, best, R, V_child, child)."""
+    S = np.asarray(states, np.float64)
+    N = S.shape[0]
+    first = np.asarray(first)
+    A = first.shape[0]
+    cands1 = first.reshape(A, 1) if model.n_actions > 0 else first.reshape(A, 1, model.d_a)
+    R, _ = plan(model, S, cands1, 1.0, goal, seed=seed, bf16=bf16, return_G=True)
+    traj, _ = plan_steps(model, S, cands1, seed=seed, bf16=bf16, want_obs=False)
+    M = A * n_obs
+    succ = np.concatenate([np.roll(traj[a, :, 0], -j, axis=0) for a in range(A) for j in range(n_obs)])
+    seg = np.arange(M + 1, dtype=np.int32) * N
+    acts = np.repeat(first, n_obs, axis=0)
+    out = pw_step(model, succ, seg, acts, np.zeros(M, np.int32), np.zeros(M, np.int32),
+                  np.zeros((M, 1, model.d_o)), 1.0, 1.0, lam, seed, U, bf16=bf16)
+    child = out["S_out"]
+    cont = np.asarray(cont)
+    K = cont.shape[0]
+    _, G2 = plan(model, child, cont, gamma, goal, seed=seed + 1, bf16=bf16, return_G=True)
+    Qc = G2.reshape(K, M, N).mean(axis=2).T
+    Vc, _, _ = soft_value(Qc, eta)
+    lp = np.full(A, -np.log(A)) if log_pi0 is None else np.asarray(log_pi0, np.float64)
+    psi = lp / eta + R + gamma * Vc.reshape(A, n_obs).mean(axis=1)
+    V, pi, best = soft_value(psi[None, :], eta, log_pi0=np.zeros((1, A)))
+    return dict(psi=psi, V=V[0], pi=pi[0], best=int(best[0]), R=R, V_child=Vc, child=child)
+
+
 def weighted_mean(G, w=None):
     G = _d(G)
     return lib().or_weighted_mean(G.shape[0], _p(G), _p(_d(w)))

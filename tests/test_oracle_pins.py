@@ -701,3 +701,35 @@ def test_soft_value_against_scipy_and_limits():
     np.testing.assert_allclose(V2, V1 + 10.0, rtol=1e-14)
     _, _, b = oracle.soft_value(np.array([[1.0, 3.0, 3.0, 2.0]]), 1.0)
     assert b[0] == 1
+
+
+# ----------------------------------------------------------------------------- one-level closed-loop tree
+def test_closed_loop_tree_special_cases():
+    w = workloads.small(seed=81, N=24, K=6, H=4)
+    m = w.model
+    first = np.arange(5, dtype=np.int32)
+    U = np.arange(5 * 3, dtype=np.uint32) * 2654435761
+    cont = w.cands[:, :3]
+    # gamma = 0: Psi = log pi0 / eta + R(b, a), R the horizon-1 plan value
+    out = oracle.plan_closed_loop(m, w.states, first, 3, cont, 0.0, 2.0, 1.0, w.goal, 11, U)
+    R1 = oracle.plan(m, w.states, first[:, None], 1.0, w.goal, seed=11)
+    np.testing.assert_allclose(out["R"], R1, rtol=0, atol=0)
+    np.testing.assert_allclose(out["psi"], -np.log(5) / 2.0 + R1, rtol=1e-15, atol=1e-15)
+    x = 2.0 * out["psi"]
+    assert out["V"] == pytest.approx(scipy.special.logsumexp(x) / 2.0, rel=1e-14)
+    np.testing.assert_allclose(out["pi"], scipy.special.softmax(x), rtol=1e-12)
+    assert out["best"] == int(np.argmax(out["psi"]))
+    # gamma > 0: the backup adds gamma times the mean child value, each child
+    # value being the soft value of the continuation returns from that child
+    out2 = oracle.plan_closed_loop(m, w.states, first, 3, cont, 0.9, 2.0, 1.0, w.goal, 11, U)
+    np.testing.assert_allclose(out2["psi"] - out["psi"], 0.9 * out2["V_child"].reshape(5, 3).mean(axis=1),
+                               rtol=1e-12, atol=1e-12)
+    child = out2["child"].reshape(15, 24, 4)
+    for g in [0, 7, 14]:
+        # every child is a resampled copy of its action's successors
+        traj, _ = oracle.plan_steps(m, w.states, first[:, None], seed=11, want_obs=False)
+        succ = traj[g // 3, :, 0]
+        assert all(any(np.array_equal(r, s) for s in succ) for r in child[g])
+    # eta -> infinity: V(b) tends to the best preference
+    out3 = oracle.plan_closed_loop(m, w.states, first, 2, cont, 0.9, 1e6, 1.0, w.goal, 11, U[:10])
+    assert out3["V"] == pytest.approx(out3["psi"].max(), abs=1e-4)
