@@ -267,6 +267,51 @@ voila_status_t voila_soft_value(const float* d_Q, const double* d_log_pi0, int32
                                 void* stream);
 
 /* ---------------------------------------------------------------------------
+ * One-level closed-loop tree with the preference backup of Eq. 1.  For a
+ * belief of N uniformly weighted particles, A first actions (d_first: int32
+ * [A] indices or float [A][d_a]), n_obs observation branches per first
+ * action and K continuation candidates of horizon H (d_cont as voila_plan's
+ * candidates):
+ *   1. every particle is moved one step under each first action (voila_plan
+ *      with horizon 1 and key seed): successors s'_{a,i}, R(b, a) their mean
+ *      reward;
+ *   2. branch j of action a is a's successor set starting at successor j,
+ *      widened once by voila_pw_step (key seed, offset d_U[a n_obs + j]): an
+ *      observation drawn at that successor, the set weighted against it and
+ *      resampled -- the child belief tau(b, a, o_j);
+ *   3. every child belief is valued by the continuation candidates
+ *      (voila_plan over all children at once, key seed + 1): Q_child[k] is
+ *      the mean return over the child's particles and V_child = L_eta Q_child
+ *      with a uniform prior (voila_soft_value);
+ *   4. Psi(b, a) = (1/eta) log pi0(a) + R(b, a) + gamma mean_j V_child(a, j)
+ *      (d_log_pi0 [A] log-probabilities, or NULL for uniform), V(b) = L_eta
+ *      Psi, pi(a) = exp(eta Psi(b, a) - eta V(b)), best = argmax_a Psi.
+ * Outputs: d_psi_out [A], d_V_out [1] (double, required); optional d_pi_out
+ * [A], d_best_out [1], d_R_out [A], d_Vchild_out [A n_obs] (double / int32)
+ * and d_child_out [A n_obs N][d_s] float (the child beliefs).
+ * N <= 8192.  The model needs its observation and likelihood networks.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double gamma;             /* discount, 0 <= gamma <= 1                        */
+    double eta;               /* temperature of L_eta, > 0                        */
+    double lambda;            /* likelihood temperature of the child updates, > 0 */
+    const float* h_goal;      /* host [d_s] goal of the reward                    */
+    uint64_t seed;            /* Philox key (continuation rollouts use seed + 1)  */
+    int32_t n_obs;            /* observation branches per first action, >= 1     */
+    const double* d_log_pi0;  /* device [A] reference policy, or NULL (uniform)   */
+    const uint32_t* d_U;      /* device [A n_obs] resampling offsets              */
+} voila_closed_loop_opts_t;
+
+size_t voila_plan_closed_loop_workspace_size(voila_model_t model, int32_t N, int32_t A, int32_t n_obs, int32_t K,
+                                             int32_t H);
+voila_status_t voila_plan_closed_loop(voila_model_t model, const float* d_states, int32_t N, const void* d_first,
+                                      int32_t A, const void* d_cont, int32_t K, int32_t H,
+                                      const voila_closed_loop_opts_t* h_opts, void* d_workspace,
+                                      size_t workspace_bytes, double* d_psi_out, double* d_V_out, double* d_pi_out,
+                                      int32_t* d_best_out, double* d_R_out, double* d_Vchild_out,
+                                      float* d_child_out, int32_t* d_status, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Grouped progressive widening (Sec. 4.3): the simulations of a planning
  * pass are grouped by their parent action node and all groups are handled at
  * once.  For each of the M nodes, with successor states d_succ[seg[m] ..

@@ -77,6 +77,11 @@ class _PwOpts(ctypes.Structure):
                 ("capacity", c_int32)]
 
 
+class _ClosedLoopOpts(ctypes.Structure):
+    _fields_ = [("gamma", c_double), ("eta", c_double), ("lambda_", c_double), ("h_goal", POINTER(c_float)),
+                ("seed", c_uint64), ("n_obs", c_int32), ("d_log_pi0", c_void_p), ("d_U", c_void_p)]
+
+
 class _GradOpts(ctypes.Structure):
     _fields_ = [("B", c_int32), ("H", c_int32), ("checkpoint", c_int32), ("d_s0", c_void_p),
                 ("d_actions", c_void_p), ("particles", c_int32), ("d_noise", c_void_p), ("seed", c_uint64),
@@ -143,6 +148,11 @@ def _load():
     L.voila_plan_observe.restype = c_int32
     L.voila_soft_value.argtypes = [vp, vp, c_int32, c_int32, c_double, vp, vp, vp, vp, vp]
     L.voila_soft_value.restype = c_int32
+    L.voila_plan_closed_loop_workspace_size.argtypes = [vp, c_int32, c_int32, c_int32, c_int32, c_int32]
+    L.voila_plan_closed_loop_workspace_size.restype = c_size_t
+    L.voila_plan_closed_loop.argtypes = [vp, vp, c_int32, vp, c_int32, vp, c_int32, c_int32,
+                                         POINTER(_ClosedLoopOpts), vp, c_size_t, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.voila_plan_closed_loop.restype = c_int32
     L.voila_pw_step_workspace_size.argtypes = [vp, c_int32, c_int32]
     L.voila_pw_step_workspace_size.restype = c_size_t
     L.voila_pw_step.argtypes = [vp, vp, c_int32, vp, c_int32, vp, vp, vp, vp, vp, POINTER(_PwOpts), vp, c_size_t,
@@ -180,6 +190,7 @@ EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_m
             "voila_resample_bits",
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_plan_observe_workspace_size",
             "voila_plan_observe", "voila_pw_step_workspace_size", "voila_pw_step", "voila_soft_value",
+            "voila_plan_closed_loop_workspace_size", "voila_plan_closed_loop",
             "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
             "voila_batch_replay", "voila_grad_param_count", "voila_rollout_grad_workspace_size",
@@ -373,6 +384,46 @@ def soft_value(Q, eta, log_pi0=None, want_pi=True, status=None, stream=None):
     _check(lib.voila_soft_value(_ptr(Q), _ptr(log_pi0), M, K, float(eta), _ptr(V), _ptr(pi), _ptr(best),
                                 _ptr(status), _stream(stream)))
     return V, pi, best
+
+
+def plan_closed_loop(model: Model, states, first, n_obs, cont, gamma, eta, lam, goal, seed, U, log_pi0=None,
+                     want_child=False, workspace=None, status=None, stream=None):
+    """One-level closed-loop tree with the preference backup: returns
+    dict(psi [A], V [1], pi [A], best [1], R [A], V_child [A n_obs], child
+    [A n_obs N, d_s] or None)."""
+    d = model.desc
+    N = int(states.shape[0])
+    _dev(states, torch.float32, (N, d.d_s), "states")
+    A = int(first.shape[0])
+    if d.n_actions > 0:
+        _dev(first, torch.int32, (A,), "first")
+        _dev(cont, torch.int32, None, "cont")
+    else:
+        _dev(first, torch.float32, (A, d.d_a), "first")
+        _dev(cont, torch.float32, None, "cont")
+    K, H = int(cont.shape[0]), int(cont.shape[1])
+    _dev(U, torch.int32, (A * n_obs,), "U")
+    if log_pi0 is not None:
+        _dev(log_pi0, torch.float64, (A,), "log_pi0")
+    dev = states.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    res = {"psi": torch.empty(A, **f64), "V": torch.empty(1, **f64), "pi": torch.empty(A, **f64),
+           "best": torch.empty(1, dtype=torch.int32, device=dev), "R": torch.empty(A, **f64),
+           "V_child": torch.empty(A * n_obs, **f64),
+           "child": torch.empty((A * n_obs * N, d.d_s), dtype=torch.float32, device=dev) if want_child else None}
+    goal_arr = (c_float * d.d_s)(*[float(x) for x in goal])
+    opts = _ClosedLoopOpts(float(gamma), float(eta), float(lam), goal_arr, int(seed) & (2**64 - 1), int(n_obs),
+                           _ptr(log_pi0), _ptr(U))
+    if workspace is None:
+        n = lib.voila_plan_closed_loop_workspace_size(model.handle, N, A, int(n_obs), K, H)
+        if n == 0:
+            raise VoilaError(VOILA_ERR_INVALID_ARG, "sizes out of range")
+        workspace = torch.empty(int(n), dtype=torch.uint8, device=dev)
+    _check(lib.voila_plan_closed_loop(model.handle, _ptr(states), N, _ptr(first), A, _ptr(cont), K, H,
+                                      ctypes.byref(opts), _ptr(workspace), workspace.numel(), _ptr(res["psi"]),
+                                      _ptr(res["V"]), _ptr(res["pi"]), _ptr(res["best"]), _ptr(res["R"]),
+                                      _ptr(res["V_child"]), _ptr(res["child"]), _ptr(status), _stream(stream)))
+    return res
 
 
 def pw_step(model: Model, succ, seg, actions, visits, children, obs_table, U, k_o, alpha_o, lam=1.0, seed=0,

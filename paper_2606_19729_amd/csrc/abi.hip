@@ -1053,6 +1053,168 @@ voila_status_t voila_soft_value(const float* d_Q, const double* d_log_pi0, int32
     return VOILA_OK;
 }
 
+namespace {
+struct TreeWs {
+    char* plan1;
+    float* succ0;
+    float* q1;
+    float* succ;
+    int32_t* seg;
+    char* acts;
+    int32_t* zeros;
+    float* table;
+    char* pw;
+    float* child;
+    char* plan2;
+    float* q2;
+    float* G2;
+    double* Qc;
+    double* Vc;
+    size_t bytes;
+};
+TreeWs carve_tree(char* base, voila_model_t m, int N, int A, int n_obs, int K) {
+    TreeWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + off;
+        off = align_up(off + bytes, 256);
+        return p;
+    };
+    const size_t M = (size_t)A * n_obs, T = M * N;
+    w.plan1 = take(plan_ws(N, A));
+    w.succ0 = reinterpret_cast<float*>(take((size_t)A * N * m->d_s * 4));
+    w.q1 = reinterpret_cast<float*>(take((size_t)A * 4));
+    w.succ = reinterpret_cast<float*>(take(T * m->d_s * 4));
+    w.seg = reinterpret_cast<int32_t*>(take((M + 1) * 4));
+    w.acts = take(M * (m->n_actions > 0 ? 4 : (size_t)m->d_a * 4));
+    w.zeros = reinterpret_cast<int32_t*>(take(2 * M * 4));
+    w.table = reinterpret_cast<float*>(take(M * m->d_o * 4));
+    w.pw = take(voila_pw_step_workspace_size(m, (int)T, (int)M));
+    w.child = reinterpret_cast<float*>(take(T * m->d_s * 4));
+    w.plan2 = take(plan_ws((int)T, K));
+    w.q2 = reinterpret_cast<float*>(take((size_t)K * 4));
+    w.G2 = reinterpret_cast<float*>(take((size_t)K * T * 4));
+    w.Qc = reinterpret_cast<double*>(take(M * K * 8));
+    w.Vc = reinterpret_cast<double*>(take(M * 8));
+    w.bytes = off;
+    return w;
+}
+bool tree_sizes_ok(int N, int A, int n_obs, int K, int H) {
+    if (N < 1 || A < 1 || n_obs < 1 || K < 1 || H < 0) return false;
+    const long long T = (long long)A * n_obs * N;
+    return T <= (1LL << 31) - 1 && (long long)K * T <= (1LL << 31) - 1 && (long long)A * N <= (1LL << 31) - 1;
+}
+}  // namespace
+
+size_t voila_plan_closed_loop_workspace_size(voila_model_t m, int32_t N, int32_t A, int32_t n_obs, int32_t K,
+                                             int32_t H) {
+    if (!m || !tree_sizes_ok(N, A, n_obs, K, H)) return 0;
+    return carve_tree(nullptr, m, N, A, n_obs, K).bytes;
+}
+
+voila_status_t voila_plan_closed_loop(voila_model_t m, const float* d_states, int32_t N, const void* d_first,
+                                      int32_t A, const void* d_cont, int32_t K, int32_t H,
+                                      const voila_closed_loop_opts_t* o, void* ws, size_t ws_bytes,
+                                      double* d_psi_out, double* d_V_out, double* d_pi_out, int32_t* d_best_out,
+                                      double* d_R_out, double* d_Vchild_out, float* d_child_out, int32_t* d_status,
+                                      void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!m->has_obs || !m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model needs observation and likelihood networks");
+    if (!o || !o->h_goal) return fail(VOILA_ERR_INVALID_ARG, "NULL options or goal");
+    if (!tree_sizes_ok(N, A, o->n_obs, K, H))
+        return fail(VOILA_ERR_INVALID_ARG, "N, A, n_obs, K >= 1, H >= 0, and the branch and rollout counts must fit in 31 bits");
+    if (N > kPwMaxGroup) return fail(VOILA_ERR_UNSUPPORTED, "N above 8192 (one workgroup resamples a branch)");
+    if (!(o->gamma >= 0.0 && o->gamma <= 1.0)) return fail(VOILA_ERR_INVALID_ARG, "gamma must lie in [0, 1]");
+    if (!(o->eta > 0.0) || !std::isfinite(o->eta)) return fail(VOILA_ERR_INVALID_ARG, "eta must be finite and > 0");
+    if (!(o->lambda > 0.0) || !std::isfinite(o->lambda)) return fail(VOILA_ERR_INVALID_ARG, "lambda must be > 0");
+    if (!d_states || !d_first || (!d_cont && H > 0) || !o->d_U || !d_psi_out || !d_V_out)
+        return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    TreeWs w = carve_tree(reinterpret_cast<char*>(ws), m, N, A, o->n_obs, K);
+    if (!ws || ws_bytes < w.bytes) return fail(VOILA_ERR_WORKSPACE, "closed-loop workspace too small");
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int M = A * o->n_obs, T = M * N;
+    voila_status_t st;
+    // 1. one step from every particle under each first action: successors and R(b, a)
+    voila_plan_opts_t p1{};
+    p1.gamma = 1.0;
+    p1.h_goal = o->h_goal;
+    p1.seed = o->seed;
+    p1.d_traj_out = w.succ0;
+    if ((st = voila_plan(m, d_states, nullptr, N, d_first, A, 1, &p1, w.plan1, plan_ws(N, A), w.q1, nullptr,
+                         d_status, stream)) != VOILA_OK)
+        return st;
+    // 2. the observation branches and their child beliefs
+    TreeParams tp{};
+    tp.succ0 = w.succ0;
+    tp.succ = w.succ;
+    tp.seg = w.seg;
+    tp.first = d_first;
+    tp.acts = w.acts;
+    tp.zeros = w.zeros;
+    tp.A = A;
+    tp.n_obs = o->n_obs;
+    tp.N = N;
+    tp.K = K;
+    tp.d_s = m->d_s;
+    tp.n_actions = m->n_actions;
+    tp.d_a = m->d_a;
+    tp.gamma = o->gamma;
+    tp.eta = o->eta;
+    VOILA_CHECK_HIP(launch_tree_groups(tp, s));
+    float* child = d_child_out ? d_child_out : w.child;
+    voila_pw_opts_t po{};
+    po.k_o = 1.0;
+    po.alpha_o = 1.0;
+    po.lambda = o->lambda;
+    po.seed = o->seed;
+    po.capacity = 1;
+    if ((st = voila_pw_step(m, w.succ, T, w.seg, M, w.acts, w.zeros, w.zeros + M, w.table, o->d_U, &po, w.pw,
+                            voila_pw_step_workspace_size(m, T, M), nullptr, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, child, d_status, stream)) != VOILA_OK)
+        return st;
+    // 3. child values from the continuation candidates (rollout key seed + 1)
+    voila_plan_opts_t p2{};
+    p2.gamma = o->gamma;
+    p2.h_goal = o->h_goal;
+    p2.seed = o->seed + 1;
+    if ((st = voila_plan(m, child, nullptr, T, d_cont, K, H, &p2, w.plan2, plan_ws(T, K), w.q2, w.G2, d_status,
+                         stream)) != VOILA_OK)
+        return st;
+    tp.G2 = w.G2;
+    tp.Qc = w.Qc;
+    VOILA_CHECK_HIP(launch_tree_child_q(tp, s));
+    double* Vc = d_Vchild_out ? d_Vchild_out : w.Vc;
+    SoftValueParams sv{};
+    sv.Qd = w.Qc;
+    sv.V = Vc;
+    sv.status = d_status;
+    sv.M = M;
+    sv.K = K;
+    sv.eta = o->eta;
+    VOILA_CHECK_HIP(launch_soft_value(sv, M < 4096 ? M : 4096, s));
+    // 4. backup and the root's soft value
+    tp.Vc = Vc;
+    tp.R = w.q1;
+    tp.log_pi0 = o->d_log_pi0;
+    tp.psi = d_psi_out;
+    tp.R_out = d_R_out;
+    VOILA_CHECK_HIP(launch_tree_backup(tp, s));
+    SoftValueParams sr{};
+    sr.Qd = d_psi_out;
+    sr.no_prior = 1;
+    sr.V = d_V_out;
+    sr.pi = d_pi_out;
+    sr.best = d_best_out;
+    sr.status = d_status;
+    sr.M = 1;
+    sr.K = A;
+    sr.eta = o->eta;
+    VOILA_CHECK_HIP(launch_soft_value(sr, 1, s));
+    return VOILA_OK;
+}
+
 size_t voila_plan_observe_workspace_size(voila_model_t m, int32_t K, int32_t H) {
     if (!m || K < 0 || H < 0) return 0;
     return align_up((size_t)K * H * m->width * 4, 256);

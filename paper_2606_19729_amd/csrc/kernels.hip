@@ -845,16 +845,18 @@ __global__ __launch_bounds__(kSoftThreads) void soft_value_kernel(SoftValueParam
     __shared__ double redd[kSoftThreads / 64];
     __shared__ int redi[kSoftThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const double lp_uniform = -log((double)p.K);
+    const double lp_uniform = p.no_prior ? 0.0 : -log((double)p.K);
     for (int m = blockIdx.x; m < p.M; m += gridDim.x) {
-        const float* q = p.Q + (size_t)m * p.K;
+        const float* qf = p.Q ? p.Q + (size_t)m * p.K : nullptr;
+        const double* qd = p.Qd ? p.Qd + (size_t)m * p.K : nullptr;
+        auto q = [&](int k) { return qd ? qd[k] : (double)qf[k]; };
         const double* lp = p.log_pi0 ? p.log_pi0 + (size_t)m * p.K : nullptr;
         // x_k = eta Q_k + log pi0_k; maximum and its first index
         double mx = -INFINITY;
         int arg = p.K;
         int bad = 0;
         for (int k = tid; k < p.K; k += kSoftThreads) {
-            const double x = p.eta * (double)q[k] + (lp ? lp[k] : lp_uniform);
+            const double x = p.eta * q(k) + (lp ? lp[k] : lp_uniform);
             if (isnan(x) || x == INFINITY) bad = 1;
             if (x > mx) {
                 mx = x;
@@ -895,7 +897,7 @@ __global__ __launch_bounds__(kSoftThreads) void soft_value_kernel(SoftValueParam
         }
         double s = 0.0;
         for (int k = tid; k < p.K; k += kSoftThreads)
-            s += exp(p.eta * (double)q[k] + (lp ? lp[k] : lp_uniform) - mx);
+            s += exp(p.eta * q(k) + (lp ? lp[k] : lp_uniform) - mx);
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
         __syncthreads();
@@ -909,9 +911,69 @@ __global__ __launch_bounds__(kSoftThreads) void soft_value_kernel(SoftValueParam
         }
         if (p.pi)
             for (int k = tid; k < p.K; k += kSoftThreads)
-                p.pi[(size_t)m * p.K + k] = exp(p.eta * (double)q[k] + (lp ? lp[k] : lp_uniform) - mx) / S;
+                p.pi[(size_t)m * p.K + k] = exp(p.eta * q(k) + (lp ? lp[k] : lp_uniform) - mx) / S;
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// one-level closed-loop tree (preference backup over observation branches)
+// ---------------------------------------------------------------------------
+// Successor set of branch group (a, j): the successors of first action a
+// starting at successor j; the group's offsets, action and empty branch table.
+__global__ __launch_bounds__(256) void tree_groups_kernel(TreeParams p) {
+    const int M = p.A * p.n_obs;
+    const long n_el = (long)M * p.N * p.d_s;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n_el; e += (long)gridDim.x * blockDim.x) {
+        const long row = e / p.d_s;
+        const int c = (int)(e - row * p.d_s);
+        const int m = (int)(row / p.N), i = (int)(row - (long)m * p.N);
+        const int a = m / p.n_obs, j = m - a * p.n_obs;
+        int src = i + j % p.N;
+        if (src >= p.N) src -= p.N;
+        p.succ[e] = p.succ0[((size_t)a * p.N + src) * p.d_s + c];
+    }
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m <= M) p.seg[m] = m * p.N;
+    if (m < M) {
+        const int a = m / p.n_obs;
+        p.zeros[m] = 0;
+        p.zeros[M + m] = 0;
+        if (p.n_actions > 0) {
+            reinterpret_cast<int32_t*>(p.acts)[m] = reinterpret_cast<const int32_t*>(p.first)[a];
+        } else {
+            for (int c = 0; c < p.d_a; ++c)
+                reinterpret_cast<float*>(p.acts)[(size_t)m * p.d_a + c] =
+                    reinterpret_cast<const float*>(p.first)[(size_t)a * p.d_a + c];
+        }
+    }
+}
+
+// Child preferences: the mean continuation return of candidate k over the
+// particles of child m, one wave per (m, k), fixed summation order.
+__global__ __launch_bounds__(256) void tree_child_q_kernel(TreeParams p) {
+    const int M = p.A * p.n_obs;
+    const int lane = threadIdx.x & 63;
+    const long item = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= (long)M * p.K) return;
+    const int m = (int)(item / p.K), k = (int)(item - (long)m * p.K);
+    const float* g = p.G2 + (size_t)k * ((size_t)M * p.N) + (size_t)m * p.N;
+    double s = 0.0;
+    for (int i = lane; i < p.N; i += 64) s += (double)g[i];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane == 0) p.Qc[(size_t)m * p.K + k] = s / p.N;
+}
+
+// Psi(b, a) = (1/eta) log pi0(a) + R(b, a) + gamma mean_j V_child(a, j).
+__global__ __launch_bounds__(64) void tree_backup_kernel(TreeParams p) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= p.A) return;
+    double v = 0.0;
+    for (int j = 0; j < p.n_obs; ++j) v += p.Vc[(size_t)a * p.n_obs + j];
+    const double lp = p.log_pi0 ? p.log_pi0[a] : -log((double)p.A);
+    p.psi[a] = lp / p.eta + (double)p.R[a] + p.gamma * (v / p.n_obs);
+    if (p.R_out) p.R_out[a] = (double)p.R[a];
 }
 
 // ---------------------------------------------------------------------------
@@ -1506,6 +1568,27 @@ hipError_t launch_fold(const FoldParams& p, hipStream_t s) {
 hipError_t launch_fold_steps(const FoldStepsParams& p, hipStream_t s) {
     if (p.rows == 0) return hipSuccess;
     hipLaunchKernelGGL(fold_steps_kernel, dim3((p.width + 255) / 256, p.rows < 65535 ? p.rows : 65535), 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_groups(const TreeParams& p, hipStream_t s) {
+    const int M = p.A * p.n_obs;
+    const long n_el = (long)M * p.N * p.d_s;
+    long blocks = (n_el + 255) / 256;
+    if (blocks < (M + 1 + 255) / 256) blocks = (M + 1 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(tree_groups_kernel, (int)blocks, 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_child_q(const TreeParams& p, hipStream_t s) {
+    const long items = (long)p.A * p.n_obs * p.K;
+    hipLaunchKernelGGL(tree_child_q_kernel, (int)((items + 3) / 4), 256, 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_backup(const TreeParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(tree_backup_kernel, (p.A + 63) / 64, 64, 0, s, p);
     return hipGetLastError();
 }
 

@@ -102,8 +102,10 @@ struct FoldStepsParams {
 
 // Soft value of M nodes' candidate preferences (one workgroup per node).
 struct SoftValueParams {
-    const float* Q;          // [M][K] preferences (plan's Q)
+    const float* Q;          // [M][K] preferences (plan's Q), or NULL when Qd is given
+    const double* Qd;        // [M][K] binary64 preferences, or NULL
     const double* log_pi0;   // [M][K] reference-policy log-probabilities, or NULL (uniform)
+    int no_prior;            // 1: no prior term at all (the preferences already hold it)
     double* V;               // [M]
     double* pi;              // [M][K] or NULL
     int32_t* best;           // [M] or NULL
@@ -112,6 +114,29 @@ struct SoftValueParams {
     double eta;
 };
 hipError_t launch_soft_value(const SoftValueParams& p, int blocks, hipStream_t s);
+
+// One-level closed-loop tree: A first actions, n_obs observation branches
+// each (M = A n_obs groups of N successors), K continuation candidates.
+struct TreeParams {
+    const float* succ0;      // [A][N][d_s] successors of each first action
+    float* succ;             // [M][N][d_s] group (a, j): successors of a from successor j on
+    int32_t* seg;            // [M + 1]
+    const void* first;       // int32 [A] or float [A][d_a]
+    void* acts;              // int32 [M] or float [M][d_a]
+    int32_t* zeros;          // [2 M] visits and branch counts (all 0)
+    const float* G2;         // [K][M N] continuation returns from the children
+    double* Qc;              // [M][K] child preferences
+    const double* Vc;        // [M] child values
+    const float* R;          // [A] first-step reward estimates
+    const double* log_pi0;   // [A] or NULL (uniform)
+    double* psi;             // [A]
+    double* R_out;           // [A] or NULL
+    int A, n_obs, N, K, d_s, n_actions, d_a;
+    double gamma, eta;
+};
+hipError_t launch_tree_groups(const TreeParams& p, hipStream_t s);
+hipError_t launch_tree_child_q(const TreeParams& p, hipStream_t s);
+hipError_t launch_tree_backup(const TreeParams& p, hipStream_t s);
 
 // Grouped progressive-widening step over M action nodes (groups of successors
 // seg[m] .. seg[m+1]).

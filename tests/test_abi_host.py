@@ -103,3 +103,6 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert L.voila_soft_value(None, None, 4, 0, 1.0, None, None, None, None, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_soft_value(None, None, 4, 3, 0.0, None, None, None, None, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_soft_value(None, None, 0, 3, 1.0, None, None, None, None, None) == V.VOILA_OK
+    assert L.voila_plan_closed_loop(None, None, 1, None, 1, None, 1, 1, None, None, 0, None, None, None, None, None,
+                                    None, None, None, None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_plan_closed_loop_workspace_size(None, 10, 2, 2, 4, 3) == 0
