@@ -32,7 +32,7 @@ PEAK_BF16_TFLOPS = 2500.0
 # WRITE_SIZE passes (scaled by the counters' reading of a copy kernel of known
 # size, see profiles/plan_kernel_f32_realistic.md), valid only for the kernel
 # sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256_16": "67762362ba760d18", "bytes": (11129 + 1024) * 1024}
+MEASURED_TRAFFIC = {"sources_sha256_16": "3ae7f37e084e6a1e", "bytes": (11105 + 1024) * 1024}
 
 
 def kernel_sources_hash():
@@ -327,6 +327,42 @@ def bench_pw(V, torch, reps):
     return out
 
 
+def bench_tree(V, torch, reps):
+    """One-level closed-loop tree with the realistic networks: 1,024 particles,
+    8 continuous first actions x 4 observation branches, 128 continuation
+    candidates of horizon 10 (42 M continuation rollout steps), binary32 and
+    bfloat16."""
+    import workloads
+    dev = torch.device("cuda", 0)
+    w = workloads.realistic(seed=9, N=1024, K=128, H=10)
+    rng = np.random.default_rng(9)
+    A, n_obs = 8, 4
+    first = torch.as_tensor(rng.uniform(-1, 1, (A, 4)).astype(np.float32), device=dev)
+    U = torch.as_tensor(rng.integers(0, 2**31, A * n_obs).astype(np.int32), device=dev)
+    S = torch.as_tensor(w.states, device=dev)
+    C = torch.as_tensor(w.cands, device=dev)
+    steps = A * n_obs * w.N * w.K * w.H + A * w.N
+    out = {"N": w.N, "first_actions": A, "branches": n_obs, "K": w.K, "H": w.H, "rollout_steps": steps}
+    stream = torch.cuda.current_stream()
+    for compute in ["f32", "bf16"]:
+        m = V.Model(w.model, compute=compute)
+        ws = torch.empty(int(V.lib.voila_plan_closed_loop_workspace_size(m.handle, w.N, A, n_obs, w.K, w.H)),
+                         dtype=torch.uint8, device=dev)
+        ms = []
+        for r in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            V.plan_closed_loop(m, S, first, n_obs, C, w.gamma, 2.0, w.lam, w.goal, r, U, workspace=ws)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                ms.append(a.elapsed_time(b))
+        t = float(np.median(ms))
+        out[compute] = {"ms": t, "rollout_steps_per_s": steps / (t / 1e3)}
+        print(f"[bench]   {compute}: {t:.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_grad(V, torch, reps):
     """Adjoint through 65,536 rollouts x 20 steps (checkpoint every 5): distillation
     gradient w.r.t. the 5,316 parameters; return gradient w.r.t. [1024, 20, 4] actions."""
@@ -578,6 +614,8 @@ def main():
         result["plan_observe"] = bench_plan_observe(V, torch, max(2, args.steps // 2), w, S, C)
         print("[bench] grouped progressive widening", file=sys.stderr, flush=True)
         result["pw_step"] = bench_pw(V, torch, max(3, args.steps))
+        print("[bench] one-level closed-loop tree", file=sys.stderr, flush=True)
+        result["closed_loop_tree"] = bench_tree(V, torch, max(2, args.steps // 2))
         print("[bench] belief-update sweep", file=sys.stderr, flush=True)
         result["update_sweep"] = bench_update_sweep(V, torch, max(3, args.steps))
 
