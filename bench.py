@@ -363,6 +363,34 @@ def bench_tree(V, torch, reps):
     return out
 
 
+def bench_gemm_reference(torch, reps):
+    """Matrix-core throughput a vendor library GEMM (torch.matmul -> hipBLASLt)
+    reaches on this GPU, 8192^3 in bfloat16 and binary32: the re-measured
+    counterpart of the datasheet MFMA peaks the roofline fractions use."""
+    dev = torch.device("cuda", 0)
+    n = 8192
+    out = {"n": n}
+    stream = torch.cuda.current_stream()
+    for name, dt in [("bf16", torch.bfloat16), ("f32", torch.float32)]:
+        a = torch.randn((n, n), device=dev, dtype=dt)
+        b = torch.randn((n, n), device=dev, dtype=dt)
+        c = torch.matmul(a, b)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            torch.matmul(a, b, out=c)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        t = float(np.median(ms))
+        out[name + "_tflops"] = 2.0 * n ** 3 / (t / 1e3) / 1e12
+        del a, b, c
+    out["f32_allow_tf32"] = bool(torch.backends.cuda.matmul.allow_tf32)
+    return out
+
+
 def bench_grad(V, torch, reps):
     """Adjoint through 65,536 rollouts x 20 steps (checkpoint every 5): distillation
     gradient w.r.t. the 5,316 parameters; return gradient w.r.t. [1024, 20, 4] actions."""
@@ -618,6 +646,12 @@ def main():
         result["closed_loop_tree"] = bench_tree(V, torch, max(2, args.steps // 2))
         print("[bench] belief-update sweep", file=sys.stderr, flush=True)
         result["update_sweep"] = bench_update_sweep(V, torch, max(3, args.steps))
+
+    if not args.no_extras:
+        print("[bench] library GEMM reference (matrix-core peak re-measured)", file=sys.stderr, flush=True)
+        result["gemm_reference"] = bench_gemm_reference(torch, 5)
+        g = result["gemm_reference"]
+        result["roofline"]["frac_of_library_f32_gemm"] = result["roofline"]["achieved"] / g["f32_tflops"]
 
     if args.calibrate_copy:
         x = torch.ones(64 << 20, dtype=torch.float32, device=dev)
