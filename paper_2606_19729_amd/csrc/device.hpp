@@ -293,6 +293,12 @@ __device__ __forceinline__ int opaque_zero() {
     return z;
 }
 
+// A wave-uniform 32-bit value the compiler cannot see through.
+__device__ __forceinline__ uint32_t opaque_u32(uint32_t v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // Fragment source reading a resident copy of the packed network (global
 // memory or LDS) directly; the address is refreshed every WIN fragments.
 template <int DT, int WIN>
@@ -329,11 +335,14 @@ struct StreamSrc {
     static_assert(NBUF >= 2 && (NBUF - 2) * ROUNDS <= 63 && NCH >= NBUF, "bad chunk pipeline");
     char* lds;          // NBUF * CHB bytes of LDS
     const char* src;    // packed fragment stream in global memory
+    const char* lsrc;   // this lane's 16-byte slot of this wave's first 1 KB round
     int cur, nxt_buf;   // buffer of the current chunk, buffer of the next load
     const char* win;    // current chunk's buffer, refreshed every WIN fragments
 
     __device__ __forceinline__ StreamSrc(char* l, const char* s)
-        : lds(l), src(s), cur(NBUF - 1), nxt_buf(NBUF - 1), win(l) {}
+        : lds(l), src(s),
+          lsrc(s + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 1024 + (threadIdx.x & 63) * 16),
+          cur(NBUF - 1), nxt_buf(NBUF - 1), win(l) {}
 
     // Copies chunk ch into buffer b: each wave moves a quarter, 1 KB per
     // round (64 lanes x 16 B), with direct-to-LDS loads.
@@ -380,7 +389,7 @@ struct StreamSrc {
             const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
             const int off = (r * kWaves + wave) * 1024;
             __builtin_amdgcn_global_load_lds(
-                (const void*)(src + opaque_zero() + (size_t)nxt_ch * CHB + off + (threadIdx.x & 63) * 16),
+                (const void*)(lsrc + opaque_u32((uint32_t)(nxt_ch * CHB + r * kWaves * 1024))),
                 (__attribute__((address_space(3))) void*)(lds + nxt_buf * CHB + off), 16, 0, 0);
             if (r == ROUNDS - 1) nxt_buf = nxt_buf + 1 == NBUF ? 0 : nxt_buf + 1;
         }
@@ -558,10 +567,13 @@ struct GroupStream {
     static_assert(NBUF >= 2 && (NBUF - 2) * ROUNDS <= 63 && NCH >= NBUF, "bad chunk pipeline");
     char* lds;
     const char* src;
+    const char* lsrc;  // this lane's 16-byte slot of this wave's first 1 KB round
     int cur, nxt_buf, gch;
     const char* win;
     __device__ __forceinline__ GroupStream(char* l, const char* s)
-        : lds(l), src(s), cur(NBUF - 1), nxt_buf(NBUF - 1), gch(0), win(l), nxt_ch(0) {}
+        : lds(l), src(s),
+          lsrc(s + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 1024 + (threadIdx.x & 63) * 16),
+          cur(NBUF - 1), nxt_buf(NBUF - 1), gch(0), win(l), nxt_ch(0) {}
     __device__ __forceinline__ void fetch(int ch, int b) const {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
@@ -582,9 +594,10 @@ struct GroupStream {
     // One 1 KB load of chunk ch into buffer b (round r of this wave).
     __device__ __forceinline__ void fetch_round(int ch, int b, int r) const {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int lane = threadIdx.x & 63;
         const int off = (r * kWaves + wave) * 1024;
-        __builtin_amdgcn_global_load_lds((const void*)(src + opaque_zero() + (size_t)ch * CHB + off + lane * 16),
+        // one scalar offset added to the lane's precomputed address (kept
+        // opaque so that its constant part is not split off into a second add)
+        __builtin_amdgcn_global_load_lds((const void*)(lsrc + opaque_u32((uint32_t)(ch * CHB + r * kWaves * 1024))),
                                          (__attribute__((address_space(3))) void*)(lds + b * CHB + off), 16, 0, 0);
     }
     // The loads of the chunk NBUF - 1 ahead are spread over the current chunk
