@@ -388,9 +388,11 @@ def soft_value(Q, eta, log_pi0=None, want_pi=True, status=None, stream=None):
 
 def plan_closed_loop(model: Model, states, first, n_obs, cont, gamma, eta, lam, goal, seed, U, log_pi0=None,
                      want_child=False, workspace=None, status=None, stream=None):
-    """One-level closed-loop tree with the preference backup: returns
-    dict(psi [A], V [1], pi [A], best [1], R [A], V_child [A n_obs], child
-    [A n_obs N, d_s] or None)."""
+    """One-level closed-loop tree with the preference backup.  `first`:
+    int32 [A] action indices or float32 [A, d_a]; `cont`: continuation
+    candidates as for plan; `U` [A n_obs] int32 holds the child resampling
+    offsets' 32-bit patterns.  Returns dict(psi [A], V [1], pi [A], best [1],
+    R [A], V_child [A n_obs], child [A n_obs N, d_s] or None)."""
     d = model.desc
     N = int(states.shape[0])
     _dev(states, torch.float32, (N, d.d_s), "states")
@@ -429,8 +431,9 @@ def plan_closed_loop(model: Model, states, first, n_obs, cont, gamma, eta, lam, 
 def pw_step(model: Model, succ, seg, actions, visits, children, obs_table, U, k_o, alpha_o, lam=1.0, seed=0,
             out=None, workspace=None, status=None, stream=None):
     """Grouped progressive widening over M action nodes (successors
-    succ[seg[m]:seg[m+1]]).  `children` [M] int32 and `obs_table`
-    [M, capacity, d_o] float32 are updated in place.  Returns dict(widen,
+    succ[seg[m]:seg[m+1]], seg [M + 1] int32).  `children` [M] int32 and
+    `obs_table` [M, capacity, d_o] float32 are updated in place; `U` [M]
+    int32 holds the resampling offsets' 32-bit patterns.  Returns dict(widen,
     branch, loglik, w, stats, idx, succ)."""
     d = model.desc
     T = int(succ.shape[0])
