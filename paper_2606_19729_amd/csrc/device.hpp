@@ -247,6 +247,10 @@ template <int HT> struct Act<DT_F32, HT> {
 #pragma unroll
             for (int i = 0; i < 16; ++i) v[t0 + t][i] = relu_f32(acc[t][i]);
     }
+    __device__ __forceinline__ void set_relu_tile(const f32x16 (&acc)[HT], int t) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[t][i] = relu_f32(acc[t][i]);
+    }
     __device__ __forceinline__ float b(int c) const { return v[c >> 4][c & 15]; }
 };
 template <int HT> struct Act<DT_BF16, HT> {
@@ -265,6 +269,10 @@ template <int HT> struct Act<DT_BF16, HT> {
             v[2 * (t0 + t)] = relu_bf16x8(acc[t], 0);
             v[2 * (t0 + t) + 1] = relu_bf16x8(acc[t], 1);
         }
+    }
+    __device__ __forceinline__ void set_relu_tile(const f32x16 (&acc)[HT], int t) {
+        v[2 * t] = relu_bf16x8(acc[t], 0);
+        v[2 * t + 1] = relu_bf16x8(acc[t], 1);
     }
     __device__ __forceinline__ bf16x8 b(int c) const { return v[c]; }
 };
@@ -424,7 +432,7 @@ __device__ __forceinline__ void mfma_layer(f32x16 (&acc)[NT], LD&& ld, BOP&& bop
                 ring[(c + DD - 1) % DD][decltype(ti)::value] = ld(c + DD - 1, decltype(ti)::value);
             });
         }
-        auto b = bop(c);
+        auto b = bop(ci);
         static_for<NT>([&](auto ti) {
             constexpr int t = decltype(ti)::value;
             acc[t] = mfma(ring[c % DD][t], b, acc[t]);
@@ -459,8 +467,43 @@ __device__ __forceinline__ f32x16 run_net(Src& src, const NetPtrs& P, const floa
                                           const float (&slots)[N::IN_SLOTS], int lane, int g) {
     if constexpr (N::CT < N::HT) {
         return run_net_grouped<N>(src, P, b0, slots, lane, g);
+    } else if constexpr (N::DT == DT_BF16 && N::WIDTH > 64) {
+        // streamed bfloat16: every loop unrolled at compile time, weight fragments of
+        // the next k-steps loaded while this one multiplies, and two
+        // accumulator sets so that each layer's ReLU and conversion run tile by
+        // tile inside the next layer, one tile ahead of the k-steps that read
+        // it, overlapped with the matrix cores instead of between layers
+        typedef FragIdx<N> FI;
+        typedef typename Frag<N::DT>::type FT;
+        constexpr int KPT = N::HID_KS / N::HT;  // k-steps that read one tile of the previous layer
+        f32x16 acc[2][N::HT];
+        Act<N::DT, N::HT> act;
+        init_bias<N::HT>(acc[0], b0 + opaque_zero(), g);
+        mfma_layer<N::IN_KS, N::HT, 2, FT>(
+            acc[0], [&](int c, int t) { return src.load(FI::first(c, t), lane); },
+            [&](int c) { return Slots<N::DT, N::IN_SLOTS>::b(slots, c); });
+        act.set_relu_tile(acc[0], 0);
+        auto lazy_b = [&](const f32x16 (&prev)[N::HT], auto ci) {
+            constexpr int c = decltype(ci)::value;
+            if constexpr (c % KPT == 0 && c / KPT + 1 < N::HT) act.set_relu_tile(prev, c / KPT + 1);
+            return act.b(c);
+        };
+        static_for<N::NHID - 1>([&](auto li) {
+            constexpr int l = decltype(li)::value + 1;
+            init_bias<N::HT>(acc[l % 2], P.bh + (l - 1) * N::WIDTH + opaque_zero(), g);
+            mfma_layer<N::HID_KS, N::HT, kPfDepth, FT>(
+                acc[l % 2], [&](int c, int t) { return src.load(FI::hidden(l, c, t), lane); },
+                [&](auto ci) { return lazy_b(acc[(l - 1) % 2], ci); });
+            act.set_relu_tile(acc[l % 2], 0);
+        });
+        f32x16 out[1];
+        init_bias<1>(out, P.bo + opaque_zero(), g);
+        mfma_layer<N::HID_KS, 1, 4, FT>(
+            out, [&](int c, int) { return src.load(FI::out(c), lane); },
+            [&](auto ci) { return lazy_b(acc[(N::NHID - 1) % 2], ci); });
+        return out[0];
     } else if constexpr (N::DT == DT_BF16 || N::WIDTH > 64) {
-        // bfloat16 and streamed binary32 networks: every loop unrolled at
+        // small bfloat16 and streamed binary32 networks: every loop unrolled at
         // compile time (fragment positions, and a streaming source's chunk
         // boundaries, are constants) and the weight fragments of the next
         // k-steps load while this one multiplies
