@@ -69,6 +69,8 @@ def lib():
         L.or_soft_value.argtypes = [c_int, c_int, dp, dp, c_double, dp, dp, i32p]
         L.or_plan_steps.argtypes = [mp, c_int, dp, c_int, c_int, i32p, dp, dp, dp, c_uint64, c_int, c_int,
                                     dp, dp]
+        L.or_info_nce_rows.argtypes = [c_int, c_int, i32p, dp, dp, dp]
+        L.or_info_nce.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, i32p, c_int, dp, dp, dp, dp]
         L.or_mlp_param_count.argtypes = [c_int, ip]
         L.or_mlp_param_count.restype = c_size_t
         L.or_set_threads.argtypes = [c_int]
@@ -355,6 +357,49 @@ def plan_closed_loop(model, states, first, n_obs, cont, gamma, eta, lam, goal, s
     psi = lp / eta + R + gamma * Vc.reshape(A, n_obs).mean(axis=1)
     V, pi, best = soft_value(psi[None, :], eta, log_pi0=np.zeros((1, A)))
     return dict(psi=psi, V=V[0], pi=pi[0], best=int(best[0]), R=R, V_child=Vc, child=child)
+
+
+def info_nce_from_scores(scores, rows=None):
+    """(row_loss [R], G [R, B]) of score rows [R, B] (Eq. 6): row r is the
+    state-action of tuple rows[r] (None: r) against all B observations,
+    row_loss_r = log sum_j exp(l_rj) - l_r,rows[r], and G the derivative of
+    the batch's mean row loss with respect to each score."""
+    L = np.atleast_2d(_d(scores))
+    R, B = L.shape
+    rw = None if rows is None else np.ascontiguousarray(np.asarray(rows, np.int32))
+    if rw is None:
+        assert R == B
+    rl = np.zeros(R)
+    G = np.zeros((R, B))
+    _check(lib().or_info_nce_rows(B, R, _p(rw, c_int32), _p(np.ascontiguousarray(L)), _p(rl), _p(G)),
+           "info_nce_rows")
+    return rl, G
+
+
+def info_nce(model, states, actions, obs, rows=None, bf16=False):
+    """InfoNCE objective of the likelihood network on a mini-batch of B
+    tuples (s'_i, a_i, o_i) (Sec. 4.2, Eq. 6).  Returns a dict with scores
+    [R, B] (l([s'_i, a_i, o_j]) for the listed rows i, None: all), row_loss
+    [R], G [R, B] (derivative of the loss with respect to each score) and,
+    with all rows, loss (the mean row loss)."""
+    S = _d(states)
+    B = S.shape[0]
+    O = _d(np.asarray(obs).reshape(B, model.d_o))
+    if model.n_actions > 0:
+        a_disc, a_cont = np.ascontiguousarray(np.asarray(actions, np.int32).reshape(B)), None
+    else:
+        a_disc, a_cont = None, _d(np.asarray(actions).reshape(B, model.d_a))
+    rw = None if rows is None else np.ascontiguousarray(np.asarray(rows, np.int32))
+    R = B if rw is None else rw.shape[0]
+    out = dict(scores=np.zeros((R, B)), row_loss=np.zeros(R), G=np.zeros((R, B)))
+    loss = np.zeros(1)
+    b = _Bound(model)
+    _check(lib().or_info_nce(b.ref(), B, _p(S), _p(a_disc, c_int32), _p(a_cont), _p(O), R, _p(rw, c_int32),
+                             int(bf16), _p(out["scores"]), _p(out["row_loss"]), _p(out["G"]),
+                             _p(loss if rw is None else None)), "info_nce")
+    if rw is None:
+        out["loss"] = float(loss[0])
+    return out
 
 
 def weighted_mean(G, w=None):

@@ -37,6 +37,10 @@
  *   soft_value  The log-sum-exp operator of the preference formulation
  *             (Sec. 2.2): soft value, soft policy and greedy action of the
  *             candidates' preferences, with a reference-policy prior.
+ *   info_nce  The contrastive objective of the likelihood network (Sec. 4.2,
+ *             Eq. 6): scores of all B x B state-action / observation pairs of
+ *             a mini-batch, per-row log-sum-exp losses, their mean and its
+ *             derivative with respect to every score.
  *   plan_steps  The states of the plan rollouts and an observation drawn
  *             from f_Z at every step (Sec. 4.3 forward-simulates with both
  *             learned samplers).
@@ -1108,5 +1112,91 @@ int or_soft_value(int M, int K, const double* Q, const double* log_pi0, double e
         if (best) best[m] = arg;
     }
     free(x);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Contrastive likelihood objective (Sec. 4.2, Eq. 6): every state-action of */
+/* a mini-batch of B tuples (s'_i, a_i, o_i) against every observation.      */
+/* ------------------------------------------------------------------------- */
+/* Given the all-pairs scores l_ij = l(s'_i, a_i, o_j) (row i, column j) of
+ * the rows listed in rows[r] (n_rows of them; the diagonal entry of row r is
+ * column rows[r]):
+ *   row_loss_r = log sum_j exp(l_ij) - l_ii     (max-shifted, compensated sum)
+ *   G_rj       = (exp(l_ij) / sum_j' exp(l_ij') - [j == i]) / B,
+ * the derivative of the mean of the B row losses with respect to l_ij. */
+int or_info_nce_rows(int B, int n_rows, const int32_t* rows, const double* Lg, double* row_loss, double* G)
+{
+    if (B < 1 || n_rows < 0) return OR_ERR_ARG;
+    for (int r = 0; r < n_rows; ++r) {
+        const int i = rows ? rows[r] : r;
+        if (i < 0 || i >= B) return OR_ERR_ARG;
+        const double* l = Lg + (size_t)r * B;
+        double mx = -INFINITY;
+        for (int j = 0; j < B; ++j) {
+            if (!isfinite(l[j])) return OR_ERR_NUMERIC;
+            if (l[j] > mx) mx = l[j];
+        }
+        double sum = 0.0, comp = 0.0;
+        for (int j = 0; j < B; ++j) {
+            double v = exp(l[j] - mx);
+            double t = sum + v;
+            if (fabs(sum) >= fabs(v)) comp += (sum - t) + v;
+            else comp += (v - t) + sum;
+            sum = t;
+        }
+        const double S = sum + comp;
+        if (row_loss) row_loss[r] = mx + log(S) - l[i];
+        if (G)
+            for (int j = 0; j < B; ++j)
+                G[(size_t)r * B + j] = (exp(l[j] - mx) / S - (j == i ? 1.0 : 0.0)) / (double)B;
+    }
+    return OR_OK;
+}
+
+/* The scores l_ij = l([s'_i, a_i, o_j]) of rows rows[r] (NULL: all B rows in
+ * order) against all B observations, then their row losses and derivatives
+ * (or_info_nce_rows).  With all rows, *loss = (1/B) sum_i row_loss_i (the
+ * InfoNCE loss of Eq. 6); loss may be NULL. */
+int or_info_nce(const or_model* m0, int B, const double* S, const int32_t* a_disc, const double* a_cont,
+                const double* O, int n_rows, const int32_t* rows, int bf16, double* Lg, double* row_loss,
+                double* G, double* loss)
+{
+    if (B < 1 || n_rows < 0 || (!rows && n_rows != B)) return OR_ERR_ARG;
+    if (mlp_check(m0->l_layers, m0->l_dims) != OR_OK) return OR_ERR_ARG;
+    if (m0->l_dims[0] != m0->d_s + action_width(m0) + m0->d_o || m0->l_dims[m0->l_layers] != 1) return OR_ERR_ARG;
+    if (m0->n_actions > 0 ? !a_disc : !a_cont) return OR_ERR_ARG;
+    for (int r = 0; r < n_rows; ++r) {
+        const int i = rows ? rows[r] : r;
+        if (i < 0 || i >= B) return OR_ERR_ARG;
+        if (m0->n_actions > 0 && (a_disc[i] < 0 || a_disc[i] >= m0->n_actions)) return OR_ERR_ARG;
+    }
+    const int d_s = m0->d_s, d_o = m0->d_o, aw = action_width(m0);
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
+    #pragma omp parallel for schedule(static)
+    for (long e = 0; e < (long)n_rows * B; ++e) {
+        const int r = (int)(e / B), j = (int)(e % B);
+        const int i = rows ? rows[r] : r;
+        double x[OR_MAX_WIDTH], y[1];
+        for (int c = 0; c < d_s; ++c) x[c] = S[(size_t)i * d_s + c];
+        put_action(m, x + d_s, a_disc ? a_disc[i] : 0, a_cont ? a_cont + (size_t)i * m->d_a : NULL);
+        for (int c = 0; c < d_o; ++c) x[d_s + aw + c] = O[(size_t)j * d_o + c];
+        mlp_forward(m->l_layers, m->l_dims, m->l_params, x, y, bf16);
+        Lg[e] = y[0];
+    }
+    release_rounded(&rm);
+    int rc = or_info_nce_rows(B, n_rows, rows, Lg, row_loss, G);
+    if (rc == OR_OK && loss && !rows && row_loss) {
+        double sum = 0.0, comp = 0.0;
+        for (int i = 0; i < B; ++i) {
+            double v = row_loss[i];
+            double t = sum + v;
+            if (fabs(sum) >= fabs(v)) comp += (sum - t) + v;
+            else comp += (v - t) + sum;
+            sum = t;
+        }
+        *loss = (sum + comp) / (double)B;
+    }
     return rc;
 }

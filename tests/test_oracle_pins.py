@@ -733,3 +733,121 @@ def test_closed_loop_tree_special_cases():
     # eta -> infinity: V(b) tends to the best preference
     out3 = oracle.plan_closed_loop(m, w.states, first, 2, cont, 0.9, 1e6, 1.0, w.goal, 11, U[:10])
     assert out3["V"] == pytest.approx(out3["psi"].max(), abs=1e-4)
+
+
+# ----------------------------------------------------------------------------- InfoNCE (Eq. 6)
+def test_info_nce_scores_exact_two_by_two():
+    # row 0: scores (0, log 3) -> softmax (1/4, 3/4), loss log 4 - 0
+    # row 1: scores (0, 0)     -> softmax (1/2, 1/2), loss log 2 - 0
+    L = np.array([[0.0, np.log(3.0)], [0.0, 0.0]])
+    rl, G = oracle.info_nce_from_scores(L)
+    np.testing.assert_allclose(rl, [2 * np.log(2.0), np.log(2.0)], rtol=1e-15)
+    assert rl.mean() == pytest.approx(1.5 * np.log(2.0), rel=1e-15)
+    np.testing.assert_allclose(G, [[-3 / 8, 3 / 8], [1 / 4, -1 / 4]], rtol=1e-15, atol=1e-16)
+    # the diagonal entry is the row's own column: listing row 1 alone
+    rl1, G1 = oracle.info_nce_from_scores(L[1:], rows=[1])
+    np.testing.assert_allclose(rl1, rl[1:], rtol=0)
+    np.testing.assert_allclose(G1, G[1:], rtol=0)
+
+
+def test_info_nce_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    B = 7
+    L = rng.standard_normal((B, B)) * 2.0
+    _, G = oracle.info_nce_from_scores(L)
+    h = 1e-6
+    for i, j in [(0, 0), (0, 5), (3, 3), (6, 1), (4, 2)]:
+        Lp, Lm = L.copy(), L.copy()
+        Lp[i, j] += h
+        Lm[i, j] -= h
+        fd = (oracle.info_nce_from_scores(Lp)[0].mean() - oracle.info_nce_from_scores(Lm)[0].mean()) / (2 * h)
+        assert G[i, j] == pytest.approx(fd, abs=1e-9)
+    np.testing.assert_allclose(G.sum(axis=1), 0.0, atol=1e-15)
+
+
+def linear_score_model(rng, d_s, n_actions, d_a, d_o, width=16):
+    """A likelihood network that computes the affine score u = v . x + c
+    exactly: hidden unit 0 is relu(u), unit 1 is relu(-u), the second hidden
+    layer copies them (they are non-negative) and the output is their
+    difference."""
+    aw = n_actions if n_actions > 0 else d_a
+    d_in = d_s + aw + d_o
+    v = rng.standard_normal(d_in).astype(np.float32)
+    c = np.float32(0.375)
+    W1 = np.zeros((width, d_in), np.float32)
+    W1[0], W1[1] = v, -v
+    b1 = np.zeros(width, np.float32)
+    b1[0], b1[1] = c, -c
+    W2 = np.eye(width, dtype=np.float32)
+    W3 = np.zeros((1, width), np.float32)
+    W3[0, 0], W3[0, 1] = 1.0, -1.0
+    lik = [(W1, b1), (W2, np.zeros(width, np.float32)), (W3, np.zeros(1, np.float32))]
+    trans = workloads.random_mlp(rng, [d_s + aw + 1, width, width, d_s])
+    return Model(d_s=d_s, n_actions=n_actions, d_a=d_a, d_w=1, d_o=d_o, d_wz=1, trans=trans, lik=lik), v, c
+
+
+@pytest.mark.parametrize("n_actions,d_a", [(5, 0), (0, 3)])
+def test_info_nce_affine_score_closed_form(n_actions, d_a):
+    # With l = v_s . s' + v_a . a + v_o . o + c the state-action part is
+    # constant along a row, so row i's loss is log sum_j exp(v_o . o_j) - v_o . o_i
+    # whatever the states and actions: only the observation varies along a row.
+    rng = np.random.default_rng(17)
+    d_s, d_o, B = 4, 3, 11
+    m, v, c = linear_score_model(rng, d_s, n_actions, d_a, d_o)
+    aw = m.action_width
+    S = rng.standard_normal((B, d_s)).astype(np.float32)
+    A = rng.integers(0, n_actions, B).astype(np.int32) if n_actions else rng.standard_normal((B, d_a)).astype(np.float32)
+    O = rng.standard_normal((B, d_o)).astype(np.float32)
+    out = oracle.info_nce(m, S, A, O)
+    vo = O.astype(np.float64) @ v[d_s + aw:].astype(np.float64)
+    lse = np.log(np.sum(np.exp(vo - vo.max()))) + vo.max()
+    np.testing.assert_allclose(out["row_loss"], lse - vo, rtol=1e-12, atol=1e-12)
+    assert out["loss"] == pytest.approx(np.mean(lse - vo), rel=1e-12)
+    # the scores themselves: the row's state-action and the column's observation
+    Aoh = np.eye(n_actions)[A] if n_actions else A.astype(np.float64)
+    sa = S.astype(np.float64) @ v[:d_s].astype(np.float64) + Aoh @ v[d_s:d_s + aw].astype(np.float64)
+    np.testing.assert_allclose(out["scores"], sa[:, None] + vo[None, :] + float(c), rtol=1e-12, atol=1e-12)
+    # the derivative: softmax of the observation scores, minus the identity, over B
+    p = np.exp(vo - vo.max())
+    p /= p.sum()
+    np.testing.assert_allclose(out["G"], (p[None, :] - np.eye(B)) / B, rtol=1e-12, atol=1e-14)
+
+
+def test_info_nce_special_cases_and_invariances():
+    w = workloads.small(seed=91, N=16)
+    m = w.model
+    rng = np.random.default_rng(5)
+    B = 13
+    S = w.states[:B]
+    A = rng.integers(0, m.n_actions, B).astype(np.int32)
+    O = rng.standard_normal((B, m.d_o)).astype(np.float32)
+    out = oracle.info_nce(m, S, A, O)
+    # B = 1: a single positive pair, zero loss and zero derivative
+    one = oracle.info_nce(m, S[:1], A[:1], O[:1])
+    assert one["loss"] == 0.0 and one["G"][0, 0] == 0.0
+    # identical observations: every row's scores are equal, loss log B
+    same = oracle.info_nce(m, S, A, np.repeat(O[:1], B, axis=0))
+    np.testing.assert_allclose(same["row_loss"], np.log(B), rtol=1e-13)
+    np.testing.assert_allclose(same["G"], (1.0 / B - np.eye(B)) / B, rtol=1e-12, atol=1e-15)
+    # a constant added to every score (the output bias) changes nothing
+    lik2 = [(W.copy(), b.copy()) for W, b in m.lik]
+    lik2[-1] = (lik2[-1][0], lik2[-1][1] + np.float32(8.0))
+    m2 = Model(**{**m.__dict__, "lik": lik2})
+    out2 = oracle.info_nce(m2, S, A, O)
+    shift = float(lik2[-1][1][0]) - float(m.lik[-1][1][0])
+    np.testing.assert_allclose(out2["scores"], out["scores"] + shift, rtol=1e-12)
+    np.testing.assert_allclose(out2["row_loss"], out["row_loss"], rtol=1e-10, atol=1e-12)
+    # permuting the batch permutes rows and columns
+    perm = rng.permutation(B)
+    outp = oracle.info_nce(m, S[perm], A[perm], O[perm])
+    np.testing.assert_allclose(outp["scores"], out["scores"][perm][:, perm], rtol=0)
+    np.testing.assert_allclose(outp["row_loss"], out["row_loss"][perm], rtol=1e-14)
+    assert outp["loss"] == pytest.approx(out["loss"], rel=1e-14)
+    # a subset of rows is the same rows of the full evaluation
+    sub = oracle.info_nce(m, S, A, O, rows=[12, 0, 5])
+    np.testing.assert_allclose(sub["scores"], out["scores"][[12, 0, 5]], rtol=0)
+    np.testing.assert_allclose(sub["row_loss"], out["row_loss"][[12, 0, 5]], rtol=0)
+    np.testing.assert_allclose(sub["G"], out["G"][[12, 0, 5]], rtol=0)
+    # scores are the likelihood network on [s'_i, a_i, o_j]
+    X = np.concatenate([S[3], np.eye(m.n_actions)[A[3]], O[8]]).astype(np.float64)
+    assert out["scores"][3, 8] == pytest.approx(_numpy_mlp(m.lik, X[None, :])[0, 0], rel=1e-12)

@@ -207,3 +207,20 @@ def explicit_update_noise(w: Workload, seed: int = 12) -> np.ndarray:
     """Explicit proposal noise [N, d_w] float32."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal((w.N, w.model.d_w)).astype(np.float32)
+
+
+def nce_batch(w: Workload, B: int, seed: int = 14):
+    """A synthetic mini-batch of B (s', a, o) tuples for the contrastive
+    likelihood objective: states drawn from the workload's particles (with
+    replacement), uniform discrete actions or continuous actions in [-1, 1],
+    and N(0, 1) observations.  Returns (states [B, d_s] float32, actions int32
+    [B] or float32 [B, d_a], observations [B, d_o] float32)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = w.model
+    S = w.states[rng.integers(0, w.N, B)].astype(np.float32)
+    if m.n_actions > 0:
+        A = rng.integers(0, m.n_actions, B).astype(np.int32)
+    else:
+        A = rng.uniform(-1.0, 1.0, size=(B, m.d_a)).astype(np.float32)
+    O = rng.standard_normal((B, m.d_o)).astype(np.float32)
+    return S, A, O
