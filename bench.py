@@ -327,6 +327,53 @@ def bench_pw(V, torch, reps):
     return out
 
 
+def lik_flops(model, first_inputs):
+    """2 * MACs of one likelihood-network evaluation whose first layer takes
+    `first_inputs` inputs."""
+    dims = [first_inputs] + [int(W.shape[0]) for W, _ in model.lik]
+    return 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+
+
+def bench_info_nce(V, torch, reps):
+    """The contrastive objective of the likelihood network with the realistic
+    networks on a mini-batch of B = 4,096 tuples (16.8 M scored pairs):
+    scores, row losses, mean loss and the derivative by every score, binary32
+    and bfloat16."""
+    import workloads
+    dev = torch.device("cuda", 0)
+    w = workloads.realistic(seed=8, N=4096, K=1, H=1)
+    B = 4096
+    S, A, O = (torch.as_tensor(x, device=dev) for x in workloads.nce_batch(w, B, seed=16))
+    m0 = w.model
+    pairs = B * B
+    # the state and action columns are folded once per row; every pair runs
+    # the rest of the network with the observation as its input
+    f_pair = lik_flops(m0, m0.d_o)
+    out = {"B": B, "pairs": pairs, "flop_per_pair_executed": f_pair,
+           "flop_per_pair_full_input": lik_flops(m0, m0.d_s + m0.action_width + m0.d_o)}
+    stream = torch.cuda.current_stream()
+    for compute in ["f32", "bf16"]:
+        m = V.Model(m0, compute=compute)
+        ws = torch.empty(int(V.lib.voila_info_nce_workspace_size(m.handle, B)), dtype=torch.uint8, device=dev)
+        res = None
+        ms = []
+        for r in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            res = V.info_nce(m, S, A, O, out=res, workspace=ws)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                ms.append(a.elapsed_time(b))
+        t = float(np.median(ms))
+        peak = PEAK_F32_TFLOPS if compute == "f32" else PEAK_BF16_TFLOPS
+        out[compute] = {"ms": t, "pairs_per_s": pairs / (t / 1e3),
+                        "mfma_frac": f_pair * pairs / (t / 1e3) / 1e12 / peak,
+                        "loss": float(res["loss"].item())}
+        print(f"[bench]   {compute}: {t:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_tree(V, torch, reps):
     """One-level closed-loop tree with the realistic networks: 1,024 particles,
     8 continuous first actions x 4 observation branches, 128 continuation
@@ -642,6 +689,8 @@ def main():
         result["plan_observe"] = bench_plan_observe(V, torch, max(2, args.steps // 2), w, S, C)
         print("[bench] grouped progressive widening", file=sys.stderr, flush=True)
         result["pw_step"] = bench_pw(V, torch, max(3, args.steps))
+        print("[bench] contrastive likelihood objective", file=sys.stderr, flush=True)
+        result["info_nce"] = bench_info_nce(V, torch, max(3, args.steps))
         print("[bench] one-level closed-loop tree", file=sys.stderr, flush=True)
         result["closed_loop_tree"] = bench_tree(V, torch, max(2, args.steps // 2))
         print("[bench] belief-update sweep", file=sys.stderr, flush=True)

@@ -251,6 +251,31 @@ voila_status_t voila_plan_observe(voila_model_t model, const float* d_traj, int3
                                   void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Contrastive (InfoNCE) objective of the likelihood network, Sec. 4.2,
+ * Eq. 6.  For a mini-batch of B tuples (s'_i, a_i, o_i) -- d_states
+ * [B][d_s] float, d_actions int32 [B] indices or float [B][d_a], d_obs
+ * [B][d_o] float -- the network is evaluated on every state-action against
+ * every observation:
+ *   l_ij = l([s'_i, a_i, o_j])                    (d_scores_out [B][B] float or NULL)
+ *   row_loss_i = log sum_j exp(l_ij) - l_ii        (d_row_loss_out [B] double or NULL)
+ *   loss = (1/B) sum_i row_loss_i                  (d_loss_out [1] double or NULL)
+ *   G_ij = d loss / d l_ij = (softmax_j(l_i.)_j - [i == j]) / B
+ *                                                  (d_grad_out [B][B] float or NULL)
+ * Scores are computed in the model's precision; the row reductions run in
+ * binary64 (max-shifted) and G is rounded to float.  1 <= B <= 32768.  The
+ * workspace (voila_info_nce_workspace_size) holds one folded first-layer
+ * bias row per tuple and, where the caller passes NULL, the scores and row
+ * losses.  A discrete action outside [0, n_actions) sets *d_status to
+ * VOILA_ERR_INVALID_ARG (action 0 is used); a non-finite score sets it to
+ * VOILA_ERR_NUMERIC.  All buffers are caller-owned device memory.
+ * ------------------------------------------------------------------------- */
+size_t voila_info_nce_workspace_size(voila_model_t model, int32_t B);
+voila_status_t voila_info_nce(voila_model_t model, const float* d_states, const void* d_actions,
+                              const float* d_obs, int32_t B, void* d_workspace, size_t workspace_bytes,
+                              float* d_scores_out, double* d_row_loss_out, float* d_grad_out, double* d_loss_out,
+                              int32_t* d_status, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Soft value and action selection (the log-sum-exp operator L_eta of the
  * preference formulation the planner builds on, Sec. 2.2): for M nodes with
  * K candidate preferences each (d_Q [M][K] float, e.g. voila_plan's Q) and a

@@ -158,6 +158,10 @@ def _load():
     L.voila_pw_step.argtypes = [vp, vp, c_int32, vp, c_int32, vp, vp, vp, vp, vp, POINTER(_PwOpts), vp, c_size_t,
                                 vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.voila_pw_step.restype = c_int32
+    L.voila_info_nce_workspace_size.argtypes = [vp, c_int32]
+    L.voila_info_nce_workspace_size.restype = c_size_t
+    L.voila_info_nce.argtypes = [vp, vp, vp, vp, c_int32, vp, c_size_t, vp, vp, vp, vp, vp, vp]
+    L.voila_info_nce.restype = c_int32
     L.voila_philox_normals.argtypes = [c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int32, c_int32, vp,
                                        vp, vp]
     L.voila_philox_normals.restype = c_int32
@@ -191,6 +195,7 @@ EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_m
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_plan_observe_workspace_size",
             "voila_plan_observe", "voila_pw_step_workspace_size", "voila_pw_step", "voila_soft_value",
             "voila_plan_closed_loop_workspace_size", "voila_plan_closed_loop",
+            "voila_info_nce_workspace_size", "voila_info_nce",
             "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
             "voila_batch_replay", "voila_grad_param_count", "voila_rollout_grad_workspace_size",
@@ -384,6 +389,35 @@ def soft_value(Q, eta, log_pi0=None, want_pi=True, status=None, stream=None):
     _check(lib.voila_soft_value(_ptr(Q), _ptr(log_pi0), M, K, float(eta), _ptr(V), _ptr(pi), _ptr(best),
                                 _ptr(status), _stream(stream)))
     return V, pi, best
+
+
+def info_nce(model: Model, states, actions, obs, want_scores=True, want_grad=True, out=None, workspace=None,
+             status=None, stream=None):
+    """Contrastive objective of the likelihood network over a mini-batch of
+    B tuples: states [B, d_s] float32, actions int32 [B] or float32 [B, d_a],
+    obs [B, d_o] float32.  Returns dict(loss [1] float64, row_loss [B]
+    float64, scores [B, B] float32 or None, grad [B, B] float32 or None)."""
+    d = model.desc
+    B = int(states.shape[0])
+    _dev(states, torch.float32, (B, d.d_s), "states")
+    if d.n_actions > 0:
+        _dev(actions, torch.int32, (B,), "actions")
+    else:
+        _dev(actions, torch.float32, (B, d.d_a), "actions")
+    _dev(obs, torch.float32, (B, d.d_o), "obs")
+    dev = states.device
+    o = out if out is not None else {}
+    res = {"loss": o.get("loss", torch.empty(1, dtype=torch.float64, device=dev)),
+           "row_loss": o.get("row_loss", torch.empty(B, dtype=torch.float64, device=dev)),
+           "scores": o.get("scores", torch.empty((B, B), dtype=torch.float32, device=dev)) if want_scores else None,
+           "grad": o.get("grad", torch.empty((B, B), dtype=torch.float32, device=dev)) if want_grad else None}
+    if workspace is None:
+        n = lib.voila_info_nce_workspace_size(model.handle, B)
+        workspace = torch.empty(max(int(n), 1), dtype=torch.uint8, device=dev)
+    _check(lib.voila_info_nce(model.handle, _ptr(states), _ptr(actions), _ptr(obs), B, _ptr(workspace),
+                              workspace.numel(), _ptr(res["scores"]), _ptr(res["row_loss"]), _ptr(res["grad"]),
+                              _ptr(res["loss"]), _ptr(status), _stream(stream)))
+    return res
 
 
 def plan_closed_loop(model: Model, states, first, n_obs, cont, gamma, eta, lam, goal, seed, U, log_pi0=None,

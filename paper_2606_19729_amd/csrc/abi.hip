@@ -64,11 +64,12 @@ struct HostNet {
 // Input column of first-layer slot si of lane group g (-1: padding).
 struct SlotMap {
     int d_s, d_ain, d_w, col_a, col_w;
+    int col_s = 0;  // input column of the first "state" slot feature
     int operator()(int si, int g) const {
         const int SS = state_slots(d_s), SA = action_slots(d_ain), SW = noise_slots(d_w);
         if (si < SS) {
             int f = 2 * si + g;
-            return f < d_s ? f : -1;
+            return f < d_s ? col_s + f : -1;
         }
         si -= SS;
         if (si < SA) {
@@ -233,15 +234,16 @@ struct voila_model_s {
     int d_s = 0, n_actions = 0, d_a = 0, d_w = 0, d_o = 0, d_wz = 0, width = 0, n_hidden = 0;
     bool has_obs = false, has_lik = false;
     char* mem = nullptr;
-    NetBlob trans_plan{}, trans_upd{}, obs{}, lik{};
+    NetBlob trans_plan{}, trans_upd{}, obs{}, lik{}, lik_nce{};
     const float* fold_w_trans = nullptr;
     const float* fold_b_trans = nullptr;
     const float* fold_w_obs = nullptr;
     const float* fold_b_obs = nullptr;
     const float* fold_w_lik = nullptr;
     const float* fold_b_lik = nullptr;
+    const float* fold_w_nce = nullptr;  // [width][a_width + d_s]: action columns, then state columns
     int nf_trans = 0, nf_obs = 0, nf_lik = 0;
-    int plan_bpc = 1, prop_bpc = 1, obs_bpc = 1, obs_roll_bpc = 1, pw_bpc = 1;
+    int plan_bpc = 1, prop_bpc = 1, obs_bpc = 1, obs_roll_bpc = 1, pw_bpc = 1, nce_bpc = 1;
     bool has_grad = false;
     NetBlob grad_fwd{}, grad_bwd{};
     int grad_bpc = 1, n_params = 0;
@@ -398,6 +400,16 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
         blobs.emplace_back();
         blobs.emplace_back();
     }
+    // the likelihood network with its first layer over the observation
+    // columns (state and action folded per row) for the contrastive objective
+    if (L.present()) {
+        std::vector<float> b0(L.b[0], L.b[0] + W);
+        SlotMap mo{m->d_o, 0, 0, 0, 0, m->d_s + aw};
+        blobs.push_back(pack_net(L, dt, nce_in_slots(shape, dt), mo, b0, 1, m->lik_nce));
+    } else {
+        blobs.emplace_back();
+    }
+    const size_t nb = blobs.size();
     std::vector<std::vector<float>> folds;
     m->nf_trans = aw;
     folds.push_back(fold_columns(T, m->d_s, aw, dt));
@@ -414,7 +426,15 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
         m->nf_lik = aw + m->d_o;
         folds.push_back(fold_columns(L, m->d_s, aw + m->d_o, dt));
         folds.push_back(std::vector<float>(L.b[0], L.b[0] + W));
+        std::vector<float> fa = fold_columns(L, m->d_s, aw, dt), fs = fold_columns(L, 0, m->d_s, dt);
+        std::vector<float> fn((size_t)W * (aw + m->d_s));
+        for (int o = 0; o < W; ++o) {
+            for (int c = 0; c < aw; ++c) fn[(size_t)o * (aw + m->d_s) + c] = fa[(size_t)o * aw + c];
+            for (int c = 0; c < m->d_s; ++c) fn[(size_t)o * (aw + m->d_s) + aw + c] = fs[(size_t)o * m->d_s + c];
+        }
+        folds.push_back(fn);
     } else {
+        folds.emplace_back();
         folds.emplace_back();
         folds.emplace_back();
     }
@@ -448,12 +468,14 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->lik.base = m->mem + offs[3];
     m->grad_fwd.base = m->mem + offs[4];
     m->grad_bwd.base = m->mem + offs[5];
-    m->fold_w_trans = reinterpret_cast<const float*>(m->mem + offs[6]);
-    m->fold_b_trans = reinterpret_cast<const float*>(m->mem + offs[7]);
-    m->fold_w_obs = reinterpret_cast<const float*>(m->mem + offs[8]);
-    m->fold_b_obs = reinterpret_cast<const float*>(m->mem + offs[9]);
-    m->fold_w_lik = reinterpret_cast<const float*>(m->mem + offs[10]);
-    m->fold_b_lik = reinterpret_cast<const float*>(m->mem + offs[11]);
+    m->lik_nce.base = m->mem + offs[6];
+    m->fold_w_trans = reinterpret_cast<const float*>(m->mem + offs[nb + 0]);
+    m->fold_b_trans = reinterpret_cast<const float*>(m->mem + offs[nb + 1]);
+    m->fold_w_obs = reinterpret_cast<const float*>(m->mem + offs[nb + 2]);
+    m->fold_b_obs = reinterpret_cast<const float*>(m->mem + offs[nb + 3]);
+    m->fold_w_lik = reinterpret_cast<const float*>(m->mem + offs[nb + 4]);
+    m->fold_b_lik = reinterpret_cast<const float*>(m->mem + offs[nb + 5]);
+    m->fold_w_nce = reinterpret_cast<const float*>(m->mem + offs[nb + 6]);
 
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->cus = prop.multiProcessorCount;
@@ -462,6 +484,7 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->obs_bpc = observe_blocks_per_cu(shape, dt);
     m->obs_roll_bpc = observe_rollout_blocks_per_cu(shape, dt);
     m->pw_bpc = pw_lik_blocks_per_cu(shape, dt);
+    m->nce_bpc = nce_scores_blocks_per_cu(shape, dt);
     if (m->has_grad) m->grad_bpc = grad_blocks_per_cu(shape, grad_lds_bytes(m));
     *out = m;
     return VOILA_OK;
@@ -1028,6 +1051,84 @@ voila_status_t voila_pw_step(voila_model_t m, const float* d_succ, int32_t T, co
     VOILA_CHECK_HIP(launch_pw_lik(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));
     // 4. per-group weights and systematic resampling
     VOILA_CHECK_HIP(launch_pw_norm_res(p, M < m->cus ? M : m->cus, s));
+    return VOILA_OK;
+}
+
+namespace {
+struct NceWs {
+    float* b0;
+    float* scores;
+    double* row_loss;
+    size_t bytes;
+};
+NceWs carve_nce(char* base, voila_model_t m, int B) {
+    NceWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + off;
+        off = align_up(off + bytes, 256);
+        return p;
+    };
+    w.b0 = reinterpret_cast<float*>(take((size_t)B * m->width * 4));
+    w.scores = reinterpret_cast<float*>(take((size_t)B * B * 4));
+    w.row_loss = reinterpret_cast<double*>(take((size_t)B * 8));
+    w.bytes = off;
+    return w;
+}
+}  // namespace
+
+size_t voila_info_nce_workspace_size(voila_model_t m, int32_t B) {
+    if (!m || B < 1 || B > kNceMaxBatch) return 0;
+    return carve_nce(nullptr, m, B).bytes;
+}
+
+voila_status_t voila_info_nce(voila_model_t m, const float* d_states, const void* d_actions, const float* d_obs,
+                              int32_t B, void* ws, size_t ws_bytes, float* d_scores_out, double* d_row_loss_out,
+                              float* d_grad_out, double* d_loss_out, int32_t* d_status, void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model has no likelihood network");
+    if (B < 1) return fail(VOILA_ERR_INVALID_ARG, "B must be >= 1");
+    if (B > kNceMaxBatch) return fail(VOILA_ERR_UNSUPPORTED, "B must be <= 32768");
+    if (!d_states || !d_actions || !d_obs) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    NceWs w = carve_nce(reinterpret_cast<char*>(ws), m, B);
+    if (!ws || ws_bytes < w.bytes) return fail(VOILA_ERR_WORKSPACE, "contrastive-objective workspace too small");
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // 1. row i's state and action folded into its first-layer bias row
+    FoldStepsParams f{};
+    f.w = m->fold_w_nce;
+    f.b = m->fold_b_lik;
+    f.out = w.b0;
+    f.cands = d_actions;
+    f.obs = d_states;
+    f.width = m->width;
+    f.nf = m->action_width() + m->d_s;
+    f.rows = B;
+    f.n_actions = m->n_actions;
+    f.d_a = m->d_a;
+    f.d_o = m->d_s;
+    f.bf16 = m->dt == DT_BF16 ? 1 : 0;
+    f.status = d_status;
+    VOILA_CHECK_HIP(launch_fold_steps(f, s));
+    // 2. scores of all pairs, 3. per-row losses and derivatives, 4. the mean
+    NceParams p{};
+    p.lik = m->lik_nce;
+    p.obs = d_obs;
+    p.b0 = w.b0;
+    p.scores = d_scores_out ? d_scores_out : w.scores;
+    p.row_loss = d_row_loss_out ? d_row_loss_out : w.row_loss;
+    p.grad = d_grad_out;
+    p.loss = d_loss_out;
+    p.status = d_status;
+    p.B = B;
+    p.d_o = m->d_o;
+    const long units = (long)B * ((B + 31) / 32);
+    const long want = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+    const long cap = (long)m->cus * m->nce_bpc;
+    VOILA_CHECK_HIP(launch_nce_scores(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));
+    VOILA_CHECK_HIP(launch_nce_rows(p, B < 8 * m->cus ? B : 8 * m->cus, s));
+    VOILA_CHECK_HIP(launch_nce_mean(p, s));
     return VOILA_OK;
 }
 

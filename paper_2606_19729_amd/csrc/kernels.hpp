@@ -28,6 +28,7 @@ int plan_in_slots(int shape, int dt);     // transition net in plan: state + con
 int update_in_slots(int shape, int dt);   // transition net in update: state + noise (action folded)
 int obs_in_slots(int shape, int dt);      // observation net: state + obs noise (action folded)
 int lik_in_slots(int shape, int dt);      // likelihood net: state (action, observation folded)
+int nce_in_slots(int shape, int dt);      // likelihood net: observation (state, action folded)
 
 struct PlanParams {
     NetBlob net;
@@ -168,6 +169,20 @@ struct PwParams {
     uint32_t key0, key1;
 };
 
+// Contrastive objective of the likelihood network over a mini-batch of B
+// tuples (s'_i, a_i, o_i): scores l_ij = l([s'_i, a_i, o_j]) of all pairs.
+struct NceParams {
+    NetBlob lik;          // likelihood network packed with its first layer over the observation columns
+    const float* obs;     // [B][d_o]
+    const float* b0;      // [B][width] first-layer biases with row i's state and action folded in
+    float* scores;        // [B][B] l_ij, row i = state-action i
+    double* row_loss;     // [B] log sum_j exp(l_ij) - l_ii
+    float* grad;          // [B][B] derivative of the mean row loss by l_ij, or NULL
+    double* loss;         // [1] mean row loss, or NULL
+    int32_t* status;      // or NULL
+    int B, d_o;
+};
+
 struct NormResParams {
     const double* x;         // [N] precomputed l / lambda (+ log prior), or NULL
     const float* loglik;     // [N] used when x is NULL and w_in is NULL
@@ -305,6 +320,13 @@ hipError_t launch_pw_tiles(const PwParams& p, hipStream_t s);
 hipError_t launch_pw_lik(int shape, int dt, const PwParams& p, int blocks, hipStream_t s);
 int pw_lik_blocks_per_cu(int shape, int dt);
 hipError_t launch_pw_norm_res(const PwParams& p, int blocks, hipStream_t s);
+// Contrastive-objective stages: all-pairs scores, per-row losses and
+// derivatives (one workgroup per row), the mean loss (one workgroup).
+hipError_t launch_nce_scores(int shape, int dt, const NceParams& p, int blocks, hipStream_t s);
+int nce_scores_blocks_per_cu(int shape, int dt);
+hipError_t launch_nce_rows(const NceParams& p, int blocks, hipStream_t s);
+hipError_t launch_nce_mean(const NceParams& p, hipStream_t s);
+constexpr int kNceMaxBatch = 32768;  // B <= this (the score matrix holds B^2 binary32 values)
 constexpr int kPwMaxGroup = 8192;  // successors per group (one workgroup normalises and resamples a group)
 hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
 hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);

@@ -106,3 +106,6 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert L.voila_plan_closed_loop(None, None, 1, None, 1, None, 1, 1, None, None, 0, None, None, None, None, None,
                                     None, None, None, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_plan_closed_loop_workspace_size(None, 10, 2, 2, 4, 3) == 0
+    assert L.voila_info_nce(None, None, None, None, 4, None, 0, None, None, None, None, None, None) == \
+        V.VOILA_ERR_INVALID_ARG
+    assert L.voila_info_nce_workspace_size(None, 4) == 0
