@@ -41,6 +41,12 @@
  *             Eq. 6): scores of all B x B state-action / observation pairs of
  *             a mini-batch, per-row log-sum-exp losses, their mean and its
  *             derivative with respect to every score.
+ *   ddim      The teacher sampler of the transition model (Sec. 4.2): the
+ *             deterministic DDIM sampler (Song, Meng, Ermon, "Denoising
+ *             diffusion implicit models", ICLR 2021) of a v-prediction
+ *             denoiser (Salimans and Ho, "Progressive distillation for fast
+ *             sampling of diffusion models", ICLR 2022) under the cosine
+ *             schedule, from the latent noise at tau = 1 to a next state.
  *   plan_steps  The states of the plan rollouts and an observation drawn
  *             from f_Z at every step (Sec. 4.3 forward-simulates with both
  *             learned samplers).
@@ -1199,4 +1205,109 @@ int or_info_nce(const or_model* m0, int B, const double* S, const int32_t* a_dis
         *loss = (sum + comp) / (double)B;
     }
     return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Teacher sampler of the transition model (Sec. 4.2): the deterministic     */
+/* (ODE) DDIM sampler of a v-prediction denoiser under the cosine schedule.  */
+/* ------------------------------------------------------------------------- */
+/* Cosine cumulative schedule (Nichol and Dhariwal, "Improved denoising
+ * diffusion probabilistic models", 2021) with offset 0.008, normalised so
+ * that abar(0) = 1:  abar(tau) = cos^2(pi/2 (tau + s)/(1 + s)) / cos^2(pi/2 s/(1 + s)).
+ * At tau = 1 the numerator's angle is pi/2 and abar is 0 up to rounding; it
+ * is clamped to [0, 1]. */
+double or_cosine_abar(double tau)
+{
+    const double s = 0.008, h = 1.5707963267948966;
+    double c = cos(h * (tau + s) / (1.0 + s)), c0 = cos(h * s / (1.0 + s));
+    double a = (c * c) / (c0 * c0);
+    return a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+}
+
+typedef void (*or_vfun)(const void* ctx, const double* s, const double* x, double tau, double* v);
+
+/* The ODE sampler from x at tau = 1 (the latent noise) to tau = 0 in n
+ * uniform steps tau_k = 1 - k/n.  With a = abar(tau_k), a' = abar(tau_{k+1})
+ * and the predicted v at (x, tau_k), the clean-sample and noise estimates of
+ * v-prediction are x0 = sqrt(a) x - sqrt(1-a) v and eps = sqrt(1-a) x +
+ * sqrt(a) v, and the step re-noises x0 with eps to the next time:
+ * x <- sqrt(a') x0 + sqrt(1-a') eps. */
+static void ddim_run(int d, const double* s, double* x, int n_steps, or_vfun vf, const void* ctx)
+{
+    double v[OR_MAX_WIDTH];
+    for (int k = 0; k < n_steps; ++k) {
+        const double tau = 1.0 - (double)k / n_steps, tau_next = 1.0 - (double)(k + 1) / n_steps;
+        const double a = or_cosine_abar(tau), an = or_cosine_abar(tau_next);
+        vf(ctx, s, x, tau, v);
+        for (int c = 0; c < d; ++c) {
+            double x0 = sqrt(a) * x[c] - sqrt(1.0 - a) * v[c];
+            double eps = sqrt(1.0 - a) * x[c] + sqrt(a) * v[c];
+            x[c] = sqrt(an) * x0 + sqrt(1.0 - an) * eps;
+        }
+    }
+}
+
+typedef struct {
+    int n_layers; const int* dims; const double* params;
+    int d_s, n_actions, d_a, a_disc; const double* a_cont; int bf16;
+} ddim_net_ctx;
+
+/* v = denoiser([s, a, x, tau]) (a one-hot over n_actions, or continuous). */
+static void ddim_net_v(const void* cp, const double* s, const double* x, double tau, double* v)
+{
+    const ddim_net_ctx* c = (const ddim_net_ctx*)cp;
+    double in[OR_MAX_WIDTH];
+    const int aw = c->n_actions > 0 ? c->n_actions : c->d_a;
+    for (int j = 0; j < c->d_s; ++j) in[j] = s[j];
+    for (int j = 0; j < aw; ++j) in[c->d_s + j] = c->n_actions > 0 ? (j == c->a_disc ? 1.0 : 0.0) : c->a_cont[j];
+    for (int j = 0; j < c->d_s; ++j) in[c->d_s + aw + j] = x[j];
+    in[2 * c->d_s + aw] = tau;
+    mlp_forward(c->n_layers, c->dims, c->params, in, v, c->bf16);
+}
+
+/* Teacher samples of n rows: X1 [n][d_s] the latent noise at tau = 1,
+ * S [n][d_s] the conditioning states, one action for all rows, a denoiser
+ * with input [s, a, x_tau, tau] and output v [d_s].  Out [n][d_s]. */
+int or_ddim_sample(int n_layers, const int* dims, const double* params, int d_s, int n_actions, int d_a,
+                   int n, const double* S, int a_disc, const double* a_cont, const double* X1, int n_steps,
+                   int bf16, double* out)
+{
+    const int aw = n_actions > 0 ? n_actions : d_a;
+    if (mlp_check(n_layers, dims) != OR_OK || n < 0 || n_steps < 1 || d_s < 1) return OR_ERR_ARG;
+    if (dims[0] != 2 * d_s + aw + 1 || dims[n_layers] != d_s) return OR_ERR_ARG;
+    if (n_actions > 0 ? (a_disc < 0 || a_disc >= n_actions) : !a_cont) return OR_ERR_ARG;
+    double* rw = bf16 ? round_weights(n_layers, dims, params) : NULL;
+    if (bf16 && !rw) return OR_ERR_ARG;
+    ddim_net_ctx c = {n_layers, dims, bf16 ? rw : params, d_s, n_actions, d_a, a_disc, a_cont, bf16};
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < n; ++r) {
+        double x[OR_MAX_WIDTH];
+        for (int j = 0; j < d_s; ++j) x[j] = X1[(size_t)r * d_s + j];
+        ddim_run(d_s, S + (size_t)r * d_s, x, n_steps, ddim_net_v, &c);
+        for (int j = 0; j < d_s; ++j) out[(size_t)r * d_s + j] = x[j];
+    }
+    free(rw);
+    return OR_OK;
+}
+
+/* The same sampler driven by the exact v of a point-mass data distribution
+ * at x0 (the conditioning input s is taken as x0): with a = abar(tau),
+ * eps = (x - sqrt(a) x0) / sqrt(1 - a) and v = sqrt(a) eps - sqrt(1 - a) x0.
+ * For tau = 1 (a = 0) eps = x.  Test hook of the step arithmetic. */
+static void ddim_point_v(const void* cp, const double* s, const double* x, double tau, double* v)
+{
+    const int d = *(const int*)cp;
+    const double a = or_cosine_abar(tau);
+    for (int j = 0; j < d; ++j) {
+        double eps = a > 0.0 ? (x[j] - sqrt(a) * s[j]) / sqrt(1.0 - a) : x[j];
+        v[j] = sqrt(a) * eps - sqrt(1.0 - a) * s[j];
+    }
+}
+
+int or_ddim_point_mass(int d, const double* x0, const double* x1, int n_steps, double* out)
+{
+    if (d < 1 || d > OR_MAX_WIDTH || n_steps < 1) return OR_ERR_ARG;
+    for (int j = 0; j < d; ++j) out[j] = x1[j];
+    ddim_run(d, x0, out, n_steps, ddim_point_v, &d);
+    return OR_OK;
 }
