@@ -374,6 +374,44 @@ def bench_info_nce(V, torch, reps):
     return out
 
 
+def bench_ddim(V, torch, reps):
+    """The teacher sampler the transition generator is distilled from: the
+    paper's 5 x 1024 v-prediction denoiser run for 50 deterministic DDIM
+    steps on 65,536 samples (bfloat16), beside one evaluation of a 4 x 1024
+    network (the paper's distilled sampler shape) through the same kernel --
+    the distilled-versus-diffusion sampling-rate comparison."""
+    import workloads
+    dev = torch.device("cuda", 0)
+    N, steps = 65536, 50
+    S, X1 = (torch.as_tensor(x, device=dev) for x in workloads.ddim_batch(N, seed=23))
+    out = {"samples": N}
+    stream = torch.cuda.current_stream()
+    for name, nh, n_steps in [("teacher_5x1024", 5, steps), ("distilled_4x1024", 4, 1)]:
+        layers = workloads.denoiser(seed=24, width=1024, n_hidden=nh)
+        den = V.Denoiser(layers, 4, 5, 0, compute="bf16")
+        ws = torch.empty(int(V.lib.voila_ddim_workspace_size(den.handle, n_steps)), dtype=torch.uint8, device=dev)
+        res = torch.empty((N, 4), dtype=torch.float32, device=dev)
+        ms = []
+        for r in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            V.ddim_sample(den, S, 2, X1, n_steps, out=res, workspace=ws)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                ms.append(a.elapsed_time(b))
+        t = float(np.median(ms))
+        # executed flop per network evaluation: the first layer over the 8
+        # slot inputs (x_tau, s; action and tau folded per step)
+        dims = [8] + [int(W.shape[0]) for W, _ in layers]
+        f_eval = 2 * sum(x * y for x, y in zip(dims[:-1], dims[1:]))
+        out[name] = {"steps": n_steps, "ms": t, "samples_per_s": N / (t / 1e3),
+                     "mfma_frac": f_eval * N * n_steps / (t / 1e3) / 1e12 / PEAK_BF16_TFLOPS}
+        print(f"[bench]   {name}: {t:.3f} ms", file=sys.stderr, flush=True)
+    out["distilled_over_teacher"] = out["distilled_4x1024"]["samples_per_s"] / out["teacher_5x1024"]["samples_per_s"]
+    return out
+
+
 def bench_tree(V, torch, reps):
     """One-level closed-loop tree with the realistic networks: 1,024 particles,
     8 continuous first actions x 4 observation branches, 128 continuation
@@ -691,6 +729,8 @@ def main():
         result["pw_step"] = bench_pw(V, torch, max(3, args.steps))
         print("[bench] contrastive likelihood objective", file=sys.stderr, flush=True)
         result["info_nce"] = bench_info_nce(V, torch, max(3, args.steps))
+        print("[bench] DDIM teacher sampler vs one distilled-sampler evaluation", file=sys.stderr, flush=True)
+        result["ddim"] = bench_ddim(V, torch, max(2, args.steps // 2))
         print("[bench] one-level closed-loop tree", file=sys.stderr, flush=True)
         result["closed_loop_tree"] = bench_tree(V, torch, max(2, args.steps // 2))
         print("[bench] belief-update sweep", file=sys.stderr, flush=True)

@@ -162,6 +162,14 @@ def _load():
     L.voila_info_nce_workspace_size.restype = c_size_t
     L.voila_info_nce.argtypes = [vp, vp, vp, vp, c_int32, vp, c_size_t, vp, vp, vp, vp, vp, vp]
     L.voila_info_nce.restype = c_int32
+    L.voila_denoiser_create.argtypes = [POINTER(_Mlp), c_int32, c_int32, c_int32, c_int32, c_int32, POINTER(vp)]
+    L.voila_denoiser_create.restype = c_int32
+    L.voila_denoiser_destroy.argtypes = [vp]
+    L.voila_denoiser_destroy.restype = c_int32
+    L.voila_ddim_workspace_size.argtypes = [vp, c_int32]
+    L.voila_ddim_workspace_size.restype = c_size_t
+    L.voila_ddim_sample.argtypes = [vp, vp, vp, vp, c_int32, c_int32, vp, c_size_t, vp, vp]
+    L.voila_ddim_sample.restype = c_int32
     L.voila_philox_normals.argtypes = [c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int32, c_int32, vp,
                                        vp, vp]
     L.voila_philox_normals.restype = c_int32
@@ -195,7 +203,8 @@ EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_m
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_plan_observe_workspace_size",
             "voila_plan_observe", "voila_pw_step_workspace_size", "voila_pw_step", "voila_soft_value",
             "voila_plan_closed_loop_workspace_size", "voila_plan_closed_loop",
-            "voila_info_nce_workspace_size", "voila_info_nce",
+            "voila_info_nce_workspace_size", "voila_info_nce", "voila_denoiser_create", "voila_denoiser_destroy",
+            "voila_ddim_workspace_size", "voila_ddim_sample",
             "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
             "voila_batch_replay", "voila_grad_param_count", "voila_rollout_grad_workspace_size",
@@ -240,6 +249,77 @@ def max_update_particles() -> int:
     return lib.voila_update_max_particles()
 
 
+def _mlp_desc(layers, keep):
+    """_Mlp view of [(W [out, in], b [out]), ...] (arrays kept alive in `keep`)."""
+    import numpy as np
+    m = _Mlp()
+    if not layers:
+        m.n_layers = 0
+        return m
+    dims = [int(layers[0][0].shape[1])] + [int(W.shape[0]) for W, _ in layers]
+    dims_arr = (c_int32 * len(dims))(*dims)
+    Ws = [np.ascontiguousarray(np.asarray(W, np.float32)) for W, _ in layers]
+    bs = [np.ascontiguousarray(np.asarray(b, np.float32)) for _, b in layers]
+    W_arr = (POINTER(c_float) * len(Ws))(*[w.ctypes.data_as(POINTER(c_float)) for w in Ws])
+    b_arr = (POINTER(c_float) * len(bs))(*[b.ctypes.data_as(POINTER(c_float)) for b in bs])
+    keep.extend([dims_arr, Ws, bs, W_arr, b_arr])
+    m.n_layers = len(layers)
+    m.h_dims = dims_arr
+    m.h_W = W_arr
+    m.h_b = b_arr
+    return m
+
+
+class Denoiser:
+    """Packed device copy of a v-prediction transition denoiser (layers
+    [(W, b), ...] with input [s, a, x_tau, tau] and output v [d_s])."""
+
+    def __init__(self, layers, d_s: int, n_actions: int, d_a: int = 0, compute: str = "bf16", device: int = 0):
+        self.d_s, self.n_actions, self.d_a = int(d_s), int(n_actions), int(d_a)
+        self.compute = compute
+        self.device = device
+        self.handle = c_void_p()
+        keep = []
+        desc = _mlp_desc(layers, keep)
+        _check(lib.voila_denoiser_create(ctypes.byref(desc), self.d_s, self.n_actions, self.d_a,
+                                         {"f32": VOILA_F32, "bf16": VOILA_BF16}[compute], int(device),
+                                         ctypes.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            lib.voila_denoiser_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ddim_sample(den: Denoiser, states, action, x1, n_steps, out=None, workspace=None, stream=None):
+    """Teacher samples [N, d_s] float32: n_steps deterministic DDIM steps of
+    the denoiser from x1 [N, d_s] (the latent noise at tau = 1) conditioned
+    on states [N, d_s] and one action (index, or d_a values)."""
+    N = int(states.shape[0])
+    _dev(states, torch.float32, (N, den.d_s), "states")
+    _dev(x1, torch.float32, (N, den.d_s), "x1")
+    if den.n_actions > 0:
+        h_action = (c_int32 * 1)(int(action))
+    else:
+        vals = [float(x) for x in (action.tolist() if hasattr(action, "tolist") else action)]
+        if len(vals) != den.d_a:
+            raise VoilaError(VOILA_ERR_INVALID_ARG, f"continuous action must have {den.d_a} values")
+        h_action = (c_float * den.d_a)(*vals)
+    res = out if out is not None else torch.empty((N, den.d_s), dtype=torch.float32, device=states.device)
+    if workspace is None:
+        n = lib.voila_ddim_workspace_size(den.handle, int(n_steps))
+        workspace = torch.empty(max(int(n), 1), dtype=torch.uint8, device=states.device)
+    _check(lib.voila_ddim_sample(den.handle, _ptr(states), h_action, _ptr(x1), N, int(n_steps), _ptr(workspace),
+                                 workspace.numel(), _ptr(res), _stream(stream)))
+    return res
+
+
 class Model:
     """Packed device copy of the transition / observation / likelihood networks.
 
@@ -256,22 +336,7 @@ class Model:
         keep = []
 
         def mlp(layers):
-            m = _Mlp()
-            if not layers:
-                m.n_layers = 0
-                return m
-            dims = [int(layers[0][0].shape[1])] + [int(W.shape[0]) for W, _ in layers]
-            dims_arr = (c_int32 * len(dims))(*dims)
-            Ws = [np.ascontiguousarray(np.asarray(W, np.float32)) for W, _ in layers]
-            bs = [np.ascontiguousarray(np.asarray(b, np.float32)) for _, b in layers]
-            W_arr = (POINTER(c_float) * len(Ws))(*[w.ctypes.data_as(POINTER(c_float)) for w in Ws])
-            b_arr = (POINTER(c_float) * len(bs))(*[b.ctypes.data_as(POINTER(c_float)) for b in bs])
-            keep.extend([dims_arr, Ws, bs, W_arr, b_arr])
-            m.n_layers = len(layers)
-            m.h_dims = dims_arr
-            m.h_W = W_arr
-            m.h_b = b_arr
-            return m
+            return _mlp_desc(layers, keep)
 
         d = _ModelDesc()
         d.d_s, d.n_actions, d.d_a = desc.d_s, desc.n_actions, desc.d_a

@@ -95,8 +95,9 @@ int row_feature(int r) {
 // kernels consume them, then the biases.  b0_variants holds n_var rows of
 // `width` first-layer biases.
 std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, const SlotMap& map,
-                           const std::vector<float>& b0_variants, int n_var, NetBlob& nb) {
+                           const std::vector<float>& b0_variants, int n_var, NetBlob& nb, bool layered = false) {
     const int W = n.width(), HT = W / 32, NHID = n.n_layers - 1, KP = kper(dt);
+    const int CT = layered ? HT : chunk_tiles(W);
     const int esz = dt == DT_F32 ? 4 : 2;
     const size_t fb = (size_t)64 * KP * esz;
     const int IN_KS = in_slots_per_group / KP, HID_KS = 16 * HT / KP;
@@ -107,7 +108,7 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
     // networks streamed whole through LDS chunk buffers are padded to whole chunks
     const size_t nfr = nf0 + (size_t)(NHID - 1) * nfh + nfo;
     const size_t fpc = VOILA_STREAM_CHB / fb;
-    const size_t pad = (W > 64 && chunk_tiles(W) == HT) ? (nfr + fpc - 1) / fpc * fpc - nfr : 0;
+    const size_t pad = (W > 64 && CT == HT) ? (nfr + fpc - 1) / fpc * fpc - nfr : 0;
     const size_t off_b0 = align_up(off_fo + (nfo + pad) * fb, 16);
     const size_t off_bh = align_up(off_b0 + (size_t)n_var * W * 4, 16);
     const size_t off_bo = align_up(off_bh + (size_t)(NHID - 1) * W * 4, 16);
@@ -125,7 +126,7 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
     };
     auto hidden_in = [](int ri, int g) { return 32 * (ri / 16) + out_row(ri % 16, g); };
     // every fragment goes to its position in the consumption order (FragLayout)
-    const FragLayout lay{HT, IN_KS, HID_KS, chunk_tiles(W), NHID};
+    const FragLayout lay{HT, IN_KS, HID_KS, CT, NHID};
     for (int c = 0; c < IN_KS; ++c)
         for (int t = 0; t < HT; ++t)
             for (int lane = 0; lane < 64; ++lane)
@@ -1129,6 +1130,149 @@ voila_status_t voila_info_nce(voila_model_t m, const float* d_states, const void
     VOILA_CHECK_HIP(launch_nce_scores(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));
     VOILA_CHECK_HIP(launch_nce_rows(p, B < 8 * m->cus ? B : 8 * m->cus, s));
     VOILA_CHECK_HIP(launch_nce_mean(p, s));
+    return VOILA_OK;
+}
+
+struct voila_denoiser_s {
+    int device = 0, shape = -1, dt = DT_F32, cus = 1, bpc = 1;
+    int d_s = 0, n_actions = 0, d_a = 0, width = 0;
+    char* mem = nullptr;
+    NetBlob net{};
+    const float* fold_w = nullptr;  // [width][a_width + 1]
+    const float* fold_b = nullptr;  // [width]
+    int action_width() const { return n_actions > 0 ? n_actions : d_a; }
+};
+
+voila_status_t voila_denoiser_create(const voila_mlp_desc_t* net, int32_t d_s, int32_t n_actions, int32_t d_a,
+                                     int32_t compute, int32_t device, voila_denoiser_t* out) {
+    if (!net || !out) return fail(VOILA_ERR_INVALID_ARG, "NULL descriptor or output handle");
+    *out = nullptr;
+    if (compute != VOILA_F32 && compute != VOILA_BF16)
+        return fail(VOILA_ERR_INVALID_ARG, "compute must be VOILA_F32 or VOILA_BF16");
+    if (d_s < 1 || n_actions < 0 || d_a < 0 || (n_actions == 0 && d_a < 1))
+        return fail(VOILA_ERR_INVALID_ARG, "bad state or action dimension");
+    const int aw = n_actions > 0 ? n_actions : d_a;
+    if (aw > 63) return fail(VOILA_ERR_UNSUPPORTED, "at most 63 action inputs");
+    HostNet D;
+    voila_status_t st;
+    if ((st = read_net(*net, D, "denoiser")) != VOILA_OK) return st;
+    if (!D.present()) return fail(VOILA_ERR_INVALID_ARG, "the denoiser network is required");
+    if (D.dims[0] != 2 * d_s + aw + 1 || D.out() != d_s)
+        return fail(VOILA_ERR_INVALID_ARG, "denoiser dims must be [2 d_s + a_width + 1, ..., d_s]");
+    const int shape = ddim_shape(d_s, D.width(), D.n_layers - 1);
+    if (shape < 0) return fail(VOILA_ERR_UNSUPPORTED, "no compiled sampler kernel for this denoiser shape");
+    if (D.width() > 256 && compute != VOILA_BF16)
+        return fail(VOILA_ERR_UNSUPPORTED, "hidden widths above 256 run in bfloat16 only");
+    int ndev = 0;
+    VOILA_CHECK_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(VOILA_ERR_INVALID_ARG, "device index out of range");
+    DeviceGuard guard(device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    voila_denoiser_s* m = new voila_denoiser_s();
+    m->device = device;
+    m->shape = shape;
+    m->dt = compute;
+    m->d_s = d_s;
+    m->n_actions = n_actions;
+    m->d_a = n_actions > 0 ? 0 : d_a;
+    m->width = D.width();
+    const int W = m->width, dt = m->dt;
+    // input [s, a, x_tau, tau]: x_tau in the state slots, s in the noise slots
+    SlotMap map{d_s, 0, d_s, d_s, 0, d_s + aw};
+    std::vector<float> b0(D.b[0], D.b[0] + W);
+    std::vector<char> blob = pack_net(D, dt, ddim_in_slots(shape, dt), map, b0, 1, m->net, ddim_split(shape));
+    std::vector<float> fa = fold_columns(D, d_s, aw, dt), ft = fold_columns(D, 2 * d_s + aw, 1, dt);
+    std::vector<float> fw((size_t)W * (aw + 1));
+    for (int o = 0; o < W; ++o) {
+        for (int c = 0; c < aw; ++c) fw[(size_t)o * (aw + 1) + c] = fa[(size_t)o * aw + c];
+        fw[(size_t)o * (aw + 1) + aw] = ft[o];
+    }
+    const size_t off_w = align_up(blob.size(), 256), off_b = align_up(off_w + fw.size() * 4, 256);
+    const size_t total = align_up(off_b + (size_t)W * 4, 256);
+    std::vector<char> host(total, 0);
+    std::memcpy(host.data(), blob.data(), blob.size());
+    std::memcpy(host.data() + off_w, fw.data(), fw.size() * 4);
+    std::memcpy(host.data() + off_b, D.b[0], (size_t)W * 4);
+    if (hipMalloc(&m->mem, total) != hipSuccess) {
+        delete m;
+        return fail(VOILA_ERR_DEVICE, "hipMalloc of the packed denoiser failed");
+    }
+    if (hipMemcpy(m->mem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(m->mem);
+        delete m;
+        return fail(VOILA_ERR_DEVICE, "upload of the packed denoiser failed");
+    }
+    m->net.base = m->mem;
+    m->fold_w = reinterpret_cast<const float*>(m->mem + off_w);
+    m->fold_b = reinterpret_cast<const float*>(m->mem + off_b);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->cus = prop.multiProcessorCount;
+    m->bpc = ddim_blocks_per_cu(shape, dt);
+    *out = m;
+    return VOILA_OK;
+}
+
+voila_status_t voila_denoiser_destroy(voila_denoiser_t m) {
+    if (!m) return VOILA_OK;
+    DeviceGuard guard(m->device);
+    if (m->mem) (void)hipFree(m->mem);
+    delete m;
+    return VOILA_OK;
+}
+
+size_t voila_ddim_workspace_size(voila_denoiser_t m, int32_t n_steps) {
+    if (!m || n_steps < 1 || n_steps > kDdimMaxSteps) return 0;
+    return align_up((size_t)n_steps * m->width * 4, 256) + align_up((size_t)n_steps * 2 * 4, 256);
+}
+
+voila_status_t voila_ddim_sample(voila_denoiser_t m, const float* d_states, const void* h_action, const float* d_x1,
+                                 int32_t N, int32_t n_steps, void* ws, size_t ws_bytes, float* d_out, void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL denoiser");
+    if (N < 0) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 0");
+    if (n_steps < 1 || n_steps > kDdimMaxSteps) return fail(VOILA_ERR_INVALID_ARG, "n_steps must be in [1, 4096]");
+    if (!h_action) return fail(VOILA_ERR_INVALID_ARG, "NULL action");
+    DdimPrepParams pp{};
+    if (m->n_actions > 0) {
+        const int a = *reinterpret_cast<const int32_t*>(h_action);
+        if (a < 0 || a >= m->n_actions) return fail(VOILA_ERR_INVALID_ARG, "action index out of range");
+        for (int j = 0; j < m->n_actions; ++j) pp.v[j] = j == a ? 1.0f : 0.0f;
+    } else {
+        const float* a = reinterpret_cast<const float*>(h_action);
+        for (int j = 0; j < m->d_a; ++j) {
+            if (!std::isfinite(a[j])) return fail(VOILA_ERR_INVALID_ARG, "non-finite action");
+            pp.v[j] = m->dt == DT_BF16 ? bf16_round(a[j]) : a[j];
+        }
+    }
+    if (N == 0) return VOILA_OK;
+    if (!d_states || !d_x1 || !d_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    const size_t need = voila_ddim_workspace_size(m, n_steps);
+    if (!ws || ws_bytes < need) return fail(VOILA_ERR_WORKSPACE, "sampler workspace too small");
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* base = reinterpret_cast<char*>(ws);
+    pp.w = m->fold_w;
+    pp.b = m->fold_b;
+    pp.b0 = reinterpret_cast<float*>(base);
+    pp.coef = reinterpret_cast<float*>(base + align_up((size_t)n_steps * m->width * 4, 256));
+    pp.width = m->width;
+    pp.aw = m->action_width();
+    pp.n_steps = n_steps;
+    pp.bf16 = m->dt == DT_BF16 ? 1 : 0;
+    VOILA_CHECK_HIP(launch_ddim_prep(pp, s));
+    DdimParams p{};
+    p.net = m->net;
+    p.states = d_states;
+    p.x1 = d_x1;
+    p.b0 = pp.b0;
+    p.coef = pp.coef;
+    p.out = d_out;
+    p.N = N;
+    p.n_steps = n_steps;
+    const long tiles = ((long)N + 31) / 32;
+    const long want = ddim_split(m->shape) ? tiles : (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const long cap = (long)m->cus * m->bpc;
+    VOILA_CHECK_HIP(launch_ddim(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));
     return VOILA_OK;
 }
 

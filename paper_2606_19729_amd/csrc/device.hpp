@@ -116,8 +116,10 @@ struct FragLayout {
 // Output tiles produced per group by the grouped evaluation of wide networks.
 __host__ __device__ constexpr int chunk_tiles(int width) { return width > 256 ? 4 : width / 32; }
 
-// Compile-time shape of one network as the engine runs it.
-template <int DT_, int WIDTH_, int NHID_, int IN_SLOTS_>
+// Compile-time shape of one network as the engine runs it.  CT_ = WIDTH_/32
+// packs a wide network layer by layer (for the split evaluation) instead of
+// in the groups of the grouped evaluation.
+template <int DT_, int WIDTH_, int NHID_, int IN_SLOTS_, int CT_ = chunk_tiles(WIDTH_)>
 struct Net {
     static constexpr int DT = DT_;
     static constexpr int WIDTH = WIDTH_;           // hidden width (multiple of 32)
@@ -131,7 +133,7 @@ struct Net {
     static constexpr int NF0 = IN_KS * HT;         // first-layer fragments
     static constexpr int NFH = HID_KS * HT;        // fragments per hidden->hidden layer
     static constexpr int NFO = HID_KS;             // output-layer fragments
-    static constexpr int CT = chunk_tiles(WIDTH);  // tiles per group of the grouped evaluation
+    static constexpr int CT = CT_;                 // tiles per group of the grouped evaluation
     static constexpr int OKS = HID_KS / HT;        // output k-steps per hidden tile
     static_assert(WIDTH % 32 == 0 && NHID >= 1 && IN_SLOTS % KPER == 0, "bad net shape");
     static_assert(CT == HT || (NHID == 2 && HT % CT == 0), "grouped evaluation needs two hidden layers");
@@ -813,7 +815,9 @@ __device__ __forceinline__ f32x16 run_net_split(const NetPtrs& P, const float* b
                                                 int lane, int g, int wave, char* lds) {
     static_assert(N::HT % 4 == 0 && N::CT == N::HT, "split evaluation needs a layered network of 4k tiles");
     constexpr int TPW = N::HT / 4, KQ = N::HID_KS / 4;
-    constexpr int D = N::DT == DT_F32 ? 16 : 8;
+    // k-steps of weight fragments in flight: 32 (binary32) or 16 (bfloat16)
+    // fragment loads over the wave's tiles
+    constexpr int D = (N::DT == DT_F32 ? 32 : 16) / TPW > 0 ? (N::DT == DT_F32 ? 32 : 16) / TPW : 1;
     typedef typename Frag<N::DT>::type FT;
     typedef FragIdx<N> FI;
     const int t0 = wave * TPW;

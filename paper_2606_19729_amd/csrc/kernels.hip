@@ -1233,6 +1233,113 @@ __global__ __launch_bounds__(kNormResThreads) void nce_mean_kernel(NceParams p) 
     if (threadIdx.x == 0) p.loss[0] = s / (double)p.B;
 }
 
+// Cosine cumulative schedule, abar(0) = 1 (offset 0.008), clamped to [0, 1].
+__device__ __forceinline__ double cosine_abar(double tau) {
+    const double s = 0.008, h = 1.5707963267948966;
+    const double c = cos(h * (tau + s) / (1.0 + s)), c0 = cos(h * s / (1.0 + s));
+    const double a = (c * c) / (c0 * c0);
+    return a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+}
+
+// Per-step first-layer biases (the action and tau_k = 1 - k/n folded in) and
+// the step coefficients of the deterministic sampler: with a = abar(tau_k),
+// a' = abar(tau_{k+1}), the v-prediction estimates x0 = sqrt(a) x - sqrt(1-a) v
+// and eps = sqrt(1-a) x + sqrt(a) v re-noised to tau_{k+1} give
+// x' = A x + B v, A = sqrt(a' a) + sqrt((1-a')(1-a)), B = sqrt((1-a') a) - sqrt(a' (1-a)).
+__global__ __launch_bounds__(256) void ddim_prep_kernel(DdimPrepParams p) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int t = blockIdx.y; t < p.n_steps; t += gridDim.y) {
+        const double tau = 1.0 - (double)t / p.n_steps, tau_n = 1.0 - (double)(t + 1) / p.n_steps;
+        if (r < p.width) {
+            float tf = (float)tau;
+            if (p.bf16) tf = (float)(__bf16)tf;
+            const int nf = p.aw + 1;
+            float acc = p.b[r];
+            for (int c = 0; c < p.aw; ++c) acc += p.w[(size_t)r * nf + c] * p.v[c];
+            acc += p.w[(size_t)r * nf + p.aw] * tf;
+            p.b0[(size_t)t * p.width + r] = acc;
+        }
+        if (r == 0) {
+            const double a = cosine_abar(tau), an = cosine_abar(tau_n);
+            p.coef[2 * t] = (float)(sqrt(an * a) + sqrt((1.0 - an) * (1.0 - a)));
+            p.coef[2 * t + 1] = (float)(sqrt((1.0 - an) * a) - sqrt(an * (1.0 - a)));
+        }
+    }
+}
+
+// One 32-sample tile of the teacher sampler: x_tau in the state slots (the
+// output tile's layout, so v updates it in place), the conditioning state in
+// the noise slots, n_steps network evaluations.  Small networks run one tile
+// per wave from LDS; deep wide networks are split over the block's four waves
+// with the activations in LDS and the weights read from L2.
+template <int DT, int D_S, int WIDTH, int NHID, int MODE>
+__global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
+    if constexpr (!net_compiled(DT, WIDTH)) {
+        return;  // binary32 networks wider than 256 are refused at creation
+    } else {
+    constexpr bool SPLIT = MODE == kSplit;
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_S), (SPLIT ? WIDTH / 32 : chunk_tiles(WIDTH))> NT;
+    constexpr int SS = state_slots(D_S), SW = noise_slots(D_S);
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wpb = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n_tiles = (p.N + 31) / 32;
+    const kconst float* coef = (const kconst float*)p.coef;
+    // one tile: returns after writing (by `writer`) the final samples
+    auto run_tile = [&](int tile, bool ok, bool writer, auto&& eval) {
+        const int i = (ok ? tile : 0) * 32 + col;
+        const bool valid = ok && i < p.N;
+        float x[SS], cond[SW];
+#pragma unroll
+        for (int s = 0; s < SS; ++s) {
+            const int f = 2 * s + g;
+            x[s] = (valid && f < D_S) ? p.x1[(size_t)i * D_S + f] : 0.0f;
+        }
+#pragma unroll
+        for (int s = 0; s < SW; ++s) {
+            const int f = noise_feature(s, g);
+            cond[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+        }
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+        for (int t = 0; t < p.n_steps; ++t) {
+            float slots[NT::IN_SLOTS];
+#pragma unroll
+            for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+            for (int s = 0; s < SS; ++s) slots[s] = x[s];
+#pragma unroll
+            for (int s = 0; s < SW; ++s) slots[SS + s] = cond[s];
+            const f32x16 v = eval(p.b0 + (size_t)t * WIDTH, slots);
+            const float A = coef[2 * t], B = coef[2 * t + 1];
+#pragma unroll
+            for (int s = 0; s < SS; ++s) x[s] = __builtin_fmaf(B, v[s], A * x[s]);
+        }
+        if (writer && valid)
+#pragma unroll
+            for (int s = 0; s < SS; ++s)
+                if (2 * s + g < D_S) p.out[(size_t)i * D_S + 2 * s + g] = x[s];
+    };
+    if constexpr (SPLIT) {
+        const NetPtrs P = net_ptrs(p.net.base, p.net);
+        for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+            run_tile(tile, true, wave == 0, [&](const float* b0, const float (&slots)[NT::IN_SLOTS]) {
+                return run_net_split<NT>(P, b0, slots, lane, g, wave, smem);
+            });
+    } else {
+        with_weights<NT, MODE, 1>(smem, p.net, [&](auto& src, const NetPtrs& P) {
+            // block-uniform loop (a streamed network's chunk barriers need every wave)
+            for (long ub = blockIdx.x; ub * wpb < n_tiles; ub += gridDim.x) {
+                const int tile = (int)(ub * wpb + wave);
+                run_tile(tile, tile < n_tiles, true, [&](const float* b0, const float (&slots)[NT::IN_SLOTS]) {
+                    return run_net<NT>(src, P, b0, slots, lane, g);
+                });
+            }
+        });
+    }
+    }
+}
+
 __global__ __launch_bounds__(256) void philox_kernel(PhiloxParams p) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= p.n) return;
@@ -1582,6 +1689,95 @@ hipError_t launch_nce_mean(const NceParams& p, hipStream_t s) {
     if (p.B == 0 || !p.loss) return hipSuccess;
     hipLaunchKernelGGL(nce_mean_kernel, 1, kNormResThreads, 0, s, p);
     return hipGetLastError();
+}
+
+template <int W> constexpr int ddim_mode() { return W <= 64 ? kResident : kSplit; }
+#define DDIM_K(id, ds, w, nh, DT) ddim_kernel<DT, ds, w, nh, ddim_mode<w>()>
+
+int ddim_shape(int d_s, int width, int n_hidden) {
+#define X(id, ds, w, nh) \
+    if (d_s == ds && width == w && n_hidden == nh) return id;
+    VOILA_DDIM_SHAPES(X)
+#undef X
+    return -1;
+}
+int ddim_in_slots(int shape, int dt) {
+    switch (shape) {
+#define X(id, ds, w, nh) \
+    case id:             \
+        return in_slots(dt, ds, 0, ds);
+        VOILA_DDIM_SHAPES(X)
+#undef X
+    }
+    return 0;
+}
+bool ddim_split(int shape) {
+    switch (shape) {
+#define X(id, ds, w, nh) \
+    case id:             \
+        return ddim_mode<w>() == kSplit;
+        VOILA_DDIM_SHAPES(X)
+#undef X
+    }
+    return false;
+}
+
+template <int DT, int D_S, int W, int NH>
+constexpr size_t ddim_split_lds() {
+    if constexpr (!net_compiled(DT, W)) {
+        return 0;
+    } else {
+        return (size_t)SplitLds<Net<DT, W, NH, in_slots(DT, D_S, 0, D_S), W / 32>>::BYTES;
+    }
+}
+
+hipError_t launch_ddim_prep(const DdimPrepParams& p, hipStream_t s) {
+    if (p.n_steps == 0) return hipSuccess;
+    hipLaunchKernelGGL(ddim_prep_kernel, dim3((p.width + 255) / 256, p.n_steps < 65535 ? p.n_steps : 65535), 256,
+                       0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_ddim(int shape, int dt, const DdimParams& p, int blocks, hipStream_t s) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, w, nh)                                                                                 \
+    case id * 2 + 0: {                                                                                  \
+        const size_t lds = ddim_mode<w>() == kSplit ? ddim_split_lds<DT_F32, ds, w, nh>() : p.net.bytes; \
+        if (lds > 65536)                                                                                \
+            (void)hipFuncSetAttribute((const void*)DDIM_K(id, ds, w, nh, DT_F32),                         \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
+        hipLaunchKernelGGL((DDIM_K(id, ds, w, nh, DT_F32)), blocks, 256, lds, s, p);                     \
+        break;                                                                                          \
+    }                                                                                                   \
+    case id * 2 + 1: {                                                                                  \
+        const size_t lds = ddim_mode<w>() == kSplit ? ddim_split_lds<DT_BF16, ds, w, nh>() : p.net.bytes; \
+        if (lds > 65536)                                                                                \
+            (void)hipFuncSetAttribute((const void*)DDIM_K(id, ds, w, nh, DT_BF16),                        \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
+        hipLaunchKernelGGL((DDIM_K(id, ds, w, nh, DT_BF16)), blocks, 256, lds, s, p);                    \
+        break;                                                                                          \
+    }
+        VOILA_DDIM_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int ddim_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, w, nh)                                                                                    \
+    case id * 2 + 0:                                                                                       \
+        return occupancy(DDIM_K(id, ds, w, nh, DT_F32),                                                    \
+                         ddim_mode<w>() == kSplit ? ddim_split_lds<DT_F32, ds, w, nh>() : kLdsGuess);      \
+    case id * 2 + 1:                                                                                       \
+        return occupancy(DDIM_K(id, ds, w, nh, DT_BF16),                                                   \
+                         ddim_mode<w>() == kSplit ? ddim_split_lds<DT_BF16, ds, w, nh>() : kLdsGuess);
+        VOILA_DDIM_SHAPES(X)
+#undef X
+    }
+    return 1;
 }
 
 int observe_rollout_blocks_per_cu(int shape, int dt) {

@@ -183,6 +183,26 @@ struct NceParams {
     int B, d_o;
 };
 
+// Teacher sampler of a v-prediction transition denoiser (input [s, a,
+// x_tau, tau], output v): n_steps deterministic DDIM steps per sample.
+struct DdimParams {
+    NetBlob net;          // state slots: x_tau; noise slots: the conditioning state
+    const float* states;  // [N][d_s] conditioning states
+    const float* x1;      // [N][d_s] latent noise at tau = 1
+    const float* b0;      // [n_steps][width] first-layer biases with the action and tau_k folded in
+    const float* coef;    // [n_steps][2]: x <- coef[0] x + coef[1] v
+    float* out;           // [N][d_s]
+    int N, n_steps;
+};
+struct DdimPrepParams {
+    const float* w;       // [width][a_width + 1]: action columns, then the tau column
+    const float* b;       // [width]
+    float* b0;            // [n_steps][width]
+    float* coef;          // [n_steps][2]
+    int width, aw, n_steps, bf16;
+    float v[64];          // action values (one-hot or continuous)
+};
+
 struct NormResParams {
     const double* x;         // [N] precomputed l / lambda (+ log prior), or NULL
     const float* loglik;     // [N] used when x is NULL and w_in is NULL
@@ -326,6 +346,19 @@ hipError_t launch_nce_scores(int shape, int dt, const NceParams& p, int blocks, 
 int nce_scores_blocks_per_cu(int shape, int dt);
 hipError_t launch_nce_rows(const NceParams& p, int blocks, hipStream_t s);
 hipError_t launch_nce_mean(const NceParams& p, hipStream_t s);
+// Denoiser shapes of the teacher sampler: (id, d_s, width, hidden layers).
+#define VOILA_DDIM_SHAPES(X) \
+    X(0, 4, 64, 2)           \
+    X(1, 4, 1024, 5)         \
+    X(2, 4, 1024, 4)
+constexpr int kNumDdimShapes = 3;
+int ddim_shape(int d_s, int width, int n_hidden);  // -1 when not compiled
+int ddim_in_slots(int shape, int dt);
+bool ddim_split(int shape);                        // evaluated by the four waves of a block per tile
+hipError_t launch_ddim_prep(const DdimPrepParams& p, hipStream_t s);
+hipError_t launch_ddim(int shape, int dt, const DdimParams& p, int blocks, hipStream_t s);
+int ddim_blocks_per_cu(int shape, int dt);
+constexpr int kDdimMaxSteps = 4096;
 constexpr int kNceMaxBatch = 32768;  // B <= this (the score matrix holds B^2 binary32 values)
 constexpr int kPwMaxGroup = 8192;  // successors per group (one workgroup normalises and resamples a group)
 hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
