@@ -1270,7 +1270,8 @@ voila_status_t voila_ddim_sample(voila_denoiser_t m, const float* d_states, cons
     p.N = N;
     p.n_steps = n_steps;
     const long tiles = ((long)N + 31) / 32;
-    const long want = ddim_split(m->shape) ? tiles : (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const long tpb = ddim_tiles_per_block(m->shape);
+    const long want = (tiles + tpb - 1) / tpb;
     const long cap = (long)m->cus * m->bpc;
     VOILA_CHECK_HIP(launch_ddim(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));
     return VOILA_OK;

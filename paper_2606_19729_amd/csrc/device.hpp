@@ -867,6 +867,113 @@ __device__ __forceinline__ f32x16 run_net_split(const NetPtrs& P, const float* b
     return out;
 }
 
+// mfma_layer for ST sample tiles at once: every weight fragment loaded (and
+// prefetched D k-steps ahead) feeds the products of all ST tiles; bop(c, st)
+// is tile st's B operand of k-step c.
+template <int KS, int NT, int ST, int D, class FT, class LD, class BOP>
+__device__ __forceinline__ void mfma_layer_multi(f32x16 (&acc)[ST][NT], LD&& ld, BOP&& bop) {
+    constexpr int DD = D < KS ? D : KS;
+    FT ring[DD][NT];
+    static_for<DD - 1>([&](auto pi) {
+        constexpr int c = decltype(pi)::value;
+        static_for<NT>([&](auto ti) { ring[c][decltype(ti)::value] = ld(c, decltype(ti)::value); });
+    });
+    static_for<KS>([&](auto ci) {
+        constexpr int c = decltype(ci)::value;
+        if constexpr (c + DD - 1 < KS) {
+            static_for<NT>([&](auto ti) {
+                ring[(c + DD - 1) % DD][decltype(ti)::value] = ld(c + DD - 1, decltype(ti)::value);
+            });
+        }
+        static_for<ST>([&](auto si) {
+            constexpr int st = decltype(si)::value;
+            auto b = bop(c, st);
+            static_for<NT>([&](auto ti) {
+                constexpr int t = decltype(ti)::value;
+                acc[st][t] = mfma(ring[c % DD][t], b, acc[st][t]);
+            });
+        });
+        if constexpr (c + DD - 1 < KS) __builtin_amdgcn_sched_group_barrier(kSchedReads, NT, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedMfma, NT * ST, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+// Split evaluation of ST sample tiles by the NW waves of a block: wave w
+// computes output tiles [w HT/NW, (w+1) HT/NW) of every layer for all ST
+// sample tiles, so each weight fragment read from L2 serves ST tiles.  The
+// activations of sample tile st live at lds + st * ACT; the output layer's
+// per-wave partials reuse that space.  out[st] is the output tile of sample
+// tile st (identical in every wave).  D k-steps of weight fragments are in
+// flight.
+template <class N, int ST, int NW, int D>
+__device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const float* b0,
+                                                    const float (&slots)[ST][N::IN_SLOTS], f32x16 (&out)[ST],
+                                                    int lane, int g, int wave, char* lds) {
+    static_assert(N::HT % NW == 0 && N::HID_KS % NW == 0 && N::CT == N::HT, "split needs a layered network");
+    constexpr int TPW = N::HT / NW, KQ = N::HID_KS / NW;
+    constexpr int ACT = SplitLds<N>::ACT;
+    static_assert(ST * NW * 16 * 64 * 4 <= ST * ACT, "partials must fit the activation space");
+    typedef typename Frag<N::DT>::type FT;
+    typedef FragIdx<N> FI;
+    const int t0 = wave * TPW;
+    auto kstep = [&](const char* base, int c) { return base + (size_t)c * N::HT * N::FRAG_BYTES + opaque_zero(); };
+    f32x16 acc[ST][TPW];
+#pragma unroll
+    for (int st = 0; st < ST; ++st) init_bias<TPW>(acc[st], b0 + 32 * t0 + opaque_zero(), g);
+    {
+        const char* base = P.f0 + (size_t)FI::first(0, t0) * N::FRAG_BYTES + opaque_zero();
+        mfma_layer_multi<N::IN_KS, TPW, ST, D, FT>(
+            acc, [&](int c, int t) { return Frag<N::DT>::load(kstep(base, c), t, lane); },
+            [&](int c, int st) { return Slots<N::DT, N::IN_SLOTS>::b(slots[st], c); });
+    }
+#pragma unroll
+    for (int st = 0; st < ST; ++st) split_store<N, TPW>(lds + st * ACT, acc[st], t0, lane);
+    __syncthreads();
+    static_for<N::NHID - 1>([&](auto li) {
+        constexpr int l = decltype(li)::value + 1;
+#pragma unroll
+        for (int st = 0; st < ST; ++st) init_bias<TPW>(acc[st], P.bh + (l - 1) * N::WIDTH + 32 * t0 + opaque_zero(), g);
+        const char* base = P.f0 + (size_t)FI::hidden(l, 0, t0) * N::FRAG_BYTES + opaque_zero();
+        mfma_layer_multi<N::HID_KS, TPW, ST, D, FT>(
+            acc, [&](int c, int t) { return Frag<N::DT>::load(kstep(base, c), t, lane); },
+            [&](int c, int st) { return split_act<N>(lds + st * ACT, c, lane); });
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < ST; ++st) split_store<N, TPW>(lds + st * ACT, acc[st], t0, lane);
+        __syncthreads();
+    });
+    f32x16 part[ST][1];
+#pragma unroll
+    for (int st = 0; st < ST; ++st) {
+        init_bias<1>(part[st], P.bo + opaque_zero(), g);
+        if (wave != 0) part[st][0] = f32x16{};
+    }
+    {
+        const int k0 = wave * KQ;
+        const char* base = P.f0 + (size_t)(FI::out(0) + k0) * N::FRAG_BYTES + opaque_zero();
+        mfma_layer_multi<KQ, 1, ST, D, FT>(
+            part, [&](int c, int) { return Frag<N::DT>::load(base + (size_t)c * N::FRAG_BYTES + opaque_zero(), 0, lane); },
+            [&](int c, int st) { return split_act<N>(lds + st * ACT, k0 + c, lane); });
+    }
+    __syncthreads();  // every wave has read the activations the partials overwrite
+    float* pl = reinterpret_cast<float*>(lds);
+#pragma unroll
+    for (int st = 0; st < ST; ++st)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) pl[((st * NW + wave) * 16 + i) * 64 + lane] = part[st][0][i];
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < ST; ++st)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            float v = pl[((st * NW) * 16 + i) * 64 + lane];
+            for (int w = 1; w < NW; ++w) v += pl[((st * NW + w) * 16 + i) * 64 + lane];
+            out[st][i] = v;
+        }
+    __syncthreads();
+}
+
 // Fragment source of a network read straight from global memory: the plain
 // source for networks evaluated layer by layer, the grouped bundle otherwise.
 template <class N, bool GROUPED = (N::CT < N::HT)> struct DirectFor;

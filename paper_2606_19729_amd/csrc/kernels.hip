@@ -1321,11 +1321,7 @@ __global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
                 if (2 * s + g < D_S) p.out[(size_t)i * D_S + 2 * s + g] = x[s];
     };
     if constexpr (SPLIT) {
-        const NetPtrs P = net_ptrs(p.net.base, p.net);
-        for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
-            run_tile(tile, true, wave == 0, [&](const float* b0, const float (&slots)[NT::IN_SLOTS]) {
-                return run_net_split<NT>(P, b0, slots, lane, g, wave, smem);
-            });
+        return;  // deep wide networks run in ddim_split_kernel
     } else {
         with_weights<NT, MODE, 1>(smem, p.net, [&](auto& src, const NetPtrs& P) {
             // block-uniform loop (a streamed network's chunk barriers need every wave)
@@ -1336,6 +1332,86 @@ __global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
                 });
             }
         });
+    }
+    }
+}
+
+// The teacher sampler for deep wide networks: a block of kDdimSplitWaves
+// waves advances kDdimSplitTiles 32-sample tiles together, each layer split
+// over the waves (run_net_split_multi), so that every weight fragment read
+// from L2 serves all of the block's tiles.  Every wave keeps the tiles'
+// samples; the first wave writes them.
+#ifndef VOILA_DDIM_SPLIT_WAVES
+#define VOILA_DDIM_SPLIT_WAVES 8
+#endif
+#ifndef VOILA_DDIM_SPLIT_TILES
+#define VOILA_DDIM_SPLIT_TILES 2
+#endif
+#ifndef VOILA_DDIM_SPLIT_DEPTH
+#define VOILA_DDIM_SPLIT_DEPTH 2
+#endif
+constexpr int kDdimSplitWaves = VOILA_DDIM_SPLIT_WAVES, kDdimSplitTiles = VOILA_DDIM_SPLIT_TILES,
+              kDdimSplitDepth = VOILA_DDIM_SPLIT_DEPTH;
+template <int DT, int D_S, int WIDTH, int NHID>
+__global__ __launch_bounds__(64 * kDdimSplitWaves) void ddim_split_kernel(DdimParams p) {
+    if constexpr (!net_compiled(DT, WIDTH) || WIDTH <= 64) {
+        return;  // small networks run one tile per wave in ddim_kernel
+    } else {
+    constexpr int ST = kDdimSplitTiles;
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_S), WIDTH / 32> NT;
+    constexpr int SS = state_slots(D_S), SW = noise_slots(D_S);
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n_groups = (p.N + 32 * ST - 1) / (32 * ST);
+    const kconst float* coef = (const kconst float*)p.coef;
+    const NetPtrs P = net_ptrs(p.net.base, p.net);
+    for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+        float x[ST][SS], cond[ST][SW];
+        bool valid[ST];
+        int row[ST];
+#pragma unroll
+        for (int st = 0; st < ST; ++st) {
+            row[st] = (grp * ST + st) * 32 + col;
+            valid[st] = row[st] < p.N;
+#pragma unroll
+            for (int s = 0; s < SS; ++s) {
+                const int f = 2 * s + g;
+                x[st][s] = (valid[st] && f < D_S) ? p.x1[(size_t)row[st] * D_S + f] : 0.0f;
+            }
+#pragma unroll
+            for (int s = 0; s < SW; ++s) {
+                const int f = noise_feature(s, g);
+                cond[st][s] = (valid[st] && f < D_S) ? p.states[(size_t)row[st] * D_S + f] : 0.0f;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+        for (int t = 0; t < p.n_steps; ++t) {
+            float slots[ST][NT::IN_SLOTS];
+#pragma unroll
+            for (int st = 0; st < ST; ++st) {
+#pragma unroll
+                for (int s = 0; s < NT::IN_SLOTS; ++s) slots[st][s] = 0.0f;
+#pragma unroll
+                for (int s = 0; s < SS; ++s) slots[st][s] = x[st][s];
+#pragma unroll
+                for (int s = 0; s < SW; ++s) slots[st][SS + s] = cond[st][s];
+            }
+            f32x16 v[ST];
+            run_net_split_multi<NT, ST, kDdimSplitWaves, kDdimSplitDepth>(P, p.b0 + (size_t)t * WIDTH, slots, v, lane, g, wave, smem);
+            const float A = coef[2 * t], B = coef[2 * t + 1];
+#pragma unroll
+            for (int st = 0; st < ST; ++st)
+#pragma unroll
+                for (int s = 0; s < SS; ++s) x[st][s] = __builtin_fmaf(B, v[st][s], A * x[st][s]);
+        }
+        if (wave == 0)
+#pragma unroll
+            for (int st = 0; st < ST; ++st)
+                if (valid[st])
+#pragma unroll
+                    for (int s = 0; s < SS; ++s)
+                        if (2 * s + g < D_S) p.out[(size_t)row[st] * D_S + 2 * s + g] = x[st][s];
     }
     }
 }
@@ -1532,6 +1608,12 @@ int occupancy(KernelT k, size_t lds) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 256, lds) != hipSuccess || n < 1) n = 1;
     return n;
 }
+template <class KernelT>
+int occupancy_t(KernelT k, int threads, size_t lds) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess || n < 1) n = 1;
+    return n;
+}
 // LDS bytes assumed for occupancy: the blob sizes of the small shape are a few tens of KB.
 constexpr size_t kLdsGuess = 32 * 1024;
 }  // namespace
@@ -1693,6 +1775,7 @@ hipError_t launch_nce_mean(const NceParams& p, hipStream_t s) {
 
 template <int W> constexpr int ddim_mode() { return W <= 64 ? kResident : kSplit; }
 #define DDIM_K(id, ds, w, nh, DT) ddim_kernel<DT, ds, w, nh, ddim_mode<w>()>
+#define DDIM_SK(id, ds, w, nh, DT) ddim_split_kernel<DT, ds, w, nh>
 
 int ddim_shape(int d_s, int width, int n_hidden) {
 #define X(id, ds, w, nh) \
@@ -1727,9 +1810,10 @@ constexpr size_t ddim_split_lds() {
     if constexpr (!net_compiled(DT, W)) {
         return 0;
     } else {
-        return (size_t)SplitLds<Net<DT, W, NH, in_slots(DT, D_S, 0, D_S), W / 32>>::BYTES;
+        return (size_t)kDdimSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_S, 0, D_S), W / 32>>::ACT;
     }
 }
+int ddim_tiles_per_block(int shape) { return ddim_split(shape) ? kDdimSplitTiles : kWavesPerBlock; }
 
 hipError_t launch_ddim_prep(const DdimPrepParams& p, hipStream_t s) {
     if (p.n_steps == 0) return hipSuccess;
@@ -1738,25 +1822,27 @@ hipError_t launch_ddim_prep(const DdimPrepParams& p, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <class K>
+void launch_ddim_one(K k, bool split, size_t lds, int blocks, const DdimParams& p, hipStream_t s) {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, blocks, split ? 64 * kDdimSplitWaves : 256, lds, s, p);
+}
+
 hipError_t launch_ddim(int shape, int dt, const DdimParams& p, int blocks, hipStream_t s) {
     switch (shape * 2 + dt) {
-#define X(id, ds, w, nh)                                                                                 \
-    case id * 2 + 0: {                                                                                  \
-        const size_t lds = ddim_mode<w>() == kSplit ? ddim_split_lds<DT_F32, ds, w, nh>() : p.net.bytes; \
-        if (lds > 65536)                                                                                \
-            (void)hipFuncSetAttribute((const void*)DDIM_K(id, ds, w, nh, DT_F32),                         \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
-        hipLaunchKernelGGL((DDIM_K(id, ds, w, nh, DT_F32)), blocks, 256, lds, s, p);                     \
-        break;                                                                                          \
-    }                                                                                                   \
-    case id * 2 + 1: {                                                                                  \
-        const size_t lds = ddim_mode<w>() == kSplit ? ddim_split_lds<DT_BF16, ds, w, nh>() : p.net.bytes; \
-        if (lds > 65536)                                                                                \
-            (void)hipFuncSetAttribute((const void*)DDIM_K(id, ds, w, nh, DT_BF16),                        \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
-        hipLaunchKernelGGL((DDIM_K(id, ds, w, nh, DT_BF16)), blocks, 256, lds, s, p);                    \
-        break;                                                                                          \
-    }
+#define X(id, ds, w, nh)                                                                                       \
+    case id * 2 + 0:                                                                                          \
+        if (ddim_mode<w>() == kSplit)                                                                         \
+            launch_ddim_one(DDIM_SK(id, ds, w, nh, DT_F32), true, ddim_split_lds<DT_F32, ds, w, nh>(), blocks, p, s); \
+        else                                                                                                  \
+            launch_ddim_one(DDIM_K(id, ds, w, nh, DT_F32), false, p.net.bytes, blocks, p, s);                  \
+        break;                                                                                                \
+    case id * 2 + 1:                                                                                          \
+        if (ddim_mode<w>() == kSplit)                                                                         \
+            launch_ddim_one(DDIM_SK(id, ds, w, nh, DT_BF16), true, ddim_split_lds<DT_BF16, ds, w, nh>(), blocks, p, s); \
+        else                                                                                                  \
+            launch_ddim_one(DDIM_K(id, ds, w, nh, DT_BF16), false, p.net.bytes, blocks, p, s);                 \
+        break;
         VOILA_DDIM_SHAPES(X)
 #undef X
         default:
@@ -1769,11 +1855,15 @@ int ddim_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, w, nh)                                                                                    \
     case id * 2 + 0:                                                                                       \
-        return occupancy(DDIM_K(id, ds, w, nh, DT_F32),                                                    \
-                         ddim_mode<w>() == kSplit ? ddim_split_lds<DT_F32, ds, w, nh>() : kLdsGuess);      \
+        return ddim_mode<w>() == kSplit                                                                    \
+                   ? occupancy_t(DDIM_SK(id, ds, w, nh, DT_F32), 64 * kDdimSplitWaves,                     \
+                                 ddim_split_lds<DT_F32, ds, w, nh>())                                      \
+                   : occupancy(DDIM_K(id, ds, w, nh, DT_F32), kLdsGuess);                                  \
     case id * 2 + 1:                                                                                       \
-        return occupancy(DDIM_K(id, ds, w, nh, DT_BF16),                                                   \
-                         ddim_mode<w>() == kSplit ? ddim_split_lds<DT_BF16, ds, w, nh>() : kLdsGuess);
+        return ddim_mode<w>() == kSplit                                                                    \
+                   ? occupancy_t(DDIM_SK(id, ds, w, nh, DT_BF16), 64 * kDdimSplitWaves,                    \
+                                 ddim_split_lds<DT_BF16, ds, w, nh>())                                     \
+                   : occupancy(DDIM_K(id, ds, w, nh, DT_BF16), kLdsGuess);
         VOILA_DDIM_SHAPES(X)
 #undef X
     }
@@ -1833,15 +1923,6 @@ hipError_t launch_propose_batch(int shape, int dt, const BatchProposeParams& p, 
     }
     return hipGetLastError();
 }
-
-namespace {
-template <class KernelT>
-int occupancy_t(KernelT k, int threads, size_t lds) {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess || n < 1) n = 1;
-    return n;
-}
-}  // namespace
 
 int plan_batch_blocks_per_cu(int shape, int dt, int wpb, size_t lds) {
     switch (shape * 2 + dt) {

@@ -354,7 +354,8 @@ hipError_t launch_nce_mean(const NceParams& p, hipStream_t s);
 constexpr int kNumDdimShapes = 3;
 int ddim_shape(int d_s, int width, int n_hidden);  // -1 when not compiled
 int ddim_in_slots(int shape, int dt);
-bool ddim_split(int shape);                        // evaluated by the four waves of a block per tile
+bool ddim_split(int shape);                        // evaluated by all waves of a block per group of tiles
+int ddim_tiles_per_block(int shape);
 hipError_t launch_ddim_prep(const DdimPrepParams& p, hipStream_t s);
 hipError_t launch_ddim(int shape, int dt, const DdimParams& p, int blocks, hipStream_t s);
 int ddim_blocks_per_cu(int shape, int dt);
