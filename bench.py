@@ -375,37 +375,42 @@ def bench_info_nce(V, torch, reps):
 
 
 def bench_ddim(V, torch, reps):
-    """The teacher sampler the transition generator is distilled from: the
-    paper's 5 x 1024 v-prediction denoiser run for 50 deterministic DDIM
-    steps on 65,536 samples (bfloat16), beside one evaluation of a 4 x 1024
-    network (the paper's distilled sampler shape) through the same kernel --
-    the distilled-versus-diffusion sampling-rate comparison."""
+    """The teacher samplers the generators are distilled from (bfloat16,
+    65,536 samples, 50 deterministic DDIM steps): the paper's 5 x 1024
+    transition denoiser, beside one evaluation of a 4 x 1024 network (the
+    paper's distilled sampler shape) through the same kernel -- the
+    distilled-versus-diffusion sampling-rate comparison -- and a 5 x 512
+    observation denoiser (32-dimensional observation, 16-dimensional state,
+    4 continuous action inputs)."""
     import workloads
     dev = torch.device("cuda", 0)
     N, steps = 65536, 50
-    S, X1 = (torch.as_tensor(x, device=dev) for x in workloads.ddim_batch(N, seed=23))
     out = {"samples": N}
     stream = torch.cuda.current_stream()
-    for name, nh, n_steps in [("teacher_5x1024", 5, steps), ("distilled_4x1024", 4, 1)]:
-        layers = workloads.denoiser(seed=24, width=1024, n_hidden=nh)
-        den = V.Denoiser(layers, 4, 5, 0, compute="bf16")
+    cases = [("teacher_5x1024", 4, 4, 5, 0, 1024, 5, steps, 2),
+             ("distilled_4x1024", 4, 4, 5, 0, 1024, 4, 1, 2),
+             ("observation_teacher_5x512", 16, 32, 0, 4, 512, 5, steps, [0.5, -1.0, 0.25, 0.0])]
+    for name, d_c, d_x, n_act, d_a, width, nh, n_steps, action in cases:
+        C, X1 = (torch.as_tensor(x, device=dev) for x in workloads.ddim_batch(N, d_c=d_c, d_x=d_x, seed=23))
+        layers = workloads.denoiser(seed=24, d_c=d_c, d_x=d_x, n_actions=n_act, d_a=d_a, width=width, n_hidden=nh)
+        den = V.Denoiser(layers, d_c, d_x, n_act, d_a, compute="bf16")
         ws = torch.empty(int(V.lib.voila_ddim_workspace_size(den.handle, n_steps)), dtype=torch.uint8, device=dev)
-        res = torch.empty((N, 4), dtype=torch.float32, device=dev)
+        res = torch.empty((N, d_x), dtype=torch.float32, device=dev)
         ms = []
         for r in range(reps + 1):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            V.ddim_sample(den, S, 2, X1, n_steps, out=res, workspace=ws)
+            V.ddim_sample(den, C, action, X1, n_steps, out=res, workspace=ws)
             b.record(stream)
             torch.cuda.synchronize()
             if r > 0:
                 ms.append(a.elapsed_time(b))
         t = float(np.median(ms))
-        # executed flop per network evaluation: the first layer over the 8
-        # slot inputs (x_tau, s; action and tau folded per step)
-        dims = [8] + [int(W.shape[0]) for W, _ in layers]
+        # executed flop per network evaluation: the first layer over the slot
+        # inputs (x_tau and c; action and tau folded per step)
+        dims = [d_x + d_c] + [int(W.shape[0]) for W, _ in layers]
         f_eval = 2 * sum(x * y for x, y in zip(dims[:-1], dims[1:]))
-        out[name] = {"steps": n_steps, "ms": t, "samples_per_s": N / (t / 1e3),
+        out[name] = {"steps": n_steps, "ms": t, "samples_per_s": N / (t / 1e3), "flop_per_evaluation": f_eval,
                      "mfma_frac": f_eval * N * n_steps / (t / 1e3) / 1e12 / PEAK_BF16_TFLOPS}
         print(f"[bench]   {name}: {t:.3f} ms", file=sys.stderr, flush=True)
     out["distilled_over_teacher"] = out["distilled_4x1024"]["samples_per_s"] / out["teacher_5x1024"]["samples_per_s"]

@@ -276,38 +276,42 @@ voila_status_t voila_info_nce(voila_model_t model, const float* d_states, const 
                               int32_t* d_status, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Teacher sampler of the transition model (Sec. 4.2): a conditional
- * v-prediction denoiser v_T(s, a, x_tau, tau) run by the deterministic (ODE)
- * DDIM sampler, the sampler the transition generator is distilled from.
+ * Teacher samplers of the learned generators (Sec. 4.2): a conditional
+ * v-prediction denoiser v(c, a, x_tau, tau) run by the deterministic (ODE)
+ * DDIM sampler, the sampler a generator is distilled from.  For the
+ * transition model c is the state s and x the next state (d_x = d_c = d_s);
+ * for the observation model c is the next state and x the observation.
  *
  * voila_denoiser_create packs a denoiser MLP (host arrays as in
- * voila_model_create; input [s, a, x_tau, tau] of width 2 d_s + a_width + 1,
- * ReLU hidden layers of equal width, linear output v of width d_s; a_width =
- * n_actions for one-hot discrete actions, else d_a).  Compiled shapes: d_s =
- * 4 with hidden layers 2 x 64 (binary32 or bfloat16), 5 x 1024 (the paper's
- * transition denoiser) and 4 x 1024 (the paper's distilled sampler, for a
- * one-step cost comparison), the last two in bfloat16 only; other shapes
- * return VOILA_ERR_UNSUPPORTED.  The handle owns a device copy of the weights.
+ * voila_model_create; input [c, a, x_tau, tau] of width d_c + a_width + d_x
+ * + 1, ReLU hidden layers of equal width, linear output v of width d_x;
+ * a_width = n_actions for one-hot discrete actions, else d_a).  Compiled
+ * shapes (d_x, d_c, hidden layers): (4, 4, 2 x 64) in binary32 or bfloat16;
+ * in bfloat16 only (4, 4, 5 x 1024) -- the paper's transition denoiser --,
+ * (4, 4, 4 x 1024) -- the distilled sampler's shape, for a one-step cost
+ * comparison -- and (32, 16, 5 x 512) -- the paper's observation denoiser
+ * width and depth; other shapes return VOILA_ERR_UNSUPPORTED.  The handle
+ * owns a device copy of the weights.
  *
  * voila_ddim_sample draws N samples in n_steps uniform steps tau_k = 1 - k/n
- * from d_x1 [N][d_s] (the latent noise at tau = 1) conditioned on d_states
- * [N][d_s] and one action (h_action: host int32 index or float[d_a]).  With
+ * from d_x1 [N][d_x] (the latent noise at tau = 1) conditioned on d_cond
+ * [N][d_c] and one action (h_action: host int32 index or float[d_a]).  With
  * the cosine schedule abar(tau) = cos^2(pi/2 (tau + 0.008)/1.008) /
  * cos^2(pi/2 0.008/1.008), a = abar(tau_k), a' = abar(tau_{k+1}) and v the
- * denoiser's output at (s, a, x, tau_k):
+ * denoiser's output at (c, a, x, tau_k):
  *   x0 = sqrt(a) x - sqrt(1 - a) v,  eps = sqrt(1 - a) x + sqrt(a) v,
  *   x <- sqrt(a') x0 + sqrt(1 - a') eps,
- * the final x (tau = 0) written to d_out [N][d_s].  The step coefficients are
+ * the final x (tau = 0) written to d_out [N][d_x].  The step coefficients are
  * formed in binary64 and applied in binary32; the network runs in the
  * denoiser's precision.  1 <= n_steps <= 4096; the workspace
  * (voila_ddim_workspace_size) holds the per-step folded biases.
  * ------------------------------------------------------------------------- */
 typedef struct voila_denoiser_s* voila_denoiser_t;
-voila_status_t voila_denoiser_create(const voila_mlp_desc_t* net, int32_t d_s, int32_t n_actions, int32_t d_a,
-                                     int32_t compute, int32_t device, voila_denoiser_t* out);
+voila_status_t voila_denoiser_create(const voila_mlp_desc_t* net, int32_t d_c, int32_t d_x, int32_t n_actions,
+                                     int32_t d_a, int32_t compute, int32_t device, voila_denoiser_t* out);
 voila_status_t voila_denoiser_destroy(voila_denoiser_t denoiser);
 size_t voila_ddim_workspace_size(voila_denoiser_t denoiser, int32_t n_steps);
-voila_status_t voila_ddim_sample(voila_denoiser_t denoiser, const float* d_states, const void* h_action,
+voila_status_t voila_ddim_sample(voila_denoiser_t denoiser, const float* d_cond, const void* h_action,
                                  const float* d_x1, int32_t N, int32_t n_steps, void* d_workspace,
                                  size_t workspace_bytes, float* d_out, void* stream);
 

@@ -73,7 +73,8 @@ def lib():
         L.or_info_nce.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, i32p, c_int, dp, dp, dp, dp]
         L.or_cosine_abar.argtypes = [c_double]
         L.or_cosine_abar.restype = c_double
-        L.or_ddim_sample.argtypes = [c_int, ip, dp, c_int, c_int, c_int, c_int, dp, c_int, dp, dp, c_int, c_int, dp]
+        L.or_ddim_sample.argtypes = [c_int, ip, dp, c_int, c_int, c_int, c_int, c_int, dp, c_int, dp, dp, c_int, c_int,
+                                     dp]
         L.or_ddim_point_mass.argtypes = [c_int, dp, dp, c_int, dp]
         L.or_mlp_param_count.argtypes = [c_int, ip]
         L.or_mlp_param_count.restype = c_size_t
@@ -411,19 +412,19 @@ def cosine_abar(tau):
     return lib().or_cosine_abar(float(tau))
 
 
-def ddim_sample(layers, d_s, n_actions, d_a, states, action, x1, n_steps, bf16=False):
-    """Teacher samples [n, d_s]: the DDIM (ODE) sampler of the v-prediction
-    denoiser `layers` (input [s, a, x_tau, tau], output v) in n_steps uniform
-    steps from x1 (the latent noise at tau = 1), conditioned on states and
-    one action (index or [d_a] values)."""
-    S = _d(states)
-    n = S.shape[0]
-    X1 = _d(np.asarray(x1).reshape(n, d_s))
+def ddim_sample(layers, d_c, d_x, n_actions, d_a, cond, action, x1, n_steps, bf16=False):
+    """Teacher samples [n, d_x]: the DDIM (ODE) sampler of the v-prediction
+    denoiser `layers` (input [c, a, x_tau, tau], output v [d_x]) in n_steps
+    uniform steps from x1 [n, d_x] (the latent noise at tau = 1),
+    conditioned on cond [n, d_c] and one action (index or [d_a] values)."""
+    C = _d(cond)
+    n = C.shape[0]
+    X1 = _d(np.asarray(x1).reshape(n, d_x))
     dims, params = flatten_layers(layers)
     a_disc, a_cont = (int(action), None) if n_actions > 0 else (0, _d(np.asarray(action).reshape(d_a)))
-    out = np.zeros((n, d_s))
-    _check(lib().or_ddim_sample(len(layers), dims.ctypes.data_as(POINTER(c_int)), _p(params), d_s, n_actions, d_a,
-                                n, _p(S), a_disc, _p(a_cont), _p(X1), int(n_steps), int(bf16), _p(out)),
+    out = np.zeros((n, d_x))
+    _check(lib().or_ddim_sample(len(layers), dims.ctypes.data_as(POINTER(c_int)), _p(params), d_c, d_x, n_actions,
+                                d_a, n, _p(C), a_disc, _p(a_cont), _p(X1), int(n_steps), int(bf16), _p(out)),
            "ddim_sample")
     return out
 

@@ -1249,42 +1249,44 @@ static void ddim_run(int d, const double* s, double* x, int n_steps, or_vfun vf,
 
 typedef struct {
     int n_layers; const int* dims; const double* params;
-    int d_s, n_actions, d_a, a_disc; const double* a_cont; int bf16;
+    int d_c, d_x, n_actions, d_a, a_disc; const double* a_cont; int bf16;
 } ddim_net_ctx;
 
-/* v = denoiser([s, a, x, tau]) (a one-hot over n_actions, or continuous). */
-static void ddim_net_v(const void* cp, const double* s, const double* x, double tau, double* v)
+/* v = denoiser([c, a, x, tau]) (a one-hot over n_actions, or continuous). */
+static void ddim_net_v(const void* cp, const double* cond, const double* x, double tau, double* v)
 {
     const ddim_net_ctx* c = (const ddim_net_ctx*)cp;
     double in[OR_MAX_WIDTH];
     const int aw = c->n_actions > 0 ? c->n_actions : c->d_a;
-    for (int j = 0; j < c->d_s; ++j) in[j] = s[j];
-    for (int j = 0; j < aw; ++j) in[c->d_s + j] = c->n_actions > 0 ? (j == c->a_disc ? 1.0 : 0.0) : c->a_cont[j];
-    for (int j = 0; j < c->d_s; ++j) in[c->d_s + aw + j] = x[j];
-    in[2 * c->d_s + aw] = tau;
+    for (int j = 0; j < c->d_c; ++j) in[j] = cond[j];
+    for (int j = 0; j < aw; ++j) in[c->d_c + j] = c->n_actions > 0 ? (j == c->a_disc ? 1.0 : 0.0) : c->a_cont[j];
+    for (int j = 0; j < c->d_x; ++j) in[c->d_c + aw + j] = x[j];
+    in[c->d_c + aw + c->d_x] = tau;
     mlp_forward(c->n_layers, c->dims, c->params, in, v, c->bf16);
 }
 
-/* Teacher samples of n rows: X1 [n][d_s] the latent noise at tau = 1,
- * S [n][d_s] the conditioning states, one action for all rows, a denoiser
- * with input [s, a, x_tau, tau] and output v [d_s].  Out [n][d_s]. */
-int or_ddim_sample(int n_layers, const int* dims, const double* params, int d_s, int n_actions, int d_a,
-                   int n, const double* S, int a_disc, const double* a_cont, const double* X1, int n_steps,
+/* Teacher samples of n rows: X1 [n][d_x] the latent noise at tau = 1,
+ * C [n][d_c] the conditioning inputs (the state for the transition
+ * denoiser, the next state for the observation denoiser), one action for
+ * all rows, a denoiser with input [c, a, x_tau, tau] and output v [d_x].
+ * Out [n][d_x]. */
+int or_ddim_sample(int n_layers, const int* dims, const double* params, int d_c, int d_x, int n_actions, int d_a,
+                   int n, const double* C, int a_disc, const double* a_cont, const double* X1, int n_steps,
                    int bf16, double* out)
 {
     const int aw = n_actions > 0 ? n_actions : d_a;
-    if (mlp_check(n_layers, dims) != OR_OK || n < 0 || n_steps < 1 || d_s < 1) return OR_ERR_ARG;
-    if (dims[0] != 2 * d_s + aw + 1 || dims[n_layers] != d_s) return OR_ERR_ARG;
+    if (mlp_check(n_layers, dims) != OR_OK || n < 0 || n_steps < 1 || d_c < 1 || d_x < 1) return OR_ERR_ARG;
+    if (dims[0] != d_c + aw + d_x + 1 || dims[n_layers] != d_x) return OR_ERR_ARG;
     if (n_actions > 0 ? (a_disc < 0 || a_disc >= n_actions) : !a_cont) return OR_ERR_ARG;
     double* rw = bf16 ? round_weights(n_layers, dims, params) : NULL;
     if (bf16 && !rw) return OR_ERR_ARG;
-    ddim_net_ctx c = {n_layers, dims, bf16 ? rw : params, d_s, n_actions, d_a, a_disc, a_cont, bf16};
+    ddim_net_ctx c = {n_layers, dims, bf16 ? rw : params, d_c, d_x, n_actions, d_a, a_disc, a_cont, bf16};
     #pragma omp parallel for schedule(static)
     for (int r = 0; r < n; ++r) {
         double x[OR_MAX_WIDTH];
-        for (int j = 0; j < d_s; ++j) x[j] = X1[(size_t)r * d_s + j];
-        ddim_run(d_s, S + (size_t)r * d_s, x, n_steps, ddim_net_v, &c);
-        for (int j = 0; j < d_s; ++j) out[(size_t)r * d_s + j] = x[j];
+        for (int j = 0; j < d_x; ++j) x[j] = X1[(size_t)r * d_x + j];
+        ddim_run(d_x, C + (size_t)r * d_c, x, n_steps, ddim_net_v, &c);
+        for (int j = 0; j < d_x; ++j) out[(size_t)r * d_x + j] = x[j];
     }
     free(rw);
     return OR_OK;

@@ -162,7 +162,8 @@ def _load():
     L.voila_info_nce_workspace_size.restype = c_size_t
     L.voila_info_nce.argtypes = [vp, vp, vp, vp, c_int32, vp, c_size_t, vp, vp, vp, vp, vp, vp]
     L.voila_info_nce.restype = c_int32
-    L.voila_denoiser_create.argtypes = [POINTER(_Mlp), c_int32, c_int32, c_int32, c_int32, c_int32, POINTER(vp)]
+    L.voila_denoiser_create.argtypes = [POINTER(_Mlp), c_int32, c_int32, c_int32, c_int32, c_int32, c_int32,
+                                        POINTER(vp)]
     L.voila_denoiser_create.restype = c_int32
     L.voila_denoiser_destroy.argtypes = [vp]
     L.voila_denoiser_destroy.restype = c_int32
@@ -271,17 +272,19 @@ def _mlp_desc(layers, keep):
 
 
 class Denoiser:
-    """Packed device copy of a v-prediction transition denoiser (layers
-    [(W, b), ...] with input [s, a, x_tau, tau] and output v [d_s])."""
+    """Packed device copy of a v-prediction denoiser (layers [(W, b), ...]
+    with input [c, a, x_tau, tau] -- conditioning input c of width d_c --
+    and output v [d_x])."""
 
-    def __init__(self, layers, d_s: int, n_actions: int, d_a: int = 0, compute: str = "bf16", device: int = 0):
-        self.d_s, self.n_actions, self.d_a = int(d_s), int(n_actions), int(d_a)
+    def __init__(self, layers, d_c: int, d_x: int, n_actions: int, d_a: int = 0, compute: str = "bf16",
+                 device: int = 0):
+        self.d_c, self.d_x, self.n_actions, self.d_a = int(d_c), int(d_x), int(n_actions), int(d_a)
         self.compute = compute
         self.device = device
         self.handle = c_void_p()
         keep = []
         desc = _mlp_desc(layers, keep)
-        _check(lib.voila_denoiser_create(ctypes.byref(desc), self.d_s, self.n_actions, self.d_a,
+        _check(lib.voila_denoiser_create(ctypes.byref(desc), self.d_c, self.d_x, self.n_actions, self.d_a,
                                          {"f32": VOILA_F32, "bf16": VOILA_BF16}[compute], int(device),
                                          ctypes.byref(self.handle)))
 
@@ -297,13 +300,13 @@ class Denoiser:
             pass
 
 
-def ddim_sample(den: Denoiser, states, action, x1, n_steps, out=None, workspace=None, stream=None):
-    """Teacher samples [N, d_s] float32: n_steps deterministic DDIM steps of
-    the denoiser from x1 [N, d_s] (the latent noise at tau = 1) conditioned
-    on states [N, d_s] and one action (index, or d_a values)."""
-    N = int(states.shape[0])
-    _dev(states, torch.float32, (N, den.d_s), "states")
-    _dev(x1, torch.float32, (N, den.d_s), "x1")
+def ddim_sample(den: Denoiser, cond, action, x1, n_steps, out=None, workspace=None, stream=None):
+    """Teacher samples [N, d_x] float32: n_steps deterministic DDIM steps of
+    the denoiser from x1 [N, d_x] (the latent noise at tau = 1) conditioned
+    on cond [N, d_c] and one action (index, or d_a values)."""
+    N = int(cond.shape[0])
+    _dev(cond, torch.float32, (N, den.d_c), "cond")
+    _dev(x1, torch.float32, (N, den.d_x), "x1")
     if den.n_actions > 0:
         h_action = (c_int32 * 1)(int(action))
     else:
@@ -311,11 +314,11 @@ def ddim_sample(den: Denoiser, states, action, x1, n_steps, out=None, workspace=
         if len(vals) != den.d_a:
             raise VoilaError(VOILA_ERR_INVALID_ARG, f"continuous action must have {den.d_a} values")
         h_action = (c_float * den.d_a)(*vals)
-    res = out if out is not None else torch.empty((N, den.d_s), dtype=torch.float32, device=states.device)
+    res = out if out is not None else torch.empty((N, den.d_x), dtype=torch.float32, device=cond.device)
     if workspace is None:
         n = lib.voila_ddim_workspace_size(den.handle, int(n_steps))
-        workspace = torch.empty(max(int(n), 1), dtype=torch.uint8, device=states.device)
-    _check(lib.voila_ddim_sample(den.handle, _ptr(states), h_action, _ptr(x1), N, int(n_steps), _ptr(workspace),
+        workspace = torch.empty(max(int(n), 1), dtype=torch.uint8, device=cond.device)
+    _check(lib.voila_ddim_sample(den.handle, _ptr(cond), h_action, _ptr(x1), N, int(n_steps), _ptr(workspace),
                                  workspace.numel(), _ptr(res), _stream(stream)))
     return res
 

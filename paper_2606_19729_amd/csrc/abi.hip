@@ -1135,7 +1135,7 @@ voila_status_t voila_info_nce(voila_model_t m, const float* d_states, const void
 
 struct voila_denoiser_s {
     int device = 0, shape = -1, dt = DT_F32, cus = 1, bpc = 1;
-    int d_s = 0, n_actions = 0, d_a = 0, width = 0;
+    int d_c = 0, d_x = 0, n_actions = 0, d_a = 0, width = 0;
     char* mem = nullptr;
     NetBlob net{};
     const float* fold_w = nullptr;  // [width][a_width + 1]
@@ -1143,23 +1143,23 @@ struct voila_denoiser_s {
     int action_width() const { return n_actions > 0 ? n_actions : d_a; }
 };
 
-voila_status_t voila_denoiser_create(const voila_mlp_desc_t* net, int32_t d_s, int32_t n_actions, int32_t d_a,
-                                     int32_t compute, int32_t device, voila_denoiser_t* out) {
+voila_status_t voila_denoiser_create(const voila_mlp_desc_t* net, int32_t d_c, int32_t d_x, int32_t n_actions,
+                                     int32_t d_a, int32_t compute, int32_t device, voila_denoiser_t* out) {
     if (!net || !out) return fail(VOILA_ERR_INVALID_ARG, "NULL descriptor or output handle");
     *out = nullptr;
     if (compute != VOILA_F32 && compute != VOILA_BF16)
         return fail(VOILA_ERR_INVALID_ARG, "compute must be VOILA_F32 or VOILA_BF16");
-    if (d_s < 1 || n_actions < 0 || d_a < 0 || (n_actions == 0 && d_a < 1))
-        return fail(VOILA_ERR_INVALID_ARG, "bad state or action dimension");
+    if (d_c < 1 || d_x < 1 || n_actions < 0 || d_a < 0 || (n_actions == 0 && d_a < 1))
+        return fail(VOILA_ERR_INVALID_ARG, "bad conditioning, sample or action dimension");
     const int aw = n_actions > 0 ? n_actions : d_a;
     if (aw > 63) return fail(VOILA_ERR_UNSUPPORTED, "at most 63 action inputs");
     HostNet D;
     voila_status_t st;
     if ((st = read_net(*net, D, "denoiser")) != VOILA_OK) return st;
     if (!D.present()) return fail(VOILA_ERR_INVALID_ARG, "the denoiser network is required");
-    if (D.dims[0] != 2 * d_s + aw + 1 || D.out() != d_s)
-        return fail(VOILA_ERR_INVALID_ARG, "denoiser dims must be [2 d_s + a_width + 1, ..., d_s]");
-    const int shape = ddim_shape(d_s, D.width(), D.n_layers - 1);
+    if (D.dims[0] != d_c + aw + d_x + 1 || D.out() != d_x)
+        return fail(VOILA_ERR_INVALID_ARG, "denoiser dims must be [d_c + a_width + d_x + 1, ..., d_x]");
+    const int shape = ddim_shape(d_x, d_c, D.width(), D.n_layers - 1);
     if (shape < 0) return fail(VOILA_ERR_UNSUPPORTED, "no compiled sampler kernel for this denoiser shape");
     if (D.width() > 256 && compute != VOILA_BF16)
         return fail(VOILA_ERR_UNSUPPORTED, "hidden widths above 256 run in bfloat16 only");
@@ -1172,16 +1172,17 @@ voila_status_t voila_denoiser_create(const voila_mlp_desc_t* net, int32_t d_s, i
     m->device = device;
     m->shape = shape;
     m->dt = compute;
-    m->d_s = d_s;
+    m->d_c = d_c;
+    m->d_x = d_x;
     m->n_actions = n_actions;
     m->d_a = n_actions > 0 ? 0 : d_a;
     m->width = D.width();
     const int W = m->width, dt = m->dt;
-    // input [s, a, x_tau, tau]: x_tau in the state slots, s in the noise slots
-    SlotMap map{d_s, 0, d_s, d_s, 0, d_s + aw};
+    // input [c, a, x_tau, tau]: x_tau in the state slots, c in the noise slots
+    SlotMap map{d_x, 0, d_c, d_c, 0, d_c + aw};
     std::vector<float> b0(D.b[0], D.b[0] + W);
     std::vector<char> blob = pack_net(D, dt, ddim_in_slots(shape, dt), map, b0, 1, m->net, ddim_split(shape));
-    std::vector<float> fa = fold_columns(D, d_s, aw, dt), ft = fold_columns(D, 2 * d_s + aw, 1, dt);
+    std::vector<float> fa = fold_columns(D, d_c, aw, dt), ft = fold_columns(D, d_c + aw + d_x, 1, dt);
     std::vector<float> fw((size_t)W * (aw + 1));
     for (int o = 0; o < W; ++o) {
         for (int c = 0; c < aw; ++c) fw[(size_t)o * (aw + 1) + c] = fa[(size_t)o * aw + c];

@@ -1272,14 +1272,14 @@ __global__ __launch_bounds__(256) void ddim_prep_kernel(DdimPrepParams p) {
 // the noise slots, n_steps network evaluations.  Small networks run one tile
 // per wave from LDS; deep wide networks are split over the block's four waves
 // with the activations in LDS and the weights read from L2.
-template <int DT, int D_S, int WIDTH, int NHID, int MODE>
+template <int DT, int D_X, int D_C, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
     if constexpr (!net_compiled(DT, WIDTH)) {
         return;  // binary32 networks wider than 256 are refused at creation
     } else {
     constexpr bool SPLIT = MODE == kSplit;
-    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_S), (SPLIT ? WIDTH / 32 : chunk_tiles(WIDTH))> NT;
-    constexpr int SS = state_slots(D_S), SW = noise_slots(D_S);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_X, 0, D_C), (SPLIT ? WIDTH / 32 : chunk_tiles(WIDTH))> NT;
+    constexpr int SS = state_slots(D_X), SW = noise_slots(D_C);
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wpb = blockDim.x >> 6;
@@ -1294,12 +1294,12 @@ __global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
 #pragma unroll
         for (int s = 0; s < SS; ++s) {
             const int f = 2 * s + g;
-            x[s] = (valid && f < D_S) ? p.x1[(size_t)i * D_S + f] : 0.0f;
+            x[s] = (valid && f < D_X) ? p.x1[(size_t)i * D_X + f] : 0.0f;
         }
 #pragma unroll
         for (int s = 0; s < SW; ++s) {
             const int f = noise_feature(s, g);
-            cond[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+            cond[s] = (valid && f < D_C) ? p.states[(size_t)i * D_C + f] : 0.0f;
         }
         __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
         for (int t = 0; t < p.n_steps; ++t) {
@@ -1318,7 +1318,7 @@ __global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
         if (writer && valid)
 #pragma unroll
             for (int s = 0; s < SS; ++s)
-                if (2 * s + g < D_S) p.out[(size_t)i * D_S + 2 * s + g] = x[s];
+                if (2 * s + g < D_X) p.out[(size_t)i * D_X + 2 * s + g] = x[s];
     };
     if constexpr (SPLIT) {
         return;  // deep wide networks run in ddim_split_kernel
@@ -1352,14 +1352,14 @@ __global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
 #endif
 constexpr int kDdimSplitWaves = VOILA_DDIM_SPLIT_WAVES, kDdimSplitTiles = VOILA_DDIM_SPLIT_TILES,
               kDdimSplitDepth = VOILA_DDIM_SPLIT_DEPTH;
-template <int DT, int D_S, int WIDTH, int NHID>
+template <int DT, int D_X, int D_C, int WIDTH, int NHID>
 __global__ __launch_bounds__(64 * kDdimSplitWaves) void ddim_split_kernel(DdimParams p) {
     if constexpr (!net_compiled(DT, WIDTH) || WIDTH <= 64) {
         return;  // small networks run one tile per wave in ddim_kernel
     } else {
     constexpr int ST = kDdimSplitTiles;
-    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_S), WIDTH / 32> NT;
-    constexpr int SS = state_slots(D_S), SW = noise_slots(D_S);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_X, 0, D_C), WIDTH / 32> NT;
+    constexpr int SS = state_slots(D_X), SW = noise_slots(D_C);
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1377,12 +1377,12 @@ __global__ __launch_bounds__(64 * kDdimSplitWaves) void ddim_split_kernel(DdimPa
 #pragma unroll
             for (int s = 0; s < SS; ++s) {
                 const int f = 2 * s + g;
-                x[st][s] = (valid[st] && f < D_S) ? p.x1[(size_t)row[st] * D_S + f] : 0.0f;
+                x[st][s] = (valid[st] && f < D_X) ? p.x1[(size_t)row[st] * D_X + f] : 0.0f;
             }
 #pragma unroll
             for (int s = 0; s < SW; ++s) {
                 const int f = noise_feature(s, g);
-                cond[st][s] = (valid[st] && f < D_S) ? p.states[(size_t)row[st] * D_S + f] : 0.0f;
+                cond[st][s] = (valid[st] && f < D_C) ? p.states[(size_t)row[st] * D_C + f] : 0.0f;
             }
         }
         __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
@@ -1411,7 +1411,7 @@ __global__ __launch_bounds__(64 * kDdimSplitWaves) void ddim_split_kernel(DdimPa
                 if (valid[st])
 #pragma unroll
                     for (int s = 0; s < SS; ++s)
-                        if (2 * s + g < D_S) p.out[(size_t)row[st] * D_S + 2 * s + g] = x[st][s];
+                        if (2 * s + g < D_X) p.out[(size_t)row[st] * D_X + 2 * s + g] = x[st][s];
     }
     }
 }
@@ -1774,21 +1774,21 @@ hipError_t launch_nce_mean(const NceParams& p, hipStream_t s) {
 }
 
 template <int W> constexpr int ddim_mode() { return W <= 64 ? kResident : kSplit; }
-#define DDIM_K(id, ds, w, nh, DT) ddim_kernel<DT, ds, w, nh, ddim_mode<w>()>
-#define DDIM_SK(id, ds, w, nh, DT) ddim_split_kernel<DT, ds, w, nh>
+#define DDIM_K(id, dx, dc, w, nh, DT) ddim_kernel<DT, dx, dc, w, nh, ddim_mode<w>()>
+#define DDIM_SK(id, dx, dc, w, nh, DT) ddim_split_kernel<DT, dx, dc, w, nh>
 
-int ddim_shape(int d_s, int width, int n_hidden) {
-#define X(id, ds, w, nh) \
-    if (d_s == ds && width == w && n_hidden == nh) return id;
+int ddim_shape(int d_x, int d_c, int width, int n_hidden) {
+#define X(id, dx, dc, w, nh) \
+    if (d_x == dx && d_c == dc && width == w && n_hidden == nh) return id;
     VOILA_DDIM_SHAPES(X)
 #undef X
     return -1;
 }
 int ddim_in_slots(int shape, int dt) {
     switch (shape) {
-#define X(id, ds, w, nh) \
-    case id:             \
-        return in_slots(dt, ds, 0, ds);
+#define X(id, dx, dc, w, nh) \
+    case id:                 \
+        return in_slots(dt, dx, 0, dc);
         VOILA_DDIM_SHAPES(X)
 #undef X
     }
@@ -1796,8 +1796,8 @@ int ddim_in_slots(int shape, int dt) {
 }
 bool ddim_split(int shape) {
     switch (shape) {
-#define X(id, ds, w, nh) \
-    case id:             \
+#define X(id, dx, dc, w, nh) \
+    case id:                 \
         return ddim_mode<w>() == kSplit;
         VOILA_DDIM_SHAPES(X)
 #undef X
@@ -1805,12 +1805,12 @@ bool ddim_split(int shape) {
     return false;
 }
 
-template <int DT, int D_S, int W, int NH>
+template <int DT, int D_X, int D_C, int W, int NH>
 constexpr size_t ddim_split_lds() {
     if constexpr (!net_compiled(DT, W)) {
         return 0;
     } else {
-        return (size_t)kDdimSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_S, 0, D_S), W / 32>>::ACT;
+        return (size_t)kDdimSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_X, 0, D_C), W / 32>>::ACT;
     }
 }
 int ddim_tiles_per_block(int shape) { return ddim_split(shape) ? kDdimSplitTiles : kWavesPerBlock; }
@@ -1830,18 +1830,18 @@ void launch_ddim_one(K k, bool split, size_t lds, int blocks, const DdimParams& 
 
 hipError_t launch_ddim(int shape, int dt, const DdimParams& p, int blocks, hipStream_t s) {
     switch (shape * 2 + dt) {
-#define X(id, ds, w, nh)                                                                                       \
+#define X(id, dx, dc, w, nh)                                                                                       \
     case id * 2 + 0:                                                                                          \
         if (ddim_mode<w>() == kSplit)                                                                         \
-            launch_ddim_one(DDIM_SK(id, ds, w, nh, DT_F32), true, ddim_split_lds<DT_F32, ds, w, nh>(), blocks, p, s); \
+            launch_ddim_one(DDIM_SK(id, dx, dc, w, nh, DT_F32), true, ddim_split_lds<DT_F32, dx, dc, w, nh>(), blocks, p, s); \
         else                                                                                                  \
-            launch_ddim_one(DDIM_K(id, ds, w, nh, DT_F32), false, p.net.bytes, blocks, p, s);                  \
+            launch_ddim_one(DDIM_K(id, dx, dc, w, nh, DT_F32), false, p.net.bytes, blocks, p, s);                  \
         break;                                                                                                \
     case id * 2 + 1:                                                                                          \
         if (ddim_mode<w>() == kSplit)                                                                         \
-            launch_ddim_one(DDIM_SK(id, ds, w, nh, DT_BF16), true, ddim_split_lds<DT_BF16, ds, w, nh>(), blocks, p, s); \
+            launch_ddim_one(DDIM_SK(id, dx, dc, w, nh, DT_BF16), true, ddim_split_lds<DT_BF16, dx, dc, w, nh>(), blocks, p, s); \
         else                                                                                                  \
-            launch_ddim_one(DDIM_K(id, ds, w, nh, DT_BF16), false, p.net.bytes, blocks, p, s);                 \
+            launch_ddim_one(DDIM_K(id, dx, dc, w, nh, DT_BF16), false, p.net.bytes, blocks, p, s);                 \
         break;
         VOILA_DDIM_SHAPES(X)
 #undef X
@@ -1853,17 +1853,17 @@ hipError_t launch_ddim(int shape, int dt, const DdimParams& p, int blocks, hipSt
 
 int ddim_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
-#define X(id, ds, w, nh)                                                                                    \
+#define X(id, dx, dc, w, nh)                                                                                    \
     case id * 2 + 0:                                                                                       \
         return ddim_mode<w>() == kSplit                                                                    \
-                   ? occupancy_t(DDIM_SK(id, ds, w, nh, DT_F32), 64 * kDdimSplitWaves,                     \
-                                 ddim_split_lds<DT_F32, ds, w, nh>())                                      \
-                   : occupancy(DDIM_K(id, ds, w, nh, DT_F32), kLdsGuess);                                  \
+                   ? occupancy_t(DDIM_SK(id, dx, dc, w, nh, DT_F32), 64 * kDdimSplitWaves,                     \
+                                 ddim_split_lds<DT_F32, dx, dc, w, nh>())                                      \
+                   : occupancy(DDIM_K(id, dx, dc, w, nh, DT_F32), kLdsGuess);                                  \
     case id * 2 + 1:                                                                                       \
         return ddim_mode<w>() == kSplit                                                                    \
-                   ? occupancy_t(DDIM_SK(id, ds, w, nh, DT_BF16), 64 * kDdimSplitWaves,                    \
-                                 ddim_split_lds<DT_BF16, ds, w, nh>())                                     \
-                   : occupancy(DDIM_K(id, ds, w, nh, DT_BF16), kLdsGuess);
+                   ? occupancy_t(DDIM_SK(id, dx, dc, w, nh, DT_BF16), 64 * kDdimSplitWaves,                    \
+                                 ddim_split_lds<DT_BF16, dx, dc, w, nh>())                                     \
+                   : occupancy(DDIM_K(id, dx, dc, w, nh, DT_BF16), kLdsGuess);
         VOILA_DDIM_SHAPES(X)
 #undef X
     }

@@ -183,15 +183,15 @@ struct NceParams {
     int B, d_o;
 };
 
-// Teacher sampler of a v-prediction transition denoiser (input [s, a,
-// x_tau, tau], output v): n_steps deterministic DDIM steps per sample.
+// Teacher sampler of a v-prediction denoiser (input [c, a, x_tau, tau],
+// output v): n_steps deterministic DDIM steps per sample.
 struct DdimParams {
-    NetBlob net;          // state slots: x_tau; noise slots: the conditioning state
-    const float* states;  // [N][d_s] conditioning states
-    const float* x1;      // [N][d_s] latent noise at tau = 1
+    NetBlob net;          // state slots: x_tau; noise slots: the conditioning input
+    const float* states;  // [N][d_c] conditioning inputs
+    const float* x1;      // [N][d_x] latent noise at tau = 1
     const float* b0;      // [n_steps][width] first-layer biases with the action and tau_k folded in
     const float* coef;    // [n_steps][2]: x <- coef[0] x + coef[1] v
-    float* out;           // [N][d_s]
+    float* out;           // [N][d_x]
     int N, n_steps;
 };
 struct DdimPrepParams {
@@ -346,13 +346,15 @@ hipError_t launch_nce_scores(int shape, int dt, const NceParams& p, int blocks, 
 int nce_scores_blocks_per_cu(int shape, int dt);
 hipError_t launch_nce_rows(const NceParams& p, int blocks, hipStream_t s);
 hipError_t launch_nce_mean(const NceParams& p, hipStream_t s);
-// Denoiser shapes of the teacher sampler: (id, d_s, width, hidden layers).
+// Denoiser shapes of the teacher sampler: (id, denoised width d_x,
+// conditioning width d_c, hidden width, hidden layers).
 #define VOILA_DDIM_SHAPES(X) \
-    X(0, 4, 64, 2)           \
-    X(1, 4, 1024, 5)         \
-    X(2, 4, 1024, 4)
-constexpr int kNumDdimShapes = 3;
-int ddim_shape(int d_s, int width, int n_hidden);  // -1 when not compiled
+    X(0, 4, 4, 64, 2)        \
+    X(1, 4, 4, 1024, 5)      \
+    X(2, 4, 4, 1024, 4)      \
+    X(3, 32, 16, 512, 5)
+constexpr int kNumDdimShapes = 4;
+int ddim_shape(int d_x, int d_c, int width, int n_hidden);  // -1 when not compiled
 int ddim_in_slots(int shape, int dt);
 bool ddim_split(int shape);                        // evaluated by all waves of a block per group of tiles
 int ddim_tiles_per_block(int shape);

@@ -111,5 +111,5 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert L.voila_info_nce_workspace_size(None, 4) == 0
     assert L.voila_ddim_sample(None, None, None, None, 4, 4, None, 0, None, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_ddim_workspace_size(None, 4) == 0
-    assert L.voila_denoiser_create(None, 4, 5, 0, 0, 0, None) == V.VOILA_ERR_INVALID_ARG
+    assert L.voila_denoiser_create(None, 4, 4, 5, 0, 0, 0, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_denoiser_destroy(None) == V.VOILA_OK

@@ -875,22 +875,22 @@ def test_ddim_recovers_a_point_mass_exactly(n_steps):
 def test_ddim_one_step_is_minus_v_at_tau_one(n_actions, d_a):
     # one step from tau = 1 (abar = 0) to tau = 0 (abar = 1): the sample is the
     # clean estimate sqrt(abar) x - sqrt(1 - abar) v = -v([s, a, x1, 1])
-    layers = workloads.denoiser(seed=5, d_s=3, n_actions=n_actions, d_a=d_a, width=16, n_hidden=3)
-    S, X1 = workloads.ddim_batch(9, d_s=3, seed=6)
+    layers = workloads.denoiser(seed=5, d_c=5, d_x=3, n_actions=n_actions, d_a=d_a, width=16, n_hidden=3)
+    S, X1 = workloads.ddim_batch(9, d_c=5, d_x=3, seed=6)
     a = 2 if n_actions else np.array([0.5, -0.25, 1.0], np.float32)
-    out = oracle.ddim_sample(layers, 3, n_actions, d_a, S, a, X1, 1)
+    out = oracle.ddim_sample(layers, 5, 3, n_actions, d_a, S, a, X1, 1)
     A = np.tile(np.eye(n_actions)[a] if n_actions else a, (9, 1))
     X = np.concatenate([S, A, X1, np.ones((9, 1))], axis=1).astype(np.float64)
     np.testing.assert_allclose(out, -_numpy_mlp(layers, X), rtol=1e-12, atol=1e-12)
 
 
 def test_ddim_zero_denoiser_single_step_and_rows_independent():
-    layers = workloads.denoiser(seed=7, d_s=4, width=8, n_hidden=2)
+    layers = workloads.denoiser(seed=7, width=8, n_hidden=2)
     zero = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
     S, X1 = workloads.ddim_batch(5, seed=8)
     # v = 0 and abar(1) = 0: one step erases the noise
-    np.testing.assert_allclose(oracle.ddim_sample(zero, 4, 5, 0, S, 1, X1, 1), 0.0, atol=1e-15)
+    np.testing.assert_allclose(oracle.ddim_sample(zero, 4, 4, 5, 0, S, 1, X1, 1), 0.0, atol=1e-15)
     # rows are independent samples
-    full = oracle.ddim_sample(layers, 4, 5, 0, S, 1, X1, 12)
-    part = oracle.ddim_sample(layers, 4, 5, 0, S[2:4], 1, X1[2:4], 12)
+    full = oracle.ddim_sample(layers, 4, 4, 5, 0, S, 1, X1, 12)
+    part = oracle.ddim_sample(layers, 4, 4, 5, 0, S[2:4], 1, X1[2:4], 12)
     np.testing.assert_array_equal(full[2:4], part)

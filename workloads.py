@@ -226,14 +226,14 @@ def nce_batch(w: Workload, B: int, seed: int = 14):
     return S, A, O
 
 
-def denoiser(seed: int = 21, d_s: int = 4, n_actions: int = 5, d_a: int = 0, width: int = 1024,
+def denoiser(seed: int = 21, d_c: int = 4, d_x: int = 4, n_actions: int = 5, d_a: int = 0, width: int = 1024,
              n_hidden: int = 5) -> List[Layer]:
-    """Random v-prediction denoiser layers (input [s, a, x_tau, tau], output
-    [d_s]): hidden weights N(0, 2/fan_in), the output layer N(0, 1/fan_in),
-    biases N(0, 0.01)."""
+    """Random v-prediction denoiser layers (input [c, a, x_tau, tau] with the
+    conditioning input c of width d_c, output [d_x]): hidden weights
+    N(0, 2/fan_in), the output layer N(0, 1/fan_in), biases N(0, 0.01)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     aw = n_actions if n_actions > 0 else d_a
-    dims = [2 * d_s + aw + 1] + [width] * n_hidden + [d_s]
+    dims = [d_c + aw + d_x + 1] + [width] * n_hidden + [d_x]
     layers = []
     for li, (n_in, n_out) in enumerate(zip(dims[:-1], dims[1:])):
         sd = np.sqrt((1.0 if li == len(dims) - 2 else 2.0) / n_in)
@@ -243,7 +243,7 @@ def denoiser(seed: int = 21, d_s: int = 4, n_actions: int = 5, d_a: int = 0, wid
     return layers
 
 
-def ddim_batch(n: int, d_s: int = 4, seed: int = 22):
-    """Conditioning states [n, d_s] ~ N(0, 1) and latent noise at tau = 1 [n, d_s] ~ N(0, 1), float32."""
+def ddim_batch(n: int, d_c: int = 4, d_x: int = 4, seed: int = 22):
+    """Conditioning inputs [n, d_c] ~ N(0, 1) and latent noise at tau = 1 [n, d_x] ~ N(0, 1), float32."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return (rng.standard_normal((n, d_s)).astype(np.float32), rng.standard_normal((n, d_s)).astype(np.float32))
+    return (rng.standard_normal((n, d_c)).astype(np.float32), rng.standard_normal((n, d_x)).astype(np.float32))
