@@ -71,6 +71,7 @@ def lib():
                                     dp, dp]
         L.or_info_nce_rows.argtypes = [c_int, c_int, i32p, dp, dp, dp]
         L.or_info_nce.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, i32p, c_int, dp, dp, dp, dp]
+        L.or_info_nce_param_grad.argtypes = [mp, c_int, dp, i32p, dp, dp, dp, dp]
         L.or_cosine_abar.argtypes = [c_double]
         L.or_cosine_abar.restype = c_double
         L.or_ddim_sample.argtypes = [c_int, ip, dp, c_int, c_int, c_int, c_int, c_int, dp, c_int, dp, dp, c_int, c_int,
@@ -405,6 +406,25 @@ def info_nce(model, states, actions, obs, rows=None, bf16=False):
     if rw is None:
         out["loss"] = float(loss[0])
     return out
+
+
+def info_nce_param_grad(model, states, actions, obs):
+    """(loss, gradient) of the InfoNCE loss with respect to the likelihood
+    network's parameters, packed per layer as W (row-major [out, in]) then b."""
+    S = _d(states)
+    B = S.shape[0]
+    O = _d(np.asarray(obs).reshape(B, model.d_o))
+    if model.n_actions > 0:
+        a_disc, a_cont = np.ascontiguousarray(np.asarray(actions, np.int32).reshape(B)), None
+    else:
+        a_disc, a_cont = None, _d(np.asarray(actions).reshape(B, model.d_a))
+    dims, _ = flatten_layers(model.lik)
+    g = np.zeros(int(lib().or_mlp_param_count(len(model.lik), dims.ctypes.data_as(POINTER(c_int)))))
+    loss = np.zeros(1)
+    b = _Bound(model)
+    _check(lib().or_info_nce_param_grad(b.ref(), B, _p(S), _p(a_disc, c_int32), _p(a_cont), _p(O), _p(g),
+                                        _p(loss)), "info_nce_param_grad")
+    return float(loss[0]), g
 
 
 def cosine_abar(tau):

@@ -39,8 +39,9 @@
  *             candidates' preferences, with a reference-policy prior.
  *   info_nce  The contrastive objective of the likelihood network (Sec. 4.2,
  *             Eq. 6): scores of all B x B state-action / observation pairs of
- *             a mini-batch, per-row log-sum-exp losses, their mean and its
- *             derivative with respect to every score.
+ *             a mini-batch, per-row log-sum-exp losses, their mean, its
+ *             derivative with respect to every score and, by reverse mode
+ *             through the network, with respect to its parameters.
  *   ddim      The teacher sampler of the transition model (Sec. 4.2): the
  *             deterministic DDIM sampler (Song, Meng, Ermon, "Denoising
  *             diffusion implicit models", ICLR 2021) of a v-prediction
@@ -73,6 +74,7 @@
 #define OR_ERR_NUMERIC 2
 
 #define OR_MAX_WIDTH 4096
+#define OR_MAX_LAYERS 8
 
 /* ------------------------------------------------------------------------- */
 /* Philox4x32-10 (SC'11 paper: Philox-4x32 with R = 10 rounds).              */
@@ -1312,4 +1314,68 @@ int or_ddim_point_mass(int d, const double* x0, const double* x1, int n_steps, d
     for (int j = 0; j < d; ++j) out[j] = x1[j];
     ddim_run(d, x0, out, n_steps, ddim_point_v, &d);
     return OR_OK;
+}
+
+/* Derivative of the InfoNCE loss (Eq. 6) with respect to the likelihood
+ * network's parameters (packed per layer as W then b, the layout of the
+ * parameter vector): sum over all pairs of G_ij times the derivative of
+ * l([s'_i, a_i, o_j]), by reverse mode through the network (ReLU'(0) = 0),
+ * accumulated in pair order.  Also returns the loss. */
+int or_info_nce_param_grad(const or_model* m, int B, const double* S, const int32_t* a_disc, const double* a_cont,
+                           const double* O, double* grad, double* loss)
+{
+    if (B < 1 || mlp_check(m->l_layers, m->l_dims) != OR_OK || m->l_layers > OR_MAX_LAYERS) return OR_ERR_ARG;
+    const int L = m->l_layers, d_s = m->d_s, d_o = m->d_o, aw = action_width(m);
+    const int* dims = m->l_dims;
+    if (dims[0] != d_s + aw + d_o || dims[L] != 1) return OR_ERR_ARG;
+    const size_t np = mlp_param_count(L, dims);
+    double* Lg = (double*)malloc(sizeof(double) * (size_t)B * B);
+    double* G = (double*)malloc(sizeof(double) * (size_t)B * B);
+    double* rl = (double*)malloc(sizeof(double) * (size_t)B);
+    if (!Lg || !G || !rl) { free(Lg); free(G); free(rl); return OR_ERR_ARG; }
+    int rc = or_info_nce(m, B, S, a_disc, a_cont, O, B, NULL, 0, Lg, rl, G, loss);
+    for (size_t q = 0; q < np; ++q) grad[q] = 0.0;
+    /* activations of every layer for one pair: act[l] is layer l's input */
+    double act[OR_MAX_LAYERS + 1][OR_MAX_WIDTH], delta[OR_MAX_WIDTH], prev[OR_MAX_WIDTH];
+    for (long e = 0; rc == OR_OK && e < (long)B * B; ++e) {
+        const int i = (int)(e / B), j = (int)(e % B);
+        double* x = act[0];
+        for (int c = 0; c < d_s; ++c) x[c] = S[(size_t)i * d_s + c];
+        put_action(m, x + d_s, a_disc ? a_disc[i] : 0, a_cont ? a_cont + (size_t)i * m->d_a : NULL);
+        for (int c = 0; c < d_o; ++c) x[d_s + aw + c] = O[(size_t)j * d_o + c];
+        const double* p = m->l_params;
+        for (int l = 0; l < L; ++l) {
+            const int n_in = dims[l], n_out = dims[l + 1];
+            for (int n = 0; n < n_out; ++n) {
+                double acc = 0.0;
+                for (int k = 0; k < n_in; ++k) acc += p[(size_t)n * n_in + k] * act[l][k];
+                acc += p[(size_t)n_out * n_in + n];
+                act[l + 1][n] = (l < L - 1 && acc < 0.0) ? 0.0 : acc;
+            }
+            p += (size_t)n_out * n_in + n_out;
+        }
+        /* reverse sweep: delta = d loss / d (pre-activation of layer l) */
+        delta[0] = G[e];
+        size_t off = np;
+        for (int l = L - 1; l >= 0; --l) {
+            const int n_in = dims[l], n_out = dims[l + 1];
+            off -= (size_t)n_out * n_in + n_out;
+            const double* W = m->l_params + off;
+            double* gW = grad + off;
+            for (int n = 0; n < n_out; ++n) {
+                for (int k = 0; k < n_in; ++k) gW[(size_t)n * n_in + k] += delta[n] * act[l][k];
+                gW[(size_t)n_out * n_in + n] += delta[n];
+            }
+            if (l > 0) {
+                for (int k = 0; k < n_in; ++k) {
+                    double acc = 0.0;
+                    for (int n = 0; n < n_out; ++n) acc += W[(size_t)n * n_in + k] * delta[n];
+                    prev[k] = act[l][k] > 0.0 ? acc : 0.0;
+                }
+                for (int k = 0; k < n_in; ++k) delta[k] = prev[k];
+            }
+        }
+    }
+    free(Lg); free(G); free(rl);
+    return rc;
 }

@@ -894,3 +894,44 @@ def test_ddim_zero_denoiser_single_step_and_rows_independent():
     full = oracle.ddim_sample(layers, 4, 4, 5, 0, S, 1, X1, 12)
     part = oracle.ddim_sample(layers, 4, 4, 5, 0, S[2:4], 1, X1[2:4], 12)
     np.testing.assert_array_equal(full[2:4], part)
+
+
+def _flat_lik(m):
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in m.lik]).astype(np.float64)
+
+
+def _with_flat_lik(m, theta):
+    layers, off = [], 0
+    for W, b in m.lik:
+        nW, nb = W.size, b.size
+        layers.append((theta[off:off + nW].reshape(W.shape), theta[off + nW:off + nW + nb]))
+        off += nW + nb
+    return Model(**{**m.__dict__, "lik": layers})
+
+
+@pytest.mark.parametrize("which", ["small", "continuous"])
+def test_info_nce_param_grad_matches_finite_differences(which):
+    w = workloads.small(seed=93, N=16) if which == "small" else workloads.continuous(seed=94, N=16)
+    m = w.model
+    S, A, O = workloads.nce_batch(w, 9, seed=3)
+    loss, g = oracle.info_nce_param_grad(m, S, A, O)
+    assert loss == pytest.approx(oracle.info_nce(m, S, A, O)["loss"], rel=1e-14)
+    theta = _flat_lik(m)
+    # the output bias shifts every score equally: its derivative is zero
+    assert abs(g[-1]) < 1e-14
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    checked = 0
+    for q in rng.choice(theta.size - 1, 40, replace=False):
+        tp, tm = theta.copy(), theta.copy()
+        tp[q] += h
+        tm[q] -= h
+        fp = oracle.info_nce(_with_flat_lik(m, tp), S, A, O)["loss"]
+        fm = oracle.info_nce(_with_flat_lik(m, tm), S, A, O)["loss"]
+        f2 = oracle.info_nce(_with_flat_lik(m, theta), S, A, O)["loss"]
+        # skip coordinates whose step crosses a ReLU kink (one-sided slopes differ)
+        if abs((fp - f2) / h - (f2 - fm) / h) > 1e-4 * max(1.0, abs(g[q])):
+            continue
+        assert g[q] == pytest.approx((fp - fm) / (2 * h), abs=1e-7, rel=1e-5), q
+        checked += 1
+    assert checked >= 30
