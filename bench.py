@@ -371,6 +371,26 @@ def bench_info_nce(V, torch, reps):
                         "mfma_frac": f_pair * pairs / (t / 1e3) / 1e12 / peak,
                         "loss": float(res["loss"].item())}
         print(f"[bench]   {compute}: {t:.3f} ms", file=sys.stderr, flush=True)
+    # the derivative with respect to the network's parameters, small binary32
+    # networks (11 -> 64 -> 64 -> 1), the same B
+    ws_small = workloads.small(seed=9)
+    S2, A2, O2 = (torch.as_tensor(x, device=dev) for x in workloads.nce_batch(ws_small, B, seed=18))
+    m2 = V.Model(ws_small.model, compute="f32")
+    ws2 = torch.empty(int(V.lib.voila_info_nce_grad_workspace_size(m2.handle, B)), dtype=torch.uint8, device=dev)
+    res2 = None
+    ms = []
+    for r in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        res2 = V.info_nce_grad(m2, S2, A2, O2, out=res2, workspace=ws2)
+        b.record(stream)
+        torch.cuda.synchronize()
+        if r > 0:
+            ms.append(a.elapsed_time(b))
+    t = float(np.median(ms))
+    out["small_param_grad_f32"] = {"ms": t, "pairs_per_s": pairs / (t / 1e3),
+                                   "n_params": int(res2["grad"].numel())}
+    print(f"[bench]   small-network parameter derivative f32: {t:.3f} ms", file=sys.stderr, flush=True)
     return out
 
 

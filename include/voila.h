@@ -275,6 +275,25 @@ voila_status_t voila_info_nce(voila_model_t model, const float* d_states, const 
                               float* d_scores_out, double* d_row_loss_out, float* d_grad_out, double* d_loss_out,
                               int32_t* d_status, void* stream);
 
+/* The derivative of the same loss with respect to the likelihood network's
+ * parameters: sum over all B^2 pairs of G_ij times the derivative of
+ * l([s'_i, a_i, o_j]) (reverse mode through the network, ReLU'(0) = 0),
+ * written to d_param_grad_out [voila_info_nce_param_count(model)] float in
+ * the layout of the network description (per layer W row-major [out][in],
+ * then b); the loss goes to d_loss_out [1] double (or NULL).  Compiled for
+ * binary32 likelihood networks with two hidden layers of width 64 over the
+ * small shapes (d_s = 4, d_o = 2, five discrete or four continuous action
+ * inputs); voila_info_nce_param_count returns 0 and voila_info_nce_grad
+ * VOILA_ERR_UNSUPPORTED for other models.  Per-wave partial sums are
+ * reduced in a fixed order (repeatable).  Workspace:
+ * voila_info_nce_grad_workspace_size.
+ */
+int32_t voila_info_nce_param_count(voila_model_t model);
+size_t voila_info_nce_grad_workspace_size(voila_model_t model, int32_t B);
+voila_status_t voila_info_nce_grad(voila_model_t model, const float* d_states, const void* d_actions,
+                                   const float* d_obs, int32_t B, void* d_workspace, size_t workspace_bytes,
+                                   double* d_loss_out, float* d_param_grad_out, int32_t* d_status, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Teacher samplers of the learned generators (Sec. 4.2): a conditional
  * v-prediction denoiser v(c, a, x_tau, tau) run by the deterministic (ODE)

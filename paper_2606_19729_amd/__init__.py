@@ -162,6 +162,12 @@ def _load():
     L.voila_info_nce_workspace_size.restype = c_size_t
     L.voila_info_nce.argtypes = [vp, vp, vp, vp, c_int32, vp, c_size_t, vp, vp, vp, vp, vp, vp]
     L.voila_info_nce.restype = c_int32
+    L.voila_info_nce_param_count.argtypes = [vp]
+    L.voila_info_nce_param_count.restype = c_int32
+    L.voila_info_nce_grad_workspace_size.argtypes = [vp, c_int32]
+    L.voila_info_nce_grad_workspace_size.restype = c_size_t
+    L.voila_info_nce_grad.argtypes = [vp, vp, vp, vp, c_int32, vp, c_size_t, vp, vp, vp, vp]
+    L.voila_info_nce_grad.restype = c_int32
     L.voila_denoiser_create.argtypes = [POINTER(_Mlp), c_int32, c_int32, c_int32, c_int32, c_int32, c_int32,
                                         POINTER(vp)]
     L.voila_denoiser_create.restype = c_int32
@@ -204,7 +210,8 @@ EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_m
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_plan_observe_workspace_size",
             "voila_plan_observe", "voila_pw_step_workspace_size", "voila_pw_step", "voila_soft_value",
             "voila_plan_closed_loop_workspace_size", "voila_plan_closed_loop",
-            "voila_info_nce_workspace_size", "voila_info_nce", "voila_denoiser_create", "voila_denoiser_destroy",
+            "voila_info_nce_workspace_size", "voila_info_nce", "voila_info_nce_param_count",
+            "voila_info_nce_grad_workspace_size", "voila_info_nce_grad", "voila_denoiser_create", "voila_denoiser_destroy",
             "voila_ddim_workspace_size", "voila_ddim_sample",
             "voila_philox_normals",
             "voila_batch_create", "voila_batch_destroy", "voila_batch_run", "voila_batch_capture",
@@ -485,6 +492,35 @@ def info_nce(model: Model, states, actions, obs, want_scores=True, want_grad=Tru
     _check(lib.voila_info_nce(model.handle, _ptr(states), _ptr(actions), _ptr(obs), B, _ptr(workspace),
                               workspace.numel(), _ptr(res["scores"]), _ptr(res["row_loss"]), _ptr(res["grad"]),
                               _ptr(res["loss"]), _ptr(status), _stream(stream)))
+    return res
+
+
+def info_nce_grad(model: Model, states, actions, obs, out=None, workspace=None, status=None, stream=None):
+    """Derivative of the contrastive objective with respect to the likelihood
+    network's parameters (binary32 width-64 two-hidden-layer networks of the
+    small shapes).  Returns dict(loss [1] float64, grad [n_params] float32,
+    per layer W [out, in] row-major then b)."""
+    d = model.desc
+    B = int(states.shape[0])
+    _dev(states, torch.float32, (B, d.d_s), "states")
+    if d.n_actions > 0:
+        _dev(actions, torch.int32, (B,), "actions")
+    else:
+        _dev(actions, torch.float32, (B, d.d_a), "actions")
+    _dev(obs, torch.float32, (B, d.d_o), "obs")
+    n_params = int(lib.voila_info_nce_param_count(model.handle))
+    if n_params == 0:
+        raise VoilaError(VOILA_ERR_UNSUPPORTED, "no compiled parameter derivative for this likelihood network")
+    dev = states.device
+    o = out if out is not None else {}
+    res = {"loss": o.get("loss", torch.empty(1, dtype=torch.float64, device=dev)),
+           "grad": o.get("grad", torch.empty(n_params, dtype=torch.float32, device=dev))}
+    if workspace is None:
+        n = lib.voila_info_nce_grad_workspace_size(model.handle, B)
+        workspace = torch.empty(max(int(n), 1), dtype=torch.uint8, device=dev)
+    _check(lib.voila_info_nce_grad(model.handle, _ptr(states), _ptr(actions), _ptr(obs), B, _ptr(workspace),
+                                   workspace.numel(), _ptr(res["loss"]), _ptr(res["grad"]), _ptr(status),
+                                   _stream(stream)))
     return res
 
 

@@ -248,6 +248,10 @@ struct voila_model_s {
     bool has_grad = false;
     NetBlob grad_fwd{}, grad_bwd{};
     int grad_bpc = 1, n_params = 0;
+    bool has_nce_grad = false;       // parameter derivative of the contrastive objective compiled
+    NetBlob lik_bwd{};               // transposed likelihood pack
+    const float* lik_w3 = nullptr;   // [width] output-layer weights of the likelihood network
+    int nce_grad_bpc = 1, n_lik_params = 0;
     int action_width() const { return n_actions > 0 ? n_actions : d_a; }
 };
 
@@ -255,6 +259,9 @@ namespace {
 constexpr int kGradWaves = 4;
 size_t grad_lds_bytes(const voila_model_s* m) {
     return (size_t)m->grad_fwd.bytes + m->grad_bwd.bytes + (size_t)kGradWaves * 32 * 129 * sizeof(float);
+}
+size_t nce_grad_lds_bytes(const voila_model_s* m) {
+    return (size_t)m->lik_nce.bytes + m->lik_bwd.bytes + (size_t)kGradWaves * 32 * 129 * sizeof(float);
 }
 }  // namespace
 
@@ -410,6 +417,14 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     } else {
         blobs.emplace_back();
     }
+    // transposed likelihood pack for the objective's parameter derivative
+    m->has_nce_grad = L.present() && nce_grad_supported(shape) && dt == DT_F32;
+    if (m->has_nce_grad) {
+        blobs.push_back(pack_bwd(L, m->lik_bwd));
+        for (int l = 0; l < L.n_layers; ++l) m->n_lik_params += L.dims[l + 1] * L.dims[l] + L.dims[l + 1];
+    } else {
+        blobs.emplace_back();
+    }
     const size_t nb = blobs.size();
     std::vector<std::vector<float>> folds;
     m->nf_trans = aw;
@@ -434,7 +449,9 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
             for (int c = 0; c < m->d_s; ++c) fn[(size_t)o * (aw + m->d_s) + aw + c] = fs[(size_t)o * m->d_s + c];
         }
         folds.push_back(fn);
+        folds.push_back(std::vector<float>(L.W[L.n_layers - 1], L.W[L.n_layers - 1] + W));
     } else {
+        folds.emplace_back();
         folds.emplace_back();
         folds.emplace_back();
         folds.emplace_back();
@@ -470,6 +487,7 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->grad_fwd.base = m->mem + offs[4];
     m->grad_bwd.base = m->mem + offs[5];
     m->lik_nce.base = m->mem + offs[6];
+    m->lik_bwd.base = m->mem + offs[7];
     m->fold_w_trans = reinterpret_cast<const float*>(m->mem + offs[nb + 0]);
     m->fold_b_trans = reinterpret_cast<const float*>(m->mem + offs[nb + 1]);
     m->fold_w_obs = reinterpret_cast<const float*>(m->mem + offs[nb + 2]);
@@ -477,6 +495,7 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->fold_w_lik = reinterpret_cast<const float*>(m->mem + offs[nb + 4]);
     m->fold_b_lik = reinterpret_cast<const float*>(m->mem + offs[nb + 5]);
     m->fold_w_nce = reinterpret_cast<const float*>(m->mem + offs[nb + 6]);
+    m->lik_w3 = reinterpret_cast<const float*>(m->mem + offs[nb + 7]);
 
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->cus = prop.multiProcessorCount;
@@ -486,6 +505,7 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->obs_roll_bpc = observe_rollout_blocks_per_cu(shape, dt);
     m->pw_bpc = pw_lik_blocks_per_cu(shape, dt);
     m->nce_bpc = nce_scores_blocks_per_cu(shape, dt);
+    if (m->has_nce_grad) m->nce_grad_bpc = nce_grad_blocks_per_cu(shape, nce_grad_lds_bytes(m));
     if (m->has_grad) m->grad_bpc = grad_blocks_per_cu(shape, grad_lds_bytes(m));
     *out = m;
     return VOILA_OK;
@@ -1275,6 +1295,82 @@ voila_status_t voila_ddim_sample(voila_denoiser_t m, const float* d_states, cons
     const long want = (tiles + tpb - 1) / tpb;
     const long cap = (long)m->cus * m->bpc;
     VOILA_CHECK_HIP(launch_ddim(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));
+    return VOILA_OK;
+}
+
+int32_t voila_info_nce_param_count(voila_model_t m) { return m && m->has_nce_grad ? m->n_lik_params : 0; }
+
+namespace {
+struct NceGradWs {
+    char* nce;
+    size_t nce_bytes;
+    float* G;
+    float* wpart;
+    int blocks;
+    size_t bytes;
+};
+NceGradWs carve_nce_grad(char* base, voila_model_t m, int B) {
+    NceGradWs w{};
+    w.nce = base;
+    w.nce_bytes = voila_info_nce_workspace_size(m, B);
+    size_t off = align_up(w.nce_bytes, 256);
+    w.G = reinterpret_cast<float*>(base + off);
+    off = align_up(off + (size_t)B * B * 4, 256);
+    const long units = (long)B * ((B + 31) / 32);
+    const long want = (units + kGradWaves - 1) / kGradWaves;
+    const long cap = (long)m->cus * m->nce_grad_bpc;
+    w.blocks = (int)(want < cap ? want : cap);
+    w.wpart = reinterpret_cast<float*>(base + off);
+    off = align_up(off + (size_t)w.blocks * kGradWaves * m->n_lik_params * 4, 256);
+    w.bytes = off;
+    return w;
+}
+}  // namespace
+
+size_t voila_info_nce_grad_workspace_size(voila_model_t m, int32_t B) {
+    if (!m || !m->has_nce_grad || B < 1 || B > kNceMaxBatch) return 0;
+    return carve_nce_grad(nullptr, m, B).bytes;
+}
+
+voila_status_t voila_info_nce_grad(voila_model_t m, const float* d_states, const void* d_actions, const float* d_obs,
+                                   int32_t B, void* ws, size_t ws_bytes, double* d_loss_out, float* d_param_grad_out,
+                                   int32_t* d_status, void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (!m->has_nce_grad)
+        return fail(VOILA_ERR_UNSUPPORTED,
+                    "the parameter derivative is compiled for binary32 width-64 likelihood networks of the small shapes");
+    if (B < 1) return fail(VOILA_ERR_INVALID_ARG, "B must be >= 1");
+    if (B > kNceMaxBatch) return fail(VOILA_ERR_UNSUPPORTED, "B must be <= 32768");
+    if (!d_states || !d_actions || !d_obs || !d_param_grad_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
+    NceGradWs w = carve_nce_grad(reinterpret_cast<char*>(ws), m, B);
+    if (!ws || ws_bytes < w.bytes) return fail(VOILA_ERR_WORKSPACE, "contrastive-gradient workspace too small");
+    voila_status_t st = voila_info_nce(m, d_states, d_actions, d_obs, B, w.nce, w.nce_bytes, nullptr, nullptr, w.G,
+                                       d_loss_out, d_status, stream);
+    if (st != VOILA_OK) return st;
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    NceWs nw = carve_nce(reinterpret_cast<char*>(w.nce), m, B);
+    NceGradParams p{};
+    p.fwd = m->lik_nce;
+    p.bwd = m->lik_bwd;
+    p.w3 = m->lik_w3;
+    p.b0 = nw.b0;
+    p.obs = d_obs;
+    p.states = d_states;
+    p.actions = d_actions;
+    p.grad = w.G;
+    p.wpart = w.wpart;
+    p.status = d_status;
+    p.B = B;
+    p.n_params = m->n_lik_params;
+    VOILA_CHECK_HIP(launch_nce_grad(m->shape, p, w.blocks, nce_grad_lds_bytes(m), s));
+    GradReduceParams r{};
+    r.wpart = w.wpart;
+    r.grad_params = d_param_grad_out;
+    r.n_params = m->n_lik_params;
+    r.n_waves = w.blocks * kGradWaves;
+    VOILA_CHECK_HIP(launch_grad_reduce(r, s));
     return VOILA_OK;
 }
 

@@ -412,6 +412,193 @@ __global__ __launch_bounds__(256) void grad_reduce_kernel(GradReduceParams p) {
     }
 }
 
+// Parameter derivative of the contrastive objective (Eq. 6): for every pair
+// (i, j) the likelihood network is re-run on [s'_i, a_i, o_j] (row i's state
+// and action folded into its first-layer bias row, the observation in the
+// input slots) and its parameters' derivative is accumulated with weight
+// G_ij = d loss / d l_ij.  One wave owns a (row i, 32 observations) tile; the
+// output layer is a dot product, so its adjoint is w3 * G_ij on the active
+// units; the hidden adjoints use the transposed pack; the weight gradients
+// are products over the tile's 32 pairs through the wave's LDS scratch, the
+// first layer's over the full input [s'_i, a_i, o_j, 1] (column 31 carries
+// the bias).  Each wave writes its partial once; grad_reduce_kernel sums them
+// in a fixed order.
+template <int D_S, int N_ACT, int D_A, int D_O>
+__global__ __launch_bounds__(256) void nce_grad_kernel(NceGradParams p) {
+    constexpr int WIDTH = 64, NHID = 2, HT = 2;
+    constexpr int D_AIN = N_ACT > 0 ? N_ACT : D_A;
+    constexpr int D_IN = D_S + D_AIN + D_O;
+    static_assert(D_IN <= 31, "inputs must fit one 32-row tile (column 31 carries the bias)");
+    typedef Net<DT_F32, WIDTH, NHID, in_slots(DT_F32, D_O, 0, 0)> NT;
+    typedef BwdIdx<1, HT> BI;
+    constexpr int SO = state_slots(D_O);
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    stage_blob(smem, p.fwd.base, p.fwd.bytes);
+    stage_blob(smem + p.fwd.bytes, p.bwd.base, p.bwd.bytes);
+    __syncthreads();
+    const NetPtrs P = net_ptrs(smem, p.fwd);
+    const char* bw = smem + p.fwd.bytes;
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6;
+    float* scr = reinterpret_cast<float*>(smem + p.fwd.bytes + p.bwd.bytes) + wave * 32 * kRow;
+
+    f32x16 gW1[HT], gW2[HT][HT], gb2[HT], gw3[HT];
+#pragma unroll
+    for (int a = 0; a < HT; ++a) {
+        gW1[a] = f32x16{};
+        gb2[a] = f32x16{};
+        gw3[a] = f32x16{};
+#pragma unroll
+        for (int b = 0; b < HT; ++b) gW2[a][b] = f32x16{};
+    }
+    float gb3 = 0.0f;
+
+    const int B = p.B, jtiles = (B + 31) / 32;
+    const long n_units = (long)B * jtiles;
+    for (long u = (long)blockIdx.x * wpb + wave; u < n_units; u += (long)gridDim.x * wpb) {
+        const int i = (int)(u / jtiles);
+        const int j = (int)(u - (long)i * jtiles) * 32 + col;
+        const bool valid = j < B;
+        float slots[NT::IN_SLOTS];
+#pragma unroll
+        for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SO; ++s) {
+            const int f = 2 * s + g;
+            slots[s] = (valid && f < D_O) ? p.obs[(size_t)j * D_O + f] : 0.0f;
+        }
+        // forward: the two hidden layers' activations of the tile
+        f32x16 acc[HT];
+        Act<DT_F32, HT> h1, h2;
+        {
+            DirectSrc<DT_F32, 8 * HT> src(P.f0);
+            init_bias<HT>(acc, p.b0 + (size_t)i * WIDTH, g);
+#pragma unroll
+            for (int c = 0; c < NT::IN_KS; ++c)
+#pragma unroll
+                for (int mt = 0; mt < HT; ++mt)
+                    acc[mt] = mfma(src.load(FragIdx<NT>::first(c, mt), lane), slots[c], acc[mt]);
+            h1.set_relu(acc);
+            init_bias<HT>(acc, P.bh + opaque_zero(), g);
+#pragma unroll
+            for (int c = 0; c < NT::HID_KS; ++c)
+#pragma unroll
+                for (int mt = 0; mt < HT; ++mt)
+                    acc[mt] = mfma(src.load(FragIdx<NT>::hidden(1, c, mt), lane), h1.b(c), acc[mt]);
+            h2.set_relu(acc);
+        }
+        const float gc = valid ? p.grad[(size_t)i * B + j] : 0.0f;
+        // output layer: dw3 += G h2, db3 += G; adjoint of h2 = w3 G on active units
+        f32x16 d2[HT];
+#pragma unroll
+        for (int mt = 0; mt < HT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float hv = h2.v[mt][r];
+                gw3[mt][r] = __builtin_fmaf(gc, hv, gw3[mt][r]);
+                d2[mt][r] = hv > 0.0f ? p.w3[32 * mt + out_row(r, g)] * gc : 0.0f;
+            }
+        if (g == 0) gb3 += gc;
+        // dW2 += d2 h1^T over the tile's pairs (rows d2 at 0..63, h1 at 64..127); b2 += d2
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int mt = 0; mt < HT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                scr[col * kRow + 32 * mt + out_row(r, g)] = d2[mt][r];
+                scr[col * kRow + 64 + 32 * mt + out_row(r, g)] = valid ? h1.v[mt][r] : 0.0f;
+            }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const float* rw = scr + (2 * c + g) * kRow;
+#pragma unroll
+            for (int nt = 0; nt < HT; ++nt) {
+                const float bx = rw[64 + 32 * nt + col];
+#pragma unroll
+                for (int mt = 0; mt < HT; ++mt) gW2[mt][nt] = mfma(rw[32 * mt + col], bx, gW2[mt][nt]);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < HT; ++mt) gb2[mt] += d2[mt];
+        // adjoint of h1 = (W2^T d2) on active units
+        f32x16 d1[HT];
+#pragma unroll
+        for (int mt = 0; mt < HT; ++mt) d1[mt] = f32x16{};
+#pragma unroll
+        for (int c0 = 0; c0 < 16 * HT; c0 += 8) {
+            const char* bwz = bw + opaque_zero();
+#pragma unroll
+            for (int c = c0; c < c0 + 8; ++c)
+#pragma unroll
+                for (int mt = 0; mt < HT; ++mt)
+                    d1[mt] = mfma(lds_frag(bwz, BI::t2(c, mt), lane), d2[c >> 4][c & 15], d1[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < HT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) d1[mt][r] = h1.v[mt][r] > 0.0f ? d1[mt][r] : 0.0f;
+        // dW1 (+ b1 through column 31) += d1 x^T, x = [s'_i, a_i, o_j, 0, ..., 1]
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int mt = 0; mt < HT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) scr[col * kRow + 32 * mt + out_row(r, g)] = d1[mt][r];
+        int a_i = 0;
+        if (N_ACT > 0) {
+            a_i = reinterpret_cast<const int32_t*>(p.actions)[i];
+            if (a_i < 0 || a_i >= N_ACT) a_i = -1;  // flagged by the fold; contributes a zero action row
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = 16 * g + q;
+            float v = 0.0f;
+            if (c < D_S) {
+                v = p.states[(size_t)i * D_S + c];
+            } else if (c < D_S + D_AIN) {
+                if (N_ACT > 0) v = (c - D_S == a_i) ? 1.0f : 0.0f;
+                else v = reinterpret_cast<const float*>(p.actions)[(size_t)i * D_AIN + (c - D_S)];
+            } else if (c < D_IN) {
+                v = p.obs[(size_t)(valid ? j : 0) * D_O + (c - D_S - D_AIN)];
+            } else if (c == 31) {
+                v = 1.0f;
+            }
+            scr[col * kRow + 64 + c] = valid ? v : 0.0f;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const float* rw = scr + (2 * c + g) * kRow;
+            const float bx = rw[64 + col];
+#pragma unroll
+            for (int mt = 0; mt < HT; ++mt) gW1[mt] = mfma(rw[32 * mt + col], bx, gW1[mt]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // per-wave partials: W1 [64][D_IN], b1 [64], W2 [64][64], b2 [64], W3 [1][64], b3 [1]
+    const int wid = blockIdx.x * wpb + wave;
+    float* out = p.wpart + (size_t)wid * p.n_params;
+    constexpr int oW1 = 0, ob1 = 64 * D_IN, oW2 = ob1 + 64, ob2 = oW2 + 64 * 64, oW3 = ob2 + 64, ob3 = oW3 + 64;
+#pragma unroll
+    for (int mt = 0; mt < HT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = 32 * mt + out_row(r, g);
+            if (col < D_IN) out[oW1 + m * D_IN + col] = gW1[mt][r];
+            if (col == 31) out[ob1 + m] = gW1[mt][r];
+#pragma unroll
+            for (int nt = 0; nt < HT; ++nt) out[oW2 + m * 64 + 32 * nt + col] = gW2[mt][nt][r];
+            const float vb = sum32(gb2[mt][r]);
+            const float vw = sum32(gw3[mt][r]);
+            if (col == 0) {
+                out[ob2 + m] = vb;
+                out[oW3 + m] = vw;
+            }
+        }
+    const float v3 = sum32(gb3);
+    if (lane == 0) out[ob3] = v3;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -449,6 +636,46 @@ int grad_blocks_per_cu(int shape, size_t lds) {
             n = 1;                                                                                            \
         break;
         GRAD_SHAPES(X)
+#undef X
+    }
+    return n < 1 ? 1 : n;
+}
+
+// (shape id, d_s, discrete actions, continuous action width, d_o)
+#define NCE_GRAD_SHAPES(X) X(0, 4, 5, 0, 2) X(2, 4, 0, 4, 2)
+
+bool nce_grad_supported(int shape) {
+#define X(id, ds, na, da, dox) if (shape == id) return true;
+    NCE_GRAD_SHAPES(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_nce_grad(int shape, const NceGradParams& p, int blocks, size_t lds, hipStream_t s) {
+    switch (shape) {
+#define X(id, ds, na, da, dox)                                                                                \
+    case id:                                                                                                 \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(nce_grad_kernel<ds, na, da, dox>),            \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                      \
+        hipLaunchKernelGGL((nce_grad_kernel<ds, na, da, dox>), blocks, 256, lds, s, p);                       \
+        break;
+        NCE_GRAD_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int nce_grad_blocks_per_cu(int shape, size_t lds) {
+    int n = 0;
+    switch (shape) {
+#define X(id, ds, na, da, dox)                                                                                 \
+    case id:                                                                                                  \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, nce_grad_kernel<ds, na, da, dox>, 256, lds) != hipSuccess) \
+            n = 1;                                                                                            \
+        break;
+        NCE_GRAD_SHAPES(X)
 #undef X
     }
     return n < 1 ? 1 : n;

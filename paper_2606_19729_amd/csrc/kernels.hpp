@@ -268,6 +268,24 @@ struct GradParams {
     float disc[64];            // gamma^t
 };
 
+// Parameter derivative of the contrastive objective for binary32 width-64
+// likelihood networks with two hidden layers.
+struct NceGradParams {
+    NetBlob fwd, bwd;     // first layer over the observation columns; transposed pack
+    const float* w3;      // [64] output-layer weights
+    const float* b0;      // [B][64] first-layer biases with row i's state and action folded in
+    const float* obs;     // [B][d_o]
+    const float* states;  // [B][d_s]
+    const void* actions;  // int32 [B] or float [B][d_a]
+    const float* grad;    // [B][B] derivative of the loss by each score
+    float* wpart;         // [waves][n_params] per-wave partials
+    int32_t* status;      // or NULL
+    int B, n_params;
+};
+bool nce_grad_supported(int shape);
+hipError_t launch_nce_grad(int shape, const NceGradParams& p, int blocks, size_t lds, hipStream_t s);
+int nce_grad_blocks_per_cu(int shape, size_t lds);
+
 struct GradReduceParams {
     const float* wpart;
     const float* lpart;

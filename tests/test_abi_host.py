@@ -113,3 +113,7 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert L.voila_ddim_workspace_size(None, 4) == 0
     assert L.voila_denoiser_create(None, 4, 4, 5, 0, 0, 0, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_denoiser_destroy(None) == V.VOILA_OK
+    assert L.voila_info_nce_param_count(None) == 0
+    assert L.voila_info_nce_grad_workspace_size(None, 8) == 0
+    assert L.voila_info_nce_grad(None, None, None, None, 8, None, 0, None, None, None, None) == \
+        V.VOILA_ERR_INVALID_ARG

@@ -170,3 +170,42 @@ def test_rejects_bad_sizes(V):
     S, A, O = workloads.nce_batch(w, 4)
     with pytest.raises(V.VoilaError):
         V.info_nce(m, dev(S[:0]), dev(A[:0], torch.int32), dev(O[:0]))
+
+
+# ----------------------------------------------------------------------------- parameter derivative
+def run_grad(V, m, S, A, O):
+    res = V.info_nce_grad(m, dev(S), dev(A, torch.int32 if A.dtype == np.int32 else torch.float32), dev(O))
+    torch.cuda.synchronize()
+    return float(res["loss"].item()), host(res["grad"]).astype(np.float64)
+
+
+@pytest.mark.parametrize("which,B", [("small", 100), ("small", 256), ("continuous", 65), ("small", 32)])
+def test_param_grad_against_oracle(V, which, B):
+    # the adjoint bound: max |g_dev - g_ref| <= 1e-4 max |g_ref| (binary32
+    # forward and reverse passes over B^2 pairs against binary64)
+    w = workloads.small(seed=81) if which == "small" else workloads.continuous(seed=82)
+    S, A, O = workloads.nce_batch(w, B, seed=17)
+    m = V.Model(w.model)
+    print(f"info_nce grad {which} B={B}", flush=True)
+    loss, g = run_grad(V, m, S, A, O)
+    loss_ref, g_ref = oracle.info_nce_param_grad(w.model, S, A, O)
+    err = float(np.max(np.abs(g - g_ref))) / float(np.max(np.abs(g_ref)))
+    print(f"  grad err {err:.2e} of scale {np.max(np.abs(g_ref)):.3e}; loss {loss:.6f} vs {loss_ref:.6f}", flush=True)
+    assert g.shape == g_ref.shape
+    assert err <= 1e-4
+    assert abs(loss - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
+    assert abs(g[-1]) <= 1e-5 * float(np.max(np.abs(g_ref)))  # output bias: the scores' derivatives sum to zero
+
+
+def test_param_grad_single_pair_repeatable_and_unsupported(V):
+    w = workloads.small(seed=83)
+    m = V.Model(w.model)
+    S, A, O = workloads.nce_batch(w, 1)
+    loss, g = run_grad(V, m, S, A, O)
+    assert loss == 0.0 and np.all(g == 0.0)
+    S, A, O = workloads.nce_batch(w, 300)
+    assert np.array_equal(run_grad(V, m, S, A, O)[1], run_grad(V, m, S, A, O)[1])
+    r = workloads.realistic(seed=84, N=64, K=1, H=1)
+    S, A, O = workloads.nce_batch(r, 8)
+    with pytest.raises(V.VoilaError):
+        V.info_nce_grad(V.Model(r.model), dev(S), dev(A), dev(O))
