@@ -1320,7 +1320,8 @@ int or_ddim_point_mass(int d, const double* x0, const double* x1, int n_steps, d
  * network's parameters (packed per layer as W then b, the layout of the
  * parameter vector): sum over all pairs of G_ij times the derivative of
  * l([s'_i, a_i, o_j]), by reverse mode through the network (ReLU'(0) = 0),
- * accumulated in pair order.  Also returns the loss. */
+ * accumulated over each row's pairs in order, then over rows in order.
+ * Also returns the loss. */
 int or_info_nce_param_grad(const or_model* m, int B, const double* S, const int32_t* a_disc, const double* a_cont,
                            const double* O, double* grad, double* loss)
 {
@@ -1334,48 +1335,59 @@ int or_info_nce_param_grad(const or_model* m, int B, const double* S, const int3
     double* rl = (double*)malloc(sizeof(double) * (size_t)B);
     if (!Lg || !G || !rl) { free(Lg); free(G); free(rl); return OR_ERR_ARG; }
     int rc = or_info_nce(m, B, S, a_disc, a_cont, O, B, NULL, 0, Lg, rl, G, loss);
-    for (size_t q = 0; q < np; ++q) grad[q] = 0.0;
-    /* activations of every layer for one pair: act[l] is layer l's input */
-    double act[OR_MAX_LAYERS + 1][OR_MAX_WIDTH], delta[OR_MAX_WIDTH], prev[OR_MAX_WIDTH];
-    for (long e = 0; rc == OR_OK && e < (long)B * B; ++e) {
-        const int i = (int)(e / B), j = (int)(e % B);
-        double* x = act[0];
-        for (int c = 0; c < d_s; ++c) x[c] = S[(size_t)i * d_s + c];
-        put_action(m, x + d_s, a_disc ? a_disc[i] : 0, a_cont ? a_cont + (size_t)i * m->d_a : NULL);
-        for (int c = 0; c < d_o; ++c) x[d_s + aw + c] = O[(size_t)j * d_o + c];
-        const double* p = m->l_params;
-        for (int l = 0; l < L; ++l) {
-            const int n_in = dims[l], n_out = dims[l + 1];
-            for (int n = 0; n < n_out; ++n) {
-                double acc = 0.0;
-                for (int k = 0; k < n_in; ++k) acc += p[(size_t)n * n_in + k] * act[l][k];
-                acc += p[(size_t)n_out * n_in + n];
-                act[l + 1][n] = (l < L - 1 && acc < 0.0) ? 0.0 : acc;
-            }
-            p += (size_t)n_out * n_in + n_out;
-        }
-        /* reverse sweep: delta = d loss / d (pre-activation of layer l) */
-        delta[0] = G[e];
-        size_t off = np;
-        for (int l = L - 1; l >= 0; --l) {
-            const int n_in = dims[l], n_out = dims[l + 1];
-            off -= (size_t)n_out * n_in + n_out;
-            const double* W = m->l_params + off;
-            double* gW = grad + off;
-            for (int n = 0; n < n_out; ++n) {
-                for (int k = 0; k < n_in; ++k) gW[(size_t)n * n_in + k] += delta[n] * act[l][k];
-                gW[(size_t)n_out * n_in + n] += delta[n];
-            }
-            if (l > 0) {
-                for (int k = 0; k < n_in; ++k) {
+    /* one partial gradient per row, summed in row order afterwards (the
+     * result does not depend on the number of threads) */
+    double* part = rc == OR_OK ? (double*)calloc((size_t)B * np, sizeof(double)) : NULL;
+    if (rc == OR_OK && !part) rc = OR_ERR_ARG;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < (rc == OR_OK ? B : 0); ++i) {
+        /* activations of every layer for one pair: act[l] is layer l's input */
+        double act[OR_MAX_LAYERS + 1][OR_MAX_WIDTH], delta[OR_MAX_WIDTH], prev[OR_MAX_WIDTH];
+        double* gi = part + (size_t)i * np;
+        for (int j = 0; j < B; ++j) {
+            double* x = act[0];
+            for (int c = 0; c < d_s; ++c) x[c] = S[(size_t)i * d_s + c];
+            put_action(m, x + d_s, a_disc ? a_disc[i] : 0, a_cont ? a_cont + (size_t)i * m->d_a : NULL);
+            for (int c = 0; c < d_o; ++c) x[d_s + aw + c] = O[(size_t)j * d_o + c];
+            const double* p = m->l_params;
+            for (int l = 0; l < L; ++l) {
+                const int n_in = dims[l], n_out = dims[l + 1];
+                for (int n = 0; n < n_out; ++n) {
                     double acc = 0.0;
-                    for (int n = 0; n < n_out; ++n) acc += W[(size_t)n * n_in + k] * delta[n];
-                    prev[k] = act[l][k] > 0.0 ? acc : 0.0;
+                    for (int k = 0; k < n_in; ++k) acc += p[(size_t)n * n_in + k] * act[l][k];
+                    acc += p[(size_t)n_out * n_in + n];
+                    act[l + 1][n] = (l < L - 1 && acc < 0.0) ? 0.0 : acc;
                 }
-                for (int k = 0; k < n_in; ++k) delta[k] = prev[k];
+                p += (size_t)n_out * n_in + n_out;
+            }
+            /* reverse sweep: delta = d loss / d (pre-activation of layer l) */
+            delta[0] = G[(size_t)i * B + j];
+            size_t off = np;
+            for (int l = L - 1; l >= 0; --l) {
+                const int n_in = dims[l], n_out = dims[l + 1];
+                off -= (size_t)n_out * n_in + n_out;
+                const double* W = m->l_params + off;
+                double* gW = gi + off;
+                for (int n = 0; n < n_out; ++n) {
+                    for (int k = 0; k < n_in; ++k) gW[(size_t)n * n_in + k] += delta[n] * act[l][k];
+                    gW[(size_t)n_out * n_in + n] += delta[n];
+                }
+                if (l > 0) {
+                    for (int k = 0; k < n_in; ++k) {
+                        double acc = 0.0;
+                        for (int n = 0; n < n_out; ++n) acc += W[(size_t)n * n_in + k] * delta[n];
+                        prev[k] = act[l][k] > 0.0 ? acc : 0.0;
+                    }
+                    for (int k = 0; k < n_in; ++k) delta[k] = prev[k];
+                }
             }
         }
     }
+    for (size_t q = 0; q < np; ++q) grad[q] = 0.0;
+    if (part)
+        for (int i = 0; i < B; ++i)
+            for (size_t q = 0; q < np; ++q) grad[q] += part[(size_t)i * np + q];
+    free(part);
     free(Lg); free(G); free(rl);
     return rc;
 }

@@ -179,7 +179,8 @@ def run_grad(V, m, S, A, O):
     return float(res["loss"].item()), host(res["grad"]).astype(np.float64)
 
 
-@pytest.mark.parametrize("which,B", [("small", 100), ("small", 256), ("continuous", 65), ("small", 32)])
+@pytest.mark.parametrize("which,B", [("small", 100), ("small", 256), ("continuous", 65), ("small", 32),
+                                     ("small", 1024)])
 def test_param_grad_against_oracle(V, which, B):
     # the adjoint bound: max |g_dev - g_ref| <= 1e-4 max |g_ref| (binary32
     # forward and reverse passes over B^2 pairs against binary64)
@@ -209,3 +210,19 @@ def test_param_grad_single_pair_repeatable_and_unsupported(V):
     S, A, O = workloads.nce_batch(r, 8)
     with pytest.raises(V.VoilaError):
         V.info_nce_grad(V.Model(r.model), dev(S), dev(A), dev(O))
+
+
+def test_param_grad_bench_size_properties(V):
+    # B = 4,096 (16.8 M pairs, the measured size): the output-bias derivative
+    # vanishes, the result is finite and repeatable, and the loss equals the
+    # forward call's
+    w = workloads.small(seed=9)
+    S, A, O = workloads.nce_batch(w, 4096, seed=18)
+    m = V.Model(w.model)
+    print("info_nce grad small B=4096", flush=True)
+    loss, g = run_grad(V, m, S, A, O)
+    assert np.all(np.isfinite(g))
+    assert abs(g[-1]) <= 1e-5 * float(np.max(np.abs(g)))
+    d = run_dev(V, m, S, A, O)
+    assert loss == pytest.approx(float(d["loss"][0]), rel=1e-12)
+    assert np.array_equal(run_grad(V, m, S, A, O)[1], g)
