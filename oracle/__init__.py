@@ -77,6 +77,7 @@ def lib():
         L.or_ddim_sample.argtypes = [c_int, ip, dp, c_int, c_int, c_int, c_int, c_int, dp, c_int, dp, dp, c_int, c_int,
                                      dp]
         L.or_ddim_point_mass.argtypes = [c_int, dp, dp, c_int, dp]
+        L.or_ddim_gaussian.argtypes = [c_int, dp, c_double, dp, c_int, dp]
         L.or_mlp_param_count.argtypes = [c_int, ip]
         L.or_mlp_param_count.restype = c_size_t
         L.or_set_threads.argtypes = [c_int]
@@ -446,6 +447,14 @@ def ddim_sample(layers, d_c, d_x, n_actions, d_a, cond, action, x1, n_steps, bf1
     _check(lib().or_ddim_sample(len(layers), dims.ctypes.data_as(POINTER(c_int)), _p(params), d_c, d_x, n_actions,
                                 d_a, n, _p(C), a_disc, _p(a_cont), _p(X1), int(n_steps), int(bf16), _p(out)),
            "ddim_sample")
+    return out
+
+
+def ddim_gaussian(mu, sigma, x1, n_steps):
+    """The sampler's steps driven by the exact v of Gaussian data N(mu, sigma^2 I)."""
+    mu, x1 = _d(np.ravel(mu)), _d(np.ravel(x1))
+    out = np.zeros_like(x1)
+    _check(lib().or_ddim_gaussian(x1.shape[0], _p(mu), float(sigma), _p(x1), int(n_steps), _p(out)), "ddim_gaussian")
     return out
 
 

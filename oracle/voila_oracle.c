@@ -1308,6 +1308,31 @@ static void ddim_point_v(const void* cp, const double* s, const double* x, doubl
     }
 }
 
+/* The exact v of Gaussian data N(mu, sigma^2 I): with a = abar(tau), the
+ * posterior mean is x0 = mu + sqrt(a) sigma^2 (x - sqrt(a) mu) / (a sigma^2
+ * + 1 - a), eps = (x - sqrt(a) x0) / sqrt(1 - a) and v = sqrt(a) eps -
+ * sqrt(1 - a) x0 (the conditioning input is taken as mu).  Test hook. */
+typedef struct { int d; double sigma; } ddim_gauss_ctx;
+static void ddim_gauss_v(const void* cp, const double* mu, const double* x, double tau, double* v)
+{
+    const ddim_gauss_ctx* c = (const ddim_gauss_ctx*)cp;
+    const double a = or_cosine_abar(tau), s2 = c->sigma * c->sigma;
+    for (int j = 0; j < c->d; ++j) {
+        double x0 = mu[j] + sqrt(a) * s2 * (x[j] - sqrt(a) * mu[j]) / (a * s2 + 1.0 - a);
+        double eps = (x[j] - sqrt(a) * x0) / sqrt(1.0 - a);
+        v[j] = sqrt(a) * eps - sqrt(1.0 - a) * x0;
+    }
+}
+
+int or_ddim_gaussian(int d, const double* mu, double sigma, const double* x1, int n_steps, double* out)
+{
+    if (d < 1 || d > OR_MAX_WIDTH || n_steps < 1 || !(sigma > 0.0)) return OR_ERR_ARG;
+    ddim_gauss_ctx c = {d, sigma};
+    for (int j = 0; j < d; ++j) out[j] = x1[j];
+    ddim_run(d, mu, out, n_steps, ddim_gauss_v, &c);
+    return OR_OK;
+}
+
 int or_ddim_point_mass(int d, const double* x0, const double* x1, int n_steps, double* out)
 {
     if (d < 1 || d > OR_MAX_WIDTH || n_steps < 1) return OR_ERR_ARG;

@@ -871,6 +871,26 @@ def test_ddim_recovers_a_point_mass_exactly(n_steps):
     np.testing.assert_allclose(oracle.ddim_point_mass(x0, x1, n_steps), x0, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("sigma", [0.5, 2.0])
+@pytest.mark.parametrize("n_steps", [1, 3, 10, 50])
+def test_ddim_gaussian_data_closed_form(sigma, n_steps):
+    # Data N(mu, sigma^2) with its exact denoiser.  In the standardised
+    # coordinate z = (x - sqrt(a) mu) / sqrt(a sigma^2 + 1 - a) a deterministic
+    # step multiplies z by cos(phi - phi'), phi = atan2(sqrt(1 - a), sqrt(a) sigma)
+    # (the estimates' directions at the two times), so from z = x1 at tau = 1
+    # the sample is mu + sigma x1 prod_k cos(phi_k - phi_{k+1}); every step's
+    # clean and noise estimates enter the product.
+    rng = np.random.default_rng(n_steps)
+    mu, x1 = rng.standard_normal(5), rng.standard_normal(5)
+    a = np.array([oracle.cosine_abar(1.0 - k / n_steps) for k in range(n_steps + 1)])
+    phi = np.arctan2(np.sqrt(1.0 - a), np.sqrt(a) * sigma)
+    shrink = np.prod(np.cos(phi[:-1] - phi[1:]))
+    np.testing.assert_allclose(oracle.ddim_gaussian(mu, sigma, x1, n_steps), mu + sigma * x1 * shrink,
+                               rtol=1e-12, atol=1e-12)
+    if n_steps == 50:
+        assert 0.96 < shrink < 1.0  # the discretisation shrinks less with more steps (0.57 at 3, 0.97 at 50)
+
+
 @pytest.mark.parametrize("n_actions,d_a", [(5, 0), (0, 3)])
 def test_ddim_one_step_is_minus_v_at_tau_one(n_actions, d_a):
     # one step from tau = 1 (abar = 0) to tau = 0 (abar = 1): the sample is the
@@ -922,7 +942,14 @@ def test_info_nce_param_grad_matches_finite_differences(which):
     rng = np.random.default_rng(4)
     h = 1e-6
     checked = 0
-    for q in rng.choice(theta.size - 1, 40, replace=False):
+    # random coordinates plus the first weights and biases of every layer
+    fixed, off = [], 0
+    for W, b in m.lik:
+        fixed += [off, off + 1, off + W.size, off + W.size + 1]
+        off += W.size + b.size
+    coords = sorted(set(int(q) for q in rng.choice(theta.size - 1, 40, replace=False)) |
+                    set(q for q in fixed if q < theta.size - 1))
+    for q in coords:
         tp, tm = theta.copy(), theta.copy()
         tp[q] += h
         tm[q] -= h
