@@ -620,7 +620,7 @@ def main():
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build",
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (single-GPU library and benchmark)",
               file=sys.stderr, flush=True)
         sys.exit(2)
 
