@@ -1155,8 +1155,9 @@ __global__ __launch_bounds__(kNormResThreads) void pw_norm_res_kernel(PwParams p
 
 // Scores of all B x B pairs of a contrastive mini-batch: tile (i, jt) is
 // state-action i against the 32 observations of column tile jt.  Row i's
-// state and action sit in its folded first-layer bias row; the observations
-// are the network's input slots.
+// state and action sit in its folded first-layer bias row, which each wave
+// copies into its own LDS row when the row changes; the observations are the
+// network's input slots.
 template <int DT, int D_O, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void nce_scores_kernel(NceParams p) {
     if constexpr (!net_compiled(DT, WIDTH)) {
@@ -1170,6 +1171,10 @@ __global__ __launch_bounds__(256) void nce_scores_kernel(NceParams p) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jtiles = (p.B + 31) / 32;
     const long n_units = (long)p.B * jtiles;
+    float* rowb = reinterpret_cast<float*>(smem + p.row_bias_lds) + wave * NTL::WIDTH;
+    constexpr int RB = NTL::WIDTH / 64;  // bias floats per lane
+    static_assert(NTL::WIDTH % 64 == 0 && RB <= 16, "bias row copy: whole lanes");
+    int have = -1;  // row held in this wave's LDS bias row
     with_weights<NTL, MODE, 1>(smem, p.lik, [&](auto& src, const NetPtrs& P) {
         // block-uniform loop (a streamed network's chunk barriers need every wave)
         for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
@@ -1186,8 +1191,22 @@ __global__ __launch_bounds__(256) void nce_scores_kernel(NceParams p) {
                 const int f = 2 * s + g;
                 slots[s] = (valid && f < D_O) ? p.obs[(size_t)j * D_O + f] : 0.0f;
             }
+            const bool fresh = i != have;  // wave-uniform
+            float bv[RB];
+            if (fresh) {
+                const float* brow = p.b0 + (size_t)i * NTL::WIDTH;
+#pragma unroll
+                for (int q = 0; q < RB; ++q) bv[q] = brow[q * 64 + lane];
+            }
             __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-            const f32x16 o = run_net<NTL>(src, P, p.b0 + (size_t)i * NTL::WIDTH, slots, lane, g);
+            if (fresh) {
+#pragma unroll
+                for (int q = 0; q < RB; ++q) rowb[q * 64 + lane] = bv[q];
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+                __builtin_amdgcn_wave_barrier();
+                have = i;
+            }
+            const f32x16 o = run_net<NTL>(src, P, rowb, slots, lane, g);
             if (g == 0 && valid) {
                 const float l = o[0];
                 p.scores[(size_t)i * p.B + j] = l;
@@ -1710,7 +1729,8 @@ int pw_lik_blocks_per_cu(int shape, int dt) {
 
 #define NCE_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) nce_scores_kernel<DT, dox, w, nh, plan_mode<w>()>
 
-hipError_t launch_nce_scores(int shape, int dt, const NceParams& p, int blocks, hipStream_t s) {
+hipError_t launch_nce_scores(int shape, int dt, const NceParams& p0, int blocks, hipStream_t s) {
+    NceParams p = p0;
     size_t lds = p.lik.bytes;
     if (!weights_in_lds(shape)) {
         switch (shape * 2 + dt) {
@@ -1726,6 +1746,10 @@ hipError_t launch_nce_scores(int shape, int dt, const NceParams& p, int blocks, 
         }
         lds += p.lik.bytes - p.lik.off_b0;
     }
+    // one first-layer bias row per wave after the staged weights and biases
+    lds = (lds + 15) / 16 * 16;
+    p.row_bias_lds = (uint32_t)lds;
+    lds += (size_t)kWavesPerBlock * shape_info(shape).width * 4;
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                \
     case id * 2 + 0:                                                                                         \

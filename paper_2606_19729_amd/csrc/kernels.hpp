@@ -181,6 +181,7 @@ struct NceParams {
     double* loss;         // [1] mean row loss, or NULL
     int32_t* status;      // or NULL
     int B, d_o;
+    uint32_t row_bias_lds;  // LDS offset of the per-wave bias rows (set by the launcher)
 };
 
 // Teacher sampler of a v-prediction denoiser (input [c, a, x_tau, tau],
