@@ -582,6 +582,12 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if constexpr (MODE == kStream) {
         const int wpb = blockDim.x >> 6;
+        // each wave keeps the (candidate, step) group's bias row in its own
+        // LDS row, refreshed when the group changes (every N/32 units)
+        float* rowb = reinterpret_cast<float*>(smem + p.row_bias_lds) + wave * NTO::WIDTH;
+        constexpr int RB = NTO::WIDTH / 64;  // bias floats per lane
+        static_assert(NTO::WIDTH % 64 == 0 && RB <= 16, "bias row copy: whole lanes");
+        int have = -1;
         with_weights<NTO, MODE, 1>(smem, p.obs, [&](auto& src, const NetPtrs& P) {
             // block-uniform loop (the stream's chunk barriers need every wave)
             for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
@@ -589,10 +595,25 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
                 const bool ok = u < n_units;
                 float slots[NTO::IN_SLOTS];
                 const ObsRow w = observe_inputs<D_S, D_WZ>(p, ok ? u : 0, n_tiles, g, col, slots);
+                const int brow = p.b0_stride ? w.grp : 0;
+                const bool fresh = brow != have;  // wave-uniform
+                float bv[RB];
+                if (fresh) {
+                    const float* src_row = p.b0 + (size_t)brow * p.b0_stride;
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) bv[q] = src_row[q * 64 + lane];
+                }
                 // complete the row loads here so that the compiler's wait for
                 // them does not also drain the weight stream inside the layers
                 __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-                const f32x16 o = run_net<NTO>(src, P, p.b0 + (size_t)w.grp * p.b0_stride, slots, lane, g);
+                if (fresh) {
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) rowb[q * 64 + lane] = bv[q];
+                    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+                    __builtin_amdgcn_wave_barrier();
+                    have = brow;
+                }
+                const f32x16 o = run_net<NTO>(src, P, rowb, slots, lane, g);
                 observe_store<D_O>(p, w, o, ok, g);
             }
         });
@@ -1596,8 +1617,15 @@ size_t observe_rollout_lds(int shape, int dt, const NetBlob& obs) {
     return chunks + (obs.bytes - obs.off_b0);
 }
 
-hipError_t launch_observe_rollouts(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s) {
-    const size_t lds = observe_rollout_lds(shape, dt, p.obs);
+hipError_t launch_observe_rollouts(int shape, int dt, const ObserveParams& p0, int blocks, hipStream_t s) {
+    ObserveParams p = p0;
+    size_t lds = observe_rollout_lds(shape, dt, p.obs);
+    if (!weights_in_lds(shape)) {
+        // one first-layer bias row per wave after the stream buffers and staged biases
+        lds = (lds + 15) / 16 * 16;
+        p.row_bias_lds = (uint32_t)lds;
+        lds += (size_t)kWavesPerBlock * kShapeInfo[shape].width * 4;
+    }
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                \
     case id * 2 + 0:                                                                                         \

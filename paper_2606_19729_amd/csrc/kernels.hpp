@@ -88,6 +88,7 @@ struct ObserveParams {
     float* out;              // [K][N][H][d_o]
     int N, K, H, crn;
     uint32_t key0, key1;
+    uint32_t row_bias_lds;   // LDS offset of the per-wave bias rows (whole-rollout launches; set by the launcher)
 };
 
 // First-layer biases with the action (and observation) of each row folded in.
