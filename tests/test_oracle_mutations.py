@@ -2,11 +2,13 @@
 
 Each case plants one mistake in a copy of the oracle's C source (on the CPU,
 in a temporary directory), builds it, points the oracle at the copy and
-checks that a pin of the affected function fails: the wrong diagonal or a
-dropped 1/B in the contrastive objective, scores against the row's own
-observation, a sign error in either estimate of the sampler step, the
-sampler's input order, and a missing bias term or ReLU mask in the
-parameter derivative.
+checks that a pin of the affected function fails: the discount or the
+reward at the wrong step of a rollout, weights without the temperature, the
+log evidence without the uniform prior, a non-strict or truncating
+resampling step, the wrong diagonal or a dropped 1/B in the contrastive
+objective, scores against the row's own observation, a sign error in either
+estimate of the sampler step, the sampler's input order, and a missing bias
+term or ReLU mask in the parameter derivative.
 """
 import os
 import subprocess
@@ -48,6 +50,30 @@ MUTATIONS = {
         "                    gW[(size_t)n_out * n_in + n] += delta[n];\n                }\n                if (l > 0) {",
         "                }\n                if (l > 0) {",
         lambda: pins.test_info_nce_param_grad_matches_finite_differences("small")),
+    "discount applied before the first reward": (
+        "        G += disc * r;\n        disc *= gamma;",
+        "        disc *= gamma;\n        G += disc * r;",
+        lambda: pins.test_plan_special_cases()),
+    "reward at the current state": (
+        "double r = reward_at ? reward(m->d_s, s, goal) : reward(m->d_s, s_next, goal);",
+        "double r = reward(m->d_s, s, goal);",
+        lambda: pins.test_reward_timing_shift_identity()),
+    "weights without the temperature": (
+        "x[i] = loglik[i] / lambda;",
+        "x[i] = loglik[i];",
+        lambda: pins.test_normalize_against_logsumexp_and_invariances()),
+    "log evidence without the uniform prior": (
+        "stats[0] = mx + log(S) - (prior_w ? 0.0 : log((double)N));",
+        "stats[0] = mx + log(S);",
+        lambda: pins.test_normalize_uniform_is_exact()),
+    "resampling comparison not strict": (
+        "while (i < N && !(C[i] > P)) ++i;",
+        "while (i < N && !(C[i] >= P)) ++i;",
+        lambda: pins.test_resample_uniform_is_identity_and_one_hot_is_constant()),
+    "quantisation by truncation": (
+        "double q = nearbyint(w[i] * scale);",
+        "double q = floor(w[i] * scale);",
+        lambda: pins.test_resample_quantisation_rounds_to_nearest()),
     "parameter derivative without the ReLU mask": (
         "prev[k] = act[l][k] > 0.0 ? acc : 0.0;",
         "prev[k] = acc;",

@@ -411,6 +411,19 @@ def test_resample_is_exactly_unbiased_over_the_offset():
         np.testing.assert_allclose(mean, q / step, rtol=0, atol=1e-9)
 
 
+def test_resample_quantisation_rounds_to_nearest():
+    # N = 2, b = 32: q_0 = rint(w_0 * 2^33) = 2^31 + 1 for w_0 * 2^33 = 2^31 + 0.6;
+    # with u = 2^31 the first output is the first particle only if q_0 was
+    # rounded up (C_0 = 2^31 + 1 > u), the second if it was truncated
+    w0 = (2.0 ** 31 + 0.6) / 2.0 ** 33
+    w = np.array([w0, 1.0 - w0])
+    assert oracle.resample_bits(2) == 32
+    idx = oracle.resample(w, 1 << 31)
+    assert idx[0] == 0
+    w0 = (2.0 ** 31 + 0.4) / 2.0 ** 33  # rounds down: C_0 = 2^31 = u, not above it
+    assert oracle.resample(np.array([w0, 1.0 - w0]), 1 << 31)[0] == 1
+
+
 def test_resample_rejects_zero_mass():
     with pytest.raises(oracle.OracleError):
         oracle.resample(np.zeros(5), 0)
