@@ -285,7 +285,8 @@ voila_status_t voila_info_nce(voila_model_t model, const float* d_states, const 
  * small shapes (d_s = 4, d_o = 2, five discrete or four continuous action
  * inputs); voila_info_nce_param_count returns 0 and voila_info_nce_grad
  * VOILA_ERR_UNSUPPORTED for other models.  Per-wave partial sums are
- * reduced in a fixed order (repeatable).  Workspace:
+ * reduced in a fixed order (repeatable).  Status and out-of-range actions as
+ * for voila_info_nce (action 0 is used in both passes).  Workspace:
  * voila_info_nce_grad_workspace_size.
  */
 int32_t voila_info_nce_param_count(voila_model_t model);

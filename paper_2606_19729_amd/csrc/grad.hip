@@ -547,7 +547,7 @@ __global__ __launch_bounds__(256) void nce_grad_kernel(NceGradParams p) {
         int a_i = 0;
         if (N_ACT > 0) {
             a_i = reinterpret_cast<const int32_t*>(p.actions)[i];
-            if (a_i < 0 || a_i >= N_ACT) a_i = -1;  // flagged by the fold; contributes a zero action row
+            if (a_i < 0 || a_i >= N_ACT) a_i = 0;  // flagged by the fold, which uses action 0 as well
         }
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
