@@ -321,9 +321,10 @@ voila_status_t voila_info_nce_grad(voila_model_t model, const float* d_states, c
  * denoiser's output at (c, a, x, tau_k):
  *   x0 = sqrt(a) x - sqrt(1 - a) v,  eps = sqrt(1 - a) x + sqrt(a) v,
  *   x <- sqrt(a') x0 + sqrt(1 - a') eps,
- * the final x (tau = 0) written to d_out [N][d_x].  The step coefficients are
- * formed in binary64 and applied in binary32; the network runs in the
- * denoiser's precision.  1 <= n_steps <= 4096; the workspace
+ * the final x (tau = 0) written to d_out [N][d_x].  The step is applied as
+ * x <- x + ((A - 1) x + B v) with A - 1 and B formed in binary64 and rounded
+ * to binary32 (A is within binary32 resolution of 1 at large step counts);
+ * the network runs in the denoiser's precision.  1 <= n_steps <= 4096; the workspace
  * (voila_ddim_workspace_size) holds the per-step folded biases.
  * ------------------------------------------------------------------------- */
 typedef struct voila_denoiser_s* voila_denoiser_t;

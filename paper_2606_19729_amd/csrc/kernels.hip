@@ -1286,6 +1286,8 @@ __device__ __forceinline__ double cosine_abar(double tau) {
 // a' = abar(tau_{k+1}), the v-prediction estimates x0 = sqrt(a) x - sqrt(1-a) v
 // and eps = sqrt(1-a) x + sqrt(a) v re-noised to tau_{k+1} give
 // x' = A x + B v, A = sqrt(a' a) + sqrt((1-a')(1-a)), B = sqrt((1-a') a) - sqrt(a' (1-a)).
+// A - 1 is stored rather than A: with many steps A is within binary32
+// resolution of 1, and x' = x + ((A - 1) x + B v) keeps its effect.
 __global__ __launch_bounds__(256) void ddim_prep_kernel(DdimPrepParams p) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     for (int t = blockIdx.y; t < p.n_steps; t += gridDim.y) {
@@ -1301,7 +1303,7 @@ __global__ __launch_bounds__(256) void ddim_prep_kernel(DdimPrepParams p) {
         }
         if (r == 0) {
             const double a = cosine_abar(tau), an = cosine_abar(tau_n);
-            p.coef[2 * t] = (float)(sqrt(an * a) + sqrt((1.0 - an) * (1.0 - a)));
+            p.coef[2 * t] = (float)((sqrt(an * a) + sqrt((1.0 - an) * (1.0 - a))) - 1.0);
             p.coef[2 * t + 1] = (float)(sqrt((1.0 - an) * a) - sqrt(an * (1.0 - a)));
         }
     }
@@ -1351,9 +1353,9 @@ __global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
 #pragma unroll
             for (int s = 0; s < SW; ++s) slots[SS + s] = cond[s];
             const f32x16 v = eval(p.b0 + (size_t)t * WIDTH, slots);
-            const float A = coef[2 * t], B = coef[2 * t + 1];
+            const float Am1 = coef[2 * t], B = coef[2 * t + 1];
 #pragma unroll
-            for (int s = 0; s < SS; ++s) x[s] = __builtin_fmaf(B, v[s], A * x[s]);
+            for (int s = 0; s < SS; ++s) x[s] += __builtin_fmaf(B, v[s], Am1 * x[s]);
         }
         if (writer && valid)
 #pragma unroll
@@ -1439,11 +1441,11 @@ __global__ __launch_bounds__(64 * kDdimSplitWaves) void ddim_split_kernel(DdimPa
             }
             f32x16 v[ST];
             run_net_split_multi<NT, ST, kDdimSplitWaves, kDdimSplitDepth>(P, p.b0 + (size_t)t * WIDTH, slots, v, lane, g, wave, smem);
-            const float A = coef[2 * t], B = coef[2 * t + 1];
+            const float Am1 = coef[2 * t], B = coef[2 * t + 1];
 #pragma unroll
             for (int st = 0; st < ST; ++st)
 #pragma unroll
-                for (int s = 0; s < SS; ++s) x[st][s] = __builtin_fmaf(B, v[st][s], A * x[st][s]);
+                for (int s = 0; s < SS; ++s) x[st][s] += __builtin_fmaf(B, v[st][s], Am1 * x[st][s]);
         }
         if (wave == 0)
 #pragma unroll

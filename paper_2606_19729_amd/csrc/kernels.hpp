@@ -192,7 +192,7 @@ struct DdimParams {
     const float* states;  // [N][d_c] conditioning inputs
     const float* x1;      // [N][d_x] latent noise at tau = 1
     const float* b0;      // [n_steps][width] first-layer biases with the action and tau_k folded in
-    const float* coef;    // [n_steps][2]: x <- coef[0] x + coef[1] v
+    const float* coef;    // [n_steps][2]: x <- x + (coef[0] x + coef[1] v), coef[0] = A - 1
     float* out;           // [N][d_x]
     int N, n_steps;
 };

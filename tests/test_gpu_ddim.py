@@ -2,14 +2,18 @@
 the deterministic DDIM sampler of a v-prediction transition denoiser under the
 cosine schedule.
 
-Bounds: binary32 within 1e-5 of the samples' scale, bfloat16 against the
-oracle's emulation (operands rounded to bfloat16 at every layer) within 2^-6
-of the scale -- the bounds of the other network parity tests.  A step maps
+Bounds: binary32 within 1e-5 + n_steps 2^-24 of the samples' scale (the
+network bound of the other parity tests plus one rounding of the step
+update per step), bfloat16 against the oracle's emulation (operands rounded
+to bfloat16 at every layer) within 2^-6 of the scale.  A step maps
 (x, v) to A x + B v with A^2 + B^2 = 1 (the sampler rotates between the clean
-and noise estimates), so a step does not amplify the error it is handed, and
-the measured errors do not grow with the step count (binary32 <= 3e-7,
-bfloat16 <= 4.2e-3 of the scale, the largest on the 5 x 1024 network).  Cases:
-ragged sample counts, one to fifty steps, discrete and continuous actions,
+and noise estimates), so a step does not amplify the error it is handed; up
+to 50 steps the measured errors do not grow with the step count (binary32
+<= 3e-7, bfloat16 <= 4.2e-3 of the scale, the largest on the 5 x 1024
+network), while thousands of steps accumulate the step's own rounding (the
+kernels apply it as x + ((A - 1) x + B v), since A is then within binary32
+resolution of 1).  Cases: ragged sample counts, one to 4,096 steps (the
+largest accepted), discrete and continuous actions,
 the 2 x 64 network in both precisions, the paper's 5 x 1024 transition
 denoiser, the 4 x 1024 one-step network and a 5 x 512 observation denoiser
 in bfloat16, sampled rows of 65,536 samples at 50 steps, bit-identical
@@ -38,7 +42,8 @@ def dev(a, dtype=torch.float32):
 
 
 def bound(compute, n_steps):
-    return 1e-5 if compute == "f32" else 2.0 ** -6
+    # binary32: 1e-5 plus one rounding (2^-24) of the step per step
+    return 1e-5 + n_steps * 2.0 ** -24 if compute == "f32" else 2.0 ** -6
 
 
 def compare(V, layers, d_c, d_x, n_actions, d_a, compute, N, n_steps, action, seed=22, rows=None):
@@ -114,3 +119,14 @@ def test_argument_errors(V):
         V.Denoiser(workloads.denoiser(seed=36, width=128, n_hidden=2), 4, 4, 5, 0, compute="f32")
     with pytest.raises(V.VoilaError):
         V.Denoiser(workloads.denoiser(seed=36, width=1024, n_hidden=5), 4, 4, 5, 0, compute="f32")
+
+
+def test_maximum_steps(V):
+    # 4,096 steps (the largest accepted) with the 2 x 64 binary32 denoiser;
+    # 4,097 is refused
+    layers = workloads.denoiser(seed=38, width=64, n_hidden=2)
+    compare(V, layers, 4, 4, 5, 0, "f32", 40, 4096, 1)
+    S, X1 = workloads.ddim_batch(8)
+    den = V.Denoiser(layers, 4, 4, 5, 0, compute="f32")
+    with pytest.raises(V.VoilaError):
+        V.ddim_sample(den, dev(S), 1, dev(X1), 4097)

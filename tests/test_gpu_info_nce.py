@@ -226,3 +226,22 @@ def test_param_grad_bench_size_properties(V):
     d = run_dev(V, m, S, A, O)
     assert loss == pytest.approx(float(d["loss"][0]), rel=1e-12)
     assert np.array_equal(run_grad(V, m, S, A, O)[1], g)
+
+
+def test_maximum_batch(V):
+    # B = 32,768 (the largest accepted; 1.07e9 pairs) with the small networks:
+    # sampled rows against the oracle; one more tuple is refused
+    w = workloads.small(seed=85, N=4096)
+    B = 32768
+    S, A, O = workloads.nce_batch(w, B, seed=19)
+    m = V.Model(w.model)
+    print(f"info_nce small f32 B={B}", flush=True)
+    d = run_dev(V, m, S, A, O)
+    rows = [0, 12345, B - 1]
+    check_against_own_scores(d, rows=rows)
+    r = oracle.info_nce(w.model, S, A, O, rows=rows)
+    check_against_oracle(d, r, TOL, rows=rows)
+    assert np.isfinite(d["loss"][0])
+    S1, A1, O1 = workloads.nce_batch(w, B + 1, seed=20)
+    with pytest.raises(V.VoilaError):
+        V.info_nce(m, dev(S1), dev(A1, torch.int32), dev(O1), want_scores=False, want_grad=False)
