@@ -1,11 +1,13 @@
 """Builds libvoila.so (HIP kernels + C ABI) for gfx950 in-tree.
 
-One hipcc invocation compiles the kernels and the ABI into a shared library
-next to this file.  Packed FP32 instructions are disabled for the device code
-(-packed-fp32-ops is turned off), the library is built at -O3 without fast-math
-and without implicit contraction of multiply-adds (kernels that share device
-functions then round identically; fused operations are written explicitly).
+Each source compiles to an object in its own hipcc process (in parallel), and
+the objects link into a shared library next to this file.  Packed FP32
+instructions are disabled for the device code (-packed-fp32-ops is turned
+off), the library is built at -O3 without fast-math and without implicit
+contraction of multiply-adds (kernels that share device functions then round
+identically; fused operations are written explicitly).
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -14,24 +16,46 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvoila.so")
-SOURCES = ["kernels.hip", "grad.hip", "resample_large.hip", "abi.hip"]
+OBJ = os.path.join(HERE, "_build")
+SOURCES = ["k_plan.hip", "k_observe.hip", "k_search.hip", "k_nce.hip", "k_ddim.hip", "k_update.hip", "grad.hip",
+           "resample_large.hip", "abi.hip"]
 ARCH = os.environ.get("VOILA_OFFLOAD_ARCH", "gfx950")
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",
+         "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
+
+
+def _jobs():
+    n = os.cpu_count() or 4
+    cap = int(os.environ.get("MAX_JOBS", "16"))
+    return max(1, min(n, cap, len(SOURCES)))
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include")]
-    cmd += list(extra)
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    cmd += ["-o", LIB + ".tmp"]
+    os.makedirs(OBJ, exist_ok=True)
+    base = ["hipcc", f"--offload-arch={ARCH}"] + FLAGS + ["-I", os.path.join(ROOT, "include")] + list(extra)
+
+    def compile_one(src):
+        obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+        cmd = base + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        return src, obj, r
+
+    with concurrent.futures.ThreadPoolExecutor(_jobs()) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    failed = [(s, r) for s, _, r in results if r.returncode != 0]
+    for s, r in failed:
+        sys.stderr.write(f"--- {s}\n" + r.stdout + r.stderr)
+    if failed:
+        raise RuntimeError("hipcc failed building libvoila.so: " + ", ".join(s for s, _ in failed))
+    link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC"] + [o for _, o, _ in results] + ["-o", LIB + ".tmp"]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
+        print(" ".join(link), flush=True)
+    r = subprocess.run(link, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libvoila.so")
+        raise RuntimeError("linking libvoila.so failed")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -1,0 +1,239 @@
+// k_observe.hip -- the observation sampler f_Z over belief rows and over the
+// rows of whole rollouts (per-step observations).
+#include "kcommon.hpp"
+
+namespace voila {
+
+// ---------------------------------------------------------------------------
+// observe
+// ---------------------------------------------------------------------------
+// Rows are (group, particle) pairs: group j = k * H + t has its own folded
+// first-layer bias (its action) and 32-particle tiles; row (k, i, t) reads
+// state row (k * N + i) * H + t, draws its noise at counter (i, k or 0 under
+// common random numbers, t) and writes the same output row.  A plain
+// observation of n states is the case K = H = 1.
+struct ObsRow {
+    size_t r;     // state / noise / output row
+    int grp;      // bias row
+    bool valid;   // this lane's particle exists
+};
+
+// Inputs [s', w_Z] of this lane's row of tile unit u in first-layer slot order.
+template <int D_S, int D_WZ, int IN_SLOTS>
+__device__ __forceinline__ ObsRow observe_inputs(const ObserveParams& p, long u, int n_tiles, int g, int col,
+                                                 float (&slots)[IN_SLOTS]) {
+    constexpr int SS = state_slots(D_S), SW = noise_slots(D_WZ);
+    ObsRow w;
+    w.grp = (int)(u / n_tiles);
+    const int tile = (int)(u - (long)w.grp * n_tiles);
+    const int k = w.grp / p.H, t = w.grp - k * p.H;
+    const int i = tile * 32 + col;
+    w.valid = i < p.N;
+    w.r = ((size_t)k * p.N + (w.valid ? i : 0)) * p.H + t;
+#pragma unroll
+    for (int s = 0; s < IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < SS; ++s) {
+        int f = 2 * s + g;
+        slots[s] = (w.valid && f < D_S) ? p.states[w.r * D_S + f] : 0.0f;
+    }
+    if (p.noise) {
+#pragma unroll
+        for (int s = 0; s < SW; ++s) {
+            int f = noise_feature(s, g);
+            slots[SS + s] = (w.valid && f < D_WZ) ? p.noise[w.r * D_WZ + f] : 0.0f;
+        }
+    } else {
+        float nz[SW];
+        noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 4u, g);
+#pragma unroll
+        for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
+    }
+    return w;
+}
+
+template <int D_O>
+__device__ __forceinline__ void observe_store(const ObserveParams& p, const ObsRow& w, const f32x16& o, bool writer,
+                                              int g) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        int f = 2 * s + g;
+        if (writer && w.valid && f < D_O) p.out[w.r * D_O + f] = o[s];
+    }
+}
+
+// MODE kResident / kSplit / kDirect: sized for one belief (n rows); kStream:
+// sized for the rows of whole rollouts, one tile per wave with the weights
+// streamed through LDS like the rollout kernel's.
+template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID, int MODE>
+__global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
+    if constexpr (!net_compiled(DT, WIDTH)) {
+        return;  // binary32 networks wider than 256 are refused at model creation
+    } else {
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ)> NTO;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int n_tiles = (p.N + 31) / 32;
+    const long n_units = (long)p.K * p.H * n_tiles;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if constexpr (MODE == kStream) {
+        const int wpb = blockDim.x >> 6;
+        // each wave keeps the (candidate, step) group's bias row in its own
+        // LDS row, refreshed when the group changes (every N/32 units)
+        float* rowb = reinterpret_cast<float*>(smem + p.row_bias_lds) + wave * NTO::WIDTH;
+        constexpr int RB = NTO::WIDTH / 64;  // bias floats per lane
+        static_assert(NTO::WIDTH % 64 == 0 && RB <= 16, "bias row copy: whole lanes");
+        int have = -1;
+        with_weights<NTO, MODE, 1>(smem, p.obs, [&](auto& src, const NetPtrs& P) {
+            // block-uniform loop (the stream's chunk barriers need every wave)
+            for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
+                const long u = ub * wpb + wave;
+                const bool ok = u < n_units;
+                float slots[NTO::IN_SLOTS];
+                const ObsRow w = observe_inputs<D_S, D_WZ>(p, ok ? u : 0, n_tiles, g, col, slots);
+                const int brow = p.b0_stride ? w.grp : 0;
+                const bool fresh = brow != have;  // wave-uniform
+                float bv[RB];
+                if (fresh) {
+                    const float* src_row = p.b0 + (size_t)brow * p.b0_stride;
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) bv[q] = src_row[q * 64 + lane];
+                }
+                // complete the row loads here so that the compiler's wait for
+                // them does not also drain the weight stream inside the layers
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+                if (fresh) {
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) rowb[q * 64 + lane] = bv[q];
+                    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+                    __builtin_amdgcn_wave_barrier();
+                    have = brow;
+                }
+                const f32x16 o = run_net<NTO>(src, P, rowb, slots, lane, g);
+                observe_store<D_O>(p, w, o, ok, g);
+            }
+        });
+    } else {
+        if (MODE == kResident) {
+            stage_blob(smem, p.obs.base, p.obs.bytes);
+            __syncthreads();
+        }
+        const NetPtrs PO = net_ptrs(MODE == kResident ? (const char*)smem : p.obs.base, p.obs);
+        // split mode: the block's four waves evaluate one tile together
+        const int tpb = MODE == kSplit ? 1 : (int)(blockDim.x >> 6);
+        const long first = MODE == kSplit ? (long)blockIdx.x : (long)blockIdx.x * tpb + wave;
+        for (long u = first; u < n_units; u += (long)gridDim.x * tpb) {
+            float slots[NTO::IN_SLOTS];
+            const ObsRow w = observe_inputs<D_S, D_WZ>(p, u, n_tiles, g, col, slots);
+            const float* b0 = p.b0 + (size_t)w.grp * p.b0_stride;
+            f32x16 o;
+            if constexpr (MODE == kSplit) {
+                o = run_net_split<NTO>(PO, b0, slots, lane, g, wave, smem);
+            } else {
+                auto srco = DirectFor<NTO>::make(PO);
+                o = run_net<NTO>(srco, PO, b0, slots, lane, g);
+            }
+            observe_store<D_O>(p, w, o, MODE != kSplit || wave == 0, g);
+        }
+    }
+    }
+}
+
+// launchers
+#define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, pass_mode<w>()>
+
+hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s) {
+    const size_t lds = weights_in_lds(shape) ? p.obs.bytes : pass_split(shape) ? kSplitLds : 0;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                             \
+    case id * 2 + 0:                                                                                      \
+        hipLaunchKernelGGL((OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);  \
+        break;                                                                                            \
+    case id * 2 + 1:                                                                                      \
+        hipLaunchKernelGGL((OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p); \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+#define OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, plan_mode<w>()>
+
+size_t observe_rollout_lds(int shape, int dt, const NetBlob& obs) {
+    if (weights_in_lds(shape)) return obs.bytes;
+    size_t chunks = kStreamLds;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                       \
+    case id * 2 + 0:                                                \
+        chunks = stream_lds_of<DT_F32, ds, 0, 0, dwz, w, nh>();     \
+        break;                                                      \
+    case id * 2 + 1:                                                \
+        chunks = stream_lds_of<DT_BF16, ds, 0, 0, dwz, w, nh>();    \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return chunks + (obs.bytes - obs.off_b0);
+}
+
+hipError_t launch_observe_rollouts(int shape, int dt, const ObserveParams& p0, int blocks, hipStream_t s) {
+    ObserveParams p = p0;
+    size_t lds = observe_rollout_lds(shape, dt, p.obs);
+    if (!weights_in_lds(shape)) {
+        // one first-layer bias row per wave after the stream buffers and staged biases
+        lds = (lds + 15) / 16 * 16;
+        p.row_bias_lds = (uint32_t)lds;
+        lds += (size_t)kWavesPerBlock * kShapeInfo[shape].width * 4;
+    }
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                \
+    case id * 2 + 0:                                                                                         \
+        if (lds > 65536)                                                                                     \
+            (void)hipFuncSetAttribute((const void*)OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),       \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                 \
+        hipLaunchKernelGGL((OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);    \
+        break;                                                                                               \
+    case id * 2 + 1:                                                                                         \
+        if (lds > 65536)                                                                                     \
+            (void)hipFuncSetAttribute((const void*)OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),      \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                 \
+        hipLaunchKernelGGL((OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p);   \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int observe_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
+    case id * 2 + 0:                                                                                       \
+        return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kSplitLds); \
+    case id * 2 + 1:                                                                                       \
+        return occupancy(OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kSplitLds);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+int observe_rollout_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
+    case id * 2 + 0:                                                                                        \
+        return occupancy(OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kStreamLds); \
+    case id * 2 + 1:                                                                                        \
+        return occupancy(OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kStreamLds);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+}  // namespace voila

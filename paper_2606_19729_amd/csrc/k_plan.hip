@@ -1,0 +1,305 @@
+// k_plan.hip -- the persistent rollout kernel (plan), its batched form and
+// the fixed-order Q reduction.
+//
+// plan_kernel     each wave owns a (candidate, 32-particle) tile, keeps the 32
+//                 states in registers for the whole horizon and runs every
+//                 transition-network layer on the matrix cores (transposed
+//                 evaluation, see device.hpp), with the noise drawn in registers
+//                 from Philox.  Small networks are staged in LDS once per block;
+//                 wide ones stream their fragments from L2.
+// q_reduce_kernel fixed-order sum of the per-tile partial returns into Q.
+#include "kcommon.hpp"
+
+namespace voila {
+
+// One (candidate, 32-particle) tile of one planning instance: H steps of the
+// transition network with the states in registers, then the tile's returns
+// and their (weighted) sum.  `unit_ok` false runs a masked dummy tile (the
+// caller's loop is block-uniform) that writes nothing.
+template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, class Src>
+__device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const PlanParams& p, const float* goal_src,
+                                          long u, bool unit_ok, int lane, int g, int col) {
+    constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
+    // the unit (candidate, tile) is uniform over the wave: its candidate's
+    // actions are read with scalar loads, which leaves the vector-memory
+    // counter to the weight stream
+    const int uw = __builtin_amdgcn_readfirstlane(unit_ok ? (int)u : 0);
+    const int k = uw / p.n_tiles;
+    const int tile = uw - k * p.n_tiles;
+    const int i = tile * 32 + col;
+    const bool valid = unit_ok && i < p.N;
+    float st[SS], goal[SS];
+#pragma unroll
+    for (int s = 0; s < SS; ++s) {
+        int f = 2 * s + g;
+        st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+        goal[s] = f < D_S ? goal_src[f] : 0.0f;
+    }
+    // complete these loads here, once per unit, so that no wait for them (and
+    // with them for the weight stream's loads in flight) lands in the step loop
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+    float G = 0.0f;
+    double disc = 1.0;
+    for (int t = 0; t < p.H; ++t) {
+        float slots[NT::IN_SLOTS];
+#pragma unroll
+        for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SS; ++s) slots[s] = st[s];
+        if (D_A > 0) {
+            const kconst float* a = (const kconst float*)p.cands + ((size_t)k * p.H + t) * D_A;
+#pragma unroll
+            for (int s = 0; s < SA; ++s) {
+                const float a0 = 2 * s < D_A ? a[2 * s] : 0.0f;
+                const float a1 = 2 * s + 1 < D_A ? a[2 * s + 1] : 0.0f;
+                slots[SS + s] = g ? a1 : a0;
+            }
+        }
+        if (p.noise) {
+            const float* nsrc = p.noise + (((size_t)k * p.N + (valid ? i : 0)) * p.H + t) * D_W;
+#pragma unroll
+            for (int s = 0; s < SW; ++s) {
+                int f = noise_feature(s, g);
+                slots[SS + SA + s] = f < D_W ? nsrc[f] : 0.0f;
+            }
+            // wait on this path only (the merged path would wait on every step)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+        } else {
+            float nz[SW];
+            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 3u, g);
+#pragma unroll
+            for (int s = 0; s < SW; ++s) slots[SS + SA + s] = nz[s];
+        }
+        const float* b0 = P.b0;
+        if (N_ACT > 0) {
+            int a = ((const kconst int32_t*)p.cands)[(size_t)k * p.H + t];
+            if (a < 0 || a >= N_ACT) {
+                if (p.status && lane == 0 && unit_ok) p.status[0] = 1;
+                a = 0;
+            }
+            b0 += (size_t)a * p.net.b0_stride;
+        }
+        float r_cur = 0.0f;
+        if (p.reward_at) r_cur = reward_to(st, goal, SS, D_S, g);
+        f32x16 out = run_net<NT>(src, P, b0, slots, lane, g);
+#pragma unroll
+        for (int s = 0; s < SS; ++s) st[s] += out[s];
+        if (p.traj && valid) {
+            float* dst = p.traj + (((size_t)k * p.N + i) * p.H + t) * D_S;
+#pragma unroll
+            for (int s = 0; s < SS; ++s)
+                if (2 * s + g < D_S) dst[2 * s + g] = st[s];
+        }
+        float r = p.reward_at ? r_cur : reward_to(st, goal, SS, D_S, g);
+        G = __builtin_fmaf((float)disc, r, G);
+        disc *= p.gamma;
+    }
+    if (p.returns && g == 0 && valid) p.returns[(size_t)k * p.N + i] = G;
+    float contrib = valid ? (p.belief_w ? (float)p.belief_w[i] * G : G) : 0.0f;
+    float tot = sum32(contrib);
+    if (lane == 0 && unit_ok) p.partials[(size_t)k * p.n_tiles + tile] = tot;
+}
+
+template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, int MODE>
+__global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
+    if constexpr (!net_compiled(DT, WIDTH)) {
+        return;  // binary32 networks wider than 256 are refused at model creation
+    } else {
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6;
+    const long n_units = (long)p.K * p.n_tiles;
+    with_weights<NT, MODE, (N_ACT > 0 ? N_ACT : 1)>(smem, p.net, [&](auto& src, const NetPtrs& P) {
+        // block-uniform loop: every wave of a block walks the same sequence of
+        // (unit, step) iterations, idle waves on a masked dummy unit
+        for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
+            const long u = ub * wpb + wave;
+            plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, p.goal, u, u < n_units, lane, g, col);
+        }
+    });
+    }
+}
+
+// Many planning instances of one network shape in one persistent launch.
+// The work list holds block items (instance, first tile unit, number of
+// units): a block takes items from a queue (atomic counter, list sorted by
+// decreasing cost) or in a static stride, restages the instance's network in
+// LDS when the instance changes, and runs one unit per wave.
+template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID>
+__global__ __launch_bounds__(512) void plan_batch_kernel(BatchPlanParams bp) {
+    if constexpr (WIDTH > 64) {
+        return;  // batches need networks that fit in LDS (the launcher refuses wider ones)
+    } else {
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    __shared__ int s_item;
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wave = threadIdx.x >> 6;
+    int loaded = -1;
+    int item = blockIdx.x;
+    for (int iter = 0;; ++iter) {
+        if (bp.dynamic) {
+            if (threadIdx.x == 0) s_item = atomicAdd(bp.counter, 1);
+            __syncthreads();
+            item = s_item;
+            __syncthreads();
+        } else if (iter > 0) {
+            item += gridDim.x;
+        }
+        if (item >= bp.n_items) break;
+        const int4 it = bp.items[item];  // (instance, first unit, units, cost)
+        PlanParams p = bp.insts[it.x];
+        p.status = bp.status;
+        if (it.x != loaded) {
+            __syncthreads();
+            stage_blob(smem, p.net.base, p.net.bytes);
+            __syncthreads();
+            loaded = it.x;
+        }
+        const NetPtrs P = net_ptrs(smem, p.net);
+        DirectSrc<DT, 8 * NT::HT> src(P.f0);
+        const long u = (long)it.y + wave;
+        // the goal is read from the instance table (a lane-indexed read of the
+        // copy above would place the whole copy in scratch memory)
+        plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, bp.insts[it.x].goal, u, wave < it.z, lane, g,
+                                                         col);
+    }
+    }
+}
+
+__global__ __launch_bounds__(64) void reset_counter_kernel(int* counter) { if (threadIdx.x == 0) *counter = 0; }
+
+__global__ __launch_bounds__(256) void q_reduce_kernel(QReduceParams p) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (k >= p.K) return;
+    float s = 0.0f;
+    for (int j = lane; j < p.n_tiles; j += 64) s += p.partials[(size_t)k * p.n_tiles + j];
+    s += __shfl_xor(s, 32);
+    s = sum32(s);
+    if (lane == 0) p.q[k] = s * p.scale;
+}
+
+__global__ __launch_bounds__(256) void q_reduce_batch_kernel(const QReduceParams* qs) {
+    const QReduceParams p = qs[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (k >= p.K) return;
+    float s = 0.0f;
+    for (int j = lane; j < p.n_tiles; j += 64) s += p.partials[(size_t)k * p.n_tiles + j];
+    s += __shfl_xor(s, 32);
+    s = sum32(s);
+    if (lane == 0) p.q[k] = s * p.scale;
+}
+
+// launchers
+#define PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) plan_kernel<DT, ds, na, da, dw, w, nh, plan_mode<w>()>
+
+size_t plan_stream_lds(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                      \
+    case id * 2 + 0:                                                               \
+        return stream_lds_of<DT_F32, ds, na, (na > 0 ? 0 : da), dw, w, nh>();            \
+    case id * 2 + 1:                                                               \
+        return stream_lds_of<DT_BF16, ds, na, (na > 0 ? 0 : da), dw, w, nh>();
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return kStreamLds;
+}
+#define PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) propose_kernel<DT, ds, dw, w, nh, pass_mode<w>()>
+#define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, pass_mode<w>()>
+
+hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s) {
+    size_t lds = weights_in_lds(shape) ? p.net.bytes : plan_stream_lds(shape, dt) + (p.net.bytes - p.net.off_b0);
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
+    case id * 2 + 0:                                                                                       \
+        if (lds > 65536)                                                                                   \
+            (void)hipFuncSetAttribute((const void*)PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),     \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
+        hipLaunchKernelGGL((PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 256, lds, s, p);  \
+        break;                                                                                             \
+    case id * 2 + 1:                                                                                       \
+        if (lds > 65536)                                                                                   \
+            (void)hipFuncSetAttribute((const void*)PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),    \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
+        hipLaunchKernelGGL((PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 256, lds, s, p); \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int plan_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
+    case id * 2 + 0:                                                                                        \
+        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kStreamLds); \
+    case id * 2 + 1:                                                                                        \
+        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kStreamLds);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+#define PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) plan_batch_kernel<DT, ds, na, da, dw, w, nh>
+
+hipError_t launch_plan_batch(int shape, int dt, const BatchPlanParams& p, int blocks, int wpb, size_t lds,
+                             hipStream_t s) {
+    if (!weights_in_lds(shape)) return hipErrorInvalidValue;
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                     \
+    case id * 2 + 0:                                                                                              \
+        hipLaunchKernelGGL((PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 64 * wpb, lds, s, p);   \
+        break;                                                                                                    \
+    case id * 2 + 1:                                                                                              \
+        hipLaunchKernelGGL((PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 64 * wpb, lds, s, p);  \
+        break;
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int plan_batch_blocks_per_cu(int shape, int dt, int wpb, size_t lds) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                        \
+    case id * 2 + 0:                                                                                 \
+        return occupancy_t(PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), 64 * wpb, lds);      \
+    case id * 2 + 1:                                                                                 \
+        return occupancy_t(PLANB_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), 64 * wpb, lds);
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+
+hipError_t launch_q_reduce_batch(const QReduceParams* d_qs, int n_inst, int max_k, hipStream_t s) {
+    if (n_inst == 0 || max_k == 0) return hipSuccess;
+    hipLaunchKernelGGL(q_reduce_batch_kernel, dim3((max_k + 3) / 4, n_inst), 256, 0, s, d_qs);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(int* d_counter, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, 1, 64, 0, s, d_counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_q_reduce(const QReduceParams& p, hipStream_t s) {
+    const int blocks = (p.K + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(q_reduce_kernel, blocks, 256, 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace voila
