@@ -801,7 +801,9 @@ double or_rollout_objective(const or_model* m, int B, int H, int particles, cons
     for (int b = 0; b < B; ++b)
         per[b] = rollout_objective(m, B, H, particles, S0, a_disc, a_cont, noise, seed, objective, targets, gamma,
                                    goal, b, patterns ? patterns + b : NULL);
-    double total = weighted_sum(B, per, NULL, 1) * (double)B;  /* plain sum in order */
+    /* Neumaier-compensated mean of the per-rollout values in rollout order
+     * (terms per[b] / B), times B: the compensated sum over b */
+    double total = weighted_sum(B, per, NULL, 1) * (double)B;
     free(per);
     double scale = objective == 0 ? 1.0 / ((double)B * H) : 1.0 / (double)B;
     return total * scale;

@@ -160,29 +160,40 @@ def test_autotuner_picks_a_measured_schedule(V, tmp_path, monkeypatch):
     assert r2["cached"] and r2["schedule"] == r["schedule"]
 
 
+# Single rollouts of the small networks in bfloat16 (horizons up to 30),
+# calibrated as twice the largest error seen over 20 seeds x 64 sampled
+# rollouts at horizon 30, rounded up to a power of two: largest seen 1.24e-2
+# against the bfloat16 emulation (median 5e-8).
+BOUND_ROLLOUT_EMUL = 2.0 ** -5
+
+
 def test_batched_workload_full_size_sampled(V):
-    # 64 instances, N in [256, 8192], H in [5, 30], K in [64, 1024], bf16
+    # 64 instances, N in [256, 8192], H in [5, 30], K in [64, 1024], bf16;
+    # 8 sampled rollouts of every instance
     works = workloads.batched()
     insts = []
     for w in works:
         m = V.Model(w.model, compute="bf16")
         insts.append(dict(model=m, states=dev(w.states), cands=dev(w.cands, torch.int32), gamma=w.gamma,
                           goal=w.goal, seed=w.plan_seed, lam=w.lam, update_seed=w.update_seed,
-                          want_returns=(w is works[0] or w is works[-1])))
+                          want_returns=True))
     acts, obs, us, obs_h = update_inputs(works)
     b = V.Batch(insts, with_update=True)
     b.run(actions=acts, obs=obs, resample_u=us)
     torch.cuda.synchronize()
-    for j in [0, len(works) - 1]:
-        w = works[j]
+    worst = 0.0
+    for j, w in enumerate(works):
         G = b.returns[j].cpu().numpy().astype(np.float64)
         rng = np.random.default_rng(j)
-        pairs = [(int(rng.integers(0, w.K)), int(rng.integers(0, w.N))) for _ in range(16)]
+        pairs = [(int(rng.integers(0, w.K)), int(rng.integers(0, w.N))) for _ in range(8)]
+        pairs[0] = (w.K - 1, w.N - 1)
         g_em = oracle.rollouts(w.model, w.states, w.cands, w.gamma, w.goal, pairs, seed=w.plan_seed, bf16=True)
-        e = np.median(np.abs(np.array([G[k, i] for k, i in pairs]) - g_em) / np.abs(g_em))
-        print(f"  instance {j}: N={w.N} K={w.K} H={w.H} median rollout err vs bf16 emulation {e:.2e}", flush=True)
-        assert e <= 2.0 ** -10
+        e = float(np.max(np.abs(np.array([G[k, i] for k, i in pairs]) - g_em) / np.abs(g_em)))
+        worst = max(worst, e)
+        assert e <= BOUND_ROLLOUT_EMUL, (j, e)
         assert torch.allclose(b.q[j], b.returns[j].mean(dim=1), rtol=1e-5)
+    print(f"  all 64 instances: max sampled rollout err vs bf16 emulation {worst:.2e}", flush=True)
+    for j, w in enumerate(works):
         ref = oracle.update(w.model, w.states, w.update_action, obs_h[j], lam=w.lam, seed=w.update_seed,
                             U=w.resample_u, bf16=True)
         mean_d = b.w[j].cpu().numpy() @ ref["S_prop"]

@@ -10,6 +10,18 @@ two (largest seen: 1.01e-2, 2.6e-4 and 1.9e-3 posterior standard deviations):
 * Q relative error vs the bfloat16-emulation oracle:  <= 2^-10
 * pre-resampling posterior mean vs the binary64 oracle, per state
   coordinate, in units of the posterior standard deviation: <= 2^-8
+
+Single rollouts (no averaging over particles) are bounded per result,
+calibrated the same way over 20 seeds x 64 sampled rollouts of the realistic
+networks at horizon 20 (largest seen: 7.7e-3 vs the emulation, 2.9e-2 vs
+binary64):
+* return of every sampled rollout vs the bfloat16-emulation oracle: <= 2^-6
+* return of every sampled rollout vs the binary64 oracle:           <= 2^-4
+Most rollouts agree with the emulation to binary32 rounding (median 5e-8);
+the largest errors come from the rounding of an activation to bfloat16
+falling the other way when the binary32 sum and the emulation's binary64 sum
+sit on either side of a rounding midpoint, which changes that activation by
+one bfloat16 unit and propagates through the later steps.
 """
 import numpy as np
 import pytest
@@ -23,6 +35,8 @@ pytestmark = pytest.mark.gpu
 BOUND_Q_FP64 = 2.0 ** -5
 BOUND_Q_EMUL = 2.0 ** -10
 BOUND_POST = 2.0 ** -8
+BOUND_ROLLOUT_EMUL = 2.0 ** -6
+BOUND_ROLLOUT_FP64 = 2.0 ** -4
 
 
 @pytest.fixture(scope="module")
@@ -82,11 +96,10 @@ def test_bf16_realistic_full_size_sampled(V):
     g_em = oracle.rollouts(w.model, w.states, w.cands, w.gamma, w.goal, pairs, seed=w.plan_seed, bf16=True)
     g64 = oracle.rollouts(w.model, w.states, w.cands, w.gamma, w.goal, pairs, seed=w.plan_seed)
     got = np.array([G[k, i] for k, i in pairs])
-    # single rollouts are noisier than Q (no averaging over particles): report,
-    # and bound the median error by the Q bound
+    # every sampled rollout against the per-rollout bounds
     e_em = np.abs(got - g_em) / np.abs(g_em)
     e64 = np.abs(got - g64) / np.abs(g64)
-    print(f"  sampled rollouts: median err vs emulation {np.median(e_em):.2e} (max {e_em.max():.2e}), "
-          f"vs fp64 {np.median(e64):.2e} (max {e64.max():.2e})", flush=True)
-    assert np.median(e_em) <= BOUND_Q_EMUL
-    assert np.median(e64) <= BOUND_Q_FP64
+    print(f"  sampled rollouts: err vs emulation max {e_em.max():.2e} (median {np.median(e_em):.2e}), "
+          f"vs fp64 max {e64.max():.2e} (median {np.median(e64):.2e})", flush=True)
+    assert e_em.max() <= BOUND_ROLLOUT_EMUL
+    assert e64.max() <= BOUND_ROLLOUT_FP64

@@ -182,8 +182,9 @@ def run_grad(V, m, S, A, O):
 @pytest.mark.parametrize("which,B", [("small", 100), ("small", 256), ("continuous", 65), ("small", 32),
                                      ("small", 1024)])
 def test_param_grad_against_oracle(V, which, B):
-    # the adjoint bound: max |g_dev - g_ref| <= 1e-4 max |g_ref| (binary32
-    # forward and reverse passes over B^2 pairs against binary64)
+    # max |g_dev - g_ref| <= 1e-5 max |g_ref|: the binary32 tolerance relative
+    # to the gradient's scale (binary32 forward and reverse passes over B^2
+    # pairs against binary64)
     w = workloads.small(seed=81) if which == "small" else workloads.continuous(seed=82)
     S, A, O = workloads.nce_batch(w, B, seed=17)
     m = V.Model(w.model)
@@ -193,7 +194,7 @@ def test_param_grad_against_oracle(V, which, B):
     err = float(np.max(np.abs(g - g_ref))) / float(np.max(np.abs(g_ref)))
     print(f"  grad err {err:.2e} of scale {np.max(np.abs(g_ref)):.3e}; loss {loss:.6f} vs {loss_ref:.6f}", flush=True)
     assert g.shape == g_ref.shape
-    assert err <= 1e-4
+    assert err <= TOL
     assert abs(loss - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
     assert abs(g[-1]) <= 1e-5 * float(np.max(np.abs(g_ref)))  # output bias: the scores' derivatives sum to zero
 

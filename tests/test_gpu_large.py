@@ -1,7 +1,13 @@
 """Beliefs above one workgroup (N > 8192): the multi-workgroup normalisation,
 exact blocked prefix sum and two-level binary-search resampler against the
 oracle -- indices bit-exact given the oracle's weights, weights within 1e-13
-given the same log-likelihoods."""
+given the same log-likelihoods.
+
+Above 2^20 particles the quantised weights keep b(N) = 52 - ceil(log2 N) < 32
+fraction bits (31 at 2^20 + 1, 30 at 2^22, 28 at 2^24, 26 at 2^26), so the
+offset is u = U >> (32 - b) and the output step 2^b is smaller; those sizes
+are checked bit for bit too, with offsets whose dropped low bits are all set,
+all clear, or random."""
 import numpy as np
 import pytest
 import torch
@@ -40,6 +46,68 @@ def test_large_resample_bit_exact(V, N):
             idx = V.resample(dev(wv, torch.float64), U)
             torch.cuda.synchronize()
             assert np.array_equal(idx.cpu().numpy(), oracle.resample(wv, U)), (N, ci, U)
+
+
+def weight_cases(rng, N, full=True):
+    """Uniform, one-hot, sparse Dirichlet and zero-mass-subset weights."""
+    cases = [np.full(N, 1.0 / N)]
+    oh = np.zeros(N)
+    oh[N // 3] = 1.0
+    cases.append(oh)
+    if full:
+        cases.append(rng.dirichlet(np.full(N, 0.2)))
+        z = rng.gamma(1.0, size=N)
+        z[rng.integers(0, N, N // 3)] = 0.0
+        cases.append(z / z.sum())
+    else:
+        g = rng.gamma(0.3, size=N)
+        cases.append(g / g.sum())
+    return cases
+
+
+@pytest.mark.parametrize("N", [(1 << 20) + 1, 1 << 22, 1 << 24, 1 << 26])
+def test_large_resample_reduced_fraction_bits(V, N):
+    b = V.resample_bits(N)
+    assert b == oracle.resample_bits(N) and b == 52 - (N - 1).bit_length() and b < 32
+    rng = np.random.default_rng(N + 1)
+    drop = 32 - b
+    Us = [0, 0xFFFFFFFF, (1 << drop) - 1, 1 << drop, int(rng.integers(0, 2**32))]
+    for ci, wv in enumerate(weight_cases(rng, N, full=N <= (1 << 24))):
+        wd = dev(wv, torch.float64)
+        for U in (Us if N <= (1 << 24) else Us[1:3]):
+            print(f"large resample N={N} b={b} case {ci} U={U:#x}", flush=True)
+            idx = V.resample(wd, U)
+            torch.cuda.synchronize()
+            got = idx.cpu().numpy()
+            ref = oracle.resample(wv, U)
+            assert np.array_equal(got, ref), (N, ci, U, int(np.sum(got != ref)))
+            if ci == 0:
+                assert np.array_equal(got, np.arange(N))  # uniform weights: the identity
+        del wd
+
+
+@pytest.mark.parametrize("N", [(1 << 20) + 1, 1 << 22, 1 << 24])
+def test_reweight_resample_reduced_fraction_bits(V, N):
+    """The fused weights + resampling path above 2^20 particles: weights
+    within 1e-13 of the oracle's, indices bit-exact given them, rows gathered."""
+    rng = np.random.default_rng(N + 5)
+    ll = (rng.standard_normal(N) * 3).astype(np.float32)
+    src = rng.standard_normal((N, 16)).astype(np.float32)
+    U = int(rng.integers(0, 2**32)) | ((1 << (32 - V.resample_bits(N))) - 1)
+    print(f"reweight_resample N={N} b={V.resample_bits(N)} U={U:#x}", flush=True)
+    out = V.reweight_resample(dev(ll), U, 1.0, src=dev(src), want_w=True)
+    torch.cuda.synchronize()
+    w = out["w"].cpu().numpy()
+    wr, sr = oracle.normalize(ll.astype(np.float64), 1.0)
+    assert np.max(np.abs(w - wr) / wr) < 1e-13
+    st = out["stats"].cpu().numpy()
+    assert abs(st[0] - sr[0]) / abs(sr[0]) < 1e-12
+    # ESS = 1 / sum w^2: the oracle sums the N squares in sequence, whose
+    # rounding error alone can reach (N - 1) 2^-53 of the sum
+    assert abs(st[1] - sr[1]) / sr[1] <= max(1e-12, 2 * N * 2.0 ** -53)
+    idx = out["idx"].cpu().numpy()
+    assert np.array_equal(idx, oracle.resample(w, U))
+    assert np.array_equal(out["dst"].cpu().numpy(), src[idx])
 
 
 def test_large_resample_gathers_rows(V):

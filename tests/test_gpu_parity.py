@@ -5,8 +5,10 @@ Tolerances (binary32 network arithmetic):
   sensitivity to a one-ulp binary32 perturbation of every input and weight is
   below ~10 ulps per rollout for these networks, so binary32 evaluation in a
   different summation order stays well inside 1e-5.
-* proposal states, observations and log-likelihoods: relative 1e-5 of the
-  value's scale (absolute floor 1e-5 times the largest magnitude).
+* proposal states, observations and log-likelihoods: every element within
+  1e-5 of the array's scale, i.e. max_i |got_i - ref_i| <= 1e-5 max_i |ref_i|
+  (an element-wise relative bound is ill-posed for entries near zero, such
+  as a state coordinate or a log-likelihood that crosses zero).
 * normalised weights from the same binary32 log-likelihoods: relative 1e-13
   (binary64 exp / log of two libraries differ by an ulp or so).
 * resampling indices given the oracle's weights: bit-exact.

@@ -8,9 +8,13 @@ own intermediate results:
   beliefs (key seed + 1), mean per child and L_eta, within 1e-5 relative;
 * Psi, V(b), pi and the greedy action from the device's R and child values:
   the backup within 1e-12, the soft value as voila_soft_value's bound;
-* the whole composition against the oracle's, within 1e-3 relative (a
-  resampling decision may fall the other way once the binary32 and binary64
-  weights differ in the last bits).
+* the whole composition against the oracle's: first every child row equals
+  the oracle's own child row within 1e-5 of the scale (every resampling
+  decision fell the same way for these seeded cases; a decision could fall
+  the other way only if binary32 and binary64 weights straddled a quantisation
+  boundary), then Psi within 1e-5 relative -- R, the prior term and the child
+  values are all non-positive, so no cancellation amplifies their 1e-5
+  relative errors in the sum.
 """
 import numpy as np
 import pytest
@@ -76,12 +80,15 @@ def run_case(V, w, first, n_obs, cont, gamma=0.95, eta=2.0, lam=1.0, seed=1234, 
     # 5. the whole composition
     full = oracle.plan_closed_loop(w.model, w.states, first, n_obs, cont, gamma, eta, lam, w.goal, seed, U,
                                    log_pi0=log_pi0)
+    e_child = float(np.max(np.abs(d["child"] - full["child"]))) / float(np.max(np.abs(full["child"])))
+    assert e_child <= 1e-5, e_child
     e_full = rel(d["psi"], full["psi"])
-    print(f"  R {e_R:.2e}; V_child {e_Vc:.2e}; psi {e_psi:.2e}; psi vs full oracle {e_full:.2e}; "
+    print(f"  R {e_R:.2e}; V_child {e_Vc:.2e}; psi {e_psi:.2e}; child rows vs full oracle {e_child:.2e}; "
+          f"psi vs full oracle {e_full:.2e}; "
           f"best {int(d['best'][0])} (oracle {full['best']})", flush=True)
     assert e_R <= 1e-5 and e_Vc <= 1e-5 and e_psi <= 1e-12
     assert rel(d["V"], V_ref) <= 1e-12 and rel(d["pi"], pi_ref[0]) <= 1e-12 and int(d["best"][0]) == best_ref[0]
-    assert e_full <= 1e-3
+    assert e_full <= 1e-5
 
 
 def test_small_tree(V):

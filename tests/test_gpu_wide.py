@@ -30,6 +30,12 @@ BOUND_Q_FP64 = 2.0 ** -5
 BOUND_Q_EMUL = 2.0 ** -10
 BOUND_OBS = 2.0 ** -9
 BOUND_POST = 2.0 ** -8
+# Single rollouts at the large counts (horizon 20), calibrated the same way
+# over 10 seeds x 32 sampled rollouts: largest seen 9.5e-3 against the
+# bfloat16 emulation (median 1.3e-7; the large ones come from an activation
+# whose bfloat16 rounding falls the other way under binary32 and binary64
+# sums, one bfloat16 unit carried through the later steps).
+BOUND_ROLLOUT_EMUL = 2.0 ** -5
 
 
 @pytest.fixture(scope="module")
@@ -165,8 +171,8 @@ def test_wide_large_counts_sampled(V):
     g_em = oracle.rollouts(w.model, w.states, w.cands, w.gamma, w.goal, pairs, seed=w.plan_seed, bf16=True)
     got = np.array([G[k, i] for k, i in pairs])
     e_em = np.abs(got - g_em) / np.abs(g_em)
-    print(f"  sampled rollouts vs emulation: median {np.median(e_em):.2e} max {e_em.max():.2e}", flush=True)
-    assert np.median(e_em) <= BOUND_Q_EMUL
+    print(f"  sampled rollouts vs emulation: max {e_em.max():.2e} median {np.median(e_em):.2e}", flush=True)
+    assert e_em.max() <= BOUND_ROLLOUT_EMUL
     # Q is the mean of the returns
     qs = G.mean(axis=1)
     assert np.max(np.abs(q.cpu().numpy() - qs) / np.abs(qs)) <= 1e-5
