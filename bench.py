@@ -167,7 +167,8 @@ def bench_wide(V, torch, reps):
     q = torch.empty(w.K, dtype=torch.float32, device=dev)
     ws = mb.plan_workspace(w.N, w.K, w.H)
     wsu = mb.update_workspace(w.N)
-    obs = np.zeros(w.model.d_o, np.float32)
+    obs = torch.zeros(w.model.d_o, dtype=torch.float32, device=dev)
+    act = torch.tensor([w.update_action], dtype=torch.int32, device=dev)
     upd_out = {"states": torch.empty((w.N, 4), dtype=torch.float32, device=dev),
                "idx": torch.empty(w.N, dtype=torch.int32, device=dev),
                "w": torch.empty(w.N, dtype=torch.float64, device=dev),
@@ -178,7 +179,7 @@ def bench_wide(V, torch, reps):
     def once(r):
         V.plan(mb, S, C, w.gamma, w.goal, seed=r, q_out=q, workspace=ws)
         e_mid.record(stream)
-        V.update(mb, S, w.update_action, obs, lam=w.lam, seed=r + 1, U=w.resample_u, out=upd_out, workspace=wsu)
+        V.update(mb, S, act, obs, lam=w.lam, seed=r + 1, U=w.resample_u, out=upd_out, workspace=wsu)
 
     e_mid = torch.cuda.Event(enable_timing=True)
     once(0)
@@ -210,7 +211,8 @@ def bench_small(V, torch, reps):
     q = torch.empty(w.K, dtype=torch.float32, device=dev)
     ws = m.plan_workspace(w.N, w.K, w.H)
     wsu = m.update_workspace(w.N)
-    obs = np.zeros(w.model.d_o, np.float32)
+    obs = torch.zeros(w.model.d_o, dtype=torch.float32, device=dev)
+    act = torch.tensor([w.update_action], dtype=torch.int32, device=dev)
     upd_out = {"states": torch.empty((w.N, w.model.d_s), dtype=torch.float32, device=dev),
                "idx": torch.empty(w.N, dtype=torch.int32, device=dev),
                "w": torch.empty(w.N, dtype=torch.float64, device=dev),
@@ -224,7 +226,7 @@ def bench_small(V, torch, reps):
         a.record(stream)
         V.plan(m, S, C, w.gamma, w.goal, seed=r, q_out=q, workspace=ws)
         mid.record(stream)
-        V.update(m, S, w.update_action, obs, lam=w.lam, seed=r + 1, U=w.resample_u, out=upd_out, workspace=wsu)
+        V.update(m, S, act, obs, lam=w.lam, seed=r + 1, U=w.resample_u, out=upd_out, workspace=wsu)
         b.record(stream)
         torch.cuda.synchronize()
         if r > 0:
@@ -651,8 +653,9 @@ def main():
              workspace=ws_upd)
     s_true = upd_out["prop"][w.true_index:w.true_index + 1].clone()
     obs = V.observe(m, s_true, w.update_action, noise=torch.as_tensor(w.obs_noise[None], device=dev))
+    obs = obs[0]  # stays in device memory: the update reads it there
+    act = torch.as_tensor(np.asarray(w.update_action, dtype=np.float32), device=dev)
     torch.cuda.synchronize()
-    obs = obs.cpu().numpy()[0]
 
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
@@ -662,8 +665,7 @@ def main():
         if e0: e0.record(stream)
         V.plan(m, S, C, w.gamma, w.goal, seed=seed, q_out=q, workspace=ws_plan)
         if e1: e1.record(stream)
-        V.update(m, S, w.update_action, obs, lam=w.lam, seed=seed + 1, U=w.resample_u, out=upd_out,
-                 workspace=ws_upd)
+        V.update(m, S, act, obs, lam=w.lam, seed=seed + 1, U=w.resample_u, out=upd_out, workspace=ws_upd)
         if e2: e2.record(stream)
         if rec is not None:
             rec.append((e0, e1, e2))

@@ -163,14 +163,20 @@ typedef struct {
 /* Bytes of device workspace voila_update needs for N particles. */
 size_t voila_update_workspace_size(voila_model_t model, int32_t N);
 
-/* h_action: host pointer to one int32 action index (discrete) or d_a floats
- * (continuous); h_obs: host [d_o] floats.  Outputs: d_states_out [N][d_s]
- * float (required); optional d_idx_out [N] int32, d_w_out [N] double (weights
- * before resampling), d_loglik_out [N] float, d_prop_out [N][d_s] float
- * (proposal particles), d_stats_out [2] double, d_status (int32 status word).
+/* d_action: device pointer to the executed action, one int32 index (discrete)
+ * or d_a floats (continuous); d_obs: device [d_o] floats, the received
+ * observation.  Both are read on the device when the stream reaches the call
+ * (an observation drawn by voila_observe needs no host round trip, and a
+ * captured graph replays with whatever the two buffers hold then).  A discrete
+ * action outside [0, n_actions) or a non-finite action or observation value
+ * sets *d_status to VOILA_ERR_INVALID_ARG (an out-of-range action is then
+ * taken as action 0).  Outputs: d_states_out [N][d_s] float (required);
+ * optional d_idx_out [N] int32, d_w_out [N] double (weights before
+ * resampling), d_loglik_out [N] float, d_prop_out [N][d_s] float (proposal
+ * particles), d_stats_out [2] double, d_status (int32 status word).
  * 1 <= N <= voila_update_max_particles(). */
 voila_status_t voila_update(voila_model_t model, const float* d_states, const double* d_prior_w, int32_t N,
-                            const void* h_action, const float* h_obs, const voila_update_opts_t* h_opts,
+                            const void* d_action, const float* d_obs, const voila_update_opts_t* h_opts,
                             void* d_workspace, size_t workspace_bytes, float* d_states_out, int32_t* d_idx_out,
                             double* d_w_out, float* d_loglik_out, float* d_prop_out, double* d_stats_out,
                             int32_t* d_status, void* stream);
@@ -184,15 +190,22 @@ int32_t voila_update_max_particles(void);
 size_t voila_weights_workspace_size(int32_t N);
 
 /* ---------------------------------------------------------------------------
- * Stages of update, exported on their own.
+ * Stages of update, exported on their own.  They are the reweighting and
+ * resampling halves of the particle belief operator tau(b, a, o) of Sec. 2.1
+ * (the posterior proportional to the observation likelihood times the
+ * predicted belief) as Sec. 3 approximates it with sequential importance
+ * resampling, weights exp(l / lambda) as in Sec. 4.2 ("Likelihood Model").
  * ------------------------------------------------------------------------- */
 /* Weight normalisation of given log-likelihoods d_loglik [N] float:
- * w'_i and stats exactly as in voila_update.  d_prior_w [N] double or NULL. */
+ * w'_i and stats exactly as in voila_update (Sec. 2.1: the normalised
+ * posterior weights; the log evidence is log Z of the same section, the
+ * normaliser of tau).  d_prior_w [N] double or NULL. */
 voila_status_t voila_normalize(const float* d_loglik, const double* d_prior_w, int32_t N, double lambda,
                                double* d_w_out, double* d_stats_out, int32_t* d_status, void* d_workspace,
                                size_t workspace_bytes, void* stream);
 
-/* The update's second stage on its own, in one call: weights of given
+/* The update's second stage on its own, in one call (the weighting and
+ * resampling steps of Sec. 3): weights of given
  * log-likelihoods d_loglik [N] (as voila_normalize) followed by systematic
  * resampling and the optional row gather (as voila_resample), without a
  * round trip of the weights through memory unless d_w_out is given.
@@ -205,7 +218,10 @@ voila_status_t voila_reweight_resample(const float* d_loglik, const double* d_pr
 /* Fraction bits b(N) = min(32, 52 - ceil(log2 N)) of the quantised weights. */
 int32_t voila_resample_bits(int32_t N);
 
-/* Systematic resampling of normalised binary64 weights d_w [N]:
+/* Systematic resampling (the resampling step of Sec. 3, whose scheme the
+ * paper leaves open; systematic with a quantised, exactly summed weight
+ * prefix, so that any summation order gives identical indices) of normalised
+ * binary64 weights d_w [N]:
  *   q_i = rint(w_i * N * 2^b)   (ties to even; exact integers)
  *   C_i = q_0 + ... + q_i       (binary64, exact because C_i < 2^53)
  *   u = U >> (32 - b), P_j = j * 2^b + u
@@ -219,15 +235,16 @@ voila_status_t voila_resample(const double* d_w, int32_t N, uint32_t U, int32_t*
 
 /* ---------------------------------------------------------------------------
  * observe: o_r = f_Z([s'_r, a, w_Z,r]) (Sec. 4.2, Eq. 5) for n rows sharing
- * one action; noise explicit (d_noise [n][d_wz]) or Philox stream 4 with
- * counter (r, 0, 0) under `seed`.  d_states [n][d_s] float, d_obs_out
- * [n][d_o] float; the workspace holds the first-layer bias with the action
- * folded in.
+ * one action (d_action: device int32 index or float [d_a], read on the
+ * device as in voila_update, with the same status on a bad value); noise
+ * explicit (d_noise [n][d_wz]) or Philox stream 4 with counter (r, 0, 0)
+ * under `seed`.  d_states [n][d_s] float, d_obs_out [n][d_o] float; the
+ * workspace holds the first-layer bias with the action folded in.
  * ------------------------------------------------------------------------- */
 size_t voila_observe_workspace_size(voila_model_t model);
-voila_status_t voila_observe(voila_model_t model, const float* d_states, int32_t n, const void* h_action,
+voila_status_t voila_observe(voila_model_t model, const float* d_states, int32_t n, const void* d_action,
                              uint64_t seed, const float* d_noise, void* d_workspace, size_t workspace_bytes,
-                             float* d_obs_out, void* stream);
+                             float* d_obs_out, int32_t* d_status, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Per-step observations of the plan rollouts: the forward simulation of

@@ -19,6 +19,7 @@ Functions mirror include/voila.h:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from ctypes import POINTER, c_double, c_float, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
 
@@ -122,7 +123,7 @@ def _load():
     L.voila_plan.restype = c_int32
     L.voila_update_workspace_size.argtypes = [vp, c_int32]
     L.voila_update_workspace_size.restype = c_size_t
-    L.voila_update.argtypes = [vp, vp, vp, c_int32, vp, POINTER(c_float), POINTER(_UpdateOpts), vp, c_size_t,
+    L.voila_update.argtypes = [vp, vp, vp, c_int32, vp, vp, POINTER(_UpdateOpts), vp, c_size_t,
                                vp, vp, vp, vp, vp, vp, vp, vp]
     L.voila_update.restype = c_int32
     L.voila_update_max_particles.restype = c_int32
@@ -139,7 +140,7 @@ def _load():
     L.voila_resample.restype = c_int32
     L.voila_observe_workspace_size.argtypes = [vp]
     L.voila_observe_workspace_size.restype = c_size_t
-    L.voila_observe.argtypes = [vp, vp, c_int32, vp, c_uint64, vp, vp, c_size_t, vp, vp]
+    L.voila_observe.argtypes = [vp, vp, c_int32, vp, c_uint64, vp, vp, c_size_t, vp, vp, vp]
     L.voila_observe.restype = c_int32
     L.voila_plan_observe_workspace_size.argtypes = [vp, c_int32, c_int32]
     L.voila_plan_observe_workspace_size.restype = c_size_t
@@ -610,19 +611,47 @@ def pw_step(model: Model, succ, seg, actions, visits, children, obs_table, U, k_
     return res
 
 
-def _action_arg(model, action):
+def _action_dev(model, action, device):
+    """The executed action as the device buffer the library reads: a CUDA
+    tensor is passed through (int32 [1] index, or float32 [d_a]); a host value
+    is checked and copied to a small device tensor."""
     d = model.desc
+    if isinstance(action, torch.Tensor) and action.is_cuda:
+        if d.n_actions > 0:
+            return _dev(action.reshape(1), torch.int32, (1,), "action")
+        return _dev(action.reshape(-1), torch.float32, (d.d_a,), "action")
     if d.n_actions > 0:
-        return (c_int32 * 1)(int(action))
+        a = int(action.item() if hasattr(action, "item") else action)
+        if not 0 <= a < d.n_actions:
+            raise VoilaError(VOILA_ERR_INVALID_ARG, "action index out of range")
+        return torch.tensor([a], dtype=torch.int32, device=device)
     vals = [float(x) for x in (action.tolist() if hasattr(action, "tolist") else action)]
     if len(vals) != d.d_a:
         raise VoilaError(VOILA_ERR_INVALID_ARG, f"continuous action must have {d.d_a} values")
-    return (c_float * d.d_a)(*vals)
+    if not all(math.isfinite(v) for v in vals):
+        raise VoilaError(VOILA_ERR_INVALID_ARG, "non-finite action")
+    return torch.tensor(vals, dtype=torch.float32, device=device)
+
+
+def _obs_dev(model, obs, device):
+    """The observation as a device float32 [d_o] buffer (a CUDA tensor is
+    passed through; a host value is checked and copied)."""
+    d = model.desc
+    if isinstance(obs, torch.Tensor) and obs.is_cuda:
+        return _dev(obs.reshape(-1), torch.float32, (d.d_o,), "observation")
+    vals = [float(x) for x in (obs.tolist() if hasattr(obs, "tolist") else obs)]
+    if len(vals) != d.d_o:
+        raise VoilaError(VOILA_ERR_INVALID_ARG, f"observation must have {d.d_o} values")
+    if not all(math.isfinite(v) for v in vals):
+        raise VoilaError(VOILA_ERR_INVALID_ARG, "non-finite observation")
+    return torch.tensor(vals, dtype=torch.float32, device=device)
 
 
 def update(model: Model, states, action, obs, lam=1.0, prior_w=None, seed=0, U=0, noise=None, want_idx=True,
            want_w=True, want_loglik=True, want_prop=True, out=None, workspace=None, status=None, stream=None):
-    """SIR belief update; returns dict(states, idx, w, loglik, prop, stats)."""
+    """SIR belief update; returns dict(states, idx, w, loglik, prop, stats).
+    `action` and `obs` are read on the device: CUDA tensors are passed as they
+    are (no host round trip, capturable), host values are copied first."""
     d = model.desc
     N = int(states.shape[0])
     _dev(states, torch.float32, (N, d.d_s), "states")
@@ -630,11 +659,12 @@ def update(model: Model, states, action, obs, lam=1.0, prior_w=None, seed=0, U=0
         _dev(prior_w, torch.float64, (N,), "prior_w")
     if noise is not None:
         _dev(noise, torch.float32, (N, d.d_w), "noise")
-    obs_vals = [float(x) for x in (obs.tolist() if hasattr(obs, "tolist") else obs)]
-    if len(obs_vals) != d.d_o:
-        raise VoilaError(VOILA_ERR_INVALID_ARG, f"observation must have {d.d_o} values")
-    obs_arr = (c_float * d.d_o)(*obs_vals)
     dev = states.device
+    a_dev = _action_dev(model, action, dev)
+    o_dev = _obs_dev(model, obs, dev)
+    if stream is not None:  # the copies of host values must outlive the call on that stream
+        a_dev.record_stream(stream)
+        o_dev.record_stream(stream)
     o = out if out is not None else {}
     res = {
         "states": o.get("states", torch.empty((N, d.d_s), dtype=torch.float32, device=dev)),
@@ -646,8 +676,8 @@ def update(model: Model, states, action, obs, lam=1.0, prior_w=None, seed=0, U=0
     }
     opts = _UpdateOpts(float(lam), int(seed) & (2**64 - 1), int(U) & 0xFFFFFFFF, _ptr(noise))
     ws = workspace if workspace is not None else model.update_workspace(N)
-    _check(lib.voila_update(model.handle, _ptr(states), _ptr(prior_w), N, ctypes.cast(_action_arg(model, action),
-                            c_void_p), obs_arr, ctypes.byref(opts), _ptr(ws), ws.numel(), _ptr(res["states"]),
+    _check(lib.voila_update(model.handle, _ptr(states), _ptr(prior_w), N, _ptr(a_dev), _ptr(o_dev),
+                            ctypes.byref(opts), _ptr(ws), ws.numel(), _ptr(res["states"]),
                             _ptr(res["idx"]), _ptr(res["w"]), _ptr(res["loglik"]), _ptr(res["prop"]),
                             _ptr(res["stats"]), _ptr(status), _stream(stream)))
     return res
@@ -716,8 +746,8 @@ def reweight_resample(loglik, U, lam=1.0, prior_w=None, src=None, want_w=False, 
     return {"idx": idx, "w": w, "stats": stats, "dst": dst}
 
 
-def observe(model: Model, states, action, seed=0, noise=None, workspace=None, out=None, stream=None):
-    """o [n, d_o] float32 from the observation network."""
+def observe(model: Model, states, action, seed=0, noise=None, workspace=None, out=None, status=None, stream=None):
+    """o [n, d_o] float32 from the observation network (`action` as in update)."""
     d = model.desc
     n = int(states.shape[0])
     _dev(states, torch.float32, (n, d.d_s), "states")
@@ -725,8 +755,11 @@ def observe(model: Model, states, action, seed=0, noise=None, workspace=None, ou
         _dev(noise, torch.float32, (n, d.d_wz), "noise")
     o = out if out is not None else torch.empty((n, d.d_o), dtype=torch.float32, device=states.device)
     ws = workspace if workspace is not None else model.observe_workspace()
-    _check(lib.voila_observe(model.handle, _ptr(states), n, ctypes.cast(_action_arg(model, action), c_void_p),
-                             int(seed) & (2**64 - 1), _ptr(noise), _ptr(ws), ws.numel(), _ptr(o), _stream(stream)))
+    a_dev = _action_dev(model, action, states.device)
+    if stream is not None:
+        a_dev.record_stream(stream)
+    _check(lib.voila_observe(model.handle, _ptr(states), n, _ptr(a_dev), int(seed) & (2**64 - 1), _ptr(noise),
+                             _ptr(ws), ws.numel(), _ptr(o), _ptr(status), _stream(stream)))
     return o
 
 

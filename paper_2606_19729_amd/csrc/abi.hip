@@ -635,27 +635,26 @@ UpdateWs carve_update(char* base, int width, int N, int d_s) {
     return w;
 }
 
-voila_status_t fold_vector(voila_model_t m, const void* h_action, const float* h_obs, bool with_obs, FoldParams& f) {
-    int nf = 0;
-    if (m->n_actions > 0) {
-        int a = *reinterpret_cast<const int32_t*>(h_action);
-        if (a < 0 || a >= m->n_actions) return fail(VOILA_ERR_INVALID_ARG, "action index out of range");
-        for (int j = 0; j < m->n_actions; ++j) f.v[nf++] = j == a ? 1.0f : 0.0f;
-    } else {
-        const float* a = reinterpret_cast<const float*>(h_action);
-        for (int j = 0; j < m->d_a; ++j) {
-            if (!std::isfinite(a[j])) return fail(VOILA_ERR_INVALID_ARG, "non-finite action");
-            f.v[nf++] = m->dt == DT_BF16 ? bf16_round(a[j]) : a[j];
-        }
-    }
-    if (with_obs)
-        for (int j = 0; j < m->d_o; ++j) {
-            if (!std::isfinite(h_obs[j])) return fail(VOILA_ERR_INVALID_ARG, "non-finite observation");
-            f.v[nf++] = m->dt == DT_BF16 ? bf16_round(h_obs[j]) : h_obs[j];
-        }
-    f.nf = nf;
+// First-layer bias of one network with the executed action (and, for the
+// likelihood, the observation) read from device memory and folded in, so the
+// fold follows whatever those buffers hold when the stream reaches it.
+FoldStepsParams fold_one(voila_model_t m, const float* w, const float* b, int nf, const void* d_action,
+                         const float* d_obs, float* out, int32_t* d_status) {
+    FoldStepsParams f{};
+    f.w = w;
+    f.b = b;
+    f.out = out;
+    f.cands = d_action;
+    f.obs = d_obs;
     f.width = m->width;
-    return VOILA_OK;
+    f.nf = nf;
+    f.rows = 1;
+    f.n_actions = m->n_actions;
+    f.d_a = m->d_a;
+    f.d_o = d_obs ? m->d_o : 0;
+    f.bf16 = m->dt == DT_BF16 ? 1 : 0;
+    f.status = d_status;
+    return f;
 }
 }  // namespace
 
@@ -665,34 +664,26 @@ size_t voila_update_workspace_size(voila_model_t m, int32_t N) {
 }
 
 voila_status_t voila_update(voila_model_t m, const float* d_states, const double* d_prior_w, int32_t N,
-                            const void* h_action, const float* h_obs, const voila_update_opts_t* o, void* ws,
+                            const void* d_action, const float* d_obs, const voila_update_opts_t* o, void* ws,
                             size_t ws_bytes, float* d_states_out, int32_t* d_idx_out, double* d_w_out,
                             float* d_loglik_out, float* d_prop_out, double* d_stats_out, int32_t* d_status,
                             void* stream) {
     if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
     if (!m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model has no likelihood network");
-    if (!o || !h_action || !h_obs) return fail(VOILA_ERR_INVALID_ARG, "NULL options, action or observation");
+    if (!o || !d_action || !d_obs) return fail(VOILA_ERR_INVALID_ARG, "NULL options, action or observation");
     if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
     if (N > kLargeMaxN) return fail(VOILA_ERR_UNSUPPORTED, "N above voila_update_max_particles()");
     if (!(o->lambda > 0.0) || !std::isfinite(o->lambda)) return fail(VOILA_ERR_INVALID_ARG, "lambda must be > 0");
     if (!d_states || !d_states_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
     UpdateWs w = carve_update(reinterpret_cast<char*>(ws), m->width, N, m->d_s);
     if (!ws || ws_bytes < w.bytes) return fail(VOILA_ERR_WORKSPACE, "update workspace too small");
-    FoldParams ft{}, fl{};
-    voila_status_t st;
-    if ((st = fold_vector(m, h_action, h_obs, false, ft)) != VOILA_OK) return st;
-    if ((st = fold_vector(m, h_action, h_obs, true, fl)) != VOILA_OK) return st;
     DeviceGuard guard(m->device);
     if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    ft.w = m->fold_w_trans;
-    ft.b = m->fold_b_trans;
-    ft.out = w.b0_trans;
-    fl.w = m->fold_w_lik;
-    fl.b = m->fold_b_lik;
-    fl.out = w.b0_lik;
-    VOILA_CHECK_HIP(launch_fold(ft, s));
-    VOILA_CHECK_HIP(launch_fold(fl, s));
+    VOILA_CHECK_HIP(launch_fold_steps(
+        fold_one(m, m->fold_w_trans, m->fold_b_trans, m->nf_trans, d_action, nullptr, w.b0_trans, d_status), s));
+    VOILA_CHECK_HIP(launch_fold_steps(
+        fold_one(m, m->fold_w_lik, m->fold_b_lik, m->nf_lik, d_action, d_obs, w.b0_lik, d_status), s));
     ProposeParams p{};
     p.trans = m->trans_upd;
     p.lik = m->lik;
@@ -899,25 +890,22 @@ size_t voila_observe_workspace_size(voila_model_t m) {
     return align_up((size_t)m->width * 4, 256);
 }
 
-voila_status_t voila_observe(voila_model_t m, const float* d_states, int32_t n, const void* h_action, uint64_t seed,
-                             const float* d_noise, void* ws, size_t ws_bytes, float* d_obs_out, void* stream) {
+voila_status_t voila_observe(voila_model_t m, const float* d_states, int32_t n, const void* d_action, uint64_t seed,
+                             const float* d_noise, void* ws, size_t ws_bytes, float* d_obs_out, int32_t* d_status,
+                             void* stream) {
     if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
     if (!m->has_obs) return fail(VOILA_ERR_INVALID_ARG, "the model has no observation network");
     if (n < 0) return fail(VOILA_ERR_INVALID_ARG, "n must be >= 0");
-    if (!h_action) return fail(VOILA_ERR_INVALID_ARG, "NULL action");
+    if (!d_action) return fail(VOILA_ERR_INVALID_ARG, "NULL action");
     if (n == 0) return VOILA_OK;
     if (!d_states || !d_obs_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
     if (!ws || ws_bytes < voila_observe_workspace_size(m)) return fail(VOILA_ERR_WORKSPACE, "observe workspace too small");
-    FoldParams f{};
-    voila_status_t st;
-    if ((st = fold_vector(m, h_action, nullptr, false, f)) != VOILA_OK) return st;
     DeviceGuard guard(m->device);
     if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    f.w = m->fold_w_obs;
-    f.b = m->fold_b_obs;
-    f.out = reinterpret_cast<float*>(ws);
-    VOILA_CHECK_HIP(launch_fold(f, s));
+    const FoldStepsParams f = fold_one(m, m->fold_w_obs, m->fold_b_obs, m->nf_obs, d_action, nullptr,
+                                       reinterpret_cast<float*>(ws), d_status);
+    VOILA_CHECK_HIP(launch_fold_steps(f, s));
     ObserveParams p{};
     p.obs = m->obs;
     p.b0 = f.out;

@@ -7,25 +7,22 @@ namespace voila {
 
 const ShapeInfo& shape_info(int shape) { return kShapeInfo[shape]; }
 
-__global__ __launch_bounds__(256) void fold_kernel(FoldParams p) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= p.width) return;
-    float acc = p.b[r];
-    for (int c = 0; c < p.nf; ++c) acc += p.w[(size_t)r * p.nf + c] * p.v[c];
-    p.out[r] = acc;
-}
-
-// First-layer biases with the action of every (candidate, step) group folded
-// in, in the column order of fold_kernel.
+// First-layer biases with the action (then the observation) of every row
+// folded in: the first layer's weight columns of those inputs times their
+// values (a one-hot action selects its column), added to the bias.  Inputs are
+// read from device memory; a discrete action outside [0, n_actions) or a
+// non-finite action or observation value sets the status word to
+// VOILA_ERR_INVALID_ARG (an out-of-range action is then taken as action 0).
 __global__ __launch_bounds__(256) void fold_steps_kernel(FoldStepsParams p) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= p.width) return;
     for (int j = blockIdx.y; j < p.rows; j += gridDim.y) {
         float acc = p.b[r];
+        bool bad = false;
         if (p.n_actions > 0) {
             int a = reinterpret_cast<const int32_t*>(p.cands)[j];
             if (a < 0 || a >= p.n_actions) {
-                if (p.status && r == 0) p.status[0] = 1;
+                bad = true;
                 a = 0;
             }
             for (int c = 0; c < p.n_actions; ++c) acc += p.w[(size_t)r * p.nf + c] * (c == a ? 1.0f : 0.0f);
@@ -33,6 +30,7 @@ __global__ __launch_bounds__(256) void fold_steps_kernel(FoldStepsParams p) {
             const float* ac = reinterpret_cast<const float*>(p.cands) + (size_t)j * p.d_a;
             for (int c = 0; c < p.d_a; ++c) {
                 float v = ac[c];
+                bad |= !isfinite(v);
                 if (p.bf16) v = (float)(__bf16)v;
                 acc += p.w[(size_t)r * p.nf + c] * v;
             }
@@ -42,10 +40,12 @@ __global__ __launch_bounds__(256) void fold_steps_kernel(FoldStepsParams p) {
             const float* ob = p.obs + (size_t)j * p.d_o;
             for (int c = 0; c < p.d_o; ++c) {
                 float v = ob[c];
+                bad |= !isfinite(v);
                 if (p.bf16) v = (float)(__bf16)v;
                 acc += p.w[(size_t)r * p.nf + c0 + c] * v;
             }
         }
+        if (bad && p.status && r == 0) p.status[0] = 1;
         p.out[(size_t)j * p.width + r] = acc;
     }
 }
@@ -363,11 +363,6 @@ hipError_t launch_norm_res_batch(const NormResParams* d_ps, int n_inst, const ui
                                  hipStream_t s) {
     if (n_inst == 0) return hipSuccess;
     hipLaunchKernelGGL(norm_res_batch_kernel, n_inst, kNormResThreads, 0, s, d_ps, d_u, d_status);
-    return hipGetLastError();
-}
-
-hipError_t launch_fold(const FoldParams& p, hipStream_t s) {
-    hipLaunchKernelGGL(fold_kernel, (p.width + 255) / 256, 256, 0, s, p);
     return hipGetLastError();
 }
 

@@ -54,14 +54,6 @@ struct QReduceParams {
     float scale;
 };
 
-struct FoldParams {
-    const float* w;   // [width][nf]
-    const float* b;   // [width]
-    float* out;       // [width]
-    int width, nf;
-    float v[96];
-};
-
 struct ProposeParams {
     NetBlob trans, lik;
     const float* b0_trans;   // folded first-layer bias of the transition net [width]
@@ -351,7 +343,6 @@ constexpr int kNormResThreads = 1024;
 // Kernel launchers (return the launch status).
 hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s);
 hipError_t launch_q_reduce(const QReduceParams& p, hipStream_t s);
-hipError_t launch_fold(const FoldParams& p, hipStream_t s);
 hipError_t launch_fold_steps(const FoldStepsParams& p, hipStream_t s);
 // Grouped progressive-widening stages.
 hipError_t launch_pw_first(const PwParams& p, hipStream_t s);
