@@ -181,6 +181,26 @@ voila_status_t voila_update(voila_model_t model, const float* d_states, const do
                             double* d_w_out, float* d_loglik_out, float* d_prop_out, double* d_stats_out,
                             int32_t* d_status, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): voila_update
+ * with its workspace taken from a fixed array in the library's device code,
+ * VOILA_UPDATE_NOALLOC_SCRATCH_BYTES (8 MiB) per device, held from the
+ * library's load until the process ends.  Arguments, outputs and results are
+ * those of voila_update.  The call allocates nothing (no hipMalloc, no
+ * allocating library routine); its first call on a device looks up that
+ * device's copy of the array.  N is limited to what the array holds:
+ * voila_update_workspace_size(model, N) <= VOILA_UPDATE_NOALLOC_SCRATCH_BYTES
+ * (every N up to 65,536 fits for the compiled shapes), else
+ * VOILA_ERR_UNSUPPORTED.  Every call on a device shares that device's array:
+ * calls that overlap on one device (concurrent streams, or host threads
+ * without ordering) race and give undefined results; calls ordered on one
+ * stream are safe.  Nothing in the array needs clearing between calls. */
+#define VOILA_UPDATE_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+voila_status_t voila_update_noalloc(voila_model_t model, const float* d_states, const double* d_prior_w, int32_t N,
+                                    const void* d_action, const float* d_obs, const voila_update_opts_t* h_opts,
+                                    float* d_states_out, int32_t* d_idx_out, double* d_w_out, float* d_loglik_out,
+                                    float* d_prop_out, double* d_stats_out, int32_t* d_status, void* stream);
+
 /* Largest N accepted by voila_update / voila_normalize / voila_resample
  * (beliefs above 8192 particles take a multi-workgroup path through HBM). */
 int32_t voila_update_max_particles(void);

@@ -126,6 +126,9 @@ def _load():
     L.voila_update.argtypes = [vp, vp, vp, c_int32, vp, vp, POINTER(_UpdateOpts), vp, c_size_t,
                                vp, vp, vp, vp, vp, vp, vp, vp]
     L.voila_update.restype = c_int32
+    L.voila_update_noalloc.argtypes = [vp, vp, vp, c_int32, vp, vp, POINTER(_UpdateOpts), vp, vp, vp, vp, vp, vp,
+                                       vp, vp]
+    L.voila_update_noalloc.restype = c_int32
     L.voila_update_max_particles.restype = c_int32
     L.voila_normalize.argtypes = [vp, vp, c_int32, c_double, vp, vp, vp, vp, c_size_t, vp]
     L.voila_normalize.restype = c_int32
@@ -205,7 +208,7 @@ lib = _load()
 # the exported C symbols (checked by the test-suite against include/voila.h)
 EXPORTED = ["voila_version", "voila_status_string", "voila_last_error", "voila_model_create",
             "voila_model_destroy", "voila_plan_workspace_size", "voila_plan", "voila_update_workspace_size",
-            "voila_update", "voila_update_max_particles", "voila_weights_workspace_size", "voila_normalize",
+            "voila_update", "voila_update_noalloc", "voila_update_max_particles", "voila_weights_workspace_size", "voila_normalize",
             "voila_reweight_resample",
             "voila_resample_bits",
             "voila_resample", "voila_observe_workspace_size", "voila_observe", "voila_plan_observe_workspace_size",
@@ -680,6 +683,37 @@ def update(model: Model, states, action, obs, lam=1.0, prior_w=None, seed=0, U=0
                             ctypes.byref(opts), _ptr(ws), ws.numel(), _ptr(res["states"]),
                             _ptr(res["idx"]), _ptr(res["w"]), _ptr(res["loglik"]), _ptr(res["prop"]),
                             _ptr(res["stats"]), _ptr(status), _stream(stream)))
+    return res
+
+
+def update_noalloc(model: Model, states, action, obs, lam=1.0, prior_w=None, seed=0, U=0, noise=None, out=None,
+                   status=None, stream=None):
+    """update() through voila_update_noalloc: the library takes the workspace
+    from its fixed device scratch (no workspace argument, nothing allocated by
+    the call).  `out` holds the output buffers (states, idx, w, loglik, prop,
+    stats); entries left out are allocated here, by the caller's side."""
+    d = model.desc
+    N = int(states.shape[0])
+    _dev(states, torch.float32, (N, d.d_s), "states")
+    if prior_w is not None:
+        _dev(prior_w, torch.float64, (N,), "prior_w")
+    if noise is not None:
+        _dev(noise, torch.float32, (N, d.d_w), "noise")
+    dev = states.device
+    a_dev = _action_dev(model, action, dev)
+    o_dev = _obs_dev(model, obs, dev)
+    if stream is not None:
+        a_dev.record_stream(stream)
+        o_dev.record_stream(stream)
+    o = out if out is not None else {}
+    res = {k: o[k] if k in o else None for k in ["states", "idx", "w", "loglik", "prop", "stats"]}
+    if res["states"] is None:
+        res["states"] = torch.empty((N, d.d_s), dtype=torch.float32, device=dev)
+    opts = _UpdateOpts(float(lam), int(seed) & (2**64 - 1), int(U) & 0xFFFFFFFF, _ptr(noise))
+    _check(lib.voila_update_noalloc(model.handle, _ptr(states), _ptr(prior_w), N, _ptr(a_dev), _ptr(o_dev),
+                                    ctypes.byref(opts), _ptr(res["states"]), _ptr(res["idx"]), _ptr(res["w"]),
+                                    _ptr(res["loglik"]), _ptr(res["prop"]), _ptr(res["stats"]), _ptr(status),
+                                    _stream(stream)))
     return res
 
 

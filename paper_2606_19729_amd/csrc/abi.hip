@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -742,6 +743,59 @@ voila_status_t voila_update(voila_model_t m, const float* d_states, const double
     r.status = d_status;
     VOILA_CHECK_HIP(launch_norm_res(r, s));
     return VOILA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// update without allocation: the workspace is a fixed device array
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kUpdateScratchBytes = VOILA_UPDATE_NOALLOC_SCRATCH_BYTES;
+// The workspace of voila_update_noalloc, one copy per device (loaded with the
+// library's code object).  In host code this name only identifies the array
+// for hipGetSymbolAddress; it is never a device address.
+__device__ __align__(256) char scratch[kUpdateScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (the caller has made `device` current).
+voila_status_t scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxScratchDevices) return fail(VOILA_ERR_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(VOILA_ERR_DEVICE, std::string("hipGetSymbolAddress of the update scratch: ") +
+                                              hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return VOILA_OK;
+}
+}  // namespace
+
+voila_status_t voila_update_noalloc(voila_model_t m, const float* d_states, const double* d_prior_w, int32_t N,
+                                    const void* d_action, const float* d_obs, const voila_update_opts_t* o,
+                                    float* d_states_out, int32_t* d_idx_out, double* d_w_out, float* d_loglik_out,
+                                    float* d_prop_out, double* d_stats_out, int32_t* d_status, void* stream) {
+    if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
+    if (N < 1) return fail(VOILA_ERR_INVALID_ARG, "N must be >= 1");
+    const size_t need = voila_update_workspace_size(m, N);
+    if (need > kUpdateScratchBytes)
+        return fail(VOILA_ERR_UNSUPPORTED, "N = " + std::to_string(N) + " needs " + std::to_string(need) +
+                                               " bytes of workspace; the fixed scratch of voila_update_noalloc "
+                                               "holds " + std::to_string(kUpdateScratchBytes));
+    DeviceGuard guard(m->device);
+    if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
+    void* ws = nullptr;
+    const voila_status_t st = scratch_address(m->device, &ws);
+    if (st != VOILA_OK) return st;
+    // every part of the workspace is written before it is read within the
+    // call, so nothing needs clearing between calls
+    return voila_update(m, d_states, d_prior_w, N, d_action, d_obs, o, ws, kUpdateScratchBytes, d_states_out,
+                        d_idx_out, d_w_out, d_loglik_out, d_prop_out, d_stats_out, d_status, stream);
 }
 
 voila_status_t voila_normalize(const float* d_loglik, const double* d_prior_w, int32_t N, double lambda,
