@@ -71,7 +71,7 @@ def lib():
                                     dp, dp]
         L.or_info_nce_rows.argtypes = [c_int, c_int, i32p, dp, dp, dp]
         L.or_info_nce.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, i32p, c_int, dp, dp, dp, dp]
-        L.or_info_nce_param_grad.argtypes = [mp, c_int, dp, i32p, dp, dp, dp, dp]
+        L.or_info_nce_param_grad.argtypes = [mp, c_int, dp, i32p, dp, dp, c_int, dp, dp]
         L.or_cosine_abar.argtypes = [c_double]
         L.or_cosine_abar.restype = c_double
         L.or_ddim_sample.argtypes = [c_int, ip, dp, c_int, c_int, c_int, c_int, c_int, dp, c_int, dp, dp, c_int, c_int,
@@ -409,9 +409,11 @@ def info_nce(model, states, actions, obs, rows=None, bf16=False):
     return out
 
 
-def info_nce_param_grad(model, states, actions, obs):
+def info_nce_param_grad(model, states, actions, obs, bf16=False):
     """(loss, gradient) of the InfoNCE loss with respect to the likelihood
-    network's parameters, packed per layer as W (row-major [out, in]) then b."""
+    network's parameters, packed per layer as W (row-major [out, in]) then b.
+    bf16=True: the bfloat16 emulation (weights, layer inputs and hidden
+    adjoints rounded to bfloat16, binary64 accumulation)."""
     S = _d(states)
     B = S.shape[0]
     O = _d(np.asarray(obs).reshape(B, model.d_o))
@@ -423,8 +425,8 @@ def info_nce_param_grad(model, states, actions, obs):
     g = np.zeros(int(lib().or_mlp_param_count(len(model.lik), dims.ctypes.data_as(POINTER(c_int)))))
     loss = np.zeros(1)
     b = _Bound(model)
-    _check(lib().or_info_nce_param_grad(b.ref(), B, _p(S), _p(a_disc, c_int32), _p(a_cont), _p(O), _p(g),
-                                        _p(loss)), "info_nce_param_grad")
+    _check(lib().or_info_nce_param_grad(b.ref(), B, _p(S), _p(a_disc, c_int32), _p(a_cont), _p(O), int(bf16),
+                                        _p(g), _p(loss)), "info_nce_param_grad")
     return float(loss[0]), g
 
 

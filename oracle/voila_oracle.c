@@ -1348,20 +1348,27 @@ int or_ddim_point_mass(int d, const double* x0, const double* x1, int n_steps, d
  * parameter vector): sum over all pairs of G_ij times the derivative of
  * l([s'_i, a_i, o_j]), by reverse mode through the network (ReLU'(0) = 0),
  * accumulated over each row's pairs in order, then over rows in order.
- * Also returns the loss. */
-int or_info_nce_param_grad(const or_model* m, int B, const double* S, const int32_t* a_disc, const double* a_cont,
-                           const double* O, double* grad, double* loss)
+ * Also returns the loss.  bf16 != 0 is the bfloat16 emulation of C.9
+ * extended to the reverse sweep: weights and every layer's input rounded to
+ * bfloat16 (the scores and G from the emulated forward pass), and the
+ * derivative with respect to each hidden layer's pre-activation rounded to
+ * bfloat16 before it enters a product or a sum (the output adjoint G stays
+ * unrounded); biases unrounded, accumulation in binary64. */
+int or_info_nce_param_grad(const or_model* m0, int B, const double* S, const int32_t* a_disc, const double* a_cont,
+                           const double* O, int bf16, double* grad, double* loss)
 {
-    if (B < 1 || mlp_check(m->l_layers, m->l_dims) != OR_OK || m->l_layers > OR_MAX_LAYERS) return OR_ERR_ARG;
-    const int L = m->l_layers, d_s = m->d_s, d_o = m->d_o, aw = action_width(m);
-    const int* dims = m->l_dims;
+    if (B < 1 || mlp_check(m0->l_layers, m0->l_dims) != OR_OK || m0->l_layers > OR_MAX_LAYERS) return OR_ERR_ARG;
+    const int L = m0->l_layers, d_s = m0->d_s, d_o = m0->d_o, aw = action_width(m0);
+    const int* dims = m0->l_dims;
     if (dims[0] != d_s + aw + d_o || dims[L] != 1) return OR_ERR_ARG;
     const size_t np = mlp_param_count(L, dims);
     double* Lg = (double*)malloc(sizeof(double) * (size_t)B * B);
     double* G = (double*)malloc(sizeof(double) * (size_t)B * B);
     double* rl = (double*)malloc(sizeof(double) * (size_t)B);
     if (!Lg || !G || !rl) { free(Lg); free(G); free(rl); return OR_ERR_ARG; }
-    int rc = or_info_nce(m, B, S, a_disc, a_cont, O, B, NULL, 0, Lg, rl, G, loss);
+    int rc = or_info_nce(m0, B, S, a_disc, a_cont, O, B, NULL, bf16, Lg, rl, G, loss);
+    rounded_model rm;
+    const or_model* m = rounded(m0, bf16, &rm);
     /* one partial gradient per row, summed in row order afterwards (the
      * result does not depend on the number of threads) */
     double* part = rc == OR_OK ? (double*)calloc((size_t)B * np, sizeof(double)) : NULL;
@@ -1376,6 +1383,8 @@ int or_info_nce_param_grad(const or_model* m, int B, const double* S, const int3
             for (int c = 0; c < d_s; ++c) x[c] = S[(size_t)i * d_s + c];
             put_action(m, x + d_s, a_disc ? a_disc[i] : 0, a_cont ? a_cont + (size_t)i * m->d_a : NULL);
             for (int c = 0; c < d_o; ++c) x[d_s + aw + c] = O[(size_t)j * d_o + c];
+            if (bf16)
+                for (int c = 0; c < dims[0]; ++c) x[c] = or_round_bf16(x[c]);
             const double* p = m->l_params;
             for (int l = 0; l < L; ++l) {
                 const int n_in = dims[l], n_out = dims[l + 1];
@@ -1384,6 +1393,7 @@ int or_info_nce_param_grad(const or_model* m, int B, const double* S, const int3
                     for (int k = 0; k < n_in; ++k) acc += p[(size_t)n * n_in + k] * act[l][k];
                     acc += p[(size_t)n_out * n_in + n];
                     act[l + 1][n] = (l < L - 1 && acc < 0.0) ? 0.0 : acc;
+                    if (bf16 && l < L - 1) act[l + 1][n] = or_round_bf16(act[l + 1][n]);
                 }
                 p += (size_t)n_out * n_in + n_out;
             }
@@ -1405,11 +1415,12 @@ int or_info_nce_param_grad(const or_model* m, int B, const double* S, const int3
                         for (int n = 0; n < n_out; ++n) acc += W[(size_t)n * n_in + k] * delta[n];
                         prev[k] = act[l][k] > 0.0 ? acc : 0.0;
                     }
-                    for (int k = 0; k < n_in; ++k) delta[k] = prev[k];
+                    for (int k = 0; k < n_in; ++k) delta[k] = bf16 ? or_round_bf16(prev[k]) : prev[k];
                 }
             }
         }
     }
+    release_rounded(&rm);
     for (size_t q = 0; q < np; ++q) grad[q] = 0.0;
     if (part)
         for (int i = 0; i < B; ++i)

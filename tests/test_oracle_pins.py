@@ -975,3 +975,75 @@ def test_info_nce_param_grad_matches_finite_differences(which):
         assert g[q] == pytest.approx((fp - fm) / (2 * h), abs=1e-7, rel=1e-5), q
         checked += 1
     assert checked >= 30
+
+
+def _deep_lik_model(seed, width=10, n_hidden=3):
+    """The small workload's model with a likelihood network of n_hidden ReLU
+    layers (the depth of the realistic likelihood network, narrower)."""
+    w = workloads.small(seed=seed, N=16)
+    rng = np.random.default_rng(seed)
+    m = w.model
+    lik = workloads.random_mlp(rng, [m.d_s + m.n_actions + m.d_o] + [width] * n_hidden + [1])
+    return w, Model(**{**m.__dict__, "lik": lik})
+
+
+def test_info_nce_param_grad_three_hidden_layers_matches_finite_differences():
+    # the reverse sweep through every hidden->hidden layer, as in the
+    # realistic (three hidden layer) likelihood network
+    w, m = _deep_lik_model(95)
+    S, A, O = workloads.nce_batch(w, 7, seed=5)
+    _, g = oracle.info_nce_param_grad(m, S, A, O)
+    theta = _flat_lik(m)
+    h, checked = 1e-6, 0
+    for q in range(theta.size - 1):
+        tp, tm = theta.copy(), theta.copy()
+        tp[q] += h
+        tm[q] -= h
+        fp = oracle.info_nce(_with_flat_lik(m, tp), S, A, O)["loss"]
+        fm = oracle.info_nce(_with_flat_lik(m, tm), S, A, O)["loss"]
+        f2 = oracle.info_nce(_with_flat_lik(m, theta), S, A, O)["loss"]
+        if abs((fp - f2) / h - (f2 - fm) / h) > 1e-4 * max(1.0, abs(g[q])):
+            continue
+        assert g[q] == pytest.approx((fp - fm) / (2 * h), abs=1e-7, rel=1e-5), q
+        checked += 1
+    assert checked >= 0.9 * (theta.size - 1)
+
+
+def _bf16_values(x):
+    """x rounded to bfloat16 (nearest, ties to even) by bit manipulation of its
+    binary32 value, returned as float32."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def test_info_nce_param_grad_bf16_emulation_within_rounding_of_exact():
+    # the emulation rounds weights, layer inputs and hidden adjoints to
+    # bfloat16 (8 significant bits).  Against the exact gradient of the
+    # network whose weights are already bfloat16 values (so only the rounding
+    # of activations and adjoints differs) it stays within a few units of
+    # 2^-8 of the gradient's scale, and differs from it (the rounding takes
+    # effect); the rounded weights alone change the function, so that is the
+    # reference
+    w, m = _deep_lik_model(96, width=24)
+    m_r = Model(**{**m.__dict__, "lik": [(_bf16_values(W), b) for W, b in m.lik]})
+    S, A, O = workloads.nce_batch(w, 12, seed=6)
+    _, g = oracle.info_nce_param_grad(m_r, S, A, O)
+    loss_b, gb = oracle.info_nce_param_grad(m, S, A, O, bf16=True)
+    assert loss_b == pytest.approx(oracle.info_nce(m, S, A, O, bf16=True)["loss"], rel=1e-14)
+    scale = np.max(np.abs(g))
+    err = np.max(np.abs(gb - g)) / scale
+    assert 1e-5 < err < 16 * 2.0 ** -8
+    # per layer, the emulated gradient points the same way as the exact one
+    off = 0
+    for W, b in m.lik:
+        n = W.size + b.size
+        a, e = gb[off:off + n], g[off:off + n]
+        assert np.dot(a, e) / (np.linalg.norm(a) * np.linalg.norm(e)) > 0.99
+        off += n
+    # with weights and inputs already bfloat16 values, rounding the inputs
+    # changes nothing: only activations and adjoints are rounded
+    S_r, O_r = _bf16_values(S), _bf16_values(O)
+    _, g1 = oracle.info_nce_param_grad(m_r, S_r, A, O_r, bf16=True)
+    _, g2 = oracle.info_nce_param_grad(m, S_r, A, O_r, bf16=True)
+    assert np.array_equal(g1, g2)
