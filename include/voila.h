@@ -320,11 +320,21 @@ voila_status_t voila_info_nce(voila_model_t model, const float* d_states, const 
  * then b); the loss goes to d_loss_out [1] double (or NULL).  Compiled for
  * binary32 likelihood networks with two hidden layers of width 64 over the
  * small shapes (d_s = 4, d_o = 2, five discrete or four continuous action
- * inputs); voila_info_nce_param_count returns 0 and voila_info_nce_grad
- * VOILA_ERR_UNSUPPORTED for other models.  Per-wave partial sums are
- * reduced in a fixed order (repeatable).  Status and out-of-range actions as
- * for voila_info_nce (action 0 is used in both passes).  Workspace:
- * voila_info_nce_grad_workspace_size.
+ * inputs), and for the realistic likelihood network (three hidden layers of
+ * width 256 over d_s = 16, d_a = 4, d_o = 32) in binary32 or bfloat16; for
+ * other models voila_info_nce_param_count returns 0 and voila_info_nce_grad
+ * VOILA_ERR_UNSUPPORTED.  The width-256 form works through chunks of up to
+ * 2^19 (binary32) or 2^20 (bfloat16) pairs: each pair's hidden activations
+ * and adjoints are stored in the workspace, then the weight derivatives are
+ * formed as products over the chunk's pairs (bfloat16 operands: activations
+ * and adjoints rounded to bfloat16, binary32 accumulation).  Partial sums
+ * are reduced in a fixed order (repeatable).  Status and out-of-range
+ * actions as for voila_info_nce (action 0 is used in both passes).
+ * Workspace: voila_info_nce_grad_workspace_size (about 2.8 GB for the
+ * width-256 network once B^2 reaches the chunk size); for the width-256
+ * network a smaller workspace is accepted down to one unit of 32 pairs per
+ * chunk (the pairs are then processed in more chunks; the partial sums are
+ * grouped differently, so results agree to rounding).
  */
 int32_t voila_info_nce_param_count(voila_model_t model);
 size_t voila_info_nce_grad_workspace_size(voila_model_t model, int32_t B);

@@ -501,9 +501,9 @@ def info_nce(model: Model, states, actions, obs, want_scores=True, want_grad=Tru
 
 def info_nce_grad(model: Model, states, actions, obs, out=None, workspace=None, status=None, stream=None):
     """Derivative of the contrastive objective with respect to the likelihood
-    network's parameters (binary32 width-64 two-hidden-layer networks of the
-    small shapes).  Returns dict(loss [1] float64, grad [n_params] float32,
-    per layer W [out, in] row-major then b)."""
+    network's parameters (binary32 width-64 networks of the small shapes, and
+    the width-256 network in binary32 or bfloat16).  Returns dict(loss [1]
+    float64, grad [n_params] float32, per layer W [out, in] row-major then b)."""
     d = model.desc
     B = int(states.shape[0])
     _dev(states, torch.float32, (B, d.d_s), "states")

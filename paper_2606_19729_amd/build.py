@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvoila.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["k_plan.hip", "k_observe.hip", "k_search.hip", "k_nce.hip", "k_ddim.hip", "k_update.hip", "grad.hip",
+SOURCES = ["k_plan.hip", "k_observe.hip", "k_search.hip", "k_nce.hip", "k_nce_grad.hip", "k_ddim.hip", "k_update.hip", "grad.hip",
            "resample_large.hip", "abi.hip"]
 ARCH = os.environ.get("VOILA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",

@@ -169,6 +169,57 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
     return blob;
 }
 
+// The likelihood network for the contrastive objective's parameter
+// derivative, as one fragment stream in the order the backward kernel
+// consumes it: the first layer over the observation inputs (the state and
+// action are folded into per-row biases), the hidden->hidden layers, then the
+// transposed hidden->hidden layers from the last to the first (the products
+// W_l^T delta_l of the reverse sweep), padded to whole stream chunks.
+std::vector<char> pack_nce_wide(const HostNet& n, int dt, int in_slots_per_group, const SlotMap& map) {
+    const int W = n.width(), HT = W / 32, NHID = n.n_layers - 1, KP = kper(dt);
+    const int esz = dt == DT_F32 ? 4 : 2;
+    const size_t fb = (size_t)64 * KP * esz;
+    const int IN_KS = in_slots_per_group / KP, HID_KS = 16 * HT / KP;
+    const size_t nf0 = (size_t)IN_KS * HT, nfh = (size_t)HID_KS * HT;
+    const size_t nfr = nf0 + 2 * (size_t)(NHID - 1) * nfh;
+    const size_t fpc = VOILA_STREAM_CHB / fb;
+    std::vector<char> blob((nfr + fpc - 1) / fpc * fpc * fb, 0);
+    auto put = [&](size_t frag, int lane, int j, float v) {
+        char* p = blob.data() + ((frag * 64 + lane) * KP + j) * esz;
+        if (dt == DT_F32) {
+            std::memcpy(p, &v, 4);
+        } else {
+            uint16_t h = bf16_bits(v);
+            std::memcpy(p, &h, 2);
+        }
+    };
+    auto hidden_in = [](int ri, int g) { return 32 * (ri / 16) + out_row(ri % 16, g); };
+    for (int c = 0; c < IN_KS; ++c)
+        for (int t = 0; t < HT; ++t)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < KP; ++j) {
+                    int col = map(c * KP + j, lane / 32);
+                    put((size_t)c * HT + t, lane, j, col >= 0 ? n.w(0, 32 * t + lane % 32, col) : 0.0f);
+                }
+    for (int l = 1; l <= NHID - 1; ++l)
+        for (int c = 0; c < HID_KS; ++c)
+            for (int t = 0; t < HT; ++t)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < KP; ++j)
+                        put(nf0 + (size_t)(l - 1) * nfh + (size_t)c * HT + t, lane, j,
+                            n.w(l, 32 * t + lane % 32, hidden_in(c * KP + j, lane / 32)));
+    for (int k = 0; k < NHID - 1; ++k) {
+        const int l = NHID - 1 - k;  // W_{l+1}^T maps the adjoint of h_{l+1} to h_l
+        for (int c = 0; c < HID_KS; ++c)
+            for (int t = 0; t < HT; ++t)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < KP; ++j)
+                        put(nf0 + (size_t)(NHID - 1 + k) * nfh + (size_t)c * HT + t, lane, j,
+                            n.w(l, hidden_in(c * KP + j, lane / 32), 32 * t + lane % 32));
+    }
+    return blob;
+}
+
 // First-layer columns [c0, c0 + nf) of a network (rounded to bfloat16 for
 // bfloat16 models), row-major [width][nf], for folding fixed inputs into the bias.
 std::vector<float> fold_columns(const HostNet& n, int c0, int nf, int dt) {
@@ -253,6 +304,12 @@ struct voila_model_s {
     NetBlob lik_bwd{};               // transposed likelihood pack
     const float* lik_w3 = nullptr;   // [width] output-layer weights of the likelihood network
     int nce_grad_bpc = 1, n_lik_params = 0;
+    // the same derivative for likelihood networks evaluated layer by layer
+    bool has_nce_wide = false;
+    const char* nce_wide_stream = nullptr;  // first layer, hidden layers, transposed hidden layers
+    const float* nce_wide_bh = nullptr;     // [n_hidden - 1][width]
+    const float* nce_wide_wout = nullptr;   // [width] (bfloat16 values for bfloat16 models)
+    int nce_wide_bpc = 1, nce_wgrad_bpc = 1;
     int action_width() const { return n_actions > 0 ? n_actions : d_a; }
 };
 
@@ -426,6 +483,16 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     } else {
         blobs.emplace_back();
     }
+    // the layered form of the same derivative (hidden width 256)
+    m->has_nce_wide = L.present() && nce_wide_supported(shape);
+    if (m->has_nce_wide) {
+        SlotMap mo{m->d_o, 0, 0, 0, 0, m->d_s + aw};
+        blobs.push_back(pack_nce_wide(L, dt, nce_in_slots(shape, dt), mo));
+        if (m->n_lik_params == 0)
+            for (int l = 0; l < L.n_layers; ++l) m->n_lik_params += L.dims[l + 1] * L.dims[l] + L.dims[l + 1];
+    } else {
+        blobs.emplace_back();
+    }
     const size_t nb = blobs.size();
     std::vector<std::vector<float>> folds;
     m->nf_trans = aw;
@@ -454,6 +521,18 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     } else {
         folds.emplace_back();
         folds.emplace_back();
+        folds.emplace_back();
+        folds.emplace_back();
+    }
+    if (m->has_nce_wide) {
+        std::vector<float> bh;
+        for (int l = 1; l < L.n_layers - 1; ++l) bh.insert(bh.end(), L.b[l], L.b[l] + W);
+        folds.push_back(bh);
+        std::vector<float> wo(L.W[L.n_layers - 1], L.W[L.n_layers - 1] + W);
+        if (dt == DT_BF16)
+            for (float& v : wo) v = bf16_round(v);
+        folds.push_back(wo);
+    } else {
         folds.emplace_back();
         folds.emplace_back();
     }
@@ -497,6 +576,11 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->fold_b_lik = reinterpret_cast<const float*>(m->mem + offs[nb + 5]);
     m->fold_w_nce = reinterpret_cast<const float*>(m->mem + offs[nb + 6]);
     m->lik_w3 = reinterpret_cast<const float*>(m->mem + offs[nb + 7]);
+    if (m->has_nce_wide) {
+        m->nce_wide_stream = m->mem + offs[8];
+        m->nce_wide_bh = reinterpret_cast<const float*>(m->mem + offs[nb + 8]);
+        m->nce_wide_wout = reinterpret_cast<const float*>(m->mem + offs[nb + 9]);
+    }
 
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->cus = prop.multiProcessorCount;
@@ -507,6 +591,10 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->pw_bpc = pw_lik_blocks_per_cu(shape, dt);
     m->nce_bpc = nce_scores_blocks_per_cu(shape, dt);
     if (m->has_nce_grad) m->nce_grad_bpc = nce_grad_blocks_per_cu(shape, nce_grad_lds_bytes(m));
+    if (m->has_nce_wide) {
+        m->nce_wide_bpc = nce_wide_bwd_blocks_per_cu(dt);
+        m->nce_wgrad_bpc = nce_wide_wgrad_blocks_per_cu(dt);
+    }
     if (m->has_grad) m->grad_bpc = grad_blocks_per_cu(shape, grad_lds_bytes(m));
     *out = m;
     return VOILA_OK;
@@ -1340,7 +1428,9 @@ voila_status_t voila_ddim_sample(voila_denoiser_t m, const float* d_states, cons
     return VOILA_OK;
 }
 
-int32_t voila_info_nce_param_count(voila_model_t m) { return m && m->has_nce_grad ? m->n_lik_params : 0; }
+int32_t voila_info_nce_param_count(voila_model_t m) {
+    return m && (m->has_nce_grad || m->has_nce_wide) ? m->n_lik_params : 0;
+}
 
 namespace {
 struct NceGradWs {
@@ -1349,9 +1439,20 @@ struct NceGradWs {
     float* G;
     float* wpart;
     int blocks;
+    // layered networks: activation arrays of one chunk of units, per-workgroup partials
+    void* act;
+    long uc;
     size_t bytes;
 };
-NceGradWs carve_nce_grad(char* base, voila_model_t m, int B) {
+// Units (32 pairs each) held by one chunk of the layered derivative's arrays
+// at most, and the array bytes per unit.
+long nce_wide_unit_cap(const voila_model_s* m) { return m->dt == DT_F32 ? (1L << 14) : (1L << 15); }
+size_t nce_wide_unit_bytes(const voila_model_s* m) {
+    return (2 * (size_t)m->n_hidden - 1) * m->width * 32 * (m->dt == DT_F32 ? 4 : 2);
+}
+// uc = 0: as many units per chunk as the workspace of ws_bytes holds (the
+// default workspace holds min(all units, the cap)).
+NceGradWs carve_nce_grad(char* base, voila_model_t m, int B, size_t ws_bytes = 0) {
     NceGradWs w{};
     w.nce = base;
     w.nce_bytes = voila_info_nce_workspace_size(m, B);
@@ -1359,18 +1460,32 @@ NceGradWs carve_nce_grad(char* base, voila_model_t m, int B) {
     w.G = reinterpret_cast<float*>(base + off);
     off = align_up(off + (size_t)B * B * 4, 256);
     const long units = (long)B * ((B + 31) / 32);
-    const long want = (units + kGradWaves - 1) / kGradWaves;
-    const long cap = (long)m->cus * m->nce_grad_bpc;
-    w.blocks = (int)(want < cap ? want : cap);
+    if (m->has_nce_wide) {
+        w.blocks = m->cus * m->nce_wgrad_bpc;
+    } else {
+        const long want = (units + kGradWaves - 1) / kGradWaves;
+        const long cap = (long)m->cus * m->nce_grad_bpc;
+        w.blocks = (int)(want < cap ? want : cap) * kGradWaves;
+    }
     w.wpart = reinterpret_cast<float*>(base + off);
-    off = align_up(off + (size_t)w.blocks * kGradWaves * m->n_lik_params * 4, 256);
+    off = align_up(off + (size_t)w.blocks * m->n_lik_params * 4, 256);
+    if (m->has_nce_wide) {
+        long uc = units < nce_wide_unit_cap(m) ? units : nce_wide_unit_cap(m);
+        if (ws_bytes > off) {
+            const long fit = (long)((ws_bytes - off) / nce_wide_unit_bytes(m));
+            uc = fit < uc ? fit : uc;
+        }
+        w.uc = uc < 1 ? 1 : uc;
+        w.act = base + off;
+        off = align_up(off + (size_t)w.uc * nce_wide_unit_bytes(m), 256);
+    }
     w.bytes = off;
     return w;
 }
 }  // namespace
 
 size_t voila_info_nce_grad_workspace_size(voila_model_t m, int32_t B) {
-    if (!m || !m->has_nce_grad || B < 1 || B > kNceMaxBatch) return 0;
+    if (!m || !(m->has_nce_grad || m->has_nce_wide) || B < 1 || B > kNceMaxBatch) return 0;
     return carve_nce_grad(nullptr, m, B).bytes;
 }
 
@@ -1378,13 +1493,14 @@ voila_status_t voila_info_nce_grad(voila_model_t m, const float* d_states, const
                                    int32_t B, void* ws, size_t ws_bytes, double* d_loss_out, float* d_param_grad_out,
                                    int32_t* d_status, void* stream) {
     if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
-    if (!m->has_nce_grad)
+    if (!m->has_nce_grad && !m->has_nce_wide)
         return fail(VOILA_ERR_UNSUPPORTED,
-                    "the parameter derivative is compiled for binary32 width-64 likelihood networks of the small shapes");
+                    "the parameter derivative is compiled for binary32 width-64 likelihood networks of the small "
+                    "shapes and for the width-256 likelihood network");
     if (B < 1) return fail(VOILA_ERR_INVALID_ARG, "B must be >= 1");
     if (B > kNceMaxBatch) return fail(VOILA_ERR_UNSUPPORTED, "B must be <= 32768");
     if (!d_states || !d_actions || !d_obs || !d_param_grad_out) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
-    NceGradWs w = carve_nce_grad(reinterpret_cast<char*>(ws), m, B);
+    NceGradWs w = carve_nce_grad(reinterpret_cast<char*>(ws), m, B, ws_bytes);
     if (!ws || ws_bytes < w.bytes) return fail(VOILA_ERR_WORKSPACE, "contrastive-gradient workspace too small");
     voila_status_t st = voila_info_nce(m, d_states, d_actions, d_obs, B, w.nce, w.nce_bytes, nullptr, nullptr, w.G,
                                        d_loss_out, d_status, stream);
@@ -1393,6 +1509,59 @@ voila_status_t voila_info_nce_grad(voila_model_t m, const float* d_states, const
     if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     NceWs nw = carve_nce(reinterpret_cast<char*>(w.nce), m, B);
+    if (m->has_nce_wide) {
+        // chunks of units: forward and reverse sweep of every pair, then the
+        // split-K products into per-workgroup partial sums
+        const long units = (long)B * ((B + 31) / 32);
+        const int upc = m->dt == DT_F32 ? 1 : 2;  // units per staged chunk of the product kernel
+        for (long u0 = 0; u0 < units; u0 += w.uc) {
+            const long u1 = u0 + w.uc < units ? u0 + w.uc : units;
+            NceWideParams a{};
+            a.stream = m->nce_wide_stream;
+            a.bh = m->nce_wide_bh;
+            a.w_out = m->nce_wide_wout;
+            a.b0 = nw.b0;
+            a.obs = d_obs;
+            a.grad = w.G;
+            a.act = w.act;
+            a.uc = w.uc;
+            a.u0 = u0;
+            a.u1 = u1;
+            a.B = B;
+            const long want = (u1 - u0 + 3) / 4;
+            const long cap = (long)m->cus * m->nce_wide_bpc;
+            VOILA_CHECK_HIP(launch_nce_wide_bwd(m->shape, m->dt, a, (int)(want < cap ? want : cap), s));
+            NceWgradParams b{};
+            b.act = w.act;
+            b.uc = w.uc;
+            b.u0 = u0;
+            b.n_units = u1 - u0;
+            const long per = (b.n_units + w.blocks - 1) / w.blocks;
+            b.per_split = (per + upc - 1) / upc * upc;
+            b.grad = w.G;
+            b.w_out = m->nce_wide_wout;
+            b.states = d_states;
+            b.actions = d_actions;
+            b.obs = d_obs;
+            b.B = B;
+            b.n_actions = m->n_actions;
+            b.d_a = m->d_a;
+            b.d_s = m->d_s;
+            b.d_o = m->d_o;
+            b.d_in = m->d_s + m->action_width() + m->d_o;
+            b.part = w.wpart;
+            b.n_params = m->n_lik_params;
+            b.accumulate = u0 > 0 ? 1 : 0;
+            VOILA_CHECK_HIP(launch_nce_wide_wgrad(m->shape, m->dt, b, w.blocks, s));
+        }
+        GradReduceParams r{};
+        r.wpart = w.wpart;
+        r.grad_params = d_param_grad_out;
+        r.n_params = m->n_lik_params;
+        r.n_waves = w.blocks;
+        VOILA_CHECK_HIP(launch_grad_reduce(r, s));
+        return VOILA_OK;
+    }
     NceGradParams p{};
     p.fwd = m->lik_nce;
     p.bwd = m->lik_bwd;
@@ -1406,12 +1575,12 @@ voila_status_t voila_info_nce_grad(voila_model_t m, const float* d_states, const
     p.status = d_status;
     p.B = B;
     p.n_params = m->n_lik_params;
-    VOILA_CHECK_HIP(launch_nce_grad(m->shape, p, w.blocks, nce_grad_lds_bytes(m), s));
+    VOILA_CHECK_HIP(launch_nce_grad(m->shape, p, w.blocks / kGradWaves, nce_grad_lds_bytes(m), s));
     GradReduceParams r{};
     r.wpart = w.wpart;
     r.grad_params = d_param_grad_out;
     r.n_params = m->n_lik_params;
-    r.n_waves = w.blocks * kGradWaves;
+    r.n_waves = w.blocks;
     VOILA_CHECK_HIP(launch_grad_reduce(r, s));
     return VOILA_OK;
 }

@@ -407,6 +407,44 @@ int observe_blocks_per_cu(int shape, int dt);
 // Whether a shape's kernels stage the packed network in LDS.
 bool weights_in_lds(int shape);
 
+// Derivative of the contrastive objective for likelihood networks evaluated
+// layer by layer: stage 1 (forward and reverse sweep of every pair of a
+// chunk, activations and adjoints stored) and stage 2 (split-K products).
+struct NceWideParams {
+    const char* stream;    // fragments: first layer (observation inputs), hidden layers, transposed hidden layers
+    const float* bh;       // [NHID - 1][width] hidden biases
+    const float* w_out;    // [width] output-layer weights (bfloat16 values for bfloat16 models)
+    const float* b0;       // [B][width] first-layer bias rows with s'_i and a_i folded in
+    const float* obs;      // [B][d_o]
+    const float* grad;     // [B][B] d loss / d l_ij
+    void* act;             // [2 NHID - 1][uc][width][32]: h_1..h_NHID, then delta_1..delta_{NHID-1}
+    long uc;               // unit capacity of the arrays
+    long u0, u1;           // units of the chunk (unit u: row u / jtiles, 32 columns from 32 (u % jtiles))
+    int B;
+    uint32_t lds_bias;     // LDS offset of the staged biases (set by the launcher)
+};
+struct NceWgradParams {
+    const void* act;       // the chunk's arrays (as NceWideParams::act)
+    long uc, u0;           // as NceWideParams
+    long n_units;          // units in the chunk
+    long per_split;        // units per workgroup (a multiple of the staged chunk)
+    const float* grad;     // [B][B]
+    const float* w_out;    // [width]
+    const float* states;   // [B][d_s]
+    const void* actions;   // int32 [B] or float [B][d_a]
+    const float* obs;      // [B][d_o]
+    int B, n_actions, d_a, d_s, d_o, d_in;
+    float* part;           // [workgroups][n_params] partial sums
+    int n_params;
+    int accumulate;        // 0: the first chunk writes the partials, 1: later chunks add
+};
+bool nce_wide_supported(int shape);
+size_t nce_wide_bwd_lds(int dt);
+hipError_t launch_nce_wide_bwd(int shape, int dt, const NceWideParams& p, int blocks, hipStream_t s);
+hipError_t launch_nce_wide_wgrad(int shape, int dt, const NceWgradParams& p, int blocks, hipStream_t s);
+int nce_wide_bwd_blocks_per_cu(int dt);
+int nce_wide_wgrad_blocks_per_cu(int dt);
+
 constexpr int kWavesPerBlock = 4;
 
 }  // namespace voila

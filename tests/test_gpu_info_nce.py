@@ -27,6 +27,11 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 BOUND_EMUL = 2.0 ** -6
+# bfloat16 parameter derivative of the width-256 network against the
+# oracle's bfloat16 emulation, relative to the gradient's scale: the largest
+# error over eight seeds (88..95, B = 96) was 1.54e-3; doubled and rounded up
+# to a power of two
+BF16_PARAM_GRAD_BOUND = 2.0 ** -8
 
 
 @pytest.fixture(scope="module")
@@ -207,10 +212,10 @@ def test_param_grad_single_pair_repeatable_and_unsupported(V):
     assert loss == 0.0 and np.all(g == 0.0)
     S, A, O = workloads.nce_batch(w, 300)
     assert np.array_equal(run_grad(V, m, S, A, O)[1], run_grad(V, m, S, A, O)[1])
-    r = workloads.realistic(seed=84, N=64, K=1, H=1)
+    r = workloads.wide(seed=84)
     S, A, O = workloads.nce_batch(r, 8)
     with pytest.raises(V.VoilaError):
-        V.info_nce_grad(V.Model(r.model), dev(S), dev(A), dev(O))
+        V.info_nce_grad(V.Model(r.model, compute="bf16"), dev(S), dev(A, torch.int32), dev(O))
 
 
 def test_param_grad_bench_size_properties(V):
@@ -246,3 +251,144 @@ def test_maximum_batch(V):
     S1, A1, O1 = workloads.nce_batch(w, B + 1, seed=20)
     with pytest.raises(V.VoilaError):
         V.info_nce(m, dev(S1), dev(A1, torch.int32), dev(O1), want_scores=False, want_grad=False)
+
+
+# ----------------------------------------------------------------------------- width-256 parameter derivative
+def run_grad_ws(V, m, S, A, O, ws_bytes=None):
+    Ad = dev(A, torch.int32 if A.dtype == np.int32 else torch.float32)
+    ws = None
+    if ws_bytes is not None:
+        ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device="cuda")
+    res = V.info_nce_grad(m, dev(S), Ad, dev(O), workspace=ws)
+    torch.cuda.synchronize()
+    return float(res["loss"].item()), host(res["grad"]).astype(np.float64)
+
+
+def kink_free(model, S, A, O, tau=3e-5):
+    """The model with each hidden unit's bias moved by the smallest amount
+    that keeps every pair's pre-activation at least tau from zero (layer by
+    layer, in binary64 on the binary32 weights).  A pre-activation closer to
+    zero than the binary32 rounding of its sum may take the other ReLU branch
+    on the device than in the binary64 reference, which moves the derivative
+    by a whole pair's contribution; with the margin both take the same branch
+    everywhere and the derivative is a smooth function of the inputs."""
+    B = S.shape[0]
+    if model.n_actions > 0:
+        a_in = np.eye(model.n_actions)[A]
+    else:
+        a_in = np.asarray(A, np.float64)
+    row = np.concatenate([np.asarray(S, np.float64), a_in], 1)
+    X = np.concatenate([np.repeat(row[:, None, :], B, 1), np.repeat(np.asarray(O, np.float64)[None], B, 0)], 2)
+    h = X.reshape(B * B, -1)
+    layers = []
+    for l, (W, b) in enumerate(model.lik):
+        W64, b_new = W.astype(np.float64), b.astype(np.float32).copy()
+        if l < len(model.lik) - 1:
+            z0 = h @ W64.T
+            for u in range(W.shape[0]):
+                z = np.sort(z0[:, u] + float(b[u]))
+                # the allowed shifts t: -t outside every [z_p - tau, z_p + tau]
+                lo, hi = z - tau, z + tau
+                cands = np.concatenate([[0.0], -lo, -hi])
+                best = None
+                for t in cands[np.argsort(np.abs(cands))]:
+                    k = np.searchsorted(z, -t)
+                    near = min(abs(z[k] + t) if k < len(z) else np.inf, abs(z[k - 1] + t) if k > 0 else np.inf)
+                    if near >= tau:
+                        best = t
+                        break
+                b_new[u] = np.float32(float(b[u]) + 1.001 * best)
+            z = z0 + b_new.astype(np.float64)
+            assert np.min(np.abs(z)) >= 0.9 * tau
+            h = np.maximum(z, 0.0)
+        layers.append((W, b_new))
+    return workloads.Model(**{**model.__dict__, "lik": layers})
+
+
+@pytest.mark.parametrize("B", [1, 37, 100, 200])
+def test_realistic_param_grad_f32_against_oracle(V, B):
+    # the realistic likelihood network (three hidden layers of 256) in
+    # binary32: max |g_dev - g_ref| <= 1e-5 max |g_ref| against the oracle's
+    # reverse mode in binary64, on a network whose hidden pre-activations stay
+    # 3e-5 away from the ReLU kink for every pair (kink_free)
+    w = workloads.realistic(seed=86, N=512, K=1, H=1)
+    S, A, O = workloads.nce_batch(w, B, seed=21)
+    w.model = kink_free(w.model, S, A, O)
+    m = V.Model(w.model)
+    print(f"info_nce grad realistic f32 B={B}", flush=True)
+    loss, g = run_grad_ws(V, m, S, A, O)
+    loss_ref, g_ref = oracle.info_nce_param_grad(w.model, S, A, O)
+    assert g.shape == g_ref.shape
+    if B == 1:
+        assert loss == 0.0 and np.all(g == 0.0)
+        return
+    err = float(np.max(np.abs(g - g_ref))) / float(np.max(np.abs(g_ref)))
+    print(f"  grad err {err:.2e} of scale {np.max(np.abs(g_ref)):.3e}; loss {loss:.6f} vs {loss_ref:.6f}", flush=True)
+    assert err <= TOL
+    assert abs(loss - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
+    assert abs(g[-1]) <= 1e-5 * float(np.max(np.abs(g_ref)))
+
+
+def test_realistic_param_grad_small_workspace_many_chunks(V):
+    # a workspace holding 7 units (224 pairs) per chunk: B = 100 (400 units)
+    # runs in 58 chunks, the partial sums accumulated across them; same
+    # bound against the oracle, and agreement with the one-chunk result to
+    # rounding
+    w = workloads.realistic(seed=87, N=512, K=1, H=1)
+    B = 100
+    S, A, O = workloads.nce_batch(w, B, seed=22)
+    w.model = kink_free(w.model, S, A, O)
+    m = V.Model(w.model)
+    full = int(V.lib.voila_info_nce_grad_workspace_size(m.handle, B))
+    unit = 5 * 256 * 32 * 4
+    small = full - (400 - 7) * unit
+    _, g1 = run_grad_ws(V, m, S, A, O)
+    loss, g = run_grad_ws(V, m, S, A, O, ws_bytes=small)
+    _, g_ref = oracle.info_nce_param_grad(w.model, S, A, O)
+    scale = float(np.max(np.abs(g_ref)))
+    err = float(np.max(np.abs(g - g_ref))) / scale
+    print(f"  58 chunks: grad err {err:.2e}; vs one chunk {np.max(np.abs(g - g1)) / scale:.2e}", flush=True)
+    assert err <= TOL
+    assert np.max(np.abs(g - g1)) <= 1e-6 * scale
+    with pytest.raises(V.VoilaError):
+        run_grad_ws(V, m, S, A, O, ws_bytes=full - 400 * unit)
+
+
+@pytest.mark.parametrize("seed", [88, 89, 94])
+def test_realistic_param_grad_bf16_against_emulation(V, seed):
+    # bfloat16 operands, binary32 accumulation: against the oracle's bfloat16
+    # emulation (weights, layer inputs and hidden adjoints rounded to
+    # bfloat16, binary64 accumulation) the error stays within the stated
+    # bound of the gradient's scale; against the binary64 gradient of the
+    # same (unrounded) network it is reported
+    w = workloads.realistic(seed=seed, N=512, K=1, H=1)
+    B = 96
+    S, A, O = workloads.nce_batch(w, B, seed=23)
+    m = V.Model(w.model, compute="bf16")
+    print(f"info_nce grad realistic bf16 B={B} seed={seed}", flush=True)
+    loss, g = run_grad_ws(V, m, S, A, O)
+    loss_em, g_em = oracle.info_nce_param_grad(w.model, S, A, O, bf16=True)
+    _, g_ref = oracle.info_nce_param_grad(w.model, S, A, O)
+    err_em = float(np.max(np.abs(g - g_em))) / float(np.max(np.abs(g_em)))
+    err_ref = float(np.max(np.abs(g - g_ref))) / float(np.max(np.abs(g_ref)))
+    print(f"  grad err vs emulation {err_em:.2e}, vs binary64 {err_ref:.2e}; loss {loss:.6f} vs {loss_em:.6f}",
+          flush=True)
+    assert err_em <= BF16_PARAM_GRAD_BOUND
+    assert abs(loss - loss_em) <= 2.0 ** -6 * max(1.0, abs(loss_em))
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_realistic_param_grad_bench_size_properties(V, compute):
+    # B = 4,096 (16.8 M pairs in 32 or 16 chunks, the measured size): finite,
+    # repeatable, the output-bias derivative vanishes (the scores' derivatives
+    # of every row sum to zero) and the loss equals the forward call's
+    w = workloads.realistic(seed=90, N=4096, K=1, H=1)
+    S, A, O = workloads.nce_batch(w, 4096, seed=24)
+    m = V.Model(w.model, compute=compute)
+    print(f"info_nce grad realistic {compute} B=4096", flush=True)
+    loss, g = run_grad_ws(V, m, S, A, O)
+    assert np.all(np.isfinite(g))
+    assert abs(g[-1]) <= 1e-4 * float(np.max(np.abs(g)))
+    d = run_dev(V, m, S, A, O)
+    assert loss == pytest.approx(float(d["loss"][0]), rel=1e-12)
+    assert np.array_equal(run_grad_ws(V, m, S, A, O)[1], g)
