@@ -393,6 +393,33 @@ def bench_info_nce(V, torch, reps):
     out["small_param_grad_f32"] = {"ms": t, "pairs_per_s": pairs / (t / 1e3),
                                    "n_params": int(res2["grad"].numel())}
     print(f"[bench]   small-network parameter derivative f32: {t:.3f} ms", file=sys.stderr, flush=True)
+    # the derivative for the realistic likelihood network: per pair the
+    # forward pass over the observation inputs, the two transposed hidden
+    # products of the reverse sweep and the weight-derivative products
+    Wd = int(m0.lik[0][0].shape[0])
+    d_in = m0.d_s + m0.action_width + m0.d_o
+    f_grad = f_pair + 2 * 2 * Wd * Wd + 2 * (2 * Wd * Wd + Wd * d_in)
+    out["realistic_param_grad"] = {"flop_per_pair": f_grad}
+    for compute in ["f32", "bf16"]:
+        m = V.Model(m0, compute=compute)
+        wsg = torch.empty(int(V.lib.voila_info_nce_grad_workspace_size(m.handle, B)), dtype=torch.uint8, device=dev)
+        res3 = None
+        ms = []
+        for r in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            res3 = V.info_nce_grad(m, S, A, O, out=res3, workspace=wsg)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:
+                ms.append(a.elapsed_time(b))
+        t = float(np.median(ms))
+        peak = PEAK_F32_TFLOPS if compute == "f32" else PEAK_BF16_TFLOPS
+        out["realistic_param_grad"][compute] = {
+            "ms": t, "pairs_per_s": pairs / (t / 1e3), "achieved_tflops": f_grad * pairs / (t / 1e3) / 1e12,
+            "mfma_frac": f_grad * pairs / (t / 1e3) / 1e12 / peak, "n_params": int(res3["grad"].numel())}
+        print(f"[bench]   realistic parameter derivative {compute}: {t:.3f} ms", file=sys.stderr, flush=True)
+        del wsg
     return out
 
 
@@ -620,7 +647,14 @@ def main():
                     help="skip the batched, gradient and update-sweep measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter calibration)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated extra sections to run (for profiling): bf16, batched, gradients, small, "
+                         "wide, plan_observe, pw_step, info_nce, ddim, tree, update_sweep, gemm")
     args = ap.parse_args()
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(section):
+        return section in only if only else True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (single-GPU library and benchmark)",
               file=sys.stderr, flush=True)
@@ -717,7 +751,7 @@ def main():
                      "rollout_steps_per_launch": steps_per_step},
     }
 
-    if not args.no_bf16:
+    if not args.no_bf16 and want("bf16"):
         mb = V.Model(w.model, compute="bf16")
         wsb = mb.plan_workspace(N, K, H)
         qb = torch.empty(K, dtype=torch.float32, device=dev)
@@ -741,29 +775,30 @@ def main():
                           "roofline_frac_bf16_peak": flops / (bms / 1000.0) / 1e12 / PEAK_BF16_TFLOPS}
         print(f"[bench] bf16 plan {bms:.2f} ms", file=sys.stderr, flush=True)
 
+    sections = [
+        ("batched", "batched instances (bf16 persistent graph vs f32 plain)", "batched",
+         lambda: bench_batched(V, torch, max(2, args.steps // 2))),
+        ("gradients", "adjoint rollouts", "gradients", lambda: bench_grad(V, torch, max(2, args.steps))),
+        ("small", "small workload latency", "small_f32", lambda: bench_small(V, torch, args.steps)),
+        ("wide", "hidden width 1024 (bf16)", "wide_bf16", lambda: bench_wide(V, torch, max(2, args.steps // 2))),
+        ("plan_observe", "rollout states and per-step observations", "plan_observe",
+         lambda: bench_plan_observe(V, torch, max(2, args.steps // 2), w, S, C)),
+        ("pw_step", "grouped progressive widening", "pw_step", lambda: bench_pw(V, torch, max(3, args.steps))),
+        ("info_nce", "contrastive likelihood objective", "info_nce",
+         lambda: bench_info_nce(V, torch, max(3, args.steps))),
+        ("ddim", "DDIM teacher sampler vs one distilled-sampler evaluation", "ddim",
+         lambda: bench_ddim(V, torch, max(2, args.steps // 2))),
+        ("tree", "one-level closed-loop tree", "closed_loop_tree", lambda: bench_tree(V, torch, max(2, args.steps // 2))),
+        ("update_sweep", "belief-update sweep", "update_sweep",
+         lambda: bench_update_sweep(V, torch, max(3, args.steps))),
+    ]
     if not args.no_extras:
-        print("[bench] batched instances (bf16 persistent graph vs f32 plain)", file=sys.stderr, flush=True)
-        result["batched"] = bench_batched(V, torch, max(2, args.steps // 2))
-        print("[bench] adjoint rollouts", file=sys.stderr, flush=True)
-        result["gradients"] = bench_grad(V, torch, max(2, args.steps))
-        print("[bench] small workload latency", file=sys.stderr, flush=True)
-        result["small_f32"] = bench_small(V, torch, args.steps)
-        print("[bench] hidden width 1024 (bf16)", file=sys.stderr, flush=True)
-        result["wide_bf16"] = bench_wide(V, torch, max(2, args.steps // 2))
-        print("[bench] rollout states and per-step observations", file=sys.stderr, flush=True)
-        result["plan_observe"] = bench_plan_observe(V, torch, max(2, args.steps // 2), w, S, C)
-        print("[bench] grouped progressive widening", file=sys.stderr, flush=True)
-        result["pw_step"] = bench_pw(V, torch, max(3, args.steps))
-        print("[bench] contrastive likelihood objective", file=sys.stderr, flush=True)
-        result["info_nce"] = bench_info_nce(V, torch, max(3, args.steps))
-        print("[bench] DDIM teacher sampler vs one distilled-sampler evaluation", file=sys.stderr, flush=True)
-        result["ddim"] = bench_ddim(V, torch, max(2, args.steps // 2))
-        print("[bench] one-level closed-loop tree", file=sys.stderr, flush=True)
-        result["closed_loop_tree"] = bench_tree(V, torch, max(2, args.steps // 2))
-        print("[bench] belief-update sweep", file=sys.stderr, flush=True)
-        result["update_sweep"] = bench_update_sweep(V, torch, max(3, args.steps))
+        for name, title, key, fn in sections:
+            if want(name):
+                print(f"[bench] {title}", file=sys.stderr, flush=True)
+                result[key] = fn()
 
-    if not args.no_extras:
+    if not args.no_extras and want("gemm"):
         print("[bench] library GEMM reference (matrix-core peak re-measured)", file=sys.stderr, flush=True)
         result["gemm_reference"] = bench_gemm_reference(torch, 5)
         g = result["gemm_reference"]

@@ -1006,28 +1006,82 @@ __device__ __forceinline__ float word_to_uniform(uint32_t x) {
     return (float)((x >> 8) | 1u) * 0x1p-24f;
 }
 
-// Box-Muller pair from two words: (r cos 2 pi u_b, r sin 2 pi u_b), r = sqrt(-2 ln u_a).
+// Box-Muller pair from two words: (r cos 2 pi u_b, r sin 2 pi u_b), r = sqrt(-2 ln u_a),
+// on the hardware transcendental units: -2 ln u_a = -2 ln 2 log2 u_a (v_log_f32),
+// v_sqrt_f32, and v_sin_f32 / v_cos_f32, which take their argument in turns
+// (sin 2 pi x), so u_b in (0, 1) needs no range reduction.
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& z_cos, float& z_sin) {
-    float ua = word_to_uniform(wa), ub = word_to_uniform(wb);
-    float r = sqrtf(-2.0f * logf(ua));
-    float s, c;
-    sincospif(2.0f * ub, &s, &c);
-    z_cos = r * c;
-    z_sin = r * s;
+    const float ua = word_to_uniform(wa), ub = word_to_uniform(wb);
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+    z_cos = r * __builtin_amdgcn_cosf(ub);
+    z_sin = r * __builtin_amdgcn_sinf(ub);
+}
+
+// The value of the lane 32 positions away: lanes l < 32 get lane l + 32's
+// value and lanes l >= 32 lane l - 32's (one v_permlane32_swap; every lane of
+// the wave must be active).
+__device__ __forceinline__ uint32_t swap_halves(uint32_t v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
 }
 
 // The noise slots of lane group g: slot s holds feature 4 (s / 2) + 2 g + s % 2,
 // i.e. pair g of Philox block s / 2 of counter (c0, c1, c2, (stream << 16) | block).
+// The two lane groups of a column need the two halves of the same blocks:
+// with an even number of blocks each group computes every other block and
+// hands the other group the pair it needs, so each block is computed once.
 template <int NS>
 __device__ __forceinline__ void noise_slots_philox(float (&out)[NS], uint32_t key0, uint32_t key1, uint32_t c0,
                                                    uint32_t c1, uint32_t c2, uint32_t stream, int g) {
+    constexpr int NB = NS / 2;
+    if constexpr (NB % 2 == 0) {
+#pragma unroll
+        for (int q = 0; q < NB / 2; ++q) {
+            // group g computes block 2 q + g
+            const uint4 w = philox4x32_10(make_uint4(c0, c1, c2, (stream << 16) | (uint32_t)(2 * q + g)), key0, key1);
+            const uint32_t own_a = g ? w.z : w.x, own_b = g ? w.w : w.y;
+            const uint32_t got_a = swap_halves(g ? w.x : w.z), got_b = swap_halves(g ? w.y : w.w);
+            // block 2 q: group 0's own pair, group 1 receives it; block 2 q + 1 the other way round
+            box_muller(g ? got_a : own_a, g ? got_b : own_b, out[4 * q], out[4 * q + 1]);
+            box_muller(g ? own_a : got_a, g ? own_b : got_b, out[4 * q + 2], out[4 * q + 3]);
+        }
+    } else {
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) {
+            uint4 w = philox4x32_10(make_uint4(c0, c1, c2, (stream << 16) | (uint32_t)blk), key0, key1);
+            uint32_t wa = g ? w.z : w.x;
+            uint32_t wb = g ? w.w : w.y;
+            box_muller(wa, wb, out[2 * blk], out[2 * blk + 1]);
+        }
+    }
+}
+
+// Philox words of the noise slots of lane group g for steps c2 and c2 + 1
+// (counter (c0, c1, step, (stream << 16) | block)), each block computed once:
+// group g computes the blocks of step c2 + g, keeps its own pair and hands the
+// other group its pair of the same step.  now[2 b], now[2 b + 1] are the
+// words of block b at step c2, next[] those at step c2 + 1.
+template <int NS>
+__device__ __forceinline__ void philox_two_steps(uint32_t (&now)[NS], uint32_t (&next)[NS], uint32_t key0,
+                                                 uint32_t key1, uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t stream, int g) {
 #pragma unroll
     for (int blk = 0; blk < NS / 2; ++blk) {
-        uint4 w = philox4x32_10(make_uint4(c0, c1, c2, (stream << 16) | (uint32_t)blk), key0, key1);
-        uint32_t wa = g ? w.z : w.x;
-        uint32_t wb = g ? w.w : w.y;
-        box_muller(wa, wb, out[2 * blk], out[2 * blk + 1]);
+        const uint4 w = philox4x32_10(make_uint4(c0, c1, c2 + (uint32_t)g, (stream << 16) | (uint32_t)blk), key0, key1);
+        const uint32_t own_a = g ? w.z : w.x, own_b = g ? w.w : w.y;
+        const uint32_t got_a = swap_halves(g ? w.x : w.z), got_b = swap_halves(g ? w.y : w.w);
+        now[2 * blk] = g ? got_a : own_a;
+        now[2 * blk + 1] = g ? got_b : own_b;
+        next[2 * blk] = g ? own_a : got_a;
+        next[2 * blk + 1] = g ? own_b : got_b;
     }
+}
+
+// Box-Muller draws of the noise slots from their Philox words.
+template <int NS>
+__device__ __forceinline__ void noise_from_words(float (&out)[NS], const uint32_t (&wd)[NS]) {
+#pragma unroll
+    for (int blk = 0; blk < NS / 2; ++blk) box_muller(wd[2 * blk], wd[2 * blk + 1], out[2 * blk], out[2 * blk + 1]);
 }
 
 // Noise feature held by slot s of group g.

@@ -41,6 +41,7 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
     __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
     float G = 0.0f;
     double disc = 1.0;
+    uint32_t wnow[SW], wnext[SW];  // Philox words of this step's and the next step's noise slots
     for (int t = 0; t < p.H; ++t) {
         float slots[NT::IN_SLOTS];
 #pragma unroll
@@ -66,8 +67,16 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
             // wait on this path only (the merged path would wait on every step)
             __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
         } else {
+            // steps come in pairs: the words of both are drawn at the even step
+            if ((t & 1) == 0) {
+                philox_two_steps<SW>(wnow, wnext, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k,
+                                     (uint32_t)t, 3u, g);
+            } else {
+#pragma unroll
+                for (int s = 0; s < SW; ++s) wnow[s] = wnext[s];
+            }
             float nz[SW];
-            noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 3u, g);
+            noise_from_words<SW>(nz, wnow);
 #pragma unroll
             for (int s = 0; s < SW; ++s) slots[SS + SA + s] = nz[s];
         }
