@@ -293,18 +293,15 @@ struct GradReduceParams {
 
 // Multi-workgroup normalisation / resampling for large beliefs.
 struct LargeResWs {
-    double* bmax;    // per-chunk max
-    double* bsum;    // per-chunk sum of exp
+    double* bmax;    // per-block max
+    double* bsum;    // per-block sum of exp
+    double* bsq;     // per-block sum of squared weights
+    int* blast;      // per-block last positive-mass particle
     double* btot;    // per-chunk total of quantised weights
-    double* bsq;     // per-chunk sum of squared weights
     double* boff;    // exclusive prefix of chunk totals
     double* bincl;   // inclusive prefix of chunk totals
-    int* blast;      // per-chunk last positive-mass particle
-    double* cloc;    // [N] chunk-relative inclusive prefix of quantised weights
     double* scal;    // [0] max, [1] sum
     int* last;       // last positive-mass particle overall
-    int* starts;     // [chunks + 1] particle of the first output of each output block
-    int* idx;        // [N] indices when the caller keeps none
 };
 
 struct LargeResParams {
@@ -313,7 +310,7 @@ struct LargeResParams {
     const double* prior_w;  // with loglik, or NULL
     const double* w_in;     // given normalised weights (resample only), or NULL
     double lambda;
-    int N, bits, uniform_prior, do_resample, n_chunks;
+    int N, bits, uniform_prior, do_resample, n_chunks, n_blocks;
     uint32_t U;
     double* w_out;
     double* stats;

@@ -1,26 +1,29 @@
 // resample_large.hip -- weight normalisation and systematic resampling for
 // beliefs larger than one workgroup can hold (N > 8192), streamed through HBM.
 //
-// Chunks of 4096 particles, 256 threads; thread t touches particles
-// chunk_base + 256 k + t (k < 16), so every global access is coalesced.
-//   pass 1  per-chunk (max, sum exp(x - max)) of x_i = l_i / lambda (+ log w_i),
-//           accumulated online (the running sum is rescaled when the running
-//           max grows), in a fixed order                        -> bmax, bsum
-//   red 1   m = max over chunks, S = sum_c bsum_c exp(bmax_c - m) in chunk order
-//   pass 2  w_i = exp(x_i - m) / S (or given weights), q_i = rint(w_i N 2^b);
-//           the chunk-relative inclusive prefix C_i is formed in LDS (each
-//           thread scans 16 consecutive entries, then the thread totals are
-//           scanned); chunk total, sum of w_i^2, last positive particle
+// Blocks of 4096 particles (256 threads, thread t touching particles
+// block_base + 256 k + t, k < 16, so global reads are coalesced) for the
+// first two passes; the quantised prefix is kept at the granularity of
+// 1024-particle chunks.
+//   pass 1  per-block (max, sum exp(x - max)) of x_i = l_i / lambda (+ log w_i)
+//           in a fixed order                                    -> bmax, bsum
+//   red 1   m = max over blocks, S = sum_b bsum_b exp(bmax_b - m) in block order
+//   pass 2  w_i = exp(x_i - m) / S (or given weights), q_i = rint(w_i N 2^b):
+//           the total of q of every 1024-particle chunk (exact), and per
+//           block the sum of w_i^2 and the last positive particle (the
+//           per-particle prefix is not stored)
 //   red 2   exclusive scan of the chunk totals, statistics
-//   starts  per block of 4096 outputs, the particle of its first output
-//           (global two-level search, one thread per block)
-//   pass 3  one workgroup per 4096 consecutive outputs j: the particles
-//           [start of this block, start of the next] own all of them; each
-//           particle writes its index to the outputs it owns (the count form
-//           of the search: its copies are the outputs between its two prefix
-//           boundaries), the rest take the last positive-mass particle
-//   gather  dst row j = src row idx_j, 16-byte vectors where the rows allow,
-//           consecutive threads on consecutive elements
+//   pass 3  one workgroup per 1024 consecutive outputs j: the chunks whose
+//           prefix range meets the block's positions j 2^b + u are found by
+//           binary search over the chunk totals; for each such chunk the
+//           q_i are recomputed (the same arithmetic as pass 2; thread t holds
+//           particles 4 t .. 4 t + 3) and their chunk-relative inclusive
+//           prefix is formed in registers (thread scan, then a scan of the
+//           thread totals); each particle writes its index to the outputs it
+//           owns (the count form of the search: a particle's copies are the
+//           outputs between its two prefix boundaries); outputs past the total
+//           mass take the last positive-mass particle; the block then writes
+//           its indices and gathers its rows dst_j = src_{idx_j}
 // Every prefix is an integer below 2^53, so the blocked sums give the same
 // bits as a sequential sum and the indices equal those of the definition.
 #include "kernels.hpp"
@@ -32,8 +35,11 @@ namespace voila {
 namespace {
 
 constexpr int kLgThreads = 256;
-constexpr int kLgItems = 16;
-constexpr int kLgChunk = kLgThreads * kLgItems;
+constexpr int kLgItems = 16;                      // particles per thread in passes 1 and 2
+constexpr int kLgBlock = kLgThreads * kLgItems;   // particles per workgroup of passes 1 and 2
+constexpr int kLgChunk = 1024;                    // particles per chunk of the quantised prefix
+constexpr int kSubPerBlock = kLgBlock / kLgChunk;
+constexpr int kChunkItems = kLgChunk / kLgThreads;  // particles per thread in pass 3
 
 __device__ __forceinline__ double lg_x(const LargeResParams& p, int i, int& bad) {
     if (p.x) {
@@ -47,8 +53,6 @@ __device__ __forceinline__ double lg_x(const LargeResParams& p, int i, int& bad)
     if (p.prior_w) x += log(p.prior_w[i]);
     return x;
 }
-
-__device__ __forceinline__ int lg_pad(int r) { return r + (r >> 4); }
 
 // (m, s) <- (m, s) combined with (m2, s2), where s = sum exp(x - m).
 __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
@@ -86,51 +90,12 @@ __device__ int blk_max_i(int v, int* red) {
     return r;
 }
 
-// Global prefix of particle i (exact integer).
-__device__ __forceinline__ double gprefix(const LargeResParams& p, int i) {
-    return p.ws.boff[i / kLgChunk] + p.ws.cloc[i];
-}
-
-// First particle with prefix > P (global memory), or `last` if none.
-__device__ int global_search(const LargeResParams& p, double P, int last) {
-    int a = 0, b = p.n_chunks;
-    while (a < b) {
-        int mid = (a + b) >> 1;
-        if (p.ws.bincl[mid] > P) b = mid;
-        else a = mid + 1;
-    }
-    if (a >= p.n_chunks) return last;
-    const double rel = P - p.ws.boff[a];
-    int lo = a * kLgChunk, hi = min(p.N, lo + kLgChunk);
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (p.ws.cloc[mid] > rel) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
-
-// dst row j0 + r = src row ids[r] for r < n_out (rows of w elements): each
-// thread keeps one column c and walks the rows, so consecutive threads move
-// consecutive elements of a row and of consecutive rows.
-template <class T>
-__device__ __forceinline__ void gather_rows(T* dst, const T* src, const int* ids, int j0, int n_out, int w) {
-    if (w <= kLgThreads) {
-        const int rpp = kLgThreads / w, r0 = threadIdx.x / w, c = threadIdx.x - r0 * w;
-        if (r0 < rpp)
-            for (int r = r0; r < n_out; r += rpp) dst[(size_t)(j0 + r) * w + c] = src[(size_t)ids[r] * w + c];
-    } else {
-        for (int r = 0; r < n_out; ++r)
-            for (int c = threadIdx.x; c < w; c += kLgThreads) dst[(size_t)(j0 + r) * w + c] = src[(size_t)ids[r] * w + c];
-    }
-}
-
 }  // namespace
 
 __global__ __launch_bounds__(kLgThreads) void lg_lse_kernel(LargeResParams p) {
-    __shared__ double rm[kLgThreads], rs[kLgThreads];
+    __shared__ double rm[kLgThreads / 64], rs[kLgThreads / 64];
     __shared__ int redi[kLgThreads / 64];
-    const int base = blockIdx.x * kLgChunk + threadIdx.x;
+    const int base = blockIdx.x * kLgBlock + threadIdx.x;
     int bad = 0;
     // this thread's 16 values: their maximum, then the sum of exp(x - max)
     // (independent exponentials, no serial merge chain)
@@ -147,22 +112,20 @@ __global__ __launch_bounds__(kLgThreads) void lg_lse_kernel(LargeResParams p) {
 #pragma unroll
         for (int k = 0; k < kLgItems; ++k) s += exp(xs[k] - m);
     }
-    rm[threadIdx.x] = m;
-    rs[threadIdx.x] = s;
-    bad = blk_max_i(bad, redi);
-    // fixed-shape tree: thread t merges t + h into t for h = 128, 64, ..., 1
-    for (int h = kLgThreads / 2; h >= 1; h >>= 1) {
-        __syncthreads();
-        if (threadIdx.x < h) {
-            double mm = rm[threadIdx.x], ss = rs[threadIdx.x];
-            lse_merge(mm, ss, rm[threadIdx.x + h], rs[threadIdx.x + h]);
-            rm[threadIdx.x] = mm;
-            rs[threadIdx.x] = ss;
-        }
+    // fixed-shape tree: lanes merge across the wave (butterfly), then the
+    // four wave results in order
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) lse_merge(m, s, __shfl_xor(m, d), __shfl_xor(s, d));
+    if ((threadIdx.x & 63) == 0) {
+        rm[threadIdx.x >> 6] = m;
+        rs[threadIdx.x >> 6] = s;
     }
+    bad = blk_max_i(bad, redi);
     if (threadIdx.x == 0) {
-        p.ws.bmax[blockIdx.x] = rm[0];
-        p.ws.bsum[blockIdx.x] = rs[0];
+        double mm = rm[0], ss = rs[0];
+        for (int w = 1; w < kLgThreads / 64; ++w) lse_merge(mm, ss, rm[w], rs[w]);
+        p.ws.bmax[blockIdx.x] = mm;
+        p.ws.bsum[blockIdx.x] = ss;
         if (bad && p.status) p.status[0] = 5;
     }
 }
@@ -171,7 +134,7 @@ constexpr int kRedThreads = 1024;
 __global__ __launch_bounds__(kRedThreads) void lg_lse_reduce_kernel(LargeResParams p) {
     __shared__ double rm[kRedThreads], rs[kRedThreads];
     double m = -INFINITY, s = 0.0;
-    for (int c = threadIdx.x; c < p.n_chunks; c += kRedThreads) lse_merge(m, s, p.ws.bmax[c], p.ws.bsum[c]);
+    for (int c = threadIdx.x; c < p.n_blocks; c += kRedThreads) lse_merge(m, s, p.ws.bmax[c], p.ws.bsum[c]);
     rm[threadIdx.x] = m;
     rs[threadIdx.x] = s;
     for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
@@ -190,66 +153,49 @@ __global__ __launch_bounds__(kRedThreads) void lg_lse_reduce_kernel(LargeResPara
     }
 }
 
+// q_i = rint(w_i N 2^b) of particle i with w_i = exp(x_i - m) / S, or the
+// given weight (checked); pass 2 and pass 3 call this same function.
+__device__ __forceinline__ double quant_w(const LargeResParams& p, int i, double m, double S, int& bad, double& w) {
+    if (p.w_in) {
+        w = p.w_in[i];
+        if (!(w >= 0.0) || w == INFINITY) bad = 1;
+    } else {
+        w = exp(lg_x(p, i, bad) - m) / S;
+    }
+    return rint(w * ldexp((double)p.N, p.bits));
+}
+
 __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) {
-    // one pad slot per 16 entries keeps the per-thread scans of 16
-    // consecutive entries off a single LDS bank
-    __shared__ double q[kLgChunk + kLgChunk / 16];
     __shared__ double red[kLgThreads / 64];
     __shared__ int redi[kLgThreads / 64];
-    __shared__ double tot[kLgThreads / 64];
-    const int cbase = blockIdx.x * kLgChunk;
+    const int bbase = blockIdx.x * kLgBlock;
     const double m = p.ws.scal[0], S = p.ws.scal[1];
-    const double scale = ldexp((double)p.N, p.bits);
-    double sq = 0.0;
+    double sq = 0.0, tq[kSubPerBlock];
     int last = -1, bad = 0;
+#pragma unroll
+    for (int c = 0; c < kSubPerBlock; ++c) tq[c] = 0.0;
+#pragma unroll
     for (int k = 0; k < kLgItems; ++k) {
-        const int r = k * kLgThreads + threadIdx.x, i = cbase + r;
-        double w = 0.0;
+        const int i = bbase + k * kLgThreads + threadIdx.x;  // chunk k / kChunkItems of the block
         if (i < p.N) {
-            if (p.w_in) {
-                w = p.w_in[i];
-                if (!(w >= 0.0) || w == INFINITY) bad = 1;
-            } else {
-                w = exp(lg_x(p, i, bad) - m) / S;
-                if (p.w_out) p.w_out[i] = w;
-            }
+            double w;
+            const double q = quant_w(p, i, m, S, bad, w);
+            if (!p.w_in && p.w_out) p.w_out[i] = w;
+            sq += w * w;
+            tq[k / kChunkItems] += q;  // exact: integers below 2^53
+            if (q > 0.0) last = i;
         }
-        sq += w * w;
-        const double qi = rint(w * scale);
-        if (qi > 0.0) last = i;
-        q[lg_pad(r)] = qi;
     }
-    __syncthreads();
-    // chunk-relative inclusive prefix: 16 consecutive entries per thread, then the thread totals
-    double run = 0.0;
-    for (int k = 0; k < kLgItems; ++k) {
-        run += q[lg_pad(threadIdx.x * kLgItems + k)];
-        q[lg_pad(threadIdx.x * kLgItems + k)] = run;
+#pragma unroll
+    for (int c = 0; c < kSubPerBlock; ++c) {
+        const double t = blk_sum(tq[c], red);
+        const int ci = blockIdx.x * kSubPerBlock + c;
+        if (threadIdx.x == 0 && ci < p.n_chunks) p.ws.btot[ci] = t;
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double incl = run;
-    for (int d = 1; d < 64; d <<= 1) {
-        double o = __shfl_up(incl, d);
-        if (lane >= d) incl += o;
-    }
-    if (lane == 63) tot[wave] = incl;
-    __syncthreads();
-    double off = incl - run;
-    for (int w2 = 0; w2 < wave; ++w2) off += tot[w2];
-    for (int k = 0; k < kLgItems; ++k) q[lg_pad(threadIdx.x * kLgItems + k)] += off;
-    double total = 0.0;
-    for (int w2 = 0; w2 < kLgThreads / 64; ++w2) total += tot[w2];
-    __syncthreads();
-    if (p.do_resample)
-        for (int k = 0; k < kLgItems; ++k) {
-            const int r = k * kLgThreads + threadIdx.x;
-            if (cbase + r < p.N) p.ws.cloc[cbase + r] = q[lg_pad(r)];
-        }
     sq = blk_sum(sq, red);
     last = blk_max_i(last, redi);
     bad = blk_max_i(bad, redi);
     if (threadIdx.x == 0) {
-        p.ws.btot[blockIdx.x] = total;
         p.ws.bsq[blockIdx.x] = sq;
         p.ws.blast[blockIdx.x] = last;
         if (bad && p.status) p.status[0] = 5;
@@ -257,19 +203,28 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
 }
 
 // One workgroup: exclusive scan of the chunk totals, global statistics.
+// Loads are issued eight at a time ahead of their use.
 __global__ __launch_bounds__(1024) void lg_scan_kernel(LargeResParams p) {
     __shared__ double tot[1024 / 64];
     __shared__ double red[1024 / 64];
     __shared__ int redi[1024 / 64];
+    constexpr int B8 = 8;
     const int nc = p.n_chunks;
     const int per = (nc + blockDim.x - 1) / blockDim.x;
     const int lo = threadIdx.x * per, hi = min(nc, lo + per);
-    double run = 0.0, sq = 0.0;
+    double run = 0.0;
+    for (int c0 = lo; c0 < hi; c0 += B8) {
+        double v[B8];
+#pragma unroll
+        for (int e = 0; e < B8; ++e) v[e] = c0 + e < hi ? p.ws.btot[c0 + e] : 0.0;
+#pragma unroll
+        for (int e = 0; e < B8; ++e) run += v[e];
+    }
+    double sq = 0.0;
     int last = -1;
-    for (int c = lo; c < hi; ++c) {
-        run += p.ws.btot[c];
-        sq += p.ws.bsq[c];
-        last = max(last, p.ws.blast[c]);
+    for (int b = threadIdx.x; b < p.n_blocks; b += blockDim.x) {
+        sq += p.ws.bsq[b];
+        last = max(last, p.ws.blast[b]);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double incl = run;
@@ -281,10 +236,18 @@ __global__ __launch_bounds__(1024) void lg_scan_kernel(LargeResParams p) {
     __syncthreads();
     double off = incl - run;
     for (int w2 = 0; w2 < wave; ++w2) off += tot[w2];
-    for (int c = lo; c < hi; ++c) {
-        p.ws.boff[c] = off;
-        off += p.ws.btot[c];
-        p.ws.bincl[c] = off;
+    for (int c0 = lo; c0 < hi; c0 += B8) {
+        double v[B8];
+#pragma unroll
+        for (int e = 0; e < B8; ++e) v[e] = c0 + e < hi ? p.ws.btot[c0 + e] : 0.0;
+#pragma unroll
+        for (int e = 0; e < B8; ++e) {
+            if (c0 + e < hi) {
+                p.ws.boff[c0 + e] = off;
+                off += v[e];
+                p.ws.bincl[c0 + e] = off;
+            }
+        }
     }
     sq = blk_sum(sq, red);
     last = blk_max_i(last, redi);
@@ -299,59 +262,122 @@ __global__ __launch_bounds__(1024) void lg_scan_kernel(LargeResParams p) {
     }
 }
 
-// Particle index of the first output of every block of 4096 outputs (and
-// `last` after the final block): the search range of each output block.
-__global__ __launch_bounds__(256) void lg_starts_kernel(LargeResParams p) {
-    const int blk = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blk > p.n_chunks) return;
-    const int last = p.ws.last[0];
-    if (last < 0) return;
-    if (blk == p.n_chunks) {
-        p.ws.starts[blk] = last;
-        return;
-    }
-    const double step = ldexp(1.0, p.bits), u = (double)(p.U >> (32 - p.bits));
-    p.ws.starts[blk] = global_search(p, (double)blk * kLgChunk * step + u, last);
-}
-
 constexpr int kHeavyCopies = 16;  // copies above which a particle's outputs are filled cooperatively
 constexpr int kHeavySlots = 64;
-__global__ __launch_bounds__(kLgThreads) void lg_search_kernel(LargeResParams p) {
-    __shared__ int ids[kLgChunk];
+constexpr int kOutBlock = kLgChunk;  // outputs per workgroup of pass 3
+
+// dst row j0 + r = src row ids[r] for r < n_out (rows of w elements): each
+// thread keeps one column and walks rows, so consecutive threads move
+// consecutive elements of a row and of consecutive rows.  The rows are
+// streamed with non-temporal loads and stores (read once / written once).
+typedef float f32x4_nt __attribute__((ext_vector_type(4)));
+template <class T> struct NtType { typedef T type; };
+template <> struct NtType<float4> { typedef f32x4_nt type; };
+template <class T>
+__device__ __forceinline__ void gather_rows(T* dst0, const T* src0, const int* ids, int j0, int n_out, int w) {
+    typedef typename NtType<T>::type V;
+    V* dst = reinterpret_cast<V*>(dst0);
+    const V* src = reinterpret_cast<const V*>(src0);
+    if (w <= kLgThreads) {
+        const int rpp = kLgThreads / w, r0 = threadIdx.x / w, c = threadIdx.x - r0 * w;
+        if (r0 < rpp)
+            for (int r = r0; r < n_out; r += rpp)
+                __builtin_nontemporal_store(__builtin_nontemporal_load(src + (size_t)ids[r] * w + c),
+                                            dst + (size_t)(j0 + r) * w + c);
+    } else {
+        for (int r = 0; r < n_out; ++r)
+            for (int c = threadIdx.x; c < w; c += kLgThreads)
+                __builtin_nontemporal_store(__builtin_nontemporal_load(src + (size_t)ids[r] * w + c),
+                                            dst + (size_t)(j0 + r) * w + c);
+    }
+}
+
+__global__ __launch_bounds__(kLgThreads) void lg_resample_kernel(LargeResParams p) {
+    __shared__ int ids[kOutBlock];
     __shared__ int3 heavy[kHeavySlots];
-    __shared__ int n_heavy;
+    __shared__ double wtot[kLgThreads / 64];
+    __shared__ int n_heavy, s_first;
     const int last = p.ws.last[0];
     if (last < 0) return;  // no particle has mass: outputs left untouched, status set
-    const int j0 = blockIdx.x * kLgChunk;
-    const int n_out = min(kLgChunk, p.N - j0);
-    const double inv_step = ldexp(1.0, -p.bits), u = (double)(p.U >> (32 - p.bits));
-    // every output of this block is owned by a particle in [starts[blk], starts[blk + 1]]
-    const int a = p.ws.starts[blockIdx.x], b = max(a, p.ws.starts[blockIdx.x + 1]);
+    const int j0 = blockIdx.x * kOutBlock;
+    const int n_out = min(kOutBlock, p.N - j0);
+    const double step = ldexp(1.0, p.bits), inv_step = ldexp(1.0, -p.bits);
+    const double u = (double)(p.U >> (32 - p.bits));
+    const double P0 = (double)j0 * step + u, P1 = (double)(j0 + n_out - 1) * step + u;
+    const double m = p.ws.scal[0], S = p.ws.scal[1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // outputs past the total mass (the top edge) take the last positive-mass particle
     for (int r = threadIdx.x; r < n_out; r += kLgThreads) ids[r] = last;
+    // first chunk whose inclusive total exceeds the block's first position:
+    // the inclusive totals are non-decreasing, so it is the count of chunks
+    // with bincl <= P0, found in two rounds of one test per thread
+    if (threadIdx.x == 0) {
+        s_first = 0;
+        n_heavy = 0;
+    }
     __syncthreads();
-    // particle i owns the outputs j with C_{i-1} <= j 2^b + u < C_i, i.e.
-    // ceil((C_{i-1} - u) / 2^b) <= j < ceil((C_i - u) / 2^b): the same index as
-    // the first i with C_i > j 2^b + u (all quantities exact integers / powers of two)
-    // particles with many copies in this block are filled by the whole workgroup
-    for (int base = a; base <= b; base += kLgThreads) {
-        if (threadIdx.x == 0) n_heavy = 0;
+    {
+        const int stride = (p.n_chunks + kLgThreads - 1) / kLgThreads;  // chunks per segment
+        const int c1 = threadIdx.x * stride;
+        // segments whose first chunk is at or below P0 (the answer lies in the last of them)
+        const int below = (c1 < p.n_chunks && p.ws.bincl[c1] <= P0) ? 1 : 0;
+        const int nseg = __syncthreads_count(below);
+        if (nseg > 0) {
+            const int seg0 = (nseg - 1) * stride;
+            const int c2 = seg0 + threadIdx.x;
+            const int in = (threadIdx.x < stride && c2 < p.n_chunks && p.ws.bincl[c2] <= P0) ? 1 : 0;
+            const int cnt = __syncthreads_count(in);
+            if (threadIdx.x == 0) s_first = seg0 + cnt;
+        }
+    }
+    __syncthreads();
+    for (int c = s_first; c < p.n_chunks; ++c) {
+        const double coff = p.ws.boff[c];
+        if (coff > P1) break;                 // this and later chunks own no output of the block
+        if (p.ws.bincl[c] == coff) continue;  // no mass in the chunk
+        // this thread's particles i0 .. i0 + 3: q and their inclusive prefix
+        const int i0 = c * kLgChunk + kChunkItems * threadIdx.x;
+        double qk[kChunkItems], run = 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int k = 0; k < kChunkItems; ++k) {
+            double w;
+            qk[k] = i0 + k < p.N ? quant_w(p, i0 + k, m, S, bad, w) : 0.0;
+            run += qk[k];
+            qk[k] = run;
+        }
+        // exclusive scan of the thread totals (exact integers: any order gives the same bits)
+        double incl = run;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double o = __shfl_up(incl, d);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) wtot[wave] = incl;
         __syncthreads();
-        const int i = base + threadIdx.x;
-        if (i <= b) {
-            const double ci = gprefix(p, i);
-            const double cp = i > 0 ? gprefix(p, i - 1) : 0.0;
+        double off = coff + incl - run;
+        for (int w2 = 0; w2 < wave; ++w2) off += wtot[w2];
+        // particle i owns the outputs j with C_{i-1} <= j 2^b + u < C_i, i.e.
+        // ceil((C_{i-1} - u) / 2^b) <= j < ceil((C_i - u) / 2^b): the same index
+        // as the first i with C_i > j 2^b + u (exact integers / powers of two);
+        // particles with many copies in this block are filled by the whole workgroup
+        double cp = off;
+#pragma unroll
+        for (int k = 0; k < kChunkItems; ++k) {
+            const double ci = off + qk[k];
             if (ci > cp) {
                 const int js = max(j0, (int)ceil((cp - u) * inv_step));
                 const int je = min(j0 + n_out, (int)min(ceil((ci - u) * inv_step), (double)p.N));
-                int slot = -1;
-                if (je - js > kHeavyCopies) slot = atomicAdd(&n_heavy, 1);
-                if (slot >= 0 && slot < kHeavySlots) {
-                    heavy[slot] = make_int3(i, js, je);
+                if (je - js > kHeavyCopies) {
+                    const int slot = atomicAdd(&n_heavy, 1);
+                    if (slot < kHeavySlots) heavy[slot] = make_int3(i0 + k, js, je);
+                    else
+                        for (int j = js; j < je; ++j) ids[j - j0] = i0 + k;
                 } else {
-                    for (int j = js; j < je; ++j) ids[j - j0] = i;
+                    for (int j = js; j < je; ++j) ids[j - j0] = i0 + k;
                 }
             }
+            cp = ci;
         }
         __syncthreads();
         const int nh = min(n_heavy, kHeavySlots);
@@ -360,67 +386,56 @@ __global__ __launch_bounds__(kLgThreads) void lg_search_kernel(LargeResParams p)
             for (int j = e.y + threadIdx.x; j < e.z; j += kLgThreads) ids[j - j0] = e.x;
         }
         __syncthreads();
+        if (threadIdx.x == 0) n_heavy = 0;
+        __syncthreads();
     }
-    for (int r = threadIdx.x; r < n_out; r += kLgThreads) p.idx_out[j0 + r] = ids[r];
-}
-
-// The resampled rows: dst row j = src row idx_j, 1024 rows per workgroup.
-constexpr int kGatherRows = 1024;
-__global__ __launch_bounds__(kLgThreads) void lg_gather_kernel(LargeResParams p) {
-    if (p.ws.last[0] < 0) return;
-    const int j0 = blockIdx.x * kGatherRows;
-    const int n_out = min(kGatherRows, p.N - j0);
-    const int rf = p.row_floats;
-    const int* ids = p.idx_out + j0;
-    if (rf % 4 == 0 && ((reinterpret_cast<uintptr_t>(p.src) | reinterpret_cast<uintptr_t>(p.dst)) & 15) == 0)
-        gather_rows(reinterpret_cast<float4*>(p.dst), reinterpret_cast<const float4*>(p.src), ids, j0, n_out, rf / 4);
-    else
-        gather_rows(p.dst, p.src, ids, j0, n_out, rf);
+    if (p.idx_out)
+        for (int r = threadIdx.x; r < n_out; r += kLgThreads) p.idx_out[j0 + r] = ids[r];
+    if (p.src && p.dst) {
+        const int rf = p.row_floats;
+        if (rf % 4 == 0 && ((reinterpret_cast<uintptr_t>(p.src) | reinterpret_cast<uintptr_t>(p.dst)) & 15) == 0)
+            gather_rows(reinterpret_cast<float4*>(p.dst), reinterpret_cast<const float4*>(p.src), ids, j0, n_out,
+                        rf / 4);
+        else
+            gather_rows(p.dst, p.src, ids, j0, n_out, rf);
+    }
 }
 
 size_t large_res_workspace_bytes(int N) {
-    const size_t nc = ((size_t)N + kLgChunk - 1) / kLgChunk;
+    const size_t nb = ((size_t)N + kLgBlock - 1) / kLgBlock, nc = ((size_t)N + kLgChunk - 1) / kLgChunk;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-    return al(nc * 8) * 6 + al(nc * 4) + al((size_t)N * 8) + al(64) + al((nc + 1) * 4) + al((size_t)N * 4);
+    return al(nb * 8) * 3 + al(nb * 4) + al(nc * 8) * 3 + al(64);
 }
 
 LargeResWs carve_large_res(void* base, int N) {
-    const size_t nc = ((size_t)N + kLgChunk - 1) / kLgChunk;
+    const size_t nb = ((size_t)N + kLgBlock - 1) / kLgBlock, nc = ((size_t)N + kLgChunk - 1) / kLgChunk;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     char* b = reinterpret_cast<char*>(base);
     LargeResWs w;
-    w.bmax = reinterpret_cast<double*>(b); b += al(nc * 8);
-    w.bsum = reinterpret_cast<double*>(b); b += al(nc * 8);
+    w.bmax = reinterpret_cast<double*>(b); b += al(nb * 8);
+    w.bsum = reinterpret_cast<double*>(b); b += al(nb * 8);
+    w.bsq = reinterpret_cast<double*>(b); b += al(nb * 8);
+    w.blast = reinterpret_cast<int*>(b); b += al(nb * 4);
     w.btot = reinterpret_cast<double*>(b); b += al(nc * 8);
-    w.bsq = reinterpret_cast<double*>(b); b += al(nc * 8);
     w.boff = reinterpret_cast<double*>(b); b += al(nc * 8);
     w.bincl = reinterpret_cast<double*>(b); b += al(nc * 8);
-    w.blast = reinterpret_cast<int*>(b); b += al(nc * 4);
-    w.cloc = reinterpret_cast<double*>(b); b += al((size_t)N * 8);
     w.scal = reinterpret_cast<double*>(b);
     w.last = reinterpret_cast<int*>(b + 32);
-    b += al(64);
-    w.starts = reinterpret_cast<int*>(b);
-    b += al((nc + 1) * 4);
-    w.idx = reinterpret_cast<int*>(b);
     return w;
 }
 
 hipError_t launch_large_res(LargeResParams p, hipStream_t s) {
+    p.n_blocks = (p.N + kLgBlock - 1) / kLgBlock;
     p.n_chunks = (p.N + kLgChunk - 1) / kLgChunk;
-    if (!p.idx_out) p.idx_out = p.ws.idx;  // the gather reads the indices back
-    const int nc = p.n_chunks;
     if (!p.w_in) {
-        hipLaunchKernelGGL(lg_lse_kernel, nc, kLgThreads, 0, s, p);
+        hipLaunchKernelGGL(lg_lse_kernel, p.n_blocks, kLgThreads, 0, s, p);
         hipLaunchKernelGGL(lg_lse_reduce_kernel, 1, kRedThreads, 0, s, p);
     }
-    hipLaunchKernelGGL(lg_quant_kernel, nc, kLgThreads, 0, s, p);
+    hipLaunchKernelGGL(lg_quant_kernel, p.n_blocks, kLgThreads, 0, s, p);
     hipLaunchKernelGGL(lg_scan_kernel, 1, 1024, 0, s, p);
     if (p.do_resample) {
-        hipLaunchKernelGGL(lg_starts_kernel, (nc + 1 + 255) / 256, 256, 0, s, p);
-        hipLaunchKernelGGL(lg_search_kernel, nc, kLgThreads, 0, s, p);
-        if (p.src && p.dst)
-            hipLaunchKernelGGL(lg_gather_kernel, (p.N + kGatherRows - 1) / kGatherRows, kLgThreads, 0, s, p);
+        if (p.idx_out || (p.src && p.dst))
+            hipLaunchKernelGGL(lg_resample_kernel, (p.N + kOutBlock - 1) / kOutBlock, kLgThreads, 0, s, p);
     }
     return hipGetLastError();
 }

@@ -75,7 +75,7 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     # beliefs above one workgroup need the caller's workspace
     assert L.voila_normalize(fake, None, 9000, 1.0, fake, None, None, None, 0, None) == V.VOILA_ERR_WORKSPACE
     assert L.voila_weights_workspace_size(8192) == 0
-    assert L.voila_weights_workspace_size(9000) > 9000 * 8
+    assert 0 < L.voila_weights_workspace_size(9000) < 9000 * 8  # per-chunk arrays only
     assert L.voila_resample(None, 0, 0, None, None, None, 0, None, None, 0, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_resample(fake, 4, 0, fake, fake, None, 1, None, None, 0, None) == V.VOILA_ERR_INVALID_ARG
     assert L.voila_resample(fake, 9000, 0, fake, None, None, 0, None, None, 0, None) == V.VOILA_ERR_WORKSPACE
