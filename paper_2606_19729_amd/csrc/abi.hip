@@ -96,7 +96,8 @@ int row_feature(int r) {
 // kernels consume them, then the biases.  b0_variants holds n_var rows of
 // `width` first-layer biases.
 std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, const SlotMap& map,
-                           const std::vector<float>& b0_variants, int n_var, NetBlob& nb, bool layered = false) {
+                           const std::vector<float>& b0_variants, int n_var, NetBlob& nb, bool layered = false,
+                           int pass_tiles = 0) {
     const int W = n.width(), HT = W / 32, NHID = n.n_layers - 1, KP = kper(dt);
     const int CT = layered ? HT : chunk_tiles(W);
     const int esz = dt == DT_F32 ? 4 : 2;
@@ -126,21 +127,27 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
         }
     };
     auto hidden_in = [](int ri, int g) { return 32 * (ri / 16) + out_row(ri % 16, g); };
-    // every fragment goes to its position in the consumption order (FragLayout)
+    // every fragment goes to its position in the consumption order (FragLayout,
+    // or the pass-major order of the paired plan evaluation)
     const FragLayout lay{HT, IN_KS, HID_KS, CT, NHID};
+    const int rp = pass_tiles;
+    auto first_pos = [&](int c, int t) { return rp ? pass_first(IN_KS, rp, c, t) : lay.first(c, t); };
+    auto hidden_pos = [&](int l, int c, int t) {
+        return rp ? pass_hidden((int)nf0, (int)nfh, HID_KS, rp, l, c, t) : lay.hidden(l, c, t);
+    };
     for (int c = 0; c < IN_KS; ++c)
         for (int t = 0; t < HT; ++t)
             for (int lane = 0; lane < 64; ++lane)
                 for (int j = 0; j < KP; ++j) {
                     int col = map(c * KP + j, lane / 32);
-                    put(off_f0, lay.first(c, t), lane, j, col >= 0 ? n.w(0, 32 * t + lane % 32, col) : 0.0f);
+                    put(off_f0, first_pos(c, t), lane, j, col >= 0 ? n.w(0, 32 * t + lane % 32, col) : 0.0f);
                 }
     for (int l = 1; l <= NHID - 1; ++l)
         for (int c = 0; c < HID_KS; ++c)
             for (int t = 0; t < HT; ++t)
                 for (int lane = 0; lane < 64; ++lane)
                     for (int j = 0; j < KP; ++j)
-                        put(off_f0, lay.hidden(l, c, t), lane, j,
+                        put(off_f0, hidden_pos(l, c, t), lane, j,
                             n.w(l, 32 * t + lane % 32, hidden_in(c * KP + j, lane / 32)));
     const int L = NHID;
     for (int c = 0; c < HID_KS; ++c)
@@ -439,7 +446,8 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     SlotMap map_plan{m->d_s, m->d_a, m->d_w, m->d_s, m->d_s + aw};
     SlotMap map_upd{m->d_s, 0, m->d_w, m->d_s, m->d_s + aw};
     std::vector<std::vector<char>> blobs;
-    blobs.push_back(pack_net(T, dt, plan_in_slots(shape, dt), map_plan, b0_plan, n_var, m->trans_plan));
+    blobs.push_back(pack_net(T, dt, plan_in_slots(shape, dt), map_plan, b0_plan, n_var, m->trans_plan, false,
+                             plan_pass_tiles(shape, dt)));
     blobs.push_back(pack_net(T, dt, update_in_slots(shape, dt), map_upd, b0_plain_T, 1, m->trans_upd));
     if (Z.present()) {
         std::vector<float> b0(Z.b[0], Z.b[0] + W);
@@ -664,7 +672,8 @@ voila_status_t voila_plan(voila_model_t m, const float* d_states, const double* 
     p.crn = o->crn ? 1 : 0;
     p.reward_at = o->reward_at;
     for (int j = 0; j < 32; ++j) p.goal[j] = j < m->d_s ? o->h_goal[j] : 0.0f;
-    const long units = (long)K * n_tiles;
+    // units: (candidate, tile), or (candidate, two tiles) for the paired evaluation
+    const long units = (long)K * (plan_pass_tiles(m->shape, m->dt) ? (n_tiles + 1) / 2 : n_tiles);
     const long want = (units + kWavesPerBlock - 1) / kWavesPerBlock;
     const long cap = (long)m->cus * m->plan_bpc;
     const int blocks = (int)(want < cap ? want : cap);

@@ -899,6 +899,71 @@ __device__ __forceinline__ void mfma_layer_multi(f32x16 (&acc)[ST][NT], LD&& ld,
     });
 }
 
+// Pass-major fragment order of a layered network whose layers are produced
+// RP output tiles at a time (run_net_passes): within each layer the
+// fragments of pass p (tiles RP p .. RP p + RP - 1) come first, k-step by
+// k-step; the output layer follows as usual.
+__host__ __device__ constexpr int pass_first(int in_ks, int rp, int c, int t) { return ((t / rp) * in_ks + c) * rp + t % rp; }
+__host__ __device__ constexpr int pass_hidden(int nf0, int nfh, int hid_ks, int rp, int l, int c, int t) {
+    return nf0 + (l - 1) * nfh + ((t / rp) * hid_ks + c) * rp + t % rp;
+}
+
+// A layered network (streamed in the pass-major order) on ST sample tiles of
+// one wave: every layer is produced RP output tiles at a time, each weight
+// fragment read from the stream serves all ST sample tiles, and the next
+// layer's operands are converted pass by pass while the current layer's
+// remain in registers.  out[st] is sample tile st's output tile.
+template <class N, int ST, int RP, class Src>
+__device__ __forceinline__ void run_net_passes(Src& src, const NetPtrs& P, const float* b0,
+                                               const float (&slots)[ST][N::IN_SLOTS], f32x16 (&out)[ST], int lane,
+                                               int g) {
+    static_assert(N::CT == N::HT && N::HT % RP == 0, "pass evaluation needs a layered network");
+    typedef typename Frag<N::DT>::type FT;
+    constexpr int NP = N::HT / RP;
+    constexpr int D = N::DT == DT_F32 ? kPfDepthF32 : kPfDepth;
+    Act<N::DT, N::HT> act[ST];
+    static_for<NP>([&](auto pi) {
+        constexpr int p = decltype(pi)::value;
+        f32x16 acc[ST][RP];
+#pragma unroll
+        for (int st = 0; st < ST; ++st) init_bias<RP>(acc[st], b0 + 32 * RP * p + opaque_zero(), g);
+        mfma_layer_multi<N::IN_KS, RP, ST, 2, FT>(
+            acc, [&](int c, int t) { return src.load(pass_first(N::IN_KS, RP, c, RP * p + t), lane); },
+            [&](int c, int st) { return Slots<N::DT, N::IN_SLOTS>::b(slots[st], c); });
+#pragma unroll
+        for (int st = 0; st < ST; ++st) act[st].template set_relu_at<RP>(acc[st], RP * p);
+    });
+    static_for<N::NHID - 1>([&](auto li) {
+        constexpr int l = decltype(li)::value + 1;
+        Act<N::DT, N::HT> nxt[ST];
+        static_for<NP>([&](auto pi) {
+            constexpr int p = decltype(pi)::value;
+            f32x16 acc[ST][RP];
+#pragma unroll
+            for (int st = 0; st < ST; ++st)
+                init_bias<RP>(acc[st], P.bh + (l - 1) * N::WIDTH + 32 * RP * p + opaque_zero(), g);
+            mfma_layer_multi<N::HID_KS, RP, ST, D, FT>(
+                acc,
+                [&](int c, int t) {
+                    return src.load(pass_hidden(N::NF0, N::NFH, N::HID_KS, RP, l, c, RP * p + t), lane);
+                },
+                [&](int c, int st) { return act[st].b(c); });
+#pragma unroll
+            for (int st = 0; st < ST; ++st) nxt[st].template set_relu_at<RP>(acc[st], RP * p);
+        });
+#pragma unroll
+        for (int st = 0; st < ST; ++st) act[st] = nxt[st];
+    });
+    f32x16 o[ST][1];
+#pragma unroll
+    for (int st = 0; st < ST; ++st) init_bias<1>(o[st], P.bo + opaque_zero(), g);
+    mfma_layer_multi<N::HID_KS, 1, ST, 4, FT>(
+        o, [&](int c, int) { return src.load(N::NF0 + (N::NHID - 1) * N::NFH + c, lane); },
+        [&](int c, int st) { return act[st].b(c); });
+#pragma unroll
+    for (int st = 0; st < ST; ++st) out[st] = o[st][0];
+}
+
 // Split evaluation of ST sample tiles by the NW waves of a block: wave w
 // computes output tiles [w HT/NW, (w+1) HT/NW) of every layer for all ST
 // sample tiles, so each weight fragment read from L2 serves ST tiles.  The

@@ -396,6 +396,11 @@ hipError_t launch_grad_reduce(const GradReduceParams& p, hipStream_t s);
 int grad_blocks_per_cu(int shape, size_t lds);
 int propose_batch_blocks_per_cu(int shape, int dt, int waves_per_block, size_t lds);
 
+// Output tiles per pass of the plan kernel's paired evaluation (two
+// 32-particle tiles per wave, weights in pass-major order), 0 when the shape
+// runs one tile per wave in the layer-major order.
+int plan_pass_tiles(int shape, int dt);
+
 // Resident blocks per CU of the plan / propose / observe kernels.
 int plan_blocks_per_cu(int shape, int dt);
 int propose_blocks_per_cu(int shape, int dt);
