@@ -133,6 +133,37 @@ def bench_batched(V, torch, reps):
     return out
 
 
+def bench_deep(V, torch, reps):
+    """Four hidden layers of 1024 in bfloat16 (the depth and width of the
+    paper's distilled samplers), run by the split rollout kernel: 256
+    candidates x 4096 particles x 20 steps."""
+    import workloads
+    dev = torch.device("cuda", 0)
+    w = workloads.deep(seed=8, N=4096, K=256, H=20)
+    mb = V.Model(w.model, compute="bf16")
+    S = torch.as_tensor(w.states, device=dev)
+    C = torch.as_tensor(w.cands, device=dev)
+    q = torch.empty(w.K, dtype=torch.float32, device=dev)
+    ws = mb.plan_workspace(w.N, w.K, w.H)
+    V.plan(mb, S, C, w.gamma, w.goal, seed=w.plan_seed, q_out=q, workspace=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for r in range(reps):
+        V.plan(mb, S, C, w.gamma, w.goal, seed=w.plan_seed + r, q_out=q, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    steps = w.K * w.N * w.H
+    fps = trans_flops_per_step(w.model)
+    tflops = fps * steps / (ms / 1e3) / 1e12
+    mb.close()
+    return {"K": w.K, "N": w.N, "H": w.H, "hidden": [1024] * 4, "plan_ms": ms,
+            "rollout_steps_per_s": steps / (ms / 1e3), "achieved_tflops": tflops,
+            "mfma_frac_bf16_peak": tflops / PEAK_BF16_TFLOPS, "flop_per_rollout_step": fps}
+
+
 def bench_wide(V, torch, reps):
     """Hidden width 1024 in bfloat16: throughput at 1024 candidates x 4096
     particles x 20 steps, and plan + update latency at the small counts."""
@@ -649,7 +680,7 @@ def main():
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter calibration)")
     ap.add_argument("--only", default="",
                     help="comma-separated extra sections to run (for profiling): bf16, batched, gradients, small, "
-                         "wide, plan_observe, pw_step, info_nce, ddim, tree, update_sweep, gemm")
+                         "wide, deep, plan_observe, pw_step, info_nce, ddim, tree, update_sweep, gemm")
     args = ap.parse_args()
     only = set(x for x in args.only.split(",") if x)
 
@@ -781,6 +812,8 @@ def main():
         ("gradients", "adjoint rollouts", "gradients", lambda: bench_grad(V, torch, max(2, args.steps))),
         ("small", "small workload latency", "small_f32", lambda: bench_small(V, torch, args.steps)),
         ("wide", "hidden width 1024 (bf16)", "wide_bf16", lambda: bench_wide(V, torch, max(2, args.steps // 2))),
+        ("deep", "four hidden layers of 1024 (bf16, split rollout kernel)", "deep_bf16",
+         lambda: bench_deep(V, torch, max(2, args.steps // 2))),
         ("plan_observe", "rollout states and per-step observations", "plan_observe",
          lambda: bench_plan_observe(V, torch, max(2, args.steps // 2), w, S, C)),
         ("pw_step", "grouped progressive widening", "pw_step", lambda: bench_pw(V, torch, max(3, args.steps))),

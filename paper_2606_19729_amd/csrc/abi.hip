@@ -99,7 +99,7 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
                            const std::vector<float>& b0_variants, int n_var, NetBlob& nb, bool layered = false,
                            int pass_tiles = 0) {
     const int W = n.width(), HT = W / 32, NHID = n.n_layers - 1, KP = kper(dt);
-    const int CT = layered ? HT : chunk_tiles(W);
+    const int CT = layered ? HT : default_ct(W, NHID);
     const int esz = dt == DT_F32 ? 4 : 2;
     const size_t fb = (size_t)64 * KP * esz;
     const int IN_KS = in_slots_per_group / KP, HID_KS = 16 * HT / KP;
@@ -403,6 +403,9 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
         }
     }
     if (shape < 0) return fail(VOILA_ERR_UNSUPPORTED, "no compiled kernel for this network shape");
+    if (plan_split_shape(shape, DT_BF16) && (Z.present() || L.present()))
+        return fail(VOILA_ERR_UNSUPPORTED,
+                    "networks wider than 256 with more than two hidden layers: transition network (plan) only");
     if (T.width() > 256 && desc->compute != VOILA_BF16)
         return fail(VOILA_ERR_UNSUPPORTED, "hidden widths above 256 run in bfloat16 only");
 
@@ -672,9 +675,11 @@ voila_status_t voila_plan(voila_model_t m, const float* d_states, const double* 
     p.crn = o->crn ? 1 : 0;
     p.reward_at = o->reward_at;
     for (int j = 0; j < 32; ++j) p.goal[j] = j < m->d_s ? o->h_goal[j] : 0.0f;
-    // units: (candidate, tile), or (candidate, two tiles) for the paired evaluation
-    const long units = (long)K * (plan_pass_tiles(m->shape, m->dt) ? (n_tiles + 1) / 2 : n_tiles);
-    const long want = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+    // units: (candidate, tile), or (candidate, group of tiles) for the paired
+    // and the split evaluations
+    const int tpu = plan_tiles_per_unit(m->shape, m->dt), upb = plan_units_per_block(m->shape, m->dt);
+    const long units = (long)K * ((n_tiles + tpu - 1) / tpu);
+    const long want = (units + upb - 1) / upb;
     const long cap = (long)m->cus * m->plan_bpc;
     const int blocks = (int)(want < cap ? want : cap);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -115,11 +115,15 @@ struct FragLayout {
 
 // Output tiles produced per group by the grouped evaluation of wide networks.
 __host__ __device__ constexpr int chunk_tiles(int width) { return width > 256 ? 4 : width / 32; }
+// Tiles per group of a network's default packing: the grouped evaluation
+// needs exactly two hidden layers, so deeper networks are packed layer by
+// layer (one group of every tile).
+__host__ __device__ constexpr int default_ct(int width, int nhid) { return nhid == 2 ? chunk_tiles(width) : width / 32; }
 
 // Compile-time shape of one network as the engine runs it.  CT_ = WIDTH_/32
 // packs a wide network layer by layer (for the split evaluation) instead of
 // in the groups of the grouped evaluation.
-template <int DT_, int WIDTH_, int NHID_, int IN_SLOTS_, int CT_ = chunk_tiles(WIDTH_)>
+template <int DT_, int WIDTH_, int NHID_, int IN_SLOTS_, int CT_ = default_ct(WIDTH_, NHID_)>
 struct Net {
     static constexpr int DT = DT_;
     static constexpr int WIDTH = WIDTH_;           // hidden width (multiple of 32)
@@ -920,7 +924,11 @@ __device__ __forceinline__ void run_net_passes(Src& src, const NetPtrs& P, const
     static_assert(N::CT == N::HT && N::HT % RP == 0, "pass evaluation needs a layered network");
     typedef typename Frag<N::DT>::type FT;
     constexpr int NP = N::HT / RP;
+#ifdef VOILA_PASS_DEPTH
+    constexpr int D = VOILA_PASS_DEPTH;
+#else
     constexpr int D = N::DT == DT_F32 ? kPfDepthF32 : kPfDepth;
+#endif
     Act<N::DT, N::HT> act[ST];
     static_for<NP>([&](auto pi) {
         constexpr int p = decltype(pi)::value;

@@ -12,8 +12,8 @@ namespace voila {
 // network's input slots.
 template <int DT, int D_O, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void nce_scores_kernel(NceParams p) {
-    if constexpr (!net_compiled(DT, WIDTH)) {
-        return;  // binary32 networks wider than 256 are refused at model creation
+    if constexpr (!generic_compiled(DT, WIDTH, NHID)) {
+        return;  // refused at model creation (binary32 wider than 256) or run by the split rollout kernel
     } else {
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_O, 0, 0)> NTL;
     constexpr int SO = state_slots(D_O);

@@ -67,8 +67,8 @@ __device__ __forceinline__ void observe_store(const ObserveParams& p, const ObsR
 // streamed through LDS like the rollout kernel's.
 template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
-    if constexpr (!net_compiled(DT, WIDTH)) {
-        return;  // binary32 networks wider than 256 are refused at model creation
+    if constexpr (!generic_compiled(DT, WIDTH, NHID)) {
+        return;  // refused at model creation (binary32 wider than 256) or run by the split rollout kernel
     } else {
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ)> NTO;
     extern __shared__ __attribute__((aligned(16))) char smem[];

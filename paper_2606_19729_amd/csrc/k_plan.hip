@@ -118,7 +118,10 @@ template <int DT, int WIDTH, int NHID>
 constexpr bool plan_pairs() {
     return DT == DT_BF16 && WIDTH > 64 && chunk_tiles(WIDTH) == WIDTH / 32 && NHID >= 2;
 }
-constexpr int kPlanPassTiles = 2;  // output tiles per pass of the paired evaluation
+#ifndef VOILA_PLAN_PASS_TILES
+#define VOILA_PLAN_PASS_TILES 2
+#endif
+constexpr int kPlanPassTiles = VOILA_PLAN_PASS_TILES;  // output tiles per pass of the paired evaluation
 
 // The unit of plan_unit for two tiles (2 tp, 2 tp + 1) of one candidate:
 // every weight fragment feeds both tiles' products.
@@ -239,8 +242,8 @@ __device__ __forceinline__ void plan_unit_pair(Src& src, const NetPtrs& P, const
 
 template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
-    if constexpr (!net_compiled(DT, WIDTH)) {
-        return;  // binary32 networks wider than 256 are refused at model creation
+    if constexpr (!generic_compiled(DT, WIDTH, NHID)) {
+        return;  // refused at model creation (binary32 wider than 256) or run by the split rollout kernel
     } else {
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W)> NT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -259,6 +262,159 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
                 plan_unit<DT, D_S, N_ACT, D_A, D_W, WIDTH, NHID>(src, P, p, p.goal, u, u < n_units, lane, g, col);
         }
     });
+    }
+}
+
+// Deep wide transition networks (more than two hidden layers wider than 256,
+// the depth of the paper's distilled samplers): a block of kPlanSplitWaves
+// waves advances kPlanSplitTiles 32-particle tiles of one candidate together,
+// each layer split over the waves (run_net_split_multi), so that every
+// weight fragment read from L2 serves all of the block's tiles.  Every wave
+// carries the tiles' states, noise and returns (the split evaluation hands
+// the same output to every wave); the first wave writes the results.  The
+// per-tile partial returns are those of plan_kernel.
+#ifndef VOILA_PLAN_SPLIT_WAVES
+#define VOILA_PLAN_SPLIT_WAVES 8
+#endif
+#ifndef VOILA_PLAN_SPLIT_TILES
+#define VOILA_PLAN_SPLIT_TILES 2
+#endif
+#ifndef VOILA_PLAN_SPLIT_DEPTH
+#define VOILA_PLAN_SPLIT_DEPTH 2
+#endif
+constexpr int kPlanSplitWaves = VOILA_PLAN_SPLIT_WAVES, kPlanSplitTiles = VOILA_PLAN_SPLIT_TILES,
+              kPlanSplitDepth = VOILA_PLAN_SPLIT_DEPTH;
+
+template <int DT, int WIDTH, int NHID>
+constexpr bool plan_split() {
+    return net_compiled(DT, WIDTH) && !generic_compiled(DT, WIDTH, NHID);
+}
+
+template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID>
+__global__ __launch_bounds__(64 * kPlanSplitWaves) void plan_split_kernel(PlanParams p) {
+    if constexpr (!plan_split<DT, WIDTH, NHID>()) {
+        return;  // the other networks run in plan_kernel
+    } else {
+    constexpr int ST = kPlanSplitTiles;
+    constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W), WIDTH / 32> NT;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n_groups = (p.n_tiles + ST - 1) / ST;
+    const long n_units = (long)p.K * n_groups;
+    const NetPtrs P = net_ptrs(p.net.base, p.net);
+    float goal[SS];
+#pragma unroll
+    for (int s = 0; s < SS; ++s) goal[s] = 2 * s + g < D_S ? p.goal[2 * s + g] : 0.0f;
+    for (long u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const int k = (int)(u / n_groups);
+        const int grp = (int)(u - (long)k * n_groups);
+        int i[ST];
+        bool valid[ST];
+        float st[ST][SS];
+#pragma unroll
+        for (int q = 0; q < ST; ++q) {
+            i[q] = (grp * ST + q) * 32 + col;
+            valid[q] = i[q] < p.N;
+#pragma unroll
+            for (int s = 0; s < SS; ++s) {
+                const int f = 2 * s + g;
+                st[q][s] = (valid[q] && f < D_S) ? p.states[(size_t)i[q] * D_S + f] : 0.0f;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+        float G[ST];
+#pragma unroll
+        for (int q = 0; q < ST; ++q) G[q] = 0.0f;
+        double disc = 1.0;
+        uint32_t wnow[ST][SW], wnext[ST][SW];
+        for (int t = 0; t < p.H; ++t) {
+            float slots[ST][NT::IN_SLOTS];
+#pragma unroll
+            for (int q = 0; q < ST; ++q) {
+#pragma unroll
+                for (int s = 0; s < NT::IN_SLOTS; ++s) slots[q][s] = 0.0f;
+#pragma unroll
+                for (int s = 0; s < SS; ++s) slots[q][s] = st[q][s];
+            }
+            if (D_A > 0) {
+                const kconst float* a = (const kconst float*)p.cands + ((size_t)k * p.H + t) * D_A;
+#pragma unroll
+                for (int s = 0; s < SA; ++s) {
+                    const float a0 = 2 * s < D_A ? a[2 * s] : 0.0f;
+                    const float a1 = 2 * s + 1 < D_A ? a[2 * s + 1] : 0.0f;
+#pragma unroll
+                    for (int q = 0; q < ST; ++q) slots[q][SS + s] = g ? a1 : a0;
+                }
+            }
+            if (p.noise) {
+#pragma unroll
+                for (int q = 0; q < ST; ++q) {
+                    const float* nsrc = p.noise + (((size_t)k * p.N + (valid[q] ? i[q] : 0)) * p.H + t) * D_W;
+#pragma unroll
+                    for (int s = 0; s < SW; ++s) {
+                        const int f = noise_feature(s, g);
+                        slots[q][SS + SA + s] = f < D_W ? nsrc[f] : 0.0f;
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+            } else {
+#pragma unroll
+                for (int q = 0; q < ST; ++q) {
+                    if ((t & 1) == 0) {
+                        philox_two_steps<SW>(wnow[q], wnext[q], p.key0, p.key1, (uint32_t)i[q],
+                                             p.crn ? 0u : (uint32_t)k, (uint32_t)t, 3u, g);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < SW; ++s) wnow[q][s] = wnext[q][s];
+                    }
+                    float nz[SW];
+                    noise_from_words<SW>(nz, wnow[q]);
+#pragma unroll
+                    for (int s = 0; s < SW; ++s) slots[q][SS + SA + s] = nz[s];
+                }
+            }
+            const float* b0 = P.b0;
+            if (N_ACT > 0) {
+                int a = ((const kconst int32_t*)p.cands)[(size_t)k * p.H + t];
+                if (a < 0 || a >= N_ACT) {
+                    if (p.status && wave == 0 && lane == 0) p.status[0] = 1;
+                    a = 0;
+                }
+                b0 += (size_t)a * p.net.b0_stride;
+            }
+            float r_cur[ST];
+#pragma unroll
+            for (int q = 0; q < ST; ++q) r_cur[q] = p.reward_at ? reward_to(st[q], goal, SS, D_S, g) : 0.0f;
+            f32x16 out[ST];
+            run_net_split_multi<NT, ST, kPlanSplitWaves, kPlanSplitDepth>(P, b0, slots, out, lane, g, wave, smem);
+#pragma unroll
+            for (int q = 0; q < ST; ++q) {
+#pragma unroll
+                for (int s = 0; s < SS; ++s) st[q][s] += out[q][s];
+                if (p.traj && wave == 0 && valid[q]) {
+                    float* dst = p.traj + (((size_t)k * p.N + i[q]) * p.H + t) * D_S;
+#pragma unroll
+                    for (int s = 0; s < SS; ++s)
+                        if (2 * s + g < D_S) dst[2 * s + g] = st[q][s];
+                }
+                const float r = p.reward_at ? r_cur[q] : reward_to(st[q], goal, SS, D_S, g);
+                G[q] = __builtin_fmaf((float)disc, r, G[q]);
+            }
+            disc *= p.gamma;
+        }
+        if (wave == 0) {
+#pragma unroll
+            for (int q = 0; q < ST; ++q) {
+                if (p.returns && g == 0 && valid[q]) p.returns[(size_t)k * p.N + i[q]] = G[q];
+                const float contrib = valid[q] ? (p.belief_w ? (float)p.belief_w[i[q]] * G[q] : G[q]) : 0.0f;
+                const float tot = sum32(contrib);
+                const int tile = grp * ST + q;
+                if (lane == 0 && tile < p.n_tiles) p.partials[(size_t)k * p.n_tiles + tile] = tot;
+            }
+        }
+    }
     }
 }
 
@@ -352,7 +508,55 @@ size_t plan_stream_lds(int shape, int dt) {
 #define PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) propose_kernel<DT, ds, dw, w, nh, pass_mode<w>()>
 #define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, pass_mode<w>()>
 
+#define PLAN_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT) plan_split_kernel<DT, ds, na, da, dw, w, nh>
+
+template <int DT, int D_S, int D_A, int D_W, int W, int NH>
+constexpr size_t plan_split_lds() {
+    if constexpr (!plan_split<DT, W, NH>()) {
+        return 0;
+    } else {
+        return (size_t)kPlanSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_S, D_A, D_W), W / 32>>::ACT;
+    }
+}
+
+bool plan_split_shape(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh) \
+    case id * 2 + 0:                           \
+        return plan_split<DT_F32, w, nh>();    \
+    case id * 2 + 1:                           \
+        return plan_split<DT_BF16, w, nh>();
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return false;
+}
+
+template <class K>
+void launch_plan_split_one(K k, size_t lds, int blocks, const PlanParams& p, hipStream_t s) {
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, blocks, 64 * kPlanSplitWaves, lds, s, p);
+}
+
 hipError_t launch_plan(int shape, int dt, const PlanParams& p, int blocks, hipStream_t s) {
+    if (plan_split_shape(shape, dt)) {
+        switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                      \
+    case id * 2 + 0:                                                                                               \
+        launch_plan_split_one(PLAN_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),                                 \
+                              plan_split_lds<DT_F32, ds, (na > 0 ? 0 : da), dw, w, nh>(), blocks, p, s);           \
+        break;                                                                                                     \
+    case id * 2 + 1:                                                                                               \
+        launch_plan_split_one(PLAN_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),                                \
+                              plan_split_lds<DT_BF16, ds, (na > 0 ? 0 : da), dw, w, nh>(), blocks, p, s);          \
+        break;
+            VOILA_SHAPES(X)
+#undef X
+            default:
+                return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     size_t lds = weights_in_lds(shape) ? p.net.bytes : plan_stream_lds(shape, dt) + (p.net.bytes - p.net.off_b0);
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
@@ -389,7 +593,26 @@ int plan_pass_tiles(int shape, int dt) {
     return 0;
 }
 
+int plan_tiles_per_unit(int shape, int dt) {
+    return plan_split_shape(shape, dt) ? kPlanSplitTiles : plan_pass_tiles(shape, dt) ? 2 : 1;
+}
+int plan_units_per_block(int shape, int dt) { return plan_split_shape(shape, dt) ? 1 : kWavesPerBlock; }
+
 int plan_blocks_per_cu(int shape, int dt) {
+    if (plan_split_shape(shape, dt)) {
+        switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                 \
+    case id * 2 + 0:                                                                                          \
+        return occupancy_t(PLAN_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), 64 * kPlanSplitWaves,          \
+                           plan_split_lds<DT_F32, ds, (na > 0 ? 0 : da), dw, w, nh>());                        \
+    case id * 2 + 1:                                                                                          \
+        return occupancy_t(PLAN_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), 64 * kPlanSplitWaves,         \
+                           plan_split_lds<DT_BF16, ds, (na > 0 ? 0 : da), dw, w, nh>());
+            VOILA_SHAPES(X)
+#undef X
+        }
+        return 1;
+    }
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
     case id * 2 + 0:                                                                                        \

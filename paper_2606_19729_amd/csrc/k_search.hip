@@ -239,8 +239,8 @@ __global__ __launch_bounds__(1024) void pw_tiles_kernel(PwParams p) {
 // x_j = l([s'_j, a_m, o_m]) / lambda, one 32-row tile of one group per wave.
 template <int DT, int D_S, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void pw_lik_kernel(PwParams p) {
-    if constexpr (!net_compiled(DT, WIDTH)) {
-        return;  // binary32 networks wider than 256 are refused at model creation
+    if constexpr (!generic_compiled(DT, WIDTH, NHID)) {
+        return;  // refused at model creation (binary32 wider than 256) or run by the split rollout kernel
     } else {
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, 0)> NTL;
     constexpr int SS = state_slots(D_S);

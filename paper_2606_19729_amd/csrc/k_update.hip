@@ -160,8 +160,8 @@ __device__ __forceinline__ void propose_tile(const NetPtrs& PT, const NetPtrs& P
 
 template <int DT, int D_S, int D_W, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void propose_kernel(ProposeParams p) {
-    if constexpr (!net_compiled(DT, WIDTH)) {
-        return;  // binary32 networks wider than 256 are refused at model creation
+    if constexpr (!generic_compiled(DT, WIDTH, NHID)) {
+        return;  // refused at model creation (binary32 wider than 256) or run by the split rollout kernel
     } else {
     constexpr bool WLDS = MODE == kResident;
     extern __shared__ __attribute__((aligned(16))) char smem[];

@@ -40,6 +40,13 @@ __device__ __forceinline__ float reward_to(const float* st, const float* goal_sl
 // Binary32 activations of a network wider than 256 do not fit in registers:
 // such networks run in bfloat16 only.
 constexpr bool net_compiled(int dt, int width) { return dt == DT_BF16 || width <= 256; }
+// The kernels that evaluate one network per wave or per block (rollouts,
+// proposals, observations, likelihoods) hold a wide network's first hidden
+// layer in registers and group the second: networks wider than 256 with
+// more than two hidden layers run in the split rollout kernel only.
+constexpr bool generic_compiled(int dt, int width, int nhid) {
+    return net_compiled(dt, width) && (width <= 256 || nhid == 2);
+}
 
 // How a kernel reads the weight fragments of a network.
 constexpr int kDirect = 0;    // straight from global memory (L2)
@@ -311,7 +318,7 @@ constexpr size_t kLdsGuess = 32 * 1024;
 // buffers (and the first layer of a grouped wide network).
 template <int DT, int D_S, int N_ACT, int D_AIN, int D_W, int WIDTH, int NHID>
 constexpr size_t stream_lds_of() {
-    if constexpr (!net_compiled(DT, WIDTH) || WIDTH <= 64) {
+    if constexpr (!generic_compiled(DT, WIDTH, NHID) || WIDTH <= 64) {
         return kStreamLds;
     } else {
         typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_AIN, D_W)> NT;

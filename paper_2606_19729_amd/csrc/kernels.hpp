@@ -14,9 +14,10 @@ namespace voila {
     X(0, 4, 5, 0, 4, 2, 2, 64, 2)     /* small */        \
     X(1, 16, 0, 4, 16, 32, 32, 256, 3) /* realistic */    \
     X(2, 4, 0, 4, 4, 2, 2, 64, 2)      /* small, continuous actions */ \
-    X(3, 4, 5, 0, 4, 2, 2, 1024, 2)    /* small, hidden width 1024 */
+    X(3, 4, 5, 0, 4, 2, 2, 1024, 2)    /* small, hidden width 1024 */ \
+    X(4, 4, 5, 0, 4, 2, 2, 1024, 4)    /* small, four hidden layers of 1024 (transition network only) */
 
-constexpr int kNumShapes = 4;
+constexpr int kNumShapes = 5;
 
 struct ShapeInfo {
     int d_s, n_actions, d_a, d_w, d_o, d_wz, width, n_hidden;
@@ -400,6 +401,11 @@ int propose_batch_blocks_per_cu(int shape, int dt, int waves_per_block, size_t l
 // 32-particle tiles per wave, weights in pass-major order), 0 when the shape
 // runs one tile per wave in the layer-major order.
 int plan_pass_tiles(int shape, int dt);
+// Rollout work units: 32-particle tiles per unit (1, 2 for the paired
+// evaluation, or the split kernel's tiles per block) and units per block.
+int plan_tiles_per_unit(int shape, int dt);
+int plan_units_per_block(int shape, int dt);
+bool plan_split_shape(int shape, int dt);
 
 // Resident blocks per CU of the plan / propose / observe kernels.
 int plan_blocks_per_cu(int shape, int dt);
