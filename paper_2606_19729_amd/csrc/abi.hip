@@ -109,7 +109,7 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
     const size_t off_fo = off_fh + (size_t)(NHID - 1) * nfh * fb;
     // networks streamed whole through LDS chunk buffers are padded to whole chunks
     const size_t nfr = nf0 + (size_t)(NHID - 1) * nfh + nfo;
-    const size_t fpc = VOILA_STREAM_CHB / fb;
+    const size_t fpc = kStreamPadBytes / fb;
     const size_t pad = (W > 64 && CT == HT) ? (nfr + fpc - 1) / fpc * fpc - nfr : 0;
     const size_t off_b0 = align_up(off_fo + (nfo + pad) * fb, 16);
     const size_t off_bh = align_up(off_b0 + (size_t)n_var * W * 4, 16);

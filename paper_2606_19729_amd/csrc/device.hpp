@@ -59,6 +59,17 @@ constexpr int DT_BF16 = 1;
 #ifndef VOILA_STREAM_NBUF
 #define VOILA_STREAM_NBUF 2
 #endif
+// Chunk bytes of the rollout kernel's stream (its single workgroup per CU
+// has the LDS for two 64 KB buffers: half the barriers of 32 KB chunks);
+// packed networks are padded to whole chunks of the larger size.
+#ifndef VOILA_PLAN_STREAM_CHB
+#define VOILA_PLAN_STREAM_CHB 65536
+#endif
+constexpr int kStreamPadBytes = VOILA_PLAN_STREAM_CHB > VOILA_STREAM_CHB ? VOILA_PLAN_STREAM_CHB : VOILA_STREAM_CHB;
+#ifndef VOILA_STREAM_REGS
+#define VOILA_STREAM_REGS 0
+#endif
+constexpr bool kStreamRegs = VOILA_STREAM_REGS != 0;
 constexpr int kPfDepth = VOILA_PF_DEPTH;
 #ifndef VOILA_PF_DEPTH_F32
 #define VOILA_PF_DEPTH_F32 6
@@ -280,6 +291,12 @@ template <int HT> struct Act<DT_BF16, HT> {
         v[2 * t] = relu_bf16x8(acc[t], 0);
         v[2 * t + 1] = relu_bf16x8(acc[t], 1);
     }
+    // values 2 j and 2 j + 1 of accumulator tile `a` as the ReLU'd pair j of tile t
+    __device__ __forceinline__ void set_relu_pair(const f32x16& a, int t, int j) {
+        u32x4 w = __builtin_bit_cast(u32x4, v[2 * t + j / 4]);
+        w[j % 4] = relu_bf16x2(a[2 * j], a[2 * j + 1]);
+        v[2 * t + j / 4] = __builtin_bit_cast(bf16x8, w);
+    }
     __device__ __forceinline__ bf16x8 b(int c) const { return v[c]; }
 };
 
@@ -373,9 +390,34 @@ struct StreamSrc {
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) round(r);
     }
-    __device__ __forceinline__ void start() {
+    // Register-staged form (kStreamRegs): this wave's quarter of the chunk
+    // after next is loaded into registers while the current chunk is read and
+    // written to LDS one round at a time during the next chunk, at the
+    // positions the direct-to-LDS rounds take.  With no LDS DMA in flight the
+    // compiler's LDS waits before each matrix instruction count only the
+    // fragment reads issued after the one it needs (a pending DMA makes them
+    // wait for every outstanding LDS operation).
+    static constexpr bool REGS = kStreamRegs;
+    static_assert(!REGS || NBUF == 2, "register staging alternates two chunk buffers");
+    u32x4 stage[REGS ? ROUNDS : 1];
+    __device__ __forceinline__ void load_stage(int ch) {
+        const char* base = lsrc + opaque_u32((uint32_t)(ch * CHB));
 #pragma unroll
-        for (int j = 0; j < NBUF - 1; ++j) fetch(j, j);
+        for (int r = 0; r < ROUNDS; ++r) stage[r] = *reinterpret_cast<const u32x4*>(base + r * kWaves * 1024);
+    }
+    __device__ __forceinline__ void start() {
+        if constexpr (REGS) {
+            const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            const int lane = threadIdx.x & 63;
+            load_stage(0);
+#pragma unroll
+            for (int r = 0; r < ROUNDS; ++r)
+                *reinterpret_cast<u32x4*>(lds + (r * kWaves + wave) * 1024 + lane * 16) = stage[r];
+            load_stage(NCH > 1 ? 1 : 0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < NBUF - 1; ++j) fetch(j, j);
+        }
     }
     // At the first fragment of a chunk: wait until only this wave's loads of
     // the NBUF - 2 newer chunks are outstanding and its LDS reads are done,
@@ -389,6 +431,28 @@ struct StreamSrc {
     int nxt_ch = 0;
     __device__ __forceinline__ typename Frag<N::DT>::type load(int f, int lane) {
         const int ch = f / FPC, within = f % FPC;
+        if constexpr (REGS) {
+            if (within == 0) {
+                // this wave's writes of the chunk are done and its reads of
+                // the other buffer; after the barrier, everyone's are
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(63));
+                __builtin_amdgcn_s_barrier();
+                cur = cur + 1 == NBUF ? 0 : cur + 1;
+            }
+            const int served = ch == NCH - 1 ? LASTF : FPC;
+            const int ahead = (ch + 2) % NCH;
+#pragma unroll
+            for (int r = 0; r < ROUNDS; ++r) {
+                if ((r * served) / ROUNDS != within) continue;
+                const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+                const int off = (r * kWaves + wave) * 1024;
+                *reinterpret_cast<u32x4*>(lds + (cur ^ 1) * CHB + off + lane * 16) = stage[r];
+                stage[r] = *reinterpret_cast<const u32x4*>(
+                    lsrc + opaque_u32((uint32_t)(ahead * CHB + r * kWaves * 1024)));
+            }
+            if (within % WIN == 0) win = lds + cur * CHB + opaque_zero();
+            return Frag<N::DT>::load(win, within, lane);
+        }
         if (within == 0) {
             __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NBUF - 2) * ROUNDS));
             __builtin_amdgcn_s_barrier();
@@ -677,13 +741,13 @@ struct GroupStream {
 
 // Bytes of one LDS chunk buffer of a streaming network source.
 // The streaming source of a network evaluated layer by layer.
-template <class N>
-using StreamFor = StreamSrc<N>;
+template <class N, int CHB = VOILA_STREAM_CHB>
+using StreamFor = StreamSrc<N, CHB>;
 
-template <class N, bool G = (N::CT < N::HT)> struct StreamChunk {
-    static constexpr int BYTES = StreamFor<N>::LDS_BYTES;  // LDS of the chunk buffers
+template <class N, int CHB = VOILA_STREAM_CHB, bool G = (N::CT < N::HT)> struct StreamChunk {
+    static constexpr int BYTES = StreamFor<N, CHB>::LDS_BYTES;  // LDS of the chunk buffers
 };
-template <class N> struct StreamChunk<N, true> {
+template <class N, int CHB> struct StreamChunk<N, CHB, true> {
     static constexpr int BYTES = GroupStream<N>::LDS_BYTES;
 };
 
@@ -972,6 +1036,146 @@ __device__ __forceinline__ void run_net_passes(Src& src, const NetPtrs& P, const
     for (int st = 0; st < ST; ++st) out[st] = o[st][0];
 }
 
+// run_net_passes as one pipelined sequence (bfloat16): the fragments are
+// consumed in stream order with a single register ring that prefetches
+// across pass and layer boundaries; the ReLU / bfloat16 conversion of each
+// finished pass is spread over the matrix instructions of the pass that
+// follows it (accumulators double-buffered by pass), so that the vector
+// instructions issue in the shadow of the matrix core; and the biases of
+// the next pass are read LEAD fragment-steps before it starts.  The
+// conversion of a layer's last pass completes before the next layer's first
+// k-step that reads it.  Same products, in the same order, as run_net_passes.
+#ifndef VOILA_FLAT_DEPTH
+#define VOILA_FLAT_DEPTH 3
+#endif
+#ifndef VOILA_FLAT_VALU
+#define VOILA_FLAT_VALU 4
+#endif
+#ifndef VOILA_FLAT_LEAD
+#define VOILA_FLAT_LEAD 4
+#endif
+template <class N, int RP, int LEAD>
+struct FlatSeq {
+    static constexpr int NP = N::HT / RP;
+    static constexpr int NQ = N::NHID * NP;  // hidden-producing passes; pass NQ is the output layer
+    static constexpr int NFR = N::NF0 + (N::NHID - 1) * N::NFH + N::NFO;
+    static constexpr int OUT0 = N::NF0 + (N::NHID - 1) * N::NFH;  // first output-layer fragment
+    static constexpr int KPT = 32 / (2 * N::KPER);                // k-steps per 32-row tile
+    // layer, pass, k-step and output tile of fragment f (output layer: layer NHID, pass 0, tile 0)
+    __host__ __device__ static constexpr int layer(int f) {
+        return f < N::NF0 ? 0 : f >= OUT0 ? N::NHID : 1 + (f - N::NF0) / N::NFH;
+    }
+    __host__ __device__ static constexpr int rel(int f) {
+        return f < N::NF0 ? f : f >= OUT0 ? f - OUT0 : (f - N::NF0) % N::NFH;
+    }
+    __host__ __device__ static constexpr int ks(int f) { return layer(f) == 0 ? N::IN_KS : N::HID_KS; }
+    __host__ __device__ static constexpr int pass(int f) { return f >= OUT0 ? 0 : rel(f) / (ks(f) * RP); }
+    __host__ __device__ static constexpr int kstep(int f) { return f >= OUT0 ? rel(f) : (rel(f) / RP) % ks(f); }
+    __host__ __device__ static constexpr int tile(int f) { return f >= OUT0 ? 0 : rel(f) % RP; }
+    __host__ __device__ static constexpr int gpass(int f) { return layer(f) * NP + pass(f); }
+    // first fragment and length (fragment-steps) of global pass q
+    __host__ __device__ static constexpr int pass_start(int q) {
+        return q / NP == 0 ? (q % NP) * N::IN_KS * RP
+               : q >= NQ   ? OUT0
+                           : N::NF0 + (q / NP - 1) * N::NFH + (q % NP) * N::HID_KS * RP;
+    }
+    __host__ __device__ static constexpr int pass_len(int q) {
+        return q >= NQ ? N::NFO : (q / NP == 0 ? N::IN_KS : N::HID_KS) * RP;
+    }
+    // fragment-step of pass q at which the biases of pass q + 1 are read
+    __host__ __device__ static constexpr int bias_at(int q) { return pass_len(q) > LEAD ? pass_len(q) - LEAD : 0; }
+    // fragment-steps of pass q + 1 over which pass q (q < NQ) is converted:
+    // before pass q + 1 reads the biases of pass q + 2 into pass q's
+    // accumulators, and before the next layer first reads pass q's tiles
+    __host__ __device__ static constexpr int window(int q) {
+        const int w = (q + 1) % NP != 0 ? pass_len(q + 1)
+                      : KPT * RP * (NP - 1) * ((q + 1) >= NQ ? 1 : RP);
+        return q + 2 < NQ && bias_at(q + 1) < w ? (bias_at(q + 1) > 0 ? bias_at(q + 1) : 1) : w;
+    }
+};
+
+template <class N, int ST, int RP, class Src>
+__device__ __forceinline__ void run_net_flat(Src& src, const NetPtrs& P, const float* b0,
+                                             const float (&slots)[ST][N::IN_SLOTS], f32x16 (&out)[ST], int lane,
+                                             int g) {
+    static_assert(N::DT == DT_BF16 && N::CT == N::HT && N::HT % RP == 0 && N::NHID >= 2,
+                  "flat evaluation needs a layered bfloat16 network");
+    typedef typename Frag<N::DT>::type FT;
+    typedef FlatSeq<N, RP, VOILA_FLAT_LEAD> Q;
+    constexpr int NP = Q::NP, NQ = Q::NQ, NFR = Q::NFR;
+    constexpr int PF = (VOILA_FLAT_DEPTH - 1) * RP;
+    constexpr int R = PF + 1;
+    constexpr int NPAIR = ST * RP * 8;  // converted value pairs per pass
+    static_assert(NP >= 2, "a layer's last pass is converted while the next layer reads its first tiles");
+    Act<N::DT, N::HT> A[2][ST];
+    f32x16 acc[2][ST][RP];
+    f32x16 o[ST];
+    FT ring[R];
+    // the biases of pass q into its accumulators
+    auto bias_of = [&](auto qi) {
+        constexpr int q = decltype(qi)::value;
+        if constexpr (q < NQ) {
+            const float* bias = (q / NP == 0 ? b0 : P.bh + (q / NP - 1) * N::WIDTH) + 32 * RP * (q % NP);
+#pragma unroll
+            for (int st = 0; st < ST; ++st) init_bias<RP>(acc[q % 2][st], bias + opaque_zero(), g);
+        } else {
+            f32x16 ob[1];
+            init_bias<1>(ob, P.bo + opaque_zero(), g);
+#pragma unroll
+            for (int st = 0; st < ST; ++st) o[st] = ob[0];
+        }
+    };
+    bias_of(std::integral_constant<int, 0>{});
+    static_for<PF>([&](auto fi) {
+        constexpr int f = decltype(fi)::value;
+        ring[f % R] = src.load(f, lane);
+    });
+    static_for<NFR>([&](auto fi) {
+        constexpr int f = decltype(fi)::value;
+        constexpr int L = Q::layer(f), c = Q::kstep(f), t = Q::tile(f);
+        constexpr bool OUT = L == N::NHID;
+        constexpr int q = Q::gpass(f);
+        constexpr int s0 = f - Q::pass_start(q);  // fragment-step within the pass
+        // conversion of the previous pass q - 1 into the activations of its
+        // layer (before this step's bias reads, which may reuse its registers)
+        if constexpr (q >= 1) {
+            constexpr int qc = q - 1;
+            constexpr int W = Q::window(qc);
+            constexpr int PPS = (NPAIR + W - 1) / W;
+            if constexpr (s0 < W) {
+                constexpr int Lc = qc / NP, pc = qc % NP;
+                static_for<PPS>([&](auto ji) {
+                    constexpr int j = s0 * PPS + decltype(ji)::value;
+                    if constexpr (j < NPAIR) {
+                        constexpr int st = j / (RP * 8), tt = (j / 8) % RP, pr = j % 8;
+                        A[Lc % 2][st].set_relu_pair(acc[qc % 2][st][tt], RP * pc + tt, pr);
+                    }
+                });
+            }
+        }
+        if constexpr (q < NQ && s0 == Q::bias_at(q)) bias_of(std::integral_constant<int, q + 1>{});
+        if constexpr (f + PF < NFR) ring[(f + PF) % R] = src.load(f + PF, lane);
+        static_for<ST>([&](auto si) {
+            constexpr int st = decltype(si)::value;
+            if constexpr (L == 0) {
+                acc[q % 2][st][t] = mfma(ring[f % R], Slots<N::DT, N::IN_SLOTS>::b(slots[st], c), acc[q % 2][st][t]);
+            } else if constexpr (!OUT) {
+                acc[q % 2][st][t] = mfma(ring[f % R], A[(L - 1) % 2][st].b(c), acc[q % 2][st][t]);
+            } else {
+                o[st] = mfma(ring[f % R], A[(L - 1) % 2][st].b(c), o[st]);
+            }
+        });
+        __builtin_amdgcn_sched_group_barrier(kSchedReads, 1, 0);
+        static_for<ST>([&](auto) {
+            __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, VOILA_FLAT_VALU, 0);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+    });
+#pragma unroll
+    for (int st = 0; st < ST; ++st) out[st] = o[st];
+}
+
 // Split evaluation of ST sample tiles by the NW waves of a block: wave w
 // computes output tiles [w HT/NW, (w+1) HT/NW) of every layer for all ST
 // sample tiles, so each weight fragment read from L2 serves ST tiles.  The
@@ -1065,8 +1269,11 @@ template <class N> struct DirectFor<N, true> {
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32) gives
+        // both halves, where separate high and low products take two
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;

@@ -121,7 +121,11 @@ constexpr bool plan_pairs() {
 #ifndef VOILA_PLAN_PASS_TILES
 #define VOILA_PLAN_PASS_TILES 2
 #endif
-constexpr int kPlanPassTiles = VOILA_PLAN_PASS_TILES;  // output tiles per pass of the paired evaluation
+constexpr int kPlanPassTiles = VOILA_PLAN_PASS_TILES;
+#ifndef VOILA_PLAN_FLAT
+#define VOILA_PLAN_FLAT 1
+#endif
+constexpr size_t kPlanStreamLds = (size_t)VOILA_STREAM_NBUF * VOILA_PLAN_STREAM_CHB;  // output tiles per pass of the paired evaluation
 
 // The unit of plan_unit for two tiles (2 tp, 2 tp + 1) of one candidate:
 // every weight fragment feeds both tiles' products.
@@ -214,7 +218,11 @@ __device__ __forceinline__ void plan_unit_pair(Src& src, const NetPtrs& P, const
 #pragma unroll
             for (int q = 0; q < ST; ++q) r_cur[q] = reward_to(st[q], goal, SS, D_S, g);
         f32x16 out[ST];
+#if VOILA_PLAN_FLAT
+        run_net_flat<NT, ST, kPlanPassTiles>(src, P, b0, slots, out, lane, g);
+#else
         run_net_passes<NT, ST, kPlanPassTiles>(src, P, b0, slots, out, lane, g);
+#endif
 #pragma unroll
         for (int q = 0; q < ST; ++q) {
 #pragma unroll
@@ -251,7 +259,7 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
     const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6;
     constexpr bool PAIRS = plan_pairs<DT, WIDTH, NHID>();
     const long n_units = (long)p.K * (PAIRS ? (p.n_tiles + 1) / 2 : p.n_tiles);
-    with_weights<NT, MODE, (N_ACT > 0 ? N_ACT : 1)>(smem, p.net, [&](auto& src, const NetPtrs& P) {
+    with_weights<NT, MODE, (N_ACT > 0 ? N_ACT : 1), VOILA_PLAN_STREAM_CHB>(smem, p.net, [&](auto& src, const NetPtrs& P) {
         // block-uniform loop: every wave of a block walks the same sequence of
         // (unit, step) iterations, idle waves on a masked dummy unit
         for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
@@ -497,9 +505,9 @@ size_t plan_stream_lds(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                      \
     case id * 2 + 0:                                                               \
-        return stream_lds_of<DT_F32, ds, na, (na > 0 ? 0 : da), dw, w, nh>();            \
+        return stream_lds_of<DT_F32, ds, na, (na > 0 ? 0 : da), dw, w, nh, VOILA_PLAN_STREAM_CHB>(); \
     case id * 2 + 1:                                                               \
-        return stream_lds_of<DT_BF16, ds, na, (na > 0 ? 0 : da), dw, w, nh>();
+        return stream_lds_of<DT_BF16, ds, na, (na > 0 ? 0 : da), dw, w, nh, VOILA_PLAN_STREAM_CHB>();
         VOILA_SHAPES(X)
 #undef X
     }
@@ -616,9 +624,9 @@ int plan_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
     case id * 2 + 0:                                                                                        \
-        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kStreamLds); \
+        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kPlanStreamLds); \
     case id * 2 + 1:                                                                                        \
-        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kStreamLds);
+        return occupancy(PLAN_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kPlanStreamLds);
         VOILA_SHAPES(X)
 #undef X
     }

@@ -60,7 +60,7 @@ constexpr int kSplit = 3;     // the four waves of a block split each layer of o
 // biases -- and for a grouped wide network the first layer -- staged after
 // them (kStream), or read from L2 (kDirect).  B0_ROWS is the number of
 // first-layer bias rows the blob carries (one per discrete action).
-template <class NT, int MODE, int B0_ROWS, class Body>
+template <class NT, int MODE, int B0_ROWS, int CHB = VOILA_STREAM_CHB, class Body>
 __device__ __forceinline__ void with_weights(char* smem, const NetBlob& net, Body&& body) {
     if (MODE == kResident) {
         stage_blob(smem, net.base, net.bytes);
@@ -70,7 +70,7 @@ __device__ __forceinline__ void with_weights(char* smem, const NetBlob& net, Bod
     constexpr bool F0_LDS = NT::CT < NT::HT && first_layer_in_lds<NT>(B0_ROWS);
     char* extra = smem;
     if constexpr (MODE == kStream) {
-        extra = smem + StreamChunk<NT>::BYTES;
+        extra = smem + StreamChunk<NT, CHB>::BYTES;
         const uint32_t f0_bytes = F0_LDS ? (uint32_t)(NT::NF0 * NT::FRAG_BYTES) : 0u;
         if (f0_bytes) stage_blob(extra, P.f0, f0_bytes);
         char* bias = extra + f0_bytes;
@@ -88,7 +88,7 @@ __device__ __forceinline__ void with_weights(char* smem, const NetBlob& net, Bod
         body(src, P);
         src.hid.finish();
     } else if constexpr (MODE == kStream) {
-        StreamFor<NT> src(smem, P.f0);
+        StreamFor<NT, CHB> src(smem, P.f0);
         src.start();
         body(src, P);
         src.finish();
@@ -316,13 +316,13 @@ constexpr size_t kLdsGuess = 32 * 1024;
 
 // LDS of a streaming rollout kernel before its staged biases: the two chunk
 // buffers (and the first layer of a grouped wide network).
-template <int DT, int D_S, int N_ACT, int D_AIN, int D_W, int WIDTH, int NHID>
+template <int DT, int D_S, int N_ACT, int D_AIN, int D_W, int WIDTH, int NHID, int CHB = VOILA_STREAM_CHB>
 constexpr size_t stream_lds_of() {
     if constexpr (!generic_compiled(DT, WIDTH, NHID) || WIDTH <= 64) {
-        return kStreamLds;
+        return (size_t)VOILA_STREAM_NBUF * CHB;
     } else {
         typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_AIN, D_W)> NT;
-        return (size_t)StreamChunk<NT>::BYTES +
+        return (size_t)StreamChunk<NT, CHB>::BYTES +
                (NT::CT < NT::HT && first_layer_in_lds<NT>(N_ACT > 0 ? N_ACT : 1) ? (size_t)NT::NF0 * NT::FRAG_BYTES
                                                                                 : 0);
     }
