@@ -66,10 +66,6 @@ constexpr int DT_BF16 = 1;
 #define VOILA_PLAN_STREAM_CHB 65536
 #endif
 constexpr int kStreamPadBytes = VOILA_PLAN_STREAM_CHB > VOILA_STREAM_CHB ? VOILA_PLAN_STREAM_CHB : VOILA_STREAM_CHB;
-#ifndef VOILA_STREAM_REGS
-#define VOILA_STREAM_REGS 0
-#endif
-constexpr bool kStreamRegs = VOILA_STREAM_REGS != 0;
 constexpr int kPfDepth = VOILA_PF_DEPTH;
 #ifndef VOILA_PF_DEPTH_F32
 #define VOILA_PF_DEPTH_F32 6
@@ -390,34 +386,9 @@ struct StreamSrc {
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) round(r);
     }
-    // Register-staged form (kStreamRegs): this wave's quarter of the chunk
-    // after next is loaded into registers while the current chunk is read and
-    // written to LDS one round at a time during the next chunk, at the
-    // positions the direct-to-LDS rounds take.  With no LDS DMA in flight the
-    // compiler's LDS waits before each matrix instruction count only the
-    // fragment reads issued after the one it needs (a pending DMA makes them
-    // wait for every outstanding LDS operation).
-    static constexpr bool REGS = kStreamRegs;
-    static_assert(!REGS || NBUF == 2, "register staging alternates two chunk buffers");
-    u32x4 stage[REGS ? ROUNDS : 1];
-    __device__ __forceinline__ void load_stage(int ch) {
-        const char* base = lsrc + opaque_u32((uint32_t)(ch * CHB));
-#pragma unroll
-        for (int r = 0; r < ROUNDS; ++r) stage[r] = *reinterpret_cast<const u32x4*>(base + r * kWaves * 1024);
-    }
     __device__ __forceinline__ void start() {
-        if constexpr (REGS) {
-            const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-            const int lane = threadIdx.x & 63;
-            load_stage(0);
 #pragma unroll
-            for (int r = 0; r < ROUNDS; ++r)
-                *reinterpret_cast<u32x4*>(lds + (r * kWaves + wave) * 1024 + lane * 16) = stage[r];
-            load_stage(NCH > 1 ? 1 : 0);
-        } else {
-#pragma unroll
-            for (int j = 0; j < NBUF - 1; ++j) fetch(j, j);
-        }
+        for (int j = 0; j < NBUF - 1; ++j) fetch(j, j);
     }
     // At the first fragment of a chunk: wait until only this wave's loads of
     // the NBUF - 2 newer chunks are outstanding and its LDS reads are done,
@@ -431,28 +402,6 @@ struct StreamSrc {
     int nxt_ch = 0;
     __device__ __forceinline__ typename Frag<N::DT>::type load(int f, int lane) {
         const int ch = f / FPC, within = f % FPC;
-        if constexpr (REGS) {
-            if (within == 0) {
-                // this wave's writes of the chunk are done and its reads of
-                // the other buffer; after the barrier, everyone's are
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(63));
-                __builtin_amdgcn_s_barrier();
-                cur = cur + 1 == NBUF ? 0 : cur + 1;
-            }
-            const int served = ch == NCH - 1 ? LASTF : FPC;
-            const int ahead = (ch + 2) % NCH;
-#pragma unroll
-            for (int r = 0; r < ROUNDS; ++r) {
-                if ((r * served) / ROUNDS != within) continue;
-                const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-                const int off = (r * kWaves + wave) * 1024;
-                *reinterpret_cast<u32x4*>(lds + (cur ^ 1) * CHB + off + lane * 16) = stage[r];
-                stage[r] = *reinterpret_cast<const u32x4*>(
-                    lsrc + opaque_u32((uint32_t)(ahead * CHB + r * kWaves * 1024)));
-            }
-            if (within % WIN == 0) win = lds + cur * CHB + opaque_zero();
-            return Frag<N::DT>::load(win, within, lane);
-        }
         if (within == 0) {
             __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0((NBUF - 2) * ROUNDS));
             __builtin_amdgcn_s_barrier();
