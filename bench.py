@@ -28,11 +28,58 @@ METRIC = "generator rollout steps/s + belief-update particles/s, BF16 vs FP32 at
 PEAK_F32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 
-# HBM bytes per launch of the f32 rollout kernel from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE passes (scaled by the counters' reading of a copy kernel of known
-# size, see profiles/plan_kernel_f32_realistic.md), valid only for the kernel
-# sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256_16": "2c1443b9b62cd03c", "bytes": (11025 + 1024) * 1024}
+# rocprofv3 counters of the hot kernels, valid only for the kernel sources
+# they were taken on (the commands and raw figures are under profiles/):
+#   mfma_busy      SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs)
+#   valu_per_mfma  (SQ_INSTS_VALU - SQ_INSTS_MFMA) / SQ_INSTS_MFMA
+#   valu_issue     (SQ_INSTS_VALU - SQ_INSTS_MFMA) x 4 cycles / (launch cycles at 2.4 GHz x 1024 SIMDs):
+#                  the share of the SIMDs' issue time the vector instructions alone take
+#   hbm_bytes      FETCH_SIZE x 2 + WRITE_SIZE per launch (the factors are what the two
+#                  counters read for an elementwise kernel of 256 MiB in + 256 MiB out)
+MEASURED = {
+    "sources_sha256_16": "60974281fb835626",
+    "kernels": {
+        "plan_kernel f32 realistic": {"mfma_busy": 0.890, "valu_per_mfma": 0.54, "valu_issue": 0.03,
+                                      "hbm_bytes": (5620 * 2 + 1024) * 1024},
+        "plan_kernel bf16 realistic": {"mfma_busy": 0.581, "valu_per_mfma": 3.78, "valu_issue": 0.22,
+                                       "hbm_bytes": (4260 * 2 + 512) * 1024},
+        "plan_batch_kernel bf16": {"mfma_busy": 0.441, "valu_per_mfma": 11.37, "valu_issue": 0.57,
+                                   "valu_per_tile_step": 160, "mfma_per_tile_step": 14.0,
+                                   "hbm_bytes": (87168 * 2 + 74716) * 1024},
+        "plan_kernel bf16 width 1024": {"mfma_busy": 0.599, "valu_per_mfma": 1.65, "valu_issue": 0.11,
+                                        "hbm_bytes": (9541 * 2 + 1024) * 1024},
+        "plan_split_kernel bf16 4 x 1024": {"mfma_busy": 0.448, "valu_per_mfma": 2.01, "valu_issue": 0.10,
+                                            "l2_hit": 0.808, "hbm_bytes": (206248000 * 2 + 11713351) * 1024},
+        "observe_kernel f32 realistic rollouts": {"mfma_busy": 0.849, "valu_per_mfma": 0.60},
+        "observe_kernel bf16 realistic rollouts": {"mfma_busy": 0.336, "valu_per_mfma": 4.40},
+        "nce_wide_bwd_kernel f32": {"mfma_busy": 0.709, "valu_per_mfma": 0.77},
+        "nce_wide_wgrad_kernel f32": {"mfma_busy": 0.547, "valu_per_mfma": 0.91},
+        "nce_wide_bwd_kernel bf16": {"mfma_busy": 0.144, "valu_per_mfma": 7.23},
+        "nce_wide_wgrad_kernel bf16": {"mfma_busy": 0.108, "valu_per_mfma": 12.35},
+        "ddim_split_kernel 5 x 1024": {"mfma_busy": 0.474, "valu_per_mfma": 1.85},
+        "ddim_split_kernel 5 x 512": {"mfma_busy": 0.436, "valu_per_mfma": 2.75},
+        "lg_resample_kernel 2^24": {"hbm_bytes": (544301 * 2 + 1114112) * 1024},
+    },
+}
+
+
+# rocprofv3 figures attached to each bench section
+SECTION_COUNTERS = {
+    "batched": ["plan_batch_kernel bf16"],
+    "wide_bf16": ["plan_kernel bf16 width 1024"],
+    "deep_bf16": ["plan_split_kernel bf16 4 x 1024"],
+    "plan_observe": ["observe_kernel f32 realistic rollouts", "observe_kernel bf16 realistic rollouts"],
+    "info_nce": ["nce_wide_bwd_kernel f32", "nce_wide_wgrad_kernel f32", "nce_wide_bwd_kernel bf16",
+                 "nce_wide_wgrad_kernel bf16"],
+    "ddim": ["ddim_split_kernel 5 x 1024", "ddim_split_kernel 5 x 512"],
+}
+
+
+def measured(kernel):
+    """The rocprofv3 figures of `kernel`, or None once the kernel sources changed."""
+    if kernel_sources_hash() != MEASURED["sources_sha256_16"]:
+        return None
+    return MEASURED["kernels"][kernel]
 
 
 def kernel_sources_hash():
@@ -632,7 +679,8 @@ def bench_update_sweep(V, torch, reps):
         torch.cuda.synchronize()
         copy_gbs = 2.0 * src.numel() * 4 / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
         out.append({"N": N, "ms": ms, "particles_per_s": N / (ms / 1e3), "algorithmic_GB_per_s": gbs,
-                    "hbm_frac": gbs / 8000.0, "copy_GB_per_s": copy_gbs, "frac_of_copy": gbs / copy_gbs})
+                    "hbm_frac": gbs / 8000.0, "copy_GB_per_s": copy_gbs, "frac_of_copy": gbs / copy_gbs,
+                    "counters": measured("lg_resample_kernel 2^24") if lg == 24 else None})
     return out
 
 
@@ -775,8 +823,8 @@ def main():
         "update_particles_per_s": N / (upd_ms / 1000.0),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_F32_TFLOPS,
-                     "traffic": MEASURED_TRAFFIC["bytes"]
-                     if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"] else None,
+                     "traffic": (measured("plan_kernel f32 realistic") or {}).get("hbm_bytes"),
+                     "counters": measured("plan_kernel f32 realistic"),
                      "kernel": "plan_kernel (f32, realistic)",
                      "flop_per_rollout_step": trans_flops_per_step(w.model),
                      "rollout_steps_per_launch": steps_per_step},
@@ -803,7 +851,8 @@ def main():
         result["bf16"] = {"plan_steps_per_s": steps_per_step / (bms / 1000.0), "plan_ms": bms,
                           "speedup_vs_f32_plan": plan_ms / bms,
                           "max_rel_q_diff_vs_f32": float(np.max(np.abs(qbh - qf) / np.abs(qf))),
-                          "roofline_frac_bf16_peak": flops / (bms / 1000.0) / 1e12 / PEAK_BF16_TFLOPS}
+                          "roofline_frac_bf16_peak": flops / (bms / 1000.0) / 1e12 / PEAK_BF16_TFLOPS,
+                          "counters": measured("plan_kernel bf16 realistic")}
         print(f"[bench] bf16 plan {bms:.2f} ms", file=sys.stderr, flush=True)
 
     sections = [
@@ -830,6 +879,9 @@ def main():
             if want(name):
                 print(f"[bench] {title}", file=sys.stderr, flush=True)
                 result[key] = fn()
+                for sect, kernels in SECTION_COUNTERS.items():
+                    if sect == key and isinstance(result[key], dict):
+                        result[key]["counters"] = {k: measured(k) for k in kernels}
 
     if not args.no_extras and want("gemm"):
         print("[bench] library GEMM reference (matrix-core peak re-measured)", file=sys.stderr, flush=True)
