@@ -541,6 +541,8 @@ def bench_ddim(V, torch, reps):
                      "mfma_frac": f_eval * N * n_steps / (t / 1e3) / 1e12 / PEAK_BF16_TFLOPS}
         print(f"[bench]   {name}: {t:.3f} ms", file=sys.stderr, flush=True)
     out["distilled_over_teacher"] = out["distilled_4x1024"]["samples_per_s"] / out["teacher_5x1024"]["samples_per_s"]
+    out["precision_note"] = ("teacher and distilled shape both in bfloat16 (binary32 accumulation); the paper "
+                             "states no precision for its 283x")
     return out
 
 
