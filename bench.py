@@ -186,7 +186,7 @@ def bench_deep(V, torch, reps):
     candidates x 4096 particles x 20 steps."""
     import workloads
     dev = torch.device("cuda", 0)
-    w = workloads.deep(seed=8, N=4096, K=256, H=20)
+    w = workloads.deep(seed=8, N=4096, K=256, H=20, with_obs=True)
     mb = V.Model(w.model, compute="bf16")
     S = torch.as_tensor(w.states, device=dev)
     C = torch.as_tensor(w.cands, device=dev)
@@ -205,10 +205,25 @@ def bench_deep(V, torch, reps):
     steps = w.K * w.N * w.H
     fps = trans_flops_per_step(w.model)
     tflops = fps * steps / (ms / 1e3) / 1e12
+    # per-step observations through the observation network of the same depth
+    _, traj = V.plan(mb, S, C, w.gamma, w.goal, seed=w.plan_seed, q_out=q, workspace=ws, return_traj=True)
+    obs = V.plan_observe(mb, traj, C, seed=w.plan_seed)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for r in range(reps):
+        V.plan_observe(mb, traj, C, seed=w.plan_seed, out=obs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    oms = e0.elapsed_time(e1) / reps
+    # [s', w_Z] -> 1024 x 4 -> o, the one-hot action folded into the bias row
+    ofl = 2 * ((w.model.d_s + w.model.d_wz) * 1024 + 3 * 1024 * 1024 + 1024 * w.model.d_o)
+    otf = ofl * steps / (oms / 1e3) / 1e12
     mb.close()
     return {"K": w.K, "N": w.N, "H": w.H, "hidden": [1024] * 4, "plan_ms": ms,
             "rollout_steps_per_s": steps / (ms / 1e3), "achieved_tflops": tflops,
-            "mfma_frac_bf16_peak": tflops / PEAK_BF16_TFLOPS, "flop_per_rollout_step": fps}
+            "mfma_frac_bf16_peak": tflops / PEAK_BF16_TFLOPS, "flop_per_rollout_step": fps,
+            "observe": {"ms": oms, "observations_per_s": steps / (oms / 1e3), "flop_per_observation": ofl,
+                        "achieved_tflops": otf, "mfma_frac_bf16_peak": otf / PEAK_BF16_TFLOPS}}
 
 
 def bench_wide(V, torch, reps):

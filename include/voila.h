@@ -106,11 +106,11 @@ const char* voila_last_error(void);
  * layers x width): (4, 5 discrete, 4, 2, 2, 2 x 64); (4, d_a = 4, 4, 2, 2,
  * 2 x 64); (16, d_a = 4, 16, 32, 32, 3 x 256); (4, 5 discrete, 4, 2, 2,
  * 2 x 1024, VOILA_BF16 only: binary32 activations of that width do not fit
- * in registers); (4, 5 discrete, 4, -, -, 4 x 1024, VOILA_BF16 only, the
- * depth and width of the paper's distilled samplers (Sec. 5)): a transition
- * network only -- observation and likelihood networks of that shape are
- * refused -- which serves voila_plan (its rollouts run in a kernel whose
- * waves split every layer of two 32-particle tiles). */
+ * in registers); (4, 5 discrete, 4, 2, 2, 4 x 1024, VOILA_BF16 only, the
+ * depth and width of the paper's distilled samplers (Sec. 5)): transition
+ * and observation networks only -- a likelihood network of that shape is
+ * refused -- serving voila_plan, voila_observe and voila_plan_observe (their
+ * kernels split every layer of two 32-row tiles over a block's waves). */
 voila_status_t voila_model_create(const voila_model_desc_t* h_desc, int32_t device, voila_model_t* out);
 /* [sync] Frees a model (NULL is accepted). */
 voila_status_t voila_model_destroy(voila_model_t model);

@@ -403,9 +403,10 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
         }
     }
     if (shape < 0) return fail(VOILA_ERR_UNSUPPORTED, "no compiled kernel for this network shape");
-    if (plan_split_shape(shape, DT_BF16) && (Z.present() || L.present()))
+    if (plan_split_shape(shape, DT_BF16) && L.present())
         return fail(VOILA_ERR_UNSUPPORTED,
-                    "networks wider than 256 with more than two hidden layers: transition network (plan) only");
+                    "networks wider than 256 with more than two hidden layers: transition and observation "
+                    "networks only (no likelihood network)");
     if (T.width() > 256 && desc->compute != VOILA_BF16)
         return fail(VOILA_ERR_UNSUPPORTED, "hidden widths above 256 run in bfloat16 only");
 

@@ -139,10 +139,120 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
     }
 }
 
+// Observation networks of more than two hidden layers wider than 256 (the
+// depth of the paper's distilled samplers): a block of kObsSplitWaves waves
+// evaluates two 32-row tiles of one (candidate, step) group together, each
+// layer split over the waves (run_net_split_multi), every weight fragment
+// read from L2 serving both tiles.  Every wave forms both tiles' inputs (the
+// split evaluation hands every wave the same output); the first wave writes.
+constexpr int kObsSplitWaves = 8, kObsSplitTiles = 2, kObsSplitDepth = 2;
+
+template <int DT, int WIDTH, int NHID>
+constexpr bool obs_split() {
+    return net_compiled(DT, WIDTH) && !generic_compiled(DT, WIDTH, NHID);
+}
+
+template <int DT, int D_S, int D_WZ, int D_O, int WIDTH, int NHID>
+__global__ __launch_bounds__(64 * kObsSplitWaves) void observe_split_kernel(ObserveParams p) {
+    if constexpr (!obs_split<DT, WIDTH, NHID>()) {
+        return;  // the other networks run in observe_kernel
+    } else {
+    constexpr int ST = kObsSplitTiles;
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ), WIDTH / 32> NT;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n_tiles = (p.N + 31) / 32;
+    const int n_pairs = (n_tiles + ST - 1) / ST;
+    const long n_units = (long)p.K * p.H * n_pairs;
+    const NetPtrs P = net_ptrs(p.obs.base, p.obs);
+    for (long u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const long grp = u / n_pairs;
+        const int tp = (int)(u - grp * n_pairs);
+        float slots[ST][NT::IN_SLOTS];
+        ObsRow w[ST];
+#pragma unroll
+        for (int q = 0; q < ST; ++q) {
+            // a tile past the last of the group reads row 0 and writes nothing
+            const int tile = tp * ST + q;
+            w[q] = observe_inputs<D_S, D_WZ>(p, grp * n_tiles + (tile < n_tiles ? tile : 0), n_tiles, g, col,
+                                             slots[q]);
+            w[q].valid = w[q].valid && tile < n_tiles;
+        }
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+        const float* b0 = p.b0 + (size_t)(p.b0_stride ? grp : 0) * p.b0_stride;
+        f32x16 o[ST];
+        run_net_split_multi<NT, ST, kObsSplitWaves, kObsSplitDepth>(P, b0, slots, o, lane, g, wave, smem);
+#pragma unroll
+        for (int q = 0; q < ST; ++q) observe_store<D_O>(p, w[q], o[q], wave == 0, g);
+    }
+    }
+}
+
+#define OBS_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_split_kernel<DT, ds, dwz, dox, w, nh>
+
+template <int DT, int D_S, int D_WZ, int W, int NH>
+constexpr size_t obs_split_lds() {
+    if constexpr (!obs_split<DT, W, NH>()) {
+        return 0;
+    } else {
+        return (size_t)kObsSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_S, 0, D_WZ), W / 32>>::ACT;
+    }
+}
+
+bool observe_split_shape(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh) \
+    case id * 2 + 0:                           \
+        return obs_split<DT_F32, w, nh>();     \
+    case id * 2 + 1:                           \
+        return obs_split<DT_BF16, w, nh>();
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return false;
+}
+
+// Rows (k, i, t) of an observation launch in the split kernel: one unit of
+// two tiles per block, the grid capped (the kernel strides over units).
+hipError_t launch_observe_split(int shape, int dt, const ObserveParams& p, hipStream_t s) {
+    const long n_pairs = ((long)(p.N + 31) / 32 + kObsSplitTiles - 1) / kObsSplitTiles;
+    const long units = (long)p.K * p.H * n_pairs;
+    if (units == 0) return hipSuccess;
+    const int blocks = (int)(units < 4096 ? units : 4096);
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
+    case id * 2 + 0: {                                                                                      \
+        const size_t lds = obs_split_lds<DT_F32, ds, dwz, w, nh>();                                         \
+        if (lds > 65536)                                                                                    \
+            (void)hipFuncSetAttribute((const void*)OBS_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),      \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+        hipLaunchKernelGGL((OBS_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks,                    \
+                           64 * kObsSplitWaves, lds, s, p);                                                 \
+        break;                                                                                              \
+    }                                                                                                       \
+    case id * 2 + 1: {                                                                                      \
+        const size_t lds = obs_split_lds<DT_BF16, ds, dwz, w, nh>();                                        \
+        if (lds > 65536)                                                                                    \
+            (void)hipFuncSetAttribute((const void*)OBS_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),     \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+        hipLaunchKernelGGL((OBS_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks,                   \
+                           64 * kObsSplitWaves, lds, s, p);                                                 \
+        break;                                                                                              \
+    }
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // launchers
 #define OBS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, pass_mode<w>()>
 
 hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s) {
+    if (observe_split_shape(shape, dt)) return launch_observe_split(shape, dt, p, s);
     const size_t lds = weights_in_lds(shape) ? p.obs.bytes : pass_split(shape) ? kSplitLds : 0;
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                             \
@@ -180,6 +290,7 @@ size_t observe_rollout_lds(int shape, int dt, const NetBlob& obs) {
 }
 
 hipError_t launch_observe_rollouts(int shape, int dt, const ObserveParams& p0, int blocks, hipStream_t s) {
+    if (observe_split_shape(shape, dt)) return launch_observe_split(shape, dt, p0, s);
     ObserveParams p = p0;
     size_t lds = observe_rollout_lds(shape, dt, p.obs);
     if (!weights_in_lds(shape)) {

@@ -167,17 +167,24 @@ def wide(seed: int = 3, N: int = 128, K: int = 32, H: int = 10, compute: str = "
     return small(seed=seed, N=N, K=K, H=H, width=1024, compute=compute, name="wide")
 
 
-def deep(seed: int = 6, N: int = 128, K: int = 32, H: int = 10, compute: str = "bf16") -> Workload:
+def deep(seed: int = 6, N: int = 128, K: int = 32, H: int = 10, compute: str = "bf16",
+         with_obs: bool = False) -> Workload:
     """The small workload's transition network at the depth and width of the
-    paper's distilled samplers: four hidden layers of 1024 (ReLU); no
-    observation or likelihood network (rollouts only)."""
+    paper's distilled samplers: four hidden layers of 1024 (ReLU); with
+    `with_obs` an observation network of the same depth and width
+    ([s', a, w_Z] -> 1024 x 4 -> o); no likelihood network (rollouts and
+    their observations only)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     trans = random_mlp(rng, [4 + 5 + 4] + [1024] * 4 + [4])
     model = Model(d_s=4, n_actions=5, d_a=0, d_w=4, d_o=2, d_wz=2, trans=trans, obs=[], lik=[])
     states = rng.standard_normal((N, 4)).astype(np.float32)
     cands = rng.integers(0, 5, size=(K, H)).astype(np.int32)
     goal = np.array([1, 1, 0, 0], np.float32)
-    return _finish("deep", rng, model, states, cands, 0.95, goal, 2, 1.0, compute)
+    w = _finish("deep", rng, model, states, cands, 0.95, goal, 2, 1.0, compute)
+    if with_obs:
+        # drawn after everything else, so the other inputs do not depend on it
+        w.model.obs = random_mlp(np.random.Generator(np.random.PCG64(seed + 1000)), [4 + 5 + 2] + [1024] * 4 + [2])
+    return w
 
 
 def batched(seed: int = 4, n_instances: int = 64, n_range=(256, 8192), h_range=(5, 30),
