@@ -54,6 +54,29 @@ __device__ __forceinline__ double lg_x(const LargeResParams& p, int i, int& bad)
     return x;
 }
 
+// exp(x) for x <= 0 in binary64, table-driven (P. T. P. Tang, Table-driven
+// implementation of the exponential function in IEEE floating-point
+// arithmetic, ACM TOMS 15(2), 1989): x = (256 e + j) ln2/256 + r with
+// |r| <= ln2/512, exp(x) = 2^e 2^(j/256) exp(r), exp(r) from its degree-5
+// Taylor polynomial (truncation below 2^-66 of the result).  ln2/256 is
+// split into a 32-bit head (k ln2/256 exact for |k| < 2^21) and a tail.
+// `tab` holds 2^(j/256), j < 256 (fill_exp_tab).  Within a few units in the
+// last place of exp; x below -745.2 (under the smallest subnormal, and -inf)
+// gives 0.
+constexpr int kExpTab = 256;
+__device__ __forceinline__ void fill_exp_tab(double* tab) {
+    for (int j = threadIdx.x; j < kExpTab; j += blockDim.x) tab[j] = exp2((double)j / kExpTab);
+    __syncthreads();
+}
+__device__ __forceinline__ double exp_tab(double x, const double* tab) {
+    if (!(x > -745.2)) return 0.0;
+    const double kd = rint(x * 369.3299304675746);  // 256 / ln 2
+    const int k = (int)kd;
+    const double r = fma(-kd, -0x1.718432a1b0e26p-43, fma(-kd, 0x1.62e42ff000000p-9, x));
+    const double poly = fma(fma(fma(fma(fma(1.0 / 120, r, 1.0 / 24), r, 1.0 / 6), r, 0.5), r, 1.0), r, 1.0);
+    return ldexp(tab[k & (kExpTab - 1)] * poly, k >> 8);
+}
+
 // (m, s) <- (m, s) combined with (m2, s2), where s = sum exp(x - m).
 __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
     if (m2 == -INFINITY) return;
@@ -95,6 +118,8 @@ __device__ int blk_max_i(int v, int* red) {
 __global__ __launch_bounds__(kLgThreads) void lg_lse_kernel(LargeResParams p) {
     __shared__ double rm[kLgThreads / 64], rs[kLgThreads / 64];
     __shared__ int redi[kLgThreads / 64];
+    __shared__ double etab[kExpTab];
+    fill_exp_tab(etab);
     const int base = blockIdx.x * kLgBlock + threadIdx.x;
     int bad = 0;
     // this thread's 16 values: their maximum, then the sum of exp(x - max)
@@ -110,7 +135,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_lse_kernel(LargeResParams p) {
     double s = 0.0;
     if (m != -INFINITY) {
 #pragma unroll
-        for (int k = 0; k < kLgItems; ++k) s += exp(xs[k] - m);
+        for (int k = 0; k < kLgItems; ++k) s += exp_tab(xs[k] - m, etab);
     }
     // fixed-shape tree: lanes merge across the wave (butterfly), then the
     // four wave results in order
@@ -155,12 +180,13 @@ __global__ __launch_bounds__(kRedThreads) void lg_lse_reduce_kernel(LargeResPara
 
 // q_i = rint(w_i N 2^b) of particle i with w_i = exp(x_i - m) / S, or the
 // given weight (checked); pass 2 and pass 3 call this same function.
-__device__ __forceinline__ double quant_w(const LargeResParams& p, int i, double m, double S, int& bad, double& w) {
+__device__ __forceinline__ double quant_w(const LargeResParams& p, int i, double m, double S, int& bad, double& w,
+                                         const double* etab) {
     if (p.w_in) {
         w = p.w_in[i];
         if (!(w >= 0.0) || w == INFINITY) bad = 1;
     } else {
-        w = exp(lg_x(p, i, bad) - m) / S;
+        w = exp_tab(lg_x(p, i, bad) - m, etab) / S;
     }
     return rint(w * ldexp((double)p.N, p.bits));
 }
@@ -168,6 +194,8 @@ __device__ __forceinline__ double quant_w(const LargeResParams& p, int i, double
 __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) {
     __shared__ double red[kLgThreads / 64];
     __shared__ int redi[kLgThreads / 64];
+    __shared__ double etab[kExpTab];
+    fill_exp_tab(etab);
     const int bbase = blockIdx.x * kLgBlock;
     const double m = p.ws.scal[0], S = p.ws.scal[1];
     double sq = 0.0, tq[kSubPerBlock];
@@ -179,7 +207,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
         const int i = bbase + k * kLgThreads + threadIdx.x;  // chunk k / kChunkItems of the block
         if (i < p.N) {
             double w;
-            const double q = quant_w(p, i, m, S, bad, w);
+            const double q = quant_w(p, i, m, S, bad, w, etab);
             if (!p.w_in && p.w_out) p.w_out[i] = w;
             sq += w * w;
             tq[k / kChunkItems] += q;  // exact: integers below 2^53
@@ -273,17 +301,32 @@ constexpr int kOutBlock = kLgChunk;  // outputs per workgroup of pass 3
 typedef float f32x4_nt __attribute__((ext_vector_type(4)));
 template <class T> struct NtType { typedef T type; };
 template <> struct NtType<float4> { typedef f32x4_nt type; };
+constexpr int kGatherBatch = 16;
 template <class T>
 __device__ __forceinline__ void gather_rows(T* dst0, const T* src0, const int* ids, int j0, int n_out, int w) {
     typedef typename NtType<T>::type V;
     V* dst = reinterpret_cast<V*>(dst0);
     const V* src = reinterpret_cast<const V*>(src0);
     if (w <= kLgThreads) {
+        // up to kGatherBatch rows per thread loaded before any is stored, so
+        // that many loads are in flight (the rows never overlap: the sources
+        // and the destination are distinct buffers)
         const int rpp = kLgThreads / w, r0 = threadIdx.x / w, c = threadIdx.x - r0 * w;
-        if (r0 < rpp)
-            for (int r = r0; r < n_out; r += rpp)
-                __builtin_nontemporal_store(__builtin_nontemporal_load(src + (size_t)ids[r] * w + c),
-                                            dst + (size_t)(j0 + r) * w + c);
+        if (r0 < rpp) {
+            for (int rb = r0; rb < n_out; rb += kGatherBatch * rpp) {
+                V v[kGatherBatch];
+#pragma unroll
+                for (int q = 0; q < kGatherBatch; ++q) {
+                    const int r = rb + q * rpp;
+                    if (r < n_out) v[q] = __builtin_nontemporal_load(src + (size_t)ids[r] * w + c);
+                }
+#pragma unroll
+                for (int q = 0; q < kGatherBatch; ++q) {
+                    const int r = rb + q * rpp;
+                    if (r < n_out) __builtin_nontemporal_store(v[q], dst + (size_t)(j0 + r) * w + c);
+                }
+            }
+        }
     } else {
         for (int r = 0; r < n_out; ++r)
             for (int c = threadIdx.x; c < w; c += kLgThreads)
@@ -294,6 +337,8 @@ __device__ __forceinline__ void gather_rows(T* dst0, const T* src0, const int* i
 
 __global__ __launch_bounds__(kLgThreads) void lg_resample_kernel(LargeResParams p) {
     __shared__ int ids[kOutBlock];
+    __shared__ double etab[kExpTab];
+    fill_exp_tab(etab);
     __shared__ int3 heavy[kHeavySlots];
     __shared__ double wtot[kLgThreads / 64];
     __shared__ int n_heavy, s_first;
@@ -342,7 +387,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_resample_kernel(LargeResParams 
 #pragma unroll
         for (int k = 0; k < kChunkItems; ++k) {
             double w;
-            qk[k] = i0 + k < p.N ? quant_w(p, i0 + k, m, S, bad, w) : 0.0;
+            qk[k] = i0 + k < p.N ? quant_w(p, i0 + k, m, S, bad, w, etab) : 0.0;
             run += qk[k];
             qk[k] = run;
         }
