@@ -521,9 +521,11 @@ def bench_ddim(V, torch, reps):
     65,536 samples, 50 deterministic DDIM steps): the paper's 5 x 1024
     transition denoiser, beside one evaluation of a 4 x 1024 network (the
     paper's distilled sampler shape) through the same kernel -- the
-    distilled-versus-diffusion sampling-rate comparison -- and a 5 x 512
-    observation denoiser (32-dimensional observation, 16-dimensional state,
-    4 continuous action inputs)."""
+    distilled-versus-diffusion sampling-rate comparison -- and two 5 x 512
+    observation denoisers: a 32-dimensional observation given a
+    16-dimensional state and 4 continuous action inputs, and the paper's
+    64-dimensional latent observation given the 39-dimensional state with a
+    one-hot environment index (44 inputs) and one of six actions."""
     import workloads
     dev = torch.device("cuda", 0)
     N, steps = 65536, 50
@@ -531,7 +533,8 @@ def bench_ddim(V, torch, reps):
     stream = torch.cuda.current_stream()
     cases = [("teacher_5x1024", 4, 4, 5, 0, 1024, 5, steps, 2),
              ("distilled_4x1024", 4, 4, 5, 0, 1024, 4, 1, 2),
-             ("observation_teacher_5x512", 16, 32, 0, 4, 512, 5, steps, [0.5, -1.0, 0.25, 0.0])]
+             ("observation_teacher_5x512", 16, 32, 0, 4, 512, 5, steps, [0.5, -1.0, 0.25, 0.0]),
+             ("observation_teacher_5x512_o64", 44, 64, 6, 0, 512, 5, steps, 4)]
     for name, d_c, d_x, n_act, d_a, width, nh, n_steps, action in cases:
         C, X1 = (torch.as_tensor(x, device=dev) for x in workloads.ddim_batch(N, d_c=d_c, d_x=d_x, seed=23))
         layers = workloads.denoiser(seed=24, d_c=d_c, d_x=d_x, n_actions=n_act, d_a=d_a, width=width, n_hidden=nh)

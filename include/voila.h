@@ -360,8 +360,11 @@ voila_status_t voila_info_nce_grad(voila_model_t model, const float* d_states, c
  * shapes (d_x, d_c, hidden layers): (4, 4, 2 x 64) in binary32 or bfloat16;
  * in bfloat16 only (4, 4, 5 x 1024) -- the paper's transition denoiser --,
  * (4, 4, 4 x 1024) -- the distilled sampler's shape, for a one-step cost
- * comparison -- and (32, 16, 5 x 512) -- the paper's observation denoiser
- * width and depth; other shapes return VOILA_ERR_UNSUPPORTED.  The handle
+ * comparison --, (32, 16, 5 x 512) -- the paper's observation denoiser
+ * width and depth -- and (64, 44, 5 x 512) -- the paper's observation
+ * denoiser over its 64-dimensional latent observation, conditioned on the
+ * 39-dimensional state with a one-hot environment index (its output layer
+ * is two 32-row tiles); other shapes return VOILA_ERR_UNSUPPORTED.  The handle
  * owns a device copy of the weights.
  *
  * voila_ddim_sample draws N samples in n_steps uniform steps tau_k = 1 - k/n

@@ -103,7 +103,10 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
     const int esz = dt == DT_F32 ? 4 : 2;
     const size_t fb = (size_t)64 * KP * esz;
     const int IN_KS = in_slots_per_group / KP, HID_KS = 16 * HT / KP;
-    const size_t nf0 = (size_t)IN_KS * HT, nfh = (size_t)HID_KS * HT, nfo = HID_KS;
+    // 32-row output tiles: more than one only for layered networks (the split
+    // evaluation), tile t's k-steps following tile t - 1's
+    const int NO = layered ? (n.out() + 31) / 32 : 1;
+    const size_t nf0 = (size_t)IN_KS * HT, nfh = (size_t)HID_KS * HT, nfo = (size_t)NO * HID_KS;
     const size_t off_f0 = 0;
     const size_t off_fh = off_f0 + nf0 * fb;
     const size_t off_fo = off_fh + (size_t)(NHID - 1) * nfh * fb;
@@ -114,7 +117,7 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
     const size_t off_b0 = align_up(off_fo + (nfo + pad) * fb, 16);
     const size_t off_bh = align_up(off_b0 + (size_t)n_var * W * 4, 16);
     const size_t off_bo = align_up(off_bh + (size_t)(NHID - 1) * W * 4, 16);
-    const size_t total = align_up(off_bo + 32 * 4, 16);
+    const size_t total = align_up(off_bo + (size_t)NO * 32 * 4, 16);
     std::vector<char> blob(total, 0);
     auto put = [&](size_t frag_off, size_t frag, int lane, int j, float v) {
         size_t e = (frag * 64 + lane) * KP + j;
@@ -150,20 +153,22 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
                         put(off_f0, hidden_pos(l, c, t), lane, j,
                             n.w(l, 32 * t + lane % 32, hidden_in(c * KP + j, lane / 32)));
     const int L = NHID;
-    for (int c = 0; c < HID_KS; ++c)
-        for (int lane = 0; lane < 64; ++lane)
-            for (int j = 0; j < KP; ++j) {
-                int f = row_feature(lane % 32);
-                put(off_f0, lay.out(c), lane, j, f < n.out() ? n.w(L, f, hidden_in(c * KP + j, lane / 32)) : 0.0f);
-            }
+    for (int t = 0; t < NO; ++t)
+        for (int c = 0; c < HID_KS; ++c)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < KP; ++j) {
+                    int f = 32 * t + row_feature(lane % 32);
+                    put(off_f0, lay.out(t * HID_KS + c), lane, j,
+                        f < n.out() ? n.w(L, f, hidden_in(c * KP + j, lane / 32)) : 0.0f);
+                }
     std::memcpy(blob.data() + off_b0, b0_variants.data(), (size_t)n_var * W * 4);
     for (int l = 1; l <= NHID - 1; ++l) std::memcpy(blob.data() + off_bh + (size_t)(l - 1) * W * 4, n.b[l], (size_t)W * 4);
-    float bo[32];
-    for (int r = 0; r < 32; ++r) {
-        int f = row_feature(r);
+    std::vector<float> bo((size_t)NO * 32);
+    for (int r = 0; r < NO * 32; ++r) {
+        int f = 32 * (r / 32) + row_feature(r % 32);
         bo[r] = f < n.out() ? n.b[L][f] : 0.0f;
     }
-    std::memcpy(blob.data() + off_bo, bo, sizeof(bo));
+    std::memcpy(blob.data() + off_bo, bo.data(), bo.size() * 4);
     nb.base = nullptr;
     nb.bytes = (uint32_t)total;
     nb.off_f0 = (uint32_t)off_f0;

@@ -129,8 +129,11 @@ __host__ __device__ constexpr int default_ct(int width, int nhid) { return nhid 
 
 // Compile-time shape of one network as the engine runs it.  CT_ = WIDTH_/32
 // packs a wide network layer by layer (for the split evaluation) instead of
-// in the groups of the grouped evaluation.
-template <int DT_, int WIDTH_, int NHID_, int IN_SLOTS_, int CT_ = default_ct(WIDTH_, NHID_)>
+// in the groups of the grouped evaluation.  NO_ 32-row output tiles (outputs
+// wider than 32 need a layered network; only the split evaluation produces
+// more than one): the output fragments of tile t are k-steps
+// t HID_KS .. t HID_KS + HID_KS - 1 of the output layer.
+template <int DT_, int WIDTH_, int NHID_, int IN_SLOTS_, int CT_ = default_ct(WIDTH_, NHID_), int NO_ = 1>
 struct Net {
     static constexpr int DT = DT_;
     static constexpr int WIDTH = WIDTH_;           // hidden width (multiple of 32)
@@ -143,11 +146,13 @@ struct Net {
     static constexpr int FRAG_BYTES = 64 * KPER * (DT == DT_F32 ? 4 : 2);
     static constexpr int NF0 = IN_KS * HT;         // first-layer fragments
     static constexpr int NFH = HID_KS * HT;        // fragments per hidden->hidden layer
-    static constexpr int NFO = HID_KS;             // output-layer fragments
+    static constexpr int NO = NO_;                 // output tiles
+    static constexpr int NFO = NO_ * HID_KS;       // output-layer fragments
     static constexpr int CT = CT_;                 // tiles per group of the grouped evaluation
     static constexpr int OKS = HID_KS / HT;        // output k-steps per hidden tile
     static_assert(WIDTH % 32 == 0 && NHID >= 1 && IN_SLOTS % KPER == 0, "bad net shape");
     static_assert(CT == HT || (NHID == 2 && HT % CT == 0), "grouped evaluation needs two hidden layers");
+    static_assert(NO >= 1 && (NO == 1 || CT == HT), "several output tiles need a layered network");
 };
 
 // Device view of one packed network (all pointers into global memory or LDS).
@@ -1134,8 +1139,9 @@ __device__ __forceinline__ void run_net_flat(Src& src, const NetPtrs& P, const f
 // flight.
 template <class N, int ST, int NW, int D>
 __device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const float* b0,
-                                                    const float (&slots)[ST][N::IN_SLOTS], f32x16 (&out)[ST],
-                                                    int lane, int g, int wave, char* lds) {
+                                                    const float (&slots)[ST][N::IN_SLOTS],
+                                                    f32x16 (&out)[ST * N::NO], int lane, int g, int wave,
+                                                    char* lds) {
     static_assert(N::HT % NW == 0 && N::HID_KS % NW == 0 && N::CT == N::HT, "split needs a layered network");
     constexpr int TPW = N::HT / NW, KQ = N::HID_KS / NW;
     constexpr int ACT = SplitLds<N>::ACT;
@@ -1169,35 +1175,46 @@ __device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const floa
         for (int st = 0; st < ST; ++st) split_store<N, TPW>(lds + st * ACT, acc[st], t0, lane);
         __syncthreads();
     });
-    f32x16 part[ST][1];
+    // the output layer: each wave multiplies its k-steps for every output
+    // tile, then the partial tiles are added in wave order, tile by tile (the
+    // partials reuse the activation space once every wave has read it)
+    f32x16 part[ST][N::NO];
 #pragma unroll
     for (int st = 0; st < ST; ++st) {
-        init_bias<1>(part[st], P.bo + opaque_zero(), g);
-        if (wave != 0) part[st][0] = f32x16{};
+        init_bias<N::NO>(part[st], P.bo + opaque_zero(), g);
+        if (wave != 0)
+#pragma unroll
+            for (int t = 0; t < N::NO; ++t) part[st][t] = f32x16{};
     }
     {
         const int k0 = wave * KQ;
         const char* base = P.f0 + (size_t)(FI::out(0) + k0) * N::FRAG_BYTES + opaque_zero();
-        mfma_layer_multi<KQ, 1, ST, D, FT>(
-            part, [&](int c, int) { return Frag<N::DT>::load(base + (size_t)c * N::FRAG_BYTES + opaque_zero(), 0, lane); },
+        mfma_layer_multi<KQ, N::NO, ST, D, FT>(
+            part,
+            [&](int c, int t) {
+                return Frag<N::DT>::load(base + (size_t)(t * N::HID_KS + c) * N::FRAG_BYTES + opaque_zero(), 0, lane);
+            },
             [&](int c, int st) { return split_act<N>(lds + st * ACT, k0 + c, lane); });
     }
     __syncthreads();  // every wave has read the activations the partials overwrite
     float* pl = reinterpret_cast<float*>(lds);
 #pragma unroll
-    for (int st = 0; st < ST; ++st)
+    for (int t = 0; t < N::NO; ++t) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) pl[((st * NW + wave) * 16 + i) * 64 + lane] = part[st][0][i];
-    __syncthreads();
+        for (int st = 0; st < ST; ++st)
 #pragma unroll
-    for (int st = 0; st < ST; ++st)
+            for (int i = 0; i < 16; ++i) pl[((st * NW + wave) * 16 + i) * 64 + lane] = part[st][t][i];
+        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            float v = pl[((st * NW) * 16 + i) * 64 + lane];
-            for (int w = 1; w < NW; ++w) v += pl[((st * NW + w) * 16 + i) * 64 + lane];
-            out[st][i] = v;
-        }
-    __syncthreads();
+        for (int st = 0; st < ST; ++st)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                float v = pl[((st * NW) * 16 + i) * 64 + lane];
+                for (int w = 1; w < NW; ++w) v += pl[((st * NW + w) * 16 + i) * 64 + lane];
+                out[st * N::NO + t][i] = v;
+            }
+        __syncthreads();
+    }
 }
 
 // Fragment source of a network read straight from global memory: the plain

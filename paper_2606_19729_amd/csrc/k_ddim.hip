@@ -46,8 +46,8 @@ __global__ __launch_bounds__(256) void ddim_prep_kernel(DdimPrepParams p) {
 // with the activations in LDS and the weights read from L2.
 template <int DT, int D_X, int D_C, int WIDTH, int NHID, int MODE>
 __global__ __launch_bounds__(256) void ddim_kernel(DdimParams p) {
-    if constexpr (!net_compiled(DT, WIDTH)) {
-        return;  // binary32 networks wider than 256 are refused at creation
+    if constexpr (!net_compiled(DT, WIDTH) || D_X > 32) {
+        return;  // binary32 wider than 256 is refused at creation; wider samples run split
     } else {
     constexpr bool SPLIT = MODE == kSplit;
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_X, 0, D_C), (SPLIT ? WIDTH / 32 : chunk_tiles(WIDTH))> NT;
@@ -129,8 +129,8 @@ __global__ __launch_bounds__(64 * kDdimSplitWaves) void ddim_split_kernel(DdimPa
     if constexpr (!net_compiled(DT, WIDTH) || WIDTH <= 64) {
         return;  // small networks run one tile per wave in ddim_kernel
     } else {
-    constexpr int ST = kDdimSplitTiles;
-    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_X, 0, D_C), WIDTH / 32> NT;
+    constexpr int ST = kDdimSplitTiles, NO = cdiv(D_X, 32);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_X, 0, D_C), WIDTH / 32, NO> NT;
     constexpr int SS = state_slots(D_X), SW = noise_slots(D_C);
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
@@ -169,13 +169,15 @@ __global__ __launch_bounds__(64 * kDdimSplitWaves) void ddim_split_kernel(DdimPa
 #pragma unroll
                 for (int s = 0; s < SW; ++s) slots[st][SS + s] = cond[st][s];
             }
-            f32x16 v[ST];
+            f32x16 v[ST * NO];
             run_net_split_multi<NT, ST, kDdimSplitWaves, kDdimSplitDepth>(P, p.b0 + (size_t)t * WIDTH, slots, v, lane, g, wave, smem);
             const float Am1 = coef[2 * t], B = coef[2 * t + 1];
+            // state slot s holds feature 2 s + g: output tile s / 16, register s % 16
 #pragma unroll
             for (int st = 0; st < ST; ++st)
 #pragma unroll
-                for (int s = 0; s < SS; ++s) x[st][s] += __builtin_fmaf(B, v[st][s], Am1 * x[st][s]);
+                for (int s = 0; s < SS; ++s)
+                    x[st][s] += __builtin_fmaf(B, v[st * NO + s / 16][s % 16], Am1 * x[st][s]);
         }
         if (wave == 0)
 #pragma unroll
@@ -226,7 +228,7 @@ constexpr size_t ddim_split_lds() {
     if constexpr (!net_compiled(DT, W)) {
         return 0;
     } else {
-        return (size_t)kDdimSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_X, 0, D_C), W / 32>>::ACT;
+        return (size_t)kDdimSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_X, 0, D_C), W / 32, cdiv(D_X, 32)>>::ACT;
     }
 }
 int ddim_tiles_per_block(int shape) { return ddim_split(shape) ? kDdimSplitTiles : kWavesPerBlock; }

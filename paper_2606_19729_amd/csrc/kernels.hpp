@@ -361,8 +361,9 @@ hipError_t launch_nce_mean(const NceParams& p, hipStream_t s);
     X(0, 4, 4, 64, 2)        \
     X(1, 4, 4, 1024, 5)      \
     X(2, 4, 4, 1024, 4)      \
-    X(3, 32, 16, 512, 5)
-constexpr int kNumDdimShapes = 4;
+    X(3, 32, 16, 512, 5)     \
+    X(4, 64, 44, 512, 5)
+constexpr int kNumDdimShapes = 5;
 int ddim_shape(int d_x, int d_c, int width, int n_hidden);  // -1 when not compiled
 int ddim_in_slots(int shape, int dt);
 bool ddim_split(int shape);                        // evaluated by all waves of a block per group of tiles

@@ -15,8 +15,8 @@ kernels apply it as x + ((A - 1) x + B v), since A is then within binary32
 resolution of 1).  Cases: ragged sample counts, one to 4,096 steps (the
 largest accepted), discrete and continuous actions,
 the 2 x 64 network in both precisions, the paper's 5 x 1024 transition
-denoiser, the 4 x 1024 one-step network and a 5 x 512 observation denoiser
-in bfloat16, sampled rows of 65,536 samples at 50 steps, bit-identical
+denoiser, the 4 x 1024 one-step network, a 5 x 512 observation denoiser over
+32 features and the paper's over 64 (two output tiles) in bfloat16, sampled rows of 65,536 samples at 50 steps, bit-identical
 repeated runs, and argument errors.
 """
 import numpy as np
@@ -93,6 +93,16 @@ def test_observation_denoiser_shape(V, N, n_steps):
     # and a continuous 4-dimensional action
     layers = workloads.denoiser(seed=37, d_c=16, d_x=32, n_actions=0, d_a=4, width=512, n_hidden=5)
     compare(V, layers, 16, 32, 0, 4, "bf16", N, n_steps, np.array([0.5, -1.0, 0.25, 0.0], np.float32))
+
+
+@pytest.mark.parametrize("N,n_steps", [(70, 5), (33, 1)])
+def test_paper_observation_denoiser(V, N, n_steps):
+    # the paper's observation denoiser: 5 x 512 over the 64-dimensional latent
+    # observation (two 32-row output tiles), conditioned on the 39-dimensional
+    # state with a one-hot environment index (44 inputs) and one of six
+    # discrete actions
+    layers = workloads.denoiser(seed=38, d_c=44, d_x=64, n_actions=6, d_a=0, width=512, n_hidden=5)
+    compare(V, layers, 44, 64, 6, 0, "bf16", N, n_steps, 4)
 
 
 def test_repeatable_and_zero_samples(V):
