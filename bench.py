@@ -180,13 +180,19 @@ def bench_batched(V, torch, reps):
     return out
 
 
-def bench_deep(V, torch, reps):
+def bench_deep(V, torch, reps, paper_dims=False):
     """Four hidden layers of 1024 in bfloat16 (the depth and width of the
     paper's distilled samplers), run by the split rollout kernel: 256
-    candidates x 4096 particles x 20 steps."""
+    candidates x 4096 particles x 20 steps, plan and per-step observations;
+    with the small workload's dimensions, or with `paper_dims` the paper's
+    target-finding task (45-dimensional state, six actions, 36 lidar
+    bins)."""
     import workloads
     dev = torch.device("cuda", 0)
-    w = workloads.deep(seed=8, N=4096, K=256, H=20, with_obs=True)
+    if paper_dims:
+        w = workloads.target_finding(seed=16, N=4096, K=256, H=20)
+    else:
+        w = workloads.deep(seed=8, N=4096, K=256, H=20, with_obs=True)
     mb = V.Model(w.model, compute="bf16")
     S = torch.as_tensor(w.states, device=dev)
     C = torch.as_tensor(w.cands, device=dev)
@@ -217,9 +223,11 @@ def bench_deep(V, torch, reps):
     oms = e0.elapsed_time(e1) / reps
     # [s', w_Z] -> 1024 x 4 -> o, the one-hot action folded into the bias row
     ofl = 2 * ((w.model.d_s + w.model.d_wz) * 1024 + 3 * 1024 * 1024 + 1024 * w.model.d_o)
+    dims = {"d_s": w.model.d_s, "n_actions": w.model.n_actions, "d_w": w.model.d_w, "d_o": w.model.d_o,
+            "d_wz": w.model.d_wz}
     otf = ofl * steps / (oms / 1e3) / 1e12
     mb.close()
-    return {"K": w.K, "N": w.N, "H": w.H, "hidden": [1024] * 4, "plan_ms": ms,
+    return {"K": w.K, "N": w.N, "H": w.H, "hidden": [1024] * 4, "dims": dims, "plan_ms": ms,
             "rollout_steps_per_s": steps / (ms / 1e3), "achieved_tflops": tflops,
             "mfma_frac_bf16_peak": tflops / PEAK_BF16_TFLOPS, "flop_per_rollout_step": fps,
             "observe": {"ms": oms, "observations_per_s": steps / (oms / 1e3), "flop_per_observation": ofl,
@@ -748,7 +756,7 @@ def main():
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter calibration)")
     ap.add_argument("--only", default="",
                     help="comma-separated extra sections to run (for profiling): bf16, batched, gradients, small, "
-                         "wide, deep, plan_observe, pw_step, info_nce, ddim, tree, update_sweep, gemm")
+                         "wide, deep, target_finding, plan_observe, pw_step, info_nce, ddim, tree, update_sweep, gemm")
     args = ap.parse_args()
     only = set(x for x in args.only.split(",") if x)
 
@@ -883,6 +891,8 @@ def main():
         ("wide", "hidden width 1024 (bf16)", "wide_bf16", lambda: bench_wide(V, torch, max(2, args.steps // 2))),
         ("deep", "four hidden layers of 1024 (bf16, split rollout kernel)", "deep_bf16",
          lambda: bench_deep(V, torch, max(2, args.steps // 2))),
+        ("target_finding", "the paper's target-finding shapes (45-d state, 36 lidar bins; 4 x 1024 bf16)",
+         "target_finding_bf16", lambda: bench_deep(V, torch, max(2, args.steps // 2), paper_dims=True)),
         ("plan_observe", "rollout states and per-step observations", "plan_observe",
          lambda: bench_plan_observe(V, torch, max(2, args.steps // 2), w, S, C)),
         ("pw_step", "grouped progressive widening", "pw_step", lambda: bench_pw(V, torch, max(3, args.steps))),

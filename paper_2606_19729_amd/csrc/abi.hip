@@ -103,9 +103,9 @@ std::vector<char> pack_net(const HostNet& n, int dt, int in_slots_per_group, con
     const int esz = dt == DT_F32 ? 4 : 2;
     const size_t fb = (size_t)64 * KP * esz;
     const int IN_KS = in_slots_per_group / KP, HID_KS = 16 * HT / KP;
-    // 32-row output tiles: more than one only for layered networks (the split
-    // evaluation), tile t's k-steps following tile t - 1's
-    const int NO = layered ? (n.out() + 31) / 32 : 1;
+    // 32-row output tiles: more than one only for networks packed layer by
+    // layer (the split evaluation), tile t's k-steps following tile t - 1's
+    const int NO = (layered || (CT == HT && !pass_tiles)) ? (n.out() + 31) / 32 : 1;
     const size_t nf0 = (size_t)IN_KS * HT, nfh = (size_t)HID_KS * HT, nfo = (size_t)NO * HID_KS;
     const size_t off_f0 = 0;
     const size_t off_fh = off_f0 + nf0 * fb;
@@ -656,7 +656,6 @@ voila_status_t voila_plan(voila_model_t m, const float* d_states, const double* 
     if (o->reward_at != 0 && o->reward_at != 1) return fail(VOILA_ERR_INVALID_ARG, "reward_at must be 0 or 1");
     if (K == 0) return VOILA_OK;
     if (!d_states || !d_q_out || (!d_cands && H > 0)) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
-    if (m->d_s > 32) return fail(VOILA_ERR_UNSUPPORTED, "d_s > 32");
     if (!ws || ws_bytes < plan_ws(N, K)) return fail(VOILA_ERR_WORKSPACE, "plan workspace too small");
     DeviceGuard guard(m->device);
     if (!guard.ok) return fail(VOILA_ERR_DEVICE, "hipSetDevice failed");
@@ -680,7 +679,7 @@ voila_status_t voila_plan(voila_model_t m, const float* d_states, const double* 
     p.key1 = (uint32_t)(o->seed >> 32);
     p.crn = o->crn ? 1 : 0;
     p.reward_at = o->reward_at;
-    for (int j = 0; j < 32; ++j) p.goal[j] = j < m->d_s ? o->h_goal[j] : 0.0f;
+    for (int j = 0; j < 64; ++j) p.goal[j] = j < m->d_s ? o->h_goal[j] : 0.0f;
     // units: (candidate, tile), or (candidate, group of tiles) for the paired
     // and the split evaluations
     const int tpu = plan_tiles_per_unit(m->shape, m->dt), upb = plan_units_per_block(m->shape, m->dt);
@@ -2021,7 +2020,7 @@ voila_status_t voila_batch_create(const voila_batch_item_t* items, int32_t n, co
         p.key1 = (uint32_t)(it.seed >> 32);
         p.crn = it.crn ? 1 : 0;
         p.reward_at = it.reward_at;
-        for (int c = 0; c < 32; ++c) p.goal[c] = c < d_s ? it.h_goal[c] : 0.0f;
+        for (int c = 0; c < 64; ++c) p.goal[c] = c < d_s ? it.h_goal[c] : 0.0f;
         hq[j] = QReduceParams{p.partials, it.d_q_out, it.K, n_tiles,
                               it.d_belief_w ? 1.0f : (float)(1.0 / (double)it.N)};
         b->plan_lds = std::max<size_t>(b->plan_lds, m->trans_plan.bytes);

@@ -1134,15 +1134,17 @@ __device__ __forceinline__ void run_net_flat(Src& src, const NetPtrs& P, const f
 // computes output tiles [w HT/NW, (w+1) HT/NW) of every layer for all ST
 // sample tiles, so each weight fragment read from L2 serves ST tiles.  The
 // activations of sample tile st live at lds + st * ACT; the output layer's
-// per-wave partials reuse that space.  out[st] is the output tile of sample
-// tile st (identical in every wave).  D k-steps of weight fragments are in
-// flight.
-template <class N, int ST, int NW, int D>
-__device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const float* b0,
-                                                    const float (&slots)[ST][N::IN_SLOTS],
-                                                    f32x16 (&out)[ST * N::NO], int lane, int g, int wave,
-                                                    char* lds) {
+// per-wave partials reuse that space.  bin(c, st) is the first-layer B
+// operand of sample tile st at k-step c.  With OWN false, out[st * NO + t] is
+// output tile t of sample tile st in every wave; with OWN true, wave w < ST
+// receives only its own sample tile's (out[t] of sample tile w) and the other
+// waves none.  D k-steps of weight fragments are in flight.
+template <class N, int ST, int NW, int D, bool OWN, class BIN>
+__device__ __forceinline__ void run_net_split_core(const NetPtrs& P, const float* b0, BIN&& bin,
+                                                   f32x16 (&out)[OWN ? N::NO : ST * N::NO], int lane, int g,
+                                                   int wave, char* lds) {
     static_assert(N::HT % NW == 0 && N::HID_KS % NW == 0 && N::CT == N::HT, "split needs a layered network");
+    static_assert(!OWN || ST <= NW, "every sample tile needs an owner wave");
     constexpr int TPW = N::HT / NW, KQ = N::HID_KS / NW;
     constexpr int ACT = SplitLds<N>::ACT;
     static_assert(ST * NW * 16 * 64 * 4 <= ST * ACT, "partials must fit the activation space");
@@ -1156,8 +1158,7 @@ __device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const floa
     {
         const char* base = P.f0 + (size_t)FI::first(0, t0) * N::FRAG_BYTES + opaque_zero();
         mfma_layer_multi<N::IN_KS, TPW, ST, D, FT>(
-            acc, [&](int c, int t) { return Frag<N::DT>::load(kstep(base, c), t, lane); },
-            [&](int c, int st) { return Slots<N::DT, N::IN_SLOTS>::b(slots[st], c); });
+            acc, [&](int c, int t) { return Frag<N::DT>::load(kstep(base, c), t, lane); }, bin);
     }
 #pragma unroll
     for (int st = 0; st < ST; ++st) split_store<N, TPW>(lds + st * ACT, acc[st], t0, lane);
@@ -1198,6 +1199,11 @@ __device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const floa
     }
     __syncthreads();  // every wave has read the activations the partials overwrite
     float* pl = reinterpret_cast<float*>(lds);
+    auto total = [&](int st, int i) {
+        float v = pl[((st * NW) * 16 + i) * 64 + lane];
+        for (int w = 1; w < NW; ++w) v += pl[((st * NW + w) * 16 + i) * 64 + lane];
+        return v;
+    };
 #pragma unroll
     for (int t = 0; t < N::NO; ++t) {
 #pragma unroll
@@ -1205,16 +1211,55 @@ __device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const floa
 #pragma unroll
             for (int i = 0; i < 16; ++i) pl[((st * NW + wave) * 16 + i) * 64 + lane] = part[st][t][i];
         __syncthreads();
+        if constexpr (OWN) {
+            if (wave < ST)
 #pragma unroll
-        for (int st = 0; st < ST; ++st)
+                for (int i = 0; i < 16; ++i) out[t][i] = total(wave, i);
+        } else {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                float v = pl[((st * NW) * 16 + i) * 64 + lane];
-                for (int w = 1; w < NW; ++w) v += pl[((st * NW + w) * 16 + i) * 64 + lane];
-                out[st * N::NO + t][i] = v;
-            }
+            for (int st = 0; st < ST; ++st)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) out[st * N::NO + t][i] = total(st, i);
+        }
         __syncthreads();
     }
+}
+
+// The split evaluation with the first-layer inputs of every sample tile in
+// each wave's slots; every wave receives every output tile.
+template <class N, int ST, int NW, int D>
+__device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const float* b0,
+                                                    const float (&slots)[ST][N::IN_SLOTS],
+                                                    f32x16 (&out)[ST * N::NO], int lane, int g, int wave,
+                                                    char* lds) {
+    run_net_split_core<N, ST, NW, D, false>(
+        P, b0, [&](int c, int st) { return Slots<N::DT, N::IN_SLOTS>::b(slots[st], c); }, out, lane, g, wave, lds);
+}
+
+// First-layer operands of one sample tile staged in LDS by the wave that owns
+// the tile (the others then carry no per-sample state).
+template <class N> struct SplitIn {
+    static constexpr int BYTES = N::IN_KS * 64 * (int)sizeof(typename Frag<N::DT>::type);
+};
+template <class N>
+__device__ __forceinline__ void split_stage_inputs(char* lds_in, const float (&slots)[N::IN_SLOTS], int lane) {
+    typedef typename Frag<N::DT>::type FT;
+    FT* d = reinterpret_cast<FT*>(lds_in);
+#pragma unroll
+    for (int c = 0; c < N::IN_KS; ++c) d[c * 64 + lane] = Slots<N::DT, N::IN_SLOTS>::b(slots, c);
+}
+
+// The split evaluation with the first-layer operands of sample tile st at
+// lds_in + st * SplitIn<N>::BYTES (written, before a barrier, by its owner
+// wave st); wave w < ST receives its own sample tile's output tiles.
+template <class N, int ST, int NW, int D>
+__device__ __forceinline__ void run_net_split_owned(const NetPtrs& P, const float* b0, const char* lds_in,
+                                                    f32x16 (&out)[N::NO], int lane, int g, int wave, char* lds) {
+    typedef typename Frag<N::DT>::type FT;
+    run_net_split_core<N, ST, NW, D, true>(
+        P, b0,
+        [&](int c, int st) { return reinterpret_cast<const FT*>(lds_in + st * SplitIn<N>::BYTES)[c * 64 + lane]; },
+        out, lane, g, wave, lds);
 }
 
 // Fragment source of a network read straight from global memory: the plain

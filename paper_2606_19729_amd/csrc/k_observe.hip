@@ -52,14 +52,22 @@ __device__ __forceinline__ ObsRow observe_inputs(const ObserveParams& p, long u,
     return w;
 }
 
+// Writes this lane's outputs: feature 2 s + g is register s % 16 of output
+// tile s / 16 (observations wider than 32 come in NO 32-row tiles).
+template <int D_O, int NO>
+__device__ __forceinline__ void observe_store(const ObserveParams& p, const ObsRow& w, const f32x16 (&o)[NO],
+                                              bool writer, int g) {
+#pragma unroll
+    for (int s = 0; s < 16 * NO; ++s) {
+        int f = 2 * s + g;
+        if (writer && w.valid && f < D_O) p.out[w.r * D_O + f] = o[s / 16][s % 16];
+    }
+}
 template <int D_O>
 __device__ __forceinline__ void observe_store(const ObserveParams& p, const ObsRow& w, const f32x16& o, bool writer,
                                               int g) {
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        int f = 2 * s + g;
-        if (writer && w.valid && f < D_O) p.out[w.r * D_O + f] = o[s];
-    }
+    const f32x16 one[1] = {o};
+    observe_store<D_O, 1>(p, w, one, writer, g);
 }
 
 // MODE kResident / kSplit / kDirect: sized for one belief (n rows); kStream:
@@ -142,9 +150,10 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
 // Observation networks of more than two hidden layers wider than 256 (the
 // depth of the paper's distilled samplers): a block of kObsSplitWaves waves
 // evaluates two 32-row tiles of one (candidate, step) group together, each
-// layer split over the waves (run_net_split_multi), every weight fragment
-// read from L2 serving both tiles.  Every wave forms both tiles' inputs (the
-// split evaluation hands every wave the same output); the first wave writes.
+// layer split over the waves (run_net_split_owned), every weight fragment
+// read from L2 serving both tiles.  Wave q forms tile q's inputs, stages
+// them in LDS and writes the tile's observations (observations wider than
+// 32 come in two output tiles).
 constexpr int kObsSplitWaves = 8, kObsSplitTiles = 2, kObsSplitDepth = 2;
 
 template <int DT, int WIDTH, int NHID>
@@ -157,11 +166,13 @@ __global__ __launch_bounds__(64 * kObsSplitWaves) void observe_split_kernel(Obse
     if constexpr (!obs_split<DT, WIDTH, NHID>()) {
         return;  // the other networks run in observe_kernel
     } else {
-    constexpr int ST = kObsSplitTiles;
-    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ), WIDTH / 32> NT;
+    constexpr int ST = kObsSplitTiles, NO = cdiv(D_O, 32);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_WZ), WIDTH / 32, NO> NT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
+    char* const in_lds = smem + ST * SplitLds<NT>::ACT;
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool owner = wave < ST;  // wave q forms and writes tile q of the group
     const int n_tiles = (p.N + 31) / 32;
     const int n_pairs = (n_tiles + ST - 1) / ST;
     const long n_units = (long)p.K * p.H * n_pairs;
@@ -169,34 +180,33 @@ __global__ __launch_bounds__(64 * kObsSplitWaves) void observe_split_kernel(Obse
     for (long u = blockIdx.x; u < n_units; u += gridDim.x) {
         const long grp = u / n_pairs;
         const int tp = (int)(u - grp * n_pairs);
-        float slots[ST][NT::IN_SLOTS];
-        ObsRow w[ST];
-#pragma unroll
-        for (int q = 0; q < ST; ++q) {
+        ObsRow w{};
+        if (owner) {
             // a tile past the last of the group reads row 0 and writes nothing
-            const int tile = tp * ST + q;
-            w[q] = observe_inputs<D_S, D_WZ>(p, grp * n_tiles + (tile < n_tiles ? tile : 0), n_tiles, g, col,
-                                             slots[q]);
-            w[q].valid = w[q].valid && tile < n_tiles;
+            const int tile = tp * ST + wave;
+            float slots[NT::IN_SLOTS];
+            w = observe_inputs<D_S, D_WZ>(p, grp * n_tiles + (tile < n_tiles ? tile : 0), n_tiles, g, col, slots);
+            w.valid = w.valid && tile < n_tiles;
+            split_stage_inputs<NT>(in_lds + wave * SplitIn<NT>::BYTES, slots, lane);
         }
-        __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
         const float* b0 = p.b0 + (size_t)(p.b0_stride ? grp : 0) * p.b0_stride;
-        f32x16 o[ST];
-        run_net_split_multi<NT, ST, kObsSplitWaves, kObsSplitDepth>(P, b0, slots, o, lane, g, wave, smem);
-#pragma unroll
-        for (int q = 0; q < ST; ++q) observe_store<D_O>(p, w[q], o[q], wave == 0, g);
+        __syncthreads();  // the owners' inputs are in LDS
+        f32x16 o[NO];
+        run_net_split_owned<NT, ST, kObsSplitWaves, kObsSplitDepth>(P, b0, in_lds, o, lane, g, wave, smem);
+        if (owner) observe_store<D_O, NO>(p, w, o, true, g);
     }
     }
 }
 
 #define OBS_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_split_kernel<DT, ds, dwz, dox, w, nh>
 
-template <int DT, int D_S, int D_WZ, int W, int NH>
+template <int DT, int D_S, int D_WZ, int D_O, int W, int NH>
 constexpr size_t obs_split_lds() {
     if constexpr (!obs_split<DT, W, NH>()) {
         return 0;
     } else {
-        return (size_t)kObsSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_S, 0, D_WZ), W / 32>>::ACT;
+        typedef Net<DT, W, NH, in_slots(DT, D_S, 0, D_WZ), W / 32, cdiv(D_O, 32)> NT;
+        return (size_t)kObsSplitTiles * (SplitLds<NT>::ACT + SplitIn<NT>::BYTES);
     }
 }
 
@@ -223,7 +233,7 @@ hipError_t launch_observe_split(int shape, int dt, const ObserveParams& p, hipSt
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
     case id * 2 + 0: {                                                                                      \
-        const size_t lds = obs_split_lds<DT_F32, ds, dwz, w, nh>();                                         \
+        const size_t lds = obs_split_lds<DT_F32, ds, dwz, dox, w, nh>();                                         \
         if (lds > 65536)                                                                                    \
             (void)hipFuncSetAttribute((const void*)OBS_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),      \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
@@ -232,7 +242,7 @@ hipError_t launch_observe_split(int shape, int dt, const ObserveParams& p, hipSt
         break;                                                                                              \
     }                                                                                                       \
     case id * 2 + 1: {                                                                                      \
-        const size_t lds = obs_split_lds<DT_BF16, ds, dwz, w, nh>();                                        \
+        const size_t lds = obs_split_lds<DT_BF16, ds, dwz, dox, w, nh>();                                        \
         if (lds > 65536)                                                                                    \
             (void)hipFuncSetAttribute((const void*)OBS_SK(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),     \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \

@@ -276,11 +276,12 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanParams p) {
 // Deep wide transition networks (more than two hidden layers wider than 256,
 // the depth of the paper's distilled samplers): a block of kPlanSplitWaves
 // waves advances kPlanSplitTiles 32-particle tiles of one candidate together,
-// each layer split over the waves (run_net_split_multi), so that every
-// weight fragment read from L2 serves all of the block's tiles.  Every wave
-// carries the tiles' states, noise and returns (the split evaluation hands
-// the same output to every wave); the first wave writes the results.  The
-// per-tile partial returns are those of plan_kernel.
+// each layer split over the waves (run_net_split_owned), so that every
+// weight fragment read from L2 serves all of the block's tiles.  Wave q
+// carries tile q's states, noise and return, stages the tile's first-layer
+// operands in LDS each step and receives the tile's output; the other waves
+// hold no per-particle state.  The per-tile partial returns are those of
+// plan_kernel.
 #ifndef VOILA_PLAN_SPLIT_WAVES
 #define VOILA_PLAN_SPLIT_WAVES 8
 #endif
@@ -298,6 +299,15 @@ constexpr bool plan_split() {
     return net_compiled(DT, WIDTH) && !generic_compiled(DT, WIDTH, NHID);
 }
 
+// LDS of the split rollout kernel beyond the activations: each owner wave's
+// first-layer operands and states ([slot][lane]), then the goal.
+template <class NT, int D_S>
+struct PlanSplitLds {
+    static constexpr int IN = kPlanSplitTiles * SplitIn<NT>::BYTES;
+    static constexpr int STATE = kPlanSplitTiles * state_slots(D_S) * 64 * 4;
+    static constexpr int BYTES = kPlanSplitTiles * SplitLds<NT>::ACT + IN + STATE + 64 * 4;
+};
+
 template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID>
 __global__ __launch_bounds__(64 * kPlanSplitWaves) void plan_split_kernel(PlanParams p) {
     if constexpr (!plan_split<DT, WIDTH, NHID>()) {
@@ -305,83 +315,92 @@ __global__ __launch_bounds__(64 * kPlanSplitWaves) void plan_split_kernel(PlanPa
     } else {
     constexpr int ST = kPlanSplitTiles;
     constexpr int SS = state_slots(D_S), SA = action_slots(D_A), SW = noise_slots(D_W);
-    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W), WIDTH / 32> NT;
+    // states wider than 32 come out of the network in two 32-row tiles: state
+    // slot s is register s % 16 of output tile s / 16
+    constexpr int NO = cdiv(D_S, 32);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, D_A, D_W), WIDTH / 32, NO> NT;
+    typedef PlanSplitLds<NT, D_S> L;
     extern __shared__ __attribute__((aligned(16))) char smem[];
+    char* const in_lds = smem + ST * SplitLds<NT>::ACT;
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // wave q < ST owns sample tile q of every group: its states (kept in LDS
+    // across the network, which needs every register), noise and return; the
+    // other waves only evaluate the network
+    const bool owner = wave < ST;
+    float* const st_lds = reinterpret_cast<float*>(in_lds + L::IN) + (owner ? wave : 0) * SS * 64 + lane;
+    float* const goal_lds = reinterpret_cast<float*>(in_lds + L::IN + L::STATE);
+    if (threadIdx.x < 64) goal_lds[threadIdx.x] = p.goal[threadIdx.x];
+    __syncthreads();
+    auto goal_at = [&](int s) { return goal_lds[2 * s + g]; };
+    // -|s - goal|^2 over this lane's state slots (both lane groups summed)
+    auto reward = [&](const float (&x)[SS]) {
+        float part = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SS; ++s)
+            if (2 * s + g < D_S) {
+                const float e = x[s] - goal_at(s);
+                part = __builtin_fmaf(e, e, part);
+            }
+        return -(part + __shfl_xor(part, 32));
+    };
     const int n_groups = (p.n_tiles + ST - 1) / ST;
     const long n_units = (long)p.K * n_groups;
     const NetPtrs P = net_ptrs(p.net.base, p.net);
-    float goal[SS];
-#pragma unroll
-    for (int s = 0; s < SS; ++s) goal[s] = 2 * s + g < D_S ? p.goal[2 * s + g] : 0.0f;
     for (long u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int k = (int)(u / n_groups);
         const int grp = (int)(u - (long)k * n_groups);
-        int i[ST];
-        bool valid[ST];
-        float st[ST][SS];
-#pragma unroll
-        for (int q = 0; q < ST; ++q) {
-            i[q] = (grp * ST + q) * 32 + col;
-            valid[q] = i[q] < p.N;
+        const int tile = grp * ST + (owner ? wave : 0);
+        const int i = tile * 32 + col;
+        const bool valid = owner && i < p.N;
+        if (owner) {
+            float st[SS];
 #pragma unroll
             for (int s = 0; s < SS; ++s) {
                 const int f = 2 * s + g;
-                st[q][s] = (valid[q] && f < D_S) ? p.states[(size_t)i[q] * D_S + f] : 0.0f;
+                st[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
             }
+#pragma unroll
+            for (int s = 0; s < SS; ++s) st_lds[s * 64] = st[s];
         }
-        __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-        float G[ST];
-#pragma unroll
-        for (int q = 0; q < ST; ++q) G[q] = 0.0f;
+        float G = 0.0f;
         double disc = 1.0;
-        uint32_t wnow[ST][SW], wnext[ST][SW];
         for (int t = 0; t < p.H; ++t) {
-            float slots[ST][NT::IN_SLOTS];
+            float r_cur = 0.0f;
+            if (owner) {
+                float slots[NT::IN_SLOTS], st[SS];
 #pragma unroll
-            for (int q = 0; q < ST; ++q) {
+                for (int s = 0; s < SS; ++s) st[s] = st_lds[s * 64];
 #pragma unroll
-                for (int s = 0; s < NT::IN_SLOTS; ++s) slots[q][s] = 0.0f;
+                for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
 #pragma unroll
-                for (int s = 0; s < SS; ++s) slots[q][s] = st[q][s];
-            }
-            if (D_A > 0) {
-                const kconst float* a = (const kconst float*)p.cands + ((size_t)k * p.H + t) * D_A;
+                for (int s = 0; s < SS; ++s) slots[s] = st[s];
+                if (D_A > 0) {
+                    const kconst float* a = (const kconst float*)p.cands + ((size_t)k * p.H + t) * D_A;
 #pragma unroll
-                for (int s = 0; s < SA; ++s) {
-                    const float a0 = 2 * s < D_A ? a[2 * s] : 0.0f;
-                    const float a1 = 2 * s + 1 < D_A ? a[2 * s + 1] : 0.0f;
-#pragma unroll
-                    for (int q = 0; q < ST; ++q) slots[q][SS + s] = g ? a1 : a0;
+                    for (int s = 0; s < SA; ++s) {
+                        const float a0 = 2 * s < D_A ? a[2 * s] : 0.0f;
+                        const float a1 = 2 * s + 1 < D_A ? a[2 * s + 1] : 0.0f;
+                        slots[SS + s] = g ? a1 : a0;
+                    }
                 }
-            }
-            if (p.noise) {
-#pragma unroll
-                for (int q = 0; q < ST; ++q) {
-                    const float* nsrc = p.noise + (((size_t)k * p.N + (valid[q] ? i[q] : 0)) * p.H + t) * D_W;
+                if (p.noise) {
+                    const float* nsrc = p.noise + (((size_t)k * p.N + (valid ? i : 0)) * p.H + t) * D_W;
 #pragma unroll
                     for (int s = 0; s < SW; ++s) {
                         const int f = noise_feature(s, g);
-                        slots[q][SS + SA + s] = f < D_W ? nsrc[f] : 0.0f;
+                        slots[SS + SA + s] = f < D_W ? nsrc[f] : 0.0f;
                     }
-                }
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-            } else {
-#pragma unroll
-                for (int q = 0; q < ST; ++q) {
-                    if ((t & 1) == 0) {
-                        philox_two_steps<SW>(wnow[q], wnext[q], p.key0, p.key1, (uint32_t)i[q],
-                                             p.crn ? 0u : (uint32_t)k, (uint32_t)t, 3u, g);
-                    } else {
-#pragma unroll
-                        for (int s = 0; s < SW; ++s) wnow[q][s] = wnext[q][s];
-                    }
+                } else {
+                    // this step's words only: nothing of the noise lives across the network
                     float nz[SW];
-                    noise_from_words<SW>(nz, wnow[q]);
+                    noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t,
+                                           3u, g);
 #pragma unroll
-                    for (int s = 0; s < SW; ++s) slots[q][SS + SA + s] = nz[s];
+                    for (int s = 0; s < SW; ++s) slots[SS + SA + s] = nz[s];
                 }
+                if (p.reward_at) r_cur = reward(st);
+                split_stage_inputs<NT>(in_lds + wave * SplitIn<NT>::BYTES, slots, lane);
             }
             const float* b0 = P.b0;
             if (N_ACT > 0) {
@@ -392,35 +411,31 @@ __global__ __launch_bounds__(64 * kPlanSplitWaves) void plan_split_kernel(PlanPa
                 }
                 b0 += (size_t)a * p.net.b0_stride;
             }
-            float r_cur[ST];
+            __syncthreads();  // the owners' inputs are in LDS
+            f32x16 out[NO];
+            run_net_split_owned<NT, ST, kPlanSplitWaves, kPlanSplitDepth>(P, b0, in_lds, out, lane, g, wave, smem);
+            if (owner) {
+                float st[SS];
 #pragma unroll
-            for (int q = 0; q < ST; ++q) r_cur[q] = p.reward_at ? reward_to(st[q], goal, SS, D_S, g) : 0.0f;
-            f32x16 out[ST];
-            run_net_split_multi<NT, ST, kPlanSplitWaves, kPlanSplitDepth>(P, b0, slots, out, lane, g, wave, smem);
+                for (int s = 0; s < SS; ++s) st[s] = st_lds[s * 64] + out[s / 16][s % 16];
 #pragma unroll
-            for (int q = 0; q < ST; ++q) {
-#pragma unroll
-                for (int s = 0; s < SS; ++s) st[q][s] += out[q][s];
-                if (p.traj && wave == 0 && valid[q]) {
-                    float* dst = p.traj + (((size_t)k * p.N + i[q]) * p.H + t) * D_S;
+                for (int s = 0; s < SS; ++s) st_lds[s * 64] = st[s];
+                if (p.traj && valid) {
+                    float* dst = p.traj + (((size_t)k * p.N + i) * p.H + t) * D_S;
 #pragma unroll
                     for (int s = 0; s < SS; ++s)
-                        if (2 * s + g < D_S) dst[2 * s + g] = st[q][s];
+                        if (2 * s + g < D_S) dst[2 * s + g] = st[s];
                 }
-                const float r = p.reward_at ? r_cur[q] : reward_to(st[q], goal, SS, D_S, g);
-                G[q] = __builtin_fmaf((float)disc, r, G[q]);
+                const float r = p.reward_at ? r_cur : reward(st);
+                G = __builtin_fmaf((float)disc, r, G);
             }
             disc *= p.gamma;
         }
-        if (wave == 0) {
-#pragma unroll
-            for (int q = 0; q < ST; ++q) {
-                if (p.returns && g == 0 && valid[q]) p.returns[(size_t)k * p.N + i[q]] = G[q];
-                const float contrib = valid[q] ? (p.belief_w ? (float)p.belief_w[i[q]] * G[q] : G[q]) : 0.0f;
-                const float tot = sum32(contrib);
-                const int tile = grp * ST + q;
-                if (lane == 0 && tile < p.n_tiles) p.partials[(size_t)k * p.n_tiles + tile] = tot;
-            }
+        if (owner) {
+            if (p.returns && g == 0 && valid) p.returns[(size_t)k * p.N + i] = G;
+            const float contrib = valid ? (p.belief_w ? (float)p.belief_w[i] * G : G) : 0.0f;
+            const float tot = sum32(contrib);
+            if (lane == 0 && tile < p.n_tiles) p.partials[(size_t)k * p.n_tiles + tile] = tot;
         }
     }
     }
@@ -523,7 +538,8 @@ constexpr size_t plan_split_lds() {
     if constexpr (!plan_split<DT, W, NH>()) {
         return 0;
     } else {
-        return (size_t)kPlanSplitTiles * SplitLds<Net<DT, W, NH, in_slots(DT, D_S, D_A, D_W), W / 32>>::ACT;
+        typedef Net<DT, W, NH, in_slots(DT, D_S, D_A, D_W), W / 32, cdiv(D_S, 32)> NT;
+        return (size_t)PlanSplitLds<NT, D_S>::BYTES;
     }
 }
 

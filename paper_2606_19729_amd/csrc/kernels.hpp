@@ -15,9 +15,10 @@ namespace voila {
     X(1, 16, 0, 4, 16, 32, 32, 256, 3) /* realistic */    \
     X(2, 4, 0, 4, 4, 2, 2, 64, 2)      /* small, continuous actions */ \
     X(3, 4, 5, 0, 4, 2, 2, 1024, 2)    /* small, hidden width 1024 */ \
-    X(4, 4, 5, 0, 4, 2, 2, 1024, 4)    /* small, four hidden layers of 1024 (transition network only) */
+    X(4, 4, 5, 0, 4, 2, 2, 1024, 4)    /* small, four hidden layers of 1024 (no likelihood network) */ \
+    X(5, 45, 6, 0, 45, 36, 36, 1024, 4) /* target finding: 45-d state, six actions, 36 lidar bins */
 
-constexpr int kNumShapes = 5;
+constexpr int kNumShapes = 6;
 
 struct ShapeInfo {
     int d_s, n_actions, d_a, d_w, d_o, d_wz, width, n_hidden;
@@ -45,7 +46,7 @@ struct PlanParams {
     double gamma;
     uint32_t key0, key1;
     int crn, reward_at;
-    float goal[32];
+    float goal[64];
 };
 
 struct QReduceParams {

@@ -187,6 +187,28 @@ def deep(seed: int = 6, N: int = 128, K: int = 32, H: int = 10, compute: str = "
     return w
 
 
+def target_finding(seed: int = 16, N: int = 128, K: int = 32, H: int = 10, compute: str = "bf16",
+                   with_obs: bool = True) -> Workload:
+    """The paper's target-finding task shapes (Sec. 5) with random weights: a
+    45-dimensional state, six discrete actions, observations of 36 lidar
+    bins; transition and observation networks of four hidden layers of 1024
+    (the distilled samplers' depth and width), their latent noise of the
+    sampled variable's dimension (45 and 36); no likelihood network.  States
+    ~ N(0, 1), goal ~ N(0, 1/4) per feature, actions uniform."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    trans = random_mlp(rng, [45 + 6 + 45] + [1024] * 4 + [45])
+    model = Model(d_s=45, n_actions=6, d_a=0, d_w=45, d_o=36, d_wz=36, trans=trans, obs=[], lik=[])
+    states = rng.standard_normal((N, 45)).astype(np.float32)
+    cands = rng.integers(0, 6, size=(K, H)).astype(np.int32)
+    goal = (0.5 * rng.standard_normal(45)).astype(np.float32)
+    w = _finish("target_finding", rng, model, states, cands, 0.95, goal, 2, 1.0, compute)
+    if with_obs:
+        # drawn after everything else, so the other inputs do not depend on it
+        w.model.obs = random_mlp(np.random.Generator(np.random.PCG64(seed + 1000)),
+                                 [45 + 6 + 36] + [1024] * 4 + [36])
+    return w
+
+
 def batched(seed: int = 4, n_instances: int = 64, n_range=(256, 8192), h_range=(5, 30),
             k_range=(64, 1024), compute: str = "bf16") -> List[Workload]:
     """Independent small-network instances with uneven sizes."""
