@@ -1135,14 +1135,14 @@ __device__ __forceinline__ void run_net_flat(Src& src, const NetPtrs& P, const f
 // sample tiles, so each weight fragment read from L2 serves ST tiles.  The
 // activations of sample tile st live at lds + st * ACT; the output layer's
 // per-wave partials reuse that space.  bin(c, st) is the first-layer B
-// operand of sample tile st at k-step c.  With OWN false, out[st * NO + t] is
-// output tile t of sample tile st in every wave; with OWN true, wave w < ST
-// receives only its own sample tile's (out[t] of sample tile w) and the other
-// waves none.  D k-steps of weight fragments are in flight.
-template <class N, int ST, int NW, int D, bool OWN, class BIN>
-__device__ __forceinline__ void run_net_split_core(const NetPtrs& P, const float* b0, BIN&& bin,
-                                                   f32x16 (&out)[OWN ? N::NO : ST * N::NO], int lane, int g,
-                                                   int wave, char* lds) {
+// operand of sample tile st at k-step c.  The outputs go to sink(st, t, i,
+// v): value i of output tile t of sample tile st; with OWN false every wave
+// receives every sample tile's, with OWN true wave w < ST only its own
+// sample tile's (st = w) and the other waves none.  D k-steps of weight
+// fragments are in flight.
+template <class N, int ST, int NW, int D, bool OWN, class BIN, class SINK>
+__device__ __forceinline__ void run_net_split_core(const NetPtrs& P, const float* b0, BIN&& bin, SINK&& sink,
+                                                   int lane, int g, int wave, char* lds) {
     static_assert(N::HT % NW == 0 && N::HID_KS % NW == 0 && N::CT == N::HT, "split needs a layered network");
     static_assert(!OWN || ST <= NW, "every sample tile needs an owner wave");
     constexpr int TPW = N::HT / NW, KQ = N::HID_KS / NW;
@@ -1152,6 +1152,12 @@ __device__ __forceinline__ void run_net_split_core(const NetPtrs& P, const float
     typedef FragIdx<N> FI;
     const int t0 = wave * TPW;
     auto kstep = [&](const char* base, int c) { return base + (size_t)c * N::HT * N::FRAG_BYTES + opaque_zero(); };
+    // one base register per sample tile's activations, the k-steps as
+    // immediate offsets (a folded constant base past 64 KB would need one
+    // address register per k-step, which the compiler hoists and spills)
+    char* act[ST];
+#pragma unroll
+    for (int st = 0; st < ST; ++st) act[st] = lds + st * ACT + opaque_zero();
     f32x16 acc[ST][TPW];
 #pragma unroll
     for (int st = 0; st < ST; ++st) init_bias<TPW>(acc[st], b0 + 32 * t0 + opaque_zero(), g);
@@ -1161,7 +1167,7 @@ __device__ __forceinline__ void run_net_split_core(const NetPtrs& P, const float
             acc, [&](int c, int t) { return Frag<N::DT>::load(kstep(base, c), t, lane); }, bin);
     }
 #pragma unroll
-    for (int st = 0; st < ST; ++st) split_store<N, TPW>(lds + st * ACT, acc[st], t0, lane);
+    for (int st = 0; st < ST; ++st) split_store<N, TPW>(act[st], acc[st], t0, lane);
     __syncthreads();
     static_for<N::NHID - 1>([&](auto li) {
         constexpr int l = decltype(li)::value + 1;
@@ -1170,10 +1176,10 @@ __device__ __forceinline__ void run_net_split_core(const NetPtrs& P, const float
         const char* base = P.f0 + (size_t)FI::hidden(l, 0, t0) * N::FRAG_BYTES + opaque_zero();
         mfma_layer_multi<N::HID_KS, TPW, ST, D, FT>(
             acc, [&](int c, int t) { return Frag<N::DT>::load(kstep(base, c), t, lane); },
-            [&](int c, int st) { return split_act<N>(lds + st * ACT, c, lane); });
+            [&](int c, int st) { return split_act<N>(act[st], c, lane); });
         __syncthreads();
 #pragma unroll
-        for (int st = 0; st < ST; ++st) split_store<N, TPW>(lds + st * ACT, acc[st], t0, lane);
+        for (int st = 0; st < ST; ++st) split_store<N, TPW>(act[st], acc[st], t0, lane);
         __syncthreads();
     });
     // the output layer: each wave multiplies its k-steps for every output
@@ -1195,7 +1201,7 @@ __device__ __forceinline__ void run_net_split_core(const NetPtrs& P, const float
             [&](int c, int t) {
                 return Frag<N::DT>::load(base + (size_t)(t * N::HID_KS + c) * N::FRAG_BYTES + opaque_zero(), 0, lane);
             },
-            [&](int c, int st) { return split_act<N>(lds + st * ACT, k0 + c, lane); });
+            [&](int c, int st) { return split_act<N>(act[st], k0 + c, lane); });
     }
     __syncthreads();  // every wave has read the activations the partials overwrite
     float* pl = reinterpret_cast<float*>(lds);
@@ -1214,12 +1220,12 @@ __device__ __forceinline__ void run_net_split_core(const NetPtrs& P, const float
         if constexpr (OWN) {
             if (wave < ST)
 #pragma unroll
-                for (int i = 0; i < 16; ++i) out[t][i] = total(wave, i);
+                for (int i = 0; i < 16; ++i) sink(wave, t, i, total(wave, i));
         } else {
 #pragma unroll
             for (int st = 0; st < ST; ++st)
 #pragma unroll
-                for (int i = 0; i < 16; ++i) out[st * N::NO + t][i] = total(st, i);
+                for (int i = 0; i < 16; ++i) sink(st, t, i, total(st, i));
         }
         __syncthreads();
     }
@@ -1233,7 +1239,8 @@ __device__ __forceinline__ void run_net_split_multi(const NetPtrs& P, const floa
                                                     f32x16 (&out)[ST * N::NO], int lane, int g, int wave,
                                                     char* lds) {
     run_net_split_core<N, ST, NW, D, false>(
-        P, b0, [&](int c, int st) { return Slots<N::DT, N::IN_SLOTS>::b(slots[st], c); }, out, lane, g, wave, lds);
+        P, b0, [&](int c, int st) { return Slots<N::DT, N::IN_SLOTS>::b(slots[st], c); },
+        [&](int st, int t, int i, float v) { out[st * N::NO + t][i] = v; }, lane, g, wave, lds);
 }
 
 // First-layer operands of one sample tile staged in LDS by the wave that owns
@@ -1251,15 +1258,19 @@ __device__ __forceinline__ void split_stage_inputs(char* lds_in, const float (&s
 
 // The split evaluation with the first-layer operands of sample tile st at
 // lds_in + st * SplitIn<N>::BYTES (written, before a barrier, by its owner
-// wave st); wave w < ST receives its own sample tile's output tiles.
+// wave st); wave w < ST receives its own sample tile's output tiles as
+// out[t][i] (plain scalars: no vector register tuple is rebuilt per value).
 template <class N, int ST, int NW, int D>
 __device__ __forceinline__ void run_net_split_owned(const NetPtrs& P, const float* b0, const char* lds_in,
-                                                    f32x16 (&out)[N::NO], int lane, int g, int wave, char* lds) {
+                                                    float (&out)[N::NO][16], int lane, int g, int wave, char* lds) {
     typedef typename Frag<N::DT>::type FT;
+    const FT* in[ST];
+#pragma unroll
+    for (int st = 0; st < ST; ++st)
+        in[st] = reinterpret_cast<const FT*>(lds_in + st * SplitIn<N>::BYTES + opaque_zero());
     run_net_split_core<N, ST, NW, D, true>(
-        P, b0,
-        [&](int c, int st) { return reinterpret_cast<const FT*>(lds_in + st * SplitIn<N>::BYTES)[c * 64 + lane]; },
-        out, lane, g, wave, lds);
+        P, b0, [&](int c, int st) { return in[st][c * 64 + lane]; },
+        [&](int, int t, int i, float v) { out[t][i] = v; }, lane, g, wave, lds);
 }
 
 // Fragment source of a network read straight from global memory: the plain

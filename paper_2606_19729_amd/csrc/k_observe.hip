@@ -54,9 +54,9 @@ __device__ __forceinline__ ObsRow observe_inputs(const ObserveParams& p, long u,
 
 // Writes this lane's outputs: feature 2 s + g is register s % 16 of output
 // tile s / 16 (observations wider than 32 come in NO 32-row tiles).
-template <int D_O, int NO>
-__device__ __forceinline__ void observe_store(const ObserveParams& p, const ObsRow& w, const f32x16 (&o)[NO],
-                                              bool writer, int g) {
+template <int D_O, int NO, class T>
+__device__ __forceinline__ void observe_store(const ObserveParams& p, const ObsRow& w, const T (&o)[NO], bool writer,
+                                              int g) {
 #pragma unroll
     for (int s = 0; s < 16 * NO; ++s) {
         int f = 2 * s + g;
@@ -67,7 +67,7 @@ template <int D_O>
 __device__ __forceinline__ void observe_store(const ObserveParams& p, const ObsRow& w, const f32x16& o, bool writer,
                                               int g) {
     const f32x16 one[1] = {o};
-    observe_store<D_O, 1>(p, w, one, writer, g);
+    observe_store<D_O, 1, f32x16>(p, w, one, writer, g);
 }
 
 // MODE kResident / kSplit / kDirect: sized for one belief (n rows); kStream:
@@ -191,9 +191,9 @@ __global__ __launch_bounds__(64 * kObsSplitWaves) void observe_split_kernel(Obse
         }
         const float* b0 = p.b0 + (size_t)(p.b0_stride ? grp : 0) * p.b0_stride;
         __syncthreads();  // the owners' inputs are in LDS
-        f32x16 o[NO];
+        float o[NO][16];
         run_net_split_owned<NT, ST, kObsSplitWaves, kObsSplitDepth>(P, b0, in_lds, o, lane, g, wave, smem);
-        if (owner) observe_store<D_O, NO>(p, w, o, true, g);
+        if (owner) observe_store<D_O, NO, float[16]>(p, w, o, true, g);
     }
     }
 }

@@ -412,7 +412,7 @@ __global__ __launch_bounds__(64 * kPlanSplitWaves) void plan_split_kernel(PlanPa
                 b0 += (size_t)a * p.net.b0_stride;
             }
             __syncthreads();  // the owners' inputs are in LDS
-            f32x16 out[NO];
+            float out[NO][16];
             run_net_split_owned<NT, ST, kPlanSplitWaves, kPlanSplitDepth>(P, b0, in_lds, out, lane, g, wave, smem);
             if (owner) {
                 float st[SS];
