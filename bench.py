@@ -182,15 +182,15 @@ def bench_batched(V, torch, reps):
 
 def bench_deep(V, torch, reps, paper_dims=False):
     """Four hidden layers of 1024 in bfloat16 (the depth and width of the
-    paper's distilled samplers), run by the split rollout kernel: 256
-    candidates x 4096 particles x 20 steps, plan and per-step observations;
-    with the small workload's dimensions, or with `paper_dims` the paper's
-    target-finding task (45-dimensional state, six actions, 36 lidar
-    bins)."""
+    paper's distilled samplers), run by the split rollout kernel: 4096
+    particles x 20 steps, plan and per-step observations; with the small
+    workload's dimensions (256 candidates), or with `paper_dims` the paper's
+    target-finding task (45-dimensional state, six actions, 36 lidar bins,
+    1024 candidates) and its belief update through the 3 x 256 likelihood."""
     import workloads
     dev = torch.device("cuda", 0)
     if paper_dims:
-        w = workloads.target_finding(seed=16, N=4096, K=256, H=20)
+        w = workloads.target_finding(seed=16, N=4096, K=1024, H=20)
     else:
         w = workloads.deep(seed=8, N=4096, K=256, H=20, with_obs=True)
     mb = V.Model(w.model, compute="bf16")
@@ -226,8 +226,26 @@ def bench_deep(V, torch, reps, paper_dims=False):
     dims = {"d_s": w.model.d_s, "n_actions": w.model.n_actions, "d_w": w.model.d_w, "d_o": w.model.d_o,
             "d_wz": w.model.d_wz}
     otf = ofl * steps / (oms / 1e3) / 1e12
+    upd = None
+    if w.model.lik:
+        # the belief update with the paper's 3 x 256 likelihood: proposals
+        # through the split transition kernel, likelihood of the proposals,
+        # normalisation and resampling (inputs resident, one observation)
+        o = torch.as_tensor((0.5 * np.random.default_rng(1).standard_normal(w.model.d_o)).astype(np.float32),
+                            device=dev)
+        a = torch.tensor([w.update_action], dtype=torch.int32, device=dev)
+        uws = torch.empty(int(V.lib.voila_update_workspace_size(mb.handle, w.N)), dtype=torch.uint8, device=dev)
+        V.update(mb, S, a, o, lam=w.lam, seed=w.update_seed, U=w.resample_u, workspace=uws)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for r in range(reps):
+            V.update(mb, S, a, o, lam=w.lam, seed=w.update_seed + r, U=w.resample_u, workspace=uws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ums = e0.elapsed_time(e1) / reps
+        upd = {"N": w.N, "likelihood_hidden": [256] * 3, "ms": ums, "particles_per_s": w.N / (ums / 1e3)}
     mb.close()
-    return {"K": w.K, "N": w.N, "H": w.H, "hidden": [1024] * 4, "dims": dims, "plan_ms": ms,
+    return {"K": w.K, "N": w.N, "H": w.H, "hidden": [1024] * 4, "dims": dims, "update": upd, "plan_ms": ms,
             "rollout_steps_per_s": steps / (ms / 1e3), "achieved_tflops": tflops,
             "mfma_frac_bf16_peak": tflops / PEAK_BF16_TFLOPS, "flop_per_rollout_step": fps,
             "observe": {"ms": oms, "observations_per_s": steps / (oms / 1e3), "flop_per_observation": ofl,

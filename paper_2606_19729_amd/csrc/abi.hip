@@ -298,6 +298,12 @@ struct voila_model_s {
     int device = 0, shape = -1, dt = DT_F32, cus = 1;
     int d_s = 0, n_actions = 0, d_a = 0, d_w = 0, d_o = 0, d_wz = 0, width = 0, n_hidden = 0;
     bool has_obs = false, has_lik = false;
+    // a likelihood network of its own shape (VOILA_LIK_SHAPES): hidden width
+    // lik_width; such models update beliefs through the split proposal and
+    // likelihood-rows kernels, and the other likelihood users refuse them
+    bool lik_split = false;
+    int lik_width = 0;
+    int lik_bpc = 1;
     char* mem = nullptr;
     NetBlob trans_plan{}, trans_upd{}, obs{}, lik{}, lik_nce{};
     const float* fold_w_trans = nullptr;
@@ -326,6 +332,8 @@ struct voila_model_s {
 };
 
 namespace {
+constexpr const char* kLikSplitOnlyUpdate =
+    "a likelihood network of another shape than the samplers' is used by the belief update only";
 constexpr int kGradWaves = 4;
 size_t grad_lds_bytes(const voila_model_s* m) {
     return (size_t)m->grad_fwd.bytes + m->grad_bwd.bytes + (size_t)kGradWaves * 32 * 129 * sizeof(float);
@@ -401,17 +409,19 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
                   si.width == T.width() && si.n_hidden == T.n_layers - 1;
         if (Z.present()) ok = ok && si.d_wz == desc->d_wz && si.d_o == desc->d_o && Z.width() == si.width &&
                               Z.n_layers - 1 == si.n_hidden;
-        if (L.present()) ok = ok && si.d_o == desc->d_o && L.width() == si.width && L.n_layers - 1 == si.n_hidden;
+        const int lw = lik_shape_width(s) ? lik_shape_width(s) : si.width;
+        const int lnh = lik_shape_hidden(s) ? lik_shape_hidden(s) : si.n_hidden;
+        if (L.present()) ok = ok && si.d_o == desc->d_o && L.width() == lw && L.n_layers - 1 == lnh;
         if (ok) {
             shape = s;
             break;
         }
     }
     if (shape < 0) return fail(VOILA_ERR_UNSUPPORTED, "no compiled kernel for this network shape");
-    if (plan_split_shape(shape, DT_BF16) && L.present())
+    if (plan_split_shape(shape, DT_BF16) && L.present() && !lik_shape_width(shape))
         return fail(VOILA_ERR_UNSUPPORTED,
                     "networks wider than 256 with more than two hidden layers: transition and observation "
-                    "networks only (no likelihood network)");
+                    "networks only (no likelihood network of the same shape)");
     if (T.width() > 256 && desc->compute != VOILA_BF16)
         return fail(VOILA_ERR_UNSUPPORTED, "hidden widths above 256 run in bfloat16 only");
 
@@ -435,7 +445,9 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->n_hidden = T.n_layers - 1;
     m->has_obs = Z.present();
     m->has_lik = L.present();
-    const int dt = m->dt, W = m->width;
+    m->lik_split = L.present() && lik_shape_width(shape) > 0;
+    m->lik_width = L.present() ? L.width() : 0;
+    const int dt = m->dt, W = m->width, LW = m->lik_width;
 
     // first-layer bias variants of the plan: one per discrete action (the
     // one-hot column folded in), or the plain bias for continuous actions
@@ -466,7 +478,7 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
         blobs.emplace_back();
     }
     if (L.present()) {
-        std::vector<float> b0(L.b[0], L.b[0] + W);
+        std::vector<float> b0(L.b[0], L.b[0] + LW);
         SlotMap ml{m->d_s, 0, 0, m->d_s, m->d_s};
         blobs.push_back(pack_net(L, dt, lik_in_slots(shape, dt), ml, b0, 1, m->lik));
     } else {
@@ -485,15 +497,15 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     }
     // the likelihood network with its first layer over the observation
     // columns (state and action folded per row) for the contrastive objective
-    if (L.present()) {
-        std::vector<float> b0(L.b[0], L.b[0] + W);
+    if (L.present() && !m->lik_split) {
+        std::vector<float> b0(L.b[0], L.b[0] + LW);
         SlotMap mo{m->d_o, 0, 0, 0, 0, m->d_s + aw};
         blobs.push_back(pack_net(L, dt, nce_in_slots(shape, dt), mo, b0, 1, m->lik_nce));
     } else {
         blobs.emplace_back();
     }
     // transposed likelihood pack for the objective's parameter derivative
-    m->has_nce_grad = L.present() && nce_grad_supported(shape) && dt == DT_F32;
+    m->has_nce_grad = L.present() && !m->lik_split && nce_grad_supported(shape) && dt == DT_F32;
     if (m->has_nce_grad) {
         blobs.push_back(pack_bwd(L, m->lik_bwd));
         for (int l = 0; l < L.n_layers; ++l) m->n_lik_params += L.dims[l + 1] * L.dims[l] + L.dims[l + 1];
@@ -501,7 +513,7 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
         blobs.emplace_back();
     }
     // the layered form of the same derivative (hidden width 256)
-    m->has_nce_wide = L.present() && nce_wide_supported(shape);
+    m->has_nce_wide = L.present() && !m->lik_split && nce_wide_supported(shape);
     if (m->has_nce_wide) {
         SlotMap mo{m->d_o, 0, 0, 0, 0, m->d_s + aw};
         blobs.push_back(pack_nce_wide(L, dt, nce_in_slots(shape, dt), mo));
@@ -526,15 +538,15 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     if (L.present()) {
         m->nf_lik = aw + m->d_o;
         folds.push_back(fold_columns(L, m->d_s, aw + m->d_o, dt));
-        folds.push_back(std::vector<float>(L.b[0], L.b[0] + W));
+        folds.push_back(std::vector<float>(L.b[0], L.b[0] + LW));
         std::vector<float> fa = fold_columns(L, m->d_s, aw, dt), fs = fold_columns(L, 0, m->d_s, dt);
-        std::vector<float> fn((size_t)W * (aw + m->d_s));
-        for (int o = 0; o < W; ++o) {
+        std::vector<float> fn((size_t)LW * (aw + m->d_s));
+        for (int o = 0; o < LW; ++o) {
             for (int c = 0; c < aw; ++c) fn[(size_t)o * (aw + m->d_s) + c] = fa[(size_t)o * aw + c];
             for (int c = 0; c < m->d_s; ++c) fn[(size_t)o * (aw + m->d_s) + aw + c] = fs[(size_t)o * m->d_s + c];
         }
         folds.push_back(fn);
-        folds.push_back(std::vector<float>(L.W[L.n_layers - 1], L.W[L.n_layers - 1] + W));
+        folds.push_back(std::vector<float>(L.W[L.n_layers - 1], L.W[L.n_layers - 1] + LW));
     } else {
         folds.emplace_back();
         folds.emplace_back();
@@ -602,7 +614,8 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) m->cus = prop.multiProcessorCount;
     m->plan_bpc = plan_blocks_per_cu(shape, dt);
-    m->prop_bpc = propose_blocks_per_cu(shape, dt);
+    m->prop_bpc = m->lik_split ? propose_split_blocks_per_cu(shape, dt) : propose_blocks_per_cu(shape, dt);
+    if (m->lik_split) m->lik_bpc = lik_rows_blocks_per_cu(shape, dt);
     m->obs_bpc = observe_blocks_per_cu(shape, dt);
     m->obs_roll_bpc = observe_rollout_blocks_per_cu(shape, dt);
     m->pw_bpc = pw_lik_blocks_per_cu(shape, dt);
@@ -747,14 +760,14 @@ UpdateWs carve_update(char* base, int width, int N, int d_s) {
 // likelihood, the observation) read from device memory and folded in, so the
 // fold follows whatever those buffers hold when the stream reaches it.
 FoldStepsParams fold_one(voila_model_t m, const float* w, const float* b, int nf, const void* d_action,
-                         const float* d_obs, float* out, int32_t* d_status) {
+                         const float* d_obs, float* out, int32_t* d_status, int width = 0) {
     FoldStepsParams f{};
     f.w = w;
     f.b = b;
     f.out = out;
     f.cands = d_action;
     f.obs = d_obs;
-    f.width = m->width;
+    f.width = width ? width : m->width;
     f.nf = nf;
     f.rows = 1;
     f.n_actions = m->n_actions;
@@ -791,7 +804,8 @@ voila_status_t voila_update(voila_model_t m, const float* d_states, const double
     VOILA_CHECK_HIP(launch_fold_steps(
         fold_one(m, m->fold_w_trans, m->fold_b_trans, m->nf_trans, d_action, nullptr, w.b0_trans, d_status), s));
     VOILA_CHECK_HIP(launch_fold_steps(
-        fold_one(m, m->fold_w_lik, m->fold_b_lik, m->nf_lik, d_action, d_obs, w.b0_lik, d_status), s));
+        fold_one(m, m->fold_w_lik, m->fold_b_lik, m->nf_lik, d_action, d_obs, w.b0_lik, d_status, m->lik_width),
+        s));
     ProposeParams p{};
     p.trans = m->trans_upd;
     p.lik = m->lik;
@@ -809,10 +823,17 @@ voila_status_t voila_update(voila_model_t m, const float* d_states, const double
     p.key0 = (uint32_t)(o->seed & 0xffffffffu);
     p.key1 = (uint32_t)(o->seed >> 32);
     const int n_tiles = (N + 31) / 32;
-    const int tpb = pass_tiles_per_block(m->shape);
-    const int want = (n_tiles + tpb - 1) / tpb;
-    const int cap = m->cus * m->prop_bpc;
-    VOILA_CHECK_HIP(launch_propose(m->shape, m->dt, p, want < cap ? want : cap, s));
+    if (m->lik_split) {
+        const int want = (n_tiles + kPropSplitTiles - 1) / kPropSplitTiles, cap = m->cus * m->prop_bpc;
+        VOILA_CHECK_HIP(launch_propose_split(m->shape, m->dt, p, want < cap ? want : cap, s));
+        const int lcap = m->cus * m->lik_bpc;
+        VOILA_CHECK_HIP(launch_lik_rows(m->shape, m->dt, p, n_tiles < lcap ? n_tiles : lcap, s));
+    } else {
+        const int tpb = pass_tiles_per_block(m->shape);
+        const int want = (n_tiles + tpb - 1) / tpb;
+        const int cap = m->cus * m->prop_bpc;
+        VOILA_CHECK_HIP(launch_propose(m->shape, m->dt, p, want < cap ? want : cap, s));
+    }
     if (N > kNormResMaxN) {
         LargeResParams r{};
         r.x = w.x;
@@ -1127,6 +1148,7 @@ voila_status_t voila_pw_step(voila_model_t m, const float* d_succ, int32_t T, co
                              int32_t* d_status, void* stream) {
     if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
     if (!m->has_obs || !m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model needs observation and likelihood networks");
+    if (m->lik_split) return fail(VOILA_ERR_UNSUPPORTED, kLikSplitOnlyUpdate);
     if (!o) return fail(VOILA_ERR_INVALID_ARG, "NULL options");
     if (T < 0 || M < 0) return fail(VOILA_ERR_INVALID_ARG, "T and M must be >= 0");
     if (o->capacity < 1) return fail(VOILA_ERR_INVALID_ARG, "capacity must be >= 1");
@@ -1257,6 +1279,7 @@ voila_status_t voila_info_nce(voila_model_t m, const float* d_states, const void
                               float* d_grad_out, double* d_loss_out, int32_t* d_status, void* stream) {
     if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
     if (!m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model has no likelihood network");
+    if (m->lik_split) return fail(VOILA_ERR_UNSUPPORTED, kLikSplitOnlyUpdate);
     if (B < 1) return fail(VOILA_ERR_INVALID_ARG, "B must be >= 1");
     if (B > kNceMaxBatch) return fail(VOILA_ERR_UNSUPPORTED, "B must be <= 32768");
     if (!d_states || !d_actions || !d_obs) return fail(VOILA_ERR_INVALID_ARG, "NULL device buffer");
@@ -1693,6 +1716,7 @@ voila_status_t voila_plan_closed_loop(voila_model_t m, const float* d_states, in
                                       void* stream) {
     if (!m) return fail(VOILA_ERR_INVALID_ARG, "NULL model");
     if (!m->has_obs || !m->has_lik) return fail(VOILA_ERR_INVALID_ARG, "the model needs observation and likelihood networks");
+    if (m->lik_split) return fail(VOILA_ERR_UNSUPPORTED, kLikSplitOnlyUpdate);
     if (!o || !o->h_goal) return fail(VOILA_ERR_INVALID_ARG, "NULL options or goal");
     if (!tree_sizes_ok(N, A, o->n_obs, K, H))
         return fail(VOILA_ERR_INVALID_ARG, "N, A, n_obs, K >= 1, H >= 0, and the branch and rollout counts must fit in 31 bits");

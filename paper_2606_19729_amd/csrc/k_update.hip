@@ -226,6 +226,102 @@ __global__ __launch_bounds__(512) void propose_batch_kernel(BatchProposeParams b
     }
 }
 
+// Proposals of models whose transition network runs in the split evaluation
+// (more than two hidden layers wider than 256): a block of kPropSplitWaves
+// waves advances two 32-particle tiles, every layer split over the waves
+// (run_net_split_owned); wave q forms tile q's inputs [s, w] (noise as in
+// propose_tile) and writes its proposals s + f_T(s, a, w).
+constexpr int kPropSplitWaves = 8, kPropSplitDepth = 2;
+
+template <int DT, int D_S, int D_W, int WIDTH, int NHID>
+__global__ __launch_bounds__(64 * kPropSplitWaves) void propose_split_kernel(ProposeParams p) {
+    if constexpr (!net_compiled(DT, WIDTH) || generic_compiled(DT, WIDTH, NHID)) {
+        return;  // the other networks run in propose_kernel
+    } else {
+    constexpr int ST = kPropSplitTiles, SS = state_slots(D_S), SW = noise_slots(D_W), NO = cdiv(D_S, 32);
+    typedef Net<DT, WIDTH, NHID, in_slots(DT, D_S, 0, D_W), WIDTH / 32, NO> NT;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    char* const in_lds = smem + ST * SplitLds<NT>::ACT;
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool owner = wave < ST;
+    const int n_groups = ((p.N + 31) / 32 + ST - 1) / ST;
+    const NetPtrs P = net_ptrs(p.trans.base, p.trans);
+    for (int u = blockIdx.x; u < n_groups; u += gridDim.x) {
+        const int i = (u * ST + (owner ? wave : 0)) * 32 + col;
+        const bool valid = owner && i < p.N;
+        if (owner) {
+            float slots[NT::IN_SLOTS];
+#pragma unroll
+            for (int s = 0; s < NT::IN_SLOTS; ++s) slots[s] = 0.0f;
+#pragma unroll
+            for (int s = 0; s < SS; ++s) {
+                const int f = 2 * s + g;
+                slots[s] = (valid && f < D_S) ? p.states[(size_t)i * D_S + f] : 0.0f;
+            }
+            if (p.noise) {
+#pragma unroll
+                for (int s = 0; s < SW; ++s) {
+                    const int f = noise_feature(s, g);
+                    slots[SS + s] = (valid && f < D_W) ? p.noise[(size_t)i * D_W + f] : 0.0f;
+                }
+            } else {
+                float nz[SW];
+                noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, 0u, 0u, 5u, g);
+#pragma unroll
+                for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
+            }
+            split_stage_inputs<NT>(in_lds + wave * SplitIn<NT>::BYTES, slots, lane);
+        }
+        __syncthreads();  // the owners' inputs are in LDS
+        float d[NO][16];
+        run_net_split_owned<NT, ST, kPropSplitWaves, kPropSplitDepth>(P, p.b0_trans, in_lds, d, lane, g, wave, smem);
+        if (valid)
+#pragma unroll
+            for (int s = 0; s < SS; ++s) {
+                const int f = 2 * s + g;
+                if (f < D_S) p.prop[(size_t)i * D_S + f] = p.states[(size_t)i * D_S + f] + d[s / 16][s % 16];
+            }
+    }
+    }
+}
+
+// The likelihood of the proposals for those models, x = l / lambda (+ log
+// prior): the block's four waves split one 32-particle tile's layers
+// (run_net_split), as the update of width-256 networks does.
+template <int DT, int D_S, int LW, int LNH>
+__global__ __launch_bounds__(256) void lik_rows_kernel(ProposeParams p) {
+    static_assert(pass_mode<LW>() == kSplit, "likelihood widths above 64 and up to 256");
+    typedef Net<DT, LW, LNH, in_slots(DT, D_S, 0, 0)> NTL;
+    constexpr int SS = state_slots(D_S);
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const NetPtrs PL = net_ptrs(p.lik.base, p.lik);
+    const int n_tiles = (p.N + 31) / 32;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int i = tile * 32 + col;
+        const bool valid = i < p.N;
+        float ls[NTL::IN_SLOTS];
+#pragma unroll
+        for (int s = 0; s < NTL::IN_SLOTS; ++s) ls[s] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SS; ++s) {
+            const int f = 2 * s + g;
+            ls[s] = (valid && f < D_S) ? p.prop[(size_t)i * D_S + f] : 0.0f;
+        }
+        const f32x16 lo = run_net_split<NTL>(PL, p.b0_lik, ls, lane, g, wave, smem);
+        if (wave == 0 && g == 0 && valid) {
+            const float l = lo[0];
+            if (p.loglik) p.loglik[i] = l;
+            if (!isfinite(l) && p.status) p.status[0] = 5;
+            double x = (double)l / p.lambda;
+            if (p.prior_w) x += log(p.prior_w[i]);
+            p.x[i] = x;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kNormResThreads) void norm_res_kernel(NormResParams p) {
     __shared__ double buf[kNormResMaxN];
     __shared__ int ids[kNormResMaxN];
@@ -312,6 +408,109 @@ int propose_blocks_per_cu(int shape, int dt) {
     case id * 2 + 1:                                                                                            \
         return occupancy(PROP_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? 2 * kLdsGuess : kSplitLds);
         VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+int lik_shape_width(int shape) {
+#define X(id, ds, lw, lnh) \
+    if (shape == id) return lw;
+    VOILA_LIK_SHAPES(X)
+#undef X
+    return 0;
+}
+int lik_shape_hidden(int shape) {
+#define X(id, ds, lw, lnh) \
+    if (shape == id) return lnh;
+    VOILA_LIK_SHAPES(X)
+#undef X
+    return 0;
+}
+
+#define PROPS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) propose_split_kernel<DT, ds, dw, w, nh>
+
+template <int DT, int D_S, int D_W, int W, int NH>
+constexpr size_t propose_split_lds() {
+    if constexpr (!net_compiled(DT, W) || generic_compiled(DT, W, NH)) {
+        return 0;
+    } else {
+        typedef Net<DT, W, NH, in_slots(DT, D_S, 0, D_W), W / 32, cdiv(D_S, 32)> NT;
+        return (size_t)kPropSplitTiles * (SplitLds<NT>::ACT + SplitIn<NT>::BYTES);
+    }
+}
+
+hipError_t launch_propose_split(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                                  \
+    case id * 2 + 0: {                                                                                         \
+        const size_t lds = propose_split_lds<DT_F32, ds, dw, w, nh>();                                          \
+        if (lds == 0) return hipErrorInvalidValue;                                                             \
+        if (lds > 65536)                                                                                       \
+            (void)hipFuncSetAttribute((const void*)PROPS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),          \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
+        hipLaunchKernelGGL((PROPS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32)), blocks, 64 * kPropSplitWaves, \
+                           lds, s, p);                                                                         \
+        break;                                                                                                 \
+    }                                                                                                          \
+    case id * 2 + 1: {                                                                                         \
+        const size_t lds = propose_split_lds<DT_BF16, ds, dw, w, nh>();                                         \
+        if (lds == 0) return hipErrorInvalidValue;                                                             \
+        if (lds > 65536)                                                                                       \
+            (void)hipFuncSetAttribute((const void*)PROPS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),         \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
+        hipLaunchKernelGGL((PROPS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16)), blocks, 64 * kPropSplitWaves, \
+                           lds, s, p);                                                                         \
+        break;                                                                                                 \
+    }
+        VOILA_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int propose_split_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                              \
+    case id * 2 + 0:                                                                                       \
+        return occupancy_t(PROPS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), 64 * kPropSplitWaves,       \
+                           propose_split_lds<DT_F32, ds, dw, w, nh>());                                     \
+    case id * 2 + 1:                                                                                       \
+        return occupancy_t(PROPS_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), 64 * kPropSplitWaves,      \
+                           propose_split_lds<DT_BF16, ds, dw, w, nh>());
+        VOILA_SHAPES(X)
+#undef X
+    }
+    return 1;
+}
+
+hipError_t launch_lik_rows(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, lw, lnh)                                                                                 \
+    case id * 2 + 0:                                                                                      \
+        hipLaunchKernelGGL((lik_rows_kernel<DT_F32, ds, lw, lnh>), blocks, 256, kSplitLds, s, p);         \
+        break;                                                                                            \
+    case id * 2 + 1:                                                                                      \
+        hipLaunchKernelGGL((lik_rows_kernel<DT_BF16, ds, lw, lnh>), blocks, 256, kSplitLds, s, p);        \
+        break;
+        VOILA_LIK_SHAPES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int lik_rows_blocks_per_cu(int shape, int dt) {
+    switch (shape * 2 + dt) {
+#define X(id, ds, lw, lnh)                                                          \
+    case id * 2 + 0:                                                               \
+        return occupancy(lik_rows_kernel<DT_F32, ds, lw, lnh>, kSplitLds);         \
+    case id * 2 + 1:                                                               \
+        return occupancy(lik_rows_kernel<DT_BF16, ds, lw, lnh>, kSplitLds);
+        VOILA_LIK_SHAPES(X)
 #undef X
     }
     return 1;

@@ -20,6 +20,15 @@ namespace voila {
 
 constexpr int kNumShapes = 6;
 
+// Model shapes whose likelihood network has a shape of its own (the paper
+// pairs four-layer samplers of width 1024 with a likelihood of three hidden
+// layers of 256): X(id, d_s, likelihood width, likelihood hidden layers).
+// Such models update beliefs (proposal and likelihood in separate kernels);
+// the other likelihood users refuse them.
+#define VOILA_LIK_SHAPES(X) X(5, 45, 256, 3)
+int lik_shape_width(int shape);   // 0: the likelihood has the model's width and depth
+int lik_shape_hidden(int shape);
+
 struct ShapeInfo {
     int d_s, n_actions, d_a, d_w, d_o, d_wz, width, n_hidden;
 };
@@ -376,6 +385,14 @@ constexpr int kDdimMaxSteps = 4096;
 constexpr int kNceMaxBatch = 32768;  // B <= this (the score matrix holds B^2 binary32 values)
 constexpr int kPwMaxGroup = 8192;  // successors per group (one workgroup normalises and resamples a group)
 hipError_t launch_propose(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
+// Update stage 1 of the models of VOILA_LIK_SHAPES: proposals through the split
+// transition kernel (two 32-particle tiles per block), then the likelihood of
+// the proposals (one tile per block of four waves).
+hipError_t launch_propose_split(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
+int propose_split_blocks_per_cu(int shape, int dt);
+constexpr int kPropSplitTiles = 2;
+hipError_t launch_lik_rows(int shape, int dt, const ProposeParams& p, int blocks, hipStream_t s);
+int lik_rows_blocks_per_cu(int shape, int dt);
 hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);
 // The observe kernel sized for the rows of whole rollouts (weights streamed like the rollout kernel's).
 hipError_t launch_observe_rollouts(int shape, int dt, const ObserveParams& p, int blocks, hipStream_t s);

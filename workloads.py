@@ -188,13 +188,14 @@ def deep(seed: int = 6, N: int = 128, K: int = 32, H: int = 10, compute: str = "
 
 
 def target_finding(seed: int = 16, N: int = 128, K: int = 32, H: int = 10, compute: str = "bf16",
-                   with_obs: bool = True) -> Workload:
+                   with_obs: bool = True, with_lik: bool = True) -> Workload:
     """The paper's target-finding task shapes (Sec. 5) with random weights: a
     45-dimensional state, six discrete actions, observations of 36 lidar
     bins; transition and observation networks of four hidden layers of 1024
     (the distilled samplers' depth and width), their latent noise of the
-    sampled variable's dimension (45 and 36); no likelihood network.  States
-    ~ N(0, 1), goal ~ N(0, 1/4) per feature, actions uniform."""
+    sampled variable's dimension (45 and 36); the likelihood network of three
+    hidden layers of 256.  States ~ N(0, 1), goal ~ N(0, 1/4) per feature,
+    actions uniform."""
     rng = np.random.Generator(np.random.PCG64(seed))
     trans = random_mlp(rng, [45 + 6 + 45] + [1024] * 4 + [45])
     model = Model(d_s=45, n_actions=6, d_a=0, d_w=45, d_o=36, d_wz=36, trans=trans, obs=[], lik=[])
@@ -206,6 +207,8 @@ def target_finding(seed: int = 16, N: int = 128, K: int = 32, H: int = 10, compu
         # drawn after everything else, so the other inputs do not depend on it
         w.model.obs = random_mlp(np.random.Generator(np.random.PCG64(seed + 1000)),
                                  [45 + 6 + 36] + [1024] * 4 + [36])
+    if with_lik:
+        w.model.lik = random_mlp(np.random.Generator(np.random.PCG64(seed + 2000)), [45 + 6 + 36] + [256] * 3 + [1])
     return w
 
 
