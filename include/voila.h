@@ -110,7 +110,14 @@ const char* voila_last_error(void);
  * depth and width of the paper's distilled samplers (Sec. 5)): transition
  * and observation networks only -- a likelihood network of that shape is
  * refused -- serving voila_plan, voila_observe and voila_plan_observe (their
- * kernels split every layer of two 32-row tiles over a block's waves). */
+ * kernels split every layer of two 32-row tiles over a block's waves);
+ * (45, 6 discrete, 45, 36, 36, 4 x 1024, VOILA_BF16 only: the paper's
+ * target-finding task (Sec. 5), a 45-dimensional state and 36 lidar bins,
+ * whose sampler outputs span two 32-row tiles) with, optionally, the
+ * paper's likelihood network of 3 x 256 (a shape of its own): such a model
+ * serves voila_plan, voila_observe, voila_plan_observe and voila_update;
+ * voila_pw_step, voila_plan_closed_loop and voila_info_nce refuse it with
+ * VOILA_ERR_UNSUPPORTED. */
 voila_status_t voila_model_create(const voila_model_desc_t* h_desc, int32_t device, voila_model_t* out);
 /* [sync] Frees a model (NULL is accepted). */
 voila_status_t voila_model_destroy(voila_model_t model);
