@@ -8,11 +8,11 @@
 //   pass 1  per-block (max, sum exp(x - max)) of x_i = l_i / lambda (+ log w_i)
 //           in a fixed order                                    -> bmax, bsum
 //   red 1   m = max over blocks, S = sum_b bsum_b exp(bmax_b - m) in block order
-//   pass 2  w_i = exp(x_i - m) / S (or given weights), q_i = rint(w_i N 2^b):
+//   pass 2  w_i = exp(x_i - m) (1 / S) (or given weights), q_i = rint(w_i N 2^b):
 //           the total of q of every 1024-particle chunk (exact), and per
 //           block the sum of w_i^2 and the last positive particle (the
 //           per-particle prefix is not stored)
-//   red 2   exclusive scan of the chunk totals, statistics
+//   red 2   exclusive scan of the chunk totals (one workgroup), statistics
 //   pass 3  one workgroup per 1024 consecutive outputs j: the chunks whose
 //           prefix range meets the block's positions j 2^b + u are found by
 //           binary search over the chunk totals; for each such chunk the
@@ -49,7 +49,8 @@ __device__ __forceinline__ double lg_x(const LargeResParams& p, int i, int& bad)
     }
     float l = p.loglik[i];
     if (!isfinite(l)) bad = 1;
-    double x = (double)l / p.lambda;
+    // a binary64 division costs a dozen instructions: skipped when lambda = 1
+    double x = p.lambda == 1.0 ? (double)l : (double)l / p.lambda;
     if (p.prior_w) x += log(p.prior_w[i]);
     return x;
 }
@@ -77,8 +78,9 @@ __device__ __forceinline__ double exp_tab(double x, const double* tab) {
     return ldexp(tab[k & (kExpTab - 1)] * poly, k >> 8);
 }
 
-// (m, s) <- (m, s) combined with (m2, s2), where s = sum exp(x - m).
-__device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
+// (m, s) <- (m, s) combined with (m2, s2), where s = sum exp(x - m)
+// (exponentials of non-positive arguments from the table).
+__device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2, const double* tab) {
     if (m2 == -INFINITY) return;
     if (m == -INFINITY) {
         m = m2;
@@ -86,10 +88,10 @@ __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, doubl
         return;
     }
     if (m2 > m) {
-        s = s * exp(m - m2) + s2;
+        s = s * exp_tab(m - m2, tab) + s2;
         m = m2;
     } else {
-        s += s2 * exp(m2 - m);
+        s += s2 * exp_tab(m2 - m, tab);
     }
 }
 
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_lse_kernel(LargeResParams p) {
     // fixed-shape tree: lanes merge across the wave (butterfly), then the
     // four wave results in order
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) lse_merge(m, s, __shfl_xor(m, d), __shfl_xor(s, d));
+    for (int d = 32; d >= 1; d >>= 1) lse_merge(m, s, __shfl_xor(m, d), __shfl_xor(s, d), etab);
     if ((threadIdx.x & 63) == 0) {
         rm[threadIdx.x >> 6] = m;
         rs[threadIdx.x >> 6] = s;
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_lse_kernel(LargeResParams p) {
     bad = blk_max_i(bad, redi);
     if (threadIdx.x == 0) {
         double mm = rm[0], ss = rs[0];
-        for (int w = 1; w < kLgThreads / 64; ++w) lse_merge(mm, ss, rm[w], rs[w]);
+        for (int w = 1; w < kLgThreads / 64; ++w) lse_merge(mm, ss, rm[w], rs[w], etab);
         p.ws.bmax[blockIdx.x] = mm;
         p.ws.bsum[blockIdx.x] = ss;
         if (bad && p.status) p.status[0] = 5;
@@ -158,15 +160,17 @@ __global__ __launch_bounds__(kLgThreads) void lg_lse_kernel(LargeResParams p) {
 constexpr int kRedThreads = 1024;
 __global__ __launch_bounds__(kRedThreads) void lg_lse_reduce_kernel(LargeResParams p) {
     __shared__ double rm[kRedThreads], rs[kRedThreads];
+    __shared__ double etab[kExpTab];
+    fill_exp_tab(etab);
     double m = -INFINITY, s = 0.0;
-    for (int c = threadIdx.x; c < p.n_blocks; c += kRedThreads) lse_merge(m, s, p.ws.bmax[c], p.ws.bsum[c]);
+    for (int c = threadIdx.x; c < p.n_blocks; c += kRedThreads) lse_merge(m, s, p.ws.bmax[c], p.ws.bsum[c], etab);
     rm[threadIdx.x] = m;
     rs[threadIdx.x] = s;
     for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
         __syncthreads();
         if (threadIdx.x < h) {
             double mm = rm[threadIdx.x], ss = rs[threadIdx.x];
-            lse_merge(mm, ss, rm[threadIdx.x + h], rs[threadIdx.x + h]);
+            lse_merge(mm, ss, rm[threadIdx.x + h], rs[threadIdx.x + h], etab);
             rm[threadIdx.x] = mm;
             rs[threadIdx.x] = ss;
         }
@@ -174,19 +178,20 @@ __global__ __launch_bounds__(kRedThreads) void lg_lse_reduce_kernel(LargeResPara
     if (threadIdx.x == 0) {
         p.ws.scal[0] = rm[0];
         p.ws.scal[1] = rs[0];
+        p.ws.scal[2] = 1.0 / rs[0];  // the weights multiply by 1 / S (one rounding more than a division)
         if (!isfinite(rm[0]) && p.status) p.status[0] = 5;
     }
 }
 
-// q_i = rint(w_i N 2^b) of particle i with w_i = exp(x_i - m) / S, or the
-// given weight (checked); pass 2 and pass 3 call this same function.
-__device__ __forceinline__ double quant_w(const LargeResParams& p, int i, double m, double S, int& bad, double& w,
+// q_i = rint(w_i N 2^b) of particle i with w_i = exp(x_i - m) (1 / S), or
+// the given weight (checked); pass 2 and pass 3 call this same function.
+__device__ __forceinline__ double quant_w(const LargeResParams& p, int i, double m, double invS, int& bad, double& w,
                                          const double* etab) {
     if (p.w_in) {
         w = p.w_in[i];
         if (!(w >= 0.0) || w == INFINITY) bad = 1;
     } else {
-        w = exp_tab(lg_x(p, i, bad) - m, etab) / S;
+        w = exp_tab(lg_x(p, i, bad) - m, etab) * invS;
     }
     return rint(w * ldexp((double)p.N, p.bits));
 }
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
     __shared__ double etab[kExpTab];
     fill_exp_tab(etab);
     const int bbase = blockIdx.x * kLgBlock;
-    const double m = p.ws.scal[0], S = p.ws.scal[1];
+    const double m = p.ws.scal[0], invS = p.ws.scal[2];
     double sq = 0.0, tq[kSubPerBlock];
     int last = -1, bad = 0;
 #pragma unroll
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
         const int i = bbase + k * kLgThreads + threadIdx.x;  // chunk k / kChunkItems of the block
         if (i < p.N) {
             double w;
-            const double q = quant_w(p, i, m, S, bad, w, etab);
+            const double q = quant_w(p, i, m, invS, bad, w, etab);
             if (!p.w_in && p.w_out) p.w_out[i] = w;
             sq += w * w;
             tq[k / kChunkItems] += q;  // exact: integers below 2^53
@@ -231,51 +236,74 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
 }
 
 // One workgroup: exclusive scan of the chunk totals, global statistics.
-// Loads are issued eight at a time ahead of their use.
+// Rounds of 4096 chunks: coalesced loads (the next round's issued before this
+// round is scanned), a transpose through LDS so that each thread scans four
+// consecutive totals, a scan of the thread totals, coalesced stores.  The
+// totals are integers below 2^53: every order of addition gives the same bits.
 __global__ __launch_bounds__(1024) void lg_scan_kernel(LargeResParams p) {
-    __shared__ double tot[1024 / 64];
-    __shared__ double red[1024 / 64];
-    __shared__ int redi[1024 / 64];
-    constexpr int B8 = 8;
-    const int nc = p.n_chunks;
-    const int per = (nc + blockDim.x - 1) / blockDim.x;
-    const int lo = threadIdx.x * per, hi = min(nc, lo + per);
-    double run = 0.0;
-    for (int c0 = lo; c0 < hi; c0 += B8) {
-        double v[B8];
-#pragma unroll
-        for (int e = 0; e < B8; ++e) v[e] = c0 + e < hi ? p.ws.btot[c0 + e] : 0.0;
-#pragma unroll
-        for (int e = 0; e < B8; ++e) run += v[e];
-    }
+    constexpr int T = 1024, R = 4, SPAN = T * R;
+    __shared__ double vals[SPAN];
+    __shared__ double tot[T / 64];
+    __shared__ double red[T / 64];
+    __shared__ int redi[T / 64];
+    const int nc = p.n_chunks, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double sq = 0.0;
     int last = -1;
-    for (int b = threadIdx.x; b < p.n_blocks; b += blockDim.x) {
+    for (int b = threadIdx.x; b < p.n_blocks; b += T) {
         sq += p.ws.bsq[b];
         last = max(last, p.ws.blast[b]);
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double incl = run;
-    for (int d = 1; d < 64; d <<= 1) {
-        double o = __shfl_up(incl, d);
-        if (lane >= d) incl += o;
+    double v[R], vn[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int c = threadIdx.x + T * k;
+        v[k] = c < nc ? p.ws.btot[c] : 0.0;
     }
-    if (lane == 63) tot[wave] = incl;
-    __syncthreads();
-    double off = incl - run;
-    for (int w2 = 0; w2 < wave; ++w2) off += tot[w2];
-    for (int c0 = lo; c0 < hi; c0 += B8) {
-        double v[B8];
+    double carry = 0.0;
+    for (int c0 = 0; c0 < nc; c0 += SPAN) {
 #pragma unroll
-        for (int e = 0; e < B8; ++e) v[e] = c0 + e < hi ? p.ws.btot[c0 + e] : 0.0;
+        for (int k = 0; k < R; ++k) vals[threadIdx.x + T * k] = v[k];
 #pragma unroll
-        for (int e = 0; e < B8; ++e) {
-            if (c0 + e < hi) {
-                p.ws.boff[c0 + e] = off;
-                off += v[e];
-                p.ws.bincl[c0 + e] = off;
+        for (int k = 0; k < R; ++k) {
+            const int c = c0 + SPAN + threadIdx.x + T * k;
+            vn[k] = c < nc ? p.ws.btot[c] : 0.0;
+        }
+        __syncthreads();
+        double e[R], run = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            e[k] = run;
+            run += vals[R * threadIdx.x + k];
+        }
+        double incl = run;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double o = __shfl_up(incl, d);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) tot[wave] = incl;
+        __syncthreads();
+        double off = carry + incl - run, round_total = 0.0;
+        for (int w2 = 0; w2 < T / 64; ++w2) {
+            if (w2 < wave) off += tot[w2];
+            round_total += tot[w2];
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) vals[R * threadIdx.x + k] = off + e[k];  // this thread's own slots
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int c = c0 + threadIdx.x + T * k;
+            if (c < nc) {
+                const double o = vals[threadIdx.x + T * k];
+                p.ws.boff[c] = o;
+                p.ws.bincl[c] = o + v[k];
             }
         }
+        carry += round_total;
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[k] = vn[k];
+        __syncthreads();  // vals and tot are rewritten by the next round
     }
     sq = blk_sum(sq, red);
     last = blk_max_i(last, redi);
@@ -349,7 +377,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_resample_kernel(LargeResParams 
     const double step = ldexp(1.0, p.bits), inv_step = ldexp(1.0, -p.bits);
     const double u = (double)(p.U >> (32 - p.bits));
     const double P0 = (double)j0 * step + u, P1 = (double)(j0 + n_out - 1) * step + u;
-    const double m = p.ws.scal[0], S = p.ws.scal[1];
+    const double m = p.ws.scal[0], invS = p.ws.scal[2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // outputs past the total mass (the top edge) take the last positive-mass particle
     for (int r = threadIdx.x; r < n_out; r += kLgThreads) ids[r] = last;
@@ -387,7 +415,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_resample_kernel(LargeResParams 
 #pragma unroll
         for (int k = 0; k < kChunkItems; ++k) {
             double w;
-            qk[k] = i0 + k < p.N ? quant_w(p, i0 + k, m, S, bad, w, etab) : 0.0;
+            qk[k] = i0 + k < p.N ? quant_w(p, i0 + k, m, invS, bad, w, etab) : 0.0;
             run += qk[k];
             qk[k] = run;
         }
