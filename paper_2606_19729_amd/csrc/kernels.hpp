@@ -309,8 +309,9 @@ struct LargeResWs {
     double* bsq;     // per-block sum of squared weights
     int* blast;      // per-block last positive-mass particle
     double* btot;    // per-chunk total of quantised weights
-    double* boff;    // exclusive prefix of chunk totals
-    double* bincl;   // inclusive prefix of chunk totals
+    double* bbt;     // per-block total of quantised weights (the sum of its chunks')
+    double* boff;    // exclusive prefix of the block totals
+    double* bincl;   // inclusive prefix of the block totals
     double* scal;    // [0] max, [1] sum
     int* last;       // last positive-mass particle overall
 };

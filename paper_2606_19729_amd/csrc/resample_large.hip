@@ -9,13 +9,15 @@
 //           in a fixed order                                    -> bmax, bsum
 //   red 1   m = max over blocks, S = sum_b bsum_b exp(bmax_b - m) in block order
 //   pass 2  w_i = exp(x_i - m) (1 / S) (or given weights), q_i = rint(w_i N 2^b):
-//           the total of q of every 1024-particle chunk (exact), and per
-//           block the sum of w_i^2 and the last positive particle (the
-//           per-particle prefix is not stored)
-//   red 2   exclusive scan of the chunk totals (one workgroup), statistics
-//   pass 3  one workgroup per 1024 consecutive outputs j: the chunks whose
-//           prefix range meets the block's positions j 2^b + u are found by
-//           binary search over the chunk totals; for each such chunk the
+//           the total of q of every 1024-particle chunk and of every block
+//           (exact), and per block the sum of w_i^2 and the last positive
+//           particle (the per-particle prefix is not stored)
+//   red 2   exclusive scan of the block totals (one workgroup), statistics
+//   pass 3  one workgroup per 1024 consecutive outputs j: the first block
+//           whose prefix range reaches the block's first position j0 2^b + u
+//           is found by search over the block prefix, and the chunks from
+//           there on get their prefix from it and the chunk totals (a running
+//           sum of exact integers); for each chunk that meets the positions the
 //           q_i are recomputed (the same arithmetic as pass 2; thread t holds
 //           particles 4 t .. 4 t + 3) and their chunk-relative inclusive
 //           prefix is formed in registers (thread scan, then a scan of the
@@ -219,12 +221,15 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
             if (q > 0.0) last = i;
         }
     }
+    double bt = 0.0;  // exact: integers below 2^53
 #pragma unroll
     for (int c = 0; c < kSubPerBlock; ++c) {
         const double t = blk_sum(tq[c], red);
         const int ci = blockIdx.x * kSubPerBlock + c;
         if (threadIdx.x == 0 && ci < p.n_chunks) p.ws.btot[ci] = t;
+        bt += t;
     }
+    if (threadIdx.x == 0) p.ws.bbt[blockIdx.x] = bt;
     sq = blk_sum(sq, red);
     last = blk_max_i(last, redi);
     bad = blk_max_i(bad, redi);
@@ -235,8 +240,8 @@ __global__ __launch_bounds__(kLgThreads) void lg_quant_kernel(LargeResParams p) 
     }
 }
 
-// One workgroup: exclusive scan of the chunk totals, global statistics.
-// Rounds of 4096 chunks: coalesced loads (the next round's issued before this
+// One workgroup: exclusive scan of the block totals, global statistics.
+// Rounds of 4096 blocks: coalesced loads (the next round's issued before this
 // round is scanned), a transpose through LDS so that each thread scans four
 // consecutive totals, a scan of the thread totals, coalesced stores.  The
 // totals are integers below 2^53: every order of addition gives the same bits.
@@ -246,18 +251,31 @@ __global__ __launch_bounds__(1024) void lg_scan_kernel(LargeResParams p) {
     __shared__ double tot[T / 64];
     __shared__ double red[T / 64];
     __shared__ int redi[T / 64];
-    const int nc = p.n_chunks, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nc = p.n_blocks, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the statistics' loads issued together (added in the same order as one
+    // at a time: b = t, t + T, ...)
     double sq = 0.0;
     int last = -1;
-    for (int b = threadIdx.x; b < p.n_blocks; b += T) {
-        sq += p.ws.bsq[b];
-        last = max(last, p.ws.blast[b]);
+    for (int b0 = 0; b0 < p.n_blocks; b0 += R * T) {
+        double q[R];
+        int l[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int b = b0 + threadIdx.x + T * k;
+            q[k] = b < p.n_blocks ? p.ws.bsq[b] : 0.0;
+            l[k] = b < p.n_blocks ? p.ws.blast[b] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            sq += q[k];
+            last = max(last, l[k]);
+        }
     }
     double v[R], vn[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int c = threadIdx.x + T * k;
-        v[k] = c < nc ? p.ws.btot[c] : 0.0;
+        v[k] = c < nc ? p.ws.bbt[c] : 0.0;
     }
     double carry = 0.0;
     for (int c0 = 0; c0 < nc; c0 += SPAN) {
@@ -266,7 +284,7 @@ __global__ __launch_bounds__(1024) void lg_scan_kernel(LargeResParams p) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int c = c0 + SPAN + threadIdx.x + T * k;
-            vn[k] = c < nc ? p.ws.btot[c] : 0.0;
+            vn[k] = c < nc ? p.ws.bbt[c] : 0.0;
         }
         __syncthreads();
         double e[R], run = 0.0;
@@ -381,8 +399,8 @@ __global__ __launch_bounds__(kLgThreads) void lg_resample_kernel(LargeResParams 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // outputs past the total mass (the top edge) take the last positive-mass particle
     for (int r = threadIdx.x; r < n_out; r += kLgThreads) ids[r] = last;
-    // first chunk whose inclusive total exceeds the block's first position:
-    // the inclusive totals are non-decreasing, so it is the count of chunks
+    // first particle block whose inclusive total exceeds the first position:
+    // the inclusive totals are non-decreasing, so it is the count of blocks
     // with bincl <= P0, found in two rounds of one test per thread
     if (threadIdx.x == 0) {
         s_first = 0;
@@ -390,24 +408,31 @@ __global__ __launch_bounds__(kLgThreads) void lg_resample_kernel(LargeResParams 
     }
     __syncthreads();
     {
-        const int stride = (p.n_chunks + kLgThreads - 1) / kLgThreads;  // chunks per segment
+        const int nb = p.n_blocks;
+        const int stride = (nb + kLgThreads - 1) / kLgThreads;  // blocks per segment
         const int c1 = threadIdx.x * stride;
-        // segments whose first chunk is at or below P0 (the answer lies in the last of them)
-        const int below = (c1 < p.n_chunks && p.ws.bincl[c1] <= P0) ? 1 : 0;
+        // segments whose first block is at or below P0 (the answer lies in the last of them)
+        const int below = (c1 < nb && p.ws.bincl[c1] <= P0) ? 1 : 0;
         const int nseg = __syncthreads_count(below);
         if (nseg > 0) {
             const int seg0 = (nseg - 1) * stride;
             const int c2 = seg0 + threadIdx.x;
-            const int in = (threadIdx.x < stride && c2 < p.n_chunks && p.ws.bincl[c2] <= P0) ? 1 : 0;
+            const int in = (threadIdx.x < stride && c2 < nb && p.ws.bincl[c2] <= P0) ? 1 : 0;
             const int cnt = __syncthreads_count(in);
             if (threadIdx.x == 0) s_first = seg0 + cnt;
         }
     }
     __syncthreads();
-    for (int c = s_first; c < p.n_chunks; ++c) {
-        const double coff = p.ws.boff[c];
-        if (coff > P1) break;                 // this and later chunks own no output of the block
-        if (p.ws.bincl[c] == coff) continue;  // no mass in the chunk
+    // chunk prefixes from the block's exclusive prefix plus the chunk totals
+    // (exact integer sums: the values a chunk-level scan gives)
+    const int bf = min(s_first, p.n_blocks - 1);
+    double cnext = p.ws.boff[bf];
+    for (int c = bf * kSubPerBlock; c < p.n_chunks; ++c) {
+        const double coff = cnext;
+        cnext = coff + p.ws.btot[c];
+        if (cnext <= P0) continue;  // the chunk ends before the block's first position
+        if (coff > P1) break;       // this and later chunks own no output of the block
+        if (cnext == coff) continue;  // no mass in the chunk
         // this thread's particles i0 .. i0 + 3: q and their inclusive prefix
         const int i0 = c * kLgChunk + kChunkItems * threadIdx.x;
         double qk[kChunkItems], run = 0.0;
@@ -477,7 +502,7 @@ __global__ __launch_bounds__(kLgThreads) void lg_resample_kernel(LargeResParams 
 size_t large_res_workspace_bytes(int N) {
     const size_t nb = ((size_t)N + kLgBlock - 1) / kLgBlock, nc = ((size_t)N + kLgChunk - 1) / kLgChunk;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-    return al(nb * 8) * 3 + al(nb * 4) + al(nc * 8) * 3 + al(64);
+    return al(nb * 8) * 6 + al(nb * 4) + al(nc * 8) + al(64);
 }
 
 LargeResWs carve_large_res(void* base, int N) {
@@ -490,8 +515,9 @@ LargeResWs carve_large_res(void* base, int N) {
     w.bsq = reinterpret_cast<double*>(b); b += al(nb * 8);
     w.blast = reinterpret_cast<int*>(b); b += al(nb * 4);
     w.btot = reinterpret_cast<double*>(b); b += al(nc * 8);
-    w.boff = reinterpret_cast<double*>(b); b += al(nc * 8);
-    w.bincl = reinterpret_cast<double*>(b); b += al(nc * 8);
+    w.bbt = reinterpret_cast<double*>(b); b += al(nb * 8);
+    w.boff = reinterpret_cast<double*>(b); b += al(nb * 8);
+    w.bincl = reinterpret_cast<double*>(b); b += al(nb * 8);
     w.scal = reinterpret_cast<double*>(b);
     w.last = reinterpret_cast<int*>(b + 32);
     return w;
