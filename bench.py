@@ -37,28 +37,33 @@ PEAK_BF16_TFLOPS = 2500.0
 #   hbm_bytes      FETCH_SIZE x 2 + WRITE_SIZE per launch (the factors are what the two
 #                  counters read for an elementwise kernel of 256 MiB in + 256 MiB out)
 MEASURED = {
-    "sources_sha256_16": "60974281fb835626",
+    "sources_sha256_16": "5acf2a5c350e9694",
     "kernels": {
         "plan_kernel f32 realistic": {"mfma_busy": 0.890, "valu_per_mfma": 0.54, "valu_issue": 0.03,
-                                      "hbm_bytes": (5620 * 2 + 1024) * 1024},
-        "plan_kernel bf16 realistic": {"mfma_busy": 0.581, "valu_per_mfma": 3.78, "valu_issue": 0.22,
-                                       "hbm_bytes": (4260 * 2 + 512) * 1024},
-        "plan_batch_kernel bf16": {"mfma_busy": 0.441, "valu_per_mfma": 11.37, "valu_issue": 0.57,
+                                      "hbm_bytes": (5627 * 2 + 1024) * 1024},
+        "plan_kernel bf16 realistic": {"mfma_busy": 0.577, "valu_per_mfma": 3.78, "valu_issue": 0.22,
+                                       "hbm_bytes": (4258 * 2 + 512) * 1024},
+        "plan_batch_kernel bf16": {"mfma_busy": 0.441, "valu_per_mfma": 11.37, "valu_issue": 0.55,
                                    "valu_per_tile_step": 160, "mfma_per_tile_step": 14.0,
-                                   "hbm_bytes": (87168 * 2 + 74716) * 1024},
-        "plan_kernel bf16 width 1024": {"mfma_busy": 0.599, "valu_per_mfma": 1.65, "valu_issue": 0.11,
+                                   "hbm_bytes": (87073 * 2 + 74719) * 1024},
+        "plan_kernel bf16 width 1024": {"mfma_busy": 0.594, "valu_per_mfma": 1.65, "valu_issue": 0.10,
                                         "hbm_bytes": (9541 * 2 + 1024) * 1024},
-        "plan_split_kernel bf16 4 x 1024": {"mfma_busy": 0.448, "valu_per_mfma": 2.01, "valu_issue": 0.10,
-                                            "l2_hit": 0.808, "hbm_bytes": (206248000 * 2 + 11713351) * 1024},
-        "observe_kernel f32 realistic rollouts": {"mfma_busy": 0.849, "valu_per_mfma": 0.60},
-        "observe_kernel bf16 realistic rollouts": {"mfma_busy": 0.336, "valu_per_mfma": 4.40},
-        "nce_wide_bwd_kernel f32": {"mfma_busy": 0.709, "valu_per_mfma": 0.77},
+        "plan_split_kernel bf16 4 x 1024": {"mfma_busy": 0.470, "valu_per_mfma": 1.85, "valu_issue": 0.09,
+                                            "l2_hit": 0.744, "hbm_bytes": (258360570 * 2 + 164361) * 1024},
+        "plan_split_kernel bf16 target finding": {"mfma_busy": 0.454, "valu_per_mfma": 1.98, "valu_issue": 0.10,
+                                                  "l2_hit": 0.792, "hbm_bytes": (892886597 * 2 + 4277181) * 1024},
+        "observe_kernel f32 realistic rollouts": {"mfma_busy": 0.846, "valu_per_mfma": 0.60},
+        "observe_kernel bf16 realistic rollouts": {"mfma_busy": 0.337, "valu_per_mfma": 4.40},
+        "observe_split_kernel bf16 4 x 1024": {"mfma_busy": 0.469, "valu_per_mfma": 1.86, "l2_hit": 0.724},
+        "observe_split_kernel bf16 target finding": {"mfma_busy": 0.436, "valu_per_mfma": 1.99, "l2_hit": 0.758},
+        "nce_wide_bwd_kernel f32": {"mfma_busy": 0.708, "valu_per_mfma": 0.77},
         "nce_wide_wgrad_kernel f32": {"mfma_busy": 0.547, "valu_per_mfma": 0.91},
-        "nce_wide_bwd_kernel bf16": {"mfma_busy": 0.144, "valu_per_mfma": 7.23},
-        "nce_wide_wgrad_kernel bf16": {"mfma_busy": 0.108, "valu_per_mfma": 12.35},
-        "ddim_split_kernel 5 x 1024": {"mfma_busy": 0.474, "valu_per_mfma": 1.85},
-        "ddim_split_kernel 5 x 512": {"mfma_busy": 0.436, "valu_per_mfma": 2.75},
-        "lg_resample_kernel 2^24": {"hbm_bytes": (544301 * 2 + 1114112) * 1024},
+        "nce_wide_bwd_kernel bf16": {"mfma_busy": 0.142, "valu_per_mfma": 7.23},
+        "nce_wide_wgrad_kernel bf16": {"mfma_busy": 0.109, "valu_per_mfma": 12.35},
+        "ddim_split_kernel 5 x 1024": {"mfma_busy": 0.476, "valu_per_mfma": 1.82},
+        "ddim_split_kernel 5 x 512": {"mfma_busy": 0.437, "valu_per_mfma": 2.76},
+        "ddim_split_kernel 5 x 512, 64-d latent": {"mfma_busy": 0.404, "valu_per_mfma": 3.37},
+        "lg_resample_kernel 2^24": {"hbm_bytes": (541249 * 2 + 1114115) * 1024},
     },
 }
 
@@ -67,11 +72,12 @@ MEASURED = {
 SECTION_COUNTERS = {
     "batched": ["plan_batch_kernel bf16"],
     "wide_bf16": ["plan_kernel bf16 width 1024"],
-    "deep_bf16": ["plan_split_kernel bf16 4 x 1024"],
+    "deep_bf16": ["plan_split_kernel bf16 4 x 1024", "observe_split_kernel bf16 4 x 1024"],
+    "target_finding_bf16": ["plan_split_kernel bf16 target finding", "observe_split_kernel bf16 target finding"],
     "plan_observe": ["observe_kernel f32 realistic rollouts", "observe_kernel bf16 realistic rollouts"],
     "info_nce": ["nce_wide_bwd_kernel f32", "nce_wide_wgrad_kernel f32", "nce_wide_bwd_kernel bf16",
                  "nce_wide_wgrad_kernel bf16"],
-    "ddim": ["ddim_split_kernel 5 x 1024", "ddim_split_kernel 5 x 512"],
+    "ddim": ["ddim_split_kernel 5 x 1024", "ddim_split_kernel 5 x 512", "ddim_split_kernel 5 x 512, 64-d latent"],
 }
 
 
