@@ -306,6 +306,9 @@ struct voila_model_s {
     int lik_bpc = 1;
     char* mem = nullptr;
     NetBlob trans_plan{}, trans_upd{}, obs{}, lik{}, lik_nce{};
+    // the observation network for the rows of whole rollouts: in the paired
+    // plan evaluation's pass-major order where that evaluation applies, else obs
+    NetBlob obs_roll{};
     const float* fold_w_trans = nullptr;
     const float* fold_b_trans = nullptr;
     const float* fold_w_obs = nullptr;
@@ -522,6 +525,15 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     } else {
         blobs.emplace_back();
     }
+    // the observation network in pass-major order for per-step observations
+    const int obs_pt = Z.present() ? plan_pass_tiles(shape, dt) : 0;
+    if (obs_pt) {
+        std::vector<float> b0(Z.b[0], Z.b[0] + W);
+        SlotMap mz{m->d_s, 0, m->d_wz, m->d_s, m->d_s + aw};
+        blobs.push_back(pack_net(Z, dt, obs_in_slots(shape, dt), mz, b0, 1, m->obs_roll, false, obs_pt));
+    } else {
+        blobs.emplace_back();
+    }
     const size_t nb = blobs.size();
     std::vector<std::vector<float>> folds;
     m->nf_trans = aw;
@@ -597,6 +609,11 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     m->grad_bwd.base = m->mem + offs[5];
     m->lik_nce.base = m->mem + offs[6];
     m->lik_bwd.base = m->mem + offs[7];
+    if (obs_pt) {
+        m->obs_roll.base = m->mem + offs[9];
+    } else {
+        m->obs_roll = m->obs;
+    }
     m->fold_w_trans = reinterpret_cast<const float*>(m->mem + offs[nb + 0]);
     m->fold_b_trans = reinterpret_cast<const float*>(m->mem + offs[nb + 1]);
     m->fold_w_obs = reinterpret_cast<const float*>(m->mem + offs[nb + 2]);
@@ -1849,7 +1866,7 @@ voila_status_t voila_plan_observe(voila_model_t m, const float* d_traj, int32_t 
     f.status = d_status;
     VOILA_CHECK_HIP(launch_fold_steps(f, s));
     ObserveParams p{};
-    p.obs = m->obs;
+    p.obs = m->obs_roll;
     p.b0 = f.out;
     p.b0_stride = m->width;
     p.states = d_traj;
@@ -1861,7 +1878,8 @@ voila_status_t voila_plan_observe(voila_model_t m, const float* d_traj, int32_t 
     p.crn = crn ? 1 : 0;
     p.key0 = (uint32_t)(seed & 0xffffffffu);
     p.key1 = (uint32_t)(seed >> 32);
-    const long units = (long)K * H * ((N + 31) / 32);
+    const int tpu = plan_pass_tiles(m->shape, m->dt) ? 2 : 1;  // tiles per wave unit (paired evaluation)
+    const long units = (long)K * H * (((N + 31) / 32 + tpu - 1) / tpu);
     const long want = (units + kWavesPerBlock - 1) / kWavesPerBlock;
     const long cap = (long)m->cus * m->obs_roll_bpc;
     VOILA_CHECK_HIP(launch_observe_rollouts(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));

@@ -91,15 +91,32 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
         float* rowb = reinterpret_cast<float*>(smem + p.row_bias_lds) + wave * NTO::WIDTH;
         constexpr int RB = NTO::WIDTH / 64;  // bias floats per lane
         static_assert(NTO::WIDTH % 64 == 0 && RB <= 16, "bias row copy: whole lanes");
+        // paired evaluation: a unit is two tiles of one group, every weight
+        // fragment (streamed in pass-major order) feeding both
+        constexpr bool PAIRS = plan_pairs<DT, WIDTH, NHID>();
+        constexpr int TPU = PAIRS ? 2 : 1;
+        const int n_tu = (n_tiles + TPU - 1) / TPU;  // units per group
+        const long n_pu = (long)p.K * p.H * n_tu;
         int have = -1;
-        with_weights<NTO, MODE, 1>(smem, p.obs, [&](auto& src, const NetPtrs& P) {
+        with_weights<NTO, MODE, 1, PAIRS ? VOILA_PLAN_STREAM_CHB : VOILA_STREAM_CHB>(
+            smem, p.obs, [&](auto& src, const NetPtrs& P) {
             // block-uniform loop (the stream's chunk barriers need every wave)
-            for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
+            for (long ub = blockIdx.x; ub * wpb < n_pu; ub += gridDim.x) {
                 const long u = ub * wpb + wave;
-                const bool ok = u < n_units;
-                float slots[NTO::IN_SLOTS];
-                const ObsRow w = observe_inputs<D_S, D_WZ>(p, ok ? u : 0, n_tiles, g, col, slots);
-                const int brow = p.b0_stride ? w.grp : 0;
+                const bool ok = u < n_pu;
+                const long uu = ok ? u : 0;
+                const long grp = uu / n_tu;
+                const int t0 = (int)(uu - grp * n_tu) * TPU;
+                float slots[TPU][NTO::IN_SLOTS];
+                ObsRow w[TPU];
+#pragma unroll
+                for (int q = 0; q < TPU; ++q) {
+                    // a tile past the group's last reads that tile and writes nothing
+                    const int tile = t0 + q < n_tiles ? t0 + q : t0;
+                    w[q] = observe_inputs<D_S, D_WZ>(p, grp * n_tiles + tile, n_tiles, g, col, slots[q]);
+                    w[q].valid = w[q].valid && ok && t0 + q < n_tiles;
+                }
+                const int brow = p.b0_stride ? w[0].grp : 0;
                 const bool fresh = brow != have;  // wave-uniform
                 float bv[RB];
                 if (fresh) {
@@ -117,8 +134,15 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
                     __builtin_amdgcn_wave_barrier();
                     have = brow;
                 }
-                const f32x16 o = run_net<NTO>(src, P, rowb, slots, lane, g);
-                observe_store<D_O>(p, w, o, ok, g);
+                if constexpr (PAIRS) {
+                    f32x16 o[2];
+                    run_net_flat<NTO, 2, kPlanPassTiles>(src, P, rowb, slots, o, lane, g);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) observe_store<D_O>(p, w[q], o[q], w[q].valid, g);
+                } else {
+                    const f32x16 o = run_net<NTO>(src, P, rowb, slots[0], lane, g);
+                    observe_store<D_O>(p, w[0], o, ok, g);
+                }
             }
         });
     } else {
@@ -282,16 +306,22 @@ hipError_t launch_observe(int shape, int dt, const ObserveParams& p, int blocks,
 
 #define OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) observe_kernel<DT, ds, dwz, dox, w, nh, plan_mode<w>()>
 
+template <int DT, int D_S, int D_WZ, int W, int NH>
+constexpr size_t obs_stream_lds() {
+    return plan_pairs<DT, W, NH>() ? stream_lds_of<DT, D_S, 0, 0, D_WZ, W, NH, VOILA_PLAN_STREAM_CHB>()
+                                   : stream_lds_of<DT, D_S, 0, 0, D_WZ, W, NH>();
+}
+
 size_t observe_rollout_lds(int shape, int dt, const NetBlob& obs) {
     if (weights_in_lds(shape)) return obs.bytes;
     size_t chunks = kStreamLds;
     switch (shape * 2 + dt) {
-#define X(id, ds, na, da, dw, dox, dwz, w, nh)                       \
-    case id * 2 + 0:                                                \
-        chunks = stream_lds_of<DT_F32, ds, 0, 0, dwz, w, nh>();     \
-        break;                                                      \
-    case id * 2 + 1:                                                \
-        chunks = stream_lds_of<DT_BF16, ds, 0, 0, dwz, w, nh>();    \
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                  \
+    case id * 2 + 0:                                           \
+        chunks = obs_stream_lds<DT_F32, ds, dwz, w, nh>();     \
+        break;                                                 \
+    case id * 2 + 1:                                           \
+        chunks = obs_stream_lds<DT_BF16, ds, dwz, w, nh>();    \
         break;
         VOILA_SHAPES(X)
 #undef X
@@ -348,9 +378,11 @@ int observe_rollout_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
     case id * 2 + 0:                                                                                        \
-        return occupancy(OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kStreamLds); \
+        return occupancy(OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),                               \
+                         lds_for_width<w>() ? kLdsGuess : obs_stream_lds<DT_F32, ds, dwz, w, nh>());          \
     case id * 2 + 1:                                                                                        \
-        return occupancy(OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kStreamLds);
+        return occupancy(OBSR_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),                              \
+                         lds_for_width<w>() ? kLdsGuess : obs_stream_lds<DT_BF16, ds, dwz, w, nh>());
         VOILA_SHAPES(X)
 #undef X
     }

@@ -110,21 +110,6 @@ __device__ __forceinline__ void plan_unit(Src& src, const NetPtrs& P, const Plan
     if (lane == 0 && unit_ok) p.partials[(size_t)k * p.n_tiles + tile] = tot;
 }
 
-// Whether the plan kernel runs two 32-particle tiles per wave through a
-// pass-major fragment stream (run_net_passes): the streamed bfloat16 layered
-// networks, where reading each weight fragment once for 64 rollouts halves
-// the LDS traffic per matrix instruction.
-template <int DT, int WIDTH, int NHID>
-constexpr bool plan_pairs() {
-    return DT == DT_BF16 && WIDTH > 64 && chunk_tiles(WIDTH) == WIDTH / 32 && NHID >= 2;
-}
-#ifndef VOILA_PLAN_PASS_TILES
-#define VOILA_PLAN_PASS_TILES 2
-#endif
-constexpr int kPlanPassTiles = VOILA_PLAN_PASS_TILES;
-#ifndef VOILA_PLAN_FLAT
-#define VOILA_PLAN_FLAT 1
-#endif
 constexpr size_t kPlanStreamLds = (size_t)VOILA_STREAM_NBUF * VOILA_PLAN_STREAM_CHB;  // output tiles per pass of the paired evaluation
 
 // The unit of plan_unit for two tiles (2 tp, 2 tp + 1) of one candidate:

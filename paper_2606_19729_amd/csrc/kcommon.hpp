@@ -314,6 +314,22 @@ int occupancy_t(KernelT k, int threads, size_t lds) {
 constexpr size_t kLdsGuess = 32 * 1024;
 }  // namespace
 
+// Whether the rollout kernels (plan, per-step observations) run two
+// 32-particle tiles per wave through a pass-major fragment stream
+// (run_net_flat): the streamed bfloat16 layered networks, where reading each
+// weight fragment once for 64 rollouts halves the LDS traffic per matrix
+// instruction.
+template <int DT, int WIDTH, int NHID>
+constexpr bool plan_pairs() {
+    return DT == DT_BF16 && WIDTH > 64 && chunk_tiles(WIDTH) == WIDTH / 32 && NHID >= 2;
+}
+#ifndef VOILA_PLAN_PASS_TILES
+#define VOILA_PLAN_PASS_TILES 2
+#endif
+constexpr int kPlanPassTiles = VOILA_PLAN_PASS_TILES;
+#ifndef VOILA_PLAN_FLAT
+#define VOILA_PLAN_FLAT 1
+#endif
 // LDS of a streaming rollout kernel before its staged biases: the two chunk
 // buffers (and the first layer of a grouped wide network).
 template <int DT, int D_S, int N_ACT, int D_AIN, int D_W, int WIDTH, int NHID, int CHB = VOILA_STREAM_CHB>
