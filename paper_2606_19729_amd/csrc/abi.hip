@@ -501,9 +501,12 @@ voila_status_t voila_model_create(const voila_model_desc_t* desc, int32_t device
     // the likelihood network with its first layer over the observation
     // columns (state and action folded per row) for the contrastive objective
     if (L.present() && !m->lik_split) {
+        // pass-major where the scores kernel runs the paired evaluation (this
+        // pack serves only that kernel there)
         std::vector<float> b0(L.b[0], L.b[0] + LW);
         SlotMap mo{m->d_o, 0, 0, 0, 0, m->d_s + aw};
-        blobs.push_back(pack_net(L, dt, nce_in_slots(shape, dt), mo, b0, 1, m->lik_nce));
+        blobs.push_back(pack_net(L, dt, nce_in_slots(shape, dt), mo, b0, 1, m->lik_nce, false,
+                                 plan_pass_tiles(shape, dt)));
     } else {
         blobs.emplace_back();
     }
@@ -1333,7 +1336,8 @@ voila_status_t voila_info_nce(voila_model_t m, const float* d_states, const void
     p.status = d_status;
     p.B = B;
     p.d_o = m->d_o;
-    const long units = (long)B * ((B + 31) / 32);
+    const int tpu = plan_pass_tiles(m->shape, m->dt) ? 2 : 1;  // column tiles per wave unit (paired evaluation)
+    const long units = (long)B * (((B + 31) / 32 + tpu - 1) / tpu);
     const long want = (units + kWavesPerBlock - 1) / kWavesPerBlock;
     const long cap = (long)m->cus * m->nce_bpc;
     VOILA_CHECK_HIP(launch_nce_scores(m->shape, m->dt, p, (int)(want < cap ? want : cap), s));

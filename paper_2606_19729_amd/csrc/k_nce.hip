@@ -17,31 +17,43 @@ __global__ __launch_bounds__(256) void nce_scores_kernel(NceParams p) {
     } else {
     typedef Net<DT, WIDTH, NHID, in_slots(DT, D_O, 0, 0)> NTL;
     constexpr int SO = state_slots(D_O);
+    // paired evaluation: a unit is two column tiles of one row, every weight
+    // fragment (streamed in pass-major order) feeding both
+    constexpr bool PAIRS = MODE == kStream && plan_pairs<DT, WIDTH, NHID>();
+    constexpr int TPU = PAIRS ? 2 : 1;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & 63, g = lane >> 5, col = lane & 31;
     const int wpb = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jtiles = (p.B + 31) / 32;
-    const long n_units = (long)p.B * jtiles;
+    const int jun = (jtiles + TPU - 1) / TPU;  // units per row
+    const long n_units = (long)p.B * jun;
     float* rowb = reinterpret_cast<float*>(smem + p.row_bias_lds) + wave * NTL::WIDTH;
     constexpr int RB = NTL::WIDTH / 64;  // bias floats per lane
     static_assert(NTL::WIDTH % 64 == 0 && RB <= 16, "bias row copy: whole lanes");
     int have = -1;  // row held in this wave's LDS bias row
-    with_weights<NTL, MODE, 1>(smem, p.lik, [&](auto& src, const NetPtrs& P) {
+    with_weights<NTL, MODE, 1, PAIRS ? VOILA_PLAN_STREAM_CHB : VOILA_STREAM_CHB>(smem, p.lik, [&](auto& src,
+                                                                                            const NetPtrs& P) {
         // block-uniform loop (a streamed network's chunk barriers need every wave)
         for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
             const long u = ub * wpb + wave;
             const bool ok = u < n_units;
-            const int i = ok ? (int)(u / jtiles) : 0;
-            const int j = ok ? (int)(u - (long)i * jtiles) * 32 + col : 0;
-            const bool valid = ok && j < p.B;
-            float slots[NTL::IN_SLOTS];
+            const int i = ok ? (int)(u / jun) : 0;
+            const int jt0 = ok ? (int)(u - (long)i * jun) * TPU : 0;
+            int j[TPU];
+            bool valid[TPU];
+            float slots[TPU][NTL::IN_SLOTS];
 #pragma unroll
-            for (int s = 0; s < NTL::IN_SLOTS; ++s) slots[s] = 0.0f;
+            for (int q = 0; q < TPU; ++q) {
+                j[q] = (jt0 + q) * 32 + col;
+                valid[q] = ok && jt0 + q < jtiles && j[q] < p.B;
 #pragma unroll
-            for (int s = 0; s < SO; ++s) {
-                const int f = 2 * s + g;
-                slots[s] = (valid && f < D_O) ? p.obs[(size_t)j * D_O + f] : 0.0f;
+                for (int s = 0; s < NTL::IN_SLOTS; ++s) slots[q][s] = 0.0f;
+#pragma unroll
+                for (int s = 0; s < SO; ++s) {
+                    const int f = 2 * s + g;
+                    slots[q][s] = (valid[q] && f < D_O) ? p.obs[(size_t)j[q] * D_O + f] : 0.0f;
+                }
             }
             const bool fresh = i != have;  // wave-uniform
             float bv[RB];
@@ -58,12 +70,19 @@ __global__ __launch_bounds__(256) void nce_scores_kernel(NceParams p) {
                 __builtin_amdgcn_wave_barrier();
                 have = i;
             }
-            const f32x16 o = run_net<NTL>(src, P, rowb, slots, lane, g);
-            if (g == 0 && valid) {
-                const float l = o[0];
-                p.scores[(size_t)i * p.B + j] = l;
-                if (!isfinite(l) && p.status) p.status[0] = 5;
+            f32x16 o[TPU];
+            if constexpr (PAIRS) {
+                run_net_flat<NTL, 2, kPlanPassTiles>(src, P, rowb, slots, o, lane, g);
+            } else {
+                o[0] = run_net<NTL>(src, P, rowb, slots[0], lane, g);
             }
+#pragma unroll
+            for (int q = 0; q < TPU; ++q)
+                if (g == 0 && valid[q]) {
+                    const float l = o[q][0];
+                    p.scores[(size_t)i * p.B + j[q]] = l;
+                    if (!isfinite(l) && p.status) p.status[0] = 5;
+                }
         }
     });
     }
@@ -107,17 +126,23 @@ __global__ __launch_bounds__(kNormResThreads) void nce_mean_kernel(NceParams p) 
 // launchers
 #define NCE_K(id, ds, na, da, dw, dox, dwz, w, nh, DT) nce_scores_kernel<DT, dox, w, nh, plan_mode<w>()>
 
+template <int DT, int D_O, int W, int NH>
+constexpr size_t nce_stream_lds() {
+    return plan_pairs<DT, W, NH>() ? stream_lds_of<DT, D_O, 0, 0, 0, W, NH, VOILA_PLAN_STREAM_CHB>()
+                                   : stream_lds_of<DT, D_O, 0, 0, 0, W, NH>();
+}
+
 hipError_t launch_nce_scores(int shape, int dt, const NceParams& p0, int blocks, hipStream_t s) {
     NceParams p = p0;
     size_t lds = p.lik.bytes;
     if (!weights_in_lds(shape)) {
         switch (shape * 2 + dt) {
-#define X(id, ds, na, da, dw, dox, dwz, w, nh)                           \
-    case id * 2 + 0:                                                    \
-        lds = stream_lds_of<DT_F32, dox, 0, 0, 0, w, nh>();             \
-        break;                                                          \
-    case id * 2 + 1:                                                    \
-        lds = stream_lds_of<DT_BF16, dox, 0, 0, 0, w, nh>();            \
+#define X(id, ds, na, da, dw, dox, dwz, w, nh)                  \
+    case id * 2 + 0:                                           \
+        lds = nce_stream_lds<DT_F32, dox, w, nh>();            \
+        break;                                                 \
+    case id * 2 + 1:                                           \
+        lds = nce_stream_lds<DT_BF16, dox, w, nh>();           \
         break;
             VOILA_SHAPES(X)
 #undef X
@@ -154,9 +179,11 @@ int nce_scores_blocks_per_cu(int shape, int dt) {
     switch (shape * 2 + dt) {
 #define X(id, ds, na, da, dw, dox, dwz, w, nh)                                                               \
     case id * 2 + 0:                                                                                        \
-        return occupancy(NCE_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32), lds_for_width<w>() ? kLdsGuess : kStreamLds); \
+        return occupancy(NCE_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_F32),                                \
+                         lds_for_width<w>() ? kLdsGuess : nce_stream_lds<DT_F32, dox, w, nh>());             \
     case id * 2 + 1:                                                                                        \
-        return occupancy(NCE_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16), lds_for_width<w>() ? kLdsGuess : kStreamLds);
+        return occupancy(NCE_K(id, ds, na, da, dw, dox, dwz, w, nh, DT_BF16),                               \
+                         lds_for_width<w>() ? kLdsGuess : nce_stream_lds<DT_BF16, dox, w, nh>());
         VOILA_SHAPES(X)
 #undef X
     }
