@@ -1065,18 +1065,19 @@ __device__ __forceinline__ void run_net_flat(Src& src, const NetPtrs& P, const f
     f32x16 acc[2][ST][RP];
     f32x16 o[ST];
     FT ring[R];
-    // the biases of pass q into its accumulators
+    // the biases of pass q into the first sample tile's accumulators: the
+    // other tiles' first products of the pass take them as their addend
+    // (D = A B + C with C the first tile's bias registers), so each bias is
+    // read from LDS once per pass, not once per sample tile
     auto bias_of = [&](auto qi) {
         constexpr int q = decltype(qi)::value;
         if constexpr (q < NQ) {
             const float* bias = (q / NP == 0 ? b0 : P.bh + (q / NP - 1) * N::WIDTH) + 32 * RP * (q % NP);
-#pragma unroll
-            for (int st = 0; st < ST; ++st) init_bias<RP>(acc[q % 2][st], bias + opaque_zero(), g);
+            init_bias<RP>(acc[q % 2][0], bias + opaque_zero(), g);
         } else {
             f32x16 ob[1];
             init_bias<1>(ob, P.bo + opaque_zero(), g);
-#pragma unroll
-            for (int st = 0; st < ST; ++st) o[st] = ob[0];
+            o[0] = ob[0];
         }
     };
     bias_of(std::integral_constant<int, 0>{});
@@ -1109,14 +1110,18 @@ __device__ __forceinline__ void run_net_flat(Src& src, const NetPtrs& P, const f
         }
         if constexpr (q < NQ && s0 == Q::bias_at(q)) bias_of(std::integral_constant<int, q + 1>{});
         if constexpr (f + PF < NFR) ring[(f + PF) % R] = src.load(f + PF, lane);
+        // the last sample tile first: at the pass's first k-step the tiles
+        // after the first add to its bias registers before it is updated
         static_for<ST>([&](auto si) {
-            constexpr int st = decltype(si)::value;
+            constexpr int st = ST - 1 - decltype(si)::value;
+            constexpr bool FROM0 = st > 0 && c == 0;
             if constexpr (L == 0) {
-                acc[q % 2][st][t] = mfma(ring[f % R], Slots<N::DT, N::IN_SLOTS>::b(slots[st], c), acc[q % 2][st][t]);
+                acc[q % 2][st][t] = mfma(ring[f % R], Slots<N::DT, N::IN_SLOTS>::b(slots[st], c),
+                                         acc[q % 2][FROM0 ? 0 : st][t]);
             } else if constexpr (!OUT) {
-                acc[q % 2][st][t] = mfma(ring[f % R], A[(L - 1) % 2][st].b(c), acc[q % 2][st][t]);
+                acc[q % 2][st][t] = mfma(ring[f % R], A[(L - 1) % 2][st].b(c), acc[q % 2][FROM0 ? 0 : st][t]);
             } else {
-                o[st] = mfma(ring[f % R], A[(L - 1) % 2][st].b(c), o[st]);
+                o[st] = mfma(ring[f % R], A[(L - 1) % 2][st].b(c), o[FROM0 ? 0 : st]);
             }
         });
         __builtin_amdgcn_sched_group_barrier(kSchedReads, 1, 0);
