@@ -1301,7 +1301,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // each three-way exclusive or in one instruction (v_bitop3_b32 with
+        // the truth table 0x96 of a ^ b ^ c), where separate ones take two
+        c = make_uint4(__builtin_amdgcn_bitop3_b32(hi1, c.y, k0, 0x96), lo1,
+                       __builtin_amdgcn_bitop3_b32(hi0, c.w, k1, 0x96), lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

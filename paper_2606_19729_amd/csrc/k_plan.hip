@@ -430,9 +430,12 @@ __global__ __launch_bounds__(64 * kPlanSplitWaves) void plan_split_kernel(PlanPa
 // The work list holds block items (instance, first tile unit, number of
 // units): a block takes items from a queue (atomic counter, list sorted by
 // decreasing cost) or in a static stride, restages the instance's network in
-// LDS when the instance changes, and runs one unit per wave.
+// LDS when the instance changes, and runs one unit per wave.  At most 128
+// registers per lane (four waves per SIMD): a small network's step
+// alternates between matrix products and the vector work that feeds them
+// (noise, ReLU, conversions), and the other waves fill each wave's gaps.
 template <int DT, int D_S, int N_ACT, int D_A, int D_W, int WIDTH, int NHID>
-__global__ __launch_bounds__(512) void plan_batch_kernel(BatchPlanParams bp) {
+__global__ __launch_bounds__(512, 4) void plan_batch_kernel(BatchPlanParams bp) {
     if constexpr (WIDTH > 64) {
         return;  // batches need networks that fit in LDS (the launcher refuses wider ones)
     } else {
