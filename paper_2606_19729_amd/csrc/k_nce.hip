@@ -32,8 +32,32 @@ __global__ __launch_bounds__(256) void nce_scores_kernel(NceParams p) {
     constexpr int RB = NTL::WIDTH / 64;  // bias floats per lane
     static_assert(NTL::WIDTH % 64 == 0 && RB <= 16, "bias row copy: whole lanes");
     int have = -1;  // row held in this wave's LDS bias row
+    // the observations and bias row of the wave's next unit, read one unit
+    // ahead: their memory latency passes while the current unit multiplies
+    // (a wave's consecutive units lie in different rows)
+    float nob[TPU][SO];
+    float nbv[RB];
+    auto next_inputs = [&](long u) {
+        const bool ok = u < n_units;  // wave-uniform
+        const int i = ok ? (int)(u / jun) : 0;
+        const int jt0 = ok ? (int)(u - (long)i * jun) * TPU : 0;
+#pragma unroll
+        for (int q = 0; q < TPU; ++q) {
+            const int j = (jt0 + q) * 32 + col;
+            const bool v = ok && jt0 + q < jtiles && j < p.B;
+#pragma unroll
+            for (int s = 0; s < SO; ++s) {
+                const int f = 2 * s + g;
+                nob[q][s] = (v && f < D_O) ? p.obs[(size_t)j * D_O + f] : 0.0f;
+            }
+        }
+        const float* brow = p.b0 + (size_t)i * NTL::WIDTH;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) nbv[q] = ok ? brow[q * 64 + lane] : 0.0f;
+    };
     with_weights<NTL, MODE, 1, PAIRS ? VOILA_PLAN_STREAM_CHB : VOILA_STREAM_CHB>(smem, p.lik, [&](auto& src,
                                                                                             const NetPtrs& P) {
+        next_inputs((long)blockIdx.x * wpb + wave);
         // block-uniform loop (a streamed network's chunk barriers need every wave)
         for (long ub = blockIdx.x; ub * wpb < n_units; ub += gridDim.x) {
             const long u = ub * wpb + wave;
@@ -50,26 +74,14 @@ __global__ __launch_bounds__(256) void nce_scores_kernel(NceParams p) {
 #pragma unroll
                 for (int s = 0; s < NTL::IN_SLOTS; ++s) slots[q][s] = 0.0f;
 #pragma unroll
-                for (int s = 0; s < SO; ++s) {
-                    const int f = 2 * s + g;
-                    slots[q][s] = (valid[q] && f < D_O) ? p.obs[(size_t)j[q] * D_O + f] : 0.0f;
-                }
+                for (int s = 0; s < SO; ++s) slots[q][s] = nob[q][s];
             }
-            const bool fresh = i != have;  // wave-uniform
-            float bv[RB];
-            if (fresh) {
-                const float* brow = p.b0 + (size_t)i * NTL::WIDTH;
+            if (i != have) {  // wave-uniform; the row's reads of the last unit precede these writes
 #pragma unroll
-                for (int q = 0; q < RB; ++q) bv[q] = brow[q * 64 + lane];
-            }
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-            if (fresh) {
-#pragma unroll
-                for (int q = 0; q < RB; ++q) rowb[q * 64 + lane] = bv[q];
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-                __builtin_amdgcn_wave_barrier();
+                for (int q = 0; q < RB; ++q) rowb[q * 64 + lane] = nbv[q];
                 have = i;
             }
+            next_inputs(u + (long)gridDim.x * wpb);
             f32x16 o[TPU];
             if constexpr (PAIRS) {
                 run_net_flat<NTL, 2, kPlanPassTiles>(src, P, rowb, slots, o, lane, g);

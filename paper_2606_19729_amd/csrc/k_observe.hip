@@ -15,28 +15,42 @@ namespace voila {
 struct ObsRow {
     size_t r;     // state / noise / output row
     int grp;      // bias row
+    int i;        // particle
     bool valid;   // this lane's particle exists
 };
 
-// Inputs [s', w_Z] of this lane's row of tile unit u in first-layer slot order.
-template <int D_S, int D_WZ, int IN_SLOTS>
-__device__ __forceinline__ ObsRow observe_inputs(const ObserveParams& p, long u, int n_tiles, int g, int col,
-                                                 float (&slots)[IN_SLOTS]) {
-    constexpr int SS = state_slots(D_S), SW = noise_slots(D_WZ);
+// This lane's row of tile unit u (index arithmetic only).
+__device__ __forceinline__ ObsRow observe_row(const ObserveParams& p, long u, int n_tiles, int col) {
     ObsRow w;
     w.grp = (int)(u / n_tiles);
     const int tile = (int)(u - (long)w.grp * n_tiles);
     const int k = w.grp / p.H, t = w.grp - k * p.H;
-    const int i = tile * 32 + col;
-    w.valid = i < p.N;
-    w.r = ((size_t)k * p.N + (w.valid ? i : 0)) * p.H + t;
+    w.i = tile * 32 + col;
+    w.valid = w.i < p.N;
+    w.r = ((size_t)k * p.N + (w.valid ? w.i : 0)) * p.H + t;
+    return w;
+}
+
+// This lane's state slots s' of row w (zero past the belief).
+template <int D_S>
+__device__ __forceinline__ void observe_states(const ObserveParams& p, const ObsRow& w, int g,
+                                               float (&st)[state_slots(D_S)]) {
+#pragma unroll
+    for (int s = 0; s < state_slots(D_S); ++s) {
+        const int f = 2 * s + g;
+        st[s] = (w.valid && f < D_S) ? p.states[w.r * D_S + f] : 0.0f;
+    }
+}
+
+// Inputs [s', w_Z] of row w in first-layer slot order, from its state slots.
+template <int D_S, int D_WZ, int IN_SLOTS>
+__device__ __forceinline__ void observe_slots(const ObserveParams& p, const ObsRow& w, int g,
+                                              const float (&st)[state_slots(D_S)], float (&slots)[IN_SLOTS]) {
+    constexpr int SS = state_slots(D_S), SW = noise_slots(D_WZ);
 #pragma unroll
     for (int s = 0; s < IN_SLOTS; ++s) slots[s] = 0.0f;
 #pragma unroll
-    for (int s = 0; s < SS; ++s) {
-        int f = 2 * s + g;
-        slots[s] = (w.valid && f < D_S) ? p.states[w.r * D_S + f] : 0.0f;
-    }
+    for (int s = 0; s < SS; ++s) slots[s] = st[s];
     if (p.noise) {
 #pragma unroll
         for (int s = 0; s < SW; ++s) {
@@ -44,11 +58,22 @@ __device__ __forceinline__ ObsRow observe_inputs(const ObserveParams& p, long u,
             slots[SS + s] = (w.valid && f < D_WZ) ? p.noise[w.r * D_WZ + f] : 0.0f;
         }
     } else {
+        const int k = w.grp / p.H, t = w.grp - k * p.H;
         float nz[SW];
-        noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 4u, g);
+        noise_slots_philox<SW>(nz, p.key0, p.key1, (uint32_t)w.i, p.crn ? 0u : (uint32_t)k, (uint32_t)t, 4u, g);
 #pragma unroll
         for (int s = 0; s < SW; ++s) slots[SS + s] = nz[s];
     }
+}
+
+// Inputs [s', w_Z] of this lane's row of tile unit u in first-layer slot order.
+template <int D_S, int D_WZ, int IN_SLOTS>
+__device__ __forceinline__ ObsRow observe_inputs(const ObserveParams& p, long u, int n_tiles, int g, int col,
+                                                 float (&slots)[IN_SLOTS]) {
+    const ObsRow w = observe_row(p, u, n_tiles, col);
+    float st[state_slots(D_S)];
+    observe_states<D_S>(p, w, g, st);
+    observe_slots<D_S, D_WZ>(p, w, g, st, slots);
     return w;
 }
 
@@ -86,8 +111,8 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if constexpr (MODE == kStream) {
         const int wpb = blockDim.x >> 6;
-        // each wave keeps the (candidate, step) group's bias row in its own
-        // LDS row, refreshed when the group changes (every N/32 units)
+        // each wave keeps its unit's (candidate, step) group bias row in an
+        // LDS row of its own, rewritten when the group changes
         float* rowb = reinterpret_cast<float*>(smem + p.row_bias_lds) + wave * NTO::WIDTH;
         constexpr int RB = NTO::WIDTH / 64;  // bias floats per lane
         static_assert(NTO::WIDTH % 64 == 0 && RB <= 16, "bias row copy: whole lanes");
@@ -98,42 +123,50 @@ __global__ __launch_bounds__(256) void observe_kernel(ObserveParams p) {
         const int n_tu = (n_tiles + TPU - 1) / TPU;  // units per group
         const long n_pu = (long)p.K * p.H * n_tu;
         int have = -1;
+        // the rows, states and bias row of the wave's next unit, read one
+        // unit ahead: their memory latency passes while the current unit
+        // multiplies (a wave's consecutive units lie in different groups)
+        constexpr int SS = state_slots(D_S);
+        ObsRow nw[TPU];
+        float nst[TPU][SS];
+        float nbv[RB];
+        auto next_rows = [&](long u) {
+            const bool ok = u < n_pu;
+            const long uu = ok ? u : 0;
+            const long grp = uu / n_tu;
+            const int t0 = (int)(uu - grp * n_tu) * TPU;
+#pragma unroll
+            for (int q = 0; q < TPU; ++q) {
+                // a tile past the group's last reads that tile and writes nothing
+                const int tile = t0 + q < n_tiles ? t0 + q : t0;
+                nw[q] = observe_row(p, grp * n_tiles + tile, n_tiles, col);
+                nw[q].valid = nw[q].valid && ok && t0 + q < n_tiles;
+                observe_states<D_S>(p, nw[q], g, nst[q]);
+            }
+            const float* src_row = p.b0 + (size_t)(p.b0_stride ? nw[0].grp : 0) * p.b0_stride;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) nbv[q] = ok ? src_row[q * 64 + lane] : 0.0f;
+        };
         with_weights<NTO, MODE, 1, PAIRS ? VOILA_PLAN_STREAM_CHB : VOILA_STREAM_CHB>(
             smem, p.obs, [&](auto& src, const NetPtrs& P) {
+            next_rows((long)blockIdx.x * wpb + wave);
             // block-uniform loop (the stream's chunk barriers need every wave)
             for (long ub = blockIdx.x; ub * wpb < n_pu; ub += gridDim.x) {
-                const long u = ub * wpb + wave;
-                const bool ok = u < n_pu;
-                const long uu = ok ? u : 0;
-                const long grp = uu / n_tu;
-                const int t0 = (int)(uu - grp * n_tu) * TPU;
+                const bool ok = ub * wpb + wave < n_pu;
                 float slots[TPU][NTO::IN_SLOTS];
                 ObsRow w[TPU];
 #pragma unroll
                 for (int q = 0; q < TPU; ++q) {
-                    // a tile past the group's last reads that tile and writes nothing
-                    const int tile = t0 + q < n_tiles ? t0 + q : t0;
-                    w[q] = observe_inputs<D_S, D_WZ>(p, grp * n_tiles + tile, n_tiles, g, col, slots[q]);
-                    w[q].valid = w[q].valid && ok && t0 + q < n_tiles;
+                    w[q] = nw[q];
+                    observe_slots<D_S, D_WZ>(p, w[q], g, nst[q], slots[q]);
                 }
                 const int brow = p.b0_stride ? w[0].grp : 0;
-                const bool fresh = brow != have;  // wave-uniform
-                float bv[RB];
-                if (fresh) {
-                    const float* src_row = p.b0 + (size_t)brow * p.b0_stride;
+                if (brow != have) {  // wave-uniform; the row's reads of the last unit precede these writes
 #pragma unroll
-                    for (int q = 0; q < RB; ++q) bv[q] = src_row[q * 64 + lane];
-                }
-                // complete the row loads here so that the compiler's wait for
-                // them does not also drain the weight stream inside the layers
-                __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-                if (fresh) {
-#pragma unroll
-                    for (int q = 0; q < RB; ++q) rowb[q * 64 + lane] = bv[q];
-                    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
-                    __builtin_amdgcn_wave_barrier();
+                    for (int q = 0; q < RB; ++q) rowb[q * 64 + lane] = nbv[q];
                     have = brow;
                 }
+                next_rows((ub + gridDim.x) * wpb + wave);
                 if constexpr (PAIRS) {
                     f32x16 o[2];
                     run_net_flat<NTO, 2, kPlanPassTiles>(src, P, rowb, slots, o, lane, g);
