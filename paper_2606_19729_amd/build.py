@@ -17,11 +17,19 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvoila.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["k_plan.hip", "k_observe.hip", "k_search.hip", "k_nce.hip", "k_nce_grad.hip", "k_ddim.hip", "k_update.hip", "grad.hip",
+SOURCES = ["k_plan.hip", "k_plan_bf16.hip", "k_observe.hip", "k_search.hip", "k_nce.hip", "k_nce_grad.hip", "k_ddim.hip", "k_update.hip", "grad.hip",
            "resample_large.hip", "abi.hip"]
 ARCH = os.environ.get("VOILA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
+# Sources whose matrix instructions keep accumulators and results in VGPRs:
+# their paired bfloat16 evaluations then hold the activations (B operands) in
+# AGPRs and convert each finished accumulator pair with one AGPR write where
+# the default form reads the pair out of AGPRs (measured faster for these
+# two; the binary32 plan kernel, in k_plan.hip, and the contrastive scores
+# kernels are not faster in that form).
+VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+EXTRA = {"k_plan_bf16.hip": VGPR_FORM, "k_observe.hip": VGPR_FORM}
 
 
 def _jobs():
@@ -36,7 +44,7 @@ def build(verbose: bool = False, extra=()) -> str:
 
     def compile_one(src):
         obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-        cmd = base + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = base + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
