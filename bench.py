@@ -37,33 +37,33 @@ PEAK_BF16_TFLOPS = 2500.0
 #   hbm_bytes      FETCH_SIZE x 2 + WRITE_SIZE per launch (the factors are what the two
 #                  counters read for an elementwise kernel of 256 MiB in + 256 MiB out)
 MEASURED = {
-    "sources_sha256_16": "87e53fe6cd149486",
+    "sources_sha256_16": "c7dd443124fe6725",
     "kernels": {
         "plan_kernel f32 realistic": {"mfma_busy": 0.890, "valu_per_mfma": 0.53, "valu_issue": 0.03,
                                       "hbm_bytes": (5627 * 2 + 1024) * 1024},
-        "plan_kernel bf16 realistic": {"mfma_busy": 0.595, "valu_per_mfma": 3.66, "valu_issue": 0.21,
-                                       "hbm_bytes": (4255 * 2 + 512) * 1024},
-        "plan_batch_kernel bf16": {"mfma_busy": 0.511, "valu_per_mfma": 10.75, "valu_issue": 0.56,
+        "plan_kernel bf16 realistic": {"mfma_busy": 0.613, "valu_per_mfma": 2.69, "valu_issue": 0.17,
+                                       "hbm_bytes": (4223 * 2 + 512) * 1024},
+        "plan_batch_kernel bf16": {"mfma_busy": 0.511, "valu_per_mfma": 10.75, "valu_issue": 0.58,
                                    "valu_per_tile_step": 150, "mfma_per_tile_step": 14.0,
-                                   "hbm_bytes": (88812 * 2 + 76899) * 1024},
-        "plan_kernel bf16 width 1024": {"mfma_busy": 0.603, "valu_per_mfma": 1.64, "valu_issue": 0.10,
-                                        "hbm_bytes": (9534 * 2 + 1024) * 1024},
-        "plan_split_kernel bf16 4 x 1024": {"mfma_busy": 0.477, "valu_per_mfma": 1.86, "valu_issue": 0.09,
-                                            "l2_hit": 0.738, "hbm_bytes": (270483707 * 2 + 164361) * 1024},
-        "plan_split_kernel bf16 target finding": {"mfma_busy": 0.459, "valu_per_mfma": 1.97, "valu_issue": 0.10,
-                                                  "l2_hit": 0.776, "hbm_bytes": (963961315 * 2 + 4279174) * 1024},
-        "observe_kernel f32 realistic rollouts": {"mfma_busy": 0.847, "valu_per_mfma": 0.59},
-        "observe_kernel bf16 realistic rollouts": {"mfma_busy": 0.421, "valu_per_mfma": 4.15},
-        "observe_split_kernel bf16 4 x 1024": {"mfma_busy": 0.472, "valu_per_mfma": 1.86, "l2_hit": 0.725},
-        "observe_split_kernel bf16 target finding": {"mfma_busy": 0.456, "valu_per_mfma": 1.97, "l2_hit": 0.818},
+                                   "hbm_bytes": (88821 * 2 + 76897) * 1024},
+        "plan_kernel bf16 width 1024": {"mfma_busy": 0.598, "valu_per_mfma": 1.47, "valu_issue": 0.10,
+                                        "hbm_bytes": (9510 * 2 + 1024) * 1024},
+        "plan_split_kernel bf16 4 x 1024": {"mfma_busy": 0.473, "valu_per_mfma": 1.86, "valu_issue": 0.10,
+                                            "l2_hit": 0.749, "hbm_bytes": (260881759 * 2 + 164361) * 1024},
+        "plan_split_kernel bf16 target finding": {"mfma_busy": 0.457, "valu_per_mfma": 1.97, "valu_issue": 0.10,
+                                                  "l2_hit": 0.788, "hbm_bytes": (925838188 * 2 + 4277267) * 1024},
+        "observe_kernel f32 realistic rollouts": {"mfma_busy": 0.854, "valu_per_mfma": 0.52},
+        "observe_kernel bf16 realistic rollouts": {"mfma_busy": 0.431, "valu_per_mfma": 3.08},
+        "observe_split_kernel bf16 4 x 1024": {"mfma_busy": 0.468, "valu_per_mfma": 1.86, "l2_hit": 0.742},
+        "observe_split_kernel bf16 target finding": {"mfma_busy": 0.452, "valu_per_mfma": 1.97, "l2_hit": 0.843},
         "nce_wide_bwd_kernel f32": {"mfma_busy": 0.705, "valu_per_mfma": 0.77},
-        "nce_wide_wgrad_kernel f32": {"mfma_busy": 0.547, "valu_per_mfma": 0.91},
-        "nce_wide_bwd_kernel bf16": {"mfma_busy": 0.143, "valu_per_mfma": 7.23},
-        "nce_wide_wgrad_kernel bf16": {"mfma_busy": 0.108, "valu_per_mfma": 12.35},
-        "ddim_split_kernel 5 x 1024": {"mfma_busy": 0.479, "valu_per_mfma": 1.82},
+        "nce_wide_wgrad_kernel f32": {"mfma_busy": 0.548, "valu_per_mfma": 0.91},
+        "nce_wide_bwd_kernel bf16": {"mfma_busy": 0.144, "valu_per_mfma": 7.23},
+        "nce_wide_wgrad_kernel bf16": {"mfma_busy": 0.109, "valu_per_mfma": 12.35},
+        "ddim_split_kernel 5 x 1024": {"mfma_busy": 0.476, "valu_per_mfma": 1.82},
         "ddim_split_kernel 5 x 512": {"mfma_busy": 0.437, "valu_per_mfma": 2.76},
-        "ddim_split_kernel 5 x 512, 64-d latent": {"mfma_busy": 0.405, "valu_per_mfma": 3.37},
-        "lg_resample_kernel 2^24": {"hbm_bytes": (541261 * 2 + 1114116) * 1024},
+        "ddim_split_kernel 5 x 512, 64-d latent": {"mfma_busy": 0.404, "valu_per_mfma": 3.37},
+        "lg_resample_kernel 2^24": {"hbm_bytes": (541267 * 2 + 1114115) * 1024},
     },
 }
 
@@ -92,7 +92,8 @@ def kernel_sources_hash():
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_19729_amd", "csrc", "*"))):
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2606_19729_amd", "csrc", "*")))
+    for f in files + [os.path.join(ROOT, "paper_2606_19729_amd", "build.py")]:  # sources and compiler flags
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
