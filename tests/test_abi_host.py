@@ -117,3 +117,22 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert L.voila_info_nce_grad_workspace_size(None, 8) == 0
     assert L.voila_info_nce_grad(None, None, None, None, 8, None, 0, None, None, None, None) == \
         V.VOILA_ERR_INVALID_ARG
+
+
+def test_plan_kernel_instances_split_by_precision():
+    """The binary32 instances of plan_kernel come only from k_plan.hip's object
+    and the bfloat16 ones only from k_plan_bf16.hip's (built with other
+    compiler flags): an instance compiled in both would leave the runtime to
+    pick either build of it."""
+    import shutil
+    import subprocess
+    build = os.path.join(ROOT, "paper_2606_19729_amd", "_build")
+    objs = {n: os.path.join(build, n + ".o") for n in ("k_plan", "k_plan_bf16")}
+    if shutil.which("nm") is None or not all(os.path.exists(o) for o in objs.values()):
+        pytest.skip("objects of the last build or nm not available")
+    kinds = {}
+    for name, path in objs.items():
+        out = subprocess.run(["nm", "-C", path], capture_output=True, text=True, check=True).stdout
+        kinds[name] = set(re.findall(r"__device_stub__plan_kernel<(\d),", out))
+    assert kinds["k_plan"] == {"0"}, kinds
+    assert kinds["k_plan_bf16"] == {"1"}, kinds
